@@ -26,7 +26,7 @@ _lib = None
 
 KINDS = {"linear": 0, "quadratic": 1, "sin1d": 2, "sincos2d": 3, "chain": 4}
 MODES = {"path": 0, "expand": 1, "classic": 2}
-FLAG_UNBOUNDED, FLAG_NONFINITE, FLAG_HULL = 1, 2, 4
+FLAG_UNBOUNDED, FLAG_BAD_INPUT, FLAG_HULL = 1, 2, 4
 
 
 def build(force: bool = False) -> str:

@@ -36,7 +36,9 @@
  *   - several contributions to one Hessian entry are summed as intervals
  *     before the product with the Delta product;
  *   - an entry whose enclosure needs division by an interval containing 0
- *     makes its output row [-inf, +inf] and sets the UNBOUNDED flag.
+ *     makes its output row [-inf, +inf] and sets the UNBOUNDED flag;
+ *   - a non-finite input or a negative radius is invalid: every row of the
+ *     unit becomes [-inf, +inf] and the BAD_INPUT flag is set.
  */
 #include <math.h>
 #include <stdint.h>
@@ -52,7 +54,7 @@ typedef struct { double lo, hi; } iv;
 
 enum { ORC_LINEAR = 0, ORC_QUADRATIC = 1, ORC_SIN1D = 2, ORC_SINCOS2D = 3, ORC_CHAIN = 4 };
 enum { ORC_PATH = 0, ORC_EXPAND = 1, ORC_CLASSIC = 2 };
-enum { ORC_FLAG_UNBOUNDED = 1u, ORC_FLAG_NONFINITE = 2u, ORC_FLAG_HULL = 4u };
+enum { ORC_FLAG_UNBOUNDED = 1u, ORC_FLAG_BAD_INPUT = 2u, ORC_FLAG_HULL = 4u };
 
 typedef struct {
     int32_t kind;          /* ORC_* */
@@ -351,7 +353,7 @@ static unsigned unit_box(int n, const double* nom, const double* mu, const doubl
     unsigned fl = 0;
     for (int i = 0; i < n; ++i) {
         double m = mu ? mu[i] : 0.0;
-        if (!isfinite(nom[i]) || !isfinite(m) || !isfinite(sg[i])) fl |= ORC_FLAG_NONFINITE;
+        if (!isfinite(nom[i]) || !isfinite(m) || !isfinite(sg[i]) || !(sg[i] >= 0.0)) fl |= ORC_FLAG_BAD_INPUT;
         if (fabs(m) > sg[i]) fl |= ORC_FLAG_HULL;
         double lo = add_rd(m, -sg[i]), hi = add_ru(m, sg[i]);
         D[i] = imk(lo < 0 ? lo : 0.0, hi > 0 ? hi : 0.0);
@@ -378,7 +380,7 @@ static unsigned unit_bound(const orc_dyn* d, int mode, const double* nom, const 
     iv* v = (iv*)malloc(sizeof(iv) * n);
     unsigned fl = unit_box(n, nom, mu, sg, D, X);
     for (int l = 0; l < d->nx; ++l) {
-        if (fl & ORC_FLAG_NONFINITE) { lo[l] = -INFINITY; hi[l] = INFINITY; continue; }
+        if (fl & ORC_FLAG_BAD_INPUT) { lo[l] = -INFINITY; hi[l] = INFINITY; continue; }
         int nc = row_candidates(d, l, ks, js, MAXCAND);
         int unbounded = 0;
         for (int c = 0; c < nc; ++c) {

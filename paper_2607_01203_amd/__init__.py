@@ -1,0 +1,173 @@
+"""MI355X (gfx950) linearization-error bounds: Python binding of libleb.so.
+
+The binding only marshals arguments: every step of the bound runs in the
+HIP kernels of libleb.so.  PyTorch provides device memory and streams.
+There is no CPU fallback: if the library is missing or a call fails, an
+exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = ["lib", "Dynamics", "LebError", "analytic_bound", "chain_dynamics", "tube_map", "fixed_point_solve", "FLAG_UNBOUNDED",
+           "FLAG_BAD_INPUT", "FLAG_HULL_EXTENDED", "DYN_LINEAR", "DYN_PQUAD_CHAIN"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libleb.so")
+
+FLAG_UNBOUNDED, FLAG_BAD_INPUT, FLAG_HULL_EXTENDED = 1, 2, 4
+DYN_LINEAR, DYN_PQUAD_CHAIN = 0, 4
+
+_lib = None
+
+
+class LebError(RuntimeError):
+    pass
+
+
+class Dynamics(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("nx", ctypes.c_int32), ("nu", ctypes.c_int32),
+                ("n_units", ctypes.c_int32), ("dt", ctypes.c_double), ("m", ctypes.c_double),
+                ("g", ctypes.c_double), ("arm", ctypes.c_double), ("inertia", ctypes.c_double),
+                ("k_spring", ctypes.c_double), ("rest_len", ctypes.c_double)]
+
+
+class FPOptions(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_sweeps", ctypes.c_int32), ("pad", ctypes.c_double),
+                ("inflate_rel", ctypes.c_double), ("inflate_abs", ctypes.c_double), ("warm", ctypes.c_int32)]
+
+
+def chain_dynamics(n_units, dt=0.05, m=1.0, g=9.81, arm=0.25, inertia=0.01, k_spring=2.0,
+                   rest_len=1.0) -> Dynamics:
+    return Dynamics(DYN_PQUAD_CHAIN, 6 * n_units, 2 * n_units, n_units, dt, m, g, arm, inertia,
+                    k_spring, rest_len)
+
+
+def dynamics_like(obj) -> Dynamics:
+    """From any object exposing n_units, dt, m, g, arm, inertia, k_spring, rest_len."""
+    return chain_dynamics(obj.n_units, obj.dt, obj.m, obj.g, obj.arm, obj.inertia, obj.k_spring,
+                          obj.rest_len)
+
+
+def lib():
+    """Load libleb.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise LebError("libleb.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        L.leb_analytic_bound.argtypes = [ctypes.POINTER(Dynamics), ctypes.c_int32, ctypes.c_int32,
+                                         vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, vp, vp]
+        L.leb_analytic_bound.restype = ctypes.c_int
+        L.leb_tube_map.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp,
+                                   ctypes.POINTER(ctypes.c_double), vp, vp, vp, vp, vp]
+        L.leb_tube_map.restype = ctypes.c_int
+        L.leb_fixed_point_solve.argtypes = [ctypes.POINTER(Dynamics), ctypes.c_int32, ctypes.c_int32, vp, vp,
+                                            vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(FPOptions),
+                                            vp, vp, vp, ctypes.POINTER(ctypes.c_int32), vp]
+        L.leb_fixed_point_solve.restype = ctypes.c_int
+        L.leb_strerror.argtypes = [ctypes.c_int]
+        L.leb_strerror.restype = ctypes.c_char_p
+        L.leb_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise LebError("libleb: %s (%d)" % (lib().leb_strerror(rc).decode(), rc))
+
+
+def _dev_ptr(t, name, dtype=None):
+    if t is None:
+        return None
+    import torch
+    if not t.is_cuda:
+        raise LebError("%s must be a GPU tensor" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise LebError("%s must be %s" % (name, dtype))
+    if not t.is_contiguous():
+        raise LebError("%s must be contiguous" % name)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def analytic_bound(dyn: Dynamics, z, v, sigma, mu=None, pad: float = 0.0, zonotope: bool = False,
+                   stream=None, out=None):
+    """Path-based Hessian bound for every (trajectory, timestep).
+
+    z [B][N][nx], v [B][N][nu], sigma (and mu) [B][N][nx+nu]: float64 GPU
+    tensors.  Returns dict with r_lo, r_hi [B][N][nx], flags [B][N] (int32
+    view of the uint32 flags) and, if zonotope, c_bar and rho_bar."""
+    import torch
+    B, N = int(z.shape[0]), int(z.shape[1])
+    f64 = torch.float64
+    if out is None:
+        out = {"r_lo": torch.empty((B, N, dyn.nx), dtype=f64, device=z.device),
+               "r_hi": torch.empty((B, N, dyn.nx), dtype=f64, device=z.device),
+               "flags": torch.empty((B, N), dtype=torch.int32, device=z.device)}
+        if zonotope:
+            out["c_bar"] = torch.empty((B, N, dyn.nx), dtype=f64, device=z.device)
+            out["rho_bar"] = torch.empty((B, N, dyn.nx), dtype=f64, device=z.device)
+    rc = lib().leb_analytic_bound(
+        ctypes.byref(dyn), B, N, _dev_ptr(z, "z", f64), _dev_ptr(v, "v", f64), _dev_ptr(mu, "mu", f64),
+        _dev_ptr(sigma, "sigma", f64), _dev_ptr(out["r_lo"], "r_lo", f64), _dev_ptr(out["r_hi"], "r_hi", f64),
+        _dev_ptr(out.get("c_bar"), "c_bar", f64), _dev_ptr(out.get("rho_bar"), "rho_bar", f64),
+        float(pad), _dev_ptr(out["flags"], "flags"), _stream(stream))
+    _check(rc)
+    return out
+
+
+def _host6(e):
+    arr = (ctypes.c_double * 6)(*[float(x) for x in e])
+    return arr
+
+
+def tube_map(n_units, phi, e, c_bar, rho_bar, stream=None, out=None):
+    """Tube centre/width from residual zonotopes (see leb.h: leb_tube_map).
+
+    phi [N-1][8][6] float64 GPU tensor, e: 6 host floats, c_bar/rho_bar
+    [B][N][6U] GPU tensors.  Returns (mu, sigma) [B][N][8U]."""
+    import torch
+    B, N = int(c_bar.shape[0]), int(c_bar.shape[1])
+    f64 = torch.float64
+    if out is None:
+        out = (torch.empty((B, N, 8 * n_units), dtype=f64, device=c_bar.device),
+               torch.empty((B, N, 8 * n_units), dtype=f64, device=c_bar.device))
+    rc = lib().leb_tube_map(B, N, int(n_units), _dev_ptr(phi, "phi", f64), _host6(e),
+                            _dev_ptr(c_bar, "c_bar", f64), _dev_ptr(rho_bar, "rho_bar", f64),
+                            _dev_ptr(out[0], "mu", f64), _dev_ptr(out[1], "sigma", f64), _stream(stream))
+    _check(rc)
+    return out
+
+
+def fixed_point_solve(dyn: Dynamics, z, v, phi, e, tol=1e-6, max_sweeps=200, pad=0.0, inflate_rel=1e-6,
+                      inflate_abs=1e-12, mu=None, sigma=None, stream=None):
+    """Certified tube/LEB fixed point (see leb.h: leb_fixed_point_solve).
+
+    Warm start when mu and sigma are given (they are updated in place).
+    Returns (mu, sigma, certified [B] int32 tensor, sweeps)."""
+    import torch
+    B, N = int(z.shape[0]), int(z.shape[1])
+    n = dyn.nx + dyn.nu
+    warm = mu is not None
+    if not warm:
+        mu = torch.zeros((B, N, n), dtype=torch.float64, device=z.device)
+        sigma = torch.zeros((B, N, n), dtype=torch.float64, device=z.device)
+    cert = torch.zeros((B,), dtype=torch.int32, device=z.device)
+    opt = FPOptions(tol, max_sweeps, pad, inflate_rel, inflate_abs, 1 if warm else 0)
+    sweeps = ctypes.c_int32(0)
+    f64 = torch.float64
+    rc = lib().leb_fixed_point_solve(ctypes.byref(dyn), B, N, _dev_ptr(z, "z", f64), _dev_ptr(v, "v", f64),
+                                     _dev_ptr(phi, "phi", f64), _host6(e), ctypes.byref(opt),
+                                     _dev_ptr(mu, "mu", f64), _dev_ptr(sigma, "sigma", f64),
+                                     _dev_ptr(cert, "certified"), ctypes.byref(sweeps), _stream(stream))
+    _check(rc)
+    return mu, sigma, cert, int(sweeps.value)

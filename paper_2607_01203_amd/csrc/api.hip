@@ -1,0 +1,69 @@
+// api.hip -- C-ABI entry points: argument validation and dispatch.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "leb.h"
+#include "leb_internal.hpp"
+
+namespace leb {
+
+bool aligned8(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+int check_chain_dynamics(const leb_dynamics* dyn) {
+    if (!dyn) return LEB_EINVAL;
+    if (dyn->kind == LEB_DYN_LINEAR) return (dyn->nx >= 0 && dyn->nu >= 0) ? LEB_OK : LEB_EINVAL;
+    if (dyn->kind != LEB_DYN_PQUAD_CHAIN) return LEB_ENOTSUP;
+    if (dyn->n_units < 1) return LEB_EINVAL;
+    if (dyn->n_units > 256) return LEB_ENOTSUP;
+    if (dyn->nx != 6 * dyn->n_units || dyn->nu != 2 * dyn->n_units) return LEB_EINVAL;
+    if (!(dyn->dt > 0.0) || !(dyn->m > 0.0) || !isfinite(dyn->dt) || !isfinite(dyn->m)) return LEB_EINVAL;
+    if (!(dyn->k_spring >= 0.0) || !(dyn->rest_len >= 0.0) || !isfinite(dyn->k_spring) ||
+        !isfinite(dyn->rest_len))
+        return LEB_EINVAL;
+    return LEB_OK;
+}
+
+}  // namespace leb
+
+using namespace leb;
+
+extern "C" int leb_analytic_bound(const leb_dynamics* dyn, int32_t batch, int32_t N, const double* z,
+                                  const double* v, const double* mu, const double* sigma, double* r_lo,
+                                  double* r_hi, double* c_bar, double* rho_bar, double pad, uint32_t* flags,
+                                  void* stream) {
+    int rc = check_chain_dynamics(dyn);
+    if (rc != LEB_OK) return rc;
+    if (batch < 0 || N < 0) return LEB_EINVAL;
+    if (!(pad >= 0.0) || !isfinite(pad)) return LEB_EINVAL;
+    if ((c_bar == nullptr) != (rho_bar == nullptr)) return LEB_EINVAL;
+    const int64_t units = (int64_t)batch * (int64_t)N;
+    if (units == 0) return LEB_OK;
+    const int64_t nx = dyn->nx, nu = dyn->nu;
+    if (nx > 0 && (!r_lo || !r_hi)) return LEB_EINVAL;
+    const void* ptrs[] = {z, v, mu, sigma, r_lo, r_hi, c_bar, rho_bar};
+    for (const void* p : ptrs)
+        if (p && !aligned8(p)) return LEB_EINVAL;
+    if (flags && (reinterpret_cast<uintptr_t>(flags) & 3u)) return LEB_EINVAL;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (dyn->kind == LEB_DYN_LINEAR) {
+        if (units * nx == 0 && !flags) return LEB_OK;
+        return launch_fill_zero(units * nx, r_lo, r_hi, c_bar, rho_bar, pad, flags, flags ? units : 0, s);
+    }
+    if (!z || !v || !sigma) return LEB_EINVAL;
+    if (units * (nx + nu) > ((int64_t)1 << 46)) return LEB_EINVAL;
+    return launch_pbh_chain(dyn, units, z, v, mu, sigma, r_lo, r_hi, c_bar, rho_bar, pad, flags, s);
+}
+
+extern "C" const char* leb_strerror(int code) {
+    switch (code) {
+    case LEB_OK: return "ok";
+    case LEB_EINVAL: return "invalid argument";
+    case LEB_ENOMEM: return "device allocation failed";
+    case LEB_EDEVICE: return "HIP runtime error";
+    case LEB_ENOTSUP: return "not supported";
+    }
+    return "unknown status";
+}
+
+extern "C" const char* leb_version(void) { return "leb-mi355x 0.1 (gfx950)"; }

@@ -1,0 +1,98 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol
+that include/leb.h declares, and rejects bad arguments before touching the
+device (these calls return before any HIP call)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w\s\*]*?\b(leb_\w+)\s*\(", text, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_2607_01203_amd as leb
+    if not os.path.exists(leb.LIB_PATH):
+        pytest.fail("libleb.so missing: run __graft_entry__.build() first")
+    return leb.lib()
+
+
+def test_header_declares_entry_points():
+    names = _declared_symbols()
+    assert "leb_analytic_bound" in names and "leb_strerror" in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    for name in _declared_symbols():
+        assert hasattr(L, name), name
+
+
+def test_strerror_and_version(L):
+    assert L.leb_strerror(0) == b"ok"
+    assert L.leb_strerror(-1) == b"invalid argument"
+    assert L.leb_version().startswith(b"leb-mi355x")
+
+
+def _call(L, dyn, batch=1, N=1, z=8, v=8, mu=None, sigma=8, lo=8, hi=8, cb=None, rb=None, pad=0.0, flags=None):
+    vp = lambda x: None if x is None else ctypes.c_void_p(x)
+    return L.leb_analytic_bound(None if dyn is None else ctypes.byref(dyn), batch, N, vp(z), vp(v), vp(mu),
+                                vp(sigma), vp(lo), vp(hi), vp(cb), vp(rb), pad, vp(flags), None)
+
+
+def test_rejects_bad_arguments_without_launching(L):
+    import paper_2607_01203_amd as leb
+    d = leb.chain_dynamics(2)
+    assert _call(L, None) == -1
+    assert _call(L, d, batch=-1) == -1
+    assert _call(L, d, N=-3) == -1
+    assert _call(L, d, z=None) == -1                 # required pointer
+    assert _call(L, d, sigma=None) == -1
+    assert _call(L, d, lo=None) == -1
+    assert _call(L, d, z=12) == -1                   # misaligned FP64 pointer
+    assert _call(L, d, cb=8) == -1                   # c_bar without rho_bar
+    assert _call(L, d, pad=-1.0) == -1
+    bad = leb.chain_dynamics(2)
+    bad.nx = 7
+    assert _call(L, bad) == -1
+    bad = leb.chain_dynamics(2, dt=0.0)
+    assert _call(L, bad) == -1
+    bad = leb.chain_dynamics(2, m=-1.0)
+    assert _call(L, bad) == -1
+    bad = leb.chain_dynamics(2, k_spring=-2.0)
+    assert _call(L, bad) == -1
+    bad = leb.chain_dynamics(300)
+    assert _call(L, bad) == -4
+    bad = leb.chain_dynamics(2)
+    bad.kind = 17
+    assert _call(L, bad) == -4
+
+
+def test_empty_problem_is_ok_without_launching(L):
+    import paper_2607_01203_amd as leb
+    d = leb.chain_dynamics(3)
+    assert _call(L, d, batch=0, N=5, z=None, v=None, sigma=None, lo=None, hi=None) == 0
+    assert _call(L, d, batch=4, N=0, z=None, v=None, sigma=None, lo=None, hi=None) == 0
+
+
+def test_binding_refuses_cpu_tensors():
+    import torch
+    import paper_2607_01203_amd as leb
+    d = leb.chain_dynamics(1)
+    z = torch.zeros((1, 2, 6), dtype=torch.float64)
+    with pytest.raises(leb.LebError):
+        leb.analytic_bound(d, z, torch.zeros((1, 2, 2), dtype=torch.float64),
+                           torch.zeros((1, 2, 8), dtype=torch.float64),
+                           out={"r_lo": z, "r_hi": z, "flags": torch.zeros((1, 2), dtype=torch.int32)})

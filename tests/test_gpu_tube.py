@@ -1,0 +1,134 @@
+"""GPU tube map and certified tube/LEB fixed point against the oracle."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2607_01203_amd as leb
+    leb.lib()
+    return torch.device("cuda:0")
+
+
+def _t(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def test_tube_map_parity(gpu, orc):
+    import torch
+    import paper_2607_01203_amd as leb
+    from oracle import tube
+    tp = W.fixed_point_cfg(seed=44, batch=5, N=23, n_units=7)
+    B, N, nx = tp.batch.z.shape
+    r = np.random.default_rng(2)
+    cb = r.normal(size=(B, N, nx)) * 1e-3
+    rb = r.uniform(0, 1e-3, (B, N, nx))
+    print("case: tube map B=5 N=23 U=7", flush=True)
+    mu, sg = leb.tube_map(7, _t(tp.phi, gpu), tp.e, _t(cb, gpu), _t(rb, gpu))
+    torch.cuda.synchronize()
+    mo, so = tube.tube_map(tp.phi, tp.e, cb, rb)
+    mu, sg = mu.cpu().numpy(), sg.cpu().numpy()
+    np.testing.assert_allclose(mu, mo, rtol=1e-12, atol=1e-15)
+    assert (sg >= so).all() and (sg <= so * (1 + 1e-11) + 1e-15).all()
+
+
+def _solve(leb, tp, dev, **kw):
+    import torch
+    b = tp.batch
+    dyn = leb.dynamics_like(b.dyn)
+    mu, sg, cert, sweeps = leb.fixed_point_solve(dyn, _t(b.z, dev), _t(b.v, dev), _t(tp.phi, dev), tp.e, **kw)
+    torch.cuda.synchronize()
+    return mu.cpu().numpy(), sg.cpu().numpy(), cert.cpu().numpy(), sweeps
+
+
+def _check_against_oracle(orc, tp, mu, sg, idx):
+    from oracle import tube
+    b = tp.batch
+    d = orc.Dyn.like(b.dyn)
+    mo, so, _, _ = tube.fixed_point(d, b.z[idx], b.v[idx], tp.phi, tp.e)
+    # the certified tube contains the least fixed point and is close to it
+    assert (sg[idx] >= so * (1 - 1e-12)).all()
+    M = np.maximum(so, 1e-300)
+    rel = np.where(so > 0, (sg[idx] - so) / M, 0.0)
+    assert rel.max() <= 1e-4, rel.max()
+    assert (np.abs(mu[idx] - mo) <= 1e-4 * np.maximum(so, 1e-12)).all()
+
+
+def test_fixed_point_small(gpu, orc):
+    import paper_2607_01203_amd as leb
+    tp = W.fixed_point_cfg(seed=45, batch=6, N=12, n_units=4)
+    print("case: fixed point B=6 N=12 U=4", flush=True)
+    mu, sg, cert, sweeps = _solve(leb, tp, gpu)
+    assert (cert == 1).all()
+    assert 2 <= sweeps <= 12 + 2
+    _check_against_oracle(orc, tp, mu, sg, np.arange(6))
+
+
+def test_fixed_point_full_shape(gpu, orc):
+    """256 trajectories x 40 steps, 168 states; oracle on a sample."""
+    import paper_2607_01203_amd as leb
+    tp = W.fixed_point_cfg()
+    print("case: fixed point 256x40x168", flush=True)
+    mu, sg, cert, sweeps = _solve(leb, tp, gpu)
+    print("sweeps", sweeps)
+    assert (cert == 1).all()
+    _check_against_oracle(orc, tp, mu, sg, np.array([0, 77, 255]))
+
+
+def test_fixed_point_certificate_holds(gpu, orc):
+    """Recheck the certificate with the oracle: F(B) inside B."""
+    import paper_2607_01203_amd as leb
+    from oracle import tube
+    tp = W.fixed_point_cfg(seed=46, batch=4, N=15, n_units=5)
+    mu, sg, cert, _ = _solve(leb, tp, gpu)
+    assert (cert == 1).all()
+    b = tp.batch
+    d = orc.Dyn.like(b.dyn)
+    lo, hi, _ = orc.leb(d, b.z, b.v, sg, mu=mu)
+    c, r = tube.zono(lo, hi)
+    m2, s2 = tube.tube_map(tp.phi, tp.e, c, r)
+    assert tube.contains(mu, sg, m2, s2).all()
+
+
+def test_fixed_point_sweep_cap_not_certified(gpu):
+    import paper_2607_01203_amd as leb
+    tp = W.fixed_point_cfg(seed=47, batch=3, N=10, n_units=3)
+    mu, sg, cert, sweeps = _solve(leb, tp, gpu, max_sweeps=1)
+    assert sweeps == 1 and (cert == 0).all()
+
+
+def test_fixed_point_boxes_sound_1e6(gpu, orc):
+    """LEBs on the accepted tube boxes contain 10^6 sampled remainders."""
+    import torch
+    import paper_2607_01203_amd as leb
+    tp = W.fixed_point_cfg(seed=4, batch=16, N=40)
+    mu, sg, cert, _ = _solve(leb, tp, gpu)
+    assert (cert == 1).all()
+    b = tp.batch
+    dyn = leb.dynamics_like(b.dyn)
+    out = leb.analytic_bound(dyn, _t(b.z, gpu), _t(b.v, gpu), _t(sg, gpu), _t(mu, gpu))
+    torch.cuda.synchronize()
+    lo = out["r_lo"].cpu().numpy().reshape(-1, 168)
+    hi = out["r_hi"].cpu().numpy().reshape(-1, 168)
+    d = orc.Dyn.like(b.dyn)
+    nom = np.concatenate([b.z, b.v], -1).reshape(-1, 224)
+    blo, bhi = orc.box(nom, sg.reshape(-1, 224), mu.reshape(-1, 224))
+    rng = W.rng_for(1_000_004)
+    per = 1_000_000 // nom.shape[0] + 1
+    viol = 0
+    for s in range(0, nom.shape[0], 64):
+        e = min(nom.shape[0], s + 64)
+        pts = W.sample_box_points(rng, blo[s:e], bhi[s:e], per)
+        r, eps = orc.remainder(d, nom[s:e], pts.reshape(-1, 224), np.repeat(np.arange(e - s), per))
+        r = r.reshape(e - s, per, 168)
+        eps = eps.reshape(e - s, per, 168)
+        viol += int(((r > hi[s:e, None] + eps) | (r < lo[s:e, None] - eps)).sum())
+    assert viol == 0

@@ -359,14 +359,20 @@ def test_singular_spring_is_unbounded(orc):
     assert lo[0, 0, 0] == 0 and hi[0, 0, 0] == 0
 
 
-def test_nonfinite_input_flagged(orc):
+def test_bad_input_flagged(orc):
+    """Non-finite inputs and negative radii make every row of the unit
+    [-inf, inf] with the BAD_INPUT flag; other units are unaffected."""
     b = W.planar_quad_cfg()
     d = orc.Dyn.like(b.dyn)
     z = b.z.copy()
     z[0, 3, 1] = np.nan
-    lo, hi, fl = orc.leb(d, z, b.v, b.sigma)
-    assert fl[0, 3] & orc.FLAG_NONFINITE
-    assert np.isneginf(lo[0, 3]).all() and np.isposinf(hi[0, 3]).all()
+    sg = b.sigma.copy()
+    sg[0, 5, 7] = -0.1
+    lo, hi, fl = orc.leb(d, z, b.v, sg)
+    for t in (3, 5):
+        assert fl[0, t] & orc.FLAG_BAD_INPUT
+        assert np.isneginf(lo[0, t]).all() and np.isposinf(hi[0, t]).all()
+    assert np.isfinite(lo[0, 4]).all() and fl[0, 4] == 0
 
 
 # ------------------------------------------------------------- sampling

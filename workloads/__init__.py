@@ -219,9 +219,15 @@ def nn_cfg(seed: int = 1, batch: int = 64, N: int = 50, hidden: int = 256,
 # --------------------------------------------------------------------------
 # tube/LEB fixed point
 
-def hover_lqr(dyn: ChainDynamics):
+HOVER_Q = (100.0, 100.0, 10.0, 1.0, 1.0, 1.0)
+HOVER_R = 0.1
+
+
+def hover_lqr(dyn: ChainDynamics, Q=HOVER_Q, R=HOVER_R):
     """Hover linearisation of one planar quadrotor (theta=0, u1=u2=mg/2),
-    forward-Euler discretised, and its discrete LQR gain (Q=I6, R=I2)."""
+    forward-Euler discretised, and its discrete LQR gain for state weights
+    diag(Q) and input weight R I2 (position-heavy, so the closed-loop tube
+    stays well inside the spring separations)."""
     import scipy.linalg
     dt, m = dyn.dt, dyn.m
     Ac = np.zeros((6, 6))
@@ -233,16 +239,19 @@ def hover_lqr(dyn: ChainDynamics):
     Bc[5, 1] = -dyn.arm / dyn.inertia
     A = np.eye(6) + dt * Ac
     Bm = dt * Bc
-    P = scipy.linalg.solve_discrete_are(A, Bm, np.eye(6), np.eye(2))
-    K = -np.linalg.solve(np.eye(2) + Bm.T @ P @ Bm, Bm.T @ P @ A)
+    Qm = np.diag(np.asarray(Q, dtype=np.float64))
+    Rm = R * np.eye(2)
+    P = scipy.linalg.solve_discrete_are(A, Bm, Qm, Rm)
+    K = -np.linalg.solve(Rm + Bm.T @ P @ Bm, Bm.T @ P @ A)
     return A, Bm, K
 
 
 def fixed_point_cfg(seed: int = 4, batch: int = 256, N: int = 40, n_units: int = 28,
-                    e_scale: float = 5e-2) -> TubeProblem:
+                    e_scale: float = 2e-2) -> TubeProblem:
     """256 chain trajectories (nx=168) of horizon 40 with a decentralised
-    hover-LQR closed loop.  Tube radii are unknowns of the fixed point, so
-    the nominal spring separations keep a fixed margin of 0.6."""
+    hover-LQR closed loop and disturbance generator e_scale on (vx, vz) of
+    every node.  Tube radii are unknowns of the fixed point, so the nominal
+    spring separations keep a fixed margin of 0.6."""
     dyn = ChainDynamics(n_units=n_units)
     rng = rng_for(seed)
     z, v = _chain_nominal(rng, (batch, N), n_units, dyn.rest_len, 0.6, None)
