@@ -95,6 +95,27 @@ int leb_analytic_bound(const leb_dynamics* dyn, int32_t batch, int32_t N,
                        uint32_t* flags, void* stream);
 
 /*
+ * leb_backward -- adjoint of leb_analytic_bound: the gradient of
+ *     L = sum_{unit, row} g_lo r_lo + g_hi r_hi
+ * with respect to z, v, sigma (and mu) for the exact-arithmetic path-based
+ * bound (rounding treated as the identity; at ties between candidate
+ * endpoints the first in the order lo*lo, lo*hi, hi*lo, hi*hi is used).
+ * The paper differentiates the bound to refine the nominal point
+ * (Table II) and to penalise propagated error (eq.
+ * linearization_error_cost_penalty).  Interval intermediates are
+ * recomputed, not stored.
+ *   g_lo, g_hi [batch][N][nx]     upstream adjoints of r_lo, r_hi
+ *   gz [batch][N][nx], gv [batch][N][nu], gsigma [batch][N][nx+nu] outputs
+ *   gmu [batch][N][nx+nu] output, may be NULL; must be NULL when mu is NULL
+ * Rows whose bound is unbounded and units with invalid data contribute 0.
+ * Chains up to 128 nodes (LEB_ENOTSUP beyond).  Deterministic: per-
+ * coordinate sums are taken in a fixed order.
+ */
+int leb_backward(const leb_dynamics* dyn, int32_t batch, int32_t N, const double* z, const double* v,
+                 const double* mu, const double* sigma, const double* g_lo, const double* g_hi,
+                 double* gz, double* gv, double* gmu, double* gsigma, void* stream);
+
+/*
  * leb_tube_map -- tube centre and width from the residual zonotopes
  * (eqs. tight_tube_center, tight_tube_width):
  *   mu_k    = sum_{j<k} Phi_{k,j} c_bar_j

@@ -21,6 +21,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "leb_oracle.c")
+_SRC_GRAD = os.path.join(_HERE, "leb_grad.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -31,10 +32,11 @@ FLAG_UNBOUNDED, FLAG_BAD_INPUT, FLAG_HULL = 1, 2, 4
 
 def build(force: bool = False) -> str:
     """Compile liboracle.so with gcc (-O2, OpenMP, no fast-math)."""
-    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+    newest = max(os.path.getmtime(_SRC), os.path.getmtime(_SRC_GRAD))
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < newest:
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-fno-fast-math",
-                               "-o", tmp, _SRC, "-lm"])
+                               "-o", tmp, _SRC, _SRC_GRAD, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -60,6 +62,8 @@ def lib():
         L.orc_hess_entry.argtypes = [ctypes.POINTER(_Dyn), ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                      dp, dp, dp, dp]
         L.orc_nonlin.argtypes = [ctypes.POINTER(_Dyn), ctypes.c_int, dp, dp, dp]
+        L.orc_leb_grad.argtypes = [ctypes.POINTER(_Dyn), ctypes.c_long, dp, dp, dp, dp, dp, dp, dp, dp,
+                                   dp, dp, dp, ctypes.c_int]
         L.orc_isin.argtypes = [ctypes.c_double, ctypes.c_double, dp]
         L.orc_icos.argtypes = [ctypes.c_double, ctypes.c_double, dp]
         _lib = L
@@ -169,3 +173,29 @@ def icos(lo, hi):
     out = np.zeros(2)
     lib().orc_icos(lo, hi, _ptr(out))
     return out
+
+
+def leb_grad(dyn: Dyn, z, v, sigma, g_lo, g_hi, mu=None, threads: int = 0):
+    """Gradient of sum(g_lo r_lo + g_hi r_hi) of the path-based bound with
+    respect to z, v, sigma (and mu when given), by forward-mode dual
+    numbers.  Returns dict gz, gv, gsigma, gmu (or None), margin [units]."""
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    lead = z.shape[:-1]
+    U = int(np.prod(lead))
+    v = np.ascontiguousarray(v, dtype=np.float64).reshape(U, dyn.nu)
+    sg = np.ascontiguousarray(sigma, dtype=np.float64).reshape(U, dyn.n)
+    mu_a = None if mu is None else np.ascontiguousarray(mu, dtype=np.float64).reshape(U, dyn.n)
+    gl = np.ascontiguousarray(g_lo, dtype=np.float64).reshape(U, dyn.nx)
+    gh = np.ascontiguousarray(g_hi, dtype=np.float64).reshape(U, dyn.nx)
+    gz = np.zeros((U, dyn.nx))
+    gv = np.zeros((U, dyn.nu))
+    gs = np.zeros((U, dyn.n))
+    gm = None if mu is None else np.zeros((U, dyn.n))
+    mg = np.zeros(U)
+    rc = lib().orc_leb_grad(ctypes.byref(dyn.c), U, _ptr(z.reshape(U, dyn.nx)), _ptr(v), _ptr(mu_a), _ptr(sg),
+                            _ptr(gl), _ptr(gh), _ptr(gz), _ptr(gv), _ptr(gm), _ptr(gs), _ptr(mg), int(threads))
+    if rc != 0:
+        raise ValueError("oracle gradient rejected the arguments")
+    return {"gz": gz.reshape(lead + (dyn.nx,)), "gv": gv.reshape(lead + (dyn.nu,)),
+            "gsigma": gs.reshape(lead + (dyn.n,)), "gmu": None if gm is None else gm.reshape(lead + (dyn.n,)),
+            "margin": mg.reshape(lead)}

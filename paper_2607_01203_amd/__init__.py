@@ -61,6 +61,8 @@ def lib():
         L.leb_analytic_bound.argtypes = [ctypes.POINTER(Dynamics), ctypes.c_int32, ctypes.c_int32,
                                          vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, vp, vp]
         L.leb_analytic_bound.restype = ctypes.c_int
+        L.leb_backward.argtypes = [ctypes.POINTER(Dynamics), ctypes.c_int32, ctypes.c_int32] + [vp] * 11
+        L.leb_backward.restype = ctypes.c_int
         L.leb_tube_map.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp,
                                    ctypes.POINTER(ctypes.c_double), vp, vp, vp, vp, vp]
         L.leb_tube_map.restype = ctypes.c_int
@@ -123,6 +125,62 @@ def analytic_bound(dyn: Dynamics, z, v, sigma, mu=None, pad: float = 0.0, zonoto
         float(pad), _dev_ptr(out["flags"], "flags"), _stream(stream))
     _check(rc)
     return out
+
+
+def backward(dyn: Dynamics, z, v, sigma, g_lo, g_hi, mu=None, stream=None):
+    """Gradient of sum(g_lo r_lo + g_hi r_hi) of the path-based bound with
+    respect to z, v, sigma (and mu when given): see leb.h, leb_backward."""
+    import torch
+    f64 = torch.float64
+    gz = torch.empty_like(z)
+    gv = torch.empty_like(v)
+    gs = torch.empty_like(sigma)
+    gm = None if mu is None else torch.empty_like(mu)
+    B, N = int(z.shape[0]), int(z.shape[1])
+    rc = lib().leb_backward(ctypes.byref(dyn), B, N, _dev_ptr(z, "z", f64), _dev_ptr(v, "v", f64),
+                            _dev_ptr(mu, "mu", f64), _dev_ptr(sigma, "sigma", f64), _dev_ptr(g_lo, "g_lo", f64),
+                            _dev_ptr(g_hi, "g_hi", f64), _dev_ptr(gz, "gz", f64), _dev_ptr(gv, "gv", f64),
+                            _dev_ptr(gm, "gmu", f64), _dev_ptr(gs, "gsigma", f64), _stream(stream))
+    _check(rc)
+    return gz, gv, gs, gm
+
+
+def _autograd_class():
+    import torch
+
+    class LEBAnalytic(torch.autograd.Function):
+        """(z, v, sigma, mu) -> (r_lo, r_hi) with the hand-written adjoint.
+        Saves only the inputs; the backward recomputes the intervals."""
+
+        @staticmethod
+        def forward(ctx, dyn_box, z, v, sigma, mu):
+            dyn = dyn_box[0]
+            out = analytic_bound(dyn, z, v, sigma, mu)
+            ctx.dyn = dyn
+            ctx.has_mu = mu is not None
+            ctx.save_for_backward(z, v, sigma, mu if mu is not None else sigma)
+            return out["r_lo"], out["r_hi"]
+
+        @staticmethod
+        def backward(ctx, g_lo, g_hi):
+            z, v, sigma, mu = ctx.saved_tensors
+            mu = mu if ctx.has_mu else None
+            gz, gv, gs, gm = backward(ctx.dyn, z, v, sigma, g_lo.contiguous(), g_hi.contiguous(), mu)
+            return None, gz, gv, gs, gm
+
+    return LEBAnalytic
+
+
+_LEBAnalytic = None
+
+
+def leb_analytic(dyn: Dynamics, z, v, sigma, mu=None):
+    """Differentiable path-based bound: returns (r_lo, r_hi) tensors that
+    back-propagate through leb_backward."""
+    global _LEBAnalytic
+    if _LEBAnalytic is None:
+        _LEBAnalytic = _autograd_class()
+    return _LEBAnalytic.apply((dyn,), z, v, sigma, mu)
 
 
 def _host6(e):

@@ -102,18 +102,35 @@ __device__ __forceinline__ float cos_poly(float x) {
     return __builtin_fmaf(y, p, 1.0f);
 }
 
-// FP64 fallback for wide or far-out intervals: library sin/cos (error far
-// below 2^-40 relative for |x| < 2^20), widened by 2^-40 relative plus
-// 2^-100 absolute, with critical points detected using an outward pi.
-__device__ __noinline__ void sincos_wide(double a, double b, fiv* s, fiv* c) {
+// Interval sine and cosine of [a, b] (FP64 endpoints), with the selected
+// endpoint of each bound recorded for the adjoint: sel = 0 (endpoint a),
+// 1 (endpoint b), 2 (an extremum inside: the bound is the constant +-1).
+struct SinCos {
+    fiv s, c;
+    float fa, fb;          // fast path: FP32 endpoints fed to the polynomials
+    uint8_t s_lo, s_hi, c_lo, c_hi;
+    bool wide;
+};
+
+// FP64 path for wide or far-out intervals: library sin/cos (error far below
+// 2^-40 relative for |x| <= 1024), widened by 2^-40 relative plus 2^-100
+// absolute, with critical points detected using an outward pi.
+__device__ __noinline__ void sincos_wide(double a, double b, SinCos* r) {
     const double PI_LO = 3.141592653589793115997963468544185161590576171875;
     const double PI_HI = 3.141592653589793560087173318606801331043243408203125;
-    if (!(b - a < 2.0 * PI_LO) || fabs(a) > 1048576.0 || fabs(b) > 1048576.0) {
-        *s = mk(-1.0f, 1.0f); *c = mk(-1.0f, 1.0f); return;
+    r->wide = true;
+    if (!(b - a < 2.0 * PI_LO) || fabs(a) > 1024.0 || fabs(b) > 1024.0) {
+        r->s = mk(-1.0f, 1.0f); r->c = mk(-1.0f, 1.0f);
+        r->s_lo = r->s_hi = r->c_lo = r->c_hi = 2;
+        return;
     }
     double sa = sin(a), sb = sin(b), ca = cos(a), cb = cos(b);
     auto wdn = [](double x) { return x - fabs(x) * 0x1p-40 - 0x1p-100; };
     auto wup = [](double x) { return x + fabs(x) * 0x1p-40 + 0x1p-100; };
+    r->s_lo = sa <= sb ? 0 : 1;
+    r->s_hi = sa >= sb ? 0 : 1;
+    r->c_lo = ca <= cb ? 0 : 1;
+    r->c_hi = ca >= cb ? 0 : 1;
     double slo = wdn(fmin(sa, sb)), shi = wup(fmax(sa, sb));
     double clo = wdn(fmin(ca, cb)), chi = wup(fmax(ca, cb));
     // may [a, b] contain x0 + 2 pi m ?  (slack 1e-12 makes the test err to "yes")
@@ -123,26 +140,29 @@ __device__ __noinline__ void sincos_wide(double a, double b, fiv* s, fiv* c) {
         double lo_crit = x0 + m * 2.0 * (m >= 0 ? PI_LO : PI_HI);
         return lo_crit <= b + 1e-12;
     };
-    if (may(0.5)) shi = 1.0;
-    if (may(-0.5)) slo = -1.0;
-    if (may(0.0)) chi = 1.0;
-    if (may(1.0)) clo = -1.0;
-    *s = mk(fmaxf(rd32(slo), -1.0f), fminf(ru32(shi), 1.0f));
-    *c = mk(fmaxf(rd32(clo), -1.0f), fminf(ru32(chi), 1.0f));
+    if (may(0.5)) { shi = 1.0; r->s_hi = 2; }
+    if (may(-0.5)) { slo = -1.0; r->s_lo = 2; }
+    if (may(0.0)) { chi = 1.0; r->c_hi = 2; }
+    if (may(1.0)) { clo = -1.0; r->c_lo = 2; }
+    r->s = mk(fmaxf(rd32(slo), -1.0f), fminf(ru32(shi), 1.0f));
+    r->c = mk(fmaxf(rd32(clo), -1.0f), fminf(ru32(chi), 1.0f));
 }
 
-// Interval sine and cosine of [a, b] given as FP64 endpoints.
-__device__ __forceinline__ void isincos(double a, double b, fiv* s, fiv* c) {
+__device__ __forceinline__ void isincos(double a, double b, SinCos* r) {
     if (a >= -0.78 && b <= 0.78) {
-        float fa = rd32(a), fb = ru32(b);
-        float sa = sin_poly(fa), sb = sin_poly(fb);           // sin increasing on [-pi/2, pi/2]
-        float ca = cos_poly(fa), cb = cos_poly(fb);
-        s->lo = dn8(sa);
-        s->hi = up8(sb);
-        c->lo = dn8(fminf(ca, cb));
-        c->hi = (fa <= 0.0f && fb >= 0.0f) ? 1.0f : fminf(up8(fmaxf(ca, cb)), 1.0f);
+        r->wide = false;
+        const float fa = rd32(a), fb = ru32(b);
+        r->fa = fa; r->fb = fb;
+        const float sa = sin_poly(fa), sb = sin_poly(fb);        // sin increasing on [-pi/2, pi/2]
+        const float ca = cos_poly(fa), cb = cos_poly(fb);
+        r->s = mk(dn8(sa), up8(sb));
+        r->s_lo = 0; r->s_hi = 1;
+        r->c_lo = ca <= cb ? 0 : 1;
+        r->c.lo = dn8(fminf(ca, cb));
+        if (fa <= 0.0f && fb >= 0.0f) { r->c.hi = 1.0f; r->c_hi = 2; }
+        else { r->c.hi = fminf(up8(fmaxf(ca, cb)), 1.0f); r->c_hi = ca >= cb ? 0 : 1; }
     } else {
-        sincos_wide(a, b, s, c);
+        sincos_wide(a, b, r);
     }
 }
 

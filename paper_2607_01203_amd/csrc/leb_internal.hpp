@@ -13,6 +13,7 @@ int launch_pbh_chain(const leb_dynamics* dyn, int64_t units, const double* z, co
 int launch_fill_zero(int64_t count, double* r_lo, double* r_hi, double* c_bar, double* rho_bar, double pad,
                      uint32_t* flags, int64_t nflags, hipStream_t stream);
 size_t pbh_smem_bytes(int U);
+size_t bwd_smem_bytes(int U);
 int launch_tube_map(int B, int N, int U, const double* phi, const double* e, const double* cbar,
                     const double* rbar, double* mu, double* sigma, hipStream_t s);
 

@@ -39,6 +39,8 @@
 #include "ivl.hpp"
 #include "leb.h"
 #include "leb_internal.hpp"
+#include "node.hpp"
+#include "pbh_common.hpp"
 
 namespace leb {
 
@@ -46,7 +48,7 @@ constexpr int PBH_BLOCK = 256;
 
 struct SpringOut {      // what spring i passes to node i+1 (row i+1)
     double xlo, xhi, zlo, zhi;      // -(cross + own-of-node-i terms), already scaled
-    fiv t_xxx3, t_xxz3, t_xzz3, t_xzz4, t_zzz4;   // node i+1's shared own-position entries
+    IV<float> L[5];                 // node i+1's shared own-position entries
     uint32_t unbounded;
     uint32_t pad_;
 };
@@ -64,22 +66,13 @@ struct ChainArgs {
     double pad;
 };
 
-__device__ __forceinline__ double wlo64(double x) { return x - fabs(x) * 0x1p-45; }
-__device__ __forceinline__ double whi64(double x) { return x + fabs(x) * 0x1p-45; }
-
-__device__ __forceinline__ double mask(fiv d) { return (d.lo != 0.0f || d.hi != 0.0f) ? 1.0 : 0.0; }
-
-// FP64 value with absolute error allowance err -> outward FP32 interval
-__device__ __forceinline__ fiv from64(double lo, double hi, double err) {
-    return mk(rd32(lo - err), ru32(hi + err));
-}
 
 __global__ void __launch_bounds__(PBH_BLOCK) pbh_chain_fwd(ChainArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int U = A.U, T = A.T;
     const int nx = 6 * U, nu = 2 * U, n = nx + nu;
     double* s_nom = reinterpret_cast<double*>(smem);                       // [T][n]
-    fiv* s_d = reinterpret_cast<fiv*>(s_nom + (size_t)T * n);              // [T][n]
+    IV<float>* s_d = reinterpret_cast<IV<float>*>(s_nom + (size_t)T * n);  // [T][n]
     SpringOut* s_sp = reinterpret_cast<SpringOut*>(s_d + (size_t)T * n);   // [T][U]
     RowOut* s_row = reinterpret_cast<RowOut*>(s_sp + (size_t)T * U);       // [T][U]
     uint32_t* s_flag = reinterpret_cast<uint32_t*>(s_row + (size_t)T * U); // [T]
@@ -118,7 +111,7 @@ __global__ void __launch_bounds__(PBH_BLOCK) pbh_chain_fwd(ChainArgs A) {
         double l = m - sg, h = m + sg;
         l = l - fabs(l) * 0x1p-52;
         h = h + fabs(h) * 0x1p-52;
-        s_d[idx] = mk(rd32(fmin(l, 0.0)), ru32(fmax(h, 0.0)));
+        s_d[idx] = iv(rd32(fmin(l, 0.0)), ru32(fmax(h, 0.0)));
     }
     __syncthreads();
 
@@ -126,94 +119,41 @@ __global__ void __launch_bounds__(PBH_BLOCK) pbh_chain_fwd(ChainArgs A) {
     const int i = tid - lt * U;
     const bool active = (lt < nloc);
     const double* nom = s_nom + lt * n;
-    const fiv* D = s_d + lt * n;
+    const IV<float>* D = s_d + lt * n;
 
     // constants with c folded in (all >= 0 for kL >= 0)
     const double K3 = 3.0 * A.kL * A.c, K15 = 1.5 * A.kL * A.c, K1 = A.kL * A.c, K05 = 0.5 * A.kL * A.c;
 
     // ---- spring i (nodes i, i+1)
     div_ rx = {0.0, 0.0}, rz = {0.0, 0.0};       // spring i's terms for row i
-    fiv R_xxx = mk(0, 0), R_xxz = mk(0, 0), R_xzz1 = mk(0, 0), R_xzz2 = mk(0, 0), R_zzz = mk(0, 0);
+    IV<float> R[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) R[q] = iv(0.0f, 0.0f);
     uint32_t unb = 0;
     if (active && i < U - 1) {
-        const int pi_ = 6 * i, pj = 6 * (i + 1);
-        const double pxi = nom[pi_], pzi = nom[pi_ + 1], pxj = nom[pj], pzj = nom[pj + 1];
-        const fiv Dxi = D[pi_], Dzi = D[pi_ + 1], Dxj = D[pj], Dzj = D[pj + 1];
-        const double dxn = A.L0 + pxj - pxi;
-        const double dzn = pzj - pzi;
-        const double sx = fabs(A.L0) + fabs(pxj) + fabs(pxi) + fabs(Dxi.lo) + fabs(Dxi.hi) + fabs(Dxj.lo) + fabs(Dxj.hi);
-        const double sz = fabs(pzj) + fabs(pzi) + fabs(Dzi.lo) + fabs(Dzi.hi) + fabs(Dzj.lo) + fabs(Dzj.hi);
-        const double ex = sx * 0x1p-50, ez = sz * 0x1p-50;
-        // separations over the prefix boxes
-        const fiv dxA = from64(dxn - (double)Dxi.hi, dxn - (double)Dxi.lo, ex);                       // V1, V2
-        const fiv dxB = from64(dxn + (double)Dxj.lo - (double)Dxi.hi, dxn + (double)Dxj.hi - (double)Dxi.lo, ex); // V3, V4
-        const fiv dz0 = from64(dzn, dzn, ez);                                                          // V1
-        const fiv dz1 = from64(dzn - (double)Dzi.hi, dzn - (double)Dzi.lo, ez);                        // V2, V3
-        const fiv dz2 = from64(dzn + (double)Dzj.lo - (double)Dzi.hi, dzn + (double)Dzj.hi - (double)Dzi.lo, ez); // V4
-        const fiv aA = sq(dxA), aB = sq(dxB), b0 = sq(dz0), b1 = sq(dz1), b2 = sq(dz2);
-        const fiv s1 = add(aA, b0), s2 = add(aA, b1), s3 = add(aB, b1), s4 = add(aB, b2);
-        const float smin = fminf(fminf(s1.lo, s2.lo), fminf(s3.lo, s4.lo));
-        unb = !(smin >= 0x1p-40f);
-        if (!unb) {
-            const fiv q1 = rcp_pos(mul_nn(mul_nn(s1, s1), sqrt_pos(s1)));
-            const fiv q2 = rcp_pos(mul_nn(mul_nn(s2, s2), sqrt_pos(s2)));
-            const fiv q3 = rcp_pos(mul_nn(mul_nn(s3, s3), sqrt_pos(s3)));
-            const fiv q4 = rcp_pos(mul_nn(mul_nn(s4, s4), sqrt_pos(s4)));
-            // unit-coefficient third-derivative enclosures per prefix box
-            const fiv Txxx1 = mul_nonneg(dxA, mul_nn(b0, q1));
-            const fiv Txxz1 = mul(dz0, mul_nonneg(twoa_minus_b(aA, b0), q1));
-            const fiv Txzz1 = mul(dxA, mul_nonneg(a_minus_twob(aA, b0), q1));
-            const fiv Txxz2 = mul(dz1, mul_nonneg(twoa_minus_b(aA, b1), q2));
-            const fiv Txzz2 = mul(dxA, mul_nonneg(a_minus_twob(aA, b1), q2));
-            const fiv Tzzz2 = mul_nonneg(dz1, mul_nn(aA, q2));
-            const fiv Txxx3 = mul_nonneg(dxB, mul_nn(b1, q3));
-            const fiv Txxz3 = mul(dz1, mul_nonneg(twoa_minus_b(aB, b1), q3));
-            const fiv Txzz3 = mul(dxB, mul_nonneg(a_minus_twob(aB, b1), q3));
-            const fiv Txzz4 = mul(dxB, mul_nonneg(a_minus_twob(aB, b2), q4));
-            const fiv Tzzz4 = mul_nonneg(dz2, mul_nn(aB, q4));
-            // displacement products (all contain 0) and zero masks
-            const double mxi = mask(Dxi), mzi = mask(Dzi), mxj = mask(Dxj), mzj = mask(Dzj);
-            const fiv C1 = mul_zz(Dxi, Dxj), C2 = mul_zz(Dxi, Dzj), C3 = mul_zz(Dzi, Dxj), C4 = mul_zz(Dzi, Dzj);
-            const fiv Pxxi = sq_z(Dxi), Pxzi = mul_zz(Dxi, Dzi), Pzzi = sq_z(Dzi);
-            const fiv Pxxj = sq_z(Dxj), Pxzj = mul_zz(Dxj, Dzj), Pzzj = sq_z(Dzj);
-            // cross entries (node i x node i+1): +row i, -row i+1
-            div_ cx = {0.0, 0.0}, cz = {0.0, 0.0};
-            acc_neg(cx, -K3 * mxi * mxj, mul_z(Txxx1, C1));
-            acc_pos(cx, K1 * mxi * mzj, mul_z(Txxz1, C2));
-            acc_pos(cx, K1 * mzi * mxj, mul_z(Txxz2, C3));
-            acc_neg(cx, -K1 * mzi * mzj, mul_z(Txzz2, C4));
-            acc_pos(cz, K1 * mxi * mxj, mul_z(Txxz1, C1));
-            acc_neg(cz, -K1 * mxi * mzj, mul_z(Txzz1, C2));
-            acc_neg(cz, -K1 * mzi * mxj, mul_z(Txzz2, C3));
-            acc_neg(cz, -K3 * mzi * mzj, mul_z(Tzzz2, C4));
-            // row i: node i+1's own position pairs (only spring i touches them in row i)
-            rx = cx; rz = cz;
-            acc_pos(rx, K15 * mxj, mul_z(Txxx3, Pxxj));
-            acc_neg(rx, -K1 * mxj * mzj, mul_z(Txxz3, Pxzj));
-            acc_pos(rx, K05 * mzj, mul_z(Txzz4, Pzzj));
-            acc_neg(rz, -K05 * mxj, mul_z(Txxz3, Pxxj));
-            acc_pos(rz, K1 * mxj * mzj, mul_z(Txzz3, Pxzj));
-            acc_pos(rz, K15 * mzj, mul_z(Tzzz4, Pzzj));
-            // row i+1 (force -F): -(cross + node i's own position pairs)
-            div_ ax = cx, az = cz;
-            acc_pos(ax, K15 * mxi, mul_z(Txxx1, Pxxi));
-            acc_neg(ax, -K1 * mxi * mzi, mul_z(Txxz1, Pxzi));
-            acc_pos(ax, K05 * mzi, mul_z(Txzz2, Pzzi));
-            acc_neg(az, -K05 * mxi, mul_z(Txxz1, Pxxi));
-            acc_pos(az, K1 * mxi * mzi, mul_z(Txzz1, Pxzi));
-            acc_pos(az, K15 * mzi, mul_z(Tzzz2, Pzzi));
-            SpringOut o;
-            o.xlo = -ax.hi; o.xhi = -ax.lo; o.zlo = -az.hi; o.zhi = -az.lo;
-            o.t_xxx3 = Txxx3; o.t_xxz3 = Txxz3; o.t_xzz3 = Txzz3; o.t_xzz4 = Txzz4; o.t_zzz4 = Tzzz4;
+        SpringSetup st;
+        spring_setup(nom, D, i, A.L0, st);
+        AccPrimal acc;
+        SpringPieces<float> pc;
+        const bool ok = spring_core<float, AccPrimal>(st.dxA, st.dxB, st.dz0, st.dz1, st.dz2, st.Dxi, st.Dzi,
+                                                      st.Dxj, st.Dzj, maskv(st.Dxi), maskv(st.Dzi),
+                                                      maskv(st.Dxj), maskv(st.Dzj), K3, K15, K1, K05, acc, pc);
+        SpringOut o = {};
+        if (ok) {
+            rx.lo = acc.a[S_CX].lo + acc.a[S_BX].lo; rx.hi = acc.a[S_CX].hi + acc.a[S_BX].hi;
+            rz.lo = acc.a[S_CZ].lo + acc.a[S_BZ].lo; rz.hi = acc.a[S_CZ].hi + acc.a[S_BZ].hi;
+            // row i+1 receives -(cross + node i's own pairs)
+            o.xlo = -(acc.a[S_CX].hi + acc.a[S_AX].hi); o.xhi = -(acc.a[S_CX].lo + acc.a[S_AX].lo);
+            o.zlo = -(acc.a[S_CZ].hi + acc.a[S_AZ].hi); o.zhi = -(acc.a[S_CZ].lo + acc.a[S_AZ].lo);
+#pragma unroll
+            for (int q = 0; q < 5; ++q) { o.L[q] = pc.L[q]; R[q] = pc.R[q]; }
             o.unbounded = 0;
-            s_sp[lt * U + i] = o;
-            R_xxx = Txxx1; R_xxz = Txxz1; R_xzz1 = Txzz1; R_xzz2 = Txzz2; R_zzz = Tzzz2;
         } else {
-            SpringOut o = {};
+            unb = 1;
             o.unbounded = 1;
-            s_sp[lt * U + i] = o;
             atomicOr(&s_flag[lt], LEB_FLAG_UNBOUNDED);
         }
+        s_sp[lt * U + i] = o;
     }
     __syncthreads();
 
@@ -221,44 +161,29 @@ __global__ void __launch_bounds__(PBH_BLOCK) pbh_chain_fwd(ChainArgs A) {
     if (active) {
         const int th = 6 * i + 2, pxc = 6 * i, pzc = 6 * i + 1;
         const int u1 = nx + 2 * i, u2 = u1 + 1;
-        const fiv Dth = D[th], Du1 = D[u1], Du2 = D[u2], Dx = D[pxc], Dz = D[pzc];
-        const double mth = mask(Dth), mu1 = mask(Du1), mu2 = mask(Du2), mx = mask(Dx), mz = mask(Dz);
-        const double thn = nom[th];
-        const double sn = nom[u1] + nom[u2];
-        double tlo = thn + (double)Dth.lo, thi = thn + (double)Dth.hi;
-        const double et = (fabs(thn) + fabs(Dth.lo) + fabs(Dth.hi)) * 0x1p-51;
-        fiv S, Cs;
-        isincos(tlo - et, thi + et, &S, &Cs);
-        const fiv Ptt = sq_z(Dth), Ptu1 = mul_zz(Dth, Du1), Ptu2 = mul_zz(Dth, Du2);
+        IV<float> L[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) L[q] = iv(0.0f, 0.0f);
         div_ ox = rx, oz = rz;
-        const double kth = 0.5 * A.c * sn * mth;
-        acc_any(ox, kth, mul_z(S, Ptt));                 //  1/2 c s~ sin(Theta) Dth^2
-        acc_neg(ox, -A.c * mth * mu1, mul_z(Cs, Ptu1));  // -c cos(Theta) Dth Du1
-        acc_neg(ox, -A.c * mth * mu2, mul_z(Cs, Ptu2));
-        acc_any(oz, -kth, mul_z(Cs, Ptt));               // -1/2 c s~ cos(Theta) Dth^2
-        acc_neg(oz, -A.c * mth * mu1, mul_z(S, Ptu1));   // -c sin(Theta) Dth Du1
-        acc_neg(oz, -A.c * mth * mu2, mul_z(S, Ptu2));
         uint32_t row_unb = unb;
-        if (U > 1) {
-            fiv L_xxx = mk(0, 0), L_xxz = mk(0, 0), L_xzz3 = mk(0, 0), L_xzz4 = mk(0, 0), L_zzz = mk(0, 0);
-            if (i > 0) {
-                const SpringOut& o = s_sp[lt * U + i - 1];
-                row_unb |= o.unbounded;
-                ox.lo += o.xlo; ox.hi += o.xhi; oz.lo += o.zlo; oz.hi += o.zhi;
-                L_xxx = o.t_xxx3; L_xxz = o.t_xxz3; L_xzz3 = o.t_xzz3; L_xzz4 = o.t_xzz4; L_zzz = o.t_zzz4;
-            }
-            if (!row_unb) {
-                // own position pairs: right spring (+F) minus left spring (-F), summed before the product
-                const fiv Pxx = sq_z(Dx), Pxz = mul_zz(Dx, Dz), Pzz = sq_z(Dz);
-                const fiv Gxxx = sub(R_xxx, L_xxx), Gxxz = sub(R_xxz, L_xxz);
-                const fiv Gxzz_xz = sub(R_xzz1, L_xzz3), Gxzz_zz = sub(R_xzz2, L_xzz4), Gzzz = sub(R_zzz, L_zzz);
-                acc_pos(ox, K15 * mx, mul_z(Gxxx, Pxx));
-                acc_neg(ox, -K1 * mx * mz, mul_z(Gxxz, Pxz));
-                acc_pos(ox, K05 * mz, mul_z(Gxzz_zz, Pzz));
-                acc_neg(oz, -K05 * mx, mul_z(Gxxz, Pxx));
-                acc_pos(oz, K1 * mx * mz, mul_z(Gxzz_xz, Pxz));
-                acc_pos(oz, K15 * mz, mul_z(Gzzz, Pzz));
-            }
+        if (i > 0) {
+            const SpringOut& o = s_sp[lt * U + i - 1];
+            row_unb |= o.unbounded;
+            ox.lo += o.xlo; ox.hi += o.xhi; oz.lo += o.zlo; oz.hi += o.zhi;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) L[q] = o.L[q];
+        }
+        NodeTerms nt;
+        const IV<float> Dth = D[th], Du1 = D[u1], Du2 = D[u2], Dx = D[pxc], Dz = D[pzc];
+        node_terms(nom[th], nom[u1] + nom[u2], Dth, Du1, Du2, Dx, Dz, R, L, U > 1 && !row_unb, A.c, K15, K1,
+                   K05, maskv(Dth), maskv(Du1), maskv(Du2), maskv(Dx), maskv(Dz), nt);
+#pragma unroll
+        for (int q = 0; q < 12; ++q) {
+            div_& acc = node_term_row(q) == 0 ? ox : oz;
+            const float a = nt.neg[q] ? nt.T[q].hi : nt.T[q].lo;
+            const float b = nt.neg[q] ? nt.T[q].lo : nt.T[q].hi;
+            acc.lo = __builtin_fma(nt.k[q], (double)a, acc.lo);
+            acc.hi = __builtin_fma(nt.k[q], (double)b, acc.hi);
         }
         RowOut r;
         if (row_unb) {
@@ -318,7 +243,7 @@ __global__ void fill_zero_kernel(double* a, double* b, double* c, double* d, dou
 
 size_t pbh_smem_bytes(int U) {
     int T = PBH_BLOCK / U, n = 8 * U;
-    return (size_t)T * n * sizeof(double) + (size_t)T * n * sizeof(fiv) + (size_t)T * U * sizeof(SpringOut)
+    return (size_t)T * n * sizeof(double) + (size_t)T * n * sizeof(IV<float>) + (size_t)T * U * sizeof(SpringOut)
          + (size_t)T * U * sizeof(RowOut) + (size_t)T * sizeof(uint32_t) + 16;
 }
 
