@@ -82,7 +82,8 @@ typedef struct {
  *   v        [batch][N][nu]   nominal inputs v_k (may be NULL when nu == 0)
  *   mu       [batch][N][nx+nu] tube centre offsets, NULL means 0
  *   sigma    [batch][N][nx+nu] tube radii (>= 0)
- *   r_lo, r_hi [batch][N][nx] outputs (FP64, outward-rounded)
+ *   r_lo, r_hi [batch][N][nx] outputs (FP64, outward-rounded); may both be
+ *            NULL when c_bar and rho_bar are given
  *   c_bar, rho_bar [batch][N][nx] optional outputs (NULL to skip); rho_bar
  *            includes the diagonal padding `pad` (>= 0) that keeps the
  *            zonotope generator right-invertible (section V.A)
@@ -115,6 +116,43 @@ int leb_backward(const leb_dynamics* dyn, int32_t batch, int32_t N, const double
                  const double* mu, const double* sigma, const double* g_lo, const double* g_hi,
                  double* gz, double* gv, double* gmu, double* gsigma, void* stream);
 
+/* Opaque ReLU MLP prepared for the device (weights converted to FP64 and
+ * laid out for the kernels).  Owned by the library. */
+typedef struct leb_mlp_s* leb_mlp;
+
+/*
+ * leb_mlp_create -- upload a ReLU MLP g: z_l = W_l a_{l-1} + b_l,
+ * a_l = relu(z_l) (l < n_layers), g = z_{n_layers}.
+ *   widths   host [n_layers + 1]: input width, hidden widths, output width.
+ *            Every width but the output must be a multiple of 16 and at
+ *            most 256; the output at most 64; 2 <= n_layers <= 8.
+ *   W, b     host arrays of n_layers host pointers to FP32 [out][in] and
+ *            [out] (the FP32 values are used exactly, widened to FP64).
+ *   nx       the first nx inputs are the state, the rest the control
+ *   residual 1: dynamics f(x, u) = x + g(x, u) (needs nx == output width);
+ *            the remainder is then that of g.
+ * Synchronous (copies to the device).  *out receives the handle.
+ */
+int leb_mlp_create(int32_t n_layers, const int32_t* widths, const float* const* W, const float* const* b,
+                   int32_t nx, int32_t residual, leb_mlp* out);
+int leb_mlp_destroy(leb_mlp net);
+
+/*
+ * leb_nn_bound -- remainder bound of ReLU-MLP dynamics (section IV.B): CROWN
+ * affine bounds over the box (full CROWN for every hidden layer's
+ * pre-activation bounds; adaptive lower slopes) and Theorem 2 with the
+ * local Jacobian J = J_g(a~) (relu'(0) = 0).  All contractions in FP64 on
+ * MFMA with a rounding allowance, so the bound is sound.
+ *   z [batch][N][nx], v [batch][N][nu], mu (NULL = 0) and sigma
+ *   [batch][N][nx+nu], outputs r_lo, r_hi (and optional c_bar, rho_bar)
+ *   [batch][N][m], flags [batch][N] (optional), as leb_analytic_bound.
+ * Uses a library-owned grow-only workspace (about 1.5 GB at the largest
+ * chunk of 1024 boxes); calls from several host threads serialise.
+ */
+int leb_nn_bound(leb_mlp net, int32_t batch, int32_t N, const double* z, const double* v, const double* mu,
+                 const double* sigma, double* r_lo, double* r_hi, double* c_bar, double* rho_bar, double pad,
+                 uint32_t* flags, void* stream);
+
 /*
  * leb_tube_map -- tube centre and width from the residual zonotopes
  * (eqs. tight_tube_center, tight_tube_width):
@@ -133,11 +171,11 @@ int leb_tube_map(int32_t batch, int32_t N, int32_t n_units, const double* phi, c
                  const double* c_bar, const double* rho_bar, double* mu, double* sigma, void* stream);
 
 typedef struct {
-    double tol;            /* stop when max |change| / sigma <= tol (e.g. 1e-6) */
-    int32_t max_sweeps;    /* cap on bound sweeps (plain LEB evaluations of all steps) */
+    double tol;            /* relative inflation per sweep (>= 0, e.g. 1e-6): the certified tube lies
+                              about tol above the least fixed point */
+    int32_t max_sweeps;    /* cap on bound sweeps (plain LEB evaluations of all steps), >= 1 */
     double pad;            /* zonotope radius padding (>= 0) */
-    double inflate_rel;    /* candidate tube: sigma (1 + inflate_rel) + inflate_abs */
-    double inflate_abs;
+    double inflate_abs;    /* absolute inflation per sweep (> 0); floor of the relative change */
     int32_t warm;          /* 1: start from the (mu, sigma) passed in; 0: disturbance-only tube */
 } leb_fp_options;
 
@@ -145,17 +183,20 @@ typedef struct {
  * leb_fixed_point_solve -- certified tube/LEB fixed point for chain
  * dynamics (the loop of section V: bound -> zonotope -> tube map, until
  * the tube stops changing; Theorem 3 gives containment of the reachable
- * set in the tube).  Jacobi sweeps bound every (trajectory, step) at once
- * with leb_analytic_bound's kernel, then apply leb_tube_map.  After the
- * change falls below tol, the tube is inflated and accepted only if
- * F(B) lies inside B for every trajectory (a post-fixed point of the
- * inclusion-isotone map F: this certifies it); otherwise iteration goes on.
+ * set in the tube).  Each sweep bounds every (trajectory, step) at once
+ * with leb_analytic_bound's kernel and applies leb_tube_map: C' = F(C).
+ * A tube C is certified when F(C) lies inside C for every step (a
+ * post-fixed point of the inclusion-isotone map F, so the Theorem 3
+ * induction goes through).  Iteration: C <- F(C) (1 + tol) + inflate_abs
+ * on sigma (mu <- mu_F), which converges, by causality of F, in at most
+ * N + 1 sweeps to a tube about tol above the least fixed point; each
+ * trajectory is frozen at the first iterate shown to be certified.
  *   z, v    [batch][N][nx], [batch][N][nu] nominal trajectories
  *   phi, e  as leb_tube_map
  *   mu, sigma [batch][N][nx+nu] in/out: warm start in (opt->warm), certified tube out
- *   certified [batch] device uint32 out: 1 = certified, 0 = sweep cap reached
+ *   certified [batch] device uint32 out: 1 = certified, 0 = sweep cap reached first
  *   sweeps_out host int32 out: number of bound sweeps, including the certifying one
- * Synchronises `stream` once per sweep (the convergence test reads one
+ * Synchronises `stream` once per sweep (the stopping test reads one
  * value per trajectory).  Uses a library-owned, grow-only device workspace
  * (kept until process exit); calls from several host threads serialise.
  */

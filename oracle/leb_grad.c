@@ -82,7 +82,9 @@ static void kink(double* margin, double x, double scale) {
 }
 static ivd isq(ivd a, double* mg) {
     double w = a.hi.v - a.lo.v;
-    if (w > 0.0) { kink(mg, a.lo.v, w); kink(mg, a.hi.v, w); }
+    /* the branch switches when an endpoint crosses 0: a kink only if it moves */
+    if (w > 0.0 && a.lo.d != 0.0) kink(mg, a.lo.v, w);
+    if (w > 0.0 && a.hi.d != 0.0) kink(mg, a.hi.v, w);
     if (a.lo.v >= 0) return I(dmul(a.lo, a.lo), dmul(a.hi, a.hi));
     if (a.hi.v <= 0) return I(dmul(a.hi, a.hi), dmul(a.lo, a.lo));
     dd c[2] = {dmul(a.lo, a.lo), dmul(a.hi, a.hi)};

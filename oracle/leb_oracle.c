@@ -343,7 +343,7 @@ static int row_candidates(const orc_dyn* d, int l, int* ks, int* js, int cap) {
 
 /* ----------------------------------------------------------- one unit */
 
-#define MAXN 1024
+#define MAXN 4096
 #define MAXCAND 4096
 
 /* Box and displacement of one unit: Delta_i = [min(mu_i - sigma_i, 0),

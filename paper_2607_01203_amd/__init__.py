@@ -35,7 +35,7 @@ class Dynamics(ctypes.Structure):
 
 class FPOptions(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_sweeps", ctypes.c_int32), ("pad", ctypes.c_double),
-                ("inflate_rel", ctypes.c_double), ("inflate_abs", ctypes.c_double), ("warm", ctypes.c_int32)]
+                ("inflate_abs", ctypes.c_double), ("warm", ctypes.c_int32)]
 
 
 def chain_dynamics(n_units, dt=0.05, m=1.0, g=9.81, arm=0.25, inertia=0.01, k_spring=2.0,
@@ -63,6 +63,15 @@ def lib():
         L.leb_analytic_bound.restype = ctypes.c_int
         L.leb_backward.argtypes = [ctypes.POINTER(Dynamics), ctypes.c_int32, ctypes.c_int32] + [vp] * 11
         L.leb_backward.restype = ctypes.c_int
+        L.leb_mlp_create.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.POINTER(ctypes.c_float)),
+                                     ctypes.POINTER(ctypes.POINTER(ctypes.c_float)), ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_void_p)]
+        L.leb_mlp_create.restype = ctypes.c_int
+        L.leb_mlp_destroy.argtypes = [ctypes.c_void_p]
+        L.leb_mlp_destroy.restype = ctypes.c_int
+        L.leb_nn_bound.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32] + [vp] * 8 + [ctypes.c_double, vp, vp]
+        L.leb_nn_bound.restype = ctypes.c_int
         L.leb_tube_map.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp,
                                    ctypes.POINTER(ctypes.c_double), vp, vp, vp, vp, vp]
         L.leb_tube_map.restype = ctypes.c_int
@@ -206,8 +215,8 @@ def tube_map(n_units, phi, e, c_bar, rho_bar, stream=None, out=None):
     return out
 
 
-def fixed_point_solve(dyn: Dynamics, z, v, phi, e, tol=1e-6, max_sweeps=200, pad=0.0, inflate_rel=1e-6,
-                      inflate_abs=1e-12, mu=None, sigma=None, stream=None):
+def fixed_point_solve(dyn: Dynamics, z, v, phi, e, tol=1e-6, max_sweeps=200, pad=0.0, inflate_abs=1e-12,
+                      mu=None, sigma=None, stream=None):
     """Certified tube/LEB fixed point (see leb.h: leb_fixed_point_solve).
 
     Warm start when mu and sigma are given (they are updated in place).
@@ -220,7 +229,7 @@ def fixed_point_solve(dyn: Dynamics, z, v, phi, e, tol=1e-6, max_sweeps=200, pad
         mu = torch.zeros((B, N, n), dtype=torch.float64, device=z.device)
         sigma = torch.zeros((B, N, n), dtype=torch.float64, device=z.device)
     cert = torch.zeros((B,), dtype=torch.int32, device=z.device)
-    opt = FPOptions(tol, max_sweeps, pad, inflate_rel, inflate_abs, 1 if warm else 0)
+    opt = FPOptions(tol, max_sweeps, pad, inflate_abs, 1 if warm else 0)
     sweeps = ctypes.c_int32(0)
     f64 = torch.float64
     rc = lib().leb_fixed_point_solve(ctypes.byref(dyn), B, N, _dev_ptr(z, "z", f64), _dev_ptr(v, "v", f64),
@@ -229,3 +238,59 @@ def fixed_point_solve(dyn: Dynamics, z, v, phi, e, tol=1e-6, max_sweeps=200, pad
                                      _dev_ptr(cert, "certified"), ctypes.byref(sweeps), _stream(stream))
     _check(rc)
     return mu, sigma, cert, int(sweeps.value)
+
+
+class MLP:
+    """ReLU MLP uploaded to the device (see leb.h: leb_mlp_create).
+
+    W, b: lists of host float32 arrays ([out][in] and [out]); nx: state
+    inputs; residual: dynamics x + g(x, u)."""
+
+    def __init__(self, W, b, nx, residual=True):
+        import numpy as np
+        self._W = [np.ascontiguousarray(w, dtype=np.float32) for w in W]
+        self._b = [np.ascontiguousarray(x, dtype=np.float32) for x in b]
+        L = len(self._W)
+        widths = [self._W[0].shape[1]] + [w.shape[0] for w in self._W]
+        self.widths = widths
+        self.nx = int(nx)
+        self.m = widths[-1]
+        fp = ctypes.POINTER(ctypes.c_float)
+        Wp = (fp * L)(*[w.ctypes.data_as(fp) for w in self._W])
+        bp = (fp * L)(*[x.ctypes.data_as(fp) for x in self._b])
+        wd = (ctypes.c_int32 * (L + 1))(*widths)
+        h = ctypes.c_void_p()
+        _check(lib().leb_mlp_create(L, wd, Wp, bp, self.nx, 1 if residual else 0, ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().leb_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def nn_bound(mlp: MLP, z, v, sigma, mu=None, pad: float = 0.0, zonotope: bool = False, stream=None):
+    """CROWN + Theorem 2 bound for ReLU-MLP dynamics (see leb.h: leb_nn_bound).
+    z [B][N][nx], v [B][N][nu], sigma (mu) [B][N][nx+nu] float64 GPU tensors."""
+    import torch
+    B, N = int(z.shape[0]), int(z.shape[1])
+    f64 = torch.float64
+    out = {"r_lo": torch.empty((B, N, mlp.m), dtype=f64, device=z.device),
+           "r_hi": torch.empty((B, N, mlp.m), dtype=f64, device=z.device),
+           "flags": torch.empty((B, N), dtype=torch.int32, device=z.device)}
+    if zonotope:
+        out["c_bar"] = torch.empty((B, N, mlp.m), dtype=f64, device=z.device)
+        out["rho_bar"] = torch.empty((B, N, mlp.m), dtype=f64, device=z.device)
+    rc = lib().leb_nn_bound(mlp.handle, B, N, _dev_ptr(z, "z", f64), _dev_ptr(v, "v", f64), _dev_ptr(mu, "mu", f64),
+                            _dev_ptr(sigma, "sigma", f64), _dev_ptr(out["r_lo"], "r_lo", f64),
+                            _dev_ptr(out["r_hi"], "r_hi", f64), _dev_ptr(out.get("c_bar"), "c_bar", f64),
+                            _dev_ptr(out.get("rho_bar"), "rho_bar", f64), float(pad),
+                            _dev_ptr(out["flags"], "flags"), _stream(stream))
+    _check(rc)
+    return out

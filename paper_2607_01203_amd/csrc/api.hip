@@ -40,7 +40,9 @@ extern "C" int leb_analytic_bound(const leb_dynamics* dyn, int32_t batch, int32_
     const int64_t units = (int64_t)batch * (int64_t)N;
     if (units == 0) return LEB_OK;
     const int64_t nx = dyn->nx, nu = dyn->nu;
-    if (nx > 0 && (!r_lo || !r_hi)) return LEB_EINVAL;
+    // outputs come in pairs; at least one pair
+    if (!r_lo != !r_hi || !c_bar != !rho_bar) return LEB_EINVAL;
+    if (nx > 0 && !r_lo && !c_bar) return LEB_EINVAL;
     const void* ptrs[] = {z, v, mu, sigma, r_lo, r_hi, c_bar, rho_bar};
     for (const void* p : ptrs)
         if (p && !aligned8(p)) return LEB_EINVAL;

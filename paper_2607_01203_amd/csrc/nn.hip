@@ -1,0 +1,642 @@
+// nn.hip -- linearization-error bound for ReLU-MLP dynamics (section IV.B).
+//
+// Dynamics f(x, u) = x + g([x; u]) (or g alone), g a ReLU MLP
+//   z_l = W_l a_{l-1} + b_l, a_l = relu(z_l), g = z_L.
+// CROWN (Theorem "CROWN bounds", Zhang et al. Thm 3.2) gives affine bounds
+// W_lo a + b_lo <= g(a) <= W_hi a + b_hi over the box; Theorem 2 turns them
+// into the remainder bound with the local Jacobian J = J_g(a~):
+//   r_hi = max_X (W_hi - J) a + J a~ - g(a~) + b_hi, r_lo = min_X (...lo...).
+// Relaxations per neuron from pre-activation bounds [l, u]: active (l >= 0)
+// identity, inactive (u <= 0) zero, unstable: upper line s z + t with
+// s = u/(u-l), t = -s l, lower line a z with a = 1 iff u >= -l.  First-layer
+// bounds are exact; every later hidden layer gets its own full CROWN pass.
+//
+// GPU design.  Each backward substitution step
+//     Lambda_next = (Lambda (.) S) W_l      (S sign-selected slopes)
+// is a batched dense contraction run on FP64 MFMA (v_mfma_f64_16x16x4):
+// the left operand is generated on the fly from Lambda and the per-box
+// slopes, the shared weight tile is staged through LDS, and the per-row bias
+// (intercepts, Omega b_l) and rounding-term weights are accumulated while
+// the operand is generated.  The upper, lower and Jacobian chains of one
+// box share the same kernel (modes), the Jacobian chain using S = 1[z^ > 0].
+//
+// Soundness in floating point: every FP64 dot product of length <= 300 has
+// error <= 2^-44.8 times the dot product of absolute values.  Each bound
+// adds 2^-40 times the absolute-value dot products of every step (computed
+// alongside as matrix-vector products), covering the relaxation scaling,
+// the contraction, the bias sums, the concretisation, the nominal forward
+// pass and the Jacobian chain.  Upper-line slopes are rounded up so the
+// computed line stays above the ReLU on [l, u].
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "leb.h"
+#include "leb_internal.hpp"
+
+namespace leb {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr double RT = 0x1p-40;   // rounding allowance factor
+constexpr int NN_MAXW = 256;     // widest layer handled
+constexpr int NN_MAXL = 8;       // most linear layers handled
+constexpr int NN_CHUNK = 1024;   // boxes per pass
+constexpr uint32_t NN_UNSTABLE = 1u << 31;   // private per-box bit: some neuron is unstable
+
+}  // namespace leb
+
+struct leb_mlp_s {
+    int L;                          // linear layers
+    int w[leb::NN_MAXL + 1];        // widths, w[0] inputs ... w[L] outputs
+    int nx, nu, residual;
+    double* W[leb::NN_MAXL];        // device, layer l+1: [w[l+1]][w[l]]
+    double* WT[leb::NN_MAXL];       // device, transposed [w[l]][w[l+1]]
+    double* b[leb::NN_MAXL];        // device [w[l+1]]
+    std::vector<void*> allocs;
+};
+
+namespace leb {
+
+// ------------------------------------------------------------------ prep
+
+struct PrepArgs {
+    const double* z; const double* v; const double* mu; const double* sigma;
+    int64_t u0; int nbox;
+    int L; int w[NN_MAXL + 1]; int nx, nu;
+    const double* W[NN_MAXL]; const double* WT[NN_MAXL]; const double* b[NN_MAXL];
+    // outputs (chunk-local)
+    double* alpha; double* c; double* rho;                 // [box][w0]
+    double* zhat;                                          // [L-1][box][W]
+    double* lo; double* hi;                                // [L-1][box][W] (layer 1 filled here)
+    double* g; double* eg;                                 // [box][m]
+    uint32_t* flags;                                       // [box]
+};
+
+// one workgroup (256 lanes) per box
+__global__ void __launch_bounds__(256) nn_prep_kernel(PrepArgs A) {
+    __shared__ double s_a[NN_MAXW], s_m[NN_MAXW], s_v[NN_MAXW];
+    __shared__ double s_c[NN_MAXW], s_r[NN_MAXW], s_al[NN_MAXW];
+    __shared__ uint32_t s_flag;
+    const int box = blockIdx.x, q = threadIdx.x;
+    const int64_t unit = A.u0 + box;
+    const int n0 = A.w[0], m = A.w[A.L];
+    if (q == 0) s_flag = 0;
+    __syncthreads();
+    if (q < n0) {
+        const double x = q < A.nx ? A.z[unit * A.nx + q] : A.v[unit * A.nu + (q - A.nx)];
+        const double sg = A.sigma[unit * n0 + q];
+        const double mu = A.mu ? A.mu[unit * n0 + q] : 0.0;
+        uint32_t f = 0;
+        if (!isfinite(x) || !isfinite(sg) || !isfinite(mu) || !(sg >= 0.0)) f |= LEB_FLAG_BAD_INPUT;
+        if (fabs(mu) > sg) f |= LEB_FLAG_HULL_EXTENDED;
+        if (f) atomicOr(&s_flag, f);
+        // box = hull({a~}, a~ + mu +/- sigma): centre and half-width, widened
+        // so the FP64 box encloses the exact one
+        const double dlo = fmin(mu - sg, 0.0), dhi = fmax(mu + sg, 0.0);
+        const double cc = x + 0.5 * (dlo + dhi);
+        double rr = 0.5 * (dhi - dlo);
+        rr = rr + rr * 0x1p-50 + (fabs(x) + fabs(dlo) + fabs(dhi)) * 0x1p-51;
+        s_al[q] = x; s_c[q] = cc; s_r[q] = rr;
+        s_a[q] = x;                                   // forward input
+        s_m[q] = fabs(x);                             // magnitude chain (nominal pass error)
+        s_v[q] = fabs(cc - x) + rr;                   // |a - a~| bound (Jacobian error)
+        A.alpha[box * n0 + q] = x; A.c[box * n0 + q] = cc; A.rho[box * n0 + q] = rr;
+    }
+    __syncthreads();
+    // first layer bounds, exact affine image of the box
+    {
+        const int h = A.w[1];
+        if (q < h) {
+            const double* Wr = A.W[0] + (size_t)q * n0;
+            double lin = A.b[0][q], mag = 0.0, abs_ = fabs(A.b[0][q]);
+            for (int k = 0; k < n0; ++k) {
+                lin = __builtin_fma(Wr[k], s_c[k], lin);
+                mag = __builtin_fma(fabs(Wr[k]), s_r[k], mag);
+                abs_ = __builtin_fma(fabs(Wr[k]), fabs(s_c[k]), abs_);
+            }
+            const double err = RT * (abs_ + mag + fabs(lin));
+            A.lo[(size_t)box * NN_MAXW + q] = lin - mag - err;
+            A.hi[(size_t)box * NN_MAXW + q] = lin + mag + err;
+        }
+    }
+    // nominal forward pass, magnitude chains (nominal error, Jacobian error)
+    for (int l = 0; l < A.L; ++l) {
+        const int in = A.w[l], out = A.w[l + 1];
+        double z = 0.0, mz = 0.0, vz = 0.0;
+        if (q < out) {
+            const double* WT = A.WT[l];
+            z = A.b[l][q];
+            mz = fabs(A.b[l][q]);
+            for (int k = 0; k < in; ++k) {
+                const double wk = WT[(size_t)k * out + q];
+                z = __builtin_fma(wk, s_a[k], z);
+                mz = __builtin_fma(fabs(wk), s_m[k], mz);
+                vz = __builtin_fma(fabs(wk), s_v[k], vz);
+            }
+        }
+        __syncthreads();
+        if (q < out) {
+            if (l < A.L - 1) {
+                const bool on = z > 0.0;
+                A.zhat[((size_t)l * A.nbox + box) * NN_MAXW + q] = z;
+                s_a[q] = on ? z : 0.0;
+                s_m[q] = mz;
+                s_v[q] = on ? vz : 0.0;
+            } else {
+                A.g[box * m + q] = z;
+                // |g^ - g| and |(J^ - J)(a - a~)| allowances
+                A.eg[box * m + q] = RT * (mz + vz);
+            }
+        }
+        __syncthreads();
+    }
+    if (q == 0) A.flags[box] = s_flag;
+}
+
+// ---------------------------------------------------------------- relax
+
+struct RelaxArgs {
+    const double* lo; const double* hi;     // [box][W] of layer l
+    const double* amax_prev;                // [box][W] of layer l-1, or NULL (input layer: |c| + rho)
+    const double* c; const double* rho;     // [box][w0]
+    const double* WT;                       // layer l transposed [w[l-1]][w[l]]
+    const double* b;                        // [w[l]]
+    const double* zhat;                     // [box][W]
+    int in, out, n0;
+    double* s; double* t; double* a; double* D; double* e; double* amax;   // [box][W]
+    uint32_t* boxflags;                     // [box]
+};
+
+// sound relaxation coefficients and rounding weights e = zmax + |W| amax_prev + |b| + |t|
+__global__ void __launch_bounds__(256) nn_relax_kernel(RelaxArgs A) {
+    __shared__ double s_am[NN_MAXW];
+    const int box = blockIdx.x, q = threadIdx.x;
+    if (q < A.in) {
+        if (A.amax_prev) s_am[q] = A.amax_prev[(size_t)box * NN_MAXW + q];
+        else s_am[q] = fabs(A.c[box * A.n0 + q]) + A.rho[box * A.n0 + q];
+    }
+    __syncthreads();
+    const size_t o = (size_t)box * NN_MAXW + q;
+    const bool unstable = q < A.out && A.lo[o] < 0.0 && A.hi[o] > 0.0;
+    if (__syncthreads_or(unstable) && q == 0) atomicOr(&A.boxflags[box], NN_UNSTABLE);
+    if (q >= A.out) return;
+    const double l = A.lo[o], u = A.hi[o];
+    double s, t, a;
+    if (l >= 0.0) { s = 1.0; t = 0.0; a = 1.0; }
+    else if (u <= 0.0) { s = 0.0; t = 0.0; a = 0.0; }
+    else {
+        s = u / (u - l);
+        s = s + s * 0x1p-50;             // rounded up: the line stays above relu on [l, u]
+        t = -s * l;
+        t = t + t * 0x1p-50;
+        a = (u >= -l) ? 1.0 : 0.0;
+    }
+    double wa = 0.0;
+    for (int k = 0; k < A.in; ++k) wa = __builtin_fma(fabs(A.WT[(size_t)k * A.out + q]), s_am[k], wa);
+    A.s[o] = s; A.t[o] = t; A.a[o] = a;
+    A.D[o] = A.zhat[o] > 0.0 ? 1.0 : 0.0;
+    A.e[o] = fmax(fabs(l), fabs(u)) + wa + fabs(A.b[q]) + fabs(t);
+    A.amax[o] = fmax(u, 0.0);
+}
+
+// ----------------------------------------------------------------- step
+//
+// C[mode][box][M][N] = (A (.) Ssel) W   with Ssel = (A >= 0 ? spos : sneg)
+// beta[mode][box][M] (+)= sum_k (A >= 0 ? A tpos : A tneg) + sum_k Omega b
+// eps [mode][box][M] (+)= sum_k |A| e
+struct StepMode {
+    const double* spos; const double* sneg; const double* tpos; const double* tneg;   // [box][W]
+};
+
+struct StepArgs {
+    const double* A;            // shared [M][K] (a_shared) or [mode][box][M][K]
+    int a_shared;
+    StepMode md[3];
+    const double* bias;         // [K]
+    const double* e;            // [box][W]
+    const double* W;            // [K][N]
+    double* C;                  // [mode][box][M][N]
+    double* beta; double* eps;  // [mode][box][M]
+    const double* beta_init;    // [M] or NULL (accumulate)
+    int M, K, N, nbox, nmode;
+    int nact;                   // boxes in use (the rest of the chunk is idle)
+};
+
+// MFMA f64 16x16x4 operand layout (per 64-lane wave; checked on gfx950):
+// lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator
+// element i of lane l is D[4 i + l / 16][l % 16].
+template <int WR, int WC, int TPW>
+__global__ void __launch_bounds__(256) nn_step_kernel(StepArgs S) {
+    constexpr int NT = 16 * TPW * WC;
+    __shared__ double s_w[16][NT];
+    __shared__ double s_red[4][64][3];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = wave / WC, wc = wave % WC;
+    const int zidx = blockIdx.y;                 // mode * nbox + box
+    const int mode = zidx / S.nbox, box = zidx - mode * S.nbox;
+    if (box >= S.nact) return;
+    const int row = blockIdx.x * (16 * WR) + 16 * wr + (lane & 15);
+    const int kq = lane >> 4;
+    const StepMode md = S.md[mode];
+    const size_t boxW = (size_t)box * NN_MAXW;
+    const double* Arow = S.a_shared ? S.A + (size_t)row * S.K
+                                    : S.A + (((size_t)mode * S.nbox + box) * S.M + row) * S.K;
+    const bool rowok = row < S.M;
+    d4 acc[TPW];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+    double pb = 0.0, pe = 0.0;                    // per-lane partial bias / rounding sums
+    for (int kc = 0; kc < S.K; kc += 16) {
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < 16 * NT; idx += 256) {
+            const int kk = idx / NT, nn = idx - kk * NT;
+            const int k = kc + kk;
+            s_w[kk][nn] = (k < S.K && nn < S.N) ? S.W[(size_t)k * S.N + nn] : 0.0;
+        }
+        __syncthreads();
+        double av[4];
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            const int k = kc + 4 * st + kq;
+            double om = 0.0;
+            if (rowok && k < S.K) {
+                const double a = Arow[k];
+                const bool pos = a >= 0.0;
+                const double sl = pos ? md.spos[boxW + k] : md.sneg[boxW + k];
+                om = a * sl;
+                if (wc == 0) {
+                    const double* tp = pos ? md.tpos : md.tneg;
+                    if (tp) pb = __builtin_fma(a, tp[boxW + k], pb);
+                    pb = __builtin_fma(om, S.bias[k], pb);
+                    pe = __builtin_fma(fabs(a), S.e[boxW + k], pe);
+                }
+            }
+            av[st] = om;
+        }
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) {
+                const double bv = s_w[4 * st + kq][16 * (wc * TPW + t) + (lane & 15)];
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[st], bv, acc[t], 0, 0, 0);
+            }
+        }
+    }
+    // store the contraction (accumulator layout -> row-major)
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+        const int col = 16 * (wc * TPW + t) + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = blockIdx.x * (16 * WR) + 16 * wr + 4 * i + kq;
+            if (r < S.M && col < S.N)
+                S.C[(((size_t)mode * S.nbox + box) * S.M + r) * S.N + col] = acc[t][i];
+        }
+    }
+    // row sums: lanes {j, j+16, j+32, j+48} of a wave hold row j's partials
+    if (wc == 0) {
+        s_red[wr][lane][0] = pb;
+        s_red[wr][lane][1] = pe;
+    }
+    __syncthreads();
+    if (wc == 0 && lane < 16) {
+        const double b_ = s_red[wr][lane][0] + s_red[wr][lane + 16][0] + s_red[wr][lane + 32][0] + s_red[wr][lane + 48][0];
+        const double e_ = s_red[wr][lane][1] + s_red[wr][lane + 16][1] + s_red[wr][lane + 32][1] + s_red[wr][lane + 48][1];
+        const int r = blockIdx.x * (16 * WR) + 16 * wr + lane;
+        if (r < S.M) {
+            const size_t o = ((size_t)mode * S.nbox + box) * S.M + r;
+            if (S.beta_init) { S.beta[o] = S.beta_init[r] + b_; S.eps[o] = e_ + fabs(S.beta_init[r]); }
+            else { S.beta[o] += b_; S.eps[o] += e_; }
+        }
+    }
+}
+
+// ----------------------------------------------------------- concretize
+
+struct ConcArgs {
+    const double* L0;            // [mode][box][M][n0]
+    const double* beta; const double* eps;   // [mode][box][M]
+    const double* c; const double* rho;      // [box][n0]
+    int M, n0, nbox;
+    double* lo; double* hi;      // [box][W]
+};
+
+// mode 0 -> upper bound into hi, mode 1 -> lower bound into lo
+__global__ void __launch_bounds__(256) nn_concretize_kernel(ConcArgs A) {
+    const int box = blockIdx.x, r = threadIdx.x, mode = blockIdx.y;
+    if (r >= A.M) return;
+    const double* Lr = A.L0 + (((size_t)mode * A.nbox + box) * A.M + r) * A.n0;
+    const double* c = A.c + (size_t)box * A.n0;
+    const double* rho = A.rho + (size_t)box * A.n0;
+    double lin = 0.0, mag = 0.0, ab = 0.0;
+    for (int k = 0; k < A.n0; ++k) {
+        lin = __builtin_fma(Lr[k], c[k], lin);
+        mag = __builtin_fma(fabs(Lr[k]), rho[k], mag);
+        ab = __builtin_fma(fabs(Lr[k]), fabs(c[k]), ab);
+    }
+    const size_t o = ((size_t)mode * A.nbox + box) * A.M + r;
+    const double beta = A.beta[o];
+    const double err = RT * (A.eps[o] + ab + mag + fabs(beta) + fabs(lin));
+    if (mode == 0) A.hi[(size_t)box * NN_MAXW + r] = lin + mag + beta + err;
+    else A.lo[(size_t)box * NN_MAXW + r] = lin - mag + beta - err;
+}
+
+// ---------------------------------------------------------------- thm 2
+
+struct Thm2Args {
+    const double* L0;            // [3][box][m][n0]: upper, lower, Jacobian
+    const double* beta; const double* eps;   // [3][box][m]
+    const double* alpha; const double* c; const double* rho;   // [box][n0]
+    const double* g; const double* eg;        // [box][m]
+    const uint32_t* flags;       // [box]
+    int m, n0, nbox;
+    int64_t u0;
+    double* r_lo; double* r_hi; double* c_bar; double* rho_bar; double pad;
+    uint32_t* flags_out;
+};
+
+__global__ void __launch_bounds__(64) nn_thm2_kernel(Thm2Args A) {
+    const int box = blockIdx.x, i = threadIdx.x;
+    if (i >= A.m) return;
+    const size_t sz = (size_t)A.nbox * A.m;
+    const double* Lu = A.L0 + ((size_t)0 * sz + (size_t)box * A.m + i) * A.n0;
+    const double* Ll = A.L0 + ((size_t)1 * sz + (size_t)box * A.m + i) * A.n0;
+    const double* J = A.L0 + ((size_t)2 * sz + (size_t)box * A.m + i) * A.n0;
+    const double* al = A.alpha + (size_t)box * A.n0;
+    const double* c = A.c + (size_t)box * A.n0;
+    const double* rho = A.rho + (size_t)box * A.n0;
+    double hu = 0.0, hl = 0.0, mu_ = 0.0, ml = 0.0, ja = 0.0, ab = 0.0;
+    for (int k = 0; k < A.n0; ++k) {
+        const double du = Lu[k] - J[k], dl = Ll[k] - J[k];
+        hu = __builtin_fma(du, c[k], hu);
+        hl = __builtin_fma(dl, c[k], hl);
+        mu_ = __builtin_fma(fabs(du), rho[k], mu_);
+        ml = __builtin_fma(fabs(dl), rho[k], ml);
+        ja = __builtin_fma(J[k], al[k], ja);
+        ab += (fabs(du) + fabs(dl)) * fabs(c[k]) + fabs(J[k]) * fabs(al[k]);
+    }
+    const size_t ou = (size_t)box * A.m + i, ol = sz + ou;
+    const double g = A.g[ou];
+    const double bu = A.beta[ou], bl = A.beta[ol];
+    const double base = ja - g;
+    double hi = hu + mu_ + base + bu;
+    double lo = hl - ml + base + bl;
+    const double common = ab + mu_ + ml + fabs(ja) + fabs(g);
+    hi += RT * (A.eps[ou] + common + fabs(bu) + fabs(hi)) + A.eg[ou];
+    lo -= RT * (A.eps[ol] + common + fabs(bl) + fabs(lo)) + A.eg[ou];
+    // 0 = r(a~) lies in every valid bound
+    hi = fmax(hi, 0.0);
+    lo = fmin(lo, 0.0);
+    const uint32_t f = A.flags[box];
+    // no unstable neuron: g is affine on the box, so the remainder is exactly 0
+    if (!(f & NN_UNSTABLE)) { lo = 0.0; hi = 0.0; }
+    if (f & LEB_FLAG_BAD_INPUT) { lo = -INFINITY; hi = INFINITY; }
+    const int64_t o = (A.u0 + box) * A.m + i;
+    A.r_lo[o] = lo;
+    A.r_hi[o] = hi;
+    if (A.c_bar) {
+        double cb, rb;
+        if (isfinite(lo) && isfinite(hi)) {
+            cb = 0.5 * (lo + hi);
+            rb = fmax(hi - cb, cb - lo);
+            rb = rb + fabs(rb) * 0x1p-50 + A.pad;
+        } else { cb = 0.0; rb = INFINITY; }
+        A.c_bar[o] = cb;
+        A.rho_bar[o] = rb;
+    }
+    if (A.flags_out && i == 0) A.flags_out[A.u0 + box] = f & ~NN_UNSTABLE;
+}
+
+// --------------------------------------------------------------- host
+
+struct NNWorkspace {
+    std::mutex mu;
+    std::vector<void*> bufs;
+    std::vector<size_t> sizes;
+};
+static NNWorkspace g_nnws;
+
+static int nn_ws(int slot, size_t bytes, double** out) {
+    if ((int)g_nnws.bufs.size() <= slot) { g_nnws.bufs.resize(slot + 1, nullptr); g_nnws.sizes.resize(slot + 1, 0); }
+    if (g_nnws.sizes[slot] < bytes) {
+        if (g_nnws.bufs[slot]) (void)hipFree(g_nnws.bufs[slot]);
+        g_nnws.bufs[slot] = nullptr;
+        g_nnws.sizes[slot] = 0;
+        if (getenv("LEB_TEST_FAIL_ALLOC")) return LEB_ENOMEM;
+        if (hipMalloc(&g_nnws.bufs[slot], bytes) != hipSuccess) return LEB_ENOMEM;
+        g_nnws.sizes[slot] = bytes;
+    }
+    *out = (double*)g_nnws.bufs[slot];
+    return LEB_OK;
+}
+
+static int launch_step(const StepArgs& s, hipStream_t st) {
+    dim3 grid, block(256);
+    if (s.N % 16 != 0 || s.N > 256 || s.K % 16 != 0) return LEB_ENOTSUP;
+    const int tiles = s.N / 16;
+    const int z = s.nmode * s.nbox;
+    if (s.M <= 16 && tiles % 4 == 0) {
+        grid = dim3(1, z);
+        switch (tiles / 4) {
+        case 1: hipLaunchKernelGGL((nn_step_kernel<1, 4, 1>), grid, block, 0, st, s); break;
+        case 2: hipLaunchKernelGGL((nn_step_kernel<1, 4, 2>), grid, block, 0, st, s); break;
+        case 4: hipLaunchKernelGGL((nn_step_kernel<1, 4, 4>), grid, block, 0, st, s); break;
+        default: return LEB_ENOTSUP;
+        }
+    } else {
+        grid = dim3((s.M + 63) / 64, z);
+        switch (tiles) {
+        case 1: hipLaunchKernelGGL((nn_step_kernel<4, 1, 1>), grid, block, 0, st, s); break;
+        case 2: hipLaunchKernelGGL((nn_step_kernel<4, 1, 2>), grid, block, 0, st, s); break;
+        case 4: hipLaunchKernelGGL((nn_step_kernel<4, 1, 4>), grid, block, 0, st, s); break;
+        case 8: hipLaunchKernelGGL((nn_step_kernel<4, 1, 8>), grid, block, 0, st, s); break;
+        case 16: hipLaunchKernelGGL((nn_step_kernel<4, 1, 16>), grid, block, 0, st, s); break;
+        default: return LEB_ENOTSUP;
+        }
+    }
+    return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
+}
+
+}  // namespace leb
+
+using namespace leb;
+
+extern "C" int leb_mlp_create(int32_t n_layers, const int32_t* widths, const float* const* W,
+                              const float* const* b, int32_t nx, int32_t residual, leb_mlp* out) {
+    if (!out || !widths || !W || !b) return LEB_EINVAL;
+    *out = nullptr;
+    if (n_layers < 2 || n_layers > NN_MAXL) return LEB_ENOTSUP;
+    for (int l = 0; l <= n_layers; ++l)
+        if (widths[l] < 1) return LEB_EINVAL;
+    for (int l = 0; l < n_layers; ++l) {
+        if (widths[l] > NN_MAXW || widths[l] % 16 != 0) return LEB_ENOTSUP;
+        if (!W[l] || !b[l]) return LEB_EINVAL;
+    }
+    if (widths[n_layers] > 64) return LEB_ENOTSUP;
+    if (nx < 0 || nx > widths[0]) return LEB_EINVAL;
+    if (residual && nx != widths[n_layers]) return LEB_EINVAL;
+    leb_mlp_s* net = new leb_mlp_s();
+    net->L = n_layers;
+    for (int l = 0; l <= n_layers; ++l) net->w[l] = widths[l];
+    net->nx = nx;
+    net->nu = widths[0] - nx;
+    net->residual = residual ? 1 : 0;
+    for (int l = 0; l < n_layers; ++l) {
+        const int in = widths[l], o = widths[l + 1];
+        std::vector<double> w((size_t)in * o), wt((size_t)in * o), bb(o);
+        for (int r = 0; r < o; ++r) {
+            for (int k = 0; k < in; ++k) {
+                const double x = (double)W[l][(size_t)r * in + k];
+                if (!isfinite(x)) { leb_mlp_destroy(net); return LEB_EINVAL; }
+                w[(size_t)r * in + k] = x;
+                wt[(size_t)k * o + r] = x;
+            }
+            bb[r] = (double)b[l][r];
+            if (!isfinite(bb[r])) { leb_mlp_destroy(net); return LEB_EINVAL; }
+        }
+        void *p1 = nullptr, *p2 = nullptr, *p3 = nullptr;
+        if (getenv("LEB_TEST_FAIL_ALLOC") || hipMalloc(&p1, w.size() * 8) != hipSuccess ||
+            hipMalloc(&p2, wt.size() * 8) != hipSuccess || hipMalloc(&p3, bb.size() * 8) != hipSuccess) {
+            if (p1) (void)hipFree(p1);
+            if (p2) (void)hipFree(p2);
+            if (p3) (void)hipFree(p3);
+            leb_mlp_destroy(net);
+            return LEB_ENOMEM;
+        }
+        net->allocs.push_back(p1); net->allocs.push_back(p2); net->allocs.push_back(p3);
+        if (hipMemcpy(p1, w.data(), w.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(p2, wt.data(), wt.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(p3, bb.data(), bb.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
+            leb_mlp_destroy(net);
+            return LEB_EDEVICE;
+        }
+        net->W[l] = (double*)p1; net->WT[l] = (double*)p2; net->b[l] = (double*)p3;
+    }
+    *out = net;
+    return LEB_OK;
+}
+
+extern "C" int leb_mlp_destroy(leb_mlp net) {
+    if (!net) return LEB_OK;
+    for (void* p : net->allocs) (void)hipFree(p);
+    delete net;
+    return LEB_OK;
+}
+
+extern "C" int leb_nn_bound(leb_mlp net, int32_t batch, int32_t N, const double* z, const double* v, const double* mu,
+                            const double* sigma, double* r_lo, double* r_hi, double* c_bar, double* rho_bar, double pad,
+                            uint32_t* flags, void* stream) {
+    if (!net) return LEB_EINVAL;
+    if (batch < 0 || N < 0 || !(pad >= 0.0) || !isfinite(pad)) return LEB_EINVAL;
+    if ((c_bar == nullptr) != (rho_bar == nullptr)) return LEB_EINVAL;
+    const int64_t units = (int64_t)batch * N;
+    if (units == 0) return LEB_OK;
+    if (!z || !sigma || !r_lo || !r_hi || (net->nu > 0 && !v) || (net->nx > 0 && !z)) return LEB_EINVAL;
+    const void* ptrs[] = {z, v, mu, sigma, r_lo, r_hi, c_bar, rho_bar};
+    for (const void* p : ptrs)
+        if (p && !aligned8(p)) return LEB_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const int L = net->L, n0 = net->w[0], m = net->w[L];
+    std::lock_guard<std::mutex> lock(g_nnws.mu);
+    const int CB = (int)(units < NN_CHUNK ? units : NN_CHUNK);
+    const size_t per = (size_t)CB * NN_MAXW * 8;
+    double *alpha, *c, *rho, *zhat, *lo, *hi, *g, *eg, *s, *t, *a, *D, *e, *amax, *bufA, *bufB, *beta, *eps, *beta2, *eps2;
+    double* fl_d;
+    int rc;
+    const size_t lam = (size_t)CB * 3 * NN_MAXW * NN_MAXW * 8;
+    if ((rc = nn_ws(0, (size_t)CB * n0 * 8, &alpha)) || (rc = nn_ws(1, (size_t)CB * n0 * 8, &c)) ||
+        (rc = nn_ws(2, (size_t)CB * n0 * 8, &rho)) || (rc = nn_ws(3, per * (L - 1), &zhat)) ||
+        (rc = nn_ws(4, per * (L - 1), &lo)) || (rc = nn_ws(5, per * (L - 1), &hi)) ||
+        (rc = nn_ws(6, (size_t)CB * m * 8, &g)) || (rc = nn_ws(7, (size_t)CB * m * 8, &eg)) ||
+        (rc = nn_ws(8, per * (L - 1), &s)) || (rc = nn_ws(9, per * (L - 1), &t)) ||
+        (rc = nn_ws(10, per * (L - 1), &a)) || (rc = nn_ws(11, per * (L - 1), &D)) ||
+        (rc = nn_ws(12, per * (L - 1), &e)) || (rc = nn_ws(13, per * (L - 1), &amax)) ||
+        (rc = nn_ws(14, lam, &bufA)) || (rc = nn_ws(15, lam, &bufB)) ||
+        (rc = nn_ws(16, (size_t)CB * 3 * NN_MAXW * 8, &beta)) || (rc = nn_ws(17, (size_t)CB * 3 * NN_MAXW * 8, &eps)) ||
+        (rc = nn_ws(18, (size_t)CB * 3 * NN_MAXW * 8, &beta2)) || (rc = nn_ws(19, (size_t)CB * 3 * NN_MAXW * 8, &eps2)) ||
+        (rc = nn_ws(20, (size_t)CB * 8, &fl_d)))
+        return rc;
+    uint32_t* fl = (uint32_t*)fl_d;
+    auto layer = [&](double* base, int l) { return base + (size_t)l * CB * NN_MAXW; };   // hidden layer l+1
+
+    for (int64_t u0 = 0; u0 < units; u0 += CB) {
+        const int nb = (int)((units - u0) < CB ? (units - u0) : CB);
+        PrepArgs pa;
+        pa.z = z; pa.v = v; pa.mu = mu; pa.sigma = sigma; pa.u0 = u0; pa.nbox = CB;
+        pa.L = L;
+        for (int l = 0; l <= L; ++l) pa.w[l] = net->w[l];
+        pa.nx = net->nx; pa.nu = net->nu;
+        for (int l = 0; l < L; ++l) { pa.W[l] = net->W[l]; pa.WT[l] = net->WT[l]; pa.b[l] = net->b[l]; }
+        pa.alpha = alpha; pa.c = c; pa.rho = rho; pa.zhat = zhat; pa.lo = lo; pa.hi = hi; pa.g = g; pa.eg = eg;
+        pa.flags = fl;
+        hipLaunchKernelGGL(nn_prep_kernel, dim3(nb), dim3(256), 0, st, pa);
+        if (hipGetLastError() != hipSuccess) return LEB_EDEVICE;
+        auto relax = [&](int l) -> int {     // hidden layer l+1 (0-based l)
+            RelaxArgs ra;
+            ra.lo = layer(lo, l); ra.hi = layer(hi, l);
+            ra.amax_prev = l == 0 ? nullptr : layer(amax, l - 1);
+            ra.c = c; ra.rho = rho;
+            ra.WT = net->WT[l]; ra.b = net->b[l]; ra.zhat = layer(zhat, l);
+            ra.in = net->w[l]; ra.out = net->w[l + 1]; ra.n0 = n0;
+            ra.s = layer(s, l); ra.t = layer(t, l); ra.a = layer(a, l); ra.D = layer(D, l);
+            ra.e = layer(e, l); ra.amax = layer(amax, l);
+            ra.boxflags = fl;
+            hipLaunchKernelGGL(nn_relax_kernel, dim3(nb), dim3(256), 0, st, ra);
+            return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
+        };
+        if ((rc = relax(0))) return rc;
+        // backward chain for target layer k (1-based, 2..L): modes 0 upper, 1 lower (, 2 Jacobian)
+        auto chain = [&](int k, int nmode, double** lam_out, double** beta_out, double** eps_out) -> int {
+            const int M = net->w[k];
+            double* src = nullptr;
+            double* dst = bufA;
+            double* bt = beta; double* ep = eps;
+            for (int j = k - 1; j >= 1; --j) {        // relax hidden layer j, multiply by W_j
+                StepArgs sa = {};
+                sa.a_shared = (j == k - 1);
+                sa.A = sa.a_shared ? net->W[k - 1] : src;
+                const int jl = j - 1;
+                sa.md[0] = {layer(s, jl), layer(a, jl), layer(t, jl), nullptr};
+                sa.md[1] = {layer(a, jl), layer(s, jl), nullptr, layer(t, jl)};
+                sa.md[2] = {layer(D, jl), layer(D, jl), nullptr, nullptr};
+                sa.bias = net->b[j - 1];
+                sa.e = layer(e, jl);
+                sa.W = net->W[j - 1];
+                sa.C = dst;
+                sa.beta = bt; sa.eps = ep;
+                sa.beta_init = (j == k - 1) ? net->b[k - 1] : nullptr;
+                sa.M = M; sa.K = net->w[j]; sa.N = net->w[j - 1]; sa.nbox = CB; sa.nmode = nmode; sa.nact = nb;
+                if ((rc = launch_step(sa, st))) return rc;
+                src = dst;
+                dst = (dst == bufA) ? bufB : bufA;
+            }
+            *lam_out = src; *beta_out = bt; *eps_out = ep;
+            return LEB_OK;
+        };
+        for (int k = 2; k <= L - 1; ++k) {
+            double *L0, *bt, *ep;
+            if ((rc = chain(k, 2, &L0, &bt, &ep))) return rc;
+            ConcArgs ca;
+            ca.L0 = L0; ca.beta = bt; ca.eps = ep; ca.c = c; ca.rho = rho;
+            ca.M = net->w[k]; ca.n0 = n0; ca.nbox = CB;
+            ca.lo = layer(lo, k - 1); ca.hi = layer(hi, k - 1);
+            hipLaunchKernelGGL(nn_concretize_kernel, dim3(nb, 2), dim3(256), 0, st, ca);
+            if (hipGetLastError() != hipSuccess) return LEB_EDEVICE;
+            if ((rc = relax(k - 1))) return rc;
+        }
+        double *L0, *bt, *ep;
+        if ((rc = chain(L, 3, &L0, &bt, &ep))) return rc;
+        Thm2Args ta;
+        ta.L0 = L0; ta.beta = bt; ta.eps = ep; ta.alpha = alpha; ta.c = c; ta.rho = rho; ta.g = g; ta.eg = eg;
+        ta.flags = fl; ta.m = m; ta.n0 = n0; ta.nbox = CB; ta.u0 = u0;
+        ta.r_lo = r_lo; ta.r_hi = r_hi; ta.c_bar = c_bar; ta.rho_bar = rho_bar; ta.pad = pad; ta.flags_out = flags;
+        hipLaunchKernelGGL(nn_thm2_kernel, dim3(nb), dim3(64), 0, st, ta);
+        if (hipGetLastError() != hipSuccess) return LEB_EDEVICE;
+    }
+    return LEB_OK;
+}

@@ -234,7 +234,7 @@ __global__ void fill_zero_kernel(double* a, double* b, double* c, double* d, dou
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t k = idx; k < count; k += stride) {
-        a[k] = 0.0; b[k] = 0.0;
+        if (a) { a[k] = 0.0; b[k] = 0.0; }
         if (c) { c[k] = 0.0; d[k] = pad; }
     }
     if (flags)

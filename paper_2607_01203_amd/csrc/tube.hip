@@ -13,6 +13,15 @@
 // Theorem 3 proof).  Jacobi sweeps update every k at once; causality (the
 // tube at k uses steps j < k) bounds the number of sweeps to reach the
 // exact fixed point by N.
+//
+// Certification.  Where the bounds grow faster than linearly in the tube
+// radius and exceed the disturbance, F expands locally, so no uniform
+// inflation of the least fixed point B* is a post-fixed point.  The causal
+// structure (the Jacobian of F is nilpotent) still gives post-fixed points
+// B* + (I - J)^-1 w for any w > 0, and the inflated Jacobi iteration
+//   C <- F(C) (1 + tol) + abs
+// converges to one of them, about tol above B*.  A trajectory is certified
+// (and frozen) on the sweep that shows F(C) inside C.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -74,45 +83,57 @@ __global__ void __launch_bounds__(256) tube_map_kernel(TubeArgs A) {
     for (int r = 0; r < 2; ++r) { mo[nx + 2 * i + r] = m[6 + r]; so[nx + 2 * i + r] = s[6 + r] + s[6 + r] * 0x1p-45; }
 }
 
-// per trajectory: max over entries of |new - old| / max(sigma_new, tiny)
-// (mode 0) or containment of box(new) in box(old) (mode 1, result 0/1)
+// Per trajectory: out[2b] = max over entries of max(|dsigma|, |dmu|) /
+// max(sigma_new, floor) (relative change), out[2b+1] = 1 if box(new) lies in
+// box(old) for every entry (containment), else 0.
 __global__ void __launch_bounds__(256) tube_compare_kernel(const double* mu_old, const double* sg_old,
                                                           const double* mu_new, const double* sg_new,
-                                                          int64_t per_traj, int mode, double* out) {
+                                                          int64_t per_traj, double floor_, double* out) {
     __shared__ double red[256];
+    __shared__ int bad[256];
     const int b = blockIdx.x;
     const double* mo = mu_old + (int64_t)b * per_traj;
     const double* so = sg_old + (int64_t)b * per_traj;
     const double* mn = mu_new + (int64_t)b * per_traj;
     const double* sn = sg_new + (int64_t)b * per_traj;
     double acc = 0.0;
+    int nok = 0;
     for (int64_t q = threadIdx.x; q < per_traj; q += 256) {
-        if (mode == 0) {
-            const double den = fmax(sn[q], 1e-300);
-            const double d = fmax(fabs(sn[q] - so[q]), fabs(mn[q] - mo[q])) / den;
-            acc = fmax(acc, (sn[q] == so[q] && mn[q] == mo[q]) ? 0.0 : d);
-        } else {
-            const bool ok = (mn[q] - sn[q] >= mo[q] - so[q]) && (mn[q] + sn[q] <= mo[q] + so[q]);
-            acc = fmax(acc, ok ? 0.0 : 1.0);
-        }
+        const double d = fmax(fabs(sn[q] - so[q]), fabs(mn[q] - mo[q]));
+        acc = fmax(acc, d / fmax(sn[q], floor_));
+        if (!(isfinite(sn[q]) && isfinite(mn[q])) && !(sn[q] == so[q] && mn[q] == mo[q])) acc = INFINITY;
+        const bool ok = (mn[q] - sn[q] >= mo[q] - so[q]) && (mn[q] + sn[q] <= mo[q] + so[q]);
+        nok |= ok ? 0 : 1;
     }
     red[threadIdx.x] = acc;
+    bad[threadIdx.x] = nok;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        if (threadIdx.x < w) {
+            red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+            bad[threadIdx.x] |= bad[threadIdx.x + w];
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[b] = red[0];
+    if (threadIdx.x == 0) { out[2 * b] = red[0]; out[2 * b + 1] = bad[0] ? 0.0 : 1.0; }
 }
 
-__global__ void inflate_kernel(const double* sg, double* out, int64_t count, double rel, double abs_) {
+// Next iterate of the inflated Jacobi map for trajectories not yet certified:
+// mu <- mu_F, sigma <- sigma_F (1 + rel) + abs (rounded up).
+__global__ void advance_kernel(const double* mu_f, const double* sg_f, double* mu, double* sg, const double* cmp,
+                               int64_t per_traj, int64_t count, double rel, double abs_) {
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < count) out[q] = sg[q] + sg[q] * rel + abs_;
+    if (q >= count) return;
+    const int64_t b = q / per_traj;
+    if (cmp[2 * b + 1] != 0.0) return;        // certified: frozen
+    const double s = sg_f[q] + sg_f[q] * rel + abs_;
+    mu[q] = mu_f[q];
+    sg[q] = s + s * 0x1p-50;
 }
 
-__global__ void copy_kernel(const double* src, double* dst, int64_t count) {
-    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < count) dst[q] = src[q];
+__global__ void cert_from_cmp(const double* cmp, uint32_t* out, int B) {
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < B) out[b] = cmp[2 * b + 1] != 0.0 ? 1u : 0u;
 }
 
 __global__ void fill_kernel(double* dst, int64_t count, double v) {
@@ -120,9 +141,12 @@ __global__ void fill_kernel(double* dst, int64_t count, double v) {
     if (q < count) dst[q] = v;
 }
 
-__global__ void cert_to_u32(const double* cmp, uint32_t* out, int B) {
+// cmp[2b+1] |= cmpn[2b+1] (certified once contained); cmp[2b] = latest change
+__global__ void merge_cert_kernel(double* cmp, const double* cmpn, int B) {
     int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < B) out[b] = cmp[b] == 0.0 ? 1u : 0u;
+    if (b >= B) return;
+    cmp[2 * b] = cmpn[2 * b];
+    if (cmpn[2 * b + 1] != 0.0) cmp[2 * b + 1] = 1.0;
 }
 
 static unsigned nblk(int64_t count) { return (unsigned)((count + 255) / 256); }
@@ -190,8 +214,8 @@ extern "C" int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int
     if (dyn->kind != LEB_DYN_PQUAD_CHAIN) return LEB_ENOTSUP;
     if (!opt || !e || !sweeps_out) return LEB_EINVAL;
     if (batch < 0 || N < 0) return LEB_EINVAL;
-    if (!(opt->tol > 0.0) || opt->max_sweeps < 1 || !(opt->pad >= 0.0) || !(opt->inflate_rel >= 0.0) ||
-        !(opt->inflate_abs >= 0.0))
+    if (!(opt->tol >= 0.0) || !isfinite(opt->tol) || opt->max_sweeps < 1 || !(opt->pad >= 0.0) ||
+        !(opt->inflate_abs > 0.0) || !isfinite(opt->inflate_abs))
         return LEB_EINVAL;
     for (int q = 0; q < 6; ++q)
         if (!(e[q] >= 0.0) || !isfinite(e[q])) return LEB_EINVAL;
@@ -206,62 +230,55 @@ extern "C" int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int
     hipStream_t s = (hipStream_t)stream;
 
     std::lock_guard<std::mutex> lock(g_ws.mu);
-    double *cb, *rb, *mu2, *sg2, *sgc, *cmp, *cmp_h;
+    double *cb, *rb, *mu2, *sg2, *cmp, *cmpn;
     const size_t bx = (size_t)units * nx * sizeof(double), bn = (size_t)units * n * sizeof(double);
     if ((rc = ws_get(0, bx, (void**)&cb)) || (rc = ws_get(1, bx, (void**)&rb)) ||
         (rc = ws_get(2, bn, (void**)&mu2)) || (rc = ws_get(3, bn, (void**)&sg2)) ||
-        (rc = ws_get(4, bn, (void**)&sgc)) || (rc = ws_get(5, (size_t)batch * sizeof(double), (void**)&cmp)))
+        (rc = ws_get(4, (size_t)batch * 2 * sizeof(double), (void**)&cmp)) ||
+        (rc = ws_get(5, (size_t)batch * 2 * sizeof(double), (void**)&cmpn)))
         return rc;
-    std::vector<double> host(batch);
-    cmp_h = host.data();
+    std::vector<double> host(2 * (size_t)batch);
     const int64_t cnt = units * n;
     auto ok = [](hipError_t e_) { return e_ == hipSuccess; };
-
-    // start: warm tube (mu, sigma as given) or the disturbance-only tube (LEB = 0)
-    if (!opt->warm) {
+    int sweeps = 0;
+    // F: bound every unit of box (m_, s_) then map to (mo, so)
+    auto F = [&](const double* m_, const double* s_, double* mo, double* so) -> int {
+        int r = launch_pbh_chain(dyn, units, z, v, m_, s_, nullptr, nullptr, cb, rb, opt->pad, nullptr, s);
+        if (r) return r;
+        if ((r = launch_tube_map(batch, N, U, phi, e, cb, rb, mo, so, s))) return r;
+        ++sweeps;
+        return LEB_OK;
+    };
+    if (!opt->warm) {       // disturbance-only tube (LEB = 0): below the fixed point
         hipLaunchKernelGGL(fill_kernel, dim3(nblk(units * nx)), dim3(256), 0, s, cb, units * nx, 0.0);
         hipLaunchKernelGGL(fill_kernel, dim3(nblk(units * nx)), dim3(256), 0, s, rb, units * nx, opt->pad);
         if ((rc = launch_tube_map(batch, N, U, phi, e, cb, rb, mu, sigma, s))) return rc;
     }
-    int sweeps = 0;
-    bool certifying = false;
-    while (true) {
-        if (sweeps >= opt->max_sweeps) break;
-        const double* sg_eval = sigma;
-        if (certifying) {   // inflated candidate
-            hipLaunchKernelGGL(inflate_kernel, dim3(nblk(cnt)), dim3(256), 0, s, sigma, sgc, cnt,
-                               opt->inflate_rel, opt->inflate_abs);
-            sg_eval = sgc;
-        }
-        if ((rc = launch_pbh_chain(dyn, units, z, v, mu, sg_eval, nullptr, nullptr, cb, rb, opt->pad, nullptr, s)))
-            return rc;
-        if ((rc = launch_tube_map(batch, N, U, phi, e, cb, rb, mu2, sg2, s))) return rc;
-        ++sweeps;
-        hipLaunchKernelGGL(tube_compare_kernel, dim3(batch), dim3(256), 0, s, mu, sg_eval, mu2, sg2, (int64_t)N * n,
-                           certifying ? 1 : 0, cmp);
+    // Inflated Jacobi: C <- F(C) (1 + tol) + abs until F(C) lies inside C.
+    // A trajectory is frozen (and certified) from the sweep that shows it.
+    hipLaunchKernelGGL(fill_kernel, dim3(nblk(2 * (int64_t)batch)), dim3(256), 0, s, cmp, 2 * (int64_t)batch, 0.0);
+    while (sweeps < opt->max_sweeps) {
+        if ((rc = F(mu, sigma, mu2, sg2))) return rc;
+        // containment per trajectory, accumulated (frozen trajectories stay certified)
+        hipLaunchKernelGGL(tube_compare_kernel, dim3(batch), dim3(256), 0, s, mu, sigma, mu2, sg2, (int64_t)N * n,
+                           opt->inflate_abs, cmpn);
+        hipLaunchKernelGGL(merge_cert_kernel, dim3(nblk(batch)), dim3(256), 0, s, cmp, cmpn, batch);
         if (!ok(hipGetLastError())) return LEB_EDEVICE;
-        if (!ok(hipMemcpyAsync(cmp_h, cmp, batch * sizeof(double), hipMemcpyDeviceToHost, s)) ||
+        if (!ok(hipMemcpyAsync(host.data(), cmp, 2 * (size_t)batch * sizeof(double), hipMemcpyDeviceToHost, s)) ||
             !ok(hipStreamSynchronize(s)))
             return LEB_EDEVICE;
-        double worst = 0.0;
-        for (int b = 0; b < batch; ++b) worst = fmax(worst, cmp_h[b]);
-        if (certifying) {
-            if (worst == 0.0) {          // every trajectory certified: return the inflated tube
-                hipLaunchKernelGGL(copy_kernel, dim3(nblk(cnt)), dim3(256), 0, s, sgc, sigma, cnt);
-                hipLaunchKernelGGL(cert_to_u32, dim3(nblk(batch)), dim3(256), 0, s, cmp, certified, batch);
-                *sweeps_out = sweeps;
-                return ok(hipGetLastError()) ? LEB_OK : LEB_EDEVICE;
-            }
-            certifying = false;          // keep iterating from F(B)
-        } else if (worst <= opt->tol) {
-            certifying = true;
+        bool all = true;
+        for (int b = 0; b < batch; ++b) all = all && host[2 * b + 1] != 0.0;
+        if (all) {
+            hipLaunchKernelGGL(cert_from_cmp, dim3(nblk(batch)), dim3(256), 0, s, cmp, certified, batch);
+            *sweeps_out = sweeps;
+            return ok(hipGetLastError()) ? LEB_OK : LEB_EDEVICE;
         }
-        hipLaunchKernelGGL(copy_kernel, dim3(nblk(cnt)), dim3(256), 0, s, mu2, mu, cnt);
-        hipLaunchKernelGGL(copy_kernel, dim3(nblk(cnt)), dim3(256), 0, s, sg2, sigma, cnt);
+        hipLaunchKernelGGL(advance_kernel, dim3(nblk(cnt)), dim3(256), 0, s, mu2, sg2, mu, sigma, cmp, (int64_t)N * n, cnt,
+                           opt->tol, opt->inflate_abs);
     }
-    // sweep budget exhausted: report per-trajectory containment of the last tube (not certified)
-    hipLaunchKernelGGL(fill_kernel, dim3(nblk(batch)), dim3(256), 0, s, cmp, batch, 1.0);
-    hipLaunchKernelGGL(cert_to_u32, dim3(nblk(batch)), dim3(256), 0, s, cmp, certified, batch);
+    // sweep budget exhausted: report which trajectories were certified
+    hipLaunchKernelGGL(cert_from_cmp, dim3(nblk(batch)), dim3(256), 0, s, cmp, certified, batch);
     *sweeps_out = sweeps;
     return ok(hipGetLastError()) ? LEB_OK : LEB_EDEVICE;
 }

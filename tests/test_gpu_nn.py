@@ -1,0 +1,117 @@
+"""GPU CROWN + Theorem 2 bound (leb_nn_bound) against the NN oracle: the
+16-256-256-256-12 workload, other widths and depths, ragged chunks, stable
+boxes, off-centre boxes, bad inputs and 10^6-sample soundness."""
+import numpy as np
+import pytest
+
+import workloads as W
+from parity import check_bounds
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2607_01203_amd as leb
+    leb.lib()
+    return torch.device("cuda:0")
+
+
+def _t(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _run(leb, net, z, v, sg, dev, mu=None, zonotope=False):
+    import torch
+    mlp = leb.MLP(net.W, net.b, net.nx, True)
+    out = leb.nn_bound(mlp, _t(z, dev), _t(v, dev), _t(sg, dev), None if mu is None else _t(mu, dev),
+                       zonotope=zonotope)
+    torch.cuda.synchronize()
+    res = {k: x.cpu().numpy() for k, x in out.items()}
+    mlp.close()
+    return res
+
+
+def _oracle(net, z, v, sg, mu=None):
+    from oracle import nn
+    a = np.concatenate([z, v], -1)
+    return nn.leb(net.W, net.b, a, sg, mu=mu)
+
+
+def test_nn_small_slice_parity(gpu):
+    import paper_2607_01203_amd as leb
+    b = W.nn_cfg()
+    z, v, sg = b.z[:2, :7], b.v[:2, :7], b.sigma[:2, :7]
+    print("case: nn 16-256x3-12, 14 boxes", flush=True)
+    g = _run(leb, b.net, z, v, sg, gpu)
+    o = _oracle(b.net, z, v, sg)
+    print("worst", check_bounds(g["r_lo"], g["r_hi"], o["r_lo"], o["r_hi"], "nn small"))
+    assert (g["flags"] == 0).all()
+
+
+def test_nn_full_config_sampled(gpu):
+    """64 trajectories x 50 steps (3200 boxes, 4 chunks of work): oracle on a sample."""
+    import paper_2607_01203_amd as leb
+    b = W.nn_cfg()
+    print("case: nn full 64x50", flush=True)
+    g = _run(leb, b.net, b.z, b.v, b.sigma, gpu, zonotope=True)
+    idx = np.random.default_rng(0).choice(3200, 120, replace=False)
+    bt, kt = idx // 50, idx % 50
+    o = _oracle(b.net, b.z[bt, kt], b.v[bt, kt], b.sigma[bt, kt])
+    print("worst", check_bounds(g["r_lo"][bt, kt], g["r_hi"][bt, kt], o["r_lo"], o["r_hi"], "nn full"))
+    assert (g["c_bar"] - g["rho_bar"] <= g["r_lo"]).all() and (g["c_bar"] + g["rho_bar"] >= g["r_hi"]).all()
+
+
+@pytest.mark.parametrize("widths,nx", [([16, 128, 128, 128, 12], 12), ([32, 64, 64, 8], 8), ([16, 48, 16], 16)])
+def test_nn_other_shapes(gpu, widths, nx):
+    import paper_2607_01203_amd as leb
+    rng = W.rng_for(77)
+    Wl, bl = W.mlp_weights(rng, widths)
+    net = W.MLPNet(Wl, bl, nx, widths[0] - nx, True)
+    a = rng.uniform(-1, 1, (3, 5, widths[0]))
+    sg = rng.uniform(0.005, 0.05, (3, 5, widths[0]))
+    print("case: nn widths %s" % widths, flush=True)
+    g = _run(leb, net, a[..., :nx].copy(), a[..., nx:].copy(), sg, gpu)
+    o = _oracle(net, a[..., :nx], a[..., nx:], sg)
+    check_bounds(g["r_lo"], g["r_hi"], o["r_lo"], o["r_hi"], "widths %s" % widths)
+
+
+def test_nn_stable_offcentre_and_bad(gpu):
+    import paper_2607_01203_amd as leb
+    b = W.nn_cfg()
+    z, v = b.z[:1, :6].copy(), b.v[:1, :6].copy()
+    sg = b.sigma[:1, :6].copy()
+    sg[0, 0] = 1e-9                                    # stable box: bound ~ [0, 0]
+    mu = np.random.default_rng(1).uniform(-0.02, 0.02, sg.shape)
+    mu[0, 0] = 0.0
+    z[0, 5, 3] = np.nan                                # invalid data
+    print("case: nn stable / off-centre / bad", flush=True)
+    g = _run(leb, b.net, z, v, sg, gpu, mu=mu)
+    o = _oracle(b.net, z[:, :5], v[:, :5], sg[:, :5], mu=mu[:, :5])
+    check_bounds(g["r_lo"][:, :5], g["r_hi"][:, :5], o["c_lo"], o["c_hi"], "nn off-centre")
+    assert np.abs(g["r_hi"][0, 0]).max() < 1e-9 and np.abs(g["r_lo"][0, 0]).max() < 1e-9
+    assert np.isinf(g["r_lo"][0, 5]).all() and g["flags"][0, 5] & 2
+
+
+def test_nn_soundness_1e6(gpu):
+    import paper_2607_01203_amd as leb
+    from oracle import nn
+    b = W.nn_cfg()
+    z, v, sg = b.z[:8], b.v[:8], b.sigma[:8]          # 400 boxes x 2500 samples
+    print("case: nn 1e6 samples", flush=True)
+    g = _run(leb, b.net, z, v, sg, gpu)
+    a = np.concatenate([z, v], -1).reshape(-1, 16)
+    c, rho = nn.box_of(a, sg.reshape(-1, 16))
+    rng = W.rng_for(1_000_001)
+    lo = g["r_lo"].reshape(-1, 12)
+    hi = g["r_hi"].reshape(-1, 12)
+    viol = 0
+    for s in range(0, 400, 50):
+        pts = W.sample_box_points(rng, (c - rho)[s:s + 50], (c + rho)[s:s + 50], 2500)
+        r, eps = nn.remainder(b.net.W, b.net.b, a[s:s + 50], pts)
+        viol += int(((r > hi[s:s + 50, None] + eps) | (r < lo[s:s + 50, None] - eps)).sum())
+    assert viol == 0

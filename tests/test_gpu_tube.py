@@ -98,6 +98,34 @@ def test_fixed_point_certificate_holds(gpu, orc):
     assert tube.contains(mu, sg, m2, s2).all()
 
 
+def test_fixed_point_warm_start_from_above(gpu, orc):
+    """A warm start 1% above the certified tube is certified within two
+    sweeps (the oracle's iteration takes one on this case), stays above the
+    least fixed point, and is no wider than the tube passed in."""
+    import torch
+    import paper_2607_01203_amd as leb
+    tp = W.fixed_point_cfg(seed=48, batch=4, N=14, n_units=4)
+    print("case: warm start B=4 N=14 U=4", flush=True)
+    mu, sg, cert, sweeps = _solve(leb, tp, gpu)
+    assert (cert == 1).all()
+    b = tp.batch
+    dyn = leb.dynamics_like(b.dyn)
+    s_in = sg * (1 + 1e-2)
+    mu2, sg2, cert2, sw2 = leb.fixed_point_solve(dyn, _t(b.z, gpu), _t(b.v, gpu), _t(tp.phi, gpu), tp.e,
+                                                 mu=_t(mu, gpu), sigma=_t(s_in, gpu))
+    torch.cuda.synchronize()
+    mu2, sg2 = mu2.cpu().numpy(), sg2.cpu().numpy()
+    assert (cert2.cpu().numpy() == 1).all() and 1 <= sw2 <= 2, sw2
+    if sw2 == 1:
+        assert np.array_equal(sg2, s_in) and np.array_equal(mu2, mu)
+    assert (sg2 <= s_in * (1 + 1e-6) + 1e-11).all()
+    from oracle import tube
+    d = orc.Dyn.like(b.dyn)
+    mo, so, _, _ = tube.fixed_point(d, b.z, b.v, tp.phi, tp.e)
+    assert (sg2 >= so * (1 - 1e-12)).all() and (sg2 <= so * 1.011 + 1e-11).all()
+    assert (np.abs(mu2 - mo) <= 1e-2 * np.maximum(so, 1e-12)).all()
+
+
 def test_fixed_point_sweep_cap_not_certified(gpu):
     import paper_2607_01203_amd as leb
     tp = W.fixed_point_cfg(seed=47, batch=3, N=10, n_units=3)

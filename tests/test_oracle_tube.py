@@ -102,19 +102,37 @@ def test_sequential_sweep_is_fixed_point_and_jacobi_reaches_it(orc, small):
     np.testing.assert_allclose(m, mu, rtol=1e-12, atol=1e-15)
 
 
-def test_inflated_fixed_point_is_certified(orc, small):
-    """Inflating the fixed point gives a post-fixed point: F(B) inside B
-    for every trajectory (the containment certificate)."""
+def test_fixed_point_is_certified(orc, small):
+    """The sequential sweep yields F(B) = B exactly (same arithmetic in the
+    same order), so the containment certificate F(B) inside B holds."""
     from oracle import tube
     tp = small
     b = tp.batch
     d = orc.Dyn.like(b.dyn)
     mu, sg, _, _ = tube.fixed_point(d, b.z, b.v, tp.phi, tp.e)
-    sgi = sg * (1 + 1e-6) + 1e-12
+    l_, h_, _ = orc.leb(d, b.z, b.v, sg, mu=mu)
+    c_, r_ = tube.zono(l_, h_)
+    m2, s2 = tube.tube_map(tp.phi, tp.e, c_, r_)
+    assert np.array_equal(m2, mu) and np.array_equal(s2, sg)
+    assert tube.contains(mu, sg, m2, s2).all()
+
+
+def test_uniform_inflation_fails_when_bounds_dominate(orc):
+    """Where the bound grows faster than linearly in the radius and exceeds
+    the disturbance, F(lambda B*) is not inside lambda B* for lambda > 1:
+    a uniform inflation of the fixed point does not certify it."""
+    from oracle import tube
+    tp = W.fixed_point_cfg(seed=4, batch=4, N=40)
+    b = tp.batch
+    d = orc.Dyn.like(b.dyn)
+    mu, sg, lo, hi = tube.fixed_point(d, b.z, b.v, tp.phi, tp.e)
+    rho = 0.5 * (hi - lo)
+    assert (rho.reshape(-1, 6) > tp.e[None, :] + 1e-12).any()
+    sgi = sg * (1 + 1e-4)
     l_, h_, _ = orc.leb(d, b.z, b.v, sgi, mu=mu)
     c_, r_ = tube.zono(l_, h_)
     m2, s2 = tube.tube_map(tp.phi, tp.e, c_, r_)
-    assert tube.contains(mu, sgi, m2, s2).all()
+    assert not tube.contains(mu, sgi, m2, s2).all()
     # a shrunken tube is not certified
     sgs = sg * 0.9
     l_, h_, _ = orc.leb(d, b.z, b.v, sgs, mu=mu)
