@@ -39,7 +39,21 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU baseline duration")
     p.add_argument("--kernel-reps", type=int, default=50)
+    p.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                   help="only run an elementwise copy (read BYTES, write BYTES) 5 times: the known-size "
+                        "kernel that scales FETCH_SIZE / WRITE_SIZE counters")
     return p.parse_args()
+
+
+def copy_calibration(nbytes):
+    import torch
+    dev = torch.device("cuda:0")
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": nbytes, "launches": 5}))
 
 
 def bytes_per_unit_fixed_point_launch(nx, nu):
@@ -55,6 +69,9 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     import numpy as np
     import torch
 

@@ -162,7 +162,11 @@ __device__ __forceinline__ void isincos(double a, double b, SinCos* r) {
         if (fa <= 0.0f && fb >= 0.0f) { r->c.hi = 1.0f; r->c_hi = 2; }
         else { r->c.hi = fminf(up8(fmaxf(ca, cb)), 1.0f); r->c_hi = ca >= cb ? 0 : 1; }
     } else {
-        sincos_wide(a, b, r);
+        // the callee writes a local of this branch only, so the caller's
+        // structures stay in registers on the common path
+        SinCos w;
+        sincos_wide(a, b, &w);
+        *r = w;
     }
 }
 

@@ -34,106 +34,147 @@
 
 namespace leb {
 
-struct TubeArgs {
-    const double* cbar; const double* rbar;   // [B][N][nx]
-    const double* phi;                        // [N-1][8][6]
-    double e[6];
-    double* mu; double* sigma;                // [B][N][n]
-    int B, N, U;
+// Fixed-point epilogue of the tube map (all NULL for the plain map).
+struct TubeFP {
+    const double* mu_in;  // C_t: the tube whose bounds produced (c_bar, rho_bar)
+    const double* sg_in;
+    uint32_t* state;      // [B]: bit 0 certified (frozen), bit 1 F(C_t) not inside C_t
+    double tol, abs_;     // C_{t+1} = (mu_F, sigma_F (1 + tol) + abs_)
 };
 
-// one thread per (trajectory, node, step): 8 tube rows of that node
-__global__ void __launch_bounds__(256) tube_map_kernel(TubeArgs A) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t total = (int64_t)A.B * A.U * A.N;
-    if (gid >= total) return;
-    const int k = (int)(gid % A.N);
-    const int64_t bi = gid / A.N;
-    const int i = (int)(bi % A.U);
-    const int b = (int)(bi / A.U);
+struct TubeArgs {
+    const double* cbar; const double* rbar;   // [B][N][nx]
+    double e[6];
+    double* mu; double* sigma;                // [B][N][n] out
+    int B, N, U;
+    int groups;        // k-groups per column group (4 k-pairs each)
+    int total;         // workgroups in the grid
+};
+
+// One wave per (64 columns, k-pair).  A column is one (trajectory, node);
+// the wave computes the 8 tube rows of its node at steps k = p and
+// k = N-1-p, so every wave performs N-1 block products.  Phi is indexed by
+// the wave-uniform lag only, so its 48 entries come through scalar loads;
+// the residual centres and radii come through vector loads shared in L2 by
+// the waves of the same columns (the workgroup order is remapped so those
+// land on one XCD).
+__global__ void __launch_bounds__(256) tube_map_kernel(const double* __restrict__ phi, TubeArgs A, TubeFP P) {
+    // XCD-aware order: workgroup ids are dealt round-robin over 8 XCDs;
+    // give each XCD a contiguous range of (column group, k-group) tiles.
+    const int id = blockIdx.x, x = id & 7, pos = id >> 3;
+    const int q8 = A.total >> 3, r8 = A.total & 7;
+    const int nid = x * q8 + min(x, r8) + pos;
+    const int cg = nid / A.groups, g = nid - cg * A.groups;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int npairs = (A.N + 1) >> 1;
+    const int p = g * 4 + wave;
+    if (p >= npairs) return;
+    const int cols = A.B * A.U;
+    const int col = cg * 64 + lane;
+    const bool valid = col < cols;
+    const int cc = valid ? col : cols - 1;
+    const int b = cc / A.U, i = cc - b * A.U;
     const int nx = 6 * A.U, n = 8 * A.U;
-    double m[8], s[8];
-#pragma unroll
-    for (int r = 0; r < 8; ++r) { m[r] = 0.0; s[r] = 0.0; }
     const double* cb = A.cbar + ((int64_t)b * A.N) * nx + 6 * i;
     const double* rb = A.rbar + ((int64_t)b * A.N) * nx + 6 * i;
-    for (int j = 0; j < k; ++j) {
-        const double* P = A.phi + (int64_t)(k - j - 1) * 48;
-        double c[6], w[6];
+    const bool fp = P.state != nullptr;
+    const bool frozen = fp && (P.state[b] & 1u);
+    // first lane of this wave holding trajectory b (columns of one trajectory are contiguous)
+    const int first = max(0, b * A.U - cg * 64);
+    for (int half = 0; half < 2; ++half) {
+        const int k = half ? A.N - 1 - p : p;
+        if (half && k == p) break;
+        double m[8], s[8];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            c[q] = cb[(int64_t)j * nx + q];
-            // residual radius plus the allowance for the rounding of the centre sum
-            w[q] = A.e[q] + rb[(int64_t)j * nx + q] + fabs(c[q]) * 0x1p-44;
-        }
-#pragma unroll
-        for (int r = 0; r < 8; ++r)
+        for (int r = 0; r < 8; ++r) { m[r] = 0.0; s[r] = 0.0; }
+#pragma unroll 2
+        for (int j = 0; j < k; ++j) {
+            const double* Pk = phi + (int64_t)(k - j - 1) * 48;
+            double c[6], w[6];
 #pragma unroll
             for (int q = 0; q < 6; ++q) {
-                const double p = P[r * 6 + q];
-                m[r] = __builtin_fma(p, c[q], m[r]);
-                s[r] = __builtin_fma(fabs(p), w[q], s[r]);
+                c[q] = cb[(int64_t)j * nx + q];
+                // residual radius plus the allowance for the rounding of the centre sum
+                w[q] = A.e[q] + rb[(int64_t)j * nx + q] + fabs(c[q]) * 0x1p-44;
             }
-    }
-    double* mo = A.mu + ((int64_t)b * A.N + k) * n;
-    double* so = A.sigma + ((int64_t)b * A.N + k) * n;
 #pragma unroll
-    for (int r = 0; r < 6; ++r) { mo[6 * i + r] = m[r]; so[6 * i + r] = s[r] + s[r] * 0x1p-45; }
+            for (int r = 0; r < 8; ++r)
 #pragma unroll
-    for (int r = 0; r < 2; ++r) { mo[nx + 2 * i + r] = m[6 + r]; so[nx + 2 * i + r] = s[6 + r] + s[6 + r] * 0x1p-45; }
-}
-
-// Per trajectory: out[2b] = max over entries of max(|dsigma|, |dmu|) /
-// max(sigma_new, floor) (relative change), out[2b+1] = 1 if box(new) lies in
-// box(old) for every entry (containment), else 0.
-__global__ void __launch_bounds__(256) tube_compare_kernel(const double* mu_old, const double* sg_old,
-                                                          const double* mu_new, const double* sg_new,
-                                                          int64_t per_traj, double floor_, double* out) {
-    __shared__ double red[256];
-    __shared__ int bad[256];
-    const int b = blockIdx.x;
-    const double* mo = mu_old + (int64_t)b * per_traj;
-    const double* so = sg_old + (int64_t)b * per_traj;
-    const double* mn = mu_new + (int64_t)b * per_traj;
-    const double* sn = sg_new + (int64_t)b * per_traj;
-    double acc = 0.0;
-    int nok = 0;
-    for (int64_t q = threadIdx.x; q < per_traj; q += 256) {
-        const double d = fmax(fabs(sn[q] - so[q]), fabs(mn[q] - mo[q]));
-        acc = fmax(acc, d / fmax(sn[q], floor_));
-        if (!(isfinite(sn[q]) && isfinite(mn[q])) && !(sn[q] == so[q] && mn[q] == mo[q])) acc = INFINITY;
-        const bool ok = (mn[q] - sn[q] >= mo[q] - so[q]) && (mn[q] + sn[q] <= mo[q] + so[q]);
-        nok |= ok ? 0 : 1;
-    }
-    red[threadIdx.x] = acc;
-    bad[threadIdx.x] = nok;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-            red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
-            bad[threadIdx.x] |= bad[threadIdx.x + w];
+                for (int q = 0; q < 6; ++q) {
+                    const double ph = Pk[r * 6 + q];
+                    m[r] = __builtin_fma(ph, c[q], m[r]);
+                    s[r] = __builtin_fma(fabs(ph), w[q], s[r]);
+                }
         }
-        __syncthreads();
+        // sums of at most 6 (N-1) rounded products: relative error below 2^-44 for N <= 2^7
+        bool bad = false;
+        const int64_t row0 = ((int64_t)b * A.N + k) * n;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int64_t o = row0 + (r < 6 ? 6 * i + r : nx + 2 * i + (r - 6));
+            const double sF = s[r] + s[r] * 0x1p-44, mF = m[r];
+            double mo = mF, so = sF;
+            if (fp) {
+                const double mi = P.mu_in[o], si = P.sg_in[o];
+                if (frozen) {
+                    mo = mi; so = si;
+                } else {
+                    // [mF - sF, mF + sF] inside [mi - si, mi + si], with the rounding of the test covered
+                    bad |= !((fabs(mF - mi) + sF) * (1.0 + 0x1p-50) <= si);
+                    so = sF + sF * P.tol + P.abs_;
+                }
+            }
+            if (valid) { A.mu[o] = mo; A.sigma[o] = so; }
+        }
+        if (fp) {
+            bad = bad && valid;
+            const uint64_t mask = __ballot(bad);
+            const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+            const uint64_t same = ~0ull << first;
+            if (bad && !(mask & below & same)) atomicOr(&P.state[b], 2u);
+        }
     }
-    if (threadIdx.x == 0) { out[2 * b] = red[0]; out[2 * b + 1] = bad[0] ? 0.0 : 1.0; }
 }
 
-// Next iterate of the inflated Jacobi map for trajectories not yet certified:
-// mu <- mu_F, sigma <- sigma_F (1 + rel) + abs (rounded up).
-__global__ void advance_kernel(const double* mu_f, const double* sg_f, double* mu, double* sg, const double* cmp,
-                               int64_t per_traj, int64_t count, double rel, double abs_) {
-    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Per sweep, after the tube map: commit trajectories whose C_t was shown
+// certified (state == 0: not frozen, contained) into the output tube.
+// With final != 0: commit every trajectory not yet certified (sweep cap).
+__global__ void fp_commit_kernel(const double* mu_in, const double* sg_in, double* mu, double* sg,
+                                 const uint32_t* state, int64_t per_traj, int64_t count, int final_) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= count) return;
-    const int64_t b = q / per_traj;
-    if (cmp[2 * b + 1] != 0.0) return;        // certified: frozen
-    const double s = sg_f[q] + sg_f[q] * rel + abs_;
-    mu[q] = mu_f[q];
-    sg[q] = s + s * 0x1p-50;
+    const uint32_t st = state[q / per_traj];
+    const bool go = final_ ? !(st & 1u) : st == 0u;
+    if (go && mu_in != mu) { mu[q] = mu_in[q]; sg[q] = sg_in[q]; }
 }
 
-__global__ void cert_from_cmp(const double* cmp, uint32_t* out, int B) {
-    int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < B) out[b] = cmp[2 * b + 1] != 0.0 ? 1u : 0u;
+// state[b]: certified once contained; clear the per-sweep bit.  state[B]
+// receives the number of trajectories not yet certified.
+__global__ void __launch_bounds__(256) fp_state_kernel(uint32_t* state, int B) {
+    __shared__ uint32_t cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    uint32_t open = 0;
+    for (int b = threadIdx.x; b < B; b += 256) {
+        const uint32_t st = state[b];
+        const uint32_t ns = (st & 1u) | ((st & 2u) ? 0u : 1u);
+        state[b] = ns;
+        open += ns ? 0u : 1u;
+    }
+    atomicAdd(&cnt, open);
+    __syncthreads();
+    if (threadIdx.x == 0) state[B] = cnt;
+}
+
+__global__ void u32_fill_kernel(uint32_t* dst, int64_t count, uint32_t v) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < count) dst[q] = v;
+}
+
+__global__ void cert_out_kernel(const uint32_t* state, uint32_t* out, int B) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < B) out[b] = state[b] & 1u;
 }
 
 __global__ void fill_kernel(double* dst, int64_t count, double v) {
@@ -141,26 +182,29 @@ __global__ void fill_kernel(double* dst, int64_t count, double v) {
     if (q < count) dst[q] = v;
 }
 
-// cmp[2b+1] |= cmpn[2b+1] (certified once contained); cmp[2b] = latest change
-__global__ void merge_cert_kernel(double* cmp, const double* cmpn, int B) {
-    int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
-    cmp[2 * b] = cmpn[2 * b];
-    if (cmpn[2 * b + 1] != 0.0) cmp[2 * b + 1] = 1.0;
-}
-
 static unsigned nblk(int64_t count) { return (unsigned)((count + 255) / 256); }
+
+static int launch_tube(int B, int N, int U, const double* phi, const double* e, const double* cbar,
+                       const double* rbar, double* mu, double* sigma, const TubeFP& fp, hipStream_t s) {
+    TubeArgs a;
+    a.cbar = cbar; a.rbar = rbar;
+    for (int q = 0; q < 6; ++q) a.e[q] = e[q];
+    a.mu = mu; a.sigma = sigma; a.B = B; a.N = N; a.U = U;
+    const int64_t cols = (int64_t)B * U;
+    if (cols == 0 || N == 0) return LEB_OK;
+    const int64_t ncg = (cols + 63) / 64;
+    a.groups = ((N + 1) / 2 + 3) / 4;
+    const int64_t total = ncg * a.groups;
+    if (total > 0x7fffffff) return LEB_EINVAL;
+    a.total = (int)total;
+    hipLaunchKernelGGL(tube_map_kernel, dim3((unsigned)total), dim3(256), 0, s, phi, a, fp);
+    return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
+}
 
 int launch_tube_map(int B, int N, int U, const double* phi, const double* e, const double* cbar,
                     const double* rbar, double* mu, double* sigma, hipStream_t s) {
-    TubeArgs a;
-    a.cbar = cbar; a.rbar = rbar; a.phi = phi;
-    for (int q = 0; q < 6; ++q) a.e[q] = e[q];
-    a.mu = mu; a.sigma = sigma; a.B = B; a.N = N; a.U = U;
-    const int64_t total = (int64_t)B * U * N;
-    if (total == 0) return LEB_OK;
-    hipLaunchKernelGGL(tube_map_kernel, dim3(nblk(total)), dim3(256), 0, s, a);
-    return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
+    TubeFP none{nullptr, nullptr, nullptr, 0.0, 0.0};
+    return launch_tube(B, N, U, phi, e, cbar, rbar, mu, sigma, none, s);
 }
 
 // ------------------------------------------------------------ workspace
@@ -230,55 +274,49 @@ extern "C" int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int
     hipStream_t s = (hipStream_t)stream;
 
     std::lock_guard<std::mutex> lock(g_ws.mu);
-    double *cb, *rb, *mu2, *sg2, *cmp, *cmpn;
+    double *cb, *rb, *xm[2], *xs[2];
+    uint32_t* state;
     const size_t bx = (size_t)units * nx * sizeof(double), bn = (size_t)units * n * sizeof(double);
     if ((rc = ws_get(0, bx, (void**)&cb)) || (rc = ws_get(1, bx, (void**)&rb)) ||
-        (rc = ws_get(2, bn, (void**)&mu2)) || (rc = ws_get(3, bn, (void**)&sg2)) ||
-        (rc = ws_get(4, (size_t)batch * 2 * sizeof(double), (void**)&cmp)) ||
-        (rc = ws_get(5, (size_t)batch * 2 * sizeof(double), (void**)&cmpn)))
+        (rc = ws_get(2, bn, (void**)&xm[0])) || (rc = ws_get(3, bn, (void**)&xs[0])) ||
+        (rc = ws_get(4, bn, (void**)&xm[1])) || (rc = ws_get(5, bn, (void**)&xs[1])) ||
+        (rc = ws_get(6, ((size_t)batch + 1) * sizeof(uint32_t), (void**)&state)))
         return rc;
-    std::vector<double> host(2 * (size_t)batch);
-    const int64_t cnt = units * n;
+    const int64_t cnt = units * n, per = (int64_t)N * n;
     auto ok = [](hipError_t e_) { return e_ == hipSuccess; };
-    int sweeps = 0;
-    // F: bound every unit of box (m_, s_) then map to (mo, so)
-    auto F = [&](const double* m_, const double* s_, double* mo, double* so) -> int {
-        int r = launch_pbh_chain(dyn, units, z, v, m_, s_, nullptr, nullptr, cb, rb, opt->pad, nullptr, s);
-        if (r) return r;
-        if ((r = launch_tube_map(batch, N, U, phi, e, cb, rb, mo, so, s))) return r;
-        ++sweeps;
-        return LEB_OK;
-    };
-    if (!opt->warm) {       // disturbance-only tube (LEB = 0): below the fixed point
+    hipLaunchKernelGGL(u32_fill_kernel, dim3(nblk(batch + 1)), dim3(256), 0, s, state, (int64_t)batch + 1, 0u);
+    // iterate C_t: the caller's tube (warm start) or the disturbance-only tube (LEB = 0, below the fixed point)
+    const double *im = mu, *is = sigma;
+    int nxt = 1;
+    if (!opt->warm) {
         hipLaunchKernelGGL(fill_kernel, dim3(nblk(units * nx)), dim3(256), 0, s, cb, units * nx, 0.0);
         hipLaunchKernelGGL(fill_kernel, dim3(nblk(units * nx)), dim3(256), 0, s, rb, units * nx, opt->pad);
-        if ((rc = launch_tube_map(batch, N, U, phi, e, cb, rb, mu, sigma, s))) return rc;
+        if ((rc = launch_tube_map(batch, N, U, phi, e, cb, rb, xm[0], xs[0], s))) return rc;
+        im = xm[0]; is = xs[0];
     }
-    // Inflated Jacobi: C <- F(C) (1 + tol) + abs until F(C) lies inside C.
-    // A trajectory is frozen (and certified) from the sweep that shows it.
-    hipLaunchKernelGGL(fill_kernel, dim3(nblk(2 * (int64_t)batch)), dim3(256), 0, s, cmp, 2 * (int64_t)batch, 0.0);
+    int sweeps = 0;
+    uint32_t open = 0;
     while (sweeps < opt->max_sweeps) {
-        if ((rc = F(mu, sigma, mu2, sg2))) return rc;
-        // containment per trajectory, accumulated (frozen trajectories stay certified)
-        hipLaunchKernelGGL(tube_compare_kernel, dim3(batch), dim3(256), 0, s, mu, sigma, mu2, sg2, (int64_t)N * n,
-                           opt->inflate_abs, cmpn);
-        hipLaunchKernelGGL(merge_cert_kernel, dim3(nblk(batch)), dim3(256), 0, s, cmp, cmpn, batch);
-        if (!ok(hipGetLastError())) return LEB_EDEVICE;
-        if (!ok(hipMemcpyAsync(host.data(), cmp, 2 * (size_t)batch * sizeof(double), hipMemcpyDeviceToHost, s)) ||
+        // F(C_t): bound every unit of the tube, then the tube map; C_{t+1} = inflated F(C_t)
+        if ((rc = launch_pbh_chain(dyn, units, z, v, im, is, nullptr, nullptr, cb, rb, opt->pad, nullptr, s)))
+            return rc;
+        const TubeFP fp{im, is, state, opt->tol, opt->inflate_abs};
+        if ((rc = launch_tube(batch, N, U, phi, e, cb, rb, xm[nxt], xs[nxt], fp, s))) return rc;
+        ++sweeps;
+        hipLaunchKernelGGL(fp_commit_kernel, dim3(nblk(cnt)), dim3(256), 0, s, im, is, mu, sigma, state, per, cnt, 0);
+        hipLaunchKernelGGL(fp_state_kernel, dim3(1), dim3(256), 0, s, state, batch);
+        if (!ok(hipGetLastError()) ||
+            !ok(hipMemcpyAsync(&open, state + batch, sizeof(uint32_t), hipMemcpyDeviceToHost, s)) ||
             !ok(hipStreamSynchronize(s)))
             return LEB_EDEVICE;
-        bool all = true;
-        for (int b = 0; b < batch; ++b) all = all && host[2 * b + 1] != 0.0;
-        if (all) {
-            hipLaunchKernelGGL(cert_from_cmp, dim3(nblk(batch)), dim3(256), 0, s, cmp, certified, batch);
-            *sweeps_out = sweeps;
-            return ok(hipGetLastError()) ? LEB_OK : LEB_EDEVICE;
-        }
-        hipLaunchKernelGGL(advance_kernel, dim3(nblk(cnt)), dim3(256), 0, s, mu2, sg2, mu, sigma, cmp, (int64_t)N * n, cnt,
-                           opt->tol, opt->inflate_abs);
+        im = xm[nxt]; is = xs[nxt];
+        nxt ^= 1;
+        if (open == 0) break;
     }
-    // sweep budget exhausted: report which trajectories were certified
-    hipLaunchKernelGGL(cert_from_cmp, dim3(nblk(batch)), dim3(256), 0, s, cmp, certified, batch);
+    // sweep cap: the latest iterate of every trajectory not certified
+    if (open != 0)
+        hipLaunchKernelGGL(fp_commit_kernel, dim3(nblk(cnt)), dim3(256), 0, s, im, is, mu, sigma, state, per, cnt, 1);
+    hipLaunchKernelGGL(cert_out_kernel, dim3(nblk(batch)), dim3(256), 0, s, state, certified, batch);
     *sweeps_out = sweeps;
     return ok(hipGetLastError()) ? LEB_OK : LEB_EDEVICE;
 }
