@@ -3,10 +3,15 @@
 Workload: 256 trajectories x 40 steps of a chain of 28 planar quadrotors
 (nx = 168, nu = 56) with a decentralised hover-LQR closed loop.  One step
 is one certified tube/LEB fixed-point solve from device-resident inputs to
-a certified tube on the device: Jacobi sweeps of the path-based Hessian
-bound over all 10,240 (trajectory, step) units, the tube map, the
-convergence test, and the certifying sweep (host orchestration included).
-value = 10,240 x steps / wall time.
+a certified tube on the device (host orchestration included), in two forms:
+  plain    Jacobi sweeps of the path-based Hessian bound over all 10,240
+           (trajectory, step) units and the tube map, from the
+           disturbance-only tube, until F(C) lies inside C;
+  learned  a few tube sweeps with the BF16 surrogate's predicted bounds,
+           inflation, then the same certified sweeps from that tube.
+The surrogate is trained beforehand (outside the timed region) by the
+library's kernels on certified bounds of other trajectories.
+value = 10,240 / (learned ms per solve); the plain rate is reported too.
 
 Prints ONE JSON line.  Extra objects:
   roofline      dominant kernel (the bound kernel) at the solve's launch
@@ -39,6 +44,9 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU baseline duration")
     p.add_argument("--kernel-reps", type=int, default=50)
+    p.add_argument("--epochs", type=int, default=20, help="surrogate training epochs (outside the timed region)")
+    p.add_argument("--surrogate-sweeps", type=int, default=6)
+    p.add_argument("--margin", type=float, default=2e-2, help="relative inflation of the surrogate tube")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                    help="only run an elementwise copy (read BYTES, write BYTES) 5 times: the known-size "
                         "kernel that scales FETCH_SIZE / WRITE_SIZE counters")
@@ -91,23 +99,37 @@ def main():
     phi = torch.from_numpy(tp.phi).to(dev)
     stream = torch.cuda.current_stream()
 
-    def step():
-        return leb.fixed_point_solve(dyn, z, v, phi, tp.e, tol=1e-6, max_sweeps=200)
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        sweeps = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            res = fn()
+            sweeps.append(res[3])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        return (t1 - t0) * 1e3 / args.steps, res, int(np.median(sweeps))
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    sweeps = []
-    certified = True
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        mu, sg, cert, sw = step()
-        sweeps.append(sw)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    # plain form: certified fixed point from the disturbance-only tube
+    plain_ms, (mu0, sg0, cert0, _), plain_sweeps = timed(
+        lambda: leb.fixed_point_solve(dyn, z, v, phi, tp.e, tol=1e-6, max_sweeps=200))
+    plain_cert = bool((cert0 == 1).all().item())
+
+    # learned form: surrogate trained (outside the timed region) on certified
+    # bounds of other trajectories, then surrogate sweeps + certified sweeps
+    net, train_info = train_chain_surrogate(leb, W, dev, args)
+    learned_ms, (mu, sg, cert, _), learned_sweeps = timed(
+        lambda: leb.fixed_point_learned(dyn, z, v, phi, tp.e, net, sweeps=args.surrogate_sweeps,
+                                        margin=args.margin, tol=1e-6, max_sweeps=200))
     certified = bool((cert == 1).all().item())
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    value = units * args.steps / (t1 - t0)
+    s0 = sg0.cpu().numpy()
+    s1 = sg.cpu().numpy()
+    pos = s0 > 0
+    excess = s1[pos] / s0[pos] - 1.0
+    ms_per_step = learned_ms
+    value = units * 1e3 / learned_ms
 
     # dominant kernel: the bound launch of a sweep, at the certified tube
     cb = torch.empty((B, N, nx), dtype=torch.float64, device=dev)
@@ -149,13 +171,43 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32-interval+f64",
         "data": "synthetic",
         "config": {"workload": "certified tube/LEB fixed point, 256 chains of 28 planar quadrotors "
-                               "(nx=168, nu=56), N=40, cold start, batched Jacobi sweeps",
+                               "(nx=168, nu=56), N=40, batched Jacobi sweeps; value: learned warm start",
                    "trajectories": B, "horizon": N, "nx": nx, "nu": nu, "tol": 1e-6,
-                   "form": "batched, cold start"},
-        "sweeps_per_solve": int(np.median(sweeps)), "certified": certified,
+                   "form": "batched + learned warm start"},
+        "certified": certified,
+        "learned": {"certified_sweeps": learned_sweeps, "surrogate_sweeps": args.surrogate_sweeps,
+                    "margin": args.margin, "ms_per_solve": round(learned_ms, 4),
+                    "sigma_over_plain_median": round(float(np.median(excess)), 6),
+                    "sigma_over_plain_max": round(float(excess.max()), 6), "training": train_info},
+        "plain": {"value": round(units * 1e3 / plain_ms, 1), "ms_per_solve": round(plain_ms, 4),
+                  "certified_sweeps": plain_sweeps, "certified": plain_cert},
         "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(line))
+
+
+def train_chain_surrogate(leb, W, dev, args):
+    """Certified training samples from 64 other trajectories (seed 100),
+    3 draws of scaled tubes around their certified fixed points (215,040
+    node samples), trained with the library's BF16 kernels."""
+    import torch
+    from paper_2607_01203_amd import learned
+    t0 = time.perf_counter()
+    tp = W.fixed_point_cfg(seed=100, batch=64, N=40)
+    b = tp.batch
+    dyn = leb.dynamics_like(b.dyn)
+    z = torch.from_numpy(b.z).to(dev)
+    v = torch.from_numpy(b.v).to(dev)
+    mu, sg, _, _ = leb.fixed_point_solve(dyn, z, v, torch.from_numpy(tp.phi).to(dev), tp.e)
+    X, T = learned.chain_samples(dyn, z, v, mu.cpu().numpy(), sg.cpu().numpy(), draws=3, seed=1)
+    net = leb.Surrogate(learned.CHAIN_WIDTHS, learned.he_init(learned.CHAIN_WIDTHS, 0))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    hist = learned.train(net, X, T, epochs=args.epochs, batch=1024, lr=2e-3)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return net, {"samples": int(X.shape[0]), "epochs": args.epochs, "loss_first": round(hist[0], 5),
+                 "loss_last": round(hist[-1], 6), "sample_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2)}
 
 
 def cpu_baseline(W, tp, seconds):

@@ -204,6 +204,99 @@ int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int32_t N, con
                           const double* v, const double* phi, const double* e, const leb_fp_options* opt,
                           double* mu, double* sigma, uint32_t* certified, int32_t* sweeps_out, void* stream);
 
+/*
+ * Learned warm start (section V: the fixed point is started from a tube the
+ * surrogate predicts; every accepted tube is still certified by the plain
+ * bound).  A GELU MLP with widths [d_0, ..., d_L] (L <= 8, every width in
+ * 1..256), FP32 master parameters and BF16 MFMA arithmetic with FP32
+ * accumulation:
+ *   a_0 = bf16(x); z_l = bf16(W_l) a_{l-1} + b_l; a_l = bf16(gelu(z_l));
+ *   y = bf16(W_L) a_{L-1} + b_L,    gelu(z) = z Phi(z) (exact form).
+ * Parameters are one flat FP32 array [W_1, b_1, ..., W_L, b_L], W_l row-major
+ * [d_l][d_{l-1}].  The object owns its device parameters, Adam moments,
+ * BF16 weight copies and a grow-only training workspace; calls on one
+ * object must not overlap (they serialise on an internal lock where they
+ * use the workspace).
+ */
+typedef struct leb_surrogate_s* leb_surrogate;
+
+/* Uploads params_host (host, leb_surrogate_n_params values); Adam moments start at 0. */
+int leb_surrogate_create(int32_t n_layers, const int32_t* widths, const float* params_host, leb_surrogate* out);
+int leb_surrogate_destroy(leb_surrogate s);
+/* Number of FP32 parameters (-1 for NULL). */
+int64_t leb_surrogate_n_params(leb_surrogate s);
+/* Synchronises the device and downloads the FP32 parameters to params_host. */
+int leb_surrogate_params(leb_surrogate s, float* params_host);
+
+/* Inference: y [batch][d_L] = net(x [batch][d_0]) (device FP32). */
+int leb_mlp_fwd_bf16(leb_surrogate s, int32_t batch, const float* x, float* y, void* stream);
+
+/* Gradient of sum(dy . net(x)) with respect to the parameters, written to
+ * grads (device FP32, the parameter layout).  batch must be a multiple of 32. */
+int leb_mlp_bwd_bf16(leb_surrogate s, int32_t batch, const float* x, const float* dy, float* grads, void* stream);
+
+/* One Adam step (Kingma and Ba, Algorithm 1; step >= 1 is the bias-
+ * correction index) with the given device gradient; refreshes the BF16 copies. */
+int leb_adam_step(leb_surrogate s, const float* grads, int32_t step, float lr, float beta1, float beta2, float eps,
+                  void* stream);
+
+/* Forward, mean-squared error against t [batch][d_L], backward and Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8) in one call.  loss (device, 1 float,
+ * may be NULL) receives the mean-squared error before the update.  batch
+ * must be a multiple of 32. */
+int leb_surrogate_train_step(leb_surrogate s, int32_t batch, const float* x, const float* t, int32_t step, float lr,
+                             float* loss, void* stream);
+
+/* Input and output widths of a surrogate (d_0 and d_L). */
+int leb_surrogate_dims(leb_surrogate s, int32_t* d_in, int32_t* d_out);
+
+/*
+ * Chain surrogate: for node i of a chain at one timestep, the bound of its
+ * two non-linear rows (vx_i+, vz_i+) is regressed on what the path-based
+ * bound of those rows depends on (Theorem 1 over the prefix boxes of the
+ * node's attitude block and of its two springs).  With
+ * Delta_c = [min(mu_c - sigma_c, 0), max(mu_c + sigma_c, 0)] scaled by 20:
+ *   x[0..11]  theta_i, (u1_i + u2_i) / 10, Delta of theta_i, u1_i, u2_i,
+ *             px_i, pz_i (lo, hi each)
+ *   x[12..18] right spring: present (1/0), separation (L0 + px_{i+1} - px_i,
+ *             pz_{i+1} - pz_i), Delta of px_{i+1}, pz_{i+1}  (zeros if absent)
+ *   x[19..25] left spring: the same for node i-1 (separation from i-1 to i)
+ * Targets: log(max(hi, 1e-14)), log(max(-lo, 1e-14)) of the vx row, then of
+ * the vz row.
+ */
+#define LEB_CHAIN_FEATURES 26
+#define LEB_CHAIN_OUTPUTS 4
+
+/* x [batch][N][n_units][26] (device FP32) from the nominal trajectory and
+ * the tube (mu may be NULL). */
+int leb_chain_features(const leb_dynamics* dyn, int32_t batch, int32_t N, const double* z, const double* v,
+                       const double* mu, const double* sigma, float* x, void* stream);
+/* t [batch][N][n_units][4] (device FP32) from a bound r_lo, r_hi [batch][N][nx]. */
+int leb_chain_targets(const leb_dynamics* dyn, int32_t batch, int32_t N, const double* r_lo, const double* r_hi,
+                      float* t, void* stream);
+
+typedef struct {
+    leb_surrogate net;     /* widths [26, ..., 4] */
+    int32_t sweeps;        /* tube sweeps with surrogate bounds before certification (>= 0) */
+    double margin;         /* relative inflation of the surrogate tube's sigma (>= 0) */
+} leb_warm_start;
+
+/*
+ * leb_fixed_point_learned -- certified tube/LEB fixed point started from a
+ * learned tube: from the disturbance-only tube, ws->sweeps tube sweeps use
+ * the surrogate's predicted bounds (features -> BF16 MLP -> zonotope ->
+ * tube map); sigma is then inflated to sigma (1 + margin) + opt->inflate_abs
+ * and passed to leb_fixed_point_solve as a warm start.  Certification is
+ * unchanged: every accepted tube satisfies F(C) inside C with the plain
+ * bound, whatever the surrogate predicted.  Arguments as
+ * leb_fixed_point_solve (opt->warm is ignored); sweeps_out counts the
+ * certified (plain-bound) sweeps only.  Uses a library-owned workspace;
+ * calls serialise.
+ */
+int leb_fixed_point_learned(const leb_dynamics* dyn, int32_t batch, int32_t N, const double* z, const double* v,
+                            const double* phi, const double* e, const leb_fp_options* opt, const leb_warm_start* ws,
+                            double* mu, double* sigma, uint32_t* certified, int32_t* sweeps_out, void* stream);
+
 /* Human-readable text of a leb_status code (static storage). */
 const char* leb_strerror(int code);
 

@@ -33,6 +33,14 @@ class Dynamics(ctypes.Structure):
                 ("k_spring", ctypes.c_double), ("rest_len", ctypes.c_double)]
 
 
+class WarmStart(ctypes.Structure):
+    _fields_ = [("net", ctypes.c_void_p), ("sweeps", ctypes.c_int32), ("margin", ctypes.c_double)]
+
+
+CHAIN_FEATURES = 26
+CHAIN_OUTPUTS = 4
+
+
 class FPOptions(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_sweeps", ctypes.c_int32), ("pad", ctypes.c_double),
                 ("inflate_abs", ctypes.c_double), ("warm", ctypes.c_int32)]
@@ -79,6 +87,35 @@ def lib():
                                             vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(FPOptions),
                                             vp, vp, vp, ctypes.POINTER(ctypes.c_int32), vp]
         L.leb_fixed_point_solve.restype = ctypes.c_int
+        f32 = ctypes.c_float
+        L.leb_surrogate_create.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), vp,
+                                           ctypes.POINTER(ctypes.c_void_p)]
+        L.leb_surrogate_create.restype = ctypes.c_int
+        L.leb_surrogate_destroy.argtypes = [vp]
+        L.leb_surrogate_destroy.restype = ctypes.c_int
+        L.leb_surrogate_n_params.argtypes = [vp]
+        L.leb_surrogate_n_params.restype = ctypes.c_int64
+        L.leb_surrogate_params.argtypes = [vp, vp]
+        L.leb_surrogate_params.restype = ctypes.c_int
+        L.leb_mlp_fwd_bf16.argtypes = [vp, ctypes.c_int32, vp, vp, vp]
+        L.leb_mlp_fwd_bf16.restype = ctypes.c_int
+        L.leb_mlp_bwd_bf16.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp]
+        L.leb_mlp_bwd_bf16.restype = ctypes.c_int
+        L.leb_adam_step.argtypes = [vp, vp, ctypes.c_int32, f32, f32, f32, f32, vp]
+        L.leb_adam_step.restype = ctypes.c_int
+        L.leb_surrogate_train_step.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_int32, f32, vp, vp]
+        L.leb_surrogate_train_step.restype = ctypes.c_int
+        L.leb_surrogate_dims.argtypes = [vp, vp, vp]
+        L.leb_surrogate_dims.restype = ctypes.c_int
+        L.leb_chain_features.argtypes = [ctypes.POINTER(Dynamics), ctypes.c_int32, ctypes.c_int32] + [vp] * 6
+        L.leb_chain_features.restype = ctypes.c_int
+        L.leb_chain_targets.argtypes = [ctypes.POINTER(Dynamics), ctypes.c_int32, ctypes.c_int32] + [vp] * 4
+        L.leb_chain_targets.restype = ctypes.c_int
+        L.leb_fixed_point_learned.argtypes = [ctypes.POINTER(Dynamics), ctypes.c_int32, ctypes.c_int32, vp, vp,
+                                              vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(FPOptions),
+                                              ctypes.POINTER(WarmStart), vp, vp, vp, ctypes.POINTER(ctypes.c_int32),
+                                              vp]
+        L.leb_fixed_point_learned.restype = ctypes.c_int
         L.leb_strerror.argtypes = [ctypes.c_int]
         L.leb_strerror.restype = ctypes.c_char_p
         L.leb_version.restype = ctypes.c_char_p
@@ -240,6 +277,51 @@ def fixed_point_solve(dyn: Dynamics, z, v, phi, e, tol=1e-6, max_sweeps=200, pad
     return mu, sigma, cert, int(sweeps.value)
 
 
+def fixed_point_learned(dyn: Dynamics, z, v, phi, e, net, sweeps=6, margin=5e-3, tol=1e-6, max_sweeps=200,
+                        pad=0.0, inflate_abs=1e-12, stream=None):
+    """Certified fixed point from a learned initial tube (see leb.h:
+    leb_fixed_point_learned).  Returns (mu, sigma, certified, certified sweeps)."""
+    import torch
+    B, N = int(z.shape[0]), int(z.shape[1])
+    n = dyn.nx + dyn.nu
+    mu = torch.empty((B, N, n), dtype=torch.float64, device=z.device)
+    sigma = torch.empty((B, N, n), dtype=torch.float64, device=z.device)
+    cert = torch.zeros((B,), dtype=torch.int32, device=z.device)
+    opt = FPOptions(tol, max_sweeps, pad, inflate_abs, 1)
+    ws = WarmStart(net.handle, int(sweeps), float(margin))
+    sw = ctypes.c_int32(0)
+    f64 = torch.float64
+    rc = lib().leb_fixed_point_learned(ctypes.byref(dyn), B, N, _dev_ptr(z, "z", f64), _dev_ptr(v, "v", f64),
+                                       _dev_ptr(phi, "phi", f64), _host6(e), ctypes.byref(opt), ctypes.byref(ws),
+                                       _dev_ptr(mu, "mu", f64), _dev_ptr(sigma, "sigma", f64),
+                                       _dev_ptr(cert, "certified"), ctypes.byref(sw), _stream(stream))
+    _check(rc)
+    return mu, sigma, cert, int(sw.value)
+
+
+def chain_features(dyn: Dynamics, z, v, sigma, mu=None, stream=None):
+    """Surrogate inputs [B][N][n_units][26] (float32) of a chain tube."""
+    import torch
+    B, N = int(z.shape[0]), int(z.shape[1])
+    x = torch.empty((B, N, dyn.n_units, CHAIN_FEATURES), dtype=torch.float32, device=z.device)
+    f64 = torch.float64
+    _check(lib().leb_chain_features(ctypes.byref(dyn), B, N, _dev_ptr(z, "z", f64), _dev_ptr(v, "v", f64),
+                                    _dev_ptr(mu, "mu", f64), _dev_ptr(sigma, "sigma", f64),
+                                    _dev_ptr(x, "x", torch.float32), _stream(stream)))
+    return x
+
+
+def chain_targets(dyn: Dynamics, r_lo, r_hi, stream=None):
+    """Surrogate targets [B][N][n_units][4] (float32) from a chain bound."""
+    import torch
+    B, N = int(r_lo.shape[0]), int(r_lo.shape[1])
+    t = torch.empty((B, N, dyn.n_units, CHAIN_OUTPUTS), dtype=torch.float32, device=r_lo.device)
+    f64 = torch.float64
+    _check(lib().leb_chain_targets(ctypes.byref(dyn), B, N, _dev_ptr(r_lo, "r_lo", f64),
+                                   _dev_ptr(r_hi, "r_hi", f64), _dev_ptr(t, "t", torch.float32), _stream(stream)))
+    return t
+
+
 class MLP:
     """ReLU MLP uploaded to the device (see leb.h: leb_mlp_create).
 
@@ -294,3 +376,70 @@ def nn_bound(mlp: MLP, z, v, sigma, mu=None, pad: float = 0.0, zonotope: bool = 
                             _dev_ptr(out["flags"], "flags"), _stream(stream))
     _check(rc)
     return out
+
+
+class Surrogate:
+    """BF16 MFMA GELU MLP of the learned warm start (see leb.h:
+    leb_surrogate_create).  widths [d_0, ..., d_L]; params: flat float32
+    host array [W_1, b_1, ..., W_L, b_L] with W_l row-major [d_l][d_{l-1}]."""
+
+    def __init__(self, widths, params):
+        import numpy as np
+        self.widths = [int(w) for w in widths]
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        wd = (ctypes.c_int32 * len(self.widths))(*self.widths)
+        h = ctypes.c_void_p()
+        _check(lib().leb_surrogate_create(len(self.widths) - 1, wd, p.ctypes.data_as(ctypes.c_void_p),
+                                          ctypes.byref(h)))
+        self.handle = h
+        self.n_params = int(lib().leb_surrogate_n_params(h))
+        if self.n_params != p.size:
+            self.close()
+            raise LebError("params has %d values, the widths need %d" % (p.size, self.n_params))
+
+    def params(self):
+        import numpy as np
+        out = np.empty(self.n_params, dtype=np.float32)
+        _check(lib().leb_surrogate_params(self.handle, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def forward(self, x, out=None, stream=None):
+        """x [B][d_0] float32 GPU tensor -> y [B][d_L]."""
+        import torch
+        B = int(x.shape[0])
+        y = out if out is not None else torch.empty((B, self.widths[-1]), dtype=torch.float32, device=x.device)
+        _check(lib().leb_mlp_fwd_bf16(self.handle, B, _dev_ptr(x, "x", torch.float32),
+                                      _dev_ptr(y, "y", torch.float32), _stream(stream)))
+        return y
+
+    def backward(self, x, dy, stream=None):
+        """Parameter gradient of sum(dy * forward(x)) (flat float32 GPU tensor)."""
+        import torch
+        g = torch.empty(self.n_params, dtype=torch.float32, device=x.device)
+        _check(lib().leb_mlp_bwd_bf16(self.handle, int(x.shape[0]), _dev_ptr(x, "x", torch.float32),
+                                      _dev_ptr(dy, "dy", torch.float32), _dev_ptr(g, "grads", torch.float32),
+                                      _stream(stream)))
+        return g
+
+    def adam(self, grads, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        import torch
+        _check(lib().leb_adam_step(self.handle, _dev_ptr(grads, "grads", torch.float32), int(step), float(lr),
+                                   float(beta1), float(beta2), float(eps), _stream(stream)))
+
+    def train_step(self, x, t, step, lr, loss=None, stream=None):
+        """Forward + MSE + backward + Adam; loss: optional 1-float GPU tensor."""
+        import torch
+        _check(lib().leb_surrogate_train_step(self.handle, int(x.shape[0]), _dev_ptr(x, "x", torch.float32),
+                                              _dev_ptr(t, "t", torch.float32), int(step), float(lr),
+                                              _dev_ptr(loss, "loss", torch.float32), _stream(stream)))
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().leb_surrogate_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,553 @@
+// mlp.hip -- BF16 MFMA kernels of the learned warm-start MLP: fused
+// forward, GEMM-based backward, MSE, Adam.
+//
+// Network: widths [d_0, ..., d_L], GELU after every hidden layer, FP32
+// master parameters, BF16 operands with FP32 accumulation:
+//   a_0 = bf16(x);  z_l = bf16(W_l) a_{l-1} + b_l;  a_l = bf16(gelu(z_l));
+//   y = bf16(W_L) a_{L-1} + b_L.
+// Backward (of sum(dy . y)): g_L = bf16(dy); dW_l = sum_b g_l a_{l-1}^T;
+//   db_l = sum_b dz_l; dz_{l-1} = (bf16(W_l)^T g_l) gelu'(z_{l-1});
+//   g_{l-1} = bf16(dz_{l-1}).
+// Adam (Kingma and Ba, Algorithm 1) updates the FP32 parameters, then the
+// BF16 copies are refreshed.
+//
+// MFMA: v_mfma_f32_16x16x32_bf16.  Lane l supplies A[l%16][8(l/16)+j] and
+// B[8(l/16)+j][l%16] (j = 0..7) and receives D[4(l/16)+i][l%16] (i = 0..3).
+// Every operand is stored with k contiguous, so each fragment is one
+// 16-byte load: activations [row][k], weights W~ [out][in] (forward) and
+// W~^T [in][out] (backward), and for the weight gradients the transposed
+// activations a^T [k][batch] and g^T [out][batch].
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "leb.h"
+#include "leb_internal.hpp"
+
+namespace leb {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int MLP_MAX_LAYERS = 8;
+constexpr int MLP_MAX_WIDTH = 256;
+constexpr int FWD_ROWS = 64;            // rows (samples) per forward workgroup
+
+__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad_f(float z) {
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+static inline int pad32(int x) { return (x + 31) & ~31; }
+static inline int pad16(int x) { return (x + 15) & ~15; }
+
+struct MlpLayout {
+    int L;
+    int w[MLP_MAX_LAYERS + 1];     // true widths
+    int kp[MLP_MAX_LAYERS];        // padded input width of layer l (multiple of 32)
+    int np[MLP_MAX_LAYERS];        // padded output width of layer l (multiple of 32)
+    int64_t poff[MLP_MAX_LAYERS];  // offset of W_l in the flat FP32 parameters (b_l follows)
+    int64_t woff[MLP_MAX_LAYERS];  // offset of W~_l [np][kp] and W~_l^T [kp][np] in the BF16 copies
+    int64_t nparams, nw;
+};
+
+// ---------------------------------------------------------------- forward
+
+struct FwdArgs {
+    MlpLayout G;
+    const __bf16* Wt;         // W~_l [np][kp] per layer
+    const float* params;      // biases b_l
+    const float* x;           // [B][d0]
+    float* y;                 // [B][dL]
+    float* zsave;             // optional [L-1][B][np]   pre-activations
+    __bf16* aT;               // optional [L][MAX_WIDTH][B]  a_l^T for l = 0..L-1
+    int B;
+    int ldA;                  // LDS row stride (BF16): widest padded layer + 8
+};
+
+// One workgroup (4 waves) carries 64 rows through every layer.  The
+// activation tile lives in LDS ([64][kp + 8] BF16, the pad skews banks);
+// weight fragments are read from global memory (L2-resident).  Output
+// tiles of 16x16 are dealt to the waves round-robin.
+__global__ void __launch_bounds__(256) mlp_fwd_kernel(FwdArgs A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int ldA = A.ldA;
+    __bf16* buf0 = reinterpret_cast<__bf16*>(smem);
+    __bf16* buf1 = buf0 + FWD_ROWS * ldA;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int row0 = blockIdx.x * FWD_ROWS;
+    const MlpLayout& G = A.G;
+    // stage a_0 = bf16(x), zero padded
+    {
+        const int d0 = G.w[0], k0 = G.kp[0];
+        for (int idx = tid; idx < FWD_ROWS * k0; idx += 256) {
+            const int r = idx / k0, k = idx - r * k0;
+            const int row = row0 + r;
+            const float v = (row < A.B && k < d0) ? A.x[(int64_t)row * d0 + k] : 0.0f;
+            const __bf16 bv = (__bf16)v;
+            buf0[r * ldA + k] = bv;
+            if (A.aT && row < A.B) A.aT[(int64_t)k * A.B + row] = bv;   // a_0^T
+        }
+    }
+    __syncthreads();
+    __bf16* cur = buf0;
+    __bf16* nxt = buf1;
+    for (int l = 0; l < G.L; ++l) {
+        const int kp = G.kp[l], np = G.np[l], nout = G.w[l + 1];
+        const bool last = (l == G.L - 1);
+        const __bf16* W = A.Wt + G.woff[l];
+        const float* bias = A.params + G.poff[l] + (int64_t)nout * G.w[l];
+        const int ntc = np / 16, ntiles = 4 * ntc;
+        f32x4 acc[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int k = 0; k < kp; k += 32) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int t = wave + 4 * q;
+                if (t < ntiles) {
+                    const int rt = t / ntc, ct = t - rt * ntc;
+                    const bf16x8 a = *reinterpret_cast<const bf16x8*>(cur + (rt * 16 + (lane & 15)) * ldA + k + 8 * (lane >> 4));
+                    const bf16x8 b = *reinterpret_cast<const bf16x8*>(W + (int64_t)(ct * 16 + (lane & 15)) * kp + k + 8 * (lane >> 4));
+                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[q], 0, 0, 0);
+                }
+            }
+        }
+        // epilogue
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int t = wave + 4 * q;
+            if (t < ntiles) {
+                const int rt = t / ntc, ct = t - rt * ntc;
+                const int c = ct * 16 + (lane & 15);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = rt * 16 + 4 * (lane >> 4) + i;
+                    const int row = row0 + r;
+                    const float z = acc[q][i] + (c < nout ? bias[c] : 0.0f);
+                    if (last) {
+                        if (row < A.B && c < nout) A.y[(int64_t)row * nout + c] = z;
+                    } else {
+                        const __bf16 a = (__bf16)(c < nout ? gelu_f(z) : 0.0f);
+                        nxt[r * ldA + c] = a;
+                        if (row < A.B) {
+                            if (A.zsave) A.zsave[((int64_t)l * A.B + row) * MLP_MAX_WIDTH + c] = c < nout ? z : 0.0f;
+                            if (A.aT) A.aT[((int64_t)(l + 1) * MLP_MAX_WIDTH + c) * A.B + row] = a;
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        __bf16* t_ = cur; cur = nxt; nxt = t_;
+    }
+}
+
+// ---------------------------------------------------------------- GEMM  C = A Bt^T
+
+struct GemmArgs {
+    const __bf16* A; int64_t lda;    // [M][K], k contiguous
+    const __bf16* Bt; int64_t ldb;   // [N][K], k contiguous
+    int M, N, K;                     // K a multiple of 32; operands hold zeros beyond their true extent
+    // epilogue
+    float* C; int64_t ldc;           // FP32 [M][N] (rows < Mst, cols < Nst stored)
+    int Mst, Nst;
+    const float* Z; int64_t ldz;     // optional: C <- C * gelu'(Z) and also emit BF16 copies
+    __bf16* G; int64_t ldg;          // BF16 [M][..] of the (scaled) result, zero where col >= Nst
+    __bf16* GT; int64_t ldgt;        // BF16 transposed [N][..], zero where col >= Nst
+};
+
+// 64 x 64 output tile per workgroup, 4 waves of 32 x 32 (2 x 2 MFMA
+// tiles); K in steps of 32 staged through LDS.
+__global__ void __launch_bounds__(256) mlp_gemm_kernel(GemmArgs P) {
+    __shared__ __align__(16) __bf16 sA[64][40];
+    __shared__ __align__(16) __bf16 sB[64][40];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // staging: 64 rows x 32 k = 256 chunks of 8 BF16; one chunk per thread per operand
+    const int sr = tid >> 2, sk = (tid & 3) * 8;
+    for (int k = 0; k < P.K; k += 32) {
+        bf16x8 va = bf16x8{}, vb = bf16x8{};
+        if (m0 + sr < P.M) va = *reinterpret_cast<const bf16x8*>(P.A + (int64_t)(m0 + sr) * P.lda + k + sk);
+        if (n0 + sr < P.N) vb = *reinterpret_cast<const bf16x8*>(P.Bt + (int64_t)(n0 + sr) * P.ldb + k + sk);
+        __syncthreads();
+        *reinterpret_cast<bf16x8*>(&sA[sr][sk]) = va;
+        *reinterpret_cast<bf16x8*>(&sB[sr][sk]) = vb;
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const bf16x8 fa = *reinterpret_cast<const bf16x8*>(&sA[wm + a * 16 + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const bf16x8 fb = *reinterpret_cast<const bf16x8*>(&sB[wn + b * 16 + (lane & 15)][8 * (lane >> 4)]);
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, acc[a][b], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int m = m0 + wm + a * 16 + 4 * (lane >> 4) + i;
+                const int n = n0 + wn + b * 16 + (lane & 15);
+                if (m >= P.M || n >= P.N) continue;
+                float v = acc[a][b][i];
+                const bool in = m < P.Mst && n < P.Nst;
+                if (P.Z) v = in ? v * gelu_grad_f(P.Z[(int64_t)m * P.ldz + n]) : 0.0f;
+                if (in && P.C) P.C[(int64_t)m * P.ldc + n] = v;
+                if (P.G) P.G[(int64_t)m * P.ldg + n] = (__bf16)(in ? v : 0.0f);
+                if (P.GT) P.GT[(int64_t)n * P.ldgt + m] = (__bf16)(in ? v : 0.0f);
+            }
+}
+
+// ---------------------------------------------------------------- small kernels
+
+// dz = dy = 2 (y - t) / (B d) in [B][ldw] (zero beyond d), G = bf16(dy)
+// [B][ldw], GT [ldw][B]; per-block partial sums of (y - t)^2
+__global__ void __launch_bounds__(256) mse_kernel(const float* y, const float* t, int B, int d, int ldw, float* dz,
+                                                  __bf16* G, __bf16* GT, float* partial) {
+    __shared__ float red[256];
+    const int64_t total = (int64_t)B * ldw;
+    const float scale = 2.0f / ((float)B * (float)d);
+    float acc = 0.0f;
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < total; q += (int64_t)gridDim.x * 256) {
+        const int b = (int)(q / ldw), c = (int)(q - (int64_t)b * ldw);
+        float g = 0.0f;
+        if (c < d) {
+            const float diff = y[(int64_t)b * d + c] - t[(int64_t)b * d + c];
+            acc += diff * diff;
+            g = scale * diff;
+        }
+        const __bf16 gb = (__bf16)g;
+        dz[q] = g;
+        G[q] = gb;
+        GT[(int64_t)c * B + b] = gb;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) sum_kernel(const float* partial, int n, float scale, float* out) {
+    __shared__ float red[256];
+    float acc = 0.0f;
+    for (int q = threadIdx.x; q < n; q += 256) acc += partial[q];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0] * scale;
+}
+
+// db[c] = sum_b X[b][c] (c < n), one workgroup per 64 columns, fixed order
+__global__ void __launch_bounds__(256) colsum_kernel(const float* X, int64_t ldx, int B, int n, float* db) {
+    __shared__ float red[4][64];
+    const int c = blockIdx.x * 64 + (threadIdx.x & 63), part = threadIdx.x >> 6;
+    float acc = 0.0f;
+    if (c < n)
+        for (int b = part; b < B; b += 4) acc += X[(int64_t)b * ldx + c];
+    red[part][threadIdx.x & 63] = acc;
+    __syncthreads();
+    if (part == 0 && c < n) db[c] = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+
+__global__ void adam_kernel(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                            float eps, float c1, float c2) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const float gq = g[q];
+    const float mq = b1 * m[q] + (1.0f - b1) * gq;
+    const float vq = b2 * v[q] + (1.0f - b2) * gq * gq;
+    m[q] = mq;
+    v[q] = vq;
+    p[q] = p[q] - lr * (mq / c1) / (sqrtf(vq / c2) + eps);
+}
+
+// BF16 copies of the weights: W~ [np][kp] and W~^T [kp][np], zero padded
+__global__ void mlp_convert_kernel(MlpLayout G, const float* params, __bf16* Wt, __bf16* WtT) {
+    const int l = blockIdx.y;
+    if (l >= G.L) return;
+    const int kp = G.kp[l], np = G.np[l], in = G.w[l], out = G.w[l + 1];
+    const float* W = params + G.poff[l];
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < kp * np; q += gridDim.x * blockDim.x) {
+        const int o = q / kp, i = q - o * kp;
+        const __bf16 v = (__bf16)((o < out && i < in) ? W[(int64_t)o * in + i] : 0.0f);
+        Wt[G.woff[l] + q] = v;
+        WtT[G.woff[l] + (int64_t)i * np + o] = v;
+    }
+}
+
+static unsigned nb(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace leb
+
+using namespace leb;
+
+// ---------------------------------------------------------------- object
+
+struct leb_surrogate_s {
+    MlpLayout G;
+    int ldA = 0;               // forward LDS row stride
+    float* params = nullptr;   // device FP32, flat
+    float* m = nullptr;
+    float* v = nullptr;
+    float* grads = nullptr;
+    __bf16* Wt = nullptr;      // [sum np kp]
+    __bf16* WtT = nullptr;
+    // training workspace, grown on demand (batch rows)
+    int cap = 0;
+    float* zsave = nullptr;    // [L-1][B][MAX_WIDTH]
+    __bf16* aT = nullptr;      // [L][MAX_WIDTH][B]
+    float* y = nullptr;        // [B][dL]
+    float* dz[2] = {nullptr, nullptr};     // [B][MAX_WIDTH]
+    __bf16* g[2] = {nullptr, nullptr};     // [B][MAX_WIDTH]
+    __bf16* gT[2] = {nullptr, nullptr};    // [MAX_WIDTH][B]
+    float* partial = nullptr;              // [1024]
+    std::mutex mu;
+};
+
+static void sur_free_ws(leb_surrogate_s* s) {
+    void* ps[] = {s->zsave, s->aT, s->y, s->dz[0], s->dz[1], s->g[0], s->g[1], s->gT[0], s->gT[1], s->partial};
+    for (void* p : ps)
+        if (p) (void)hipFree(p);
+    s->zsave = nullptr; s->aT = nullptr; s->y = nullptr; s->partial = nullptr;
+    for (int q = 0; q < 2; ++q) { s->dz[q] = nullptr; s->g[q] = nullptr; s->gT[q] = nullptr; }
+    s->cap = 0;
+}
+
+static int sur_ws(leb_surrogate_s* s, int B) {
+    if (B <= s->cap) return LEB_OK;
+    sur_free_ws(s);
+    const int L = s->G.L;
+    const size_t W = MLP_MAX_WIDTH;
+    bool ok = hipMalloc(&s->zsave, (size_t)(L > 1 ? L - 1 : 1) * B * W * sizeof(float)) == hipSuccess &&
+              hipMalloc(&s->aT, (size_t)L * W * B * sizeof(__bf16)) == hipSuccess &&
+              hipMalloc(&s->y, (size_t)B * s->G.w[L] * sizeof(float)) == hipSuccess &&
+              hipMalloc(&s->partial, 1024 * sizeof(float)) == hipSuccess;
+    for (int q = 0; q < 2 && ok; ++q)
+        ok = hipMalloc(&s->dz[q], (size_t)B * W * sizeof(float)) == hipSuccess &&
+             hipMalloc(&s->g[q], (size_t)B * W * sizeof(__bf16)) == hipSuccess &&
+             hipMalloc(&s->gT[q], (size_t)W * B * sizeof(__bf16)) == hipSuccess;
+    if (!ok) { sur_free_ws(s); return LEB_ENOMEM; }
+    s->cap = B;
+    return LEB_OK;
+}
+
+extern "C" int leb_surrogate_create(int32_t n_layers, const int32_t* widths, const float* params_host,
+                                    leb_surrogate* out) {
+    if (!out || !widths || !params_host || n_layers < 1 || n_layers > MLP_MAX_LAYERS) return LEB_EINVAL;
+    *out = nullptr;
+    for (int l = 0; l <= n_layers; ++l)
+        if (widths[l] < 1 || widths[l] > MLP_MAX_WIDTH) return LEB_EINVAL;
+    leb_surrogate_s* s = new (std::nothrow) leb_surrogate_s;
+    if (!s) return LEB_ENOMEM;
+    MlpLayout& G = s->G;
+    memset(&G, 0, sizeof(G));
+    G.L = n_layers;
+    int64_t po = 0, wo = 0;
+    for (int l = 0; l <= n_layers; ++l) G.w[l] = widths[l];
+    for (int l = 0; l < n_layers; ++l) {
+        G.kp[l] = pad32(widths[l]);
+        G.np[l] = pad32(widths[l + 1]);
+        G.poff[l] = po;
+        po += (int64_t)widths[l] * widths[l + 1] + widths[l + 1];
+        G.woff[l] = wo;
+        wo += (int64_t)G.kp[l] * G.np[l];
+    }
+    G.nparams = po;
+    G.nw = wo;
+    int widest = 0;
+    for (int l = 0; l < n_layers; ++l) widest = widest > G.kp[l] ? widest : G.kp[l];
+    for (int l = 0; l < n_layers; ++l) widest = widest > G.np[l] ? widest : G.np[l];
+    s->ldA = widest + 8;
+    const size_t smem = 2 * (size_t)FWD_ROWS * s->ldA * sizeof(__bf16);
+    if (smem > 65536 &&
+        hipFuncSetAttribute((const void*)mlp_fwd_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) !=
+            hipSuccess) {
+        delete s;
+        return LEB_EDEVICE;
+    }
+    const size_t pb = (size_t)po * sizeof(float);
+    bool ok = hipMalloc(&s->params, pb) == hipSuccess && hipMalloc(&s->m, pb) == hipSuccess &&
+              hipMalloc(&s->v, pb) == hipSuccess && hipMalloc(&s->grads, pb) == hipSuccess &&
+              hipMalloc(&s->Wt, (size_t)wo * sizeof(__bf16)) == hipSuccess &&
+              hipMalloc(&s->WtT, (size_t)wo * sizeof(__bf16)) == hipSuccess;
+    ok = ok && hipMemcpy(s->params, params_host, pb, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemset(s->m, 0, pb) == hipSuccess && hipMemset(s->v, 0, pb) == hipSuccess;
+    if (ok) {
+        hipLaunchKernelGGL(mlp_convert_kernel, dim3(64, n_layers), dim3(256), 0, 0, G, s->params, s->Wt, s->WtT);
+        ok = hipGetLastError() == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+    }
+    if (!ok) {
+        leb_surrogate_destroy(s);
+        return LEB_ENOMEM;
+    }
+    *out = s;
+    return LEB_OK;
+}
+
+extern "C" int leb_surrogate_destroy(leb_surrogate s) {
+    if (!s) return LEB_OK;
+    void* ps[] = {s->params, s->m, s->v, s->grads, s->Wt, s->WtT};
+    for (void* p : ps)
+        if (p) (void)hipFree(p);
+    sur_free_ws(s);
+    delete s;
+    return LEB_OK;
+}
+
+extern "C" int leb_surrogate_params(leb_surrogate s, float* params_host) {
+    if (!s || !params_host) return LEB_EINVAL;
+    std::lock_guard<std::mutex> lock(s->mu);
+    if (hipDeviceSynchronize() != hipSuccess) return LEB_EDEVICE;
+    return hipMemcpy(params_host, s->params, (size_t)s->G.nparams * sizeof(float), hipMemcpyDeviceToHost) ==
+                   hipSuccess
+               ? LEB_OK
+               : LEB_EDEVICE;
+}
+
+extern "C" int64_t leb_surrogate_n_params(leb_surrogate s) { return s ? s->G.nparams : -1; }
+
+extern "C" int leb_surrogate_dims(leb_surrogate s, int32_t* d_in, int32_t* d_out) {
+    if (!s) return LEB_EINVAL;
+    if (d_in) *d_in = s->G.w[0];
+    if (d_out) *d_out = s->G.w[s->G.L];
+    return LEB_OK;
+}
+
+static int fwd_launch(leb_surrogate_s* s, int B, const float* x, float* y, bool save, hipStream_t st) {
+    FwdArgs a;
+    a.G = s->G; a.Wt = s->Wt; a.params = s->params; a.x = x; a.y = y; a.B = B;
+    a.zsave = save ? s->zsave : nullptr;
+    a.aT = save ? s->aT : nullptr;
+    a.ldA = s->ldA;
+    const size_t smem = 2 * (size_t)FWD_ROWS * s->ldA * sizeof(__bf16);
+    hipLaunchKernelGGL(mlp_fwd_kernel, dim3(nb(B, FWD_ROWS)), dim3(256), smem, st, a);
+    return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
+}
+
+extern "C" int leb_mlp_fwd_bf16(leb_surrogate s, int32_t batch, const float* x, float* y, void* stream) {
+    if (!s || batch < 0) return LEB_EINVAL;
+    if (batch == 0) return LEB_OK;
+    if (!x || !y || !aligned8(x) || !aligned8(y)) return LEB_EINVAL;
+    return fwd_launch(s, batch, x, y, false, (hipStream_t)stream);
+}
+
+// backward of sum(dy . y) from the saved forward (zsave, aT) and g_L in g[0]/gT[0]
+static int bwd_core(leb_surrogate_s* s, int B, float* grads, hipStream_t st) {
+    const MlpLayout& G = s->G;
+    const int W = MLP_MAX_WIDTH;
+    int cur = 0;
+    for (int l = G.L - 1; l >= 0; --l) {
+        const int in = G.w[l], out = G.w[l + 1];
+        float* dW = grads + G.poff[l];
+        float* db = dW + (int64_t)in * out;
+        // dW_l [out][in] = g_l^T a_{l-1}: A = gT [out][B], Bt = aT_{l} [in][B], K = B
+        GemmArgs p{};
+        p.A = s->gT[cur]; p.lda = B;
+        p.Bt = s->aT + (int64_t)l * W * B; p.ldb = B;
+        p.M = out; p.N = in; p.K = B;
+        p.C = dW; p.ldc = in; p.Mst = out; p.Nst = in;
+        hipLaunchKernelGGL(mlp_gemm_kernel, dim3(nb(in, 64), nb(out, 64)), dim3(256), 0, st, p);
+        // db_l = column sums of dz_l
+        hipLaunchKernelGGL(colsum_kernel, dim3(nb(out, 64)), dim3(256), 0, st, s->dz[cur], (int64_t)W, B, out, db);
+        if (l > 0) {
+            // dz_{l-1} = (g_l W~_l) * gelu'(z_{l-1}): A = g [B][np_l], Bt = W~_l^T [kp_l][np_l]
+            GemmArgs q{};
+            q.A = s->g[cur]; q.lda = W;
+            q.Bt = s->WtT + G.woff[l]; q.ldb = G.np[l];
+            q.M = B; q.N = G.kp[l]; q.K = G.np[l];
+            q.C = s->dz[cur ^ 1]; q.ldc = W; q.Mst = B; q.Nst = in;
+            q.Z = s->zsave + (int64_t)(l - 1) * B * W; q.ldz = W;
+            q.G = s->g[cur ^ 1]; q.ldg = W;
+            q.GT = s->gT[cur ^ 1]; q.ldgt = B;
+            hipLaunchKernelGGL(mlp_gemm_kernel, dim3(nb(G.kp[l], 64), nb(B, 64)), dim3(256), 0, st, q);
+            cur ^= 1;
+        }
+    }
+    return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
+}
+
+// g_L, gT_L and dz_L from dy [B][dL]
+__global__ void dy_stage_kernel(const float* dy, int B, int d, float* dz, __bf16* G, __bf16* GT, int ldw) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)B * ldw;
+    if (q >= total) return;
+    const int b = (int)(q / ldw), c = (int)(q - (int64_t)b * ldw);
+    const float v = c < d ? dy[(int64_t)b * d + c] : 0.0f;
+    const __bf16 gb = (__bf16)v;
+    dz[q] = v;
+    G[q] = gb;
+    GT[(int64_t)c * B + b] = gb;
+}
+
+extern "C" int leb_mlp_bwd_bf16(leb_surrogate s, int32_t batch, const float* x, const float* dy, float* grads,
+                                void* stream) {
+    if (!s || batch < 0) return LEB_EINVAL;
+    if (batch == 0) return LEB_OK;
+    if (!x || !dy || !grads || (batch & 31)) return LEB_EINVAL;
+    std::lock_guard<std::mutex> lock(s->mu);
+    hipStream_t st = (hipStream_t)stream;
+    int rc = sur_ws(s, batch);
+    if (rc) return rc;
+    if ((rc = fwd_launch(s, batch, x, s->y, true, st))) return rc;
+    hipLaunchKernelGGL(dy_stage_kernel, dim3(nb((int64_t)batch * MLP_MAX_WIDTH)), dim3(256), 0, st, dy, batch,
+                       s->G.w[s->G.L], s->dz[0], s->g[0], s->gT[0], MLP_MAX_WIDTH);
+    return bwd_core(s, batch, grads, st);
+}
+
+static int adam_launch(leb_surrogate_s* s, const float* grads, int step, float lr, float b1, float b2, float eps,
+                       hipStream_t st) {
+    const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+    hipLaunchKernelGGL(adam_kernel, dim3(nb(s->G.nparams)), dim3(256), 0, st, s->params, grads, s->m, s->v,
+                       s->G.nparams, lr, b1, b2, eps, c1, c2);
+    hipLaunchKernelGGL(mlp_convert_kernel, dim3(64, s->G.L), dim3(256), 0, st, s->G, s->params, s->Wt, s->WtT);
+    return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
+}
+
+extern "C" int leb_adam_step(leb_surrogate s, const float* grads, int32_t step, float lr, float beta1, float beta2,
+                             float eps, void* stream) {
+    if (!s || !grads || step < 1 || !(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) ||
+        !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+        return LEB_EINVAL;
+    std::lock_guard<std::mutex> lock(s->mu);
+    return adam_launch(s, grads, step, lr, beta1, beta2, eps, (hipStream_t)stream);
+}
+
+extern "C" int leb_surrogate_train_step(leb_surrogate s, int32_t batch, const float* x, const float* t,
+                                        int32_t step, float lr, float* loss, void* stream) {
+    if (!s || !x || !t || batch <= 0 || (batch & 31) || step < 1 || !(lr >= 0.0f)) return LEB_EINVAL;
+    std::lock_guard<std::mutex> lock(s->mu);
+    hipStream_t st = (hipStream_t)stream;
+    int rc = sur_ws(s, batch);
+    if (rc) return rc;
+    if ((rc = fwd_launch(s, batch, x, s->y, true, st))) return rc;
+    const int d = s->G.w[s->G.L];
+    const int nblocks = 256;
+    hipLaunchKernelGGL(mse_kernel, dim3(nblocks), dim3(256), 0, st, s->y, t, batch, d, MLP_MAX_WIDTH, s->dz[0],
+                       s->g[0], s->gT[0], s->partial);
+    if (loss)
+        hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, st, s->partial, nblocks, 1.0f / ((float)batch * d), loss);
+    if ((rc = bwd_core(s, batch, s->grads, st))) return rc;
+    return adam_launch(s, s->grads, step, lr, 0.9f, 0.999f, 1e-8f, st);
+}

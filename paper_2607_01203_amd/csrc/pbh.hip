@@ -58,6 +58,7 @@ struct RowOut { double xlo, xhi, zlo, zhi; };
 struct ChainArgs {
     const double* z; const double* v; const double* mu; const double* sigma;
     double* r_lo; double* r_hi; double* c_bar; double* rho_bar; uint32_t* flags;
+    const uint32_t* open;   // optional: return at once when *open == 0 (fixed point already certified)
     int64_t units;
     int U, T;
     double c;        // dt / m
@@ -77,6 +78,7 @@ __global__ void __launch_bounds__(PBH_BLOCK) pbh_chain_fwd(ChainArgs A) {
     RowOut* s_row = reinterpret_cast<RowOut*>(s_sp + (size_t)T * U);       // [T][U]
     uint32_t* s_flag = reinterpret_cast<uint32_t*>(s_row + (size_t)T * U); // [T]
 
+    if (A.open && *A.open == 0u) return;
     const int tid = threadIdx.x;
     const int64_t u0 = (int64_t)blockIdx.x * T;
     const int64_t left = A.units - u0;
@@ -249,10 +251,11 @@ size_t pbh_smem_bytes(int U) {
 
 int launch_pbh_chain(const leb_dynamics* dyn, int64_t units, const double* z, const double* v,
                      const double* mu, const double* sigma, double* r_lo, double* r_hi, double* c_bar,
-                     double* rho_bar, double pad, uint32_t* flags, hipStream_t stream) {
+                     double* rho_bar, double pad, uint32_t* flags, hipStream_t stream, const uint32_t* open) {
     ChainArgs a;
     a.z = z; a.v = v; a.mu = mu; a.sigma = sigma;
     a.r_lo = r_lo; a.r_hi = r_hi; a.c_bar = c_bar; a.rho_bar = rho_bar; a.flags = flags;
+    a.open = open;
     a.units = units;
     a.U = dyn->n_units;
     a.T = PBH_BLOCK / a.U;

@@ -1,0 +1,226 @@
+// surrogate.hip -- features, targets and decoding of the learned warm start,
+// and the learned tube/LEB fixed point.
+//
+// The surrogate predicts, for node i of a chain at one timestep, the bound
+// of its two non-linear rows (vx_i+, vz_i+) from the quantities the
+// path-based bound of those rows depends on (Theorem 1 over the prefix
+// boxes of node i's attitude block and of its two springs):
+//   nominal theta_i, u1_i + u2_i, the spring separations to the
+//   neighbours, and the displacement intervals
+//   Delta_c = [min(mu_c - sigma_c, 0), max(mu_c + sigma_c, 0)]
+//   of theta_i, u1_i, u2_i and of the positions of nodes i-1, i, i+1.
+// Outputs (regression targets): log(max(hi, 1e-14)) and log(max(-lo, 1e-14))
+// of the vx and vz rows (every term of the bound contains 0, so lo <= 0 <= hi).
+//
+// The learned fixed point runs the tube iteration with surrogate bounds
+// for a few sweeps (the initial tube), inflates it, and hands it to the
+// certified iteration as a warm start; the result is certified by the
+// plain bound exactly as from a cold start.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <mutex>
+
+#include "leb.h"
+#include "leb_internal.hpp"
+
+namespace leb {
+
+constexpr float DSCALE = 20.0f;      // 1 / 0.05: displacements of the tube scale to O(1)
+constexpr float LOG_FLOOR = 1e-14f;
+
+// one thread per (unit, node)
+__global__ void chain_features_kernel(const double* z, const double* v, const double* mu, const double* sigma,
+                                      int64_t units, int U, double L0, float* X) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= units * U) return;
+    const int64_t u = q / U;
+    const int i = (int)(q - u * U);
+    const int nx = 6 * U, nu = 2 * U, n = nx + nu;
+    const double* zn = z + u * nx;
+    const double* vn = v + u * nu;
+    const double* m = mu ? mu + u * n : nullptr;
+    const double* s = sigma + u * n;
+    auto dlo = [&](int c) { return (float)(fmin((m ? m[c] : 0.0) - s[c], 0.0) * DSCALE); };
+    auto dhi = [&](int c) { return (float)(fmax((m ? m[c] : 0.0) + s[c], 0.0) * DSCALE); };
+    float* f = X + q * LEB_CHAIN_FEATURES;
+    const int th = 6 * i + 2, px = 6 * i, pz = 6 * i + 1, u1 = nx + 2 * i, u2 = u1 + 1;
+    f[0] = (float)zn[th];
+    f[1] = (float)((vn[2 * i] + vn[2 * i + 1]) * 0.1);
+    f[2] = dlo(th); f[3] = dhi(th);
+    f[4] = dlo(u1); f[5] = dhi(u1);
+    f[6] = dlo(u2); f[7] = dhi(u2);
+    f[8] = dlo(px); f[9] = dhi(px);
+    f[10] = dlo(pz); f[11] = dhi(pz);
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const int j = side == 0 ? i + 1 : i - 1;      // right, then left neighbour
+        float* g = f + 12 + 7 * side;
+        if (j >= 0 && j < U) {
+            const int a = side == 0 ? i : j, b = side == 0 ? j : i;   // spring from node a to node b = a + 1
+            g[0] = 1.0f;
+            g[1] = (float)(L0 + zn[6 * b] - zn[6 * a]);
+            g[2] = (float)(zn[6 * b + 1] - zn[6 * a + 1]);
+            g[3] = dlo(6 * j); g[4] = dhi(6 * j);
+            g[5] = dlo(6 * j + 1); g[6] = dhi(6 * j + 1);
+        } else {
+#pragma unroll
+            for (int t = 0; t < 7; ++t) g[t] = 0.0f;
+        }
+    }
+}
+
+// targets from a bound: one thread per (unit, node)
+__global__ void chain_targets_kernel(const double* r_lo, const double* r_hi, int64_t units, int U, float* T) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= units * U) return;
+    const int64_t u = q / U;
+    const int i = (int)(q - u * U);
+    const int64_t o = u * 6 * U + 6 * i;
+    float* t = T + q * LEB_CHAIN_OUTPUTS;
+    t[0] = logf(fmaxf((float)r_hi[o + 3], LOG_FLOOR));
+    t[1] = logf(fmaxf((float)-r_lo[o + 3], LOG_FLOOR));
+    t[2] = logf(fmaxf((float)r_hi[o + 4], LOG_FLOOR));
+    t[3] = logf(fmaxf((float)-r_lo[o + 4], LOG_FLOOR));
+}
+
+// predicted bounds -> residual zonotope (c_bar, rho_bar): one thread per (unit, row)
+__global__ void chain_decode_kernel(const float* Y, int64_t units, int U, double pad, double* cb, double* rb) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int nx = 6 * U;
+    if (q >= units * nx) return;
+    const int64_t u = q / nx;
+    const int row = (int)(q - u * nx), i = row / 6, rc = row - 6 * i;
+    double c = 0.0, r = 0.0;
+    if (rc == 3 || rc == 4) {
+        const float* y = Y + (u * U + i) * LEB_CHAIN_OUTPUTS + 2 * (rc - 3);
+        // a prediction that is not finite counts as a zero bound (the
+        // certified iteration then starts below the fixed point); bounds
+        // above 1 are clamped
+        const double yh = isfinite(y[0]) ? fmin((double)y[0], 0.0) : -1e30;
+        const double yl = isfinite(y[1]) ? fmin((double)y[1], 0.0) : -1e30;
+        const double hi = exp(yh), lo = -exp(yl);
+        c = 0.5 * (lo + hi);
+        r = 0.5 * (hi - lo);
+    }
+    cb[q] = c;
+    rb[q] = r + pad;
+}
+
+__global__ void scale_sigma_kernel(double* sigma, int64_t count, double f, double a) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < count) sigma[q] = sigma[q] * f + a;
+}
+
+__global__ void fill64_kernel(double* dst, int64_t count, double v) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < count) dst[q] = v;
+}
+
+static unsigned nbk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+struct SurWorkspace {
+    std::mutex mu;
+    float* X = nullptr; float* Y = nullptr; double* cb = nullptr; double* rb = nullptr;
+    int64_t cap_nodes = 0, cap_rows = 0;
+};
+static SurWorkspace g_sw;
+
+static int sw_get(int64_t nodes, int64_t rows) {
+    if (nodes > g_sw.cap_nodes) {
+        if (g_sw.X) (void)hipFree(g_sw.X);
+        if (g_sw.Y) (void)hipFree(g_sw.Y);
+        g_sw.X = nullptr; g_sw.Y = nullptr; g_sw.cap_nodes = 0;
+        if (hipMalloc(&g_sw.X, (size_t)nodes * LEB_CHAIN_FEATURES * sizeof(float)) != hipSuccess ||
+            hipMalloc(&g_sw.Y, (size_t)nodes * LEB_CHAIN_OUTPUTS * sizeof(float)) != hipSuccess)
+            return LEB_ENOMEM;
+        g_sw.cap_nodes = nodes;
+    }
+    if (rows > g_sw.cap_rows) {
+        if (g_sw.cb) (void)hipFree(g_sw.cb);
+        if (g_sw.rb) (void)hipFree(g_sw.rb);
+        g_sw.cb = nullptr; g_sw.rb = nullptr; g_sw.cap_rows = 0;
+        if (hipMalloc(&g_sw.cb, (size_t)rows * sizeof(double)) != hipSuccess ||
+            hipMalloc(&g_sw.rb, (size_t)rows * sizeof(double)) != hipSuccess)
+            return LEB_ENOMEM;
+        g_sw.cap_rows = rows;
+    }
+    return LEB_OK;
+}
+
+}  // namespace leb
+
+using namespace leb;
+
+extern "C" int leb_chain_features(const leb_dynamics* dyn, int32_t batch, int32_t N, const double* z, const double* v,
+                                  const double* mu, const double* sigma, float* x, void* stream) {
+    int rc = check_chain_dynamics(dyn);
+    if (rc != LEB_OK) return rc;
+    if (dyn->kind != LEB_DYN_PQUAD_CHAIN || batch < 0 || N < 0) return LEB_EINVAL;
+    const int64_t units = (int64_t)batch * N;
+    if (units == 0) return LEB_OK;
+    if (!z || !v || !sigma || !x) return LEB_EINVAL;
+    hipLaunchKernelGGL(chain_features_kernel, dim3(nbk(units * dyn->n_units)), dim3(256), 0, (hipStream_t)stream, z, v,
+                       mu, sigma, units, dyn->n_units, dyn->rest_len, x);
+    return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
+}
+
+extern "C" int leb_chain_targets(const leb_dynamics* dyn, int32_t batch, int32_t N, const double* r_lo,
+                                 const double* r_hi, float* t, void* stream) {
+    int rc = check_chain_dynamics(dyn);
+    if (rc != LEB_OK) return rc;
+    if (dyn->kind != LEB_DYN_PQUAD_CHAIN || batch < 0 || N < 0) return LEB_EINVAL;
+    const int64_t units = (int64_t)batch * N;
+    if (units == 0) return LEB_OK;
+    if (!r_lo || !r_hi || !t) return LEB_EINVAL;
+    hipLaunchKernelGGL(chain_targets_kernel, dim3(nbk(units * dyn->n_units)), dim3(256), 0, (hipStream_t)stream, r_lo,
+                       r_hi, units, dyn->n_units, t);
+    return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
+}
+
+extern "C" int leb_fixed_point_learned(const leb_dynamics* dyn, int32_t batch, int32_t N, const double* z,
+                                       const double* v, const double* phi, const double* e, const leb_fp_options* opt,
+                                       const leb_warm_start* ws, double* mu, double* sigma, uint32_t* certified,
+                                       int32_t* sweeps_out, void* stream) {
+    int rc = check_chain_dynamics(dyn);
+    if (rc != LEB_OK) return rc;
+    if (dyn->kind != LEB_DYN_PQUAD_CHAIN) return LEB_ENOTSUP;
+    if (!opt || !ws || !ws->net || !e || !sweeps_out || batch < 0 || N < 0) return LEB_EINVAL;
+    if (ws->sweeps < 0 || !(ws->margin >= 0.0) || !isfinite(ws->margin)) return LEB_EINVAL;
+    int32_t din = 0, dout = 0;
+    if (leb_surrogate_dims(ws->net, &din, &dout) || din != LEB_CHAIN_FEATURES || dout != LEB_CHAIN_OUTPUTS)
+        return LEB_EINVAL;
+    *sweeps_out = 0;
+    const int64_t units = (int64_t)batch * N;
+    if (units == 0) return LEB_OK;
+    if (!z || !v || !mu || !sigma || !certified || (N > 1 && !phi)) return LEB_EINVAL;
+    const int U = dyn->n_units, nx = dyn->nx, n = dyn->nx + dyn->nu;
+    const int64_t nodes = units * U;
+    if (nodes > 0x7fffffff) return LEB_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    {
+        std::lock_guard<std::mutex> lock(g_sw.mu);
+        if ((rc = sw_get(nodes, units * nx))) return rc;
+        // C_0: disturbance-only tube
+        hipLaunchKernelGGL(fill64_kernel, dim3(nbk(units * nx)), dim3(256), 0, s, g_sw.cb, units * nx, 0.0);
+        hipLaunchKernelGGL(fill64_kernel, dim3(nbk(units * nx)), dim3(256), 0, s, g_sw.rb, units * nx, opt->pad);
+        if ((rc = launch_tube_map(batch, N, U, phi, e, g_sw.cb, g_sw.rb, mu, sigma, s))) return rc;
+        // surrogate sweeps: C <- T(surrogate bound of C)
+        for (int t = 0; t < ws->sweeps; ++t) {
+            hipLaunchKernelGGL(chain_features_kernel, dim3(nbk(nodes)), dim3(256), 0, s, z, v, mu, sigma, units, U,
+                               dyn->rest_len, g_sw.X);
+            if ((rc = leb_mlp_fwd_bf16(ws->net, (int32_t)nodes, g_sw.X, g_sw.Y, stream))) return rc;
+            hipLaunchKernelGGL(chain_decode_kernel, dim3(nbk(units * nx)), dim3(256), 0, s, g_sw.Y, units, U,
+                               opt->pad, g_sw.cb, g_sw.rb);
+            if ((rc = launch_tube_map(batch, N, U, phi, e, g_sw.cb, g_sw.rb, mu, sigma, s))) return rc;
+        }
+        // warm start above the surrogate's fixed point
+        hipLaunchKernelGGL(scale_sigma_kernel, dim3(nbk(units * n)), dim3(256), 0, s, sigma, units * n,
+                           1.0 + ws->margin, opt->inflate_abs);
+        if (hipGetLastError() != hipSuccess) return LEB_EDEVICE;
+    }
+    leb_fp_options o = *opt;
+    o.warm = 1;
+    return leb_fixed_point_solve(dyn, batch, N, z, v, phi, e, &o, mu, sigma, certified, sweeps_out, stream);
+}

@@ -7,21 +7,21 @@
 // shared by every node (rows 0..5 -> node state rows of the tube, rows 6..7
 // -> node input rows; columns -> node residual rows).
 //
-// Fixed point: B -> LEB(B) -> (c_bar, rho_bar) -> tube map -> F(B).  F is
-// inclusion-isotone, so a box with F(B) inside B contains the least fixed
+// Fixed point: C -> LEB(C) -> (c_bar, rho_bar) -> tube map -> F(C).  F is
+// inclusion-isotone, so a tube with F(C) inside C contains the least fixed
 // point and certifies the tube by induction over k (the argument of the
 // Theorem 3 proof).  Jacobi sweeps update every k at once; causality (the
 // tube at k uses steps j < k) bounds the number of sweeps to reach the
-// exact fixed point by N.
+// fixed point by N.
 //
 // Certification.  Where the bounds grow faster than linearly in the tube
 // radius and exceed the disturbance, F expands locally, so no uniform
-// inflation of the least fixed point B* is a post-fixed point.  The causal
+// inflation of the least fixed point C* is a post-fixed point.  The causal
 // structure (the Jacobian of F is nilpotent) still gives post-fixed points
-// B* + (I - J)^-1 w for any w > 0, and the inflated Jacobi iteration
+// C* + (I - J)^-1 w for any w > 0, and the inflated Jacobi iteration
 //   C <- F(C) (1 + tol) + abs
-// converges to one of them, about tol above B*.  A trajectory is certified
-// (and frozen) on the sweep that shows F(C) inside C.
+// converges to one of them, about tol above C*.  A trajectory is certified
+// (and frozen) by the sweep that shows F(C) inside C.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -34,18 +34,26 @@
 
 namespace leb {
 
-// Fixed-point epilogue of the tube map (all NULL for the plain map).
+// Per-trajectory fixed-point state word.
+constexpr uint32_t FP_CERT = 1u;          // certified (frozen)
+constexpr uint32_t FP_OPEN = 1u << 31;    // this sweep: F(C) not inside C
+constexpr int FP_SLOTS = 4096;            // host-visible open counts, one per sweep (mod FP_SLOTS)
+
+// Fixed-point epilogue of the tube map (state == NULL for the plain map).
 struct TubeFP {
-    const double* mu_in;  // C_t: the tube whose bounds produced (c_bar, rho_bar)
+    const double* mu_in;  // C_{t-1}: the tube whose bounds produced (c_bar, rho_bar)
     const double* sg_in;
-    uint32_t* state;      // [B]: bit 0 certified (frozen), bit 1 F(C_t) not inside C_t
-    double tol, abs_;     // C_{t+1} = (mu_F, sigma_F (1 + tol) + abs_)
+    uint32_t* state;      // [B] state words, [B] open count, [B+1] finished-workgroup counter
+    uint32_t* host_open;  // host-mapped [FP_SLOTS]: open count after each sweep
+    double tol, abs_;     // C_t = (mu_F, sigma_F (1 + tol) + abs_)
+    int sweep;            // t (1-based)
 };
 
 struct TubeArgs {
     const double* cbar; const double* rbar;   // [B][N][nx]
     double e[6];
     double* mu; double* sigma;                // [B][N][n] out
+    double wid;        // relative rounding allowance of the tube sums
     int B, N, U;
     int groups;        // k-groups per column group (4 k-pairs each)
     int total;         // workgroups in the grid
@@ -58,7 +66,14 @@ struct TubeArgs {
 // the residual centres and radii come through vector loads shared in L2 by
 // the waves of the same columns (the workgroup order is remapped so those
 // land on one XCD).
+//
+// Fixed-point form: frozen trajectories are not written; containment
+// failures are or-ed into the state words, and the last workgroup to
+// finish turns them into the next state (certified at this sweep, or open)
+// and publishes the open count to the device word and to host memory.
 __global__ void __launch_bounds__(256) tube_map_kernel(const double* __restrict__ phi, TubeArgs A, TubeFP P) {
+    const bool fp = P.state != nullptr;
+    if (fp && P.state[A.B] == 0u) return;     // every trajectory certified by an earlier sweep
     // XCD-aware order: workgroup ids are dealt round-robin over 8 XCDs;
     // give each XCD a contiguous range of (column group, k-group) tiles.
     const int id = blockIdx.x, x = id & 7, pos = id >> 3;
@@ -69,7 +84,6 @@ __global__ void __launch_bounds__(256) tube_map_kernel(const double* __restrict_
     const int lane = threadIdx.x & 63;
     const int npairs = (A.N + 1) >> 1;
     const int p = g * 4 + wave;
-    if (p >= npairs) return;
     const int cols = A.B * A.U;
     const int col = cg * 64 + lane;
     const bool valid = col < cols;
@@ -78,11 +92,10 @@ __global__ void __launch_bounds__(256) tube_map_kernel(const double* __restrict_
     const int nx = 6 * A.U, n = 8 * A.U;
     const double* cb = A.cbar + ((int64_t)b * A.N) * nx + 6 * i;
     const double* rb = A.rbar + ((int64_t)b * A.N) * nx + 6 * i;
-    const bool fp = P.state != nullptr;
-    const bool frozen = fp && (P.state[b] & 1u);
+    const bool frozen = fp && (P.state[b] & FP_CERT);
     // first lane of this wave holding trajectory b (columns of one trajectory are contiguous)
     const int first = max(0, b * A.U - cg * 64);
-    for (int half = 0; half < 2; ++half) {
+    for (int half = 0; half < 2 && p < npairs; ++half) {
         const int k = half ? A.N - 1 - p : p;
         if (half && k == p) break;
         double m[8], s[8];
@@ -96,7 +109,7 @@ __global__ void __launch_bounds__(256) tube_map_kernel(const double* __restrict_
             for (int q = 0; q < 6; ++q) {
                 c[q] = cb[(int64_t)j * nx + q];
                 // residual radius plus the allowance for the rounding of the centre sum
-                w[q] = A.e[q] + rb[(int64_t)j * nx + q] + fabs(c[q]) * 0x1p-44;
+                w[q] = A.e[q] + rb[(int64_t)j * nx + q] + fabs(c[q]) * A.wid;
             }
 #pragma unroll
             for (int r = 0; r < 8; ++r)
@@ -107,74 +120,83 @@ __global__ void __launch_bounds__(256) tube_map_kernel(const double* __restrict_
                     s[r] = __builtin_fma(fabs(ph), w[q], s[r]);
                 }
         }
-        // sums of at most 6 (N-1) rounded products: relative error below 2^-44 for N <= 2^7
         bool bad = false;
         const int64_t row0 = ((int64_t)b * A.N + k) * n;
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             const int64_t o = row0 + (r < 6 ? 6 * i + r : nx + 2 * i + (r - 6));
-            const double sF = s[r] + s[r] * 0x1p-44, mF = m[r];
-            double mo = mF, so = sF;
+            const double sF = s[r] + s[r] * A.wid, mF = m[r];
+            double so = sF;
             if (fp) {
                 const double mi = P.mu_in[o], si = P.sg_in[o];
-                if (frozen) {
-                    mo = mi; so = si;
-                } else {
-                    // [mF - sF, mF + sF] inside [mi - si, mi + si], with the rounding of the test covered
-                    bad |= !((fabs(mF - mi) + sF) * (1.0 + 0x1p-50) <= si);
-                    so = sF + sF * P.tol + P.abs_;
-                }
+                // [mF - sF, mF + sF] inside [mi - si, mi + si], with the rounding of the test covered
+                bad |= !((fabs(mF - mi) + sF) * (1.0 + 0x1p-50) <= si);
+                so = sF + sF * P.tol + P.abs_;
             }
-            if (valid) { A.mu[o] = mo; A.sigma[o] = so; }
+            if (valid && !frozen) { A.mu[o] = mF; A.sigma[o] = so; }
         }
         if (fp) {
-            bad = bad && valid;
+            bad = bad && valid && !frozen;
             const uint64_t mask = __ballot(bad);
             const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
             const uint64_t same = ~0ull << first;
-            if (bad && !(mask & below & same)) atomicOr(&P.state[b], 2u);
+            if (bad && !(mask & below & same)) atomicOr(&P.state[b], FP_OPEN);
         }
     }
-}
-
-// Per sweep, after the tube map: commit trajectories whose C_t was shown
-// certified (state == 0: not frozen, contained) into the output tube.
-// With final != 0: commit every trajectory not yet certified (sweep cap).
-__global__ void fp_commit_kernel(const double* mu_in, const double* sg_in, double* mu, double* sg,
-                                 const uint32_t* state, int64_t per_traj, int64_t count, int final_) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= count) return;
-    const uint32_t st = state[q / per_traj];
-    const bool go = final_ ? !(st & 1u) : st == 0u;
-    if (go && mu_in != mu) { mu[q] = mu_in[q]; sg[q] = sg_in[q]; }
-}
-
-// state[b]: certified once contained; clear the per-sweep bit.  state[B]
-// receives the number of trajectories not yet certified.
-__global__ void __launch_bounds__(256) fp_state_kernel(uint32_t* state, int B) {
+    if (!fp) return;
+    // last workgroup to finish: fold this sweep's containment into the state words
+    __shared__ uint32_t last;
+    __threadfence();        // this thread's state updates are visible device-wide
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(&P.state[A.B + 1], 1u) == (uint32_t)(A.total - 1);
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
     __shared__ uint32_t cnt;
     if (threadIdx.x == 0) cnt = 0;
     __syncthreads();
     uint32_t open = 0;
-    for (int b = threadIdx.x; b < B; b += 256) {
-        const uint32_t st = state[b];
-        const uint32_t ns = (st & 1u) | ((st & 2u) ? 0u : 1u);
-        state[b] = ns;
-        open += ns ? 0u : 1u;
+    for (int t = threadIdx.x; t < A.B; t += 256) {
+        const uint32_t st = __hip_atomic_load(&P.state[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t ns = st;
+        if (!(st & FP_CERT)) {
+            ns = (st & FP_OPEN) ? 0u : (FP_CERT | ((uint32_t)P.sweep << 1));
+            __hip_atomic_store(&P.state[t], ns, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        open += (ns & FP_CERT) ? 0u : 1u;
     }
     atomicAdd(&cnt, open);
     __syncthreads();
-    if (threadIdx.x == 0) state[B] = cnt;
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(&P.state[A.B], cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&P.state[A.B + 1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&P.host_open[P.sweep % FP_SLOTS], cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
 }
 
-__global__ void u32_fill_kernel(uint32_t* dst, int64_t count, uint32_t v) {
+// After the last sweep: the certified tube of each trajectory is C_{s-1}
+// (s = the sweep that certified it), which sits in buffer (s-1) & 1; an
+// uncertified trajectory takes the latest iterate C_T from buffer T & 1.
+// Buffer 0 is the caller's; buffer 1 is copied into it where needed.
+__global__ void fp_final_kernel(const double* xm1, const double* xs1, double* mu, double* sg,
+                                const uint32_t* state, int64_t per_traj, int64_t count, int last_sweep) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < count) dst[q] = v;
+    if (q >= count) return;
+    const uint32_t st = state[q / per_traj];
+    const int src = (st & FP_CERT) ? (int)(((st >> 1) - 1) & 1u) : (last_sweep & 1);
+    if (src == 1) { mu[q] = xm1[q]; sg[q] = xs1[q]; }
+}
+
+__global__ void fp_init_kernel(uint32_t* state, int B) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < B) state[t] = 0u;
+    if (t == B) state[B] = (uint32_t)B;     // open count
+    if (t == B + 1) state[B + 1] = 0u;      // finished-workgroup counter
 }
 
 __global__ void cert_out_kernel(const uint32_t* state, uint32_t* out, int B) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < B) out[b] = state[b] & 1u;
+    if (b < B) out[b] = state[b] & FP_CERT;
 }
 
 __global__ void fill_kernel(double* dst, int64_t count, double v) {
@@ -190,6 +212,11 @@ static int launch_tube(int B, int N, int U, const double* phi, const double* e, 
     a.cbar = cbar; a.rbar = rbar;
     for (int q = 0; q < 6; ++q) a.e[q] = e[q];
     a.mu = mu; a.sigma = sigma; a.B = B; a.N = N; a.U = U;
+    // A sum of m rounded products (and the 3 operations forming a weight)
+    // errs by at most gamma_{m+3} ~ (m+3) 2^-53 relative; twice that covers
+    // both the sigma sums and, through |c_bar| wid in the weights, the
+    // rounding of the centre sums.
+    a.wid = fmax(0x1p-44, (6.0 * (N > 0 ? N - 1 : 0) + 4.0) * 0x1p-52);
     const int64_t cols = (int64_t)B * U;
     if (cols == 0 || N == 0) return LEB_OK;
     const int64_t ncg = (cols + 63) / 64;
@@ -203,7 +230,7 @@ static int launch_tube(int B, int N, int U, const double* phi, const double* e, 
 
 int launch_tube_map(int B, int N, int U, const double* phi, const double* e, const double* cbar,
                     const double* rbar, double* mu, double* sigma, hipStream_t s) {
-    TubeFP none{nullptr, nullptr, nullptr, 0.0, 0.0};
+    TubeFP none{nullptr, nullptr, nullptr, nullptr, 0.0, 0.0, 0};
     return launch_tube(B, N, U, phi, e, cbar, rbar, mu, sigma, none, s);
 }
 
@@ -213,6 +240,9 @@ struct Workspace {
     std::mutex mu;
     std::vector<void*> bufs;
     std::vector<size_t> sizes;
+    uint32_t* host_open = nullptr;      // pinned, host-mapped
+    uint32_t* host_open_dev = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
 };
 static Workspace g_ws;
 
@@ -228,6 +258,21 @@ static int ws_get(int slot, size_t bytes, void** out) {
         g_ws.sizes[slot] = bytes;
     }
     *out = g_ws.bufs[slot];
+    return LEB_OK;
+}
+
+static int ws_host_and_events() {
+    if (!g_ws.host_open) {
+        void* h = nullptr;
+        if (hipHostMalloc(&h, FP_SLOTS * sizeof(uint32_t), hipHostMallocMapped) != hipSuccess) return LEB_ENOMEM;
+        void* d = nullptr;
+        if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) { (void)hipHostFree(h); return LEB_EDEVICE; }
+        g_ws.host_open = (uint32_t*)h;
+        g_ws.host_open_dev = (uint32_t*)d;
+    }
+    for (int q = 0; q < 2; ++q)
+        if (!g_ws.ev[q] && hipEventCreateWithFlags(&g_ws.ev[q], hipEventDisableTiming) != hipSuccess)
+            return LEB_EDEVICE;
     return LEB_OK;
 }
 
@@ -274,49 +319,50 @@ extern "C" int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int
     hipStream_t s = (hipStream_t)stream;
 
     std::lock_guard<std::mutex> lock(g_ws.mu);
-    double *cb, *rb, *xm[2], *xs[2];
+    double *cb, *rb, *xm1, *xs1;
     uint32_t* state;
     const size_t bx = (size_t)units * nx * sizeof(double), bn = (size_t)units * n * sizeof(double);
     if ((rc = ws_get(0, bx, (void**)&cb)) || (rc = ws_get(1, bx, (void**)&rb)) ||
-        (rc = ws_get(2, bn, (void**)&xm[0])) || (rc = ws_get(3, bn, (void**)&xs[0])) ||
-        (rc = ws_get(4, bn, (void**)&xm[1])) || (rc = ws_get(5, bn, (void**)&xs[1])) ||
-        (rc = ws_get(6, ((size_t)batch + 1) * sizeof(uint32_t), (void**)&state)))
+        (rc = ws_get(2, bn, (void**)&xm1)) || (rc = ws_get(3, bn, (void**)&xs1)) ||
+        (rc = ws_get(4, ((size_t)batch + 2) * sizeof(uint32_t), (void**)&state)) || (rc = ws_host_and_events()))
         return rc;
+    // iterates: buffer 0 = the caller's (mu, sigma), buffer 1 = workspace; sweep t reads C_{t-1}
+    // from buffer (t-1) & 1 and writes C_t to buffer t & 1
+    double* xm[2] = {mu, xm1};
+    double* xs[2] = {sigma, xs1};
     const int64_t cnt = units * n, per = (int64_t)N * n;
     auto ok = [](hipError_t e_) { return e_ == hipSuccess; };
-    hipLaunchKernelGGL(u32_fill_kernel, dim3(nblk(batch + 1)), dim3(256), 0, s, state, (int64_t)batch + 1, 0u);
-    // iterate C_t: the caller's tube (warm start) or the disturbance-only tube (LEB = 0, below the fixed point)
-    const double *im = mu, *is = sigma;
-    int nxt = 1;
-    if (!opt->warm) {
+    hipLaunchKernelGGL(fp_init_kernel, dim3(nblk(batch + 2)), dim3(256), 0, s, state, batch);
+    if (!opt->warm) {       // C_0: the disturbance-only tube (LEB = 0), below the fixed point
         hipLaunchKernelGGL(fill_kernel, dim3(nblk(units * nx)), dim3(256), 0, s, cb, units * nx, 0.0);
         hipLaunchKernelGGL(fill_kernel, dim3(nblk(units * nx)), dim3(256), 0, s, rb, units * nx, opt->pad);
-        if ((rc = launch_tube_map(batch, N, U, phi, e, cb, rb, xm[0], xs[0], s))) return rc;
-        im = xm[0]; is = xs[0];
+        if ((rc = launch_tube_map(batch, N, U, phi, e, cb, rb, mu, sigma, s))) return rc;
     }
-    int sweeps = 0;
-    uint32_t open = 0;
-    while (sweeps < opt->max_sweeps) {
-        // F(C_t): bound every unit of the tube, then the tube map; C_{t+1} = inflated F(C_t)
-        if ((rc = launch_pbh_chain(dyn, units, z, v, im, is, nullptr, nullptr, cb, rb, opt->pad, nullptr, s)))
-            return rc;
-        const TubeFP fp{im, is, state, opt->tol, opt->inflate_abs};
-        if ((rc = launch_tube(batch, N, U, phi, e, cb, rb, xm[nxt], xs[nxt], fp, s))) return rc;
-        ++sweeps;
-        hipLaunchKernelGGL(fp_commit_kernel, dim3(nblk(cnt)), dim3(256), 0, s, im, is, mu, sigma, state, per, cnt, 0);
-        hipLaunchKernelGGL(fp_state_kernel, dim3(1), dim3(256), 0, s, state, batch);
-        if (!ok(hipGetLastError()) ||
-            !ok(hipMemcpyAsync(&open, state + batch, sizeof(uint32_t), hipMemcpyDeviceToHost, s)) ||
-            !ok(hipStreamSynchronize(s)))
-            return LEB_EDEVICE;
-        im = xm[nxt]; is = xs[nxt];
-        nxt ^= 1;
-        if (open == 0) break;
+    volatile uint32_t* hopen = g_ws.host_open;
+    auto sweep = [&](int t) -> int {
+        const int a = (t - 1) & 1, w = t & 1;
+        int r = launch_pbh_chain(dyn, units, z, v, xm[a], xs[a], nullptr, nullptr, cb, rb, opt->pad, nullptr, s,
+                                 state + batch);
+        if (r) return r;
+        hopen[t % FP_SLOTS] = 0xffffffffu;
+        const TubeFP fp{xm[a], xs[a], state, g_ws.host_open_dev, opt->tol, opt->inflate_abs, t};
+        if ((r = launch_tube(batch, N, U, phi, e, cb, rb, xm[w], xs[w], fp, s))) return r;
+        return ok(hipEventRecord(g_ws.ev[t & 1], s)) ? LEB_OK : LEB_EDEVICE;
+    };
+    // one sweep stays in flight while the host reads the previous sweep's
+    // open count; a sweep enqueued after the last needed one exits at once
+    if ((rc = sweep(1))) return rc;
+    int t = 1;
+    for (;;) {
+        if (t < opt->max_sweeps && (rc = sweep(t + 1))) return rc;
+        if (!ok(hipEventSynchronize(g_ws.ev[t & 1]))) return LEB_EDEVICE;
+        const uint32_t open = hopen[t % FP_SLOTS];
+        if (open == 0xffffffffu) return LEB_EDEVICE;     // the sweep did not publish its count
+        if (open == 0 || t == opt->max_sweeps) break;
+        ++t;
     }
-    // sweep cap: the latest iterate of every trajectory not certified
-    if (open != 0)
-        hipLaunchKernelGGL(fp_commit_kernel, dim3(nblk(cnt)), dim3(256), 0, s, im, is, mu, sigma, state, per, cnt, 1);
+    hipLaunchKernelGGL(fp_final_kernel, dim3(nblk(cnt)), dim3(256), 0, s, xm1, xs1, mu, sigma, state, per, cnt, t);
     hipLaunchKernelGGL(cert_out_kernel, dim3(nblk(batch)), dim3(256), 0, s, state, certified, batch);
-    *sweeps_out = sweeps;
+    *sweeps_out = t;
     return ok(hipGetLastError()) ? LEB_OK : LEB_EDEVICE;
 }

@@ -1,0 +1,111 @@
+"""Learned warm start on the GPU: a chain surrogate trained by the library's
+own kernels on certified bounds, its prediction quality on held-out
+trajectories, and the learned fixed point: certified like the cold start
+(checked again with the oracle), never below the least fixed point, and
+needing fewer certified sweeps."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+@pytest.fixture(scope="module")
+def trained():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2607_01203_amd as leb
+    from paper_2607_01203_amd import learned
+    dev = torch.device("cuda:0")
+    tp = W.fixed_point_cfg(seed=100, batch=32, N=40)
+    b = tp.batch
+    dyn = leb.dynamics_like(b.dyn)
+    z, v = _t(b.z, dev), _t(b.v, dev)
+    print("case: learned -- training set", flush=True)
+    mu, sg, cert, _ = leb.fixed_point_solve(dyn, z, v, _t(tp.phi, dev), tp.e)
+    assert bool((cert == 1).all())
+    X, T = learned.chain_samples(dyn, z, v, mu.cpu().numpy(), sg.cpu().numpy(), draws=3, seed=1)
+    net = leb.Surrogate(learned.CHAIN_WIDTHS, learned.he_init(learned.CHAIN_WIDTHS, 0))
+    hist = learned.train(net, X, T, epochs=12, batch=1024, lr=2e-3)
+    print("train loss", hist[0], hist[-1], flush=True)
+    yield leb, net, dev, hist
+    net.close()
+
+
+def test_training_converges_and_generalises(trained):
+    from paper_2607_01203_amd import learned
+    leb, net, dev, hist = trained
+    assert hist[-1] < 0.1 * hist[0]
+    tp = W.fixed_point_cfg(seed=101, batch=8, N=40)
+    b = tp.batch
+    dyn = leb.dynamics_like(b.dyn)
+    z, v = _t(b.z, dev), _t(b.v, dev)
+    mu, sg, _, _ = leb.fixed_point_solve(dyn, z, v, _t(tp.phi, dev), tp.e)
+    X, T = learned.chain_samples(dyn, z, v, mu.cpu().numpy(), sg.cpu().numpy(), draws=1, seed=2)
+    ev = learned.evaluate(net, X, T)
+    print("held-out", ev)
+    # median error of the predicted bound within 25% (log space)
+    assert ev["abs_log_err_q50_q90_q99"][0] < 0.22
+
+
+def _oracle_fixed_point(orc, tp, idx):
+    from oracle import tube
+    b = tp.batch
+    d = orc.Dyn.like(b.dyn)
+    return tube.fixed_point(d, b.z[idx], b.v[idx], tp.phi, tp.e)
+
+
+def test_learned_fixed_point_certified_and_fewer_sweeps(trained, orc):
+    import torch
+    from oracle import tube
+    leb, net, dev, _ = trained
+    tp = W.fixed_point_cfg(seed=4, batch=64, N=40)
+    b = tp.batch
+    dyn = leb.dynamics_like(b.dyn)
+    z, v, phi = _t(b.z, dev), _t(b.v, dev), _t(tp.phi, dev)
+    print("case: learned fixed point 64x40x168", flush=True)
+    _, sg0, c0, sw0 = leb.fixed_point_solve(dyn, z, v, phi, tp.e)
+    mu1, sg1, c1, sw1 = leb.fixed_point_learned(dyn, z, v, phi, tp.e, net, sweeps=6, margin=2e-2)
+    torch.cuda.synchronize()
+    print("certified sweeps cold %d learned %d" % (sw0, sw1))
+    assert bool((c0 == 1).all()) and bool((c1 == 1).all())
+    assert sw1 < sw0
+    mu1, sg1, sg0 = mu1.cpu().numpy(), sg1.cpu().numpy(), sg0.cpu().numpy()
+    ratio = sg1[sg0 > 0] / sg0[sg0 > 0]
+    print("sigma learned / cold: median %.6f max %.6f" % (np.median(ratio), ratio.max()))
+    # contains the least fixed point of the oracle
+    idx = np.array([0, 33])
+    mo, so, _, _ = _oracle_fixed_point(orc, tp, idx)
+    assert (sg1[idx] >= so * (1 - 1e-12)).all()
+    # the certificate holds for the oracle too: F(C) inside C
+    d = orc.Dyn.like(b.dyn)
+    lo, hi, _ = orc.leb(d, b.z[idx], b.v[idx], sg1[idx], mu=mu1[idx])
+    c, r = tube.zono(lo, hi)
+    m2, s2 = tube.tube_map(tp.phi, tp.e, c, r)
+    assert tube.contains(mu1[idx], sg1[idx], m2, s2).all()
+
+
+def test_untrained_surrogate_still_certifies(trained, orc):
+    """A surrogate that predicts nonsense changes the start, not the
+    certificate: the certified iteration converges from any start."""
+    import torch
+    from paper_2607_01203_amd import learned
+    leb, _, dev, _ = trained
+    bad = leb.Surrogate(learned.CHAIN_WIDTHS, learned.he_init(learned.CHAIN_WIDTHS, 9))
+    tp = W.fixed_point_cfg(seed=50, batch=4, N=12, n_units=28)
+    b = tp.batch
+    dyn = leb.dynamics_like(b.dyn)
+    mu, sg, cert, sw = leb.fixed_point_learned(dyn, _t(b.z, dev), _t(b.v, dev), _t(tp.phi, dev), tp.e, bad,
+                                               sweeps=3, margin=0.0)
+    torch.cuda.synchronize()
+    bad.close()
+    assert bool((cert == 1).all())
+    mo, so, _, _ = _oracle_fixed_point(orc, tp, np.arange(4))
+    assert (sg.cpu().numpy() >= so * (1 - 1e-12)).all()

@@ -126,6 +126,33 @@ def test_fixed_point_warm_start_from_above(gpu, orc):
     assert (np.abs(mu2 - mo) <= 1e-2 * np.maximum(so, 1e-12)).all()
 
 
+def test_fixed_point_trajectories_certified_at_different_sweeps(gpu, orc):
+    """Half the batch starts from a certified tube (certified by the first
+    sweep, returned unchanged), half from a zero tube (certified several
+    sweeps later); 5 x 7 nodes = 35 columns per trajectory, so columns of
+    one trajectory straddle waves."""
+    import torch
+    import paper_2607_01203_amd as leb
+    tp = W.fixed_point_cfg(seed=49, batch=6, N=13, n_units=7)
+    print("case: mixed certification B=6 N=13 U=7", flush=True)
+    mu, sg, cert, sweeps = _solve(leb, tp, gpu)
+    assert (cert == 1).all()
+    b = tp.batch
+    dyn = leb.dynamics_like(b.dyn)
+    m_in = mu.copy()
+    s_in = sg * (1 + 1e-2)
+    m_in[1::2] = 0.0
+    s_in[1::2] = 0.0
+    mu2, sg2, cert2, sw2 = leb.fixed_point_solve(dyn, _t(b.z, gpu), _t(b.v, gpu), _t(tp.phi, gpu), tp.e,
+                                                 mu=_t(m_in, gpu), sigma=_t(s_in, gpu))
+    torch.cuda.synchronize()
+    mu2, sg2 = mu2.cpu().numpy(), sg2.cpu().numpy()
+    print("sweeps", sweeps, sw2)
+    assert (cert2.cpu().numpy() == 1).all() and sw2 >= 3
+    assert np.array_equal(sg2[0::2], s_in[0::2]) and np.array_equal(mu2[0::2], m_in[0::2])
+    _check_against_oracle(orc, tp, mu2, sg2, np.arange(1, 6, 2))
+
+
 def test_fixed_point_sweep_cap_not_certified(gpu):
     import paper_2607_01203_amd as leb
     tp = W.fixed_point_cfg(seed=47, batch=3, N=10, n_units=3)
