@@ -236,15 +236,17 @@ int leb_mlp_fwd_bf16(leb_surrogate s, int32_t batch, const float* x, float* y, v
 int leb_mlp_bwd_bf16(leb_surrogate s, int32_t batch, const float* x, const float* dy, float* grads, void* stream);
 
 /* One Adam step (Kingma and Ba, Algorithm 1; step >= 1 is the bias-
- * correction index) with the given device gradient; refreshes the BF16 copies. */
-int leb_adam_step(leb_surrogate s, const float* grads, int32_t step, float lr, float beta1, float beta2, float eps,
-                  void* stream);
+ * correction index) with the given device gradient; refreshes the BF16
+ * copies.  The moments and parameters are FP32; lr / (1 - beta1^step),
+ * 1 / sqrt(1 - beta2^step) and 1 - beta are formed in FP64. */
+int leb_adam_step(leb_surrogate s, const float* grads, int32_t step, double lr, double beta1, double beta2,
+                  double eps, void* stream);
 
 /* Forward, mean-squared error against t [batch][d_L], backward and Adam
  * (beta1 0.9, beta2 0.999, eps 1e-8) in one call.  loss (device, 1 float,
  * may be NULL) receives the mean-squared error before the update.  batch
  * must be a multiple of 32. */
-int leb_surrogate_train_step(leb_surrogate s, int32_t batch, const float* x, const float* t, int32_t step, float lr,
+int leb_surrogate_train_step(leb_surrogate s, int32_t batch, const float* x, const float* t, int32_t step, double lr,
                              float* loss, void* stream);
 
 /* Input and output widths of a surrogate (d_0 and d_L). */
@@ -261,22 +263,23 @@ int leb_surrogate_dims(leb_surrogate s, int32_t* d_in, int32_t* d_out);
  *   x[12..18] right spring: present (1/0), separation (L0 + px_{i+1} - px_i,
  *             pz_{i+1} - pz_i), Delta of px_{i+1}, pz_{i+1}  (zeros if absent)
  *   x[19..25] left spring: the same for node i-1 (separation from i-1 to i)
+ *   x[26..31] 0 (rows are 128 bytes)
  * Targets: log(max(hi, 1e-14)), log(max(-lo, 1e-14)) of the vx row, then of
  * the vz row.
  */
-#define LEB_CHAIN_FEATURES 26
+#define LEB_CHAIN_FEATURES 32
 #define LEB_CHAIN_OUTPUTS 4
 
-/* x [batch][N][n_units][26] (device FP32) from the nominal trajectory and
- * the tube (mu may be NULL). */
+/* x [batch][N][n_units][32] (device FP32, 16-byte aligned) from the
+ * nominal trajectory and the tube (mu may be NULL). */
 int leb_chain_features(const leb_dynamics* dyn, int32_t batch, int32_t N, const double* z, const double* v,
                        const double* mu, const double* sigma, float* x, void* stream);
-/* t [batch][N][n_units][4] (device FP32) from a bound r_lo, r_hi [batch][N][nx]. */
+/* t [batch][N][n_units][4] (device FP32, 16-byte aligned) from a bound r_lo, r_hi [batch][N][nx]. */
 int leb_chain_targets(const leb_dynamics* dyn, int32_t batch, int32_t N, const double* r_lo, const double* r_hi,
                       float* t, void* stream);
 
 typedef struct {
-    leb_surrogate net;     /* widths [26, ..., 4] */
+    leb_surrogate net;     /* widths [32, ..., 4] */
     int32_t sweeps;        /* tube sweeps with surrogate bounds before certification (>= 0) */
     double margin;         /* relative inflation of the surrogate tube's sigma (>= 0) */
 } leb_warm_start;
@@ -296,6 +299,46 @@ typedef struct {
 int leb_fixed_point_learned(const leb_dynamics* dyn, int32_t batch, int32_t N, const double* z, const double* v,
                             const double* phi, const double* e, const leb_fp_options* opt, const leb_warm_start* ws,
                             double* mu, double* sigma, uint32_t* certified, int32_t* sweeps_out, void* stream);
+
+/*
+ * Batching: many uneven problems (analytic chains of any node count, and
+ * ReLU-MLP dynamics), each one trajectory of its own horizon N, bounded by
+ * one graph launch.  leb_batch_create groups the problems by launch shape
+ * (analytic: node count and dynamics constants; MLP: network), picks each
+ * group's tile shape by timing candidates on the problems' own data (steps
+ * per workgroup for the path-based bound; boxes per chunk for the MLP
+ * bound), caches the choice in the text file tune_cache (key: GPU
+ * architecture and group shape; NULL: no cache), and captures all launches
+ * (analytic and MLP groups on two streams, joined) into a hipGraph.
+ * leb_batch_submit replays it on `stream`: every problem's r_lo, r_hi are
+ * recomputed from the current contents of its input buffers.
+ * The problem buffers are the caller's and must stay allocated, at the same
+ * addresses, for the life of the batch; they must hold valid data at
+ * creation (the autotuner runs the bounds).  Results are identical to
+ * leb_analytic_bound / leb_nn_bound on each problem.  Submits of one batch
+ * must not overlap.
+ */
+typedef enum { LEB_PROBLEM_ANALYTIC = 0, LEB_PROBLEM_NN = 1 } leb_problem_type;
+typedef struct {
+    int32_t type;                  /* leb_problem_type */
+    const leb_dynamics* dyn;       /* analytic: chain dynamics (copied at creation) */
+    leb_mlp net;                   /* NN: network (must outlive the batch) */
+    int32_t N;                     /* horizon: steps of this trajectory (>= 1) */
+    const double* z;               /* [N][nx] */
+    const double* v;               /* [N][nu] */
+    const double* mu;              /* [N][nx+nu] or NULL */
+    const double* sigma;           /* [N][nx+nu] */
+    double* r_lo;                  /* [N][nx] out */
+    double* r_hi;                  /* [N][nx] out */
+} leb_problem;
+typedef struct leb_batch_s* leb_batch;
+
+int leb_batch_create(const leb_problem* probs, int32_t count, const char* tune_cache, leb_batch* out);
+int leb_batch_submit(leb_batch b, void* stream);
+/* Synchronises the device, then frees the graph and the batch's buffers. */
+int leb_batch_destroy(leb_batch b);
+/* One line per group: kind, shape, problems, steps, chosen tile and whether it came from the cache. */
+int leb_batch_info(leb_batch b, char* buf, int32_t len);
 
 /* Human-readable text of a leb_status code (static storage). */
 const char* leb_strerror(int code);

@@ -37,8 +37,18 @@ class WarmStart(ctypes.Structure):
     _fields_ = [("net", ctypes.c_void_p), ("sweeps", ctypes.c_int32), ("margin", ctypes.c_double)]
 
 
-CHAIN_FEATURES = 26
+CHAIN_FEATURES = 32
 CHAIN_OUTPUTS = 4
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("type", ctypes.c_int32), ("dyn", ctypes.POINTER(Dynamics)), ("net", ctypes.c_void_p),
+                ("N", ctypes.c_int32), ("z", ctypes.c_void_p), ("v", ctypes.c_void_p), ("mu", ctypes.c_void_p),
+                ("sigma", ctypes.c_void_p), ("r_lo", ctypes.c_void_p), ("r_hi", ctypes.c_void_p)]
+
+
+PROBLEM_ANALYTIC = 0
+PROBLEM_NN = 1
 
 
 class FPOptions(ctypes.Structure):
@@ -101,9 +111,10 @@ def lib():
         L.leb_mlp_fwd_bf16.restype = ctypes.c_int
         L.leb_mlp_bwd_bf16.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp]
         L.leb_mlp_bwd_bf16.restype = ctypes.c_int
-        L.leb_adam_step.argtypes = [vp, vp, ctypes.c_int32, f32, f32, f32, f32, vp]
+        f64c = ctypes.c_double
+        L.leb_adam_step.argtypes = [vp, vp, ctypes.c_int32, f64c, f64c, f64c, f64c, vp]
         L.leb_adam_step.restype = ctypes.c_int
-        L.leb_surrogate_train_step.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_int32, f32, vp, vp]
+        L.leb_surrogate_train_step.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_int32, ctypes.c_double, vp, vp]
         L.leb_surrogate_train_step.restype = ctypes.c_int
         L.leb_surrogate_dims.argtypes = [vp, vp, vp]
         L.leb_surrogate_dims.restype = ctypes.c_int
@@ -116,6 +127,14 @@ def lib():
                                               ctypes.POINTER(WarmStart), vp, vp, vp, ctypes.POINTER(ctypes.c_int32),
                                               vp]
         L.leb_fixed_point_learned.restype = ctypes.c_int
+        L.leb_batch_create.argtypes = [vp, ctypes.c_int32, ctypes.c_char_p, ctypes.POINTER(ctypes.c_void_p)]
+        L.leb_batch_create.restype = ctypes.c_int
+        L.leb_batch_submit.argtypes = [vp, vp]
+        L.leb_batch_submit.restype = ctypes.c_int
+        L.leb_batch_destroy.argtypes = [vp]
+        L.leb_batch_destroy.restype = ctypes.c_int
+        L.leb_batch_info.argtypes = [vp, ctypes.c_char_p, ctypes.c_int32]
+        L.leb_batch_info.restype = ctypes.c_int
         L.leb_strerror.argtypes = [ctypes.c_int]
         L.leb_strerror.restype = ctypes.c_char_p
         L.leb_version.restype = ctypes.c_char_p
@@ -300,7 +319,7 @@ def fixed_point_learned(dyn: Dynamics, z, v, phi, e, net, sweeps=6, margin=5e-3,
 
 
 def chain_features(dyn: Dynamics, z, v, sigma, mu=None, stream=None):
-    """Surrogate inputs [B][N][n_units][26] (float32) of a chain tube."""
+    """Surrogate inputs [B][N][n_units][32] (float32) of a chain tube."""
     import torch
     B, N = int(z.shape[0]), int(z.shape[1])
     x = torch.empty((B, N, dyn.n_units, CHAIN_FEATURES), dtype=torch.float32, device=z.device)
@@ -436,6 +455,62 @@ class Surrogate:
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             lib().leb_surrogate_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Uneven problems bounded by one graph launch (see leb.h:
+    leb_batch_create).  problems: list of dicts with keys kind ("analytic"
+    with dyn, or "nn" with net: MLP), z [N][nx], v [N][nu], sigma [N][n],
+    optional mu, and r_lo, r_hi [N][nx] output tensors (float64 GPU,
+    contiguous; they must stay alive while the batch exists)."""
+
+    def __init__(self, problems, tune_cache=None):
+        import torch
+        f64 = torch.float64
+        arr = (Problem * len(problems))()
+        self._keep = []
+        for i, p in enumerate(problems):
+            q = arr[i]
+            if p["kind"] == "analytic":
+                q.type = PROBLEM_ANALYTIC
+                d = p["dyn"]
+                self._keep.append(d)
+                q.dyn = ctypes.pointer(d)
+            else:
+                q.type = PROBLEM_NN
+                q.net = p["net"].handle
+                self._keep.append(p["net"])
+            q.N = int(p["z"].shape[0])
+            q.z = _dev_ptr(p["z"], "z", f64)
+            q.v = _dev_ptr(p["v"], "v", f64)
+            q.mu = _dev_ptr(p.get("mu"), "mu", f64)
+            q.sigma = _dev_ptr(p["sigma"], "sigma", f64)
+            q.r_lo = _dev_ptr(p["r_lo"], "r_lo", f64)
+            q.r_hi = _dev_ptr(p["r_hi"], "r_hi", f64)
+            self._keep.append(p)
+        h = ctypes.c_void_p()
+        _check(lib().leb_batch_create(arr, len(problems), None if tune_cache is None else str(tune_cache).encode(),
+                                      ctypes.byref(h)))
+        self.handle = h
+
+    def submit(self, stream=None):
+        _check(lib().leb_batch_submit(self.handle, _stream(stream)))
+
+    def info(self):
+        buf = ctypes.create_string_buffer(4096)
+        _check(lib().leb_batch_info(self.handle, buf, 4096))
+        return buf.value.decode()
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().leb_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -7,6 +7,18 @@
 
 namespace leb {
 
+// one workgroup's share of a batched bound launch: up to T units of one problem
+struct PbhTile {
+    const double* z; const double* v; const double* mu; const double* sigma;
+    double* r_lo; double* r_hi; double* c_bar; double* rho_bar; uint32_t* flags;
+    int n;
+    int pad_;
+};
+constexpr int PBH_BLOCK_LANES = 256;
+// tiles: device array of n_tiles tiles, each of at most T units (T <= 256 / n_units)
+int launch_pbh_tiles(const leb_dynamics* dyn, const PbhTile* tiles, int n_tiles, int T, hipStream_t stream);
+size_t pbh_smem_bytes_T(int U, int T);
+
 int launch_pbh_chain(const leb_dynamics* dyn, int64_t units, const double* z, const double* v,
                      const double* mu, const double* sigma, double* r_lo, double* r_hi, double* c_bar,
                      double* rho_bar, double pad, uint32_t* flags, hipStream_t stream,
@@ -17,6 +29,14 @@ size_t pbh_smem_bytes(int U);
 size_t bwd_smem_bytes(int U);
 int launch_tube_map(int B, int N, int U, const double* phi, const double* e, const double* cbar,
                     const double* rbar, double* mu, double* sigma, hipStream_t s);
+
+// ReLU-MLP bound with caller-provided work buffers
+constexpr int NN_NBUF = 21;
+void nn_buffer_sizes(const leb_mlp_s* net, int CB, size_t sizes[NN_NBUF]);
+int nn_bound_run(const leb_mlp_s* net, int64_t units, const double* z, const double* v, const double* mu,
+                 const double* sigma, double* r_lo, double* r_hi, double* c_bar, double* rho_bar, double pad,
+                 uint32_t* flags, int CB, double* const* buf, hipStream_t st);
+void nn_dims(const leb_mlp_s* net, int* nx, int* nu, int* m);
 
 // argument checks shared by the entry points
 bool aligned8(const void* p);

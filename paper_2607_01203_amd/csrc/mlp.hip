@@ -70,9 +70,13 @@ struct FwdArgs {
 };
 
 // One workgroup (4 waves) carries 64 rows through every layer.  The
-// activation tile lives in LDS ([64][kp + 8] BF16, the pad skews banks);
-// weight fragments are read from global memory (L2-resident).  Output
-// tiles of 16x16 are dealt to the waves round-robin.
+// activation tile lives in LDS ([64][ldA] BF16, ldA = widest padded layer
+// + 8, the pad skews banks); weight fragments are read from global memory
+// (L2-resident).  Wave w owns the 16-column output tiles w, w+4, ..., up to
+// CT of them, over all four 16-row tiles.  The loads of a k-step are
+// issued together and unconditionally (a slot beyond the layer's width
+// reads a valid tile and is never stored), so no MFMA waits on a branch.
+template <int CT>
 __global__ void __launch_bounds__(256) mlp_fwd_kernel(FwdArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int ldA = A.ldA;
@@ -82,6 +86,7 @@ __global__ void __launch_bounds__(256) mlp_fwd_kernel(FwdArgs A) {
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int row0 = blockIdx.x * FWD_ROWS;
     const MlpLayout& G = A.G;
+    const int lr = lane & 15, lk = 8 * (lane >> 4);
     // stage a_0 = bf16(x), zero padded
     {
         const int d0 = G.w[0], k0 = G.kp[0];
@@ -102,46 +107,55 @@ __global__ void __launch_bounds__(256) mlp_fwd_kernel(FwdArgs A) {
         const bool last = (l == G.L - 1);
         const __bf16* W = A.Wt + G.woff[l];
         const float* bias = A.params + G.poff[l] + (int64_t)nout * G.w[l];
-        const int ntc = np / 16, ntiles = 4 * ntc;
-        f32x4 acc[16];
+        const int ntc = np / 16;
+        f32x4 acc[CT][4];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int s = 0; s < CT; ++s)
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) acc[s][rt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        const __bf16* wrow[CT];
+#pragma unroll
+        for (int s = 0; s < CT; ++s) {
+            const int ct = min(wave + 4 * s, ntc - 1);
+            wrow[s] = W + (int64_t)(ct * 16 + lr) * kp + lk;
+        }
         for (int k = 0; k < kp; k += 32) {
+            bf16x8 a[4], b[CT];
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int t = wave + 4 * q;
-                if (t < ntiles) {
-                    const int rt = t / ntc, ct = t - rt * ntc;
-                    const bf16x8 a = *reinterpret_cast<const bf16x8*>(cur + (rt * 16 + (lane & 15)) * ldA + k + 8 * (lane >> 4));
-                    const bf16x8 b = *reinterpret_cast<const bf16x8*>(W + (int64_t)(ct * 16 + (lane & 15)) * kp + k + 8 * (lane >> 4));
-                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[q], 0, 0, 0);
-                }
-            }
+            for (int s = 0; s < CT; ++s) b[s] = *reinterpret_cast<const bf16x8*>(wrow[s] + k);
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) a[rt] = *reinterpret_cast<const bf16x8*>(cur + (rt * 16 + lr) * ldA + k + lk);
+#pragma unroll
+            for (int s = 0; s < CT; ++s)
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt)
+                    acc[s][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rt], b[s], acc[s][rt], 0, 0, 0);
         }
         // epilogue
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int t = wave + 4 * q;
-            if (t < ntiles) {
-                const int rt = t / ntc, ct = t - rt * ntc;
-                const int c = ct * 16 + (lane & 15);
+        for (int s = 0; s < CT; ++s) {
+            const int ct = wave + 4 * s;
+            if (ct >= ntc) continue;
+            const int c = ct * 16 + lr;
+            const float bc = c < nout ? bias[c] : 0.0f;
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int r = rt * 16 + 4 * (lane >> 4) + i;
                     const int row = row0 + r;
-                    const float z = acc[q][i] + (c < nout ? bias[c] : 0.0f);
+                    const float z = acc[s][rt][i] + bc;
                     if (last) {
                         if (row < A.B && c < nout) A.y[(int64_t)row * nout + c] = z;
                     } else {
-                        const __bf16 a = (__bf16)(c < nout ? gelu_f(z) : 0.0f);
-                        nxt[r * ldA + c] = a;
+                        const __bf16 av = (__bf16)(c < nout ? gelu_f(z) : 0.0f);
+                        nxt[r * ldA + c] = av;
                         if (row < A.B) {
                             if (A.zsave) A.zsave[((int64_t)l * A.B + row) * MLP_MAX_WIDTH + c] = c < nout ? z : 0.0f;
-                            if (A.aT) A.aT[((int64_t)(l + 1) * MLP_MAX_WIDTH + c) * A.B + row] = a;
+                            if (A.aT) A.aT[((int64_t)(l + 1) * MLP_MAX_WIDTH + c) * A.B + row] = av;
                         }
                     }
                 }
-            }
         }
         __syncthreads();
         __bf16* t_ = cur; cur = nxt; nxt = t_;
@@ -271,16 +285,19 @@ __global__ void __launch_bounds__(256) colsum_kernel(const float* X, int64_t ldx
     if (part == 0 && c < n) db[c] = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
 }
 
-__global__ void adam_kernel(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
-                            float eps, float c1, float c2) {
+// Adam with the step-dependent factors formed on the host in FP64:
+// lr_t = lr / (1 - b1^t), isc2 = 1 / sqrt(1 - b2^t), ob = 1 - b (so that
+// 1 - 0.999 is not formed in FP32).
+__global__ void adam_kernel(float* p, const float* g, float* m, float* v, int64_t n, float b1, float ob1, float b2,
+                            float ob2, float lr_t, float isc2, float eps) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n) return;
     const float gq = g[q];
-    const float mq = b1 * m[q] + (1.0f - b1) * gq;
-    const float vq = b2 * v[q] + (1.0f - b2) * gq * gq;
+    const float mq = b1 * m[q] + ob1 * gq;
+    const float vq = b2 * v[q] + ob2 * gq * gq;
     m[q] = mq;
     v[q] = vq;
-    p[q] = p[q] - lr * (mq / c1) / (sqrtf(vq / c2) + eps);
+    p[q] = p[q] - lr_t * mq / (sqrtf(vq) * isc2 + eps);
 }
 
 // BF16 copies of the weights: W~ [np][kp] and W~^T [kp][np], zero padded
@@ -382,8 +399,10 @@ extern "C" int leb_surrogate_create(int32_t n_layers, const int32_t* widths, con
     s->ldA = widest + 8;
     const size_t smem = 2 * (size_t)FWD_ROWS * s->ldA * sizeof(__bf16);
     if (smem > 65536 &&
-        hipFuncSetAttribute((const void*)mlp_fwd_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) !=
-            hipSuccess) {
+        (hipFuncSetAttribute((const void*)mlp_fwd_kernel<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) !=
+             hipSuccess ||
+         hipFuncSetAttribute((const void*)mlp_fwd_kernel<4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) !=
+             hipSuccess)) {
         delete s;
         return LEB_EDEVICE;
     }
@@ -442,7 +461,10 @@ static int fwd_launch(leb_surrogate_s* s, int B, const float* x, float* y, bool 
     a.aT = save ? s->aT : nullptr;
     a.ldA = s->ldA;
     const size_t smem = 2 * (size_t)FWD_ROWS * s->ldA * sizeof(__bf16);
-    hipLaunchKernelGGL(mlp_fwd_kernel, dim3(nb(B, FWD_ROWS)), dim3(256), smem, st, a);
+    if (s->ldA - 8 <= 128)
+        hipLaunchKernelGGL(mlp_fwd_kernel<2>, dim3(nb(B, FWD_ROWS)), dim3(256), smem, st, a);
+    else
+        hipLaunchKernelGGL(mlp_fwd_kernel<4>, dim3(nb(B, FWD_ROWS)), dim3(256), smem, st, a);
     return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
 }
 
@@ -516,27 +538,28 @@ extern "C" int leb_mlp_bwd_bf16(leb_surrogate s, int32_t batch, const float* x, 
     return bwd_core(s, batch, grads, st);
 }
 
-static int adam_launch(leb_surrogate_s* s, const float* grads, int step, float lr, float b1, float b2, float eps,
+static int adam_launch(leb_surrogate_s* s, const float* grads, int step, double lr, double b1, double b2, double eps,
                        hipStream_t st) {
-    const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+    const double c1 = 1.0 - pow(b1, step), c2 = 1.0 - pow(b2, step);
     hipLaunchKernelGGL(adam_kernel, dim3(nb(s->G.nparams)), dim3(256), 0, st, s->params, grads, s->m, s->v,
-                       s->G.nparams, lr, b1, b2, eps, c1, c2);
+                       s->G.nparams, (float)b1, (float)(1.0 - b1), (float)b2, (float)(1.0 - b2), (float)(lr / c1),
+                       (float)(1.0 / sqrt(c2)), (float)eps);
     hipLaunchKernelGGL(mlp_convert_kernel, dim3(64, s->G.L), dim3(256), 0, st, s->G, s->params, s->Wt, s->WtT);
     return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
 }
 
-extern "C" int leb_adam_step(leb_surrogate s, const float* grads, int32_t step, float lr, float beta1, float beta2,
-                             float eps, void* stream) {
-    if (!s || !grads || step < 1 || !(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) ||
-        !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+extern "C" int leb_adam_step(leb_surrogate s, const float* grads, int32_t step, double lr, double beta1,
+                             double beta2, double eps, void* stream) {
+    if (!s || !grads || step < 1 || !(lr >= 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) ||
+        !(eps > 0.0))
         return LEB_EINVAL;
     std::lock_guard<std::mutex> lock(s->mu);
     return adam_launch(s, grads, step, lr, beta1, beta2, eps, (hipStream_t)stream);
 }
 
 extern "C" int leb_surrogate_train_step(leb_surrogate s, int32_t batch, const float* x, const float* t,
-                                        int32_t step, float lr, float* loss, void* stream) {
-    if (!s || !x || !t || batch <= 0 || (batch & 31) || step < 1 || !(lr >= 0.0f)) return LEB_EINVAL;
+                                        int32_t step, double lr, float* loss, void* stream) {
+    if (!s || !x || !t || batch <= 0 || (batch & 31) || step < 1 || !(lr >= 0.0)) return LEB_EINVAL;
     std::lock_guard<std::mutex> lock(s->mu);
     hipStream_t st = (hipStream_t)stream;
     int rc = sur_ws(s, batch);
@@ -549,5 +572,5 @@ extern "C" int leb_surrogate_train_step(leb_surrogate s, int32_t batch, const fl
     if (loss)
         hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, st, s->partial, nblocks, 1.0f / ((float)batch * d), loss);
     if ((rc = bwd_core(s, batch, s->grads, st))) return rc;
-    return adam_launch(s, s->grads, step, lr, 0.9f, 0.999f, 1e-8f, st);
+    return adam_launch(s, s->grads, step, lr, 0.9, 0.999, 1e-8, st);
 }

@@ -528,40 +528,38 @@ extern "C" int leb_mlp_destroy(leb_mlp net) {
     return LEB_OK;
 }
 
-extern "C" int leb_nn_bound(leb_mlp net, int32_t batch, int32_t N, const double* z, const double* v, const double* mu,
-                            const double* sigma, double* r_lo, double* r_hi, double* c_bar, double* rho_bar, double pad,
-                            uint32_t* flags, void* stream) {
-    if (!net) return LEB_EINVAL;
-    if (batch < 0 || N < 0 || !(pad >= 0.0) || !isfinite(pad)) return LEB_EINVAL;
-    if ((c_bar == nullptr) != (rho_bar == nullptr)) return LEB_EINVAL;
-    const int64_t units = (int64_t)batch * N;
-    if (units == 0) return LEB_OK;
-    if (!z || !sigma || !r_lo || !r_hi || (net->nu > 0 && !v) || (net->nx > 0 && !z)) return LEB_EINVAL;
-    const void* ptrs[] = {z, v, mu, sigma, r_lo, r_hi, c_bar, rho_bar};
-    for (const void* p : ptrs)
-        if (p && !aligned8(p)) return LEB_EINVAL;
-    hipStream_t st = (hipStream_t)stream;
+namespace leb {
+
+void nn_dims(const leb_mlp_s* net, int* nx, int* nu, int* m) {
+    *nx = net->nx;
+    *nu = net->nu;
+    *m = net->w[net->L];
+}
+
+// Sizes (bytes) of the 21 work buffers of the bound for chunks of CB boxes.
+void nn_buffer_sizes(const leb_mlp_s* net, int CB, size_t sizes[NN_NBUF]) {
     const int L = net->L, n0 = net->w[0], m = net->w[L];
-    std::lock_guard<std::mutex> lock(g_nnws.mu);
-    const int CB = (int)(units < NN_CHUNK ? units : NN_CHUNK);
     const size_t per = (size_t)CB * NN_MAXW * 8;
-    double *alpha, *c, *rho, *zhat, *lo, *hi, *g, *eg, *s, *t, *a, *D, *e, *amax, *bufA, *bufB, *beta, *eps, *beta2, *eps2;
-    double* fl_d;
-    int rc;
     const size_t lam = (size_t)CB * 3 * NN_MAXW * NN_MAXW * 8;
-    if ((rc = nn_ws(0, (size_t)CB * n0 * 8, &alpha)) || (rc = nn_ws(1, (size_t)CB * n0 * 8, &c)) ||
-        (rc = nn_ws(2, (size_t)CB * n0 * 8, &rho)) || (rc = nn_ws(3, per * (L - 1), &zhat)) ||
-        (rc = nn_ws(4, per * (L - 1), &lo)) || (rc = nn_ws(5, per * (L - 1), &hi)) ||
-        (rc = nn_ws(6, (size_t)CB * m * 8, &g)) || (rc = nn_ws(7, (size_t)CB * m * 8, &eg)) ||
-        (rc = nn_ws(8, per * (L - 1), &s)) || (rc = nn_ws(9, per * (L - 1), &t)) ||
-        (rc = nn_ws(10, per * (L - 1), &a)) || (rc = nn_ws(11, per * (L - 1), &D)) ||
-        (rc = nn_ws(12, per * (L - 1), &e)) || (rc = nn_ws(13, per * (L - 1), &amax)) ||
-        (rc = nn_ws(14, lam, &bufA)) || (rc = nn_ws(15, lam, &bufB)) ||
-        (rc = nn_ws(16, (size_t)CB * 3 * NN_MAXW * 8, &beta)) || (rc = nn_ws(17, (size_t)CB * 3 * NN_MAXW * 8, &eps)) ||
-        (rc = nn_ws(18, (size_t)CB * 3 * NN_MAXW * 8, &beta2)) || (rc = nn_ws(19, (size_t)CB * 3 * NN_MAXW * 8, &eps2)) ||
-        (rc = nn_ws(20, (size_t)CB * 8, &fl_d)))
-        return rc;
-    uint32_t* fl = (uint32_t*)fl_d;
+    const size_t v3 = (size_t)CB * 3 * NN_MAXW * 8;
+    const size_t tab[NN_NBUF] = {(size_t)CB * n0 * 8, (size_t)CB * n0 * 8, (size_t)CB * n0 * 8, per * (L - 1),
+                                 per * (L - 1), per * (L - 1), (size_t)CB * m * 8, (size_t)CB * m * 8,
+                                 per * (L - 1), per * (L - 1), per * (L - 1), per * (L - 1), per * (L - 1),
+                                 per * (L - 1), lam, lam, v3, v3, v3, v3, (size_t)CB * 8};
+    for (int q = 0; q < NN_NBUF; ++q) sizes[q] = tab[q];
+}
+
+// The bound of `units` boxes in chunks of CB, with caller-provided work
+// buffers (nn_buffer_sizes); only kernels are enqueued on st.
+int nn_bound_run(const leb_mlp_s* net, int64_t units, const double* z, const double* v, const double* mu,
+                 const double* sigma, double* r_lo, double* r_hi, double* c_bar, double* rho_bar, double pad,
+                 uint32_t* flags, int CB, double* const* buf, hipStream_t st) {
+    const int L = net->L, n0 = net->w[0], m = net->w[L];
+    int rc;
+    double *alpha = buf[0], *c = buf[1], *rho = buf[2], *zhat = buf[3], *lo = buf[4], *hi = buf[5], *g = buf[6],
+           *eg = buf[7], *s = buf[8], *t = buf[9], *a = buf[10], *D = buf[11], *e = buf[12], *amax = buf[13],
+           *bufA = buf[14], *bufB = buf[15], *beta = buf[16], *eps = buf[17];
+    uint32_t* fl = (uint32_t*)buf[20];
     auto layer = [&](double* base, int l) { return base + (size_t)l * CB * NN_MAXW; };   // hidden layer l+1
 
     for (int64_t u0 = 0; u0 < units; u0 += CB) {
@@ -639,4 +637,31 @@ extern "C" int leb_nn_bound(leb_mlp net, int32_t batch, int32_t N, const double*
         if (hipGetLastError() != hipSuccess) return LEB_EDEVICE;
     }
     return LEB_OK;
+}
+
+}  // namespace leb
+
+extern "C" int leb_nn_bound(leb_mlp net, int32_t batch, int32_t N, const double* z, const double* v, const double* mu,
+                            const double* sigma, double* r_lo, double* r_hi, double* c_bar, double* rho_bar, double pad,
+                            uint32_t* flags, void* stream) {
+    if (!net) return LEB_EINVAL;
+    if (batch < 0 || N < 0 || !(pad >= 0.0) || !isfinite(pad)) return LEB_EINVAL;
+    if ((c_bar == nullptr) != (rho_bar == nullptr)) return LEB_EINVAL;
+    const int64_t units = (int64_t)batch * N;
+    if (units == 0) return LEB_OK;
+    if (!z || !sigma || !r_lo || !r_hi || (net->nu > 0 && !v) || (net->nx > 0 && !z)) return LEB_EINVAL;
+    const void* ptrs[] = {z, v, mu, sigma, r_lo, r_hi, c_bar, rho_bar};
+    for (const void* p : ptrs)
+        if (p && !aligned8(p)) return LEB_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const int L = net->L, n0 = net->w[0], m = net->w[L];
+    std::lock_guard<std::mutex> lock(g_nnws.mu);
+    const int CB = (int)(units < NN_CHUNK ? units : NN_CHUNK);
+    size_t sizes[NN_NBUF];
+    nn_buffer_sizes(net, CB, sizes);
+    double* buf[NN_NBUF];
+    int rc;
+    for (int q = 0; q < NN_NBUF; ++q)
+        if ((rc = nn_ws(q, sizes[q], &buf[q]))) return rc;
+    return nn_bound_run(net, units, z, v, mu, sigma, r_lo, r_hi, c_bar, rho_bar, pad, flags, CB, buf, st);
 }

@@ -59,6 +59,7 @@ struct ChainArgs {
     const double* z; const double* v; const double* mu; const double* sigma;
     double* r_lo; double* r_hi; double* c_bar; double* rho_bar; uint32_t* flags;
     const uint32_t* open;   // optional: return at once when *open == 0 (fixed point already certified)
+    const PbhTile* tiles;   // optional: one tile (its own pointers, <= T units) per workgroup
     int64_t units;
     int U, T;
     double c;        // dt / m
@@ -80,9 +81,25 @@ __global__ void __launch_bounds__(PBH_BLOCK) pbh_chain_fwd(ChainArgs A) {
 
     if (A.open && *A.open == 0u) return;
     const int tid = threadIdx.x;
-    const int64_t u0 = (int64_t)blockIdx.x * T;
-    const int64_t left = A.units - u0;
-    const int nloc = left < T ? (int)left : T;
+    const double *Z, *V, *MU, *SG;
+    double *RLO, *RHI, *CB, *RB;
+    uint32_t* FL;
+    int nloc;
+    if (A.tiles) {
+        const PbhTile& tl = A.tiles[blockIdx.x];
+        Z = tl.z; V = tl.v; MU = tl.mu; SG = tl.sigma;
+        RLO = tl.r_lo; RHI = tl.r_hi; CB = tl.c_bar; RB = tl.rho_bar; FL = tl.flags;
+        nloc = tl.n;
+    } else {
+        const int64_t u0 = (int64_t)blockIdx.x * T;
+        const int64_t left = A.units - u0;
+        nloc = left < T ? (int)left : T;
+        Z = A.z + u0 * nx; V = A.v ? A.v + u0 * nu : nullptr; MU = A.mu ? A.mu + u0 * n : nullptr;
+        SG = A.sigma + u0 * n;
+        RLO = A.r_lo ? A.r_lo + u0 * nx : nullptr; RHI = A.r_hi ? A.r_hi + u0 * nx : nullptr;
+        CB = A.c_bar ? A.c_bar + u0 * nx : nullptr; RB = A.rho_bar ? A.rho_bar + u0 * nx : nullptr;
+        FL = A.flags ? A.flags + u0 : nullptr;
+    }
 
     for (int i = tid; i < T; i += PBH_BLOCK) s_flag[i] = 0u;
     __syncthreads();
@@ -90,20 +107,20 @@ __global__ void __launch_bounds__(PBH_BLOCK) pbh_chain_fwd(ChainArgs A) {
     // ---- stage inputs (coalesced)
     for (int idx = tid; idx < nloc * nx; idx += PBH_BLOCK) {
         int lt = idx / nx, c = idx - lt * nx;
-        double x = A.z[u0 * nx + idx];
+        double x = Z[idx];
         if (!isfinite(x)) atomicOr(&s_flag[lt], LEB_FLAG_BAD_INPUT);
         s_nom[lt * n + c] = x;
     }
     for (int idx = tid; idx < nloc * nu; idx += PBH_BLOCK) {
         int lt = idx / nu, c = idx - lt * nu;
-        double x = A.v[u0 * nu + idx];
+        double x = V[idx];
         if (!isfinite(x)) atomicOr(&s_flag[lt], LEB_FLAG_BAD_INPUT);
         s_nom[lt * n + nx + c] = x;
     }
     for (int idx = tid; idx < nloc * n; idx += PBH_BLOCK) {
         int lt = idx / n;
-        double sg = A.sigma[u0 * n + idx];
-        double m = A.mu ? A.mu[u0 * n + idx] : 0.0;
+        double sg = SG[idx];
+        double m = MU ? MU[idx] : 0.0;
         uint32_t f = 0;
         if (!isfinite(sg) || !isfinite(m) || !(sg >= 0.0)) f |= LEB_FLAG_BAD_INPUT;
         if (fabs(m) > sg) f |= LEB_FLAG_HULL_EXTENDED;
@@ -208,26 +225,26 @@ __global__ void __launch_bounds__(PBH_BLOCK) pbh_chain_fwd(ChainArgs A) {
         if (f & LEB_FLAG_BAD_INPUT) { lo = -INFINITY; hi = INFINITY; }
         else if (rc == 3) { lo = s_row[t * U + node].xlo; hi = s_row[t * U + node].xhi; }
         else if (rc == 4) { lo = s_row[t * U + node].zlo; hi = s_row[t * U + node].zhi; }
-        const int64_t o = u0 * nx + idx;
-        if (A.r_lo) {
-            A.r_lo[o] = lo;
-            A.r_hi[o] = hi;
+        const int o = idx;
+        if (RLO) {
+            RLO[o] = lo;
+            RHI[o] = hi;
         }
-        if (A.c_bar) {
+        if (CB) {
             double cb, rb;
             if (isfinite(lo) && isfinite(hi)) {
                 cb = 0.5 * (lo + hi);
                 rb = fmax(hi - cb, cb - lo);
                 rb = rb + fabs(rb) * 0x1p-50 + A.pad;
             } else { cb = 0.0; rb = INFINITY; }
-            A.c_bar[o] = cb;
-            A.rho_bar[o] = rb;
+            CB[o] = cb;
+            RB[o] = rb;
         }
     }
-    if (A.flags)
+    if (FL)
         for (int t = tid; t < nloc; t += PBH_BLOCK) {
             uint32_t f = s_flag[t];
-            A.flags[u0 + t] = (f & LEB_FLAG_BAD_INPUT) ? (f & ~LEB_FLAG_UNBOUNDED) : f;
+            FL[t] = (f & LEB_FLAG_BAD_INPUT) ? (f & ~LEB_FLAG_UNBOUNDED) : f;
         }
 }
 
@@ -243,8 +260,10 @@ __global__ void fill_zero_kernel(double* a, double* b, double* c, double* d, dou
         for (int64_t k = idx; k < nflags; k += stride) flags[k] = 0u;
 }
 
-size_t pbh_smem_bytes(int U) {
-    int T = PBH_BLOCK / U, n = 8 * U;
+size_t pbh_smem_bytes(int U) { return pbh_smem_bytes_T(U, PBH_BLOCK / U); }
+
+size_t pbh_smem_bytes_T(int U, int T) {
+    const int n = 8 * U;
     return (size_t)T * n * sizeof(double) + (size_t)T * n * sizeof(IV<float>) + (size_t)T * U * sizeof(SpringOut)
          + (size_t)T * U * sizeof(RowOut) + (size_t)T * sizeof(uint32_t) + 16;
 }
@@ -256,6 +275,7 @@ int launch_pbh_chain(const leb_dynamics* dyn, int64_t units, const double* z, co
     a.z = z; a.v = v; a.mu = mu; a.sigma = sigma;
     a.r_lo = r_lo; a.r_hi = r_hi; a.c_bar = c_bar; a.rho_bar = rho_bar; a.flags = flags;
     a.open = open;
+    a.tiles = nullptr;
     a.units = units;
     a.U = dyn->n_units;
     a.T = PBH_BLOCK / a.U;
@@ -267,6 +287,21 @@ int launch_pbh_chain(const leb_dynamics* dyn, int64_t units, const double* z, co
     if (blocks > 0x7fffffff) return LEB_EINVAL;
     size_t smem = pbh_smem_bytes(a.U);
     hipLaunchKernelGGL(pbh_chain_fwd, dim3((unsigned)blocks), dim3(PBH_BLOCK), smem, stream, a);
+    return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
+}
+
+int launch_pbh_tiles(const leb_dynamics* dyn, const PbhTile* tiles, int n_tiles, int T, hipStream_t stream) {
+    if (n_tiles == 0) return LEB_OK;
+    ChainArgs a = {};
+    a.tiles = tiles;
+    a.U = dyn->n_units;
+    if (T < 1 || T * a.U > PBH_BLOCK) return LEB_EINVAL;
+    a.T = T;
+    a.c = dyn->dt / dyn->m;
+    a.kL = dyn->k_spring * dyn->rest_len;
+    a.L0 = dyn->rest_len;
+    a.pad = 0.0;
+    hipLaunchKernelGGL(pbh_chain_fwd, dim3((unsigned)n_tiles), dim3(PBH_BLOCK), pbh_smem_bytes_T(a.U, T), stream, a);
     return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
 }
 

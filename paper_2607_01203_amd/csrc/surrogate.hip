@@ -30,21 +30,20 @@ namespace leb {
 constexpr float DSCALE = 20.0f;      // 1 / 0.05: displacements of the tube scale to O(1)
 constexpr float LOG_FLOOR = 1e-14f;
 
-// one thread per (unit, node)
+// one thread per (unit, node); rows of 32 floats written as 8 float4
 __global__ void chain_features_kernel(const double* z, const double* v, const double* mu, const double* sigma,
-                                      int64_t units, int U, double L0, float* X) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= units * U) return;
-    const int64_t u = q / U;
-    const int i = (int)(q - u * U);
+                                      int nodes, int U, double L0, float* X) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nodes) return;
+    const int u = q / U, i = q - u * U;
     const int nx = 6 * U, nu = 2 * U, n = nx + nu;
-    const double* zn = z + u * nx;
-    const double* vn = v + u * nu;
-    const double* m = mu ? mu + u * n : nullptr;
-    const double* s = sigma + u * n;
+    const double* zn = z + (int64_t)u * nx;
+    const double* vn = v + (int64_t)u * nu;
+    const double* m = mu ? mu + (int64_t)u * n : nullptr;
+    const double* s = sigma + (int64_t)u * n;
     auto dlo = [&](int c) { return (float)(fmin((m ? m[c] : 0.0) - s[c], 0.0) * DSCALE); };
     auto dhi = [&](int c) { return (float)(fmax((m ? m[c] : 0.0) + s[c], 0.0) * DSCALE); };
-    float* f = X + q * LEB_CHAIN_FEATURES;
+    float f[LEB_CHAIN_FEATURES];
     const int th = 6 * i + 2, px = 6 * i, pz = 6 * i + 1, u1 = nx + 2 * i, u2 = u1 + 1;
     f[0] = (float)zn[th];
     f[1] = (float)((vn[2 * i] + vn[2 * i + 1]) * 0.1);
@@ -56,33 +55,36 @@ __global__ void chain_features_kernel(const double* z, const double* v, const do
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
         const int j = side == 0 ? i + 1 : i - 1;      // right, then left neighbour
-        float* g = f + 12 + 7 * side;
+        const int o = 12 + 7 * side;
         if (j >= 0 && j < U) {
             const int a = side == 0 ? i : j, b = side == 0 ? j : i;   // spring from node a to node b = a + 1
-            g[0] = 1.0f;
-            g[1] = (float)(L0 + zn[6 * b] - zn[6 * a]);
-            g[2] = (float)(zn[6 * b + 1] - zn[6 * a + 1]);
-            g[3] = dlo(6 * j); g[4] = dhi(6 * j);
-            g[5] = dlo(6 * j + 1); g[6] = dhi(6 * j + 1);
+            f[o] = 1.0f;
+            f[o + 1] = (float)(L0 + zn[6 * b] - zn[6 * a]);
+            f[o + 2] = (float)(zn[6 * b + 1] - zn[6 * a + 1]);
+            f[o + 3] = dlo(6 * j); f[o + 4] = dhi(6 * j);
+            f[o + 5] = dlo(6 * j + 1); f[o + 6] = dhi(6 * j + 1);
         } else {
 #pragma unroll
-            for (int t = 0; t < 7; ++t) g[t] = 0.0f;
+            for (int t = 0; t < 7; ++t) f[o + t] = 0.0f;
         }
     }
+#pragma unroll
+    for (int t = 26; t < LEB_CHAIN_FEATURES; ++t) f[t] = 0.0f;
+    float4* out = reinterpret_cast<float4*>(X + (int64_t)q * LEB_CHAIN_FEATURES);
+#pragma unroll
+    for (int t = 0; t < LEB_CHAIN_FEATURES / 4; ++t) out[t] = make_float4(f[4 * t], f[4 * t + 1], f[4 * t + 2], f[4 * t + 3]);
 }
 
 // targets from a bound: one thread per (unit, node)
-__global__ void chain_targets_kernel(const double* r_lo, const double* r_hi, int64_t units, int U, float* T) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= units * U) return;
-    const int64_t u = q / U;
-    const int i = (int)(q - u * U);
-    const int64_t o = u * 6 * U + 6 * i;
-    float* t = T + q * LEB_CHAIN_OUTPUTS;
-    t[0] = logf(fmaxf((float)r_hi[o + 3], LOG_FLOOR));
-    t[1] = logf(fmaxf((float)-r_lo[o + 3], LOG_FLOOR));
-    t[2] = logf(fmaxf((float)r_hi[o + 4], LOG_FLOOR));
-    t[3] = logf(fmaxf((float)-r_lo[o + 4], LOG_FLOOR));
+__global__ void chain_targets_kernel(const double* r_lo, const double* r_hi, int nodes, int U, float* T) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nodes) return;
+    const int u = q / U, i = q - u * U;
+    const int64_t o = (int64_t)u * 6 * U + 6 * i;
+    reinterpret_cast<float4*>(T)[q] = make_float4(logf(fmaxf((float)r_hi[o + 3], LOG_FLOOR)),
+                                                  logf(fmaxf((float)-r_lo[o + 3], LOG_FLOOR)),
+                                                  logf(fmaxf((float)r_hi[o + 4], LOG_FLOOR)),
+                                                  logf(fmaxf((float)-r_lo[o + 4], LOG_FLOOR)));
 }
 
 // predicted bounds -> residual zonotope (c_bar, rho_bar): one thread per (unit, row)
@@ -160,9 +162,10 @@ extern "C" int leb_chain_features(const leb_dynamics* dyn, int32_t batch, int32_
     if (dyn->kind != LEB_DYN_PQUAD_CHAIN || batch < 0 || N < 0) return LEB_EINVAL;
     const int64_t units = (int64_t)batch * N;
     if (units == 0) return LEB_OK;
-    if (!z || !v || !sigma || !x) return LEB_EINVAL;
+    if (!z || !v || !sigma || !x || ((uintptr_t)x & 15)) return LEB_EINVAL;
+    if (units * dyn->n_units > 0x7fffffff) return LEB_EINVAL;
     hipLaunchKernelGGL(chain_features_kernel, dim3(nbk(units * dyn->n_units)), dim3(256), 0, (hipStream_t)stream, z, v,
-                       mu, sigma, units, dyn->n_units, dyn->rest_len, x);
+                       mu, sigma, (int)(units * dyn->n_units), dyn->n_units, dyn->rest_len, x);
     return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
 }
 
@@ -173,9 +176,10 @@ extern "C" int leb_chain_targets(const leb_dynamics* dyn, int32_t batch, int32_t
     if (dyn->kind != LEB_DYN_PQUAD_CHAIN || batch < 0 || N < 0) return LEB_EINVAL;
     const int64_t units = (int64_t)batch * N;
     if (units == 0) return LEB_OK;
-    if (!r_lo || !r_hi || !t) return LEB_EINVAL;
+    if (!r_lo || !r_hi || !t || ((uintptr_t)t & 15)) return LEB_EINVAL;
+    if (units * dyn->n_units > 0x7fffffff) return LEB_EINVAL;
     hipLaunchKernelGGL(chain_targets_kernel, dim3(nbk(units * dyn->n_units)), dim3(256), 0, (hipStream_t)stream, r_lo,
-                       r_hi, units, dyn->n_units, t);
+                       r_hi, (int)(units * dyn->n_units), dyn->n_units, t);
     return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
 }
 
@@ -208,8 +212,8 @@ extern "C" int leb_fixed_point_learned(const leb_dynamics* dyn, int32_t batch, i
         if ((rc = launch_tube_map(batch, N, U, phi, e, g_sw.cb, g_sw.rb, mu, sigma, s))) return rc;
         // surrogate sweeps: C <- T(surrogate bound of C)
         for (int t = 0; t < ws->sweeps; ++t) {
-            hipLaunchKernelGGL(chain_features_kernel, dim3(nbk(nodes)), dim3(256), 0, s, z, v, mu, sigma, units, U,
-                               dyn->rest_len, g_sw.X);
+            hipLaunchKernelGGL(chain_features_kernel, dim3(nbk(nodes)), dim3(256), 0, s, z, v, mu, sigma, (int)nodes,
+                               U, dyn->rest_len, g_sw.X);
             if ((rc = leb_mlp_fwd_bf16(ws->net, (int32_t)nodes, g_sw.X, g_sw.Y, stream))) return rc;
             hipLaunchKernelGGL(chain_decode_kernel, dim3(nbk(units * nx)), dim3(256), 0, s, g_sw.Y, units, U,
                                opt->pad, g_sw.cb, g_sw.rb);

@@ -43,10 +43,8 @@ constexpr int FP_SLOTS = 4096;            // host-visible open counts, one per s
 struct TubeFP {
     const double* mu_in;  // C_{t-1}: the tube whose bounds produced (c_bar, rho_bar)
     const double* sg_in;
-    uint32_t* state;      // [B] state words, [B] open count, [B+1] finished-workgroup counter
-    uint32_t* host_open;  // host-mapped [FP_SLOTS]: open count after each sweep
+    uint32_t* state;      // [B] state words, [B] open count
     double tol, abs_;     // C_t = (mu_F, sigma_F (1 + tol) + abs_)
-    int sweep;            // t (1-based)
 };
 
 struct TubeArgs {
@@ -55,77 +53,94 @@ struct TubeArgs {
     double* mu; double* sigma;                // [B][N][n] out
     double wid;        // relative rounding allowance of the tube sums
     int B, N, U;
-    int groups;        // k-groups per column group (4 k-pairs each)
-    int total;         // workgroups in the grid
 };
 
-// One wave per (64 columns, k-pair).  A column is one (trajectory, node);
-// the wave computes the 8 tube rows of its node at steps k = p and
-// k = N-1-p, so every wave performs N-1 block products.  Phi is indexed by
-// the wave-uniform lag only, so its 48 entries come through scalar loads;
-// the residual centres and radii come through vector loads shared in L2 by
-// the waves of the same columns (the workgroup order is remapped so those
-// land on one XCD).
+typedef double d4 __attribute__((ext_vector_type(4)));
+constexpr int TM_RT = 5;        // 16-row tiles per wave and row group
+
+// The tube map as a contraction on FP64 MFMA (v_mfma_f64_16x16x4f64):
+//   [mu; sigma][row (k, r)][col] = sum_{kk = (j, q)} T[row][kk] [c; w][kk][col],
+//   T = Phi_{k-j-1}[r][q] for j < k (|Phi| for sigma), 0 otherwise,
+//   c = c_bar_j[q], w = e_q + rho_bar_j[q] + |c| wid,
+// with a column per (trajectory, node).  A workgroup owns 16 columns; wave w
+// owns the row tiles w, w+4, ... (16 rows = 2 steps each) of its row group
+// and skips the K range above the causal diagonal of each tile.  A
+// fragments come from Phi in LDS, B fragments from the residual zonotopes
+// (shared in L1 by the four waves).  Lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; element i of its accumulator is D[4i + l/16][l%16].
 //
 // Fixed-point form: frozen trajectories are not written; containment
-// failures are or-ed into the state words, and the last workgroup to
-// finish turns them into the next state (certified at this sweep, or open)
-// and publishes the open count to the device word and to host memory.
+// failures are or-ed into the state words (fp_state_kernel folds them).
 __global__ void __launch_bounds__(256) tube_map_kernel(const double* __restrict__ phi, TubeArgs A, TubeFP P) {
+    extern __shared__ double sphi[];          // [(N-1) * 48] Phi, then e[6]
+    __shared__ uint32_t sbad[16];
     const bool fp = P.state != nullptr;
     if (fp && P.state[A.B] == 0u) return;     // every trajectory certified by an earlier sweep
-    // XCD-aware order: workgroup ids are dealt round-robin over 8 XCDs;
-    // give each XCD a contiguous range of (column group, k-group) tiles.
-    const int id = blockIdx.x, x = id & 7, pos = id >> 3;
-    const int q8 = A.total >> 3, r8 = A.total & 7;
-    const int nid = x * q8 + min(x, r8) + pos;
-    const int cg = nid / A.groups, g = nid - cg * A.groups;
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int lane = threadIdx.x & 63;
-    const int npairs = (A.N + 1) >> 1;
-    const int p = g * 4 + wave;
-    const int cols = A.B * A.U;
-    const int col = cg * 64 + lane;
-    const bool valid = col < cols;
-    const int cc = valid ? col : cols - 1;
-    const int b = cc / A.U, i = cc - b * A.U;
-    const int nx = 6 * A.U, n = 8 * A.U;
-    const double* cb = A.cbar + ((int64_t)b * A.N) * nx + 6 * i;
-    const double* rb = A.rbar + ((int64_t)b * A.N) * nx + 6 * i;
-    const bool frozen = fp && (P.state[b] & FP_CERT);
-    // first lane of this wave holding trajectory b (columns of one trajectory are contiguous)
-    const int first = max(0, b * A.U - cg * 64);
-    for (int half = 0; half < 2 && p < npairs; ++half) {
-        const int k = half ? A.N - 1 - p : p;
-        if (half && k == p) break;
-        double m[8], s[8];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int N = A.N, U = A.U, nx = 6 * U, n = 8 * U;
+    const int nphi = (N - 1) * 48;
+    for (int idx = tid; idx < nphi; idx += 256) sphi[idx] = phi[idx];
+    if (tid < 6) sphi[nphi + tid] = A.e[tid];
+    if (tid < 16) sbad[tid] = 0u;
+    __syncthreads();
+    const double* se = sphi + nphi;
+    const int cols = A.B * U;
+    const int c0 = blockIdx.x * 16;
+    const int col = c0 + (lane & 15);
+    const bool cvalid = col < cols;
+    const int cc = cvalid ? col : cols - 1;
+    const int b = cc / U, node = cc - b * U;
+    const int bfirst = c0 / U;
+    const double* cbp = A.cbar + (int64_t)b * N * nx + 6 * node;
+    const double* rbp = A.rbar + (int64_t)b * N * nx + 6 * node;
+    const int nrt = (N + 1) >> 1;
+    const int kfull = 6 * (N - 1);
+    int kmax[TM_RT];
+    int kw = 0;
 #pragma unroll
-        for (int r = 0; r < 8; ++r) { m[r] = 0.0; s[r] = 0.0; }
-#pragma unroll 2
-        for (int j = 0; j < k; ++j) {
-            const double* Pk = phi + (int64_t)(k - j - 1) * 48;
-            double c[6], w[6];
+    for (int s = 0; s < TM_RT; ++s) {
+        const int rt = wave + 4 * (blockIdx.y * TM_RT + s);
+        kmax[s] = rt < nrt ? 6 * min(N - 1, 2 * rt + 1) : 0;
+        kw = max(kw, kmax[s]);
+    }
+    d4 am[TM_RT], as[TM_RT];
 #pragma unroll
-            for (int q = 0; q < 6; ++q) {
-                c[q] = cb[(int64_t)j * nx + q];
-                // residual radius plus the allowance for the rounding of the centre sum
-                w[q] = A.e[q] + rb[(int64_t)j * nx + q] + fabs(c[q]) * A.wid;
-            }
-#pragma unroll
-            for (int r = 0; r < 8; ++r)
-#pragma unroll
-                for (int q = 0; q < 6; ++q) {
-                    const double ph = Pk[r * 6 + q];
-                    m[r] = __builtin_fma(ph, c[q], m[r]);
-                    s[r] = __builtin_fma(fabs(ph), w[q], s[r]);
-                }
+    for (int s = 0; s < TM_RT; ++s) { am[s] = d4{0.0, 0.0, 0.0, 0.0}; as[s] = d4{0.0, 0.0, 0.0, 0.0}; }
+    const int lr = lane & 15, lq = lane >> 4;
+    for (int k0 = 0; k0 < kw; k0 += 4) {
+        const int kk = k0 + lq;
+        const int j = kk / 6, q = kk - 6 * j;
+        double c = 0.0, w = 0.0;
+        if (kk < kfull && cvalid) {
+            c = cbp[(int64_t)j * nx + q];
+            // residual radius plus the allowance for the rounding of the centre sum
+            w = se[q] + rbp[(int64_t)j * nx + q] + fabs(c) * A.wid;
         }
-        bool bad = false;
-        const int64_t row0 = ((int64_t)b * A.N + k) * n;
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            const int64_t o = row0 + (r < 6 ? 6 * i + r : nx + 2 * i + (r - 6));
-            const double sF = s[r] + s[r] * A.wid, mF = m[r];
+        for (int s = 0; s < TM_RT; ++s) {
+            if (k0 >= kmax[s]) continue;       // wave-uniform
+            const int rt = wave + 4 * (blockIdx.y * TM_RT + s);
+            const int r = 16 * rt + lr, k = r >> 3, rr = r & 7;
+            const int lag = k - j - 1;
+            const double a = (lag >= 0 && lag < N - 1 && kk < kfull) ? sphi[lag * 48 + rr * 6 + q] : 0.0;
+            am[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, c, am[s], 0, 0, 0);
+            as[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(fabs(a), w, as[s], 0, 0, 0);
+        }
+    }
+    const bool frozen = fp && (P.state[b] & FP_CERT);
+    bool bad = false;
+#pragma unroll
+    for (int s = 0; s < TM_RT; ++s) {
+        const int rt = wave + 4 * (blockIdx.y * TM_RT + s);
+        if (rt >= nrt) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 16 * rt + 4 * i + lq, k = r >> 3, rr = r & 7;
+            if (k >= N || !cvalid) continue;
+            const int64_t o = ((int64_t)b * N + k) * n + (rr < 6 ? 6 * node + rr : nx + 2 * node + (rr - 6));
+            // sums of nonnegative terms, rounded upward; 2^-1000 covers any flushed subnormal part
+            const double sF = as[s][i] + as[s][i] * A.wid + 0x1p-1000, mF = am[s][i];
             double so = sF;
             if (fp) {
                 const double mi = P.mu_in[o], si = P.sg_in[o];
@@ -133,44 +148,38 @@ __global__ void __launch_bounds__(256) tube_map_kernel(const double* __restrict_
                 bad |= !((fabs(mF - mi) + sF) * (1.0 + 0x1p-50) <= si);
                 so = sF + sF * P.tol + P.abs_;
             }
-            if (valid && !frozen) { A.mu[o] = mF; A.sigma[o] = so; }
-        }
-        if (fp) {
-            bad = bad && valid && !frozen;
-            const uint64_t mask = __ballot(bad);
-            const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-            const uint64_t same = ~0ull << first;
-            if (bad && !(mask & below & same)) atomicOr(&P.state[b], FP_OPEN);
+            if (!frozen) { A.mu[o] = mF; A.sigma[o] = so; }
         }
     }
     if (!fp) return;
-    // last workgroup to finish: fold this sweep's containment into the state words
-    __shared__ uint32_t last;
-    __threadfence();        // this thread's state updates are visible device-wide
+    if (bad && !frozen) sbad[b - bfirst] = 1u;
     __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(&P.state[A.B + 1], 1u) == (uint32_t)(A.total - 1);
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
+    if (tid < 16 && sbad[tid] && bfirst + tid < A.B) atomicOr(&P.state[bfirst + tid], FP_OPEN);
+}
+
+// After the tube map of sweep t: fold this sweep's containment into the
+// state words (certified at t, or open) and publish the open count to the
+// device word and to host memory.  One workgroup.
+__global__ void __launch_bounds__(256) fp_state_kernel(uint32_t* state, int B, uint32_t* host_open, int sweep) {
+    if (state[B] == 0u) return;       // nothing open: this sweep was not needed
     __shared__ uint32_t cnt;
     if (threadIdx.x == 0) cnt = 0;
     __syncthreads();
     uint32_t open = 0;
-    for (int t = threadIdx.x; t < A.B; t += 256) {
-        const uint32_t st = __hip_atomic_load(&P.state[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int t = threadIdx.x; t < B; t += 256) {
+        const uint32_t st = state[t];
         uint32_t ns = st;
         if (!(st & FP_CERT)) {
-            ns = (st & FP_OPEN) ? 0u : (FP_CERT | ((uint32_t)P.sweep << 1));
-            __hip_atomic_store(&P.state[t], ns, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ns = (st & FP_OPEN) ? 0u : (FP_CERT | ((uint32_t)sweep << 1));
+            state[t] = ns;
         }
         open += (ns & FP_CERT) ? 0u : 1u;
     }
     atomicAdd(&cnt, open);
     __syncthreads();
     if (threadIdx.x == 0) {
-        __hip_atomic_store(&P.state[A.B], cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&P.state[A.B + 1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&P.host_open[P.sweep % FP_SLOTS], cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        state[B] = cnt;
+        __hip_atomic_store(&host_open[sweep % FP_SLOTS], cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
@@ -191,7 +200,6 @@ __global__ void fp_init_kernel(uint32_t* state, int B) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < B) state[t] = 0u;
     if (t == B) state[B] = (uint32_t)B;     // open count
-    if (t == B + 1) state[B + 1] = 0u;      // finished-workgroup counter
 }
 
 __global__ void cert_out_kernel(const uint32_t* state, uint32_t* out, int B) {
@@ -213,24 +221,25 @@ static int launch_tube(int B, int N, int U, const double* phi, const double* e, 
     for (int q = 0; q < 6; ++q) a.e[q] = e[q];
     a.mu = mu; a.sigma = sigma; a.B = B; a.N = N; a.U = U;
     // A sum of m rounded products (and the 3 operations forming a weight)
-    // errs by at most gamma_{m+3} ~ (m+3) 2^-53 relative; twice that covers
-    // both the sigma sums and, through |c_bar| wid in the weights, the
-    // rounding of the centre sums.
+    // errs by at most gamma_{m+3} ~ (m+3) 2^-53 relative, in any order of
+    // accumulation; twice that covers both the sigma sums and, through
+    // |c_bar| wid in the weights, the rounding of the centre sums.
     a.wid = fmax(0x1p-44, (6.0 * (N > 0 ? N - 1 : 0) + 4.0) * 0x1p-52);
     const int64_t cols = (int64_t)B * U;
     if (cols == 0 || N == 0) return LEB_OK;
-    const int64_t ncg = (cols + 63) / 64;
-    a.groups = ((N + 1) / 2 + 3) / 4;
-    const int64_t total = ncg * a.groups;
-    if (total > 0x7fffffff) return LEB_EINVAL;
-    a.total = (int)total;
-    hipLaunchKernelGGL(tube_map_kernel, dim3((unsigned)total), dim3(256), 0, s, phi, a, fp);
+    const int64_t gx = (cols + 15) / 16;
+    const int nrt = (N + 1) / 2;
+    const int gy = (nrt + 4 * TM_RT - 1) / (4 * TM_RT);
+    if (gx > 0x7fffffff || (int64_t)cols > 0x7fffffff) return LEB_EINVAL;
+    const size_t smem = ((size_t)(N > 1 ? N - 1 : 0) * 48 + 6) * sizeof(double);
+    if (smem > 65536) return LEB_ENOTSUP;     // Phi must fit in LDS: N <= 171
+    hipLaunchKernelGGL(tube_map_kernel, dim3((unsigned)gx, gy), dim3(256), smem, s, phi, a, fp);
     return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
 }
 
 int launch_tube_map(int B, int N, int U, const double* phi, const double* e, const double* cbar,
                     const double* rbar, double* mu, double* sigma, hipStream_t s) {
-    TubeFP none{nullptr, nullptr, nullptr, nullptr, 0.0, 0.0, 0};
+    TubeFP none{nullptr, nullptr, nullptr, 0.0, 0.0};
     return launch_tube(B, N, U, phi, e, cbar, rbar, mu, sigma, none, s);
 }
 
@@ -324,7 +333,7 @@ extern "C" int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int
     const size_t bx = (size_t)units * nx * sizeof(double), bn = (size_t)units * n * sizeof(double);
     if ((rc = ws_get(0, bx, (void**)&cb)) || (rc = ws_get(1, bx, (void**)&rb)) ||
         (rc = ws_get(2, bn, (void**)&xm1)) || (rc = ws_get(3, bn, (void**)&xs1)) ||
-        (rc = ws_get(4, ((size_t)batch + 2) * sizeof(uint32_t), (void**)&state)) || (rc = ws_host_and_events()))
+        (rc = ws_get(4, ((size_t)batch + 1) * sizeof(uint32_t), (void**)&state)) || (rc = ws_host_and_events()))
         return rc;
     // iterates: buffer 0 = the caller's (mu, sigma), buffer 1 = workspace; sweep t reads C_{t-1}
     // from buffer (t-1) & 1 and writes C_t to buffer t & 1
@@ -332,7 +341,7 @@ extern "C" int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int
     double* xs[2] = {sigma, xs1};
     const int64_t cnt = units * n, per = (int64_t)N * n;
     auto ok = [](hipError_t e_) { return e_ == hipSuccess; };
-    hipLaunchKernelGGL(fp_init_kernel, dim3(nblk(batch + 2)), dim3(256), 0, s, state, batch);
+    hipLaunchKernelGGL(fp_init_kernel, dim3(nblk(batch + 1)), dim3(256), 0, s, state, batch);
     if (!opt->warm) {       // C_0: the disturbance-only tube (LEB = 0), below the fixed point
         hipLaunchKernelGGL(fill_kernel, dim3(nblk(units * nx)), dim3(256), 0, s, cb, units * nx, 0.0);
         hipLaunchKernelGGL(fill_kernel, dim3(nblk(units * nx)), dim3(256), 0, s, rb, units * nx, opt->pad);
@@ -345,8 +354,9 @@ extern "C" int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int
                                  state + batch);
         if (r) return r;
         hopen[t % FP_SLOTS] = 0xffffffffu;
-        const TubeFP fp{xm[a], xs[a], state, g_ws.host_open_dev, opt->tol, opt->inflate_abs, t};
+        const TubeFP fp{xm[a], xs[a], state, opt->tol, opt->inflate_abs};
         if ((r = launch_tube(batch, N, U, phi, e, cb, rb, xm[w], xs[w], fp, s))) return r;
+        hipLaunchKernelGGL(fp_state_kernel, dim3(1), dim3(256), 0, s, state, batch, g_ws.host_open_dev, t);
         return ok(hipEventRecord(g_ws.ev[t & 1], s)) ? LEB_OK : LEB_EDEVICE;
     };
     // one sweep stays in flight while the host reads the previous sweep's
