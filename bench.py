@@ -33,6 +33,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 matrix (= vector) peak
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # lane-ops/s of non-packed VALU issue (39.3 T)
 
 
@@ -47,6 +48,7 @@ def parse():
     p.add_argument("--epochs", type=int, default=20, help="surrogate training epochs (outside the timed region)")
     p.add_argument("--surrogate-sweeps", type=int, default=6)
     p.add_argument("--margin", type=float, default=2e-2, help="relative inflation of the surrogate tube")
+    p.add_argument("--no-extra", action="store_true", help="skip the MLP-bound roofline and the uneven batch")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                    help="only run an elementwise copy (read BYTES, write BYTES) 5 times: the known-size "
                         "kernel that scales FETCH_SIZE / WRITE_SIZE counters")
@@ -160,6 +162,9 @@ def main():
                 "kernel": "pbh_chain_fwd", "launch_us": round(kern_us, 3), "units_per_launch": units,
                 "bytes_per_unit": bpu}
 
+    nn_line = None if args.no_extra else nn_roofline(leb, W, dev, stream, args)
+    batch_line = None if args.no_extra else batched_uneven(leb, W, dev, stream, args)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(W, tp, args.cpu_seconds)
@@ -182,8 +187,103 @@ def main():
         "plain": {"value": round(units * 1e3 / plain_ms, 1), "ms_per_solve": round(plain_ms, 4),
                   "certified_sweeps": plain_sweeps, "certified": plain_cert},
         "roofline": roofline, "cpu_baseline": cpu,
+        "roofline_nn": nn_line, "batched_uneven": batch_line,
     }
     print(json.dumps(line))
+
+
+def nn_crown_flops(widths):
+    """Algorithmic FLOPs per box of the CROWN passes as the MLP bound runs
+    them: for every target layer k >= 2 (hidden layers with 2 modes, upper
+    and lower; the output layer with 3, adding the Jacobian), the chain of
+    products through layers k-1 .. 1 is [w_k x w_j] . [w_j x w_{j-1}]."""
+    L = len(widths) - 1
+    mac = 0
+    for k in range(2, L + 1):
+        modes = 3 if k == L else 2
+        for j in range(k - 1, 0, -1):
+            mac += modes * widths[k] * widths[j] * widths[j - 1]
+    return 2 * mac
+
+
+def nn_roofline(leb, W, dev, stream, args):
+    """MLP bound (CROWN + Theorem 2) on 64 x 50 boxes of the 16-256-256-256-12
+    network: FP64 MFMA, timed with HIP events on its stream."""
+    import torch
+    b = W.nn_cfg()
+    net = leb.MLP(b.net.W, b.net.b, b.net.nx, True)
+    z = torch.from_numpy(b.z).to(dev)
+    v = torch.from_numpy(b.v).to(dev)
+    sg = torch.from_numpy(b.sigma).to(dev)
+    for _ in range(2):
+        leb.nn_bound(net, z, v, sg, stream=stream)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record(stream)
+    for _ in range(reps):
+        leb.nn_bound(net, z, v, sg, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    boxes = b.z.shape[0] * b.z.shape[1]
+    widths = [b.net.W[0].shape[1]] + [w.shape[0] for w in b.net.W]
+    fl = nn_crown_flops(widths) * boxes
+    net.close()
+    achieved = fl / (ms * 1e-3) / 1e12
+    return {"workload": "MLP bound, 64 x 50 boxes, widths %s" % widths, "ms_per_call": round(ms, 4),
+            "timestep_bounds_per_s": round(boxes / (ms * 1e-3), 1),
+            "bound": "mfma", "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "flops_per_box": nn_crown_flops(widths)}
+
+
+def batched_uneven(leb, W, dev, stream, args):
+    """256 uneven problems (nx in {6, 12, 48, 168}, horizons 10..80) in one
+    graph launch, tiles from the autotuner."""
+    import numpy as np
+    import torch
+    mb = W.mixed_batch_cfg(seed=3, count=256)
+    nets = {}
+    probs = []
+    units = 0
+    for kind, cfg in mb.problems:
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a[0])).to(dev)
+        p = {"z": t(cfg.z), "v": t(cfg.v), "sigma": t(cfg.sigma)}
+        if kind == "analytic":
+            p.update(kind="analytic", dyn=leb.dynamics_like(cfg.dyn))
+            nx = cfg.z.shape[2]
+        else:
+            if id(cfg.net) not in nets:
+                nets[id(cfg.net)] = leb.MLP(cfg.net.W, cfg.net.b, cfg.net.nx, True)
+            p.update(kind="nn", net=nets[id(cfg.net)])
+            nx = cfg.net.W[-1].shape[0]
+        N = cfg.z.shape[1]
+        units += N
+        p["r_lo"] = torch.empty((N, nx), dtype=torch.float64, device=dev)
+        p["r_hi"] = torch.empty((N, nx), dtype=torch.float64, device=dev)
+        probs.append(p)
+    t0 = time.perf_counter()
+    bt = leb.Batch(probs, tune_cache=None)
+    create_s = time.perf_counter() - t0
+    bt.submit(stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record(stream)
+    for _ in range(reps):
+        bt.submit(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    info = bt.info().strip().splitlines()
+    bt.close()
+    for n in nets.values():
+        n.close()
+    return {"workload": "256 uneven problems, nx in {6,12,48,168}, N in 10..80, one graph launch",
+            "timestep_bounds": units, "ms_per_submit": round(ms, 4),
+            "timestep_bounds_per_s": round(units / (ms * 1e-3), 1), "create_s": round(create_s, 2),
+            "groups": info}
 
 
 def train_chain_surrogate(leb, W, dev, args):

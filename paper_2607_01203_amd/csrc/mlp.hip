@@ -9,7 +9,8 @@
 //   db_l = sum_b dz_l; dz_{l-1} = (bf16(W_l)^T g_l) gelu'(z_{l-1});
 //   g_{l-1} = bf16(dz_{l-1}).
 // Adam (Kingma and Ba, Algorithm 1) updates the FP32 parameters, then the
-// BF16 copies are refreshed.
+// BF16 copies are refreshed.  gelu(z) = z Phi(z) is evaluated in FP32 with
+// a published approximation of erf (below), well inside BF16 rounding.
 //
 // MFMA: v_mfma_f32_16x16x32_bf16.  Lane l supplies A[l%16][8(l/16)+j] and
 // B[8(l/16)+j][l%16] (j = 0..7) and receives D[4(l/16)+i][l%16] (i = 0..3).
@@ -37,9 +38,29 @@ constexpr int MLP_MAX_LAYERS = 8;
 constexpr int MLP_MAX_WIDTH = 256;
 constexpr int FWD_ROWS = 64;            // rows (samples) per forward workgroup
 
-__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// Standard normal CDF Phi(z) = (1 + erf(z / sqrt 2)) / 2 and exp(-z^2 / 2),
+// with erf from Abramowitz and Stegun, Handbook of Mathematical Functions,
+// formula 7.1.26 (|error| <= 1.5e-7): erf(x) ~ 1 - (a1 t + ... + a5 t^5)
+// exp(-x^2), t = 1 / (1 + p x), x >= 0; odd extension for x < 0.
+__device__ __forceinline__ void normal_cdf(float z, float* Phi, float* ex) {
+    const float u = fabsf(z) * 0.70710678118654752f;
+    const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * u);
+    const float e = __expf(-0.5f * z * z);
+    const float poly = t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f +
+                                                                                        t * 1.061405429f))));
+    const float erf_abs = 1.0f - poly * e;
+    *Phi = 0.5f + 0.5f * copysignf(erf_abs, z);
+    *ex = e;
+}
+__device__ __forceinline__ float gelu_f(float z) {
+    float P, e;
+    normal_cdf(z, &P, &e);
+    return z * P;
+}
 __device__ __forceinline__ float gelu_grad_f(float z) {
-    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+    float P, e;
+    normal_cdf(z, &P, &e);
+    return P + z * e * 0.39894228040143268f;
 }
 
 static inline int pad32(int x) { return (x + 31) & ~31; }
@@ -76,7 +97,7 @@ struct FwdArgs {
 // CT of them, over all four 16-row tiles.  The loads of a k-step are
 // issued together and unconditionally (a slot beyond the layer's width
 // reads a valid tile and is never stored), so no MFMA waits on a branch.
-template <int CT>
+template <int CT, bool SAVE>
 __global__ void __launch_bounds__(256) mlp_fwd_kernel(FwdArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int ldA = A.ldA;
@@ -96,7 +117,7 @@ __global__ void __launch_bounds__(256) mlp_fwd_kernel(FwdArgs A) {
             const float v = (row < A.B && k < d0) ? A.x[(int64_t)row * d0 + k] : 0.0f;
             const __bf16 bv = (__bf16)v;
             buf0[r * ldA + k] = bv;
-            if (A.aT && row < A.B) A.aT[(int64_t)k * A.B + row] = bv;   // a_0^T
+            if (SAVE && row < A.B) A.aT[(int64_t)k * A.B + row] = bv;   // a_0^T
         }
     }
     __syncthreads();
@@ -107,7 +128,9 @@ __global__ void __launch_bounds__(256) mlp_fwd_kernel(FwdArgs A) {
         const bool last = (l == G.L - 1);
         const __bf16* W = A.Wt + G.woff[l];
         const float* bias = A.params + G.poff[l] + (int64_t)nout * G.w[l];
-        const int ntc = np / 16;
+        // column tiles of this layer (the output layer stops at its true width)
+        const int ntc = last ? (nout + 15) / 16 : np / 16;
+        const int ns = __builtin_amdgcn_readfirstlane((ntc - wave + 3) >> 2);   // slots of this wave (may be <= 0)
         f32x4 acc[CT][4];
 #pragma unroll
         for (int s = 0; s < CT; ++s)
@@ -119,43 +142,62 @@ __global__ void __launch_bounds__(256) mlp_fwd_kernel(FwdArgs A) {
             const int ct = min(wave + 4 * s, ntc - 1);
             wrow[s] = W + (int64_t)(ct * 16 + lr) * kp + lk;
         }
-        for (int k = 0; k < kp; k += 32) {
-            bf16x8 a[4], b[CT];
+        if (ns > 0) {
+            for (int k = 0; k < kp; k += 32) {
+                bf16x8 a[4], b[CT];
 #pragma unroll
-            for (int s = 0; s < CT; ++s) b[s] = *reinterpret_cast<const bf16x8*>(wrow[s] + k);
-#pragma unroll
-            for (int rt = 0; rt < 4; ++rt) a[rt] = *reinterpret_cast<const bf16x8*>(cur + (rt * 16 + lr) * ldA + k + lk);
-#pragma unroll
-            for (int s = 0; s < CT; ++s)
+                for (int s = 0; s < CT; ++s)
+                    if (s < ns) b[s] = *reinterpret_cast<const bf16x8*>(wrow[s] + k);
 #pragma unroll
                 for (int rt = 0; rt < 4; ++rt)
-                    acc[s][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rt], b[s], acc[s][rt], 0, 0, 0);
+                    a[rt] = *reinterpret_cast<const bf16x8*>(cur + (rt * 16 + lr) * ldA + k + lk);
+#pragma unroll
+                for (int s = 0; s < CT; ++s)
+                    if (s < ns)
+#pragma unroll
+                        for (int rt = 0; rt < 4; ++rt)
+                            acc[s][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rt], b[s], acc[s][rt], 0, 0, 0);
+            }
         }
         // epilogue
+        if (last) {
 #pragma unroll
-        for (int s = 0; s < CT; ++s) {
-            const int ct = wave + 4 * s;
-            if (ct >= ntc) continue;
-            const int c = ct * 16 + lr;
-            const float bc = c < nout ? bias[c] : 0.0f;
+            for (int s = 0; s < CT; ++s) {
+                if (s >= ns) continue;
+                const int c = (wave + 4 * s) * 16 + lr;
+                const float bc = c < nout ? bias[c] : 0.0f;
 #pragma unroll
-            for (int rt = 0; rt < 4; ++rt)
+                for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int r = rt * 16 + 4 * (lane >> 4) + i;
-                    const int row = row0 + r;
-                    const float z = acc[s][rt][i] + bc;
-                    if (last) {
-                        if (row < A.B && c < nout) A.y[(int64_t)row * nout + c] = z;
-                    } else {
-                        const __bf16 av = (__bf16)(c < nout ? gelu_f(z) : 0.0f);
+                    for (int i = 0; i < 4; ++i) {
+                        const int row = row0 + rt * 16 + 4 * (lane >> 4) + i;
+                        if (row < A.B && c < nout) A.y[(int64_t)row * nout + c] = acc[s][rt][i] + bc;
+                    }
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < CT; ++s) {
+                if (s >= ns) continue;
+                const int c = (wave + 4 * s) * 16 + lr;
+                const bool cin = c < nout;
+                const float bc = cin ? bias[c] : 0.0f;
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int r = rt * 16 + 4 * (lane >> 4) + i;
+                        const float z = acc[s][rt][i] + bc;
+                        const __bf16 av = (__bf16)(cin ? gelu_f(z) : 0.0f);
                         nxt[r * ldA + c] = av;
-                        if (row < A.B) {
-                            if (A.zsave) A.zsave[((int64_t)l * A.B + row) * MLP_MAX_WIDTH + c] = c < nout ? z : 0.0f;
-                            if (A.aT) A.aT[((int64_t)(l + 1) * MLP_MAX_WIDTH + c) * A.B + row] = av;
+                        if (SAVE) {
+                            const int row = row0 + r;
+                            if (row < A.B) {
+                                A.zsave[((int64_t)l * A.B + row) * MLP_MAX_WIDTH + c] = cin ? z : 0.0f;
+                                A.aT[((int64_t)(l + 1) * MLP_MAX_WIDTH + c) * A.B + row] = av;
+                            }
                         }
                     }
-                }
+            }
         }
         __syncthreads();
         __bf16* t_ = cur; cur = nxt; nxt = t_;
@@ -399,10 +441,14 @@ extern "C" int leb_surrogate_create(int32_t n_layers, const int32_t* widths, con
     s->ldA = widest + 8;
     const size_t smem = 2 * (size_t)FWD_ROWS * s->ldA * sizeof(__bf16);
     if (smem > 65536 &&
-        (hipFuncSetAttribute((const void*)mlp_fwd_kernel<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) !=
-             hipSuccess ||
-         hipFuncSetAttribute((const void*)mlp_fwd_kernel<4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) !=
-             hipSuccess)) {
+        (hipFuncSetAttribute((const void*)mlp_fwd_kernel<2, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)smem) != hipSuccess ||
+         hipFuncSetAttribute((const void*)mlp_fwd_kernel<2, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)smem) != hipSuccess ||
+         hipFuncSetAttribute((const void*)mlp_fwd_kernel<4, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)smem) != hipSuccess ||
+         hipFuncSetAttribute((const void*)mlp_fwd_kernel<4, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)smem) != hipSuccess)) {
         delete s;
         return LEB_EDEVICE;
     }
@@ -461,10 +507,14 @@ static int fwd_launch(leb_surrogate_s* s, int B, const float* x, float* y, bool 
     a.aT = save ? s->aT : nullptr;
     a.ldA = s->ldA;
     const size_t smem = 2 * (size_t)FWD_ROWS * s->ldA * sizeof(__bf16);
-    if (s->ldA - 8 <= 128)
-        hipLaunchKernelGGL(mlp_fwd_kernel<2>, dim3(nb(B, FWD_ROWS)), dim3(256), smem, st, a);
-    else
-        hipLaunchKernelGGL(mlp_fwd_kernel<4>, dim3(nb(B, FWD_ROWS)), dim3(256), smem, st, a);
+    const dim3 g(nb(B, FWD_ROWS)), t(256);
+    if (s->ldA - 8 <= 128) {
+        if (save) hipLaunchKernelGGL((mlp_fwd_kernel<2, true>), g, t, smem, st, a);
+        else hipLaunchKernelGGL((mlp_fwd_kernel<2, false>), g, t, smem, st, a);
+    } else {
+        if (save) hipLaunchKernelGGL((mlp_fwd_kernel<4, true>), g, t, smem, st, a);
+        else hipLaunchKernelGGL((mlp_fwd_kernel<4, false>), g, t, smem, st, a);
+    }
     return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
 }
 

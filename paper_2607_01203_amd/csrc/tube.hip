@@ -23,6 +23,7 @@
 // converges to one of them, about tol above C*.  A trajectory is certified
 // (and frozen) by the sweep that shows F(C) inside C.
 #include <hip/hip_runtime.h>
+#include <float.h>
 #include <math.h>
 #include <stdint.h>
 
@@ -72,30 +73,57 @@ constexpr int TM_RT = 5;        // 16-row tiles per wave and row group
 // Fixed-point form: frozen trajectories are not written; containment
 // failures are or-ed into the state words (fp_state_kernel folds them).
 __global__ void __launch_bounds__(256) tube_map_kernel(const double* __restrict__ phi, TubeArgs A, TubeFP P) {
-    extern __shared__ double sphi[];          // [(N-1) * 48] Phi, then e[6]
+    // LDS: Phi [(N-1)*48], e[6], then the B block of this workgroup's 16
+    // columns: c [6(N-1)][16] and w [6(N-1)][16]
+    extern __shared__ double sphi[];
     __shared__ uint32_t sbad[16];
+    __shared__ int sjinf[16];
     const bool fp = P.state != nullptr;
     if (fp && P.state[A.B] == 0u) return;     // every trajectory certified by an earlier sweep
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int N = A.N, U = A.U, nx = 6 * U, n = 8 * U;
     const int nphi = (N - 1) * 48;
+    const int kfull = 6 * (N - 1);
+    double* se = sphi + nphi;
+    double* sc = se + 8;
+    double* sw = sc + (size_t)kfull * 16;
     for (int idx = tid; idx < nphi; idx += 256) sphi[idx] = phi[idx];
-    if (tid < 6) sphi[nphi + tid] = A.e[tid];
-    if (tid < 16) sbad[tid] = 0u;
+    if (tid < 6) se[tid] = A.e[tid];
+    if (tid < 16) { sbad[tid] = 0u; sjinf[tid] = 0x7fffffff; }
     __syncthreads();
-    const double* se = sphi + nphi;
     const int cols = A.B * U;
     const int c0 = blockIdx.x * 16;
+    // stage c_bar and w = e + rho_bar + |c_bar| wid: thread (kk-chunk, column), the 6 q of one
+    // (column, step) are contiguous in HBM.  A residual that is not finite enters as 0, and
+    // every later step of its column gets sigma = +inf (a product 0 * inf with the zero
+    // entries of T would otherwise make earlier rows NaN).
+    for (int idx = tid; idx < kfull * 16; idx += 256) {
+        const int cl = idx / kfull, kk = idx - cl * kfull;
+        const int j = kk / 6, q = kk - 6 * j;
+        const int col = c0 + cl;
+        double c = 0.0, w = 0.0;
+        if (col < cols) {
+            const int bb = col / U, nd = col - bb * U;
+            const int64_t o = ((int64_t)bb * N + j) * nx + 6 * nd + q;
+            c = A.cbar[o];
+            w = se[q] + A.rbar[o] + fabs(c) * A.wid;
+            if (!(fabs(c) <= DBL_MAX && w <= DBL_MAX)) {
+                atomicMin(&sjinf[cl], j);
+                c = 0.0;
+                w = 0.0;
+            }
+        }
+        sc[kk * 16 + cl] = c;
+        sw[kk * 16 + cl] = w;
+    }
+    __syncthreads();
     const int col = c0 + (lane & 15);
     const bool cvalid = col < cols;
     const int cc = cvalid ? col : cols - 1;
     const int b = cc / U, node = cc - b * U;
     const int bfirst = c0 / U;
-    const double* cbp = A.cbar + (int64_t)b * N * nx + 6 * node;
-    const double* rbp = A.rbar + (int64_t)b * N * nx + 6 * node;
     const int nrt = (N + 1) >> 1;
-    const int kfull = 6 * (N - 1);
     int kmax[TM_RT];
     int kw = 0;
 #pragma unroll
@@ -111,23 +139,21 @@ __global__ void __launch_bounds__(256) tube_map_kernel(const double* __restrict_
     for (int k0 = 0; k0 < kw; k0 += 4) {
         const int kk = k0 + lq;
         const int j = kk / 6, q = kk - 6 * j;
-        double c = 0.0, w = 0.0;
-        if (kk < kfull && cvalid) {
-            c = cbp[(int64_t)j * nx + q];
-            // residual radius plus the allowance for the rounding of the centre sum
-            w = se[q] + rbp[(int64_t)j * nx + q] + fabs(c) * A.wid;
-        }
+        const bool kin = kk < kfull;
+        const double c = kin ? sc[kk * 16 + lr] : 0.0;
+        const double w = kin ? sw[kk * 16 + lr] : 0.0;
 #pragma unroll
         for (int s = 0; s < TM_RT; ++s) {
             if (k0 >= kmax[s]) continue;       // wave-uniform
             const int rt = wave + 4 * (blockIdx.y * TM_RT + s);
             const int r = 16 * rt + lr, k = r >> 3, rr = r & 7;
             const int lag = k - j - 1;
-            const double a = (lag >= 0 && lag < N - 1 && kk < kfull) ? sphi[lag * 48 + rr * 6 + q] : 0.0;
+            const double a = (lag >= 0 && lag < N - 1 && kin) ? sphi[lag * 48 + rr * 6 + q] : 0.0;
             am[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, c, am[s], 0, 0, 0);
             as[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(fabs(a), w, as[s], 0, 0, 0);
         }
     }
+    const int jinf = sjinf[lr];
     const bool frozen = fp && (P.state[b] & FP_CERT);
     bool bad = false;
 #pragma unroll
@@ -140,12 +166,13 @@ __global__ void __launch_bounds__(256) tube_map_kernel(const double* __restrict_
             if (k >= N || !cvalid) continue;
             const int64_t o = ((int64_t)b * N + k) * n + (rr < 6 ? 6 * node + rr : nx + 2 * node + (rr - 6));
             // sums of nonnegative terms, rounded upward; 2^-1000 covers any flushed subnormal part
-            const double sF = as[s][i] + as[s][i] * A.wid + 0x1p-1000, mF = am[s][i];
+            const double sF = k > jinf ? INFINITY : as[s][i] + as[s][i] * A.wid + 0x1p-1000, mF = am[s][i];
             double so = sF;
             if (fp) {
                 const double mi = P.mu_in[o], si = P.sg_in[o];
-                // [mF - sF, mF + sF] inside [mi - si, mi + si], with the rounding of the test covered
-                bad |= !((fabs(mF - mi) + sF) * (1.0 + 0x1p-50) <= si);
+                // [mF - sF, mF + sF] inside [mi - si, mi + si], with the rounding of the test
+                // covered; a tube that is not finite is never accepted
+                bad |= !(sF <= DBL_MAX && (fabs(mF - mi) + sF) * (1.0 + 0x1p-50) <= si);
                 so = sF + sF * P.tol + P.abs_;
             }
             if (!frozen) { A.mu[o] = mF; A.sigma[o] = so; }
@@ -231,8 +258,17 @@ static int launch_tube(int B, int N, int U, const double* phi, const double* e, 
     const int nrt = (N + 1) / 2;
     const int gy = (nrt + 4 * TM_RT - 1) / (4 * TM_RT);
     if (gx > 0x7fffffff || (int64_t)cols > 0x7fffffff) return LEB_EINVAL;
-    const size_t smem = ((size_t)(N > 1 ? N - 1 : 0) * 48 + 6) * sizeof(double);
-    if (smem > 65536) return LEB_ENOTSUP;     // Phi must fit in LDS: N <= 171
+    // Phi, e (padded to 8) and the B block (c and w for 16 columns)
+    const size_t nm1 = N > 1 ? N - 1 : 0;
+    const size_t smem = (nm1 * 48 + 8 + 2 * 6 * nm1 * 16) * sizeof(double);
+    if (smem > 160 * 1024 - 256) return LEB_ENOTSUP;     // N <= 86
+    static bool lds_attr = false;      // the kernel may use up to 160 KB of LDS (set once)
+    if (smem > 65536 && !lds_attr) {
+        if (hipFuncSetAttribute((const void*)tube_map_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                160 * 1024 - 256) != hipSuccess)
+            return LEB_EDEVICE;
+        lds_attr = true;
+    }
     hipLaunchKernelGGL(tube_map_kernel, dim3((unsigned)gx, gy), dim3(256), smem, s, phi, a, fp);
     return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
 }

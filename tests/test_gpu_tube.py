@@ -40,6 +40,39 @@ def test_tube_map_parity(gpu, orc):
     assert (sg >= so).all() and (sg <= so * (1 + 1e-11) + 1e-15).all()
 
 
+def test_tube_map_non_finite_residual(gpu, orc):
+    """A residual that is not finite at step j of one node makes sigma +inf
+    at that node's later steps only; earlier steps and other nodes keep the
+    finite result (the zero blocks of the contraction never turn it to NaN)."""
+    import torch
+    import paper_2607_01203_amd as leb
+    from oracle import tube
+    tp = W.fixed_point_cfg(seed=51, batch=2, N=10, n_units=5)
+    B, N, nx = tp.batch.z.shape
+    r = np.random.default_rng(3)
+    cb = r.normal(size=(B, N, nx)) * 1e-3
+    rb = r.uniform(0, 1e-3, (B, N, nx))
+    mo, so = tube.tube_map(tp.phi, tp.e, cb, rb)
+    cb2, rb2 = cb.copy(), rb.copy()
+    rb2[1, 4, 6 * 2 + 3] = np.inf          # trajectory 1, step 4, node 2, vx row
+    cb2[0, 6, 6 * 4 + 1] = np.nan          # trajectory 0, step 6, node 4
+    print("case: tube map with non-finite residuals", flush=True)
+    mu, sg = leb.tube_map(5, _t(tp.phi, gpu), tp.e, _t(cb2, gpu), _t(rb2, gpu))
+    torch.cuda.synchronize()
+    mu, sg = mu.cpu().numpy(), sg.cpu().numpy()
+    n = 8 * 5
+    node = lambda i: list(range(6 * i, 6 * i + 6)) + [30 + 2 * i, 31 + 2 * i]
+    inf_mask = np.zeros(sg.shape, dtype=bool)
+    inf_mask[1, 5:, node(2)] = True
+    inf_mask[0, 7:, node(4)] = True
+    assert np.isinf(sg[inf_mask]).all() and not np.isnan(sg).any() and not np.isnan(mu).any()
+    fin = ~inf_mask
+    assert (sg[fin] >= so[fin]).all() and (sg[fin] <= so[fin] * (1 + 1e-11) + 1e-15).all()
+    ok_mu = np.ones(mu.shape, dtype=bool)
+    ok_mu[0, 7:, node(4)] = False          # the NaN centre entered as 0: only sigma is meaningful there
+    np.testing.assert_allclose(mu[ok_mu], mo[ok_mu], rtol=1e-12, atol=1e-15)
+
+
 def _solve(leb, tp, dev, **kw):
     import torch
     b = tp.batch
