@@ -46,8 +46,8 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU baseline duration")
     p.add_argument("--kernel-reps", type=int, default=50)
     p.add_argument("--epochs", type=int, default=20, help="surrogate training epochs (outside the timed region)")
-    p.add_argument("--surrogate-sweeps", type=int, default=6)
-    p.add_argument("--margin", type=float, default=2e-2, help="relative inflation of the surrogate tube")
+    p.add_argument("--surrogate-sweeps", type=int, default=1)
+    p.add_argument("--margin", type=float, default=5e-2, help="relative inflation of the surrogate tube")
     p.add_argument("--no-extra", action="store_true", help="skip the MLP-bound roofline and the uneven batch")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                    help="only run an elementwise copy (read BYTES, write BYTES) 5 times: the known-size "

@@ -279,6 +279,20 @@ int leb_chain_features(const leb_dynamics* dyn, int32_t batch, int32_t N, const 
 int leb_chain_targets(const leb_dynamics* dyn, int32_t batch, int32_t N, const double* r_lo, const double* r_hi,
                       float* t, void* stream);
 
+/*
+ * leb_chain_surrogate_bound -- the surrogate's residual zonotope for a chain
+ * tube (the learned counterpart of leb_analytic_bound's c_bar, rho_bar):
+ * features, the BF16 MLP and the decoding hi = exp(min(y_hi, 0)),
+ * lo = -exp(min(y_lo, 0)) run in one kernel; c_bar = (lo + hi) / 2 and
+ * rho_bar = (hi - lo) / 2 + pad on the vx, vz rows, 0 and pad on the
+ * affine rows.  A prediction that is not finite counts as a zero bound.
+ * Not a certified bound: it only seeds the certified iteration.
+ *   z, v, mu (NULL = 0), sigma as leb_analytic_bound; c_bar, rho_bar [batch][N][nx]
+ */
+int leb_chain_surrogate_bound(const leb_dynamics* dyn, int32_t batch, int32_t N, const double* z, const double* v,
+                              const double* mu, const double* sigma, leb_surrogate net, double* c_bar,
+                              double* rho_bar, double pad, void* stream);
+
 typedef struct {
     leb_surrogate net;     /* widths [32, ..., 4] */
     int32_t sweeps;        /* tube sweeps with surrogate bounds before certification (>= 0) */

@@ -135,6 +135,9 @@ def lib():
         L.leb_batch_destroy.restype = ctypes.c_int
         L.leb_batch_info.argtypes = [vp, ctypes.c_char_p, ctypes.c_int32]
         L.leb_batch_info.restype = ctypes.c_int
+        L.leb_chain_surrogate_bound.argtypes = [ctypes.POINTER(Dynamics), ctypes.c_int32, ctypes.c_int32] + \
+            [vp] * 5 + [vp, vp, ctypes.c_double, vp]
+        L.leb_chain_surrogate_bound.restype = ctypes.c_int
         L.leb_strerror.argtypes = [ctypes.c_int]
         L.leb_strerror.restype = ctypes.c_char_p
         L.leb_version.restype = ctypes.c_char_p
@@ -296,7 +299,7 @@ def fixed_point_solve(dyn: Dynamics, z, v, phi, e, tol=1e-6, max_sweeps=200, pad
     return mu, sigma, cert, int(sweeps.value)
 
 
-def fixed_point_learned(dyn: Dynamics, z, v, phi, e, net, sweeps=6, margin=5e-3, tol=1e-6, max_sweeps=200,
+def fixed_point_learned(dyn: Dynamics, z, v, phi, e, net, sweeps=1, margin=5e-2, tol=1e-6, max_sweeps=200,
                         pad=0.0, inflate_abs=1e-12, stream=None):
     """Certified fixed point from a learned initial tube (see leb.h:
     leb_fixed_point_learned).  Returns (mu, sigma, certified, certified sweeps)."""
@@ -328,6 +331,21 @@ def chain_features(dyn: Dynamics, z, v, sigma, mu=None, stream=None):
                                     _dev_ptr(mu, "mu", f64), _dev_ptr(sigma, "sigma", f64),
                                     _dev_ptr(x, "x", torch.float32), _stream(stream)))
     return x
+
+
+def chain_surrogate_bound(dyn: Dynamics, z, v, sigma, net, mu=None, pad=0.0, stream=None):
+    """The surrogate's residual zonotope (c_bar, rho_bar) [B][N][nx] for a
+    chain tube (see leb.h: leb_chain_surrogate_bound).  Not certified."""
+    import torch
+    B, N = int(z.shape[0]), int(z.shape[1])
+    f64 = torch.float64
+    cb = torch.empty((B, N, dyn.nx), dtype=f64, device=z.device)
+    rb = torch.empty_like(cb)
+    _check(lib().leb_chain_surrogate_bound(ctypes.byref(dyn), B, N, _dev_ptr(z, "z", f64), _dev_ptr(v, "v", f64),
+                                           _dev_ptr(mu, "mu", f64), _dev_ptr(sigma, "sigma", f64), net.handle,
+                                           _dev_ptr(cb, "c_bar", f64), _dev_ptr(rb, "rho_bar", f64), float(pad),
+                                           _stream(stream)))
+    return cb, rb
 
 
 def chain_targets(dyn: Dynamics, r_lo, r_hi, stream=None):

@@ -19,8 +19,12 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libleb.so")
 ARCH = "gfx950"
 
+# -packed-fp32-ops: no packed FP32 instructions.  -amdgpu-mfma-vgpr-form: MFMA
+# accumulators in the unified VGPR file (gfx950), which keeps loop-carried
+# accumulators in place instead of copying them to and from AGPRs.
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 
 

@@ -38,6 +38,10 @@ int nn_bound_run(const leb_mlp_s* net, int64_t units, const double* z, const dou
                  uint32_t* flags, int CB, double* const* buf, hipStream_t st);
 void nn_dims(const leb_mlp_s* net, int* nx, int* nu, int* m);
 
+// one surrogate sweep over a chain tube (features -> BF16 MLP -> residual zonotope rows 6i+3, 6i+4)
+int surrogate_chain_sweep(leb_surrogate s, const double* z, const double* v, const double* mu, const double* sigma,
+                          int nodes, int U, double L0, double pad, double* cbar, double* rbar, hipStream_t st);
+
 // argument checks shared by the entry points
 bool aligned8(const void* p);
 int check_chain_dynamics(const leb_dynamics* dyn);

@@ -27,6 +27,7 @@
 #include <vector>
 
 #include "leb.h"
+#include "chain_features.hpp"
 #include "leb_internal.hpp"
 
 namespace leb {
@@ -44,12 +45,13 @@ constexpr int FWD_ROWS = 64;            // rows (samples) per forward workgroup
 // exp(-x^2), t = 1 / (1 + p x), x >= 0; odd extension for x < 0.
 __device__ __forceinline__ void normal_cdf(float z, float* Phi, float* ex) {
     const float u = fabsf(z) * 0.70710678118654752f;
-    const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * u);
-    const float e = __expf(-0.5f * z * z);
-    const float poly = t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f +
-                                                                                        t * 1.061405429f))));
-    const float erf_abs = 1.0f - poly * e;
-    *Phi = 0.5f + 0.5f * copysignf(erf_abs, z);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, u, 1.0f));
+    const float e = __builtin_amdgcn_exp2f(z * z * -0.72134752044448170f);     // exp(-z^2 / 2)
+    const float poly =
+        t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f),
+                 0.254829592f);
+    const float erf_abs = fmaf(-poly, e, 1.0f);
+    *Phi = fmaf(0.5f, copysignf(erf_abs, z), 0.5f);
     *ex = e;
 }
 __device__ __forceinline__ float gelu_f(float z) {
@@ -88,7 +90,14 @@ struct FwdArgs {
     __bf16* aT;               // optional [L][MAX_WIDTH][B]  a_l^T for l = 0..L-1
     int B;
     int ldA;                  // LDS row stride (BF16): widest padded layer + 8
+    // chain surrogate sweep (FWD_CHAIN): rows are (unit, node) of a chain tube
+    const double *cz, *cv, *cmu, *csg;
+    double *cbar, *rbar;      // rows 6i+3, 6i+4 of every unit written
+    int U;
+    double L0, pad;
 };
+
+enum { FWD_PLAIN = 0, FWD_SAVE = 1, FWD_CHAIN = 2 };
 
 // One workgroup (4 waves) carries 64 rows through every layer.  The
 // activation tile lives in LDS ([64][ldA] BF16, ldA = widest padded layer
@@ -97,8 +106,15 @@ struct FwdArgs {
 // CT of them, over all four 16-row tiles.  The loads of a k-step are
 // issued together and unconditionally (a slot beyond the layer's width
 // reads a valid tile and is never stored), so no MFMA waits on a branch.
-template <int CT, bool SAVE>
+//
+// FWD_CHAIN: the rows are the nodes of a chain tube; the inputs are the
+// chain surrogate's features, computed in the staging step, and the output
+// (log-bounds of the vx, vz rows) is decoded into the residual zonotope in
+// place of y: one kernel per surrogate sweep.
+template <int CT, int MODE>
 __global__ void __launch_bounds__(256) mlp_fwd_kernel(FwdArgs A) {
+    constexpr bool SAVE = MODE == FWD_SAVE;
+    __shared__ float sy[FWD_ROWS][LEB_CHAIN_OUTPUTS];
     extern __shared__ __align__(16) unsigned char smem[];
     const int ldA = A.ldA;
     __bf16* buf0 = reinterpret_cast<__bf16*>(smem);
@@ -109,7 +125,23 @@ __global__ void __launch_bounds__(256) mlp_fwd_kernel(FwdArgs A) {
     const MlpLayout& G = A.G;
     const int lr = lane & 15, lk = 8 * (lane >> 4);
     // stage a_0 = bf16(x), zero padded
-    {
+    if (MODE == FWD_CHAIN) {
+        if (tid < FWD_ROWS) {
+            const int row = row0 + tid;
+            float f[LEB_CHAIN_FEATURES];
+            if (row < A.B) {
+                const int U = A.U, nx = 6 * U, nu = 2 * U, n = nx + nu;
+                const int u = row / U, i = row - u * U;
+                chain_node_features(A.cz + (int64_t)u * nx, A.cv + (int64_t)u * nu,
+                                    A.cmu ? A.cmu + (int64_t)u * n : nullptr, A.csg + (int64_t)u * n, i, U, A.L0, f);
+            } else {
+#pragma unroll
+                for (int k = 0; k < LEB_CHAIN_FEATURES; ++k) f[k] = 0.0f;
+            }
+#pragma unroll
+            for (int k = 0; k < LEB_CHAIN_FEATURES; ++k) buf0[tid * ldA + k] = (__bf16)f[k];
+        }
+    } else {
         const int d0 = G.w[0], k0 = G.kp[0];
         for (int idx = tid; idx < FWD_ROWS * k0; idx += 256) {
             const int r = idx / k0, k = idx - r * k0;
@@ -170,8 +202,13 @@ __global__ void __launch_bounds__(256) mlp_fwd_kernel(FwdArgs A) {
                 for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        const int row = row0 + rt * 16 + 4 * (lane >> 4) + i;
-                        if (row < A.B && c < nout) A.y[(int64_t)row * nout + c] = acc[s][rt][i] + bc;
+                        const int r = rt * 16 + 4 * (lane >> 4) + i;
+                        const int row = row0 + r;
+                        if (MODE == FWD_CHAIN) {
+                            if (c < LEB_CHAIN_OUTPUTS) sy[r][c] = acc[s][rt][i] + bc;
+                        } else if (row < A.B && c < nout) {
+                            A.y[(int64_t)row * nout + c] = acc[s][rt][i] + bc;
+                        }
                     }
             }
         } else {
@@ -201,6 +238,19 @@ __global__ void __launch_bounds__(256) mlp_fwd_kernel(FwdArgs A) {
         }
         __syncthreads();
         __bf16* t_ = cur; cur = nxt; nxt = t_;
+    }
+    if (MODE == FWD_CHAIN && tid < 2 * FWD_ROWS) {
+        // decode: thread (row, vx | vz) writes that row of the residual zonotope
+        const int r = tid >> 1, w = tid & 1;
+        const int row = row0 + r;
+        if (row < A.B) {
+            const int U = A.U, u = row / U, i = row - u * U;
+            double c, rad;
+            chain_decode_row(sy[r][2 * w], sy[r][2 * w + 1], &c, &rad);
+            const int64_t o = (int64_t)u * 6 * U + 6 * i + 3 + w;
+            A.cbar[o] = c;
+            A.rbar[o] = rad + A.pad;
+        }
     }
 }
 
@@ -440,15 +490,15 @@ extern "C" int leb_surrogate_create(int32_t n_layers, const int32_t* widths, con
     for (int l = 0; l < n_layers; ++l) widest = widest > G.np[l] ? widest : G.np[l];
     s->ldA = widest + 8;
     const size_t smem = 2 * (size_t)FWD_ROWS * s->ldA * sizeof(__bf16);
-    if (smem > 65536 &&
-        (hipFuncSetAttribute((const void*)mlp_fwd_kernel<2, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)smem) != hipSuccess ||
-         hipFuncSetAttribute((const void*)mlp_fwd_kernel<2, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)smem) != hipSuccess ||
-         hipFuncSetAttribute((const void*)mlp_fwd_kernel<4, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)smem) != hipSuccess ||
-         hipFuncSetAttribute((const void*)mlp_fwd_kernel<4, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)smem) != hipSuccess)) {
+    const void* fns[] = {(const void*)mlp_fwd_kernel<2, FWD_PLAIN>, (const void*)mlp_fwd_kernel<2, FWD_SAVE>,
+                         (const void*)mlp_fwd_kernel<2, FWD_CHAIN>, (const void*)mlp_fwd_kernel<4, FWD_PLAIN>,
+                         (const void*)mlp_fwd_kernel<4, FWD_SAVE>, (const void*)mlp_fwd_kernel<4, FWD_CHAIN>};
+    bool attr_ok = true;
+    if (smem > 65536)
+        for (const void* f : fns)
+            attr_ok = attr_ok &&
+                      hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) == hipSuccess;
+    if (!attr_ok) {
         delete s;
         return LEB_EDEVICE;
     }
@@ -500,23 +550,44 @@ extern "C" int leb_surrogate_dims(leb_surrogate s, int32_t* d_in, int32_t* d_out
     return LEB_OK;
 }
 
+static int fwd_dispatch(leb_surrogate_s* s, const FwdArgs& a, int mode, hipStream_t st) {
+    const size_t smem = 2 * (size_t)FWD_ROWS * s->ldA * sizeof(__bf16);
+    const dim3 g(nb(a.B, FWD_ROWS)), t(256);
+    const bool narrow = s->ldA - 8 <= 128;
+    if (narrow) {
+        if (mode == FWD_SAVE) hipLaunchKernelGGL((mlp_fwd_kernel<2, FWD_SAVE>), g, t, smem, st, a);
+        else if (mode == FWD_CHAIN) hipLaunchKernelGGL((mlp_fwd_kernel<2, FWD_CHAIN>), g, t, smem, st, a);
+        else hipLaunchKernelGGL((mlp_fwd_kernel<2, FWD_PLAIN>), g, t, smem, st, a);
+    } else {
+        if (mode == FWD_SAVE) hipLaunchKernelGGL((mlp_fwd_kernel<4, FWD_SAVE>), g, t, smem, st, a);
+        else if (mode == FWD_CHAIN) hipLaunchKernelGGL((mlp_fwd_kernel<4, FWD_CHAIN>), g, t, smem, st, a);
+        else hipLaunchKernelGGL((mlp_fwd_kernel<4, FWD_PLAIN>), g, t, smem, st, a);
+    }
+    return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
+}
+
 static int fwd_launch(leb_surrogate_s* s, int B, const float* x, float* y, bool save, hipStream_t st) {
-    FwdArgs a;
+    FwdArgs a = {};
     a.G = s->G; a.Wt = s->Wt; a.params = s->params; a.x = x; a.y = y; a.B = B;
     a.zsave = save ? s->zsave : nullptr;
     a.aT = save ? s->aT : nullptr;
     a.ldA = s->ldA;
-    const size_t smem = 2 * (size_t)FWD_ROWS * s->ldA * sizeof(__bf16);
-    const dim3 g(nb(B, FWD_ROWS)), t(256);
-    if (s->ldA - 8 <= 128) {
-        if (save) hipLaunchKernelGGL((mlp_fwd_kernel<2, true>), g, t, smem, st, a);
-        else hipLaunchKernelGGL((mlp_fwd_kernel<2, false>), g, t, smem, st, a);
-    } else {
-        if (save) hipLaunchKernelGGL((mlp_fwd_kernel<4, true>), g, t, smem, st, a);
-        else hipLaunchKernelGGL((mlp_fwd_kernel<4, false>), g, t, smem, st, a);
-    }
-    return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
+    return fwd_dispatch(s, a, save ? FWD_SAVE : FWD_PLAIN, st);
 }
+
+namespace leb {
+// One surrogate sweep over a chain tube: features -> MLP -> rows 6i+3, 6i+4 of
+// (c_bar, rho_bar) for every (unit, node); the other rows are left as they are.
+int surrogate_chain_sweep(leb_surrogate s, const double* z, const double* v, const double* mu, const double* sigma,
+                          int nodes, int U, double L0, double pad, double* cbar, double* rbar, hipStream_t st) {
+    if (s->G.w[0] != LEB_CHAIN_FEATURES || s->G.w[s->G.L] != LEB_CHAIN_OUTPUTS) return LEB_EINVAL;
+    if (nodes == 0) return LEB_OK;
+    FwdArgs a = {};
+    a.G = s->G; a.Wt = s->Wt; a.params = s->params; a.B = nodes; a.ldA = s->ldA;
+    a.cz = z; a.cv = v; a.cmu = mu; a.csg = sigma; a.cbar = cbar; a.rbar = rbar; a.U = U; a.L0 = L0; a.pad = pad;
+    return fwd_dispatch(s, a, FWD_CHAIN, st);
+}
+}  // namespace leb
 
 extern "C" int leb_mlp_fwd_bf16(leb_surrogate s, int32_t batch, const float* x, float* y, void* stream) {
     if (!s || batch < 0) return LEB_EINVAL;

@@ -23,11 +23,11 @@
 #include <mutex>
 
 #include "leb.h"
+#include "chain_features.hpp"
 #include "leb_internal.hpp"
 
 namespace leb {
 
-constexpr float DSCALE = 20.0f;      // 1 / 0.05: displacements of the tube scale to O(1)
 constexpr float LOG_FLOOR = 1e-14f;
 
 // one thread per (unit, node); rows of 32 floats written as 8 float4
@@ -37,39 +37,9 @@ __global__ void chain_features_kernel(const double* z, const double* v, const do
     if (q >= nodes) return;
     const int u = q / U, i = q - u * U;
     const int nx = 6 * U, nu = 2 * U, n = nx + nu;
-    const double* zn = z + (int64_t)u * nx;
-    const double* vn = v + (int64_t)u * nu;
-    const double* m = mu ? mu + (int64_t)u * n : nullptr;
-    const double* s = sigma + (int64_t)u * n;
-    auto dlo = [&](int c) { return (float)(fmin((m ? m[c] : 0.0) - s[c], 0.0) * DSCALE); };
-    auto dhi = [&](int c) { return (float)(fmax((m ? m[c] : 0.0) + s[c], 0.0) * DSCALE); };
     float f[LEB_CHAIN_FEATURES];
-    const int th = 6 * i + 2, px = 6 * i, pz = 6 * i + 1, u1 = nx + 2 * i, u2 = u1 + 1;
-    f[0] = (float)zn[th];
-    f[1] = (float)((vn[2 * i] + vn[2 * i + 1]) * 0.1);
-    f[2] = dlo(th); f[3] = dhi(th);
-    f[4] = dlo(u1); f[5] = dhi(u1);
-    f[6] = dlo(u2); f[7] = dhi(u2);
-    f[8] = dlo(px); f[9] = dhi(px);
-    f[10] = dlo(pz); f[11] = dhi(pz);
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-        const int j = side == 0 ? i + 1 : i - 1;      // right, then left neighbour
-        const int o = 12 + 7 * side;
-        if (j >= 0 && j < U) {
-            const int a = side == 0 ? i : j, b = side == 0 ? j : i;   // spring from node a to node b = a + 1
-            f[o] = 1.0f;
-            f[o + 1] = (float)(L0 + zn[6 * b] - zn[6 * a]);
-            f[o + 2] = (float)(zn[6 * b + 1] - zn[6 * a + 1]);
-            f[o + 3] = dlo(6 * j); f[o + 4] = dhi(6 * j);
-            f[o + 5] = dlo(6 * j + 1); f[o + 6] = dhi(6 * j + 1);
-        } else {
-#pragma unroll
-            for (int t = 0; t < 7; ++t) f[o + t] = 0.0f;
-        }
-    }
-#pragma unroll
-    for (int t = 26; t < LEB_CHAIN_FEATURES; ++t) f[t] = 0.0f;
+    chain_node_features(z + (int64_t)u * nx, v + (int64_t)u * nu, mu ? mu + (int64_t)u * n : nullptr,
+                        sigma + (int64_t)u * n, i, U, L0, f);
     float4* out = reinterpret_cast<float4*>(X + (int64_t)q * LEB_CHAIN_FEATURES);
 #pragma unroll
     for (int t = 0; t < LEB_CHAIN_FEATURES / 4; ++t) out[t] = make_float4(f[4 * t], f[4 * t + 1], f[4 * t + 2], f[4 * t + 3]);
@@ -97,14 +67,7 @@ __global__ void chain_decode_kernel(const float* Y, int64_t units, int U, double
     double c = 0.0, r = 0.0;
     if (rc == 3 || rc == 4) {
         const float* y = Y + (u * U + i) * LEB_CHAIN_OUTPUTS + 2 * (rc - 3);
-        // a prediction that is not finite counts as a zero bound (the
-        // certified iteration then starts below the fixed point); bounds
-        // above 1 are clamped
-        const double yh = isfinite(y[0]) ? fmin((double)y[0], 0.0) : -1e30;
-        const double yl = isfinite(y[1]) ? fmin((double)y[1], 0.0) : -1e30;
-        const double hi = exp(yh), lo = -exp(yl);
-        c = 0.5 * (lo + hi);
-        r = 0.5 * (hi - lo);
+        chain_decode_row(y[0], y[1], &c, &r);
     }
     cb[q] = c;
     rb[q] = r + pad;
@@ -183,6 +146,27 @@ extern "C" int leb_chain_targets(const leb_dynamics* dyn, int32_t batch, int32_t
     return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
 }
 
+extern "C" int leb_chain_surrogate_bound(const leb_dynamics* dyn, int32_t batch, int32_t N, const double* z,
+                                         const double* v, const double* mu, const double* sigma, leb_surrogate net,
+                                         double* c_bar, double* rho_bar, double pad, void* stream) {
+    int rc = check_chain_dynamics(dyn);
+    if (rc != LEB_OK) return rc;
+    if (dyn->kind != LEB_DYN_PQUAD_CHAIN || batch < 0 || N < 0 || !net || !(pad >= 0.0)) return LEB_EINVAL;
+    int32_t din = 0, dout = 0;
+    if (leb_surrogate_dims(net, &din, &dout) || din != LEB_CHAIN_FEATURES || dout != LEB_CHAIN_OUTPUTS)
+        return LEB_EINVAL;
+    const int64_t units = (int64_t)batch * N;
+    if (units == 0) return LEB_OK;
+    if (!z || !v || !sigma || !c_bar || !rho_bar) return LEB_EINVAL;
+    if (units * dyn->n_units > 0x7fffffff) return LEB_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(fill64_kernel, dim3(nbk(units * dyn->nx)), dim3(256), 0, s, c_bar, units * dyn->nx, 0.0);
+    hipLaunchKernelGGL(fill64_kernel, dim3(nbk(units * dyn->nx)), dim3(256), 0, s, rho_bar, units * dyn->nx, pad);
+    if (hipGetLastError() != hipSuccess) return LEB_EDEVICE;
+    return surrogate_chain_sweep(net, z, v, mu, sigma, (int)(units * dyn->n_units), dyn->n_units, dyn->rest_len, pad,
+                                 c_bar, rho_bar, s);
+}
+
 extern "C" int leb_fixed_point_learned(const leb_dynamics* dyn, int32_t batch, int32_t N, const double* z,
                                        const double* v, const double* phi, const double* e, const leb_fp_options* opt,
                                        const leb_warm_start* ws, double* mu, double* sigma, uint32_t* certified,
@@ -210,13 +194,12 @@ extern "C" int leb_fixed_point_learned(const leb_dynamics* dyn, int32_t batch, i
         hipLaunchKernelGGL(fill64_kernel, dim3(nbk(units * nx)), dim3(256), 0, s, g_sw.cb, units * nx, 0.0);
         hipLaunchKernelGGL(fill64_kernel, dim3(nbk(units * nx)), dim3(256), 0, s, g_sw.rb, units * nx, opt->pad);
         if ((rc = launch_tube_map(batch, N, U, phi, e, g_sw.cb, g_sw.rb, mu, sigma, s))) return rc;
-        // surrogate sweeps: C <- T(surrogate bound of C)
+        // surrogate sweeps: C <- T(surrogate bound of C); only the rows 6i+3, 6i+4 of
+        // (c_bar, rho_bar) change, the affine rows keep (0, pad)
         for (int t = 0; t < ws->sweeps; ++t) {
-            hipLaunchKernelGGL(chain_features_kernel, dim3(nbk(nodes)), dim3(256), 0, s, z, v, mu, sigma, (int)nodes,
-                               U, dyn->rest_len, g_sw.X);
-            if ((rc = leb_mlp_fwd_bf16(ws->net, (int32_t)nodes, g_sw.X, g_sw.Y, stream))) return rc;
-            hipLaunchKernelGGL(chain_decode_kernel, dim3(nbk(units * nx)), dim3(256), 0, s, g_sw.Y, units, U,
-                               opt->pad, g_sw.cb, g_sw.rb);
+            if ((rc = surrogate_chain_sweep(ws->net, z, v, mu, sigma, (int)nodes, U, dyn->rest_len, opt->pad, g_sw.cb,
+                                            g_sw.rb, s)))
+                return rc;
             if ((rc = launch_tube_map(batch, N, U, phi, e, g_sw.cb, g_sw.rb, mu, sigma, s))) return rc;
         }
         // warm start above the surrogate's fixed point

@@ -27,6 +27,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -72,9 +73,17 @@ constexpr int TM_RT = 5;        // 16-row tiles per wave and row group
 //
 // Fixed-point form: frozen trajectories are not written; containment
 // failures are or-ed into the state words (fp_state_kernel folds them).
+// row tile of slot s of a wave: tiles are dealt so that each wave gets a
+// mix of short (early steps) and long (late steps) K ranges
+__device__ __forceinline__ int tm_tile(int wave, int s, int group) {
+    const int base = group * 4 * TM_RT + 4 * s;
+    return base + ((s & 1) ? 3 - wave : wave);
+}
+
 __global__ void __launch_bounds__(256) tube_map_kernel(const double* __restrict__ phi, TubeArgs A, TubeFP P) {
-    // LDS: Phi [(N-1)*48], e[6], then the B block of this workgroup's 16
-    // columns: c [6(N-1)][16] and w [6(N-1)][16]
+    // LDS, phase 1: Phi with zero blocks at lags -4..-1 and N-1 [(N+4)*48],
+    // e[8], c [6(N-1)+8][16], w [6(N-1)+8][16] (8 zero rows past the end);
+    // phase 2 (after the contraction): mu, sigma of 8 steps [64][16] each
     extern __shared__ double sphi[];
     __shared__ uint32_t sbad[16];
     __shared__ int sjinf[16];
@@ -85,101 +94,179 @@ __global__ void __launch_bounds__(256) tube_map_kernel(const double* __restrict_
     const int N = A.N, U = A.U, nx = 6 * U, n = 8 * U;
     const int nphi = (N - 1) * 48;
     const int kfull = 6 * (N - 1);
-    double* se = sphi + nphi;
+    const int kpad = kfull + 8;
+    double* sp = sphi;                         // sp[(lag + 4) * 48 + r * 6 + q]
+    double* se = sphi + (N + 4) * 48;
     double* sc = se + 8;
-    double* sw = sc + (size_t)kfull * 16;
-    for (int idx = tid; idx < nphi; idx += 256) sphi[idx] = phi[idx];
+    double* sw = sc + (size_t)kpad * 16;
+    // Phi (8 loads in flight per thread)
+    for (int i0 = tid; i0 < (N + 4) * 48; i0 += 8 * 256) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int l48 = i0 + 256 * u - 192;            // lag * 48 + r * 6 + q
+            v[u] = (l48 >= 0 && l48 < nphi) ? phi[l48] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (i0 + 256 * u < (N + 4) * 48) sp[i0 + 256 * u] = v[u];
+    }
     if (tid < 6) se[tid] = A.e[tid];
     if (tid < 16) { sbad[tid] = 0u; sjinf[tid] = 0x7fffffff; }
     __syncthreads();
     const int cols = A.B * U;
     const int c0 = blockIdx.x * 16;
-    // stage c_bar and w = e + rho_bar + |c_bar| wid: thread (kk-chunk, column), the 6 q of one
-    // (column, step) are contiguous in HBM.  A residual that is not finite enters as 0, and
-    // every later step of its column gets sigma = +inf (a product 0 * inf with the zero
-    // entries of T would otherwise make earlier rows NaN).
-    for (int idx = tid; idx < kfull * 16; idx += 256) {
-        const int cl = idx / kfull, kk = idx - cl * kfull;
-        const int j = kk / 6, q = kk - 6 * j;
+    // stage c_bar and w = e + rho_bar + |c_bar| wid: 16 threads per column, entry
+    // kk = 6 j + q of a column at j * nx + q (6 contiguous per step), 8 loads of
+    // each in flight per thread.  A residual radius that is not finite enters as 0
+    // and every later step of its column gets sigma = +inf (a product 0 * inf with
+    // the zero entries of T would otherwise make earlier rows NaN); a centre that
+    // is not finite enters as 0 the same way.
+    {
+        const int cl = tid >> 4, sub = tid & 15;
         const int col = c0 + cl;
-        double c = 0.0, w = 0.0;
-        if (col < cols) {
-            const int bb = col / U, nd = col - bb * U;
-            const int64_t o = ((int64_t)bb * N + j) * nx + 6 * nd + q;
-            c = A.cbar[o];
-            w = se[q] + A.rbar[o] + fabs(c) * A.wid;
-            if (!(fabs(c) <= DBL_MAX && w <= DBL_MAX)) {
-                atomicMin(&sjinf[cl], j);
-                c = 0.0;
-                w = 0.0;
+        const bool cin = col < cols;
+        const int bb = cin ? col / U : 0, nd = cin ? col - bb * U : 0;
+        const double* cbp = A.cbar + (int64_t)bb * N * nx + 6 * nd;
+        const double* rbp = A.rbar + (int64_t)bb * N * nx + 6 * nd;
+        for (int k0 = sub; k0 < kpad; k0 += 8 * 16) {
+            double cv[8], rv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int kk = max(0, min(k0 + 16 * u, kfull - 1));     // a valid address; N = 1 has no entries
+                const int j = kk / 6, q = kk - 6 * j;
+                cv[u] = cin ? cbp[(int64_t)j * nx + q] : 0.0;
+                rv[u] = cin ? rbp[(int64_t)j * nx + q] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int kk = k0 + 16 * u;
+                if (kk >= kpad) break;
+                double c = 0.0, w = 0.0;
+                if (kk < kfull && cin) {
+                    const int j = kk / 6, q = kk - 6 * j;
+                    c = cv[u];
+                    const bool cfin = fabs(c) <= DBL_MAX;
+                    if (!cfin) c = 0.0;
+                    w = se[q] + rv[u] + fabs(c) * A.wid;
+                    if (!(cfin && w <= DBL_MAX)) {
+                        atomicMin(&sjinf[cl], j);
+                        w = 0.0;
+                    }
+                }
+                sc[kk * 16 + cl] = c;
+                sw[kk * 16 + cl] = w;
             }
         }
-        sc[kk * 16 + cl] = c;
-        sw[kk * 16 + cl] = w;
     }
     __syncthreads();
-    const int col = c0 + (lane & 15);
-    const bool cvalid = col < cols;
-    const int cc = cvalid ? col : cols - 1;
-    const int b = cc / U, node = cc - b * U;
-    const int bfirst = c0 / U;
     const int nrt = (N + 1) >> 1;
-    int kmax[TM_RT];
-    int kw = 0;
+    const int lr = lane & 15, lq = lane >> 4;
+    int kmax[TM_RT], abase[TM_RT];
 #pragma unroll
     for (int s = 0; s < TM_RT; ++s) {
-        const int rt = wave + 4 * (blockIdx.y * TM_RT + s);
+        const int rt = tm_tile(wave, s, blockIdx.y);
         kmax[s] = rt < nrt ? 6 * min(N - 1, 2 * rt + 1) : 0;
-        kw = max(kw, kmax[s]);
+        const int r = 16 * rt + lr, k = r >> 3, rr = r & 7;
+        // A[(k, rr)][(j, q)] = Phi_{k-j-1}[rr][q] at sp[(k - j + 3) * 48 + rr * 6 + q]
+        abase[s] = (k + 3) * 48 + rr * 6;
     }
     d4 am[TM_RT], as[TM_RT];
-#pragma unroll
-    for (int s = 0; s < TM_RT; ++s) { am[s] = d4{0.0, 0.0, 0.0, 0.0}; as[s] = d4{0.0, 0.0, 0.0, 0.0}; }
-    const int lr = lane & 15, lq = lane >> 4;
-    for (int k0 = 0; k0 < kw; k0 += 4) {
-        const int kk = k0 + lq;
-        const int j = kk / 6, q = kk - 6 * j;
-        const bool kin = kk < kfull;
-        const double c = kin ? sc[kk * 16 + lr] : 0.0;
-        const double w = kin ? sw[kk * 16 + lr] : 0.0;
-#pragma unroll
-        for (int s = 0; s < TM_RT; ++s) {
-            if (k0 >= kmax[s]) continue;       // wave-uniform
-            const int rt = wave + 4 * (blockIdx.y * TM_RT + s);
-            const int r = 16 * rt + lr, k = r >> 3, rr = r & 7;
-            const int lag = k - j - 1;
-            const double a = (lag >= 0 && lag < N - 1 && kin) ? sphi[lag * 48 + rr * 6 + q] : 0.0;
-            am[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, c, am[s], 0, 0, 0);
-            as[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(fabs(a), w, as[s], 0, 0, 0);
-        }
-    }
-    const int jinf = sjinf[lr];
-    const bool frozen = fp && (P.state[b] & FP_CERT);
-    bool bad = false;
+    // one K loop per slot, two K steps per iteration into separate accumulators
+    // (four independent MFMA chains); the zero padding of Phi (lags down to -4)
+    // and of the B block (8 rows) covers the reads past a tile's range.
+    // kk = k0 + lq = 6 j + q, and the A offset of kk is abase - (48 j - q).
 #pragma unroll
     for (int s = 0; s < TM_RT; ++s) {
-        const int rt = wave + 4 * (blockIdx.y * TM_RT + s);
-        if (rt >= nrt) continue;
+        d4 m0 = d4{0.0, 0.0, 0.0, 0.0}, v0 = m0, m1 = m0, v1 = m0;
+        int j = 0, q = lq;                     // entry kk
+        int j2 = (lq + 4) / 6, q2 = lq + 4 - 6 * ((lq + 4) / 6);   // entry kk + 4
+        for (int k0 = 0; k0 < kmax[s]; k0 += 8) {
+            const int kk = k0 + lq;
+            const double c0v = sc[kk * 16 + lr], w0v = sw[kk * 16 + lr];
+            const double c1v = sc[(kk + 4) * 16 + lr], w1v = sw[(kk + 4) * 16 + lr];
+            const double a0 = sp[abase[s] - (48 * j - q)];
+            const double a1 = sp[abase[s] - (48 * j2 - q2)];
+            m0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, c0v, m0, 0, 0, 0);
+            v0 = __builtin_amdgcn_mfma_f64_16x16x4f64(fabs(a0), w0v, v0, 0, 0, 0);
+            m1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, c1v, m1, 0, 0, 0);
+            v1 = __builtin_amdgcn_mfma_f64_16x16x4f64(fabs(a1), w1v, v1, 0, 0, 0);
+            // kk += 8: q += 2 with a carry into j, for both entries
+            q += 2; j += 1; if (q >= 6) { q -= 6; ++j; }
+            q2 += 2; j2 += 1; if (q2 >= 6) { q2 -= 6; ++j2; }
+        }
+        am[s] = m0 + m1;
+        as[s] = v0 + v1;
+    }
+    // phase 2, one slot at a time: the slot-s tiles of the four waves are four
+    // consecutive row tiles (8 steps); they go through LDS ([row][column]) so
+    // that the tube is read (containment) and written with coalesced accesses
+    double* om = sphi;
+    double* os = sphi + 64 * 16;
+    const int ncol = min(16, cols - c0);
+    const int bfirst = c0 / U;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int r = 16 * rt + 4 * i + lq, k = r >> 3, rr = r & 7;
-            if (k >= N || !cvalid) continue;
-            const int64_t o = ((int64_t)b * N + k) * n + (rr < 6 ? 6 * node + rr : nx + 2 * node + (rr - 6));
+    for (int s = 0; s < TM_RT; ++s) {
+        const int base = blockIdx.y * 4 * TM_RT + 4 * s;      // first tile of the slot
+        if (base >= nrt) break;                                // uniform over the workgroup
+        __syncthreads();
+        const int rt = tm_tile(wave, s, blockIdx.y);
+        if (rt < nrt) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 16 * (rt - base) + 4 * i + lq;   // row within the slot: (k, row) = (r >> 3, r & 7)
+                om[r * 16 + lr] = am[s][i];
+                os[r * 16 + lr] = as[s][i];
+            }
+        }
+        __syncthreads();
+        const int k0s = 2 * base;
+        const int nk = min(8, N - k0s);
+        // thread -> (step within the slot, column, row); 8 x 16 x 8 = 1024 entries, 4 per
+        // thread with their tube loads in flight together
+        int64_t off[4];
+        bool live[4];
+        int kl4[4], cl4[4], rr4[4], b4[4];
+        double mi4[4], si4[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int idx = tid + 256 * u;
+            const int kl = idx >> 7, rem = idx & 127;
+            const bool st = rem < 96;                               // 6 state rows per node, contiguous
+            const int cl = st ? (rem * 43) >> 8 : (rem - 96) >> 1;  // rem / 6 for rem < 96
+            const int rr = st ? rem - cl * 6 : 6 + ((rem - 96) & 1);
+            live[u] = kl < nk && cl < ncol;
+            const int col = min(c0 + cl, cols - 1);
+            const int bb = col / U, nd = col - bb * U;
+            const int k = min(k0s + kl, N - 1);
+            off[u] = ((int64_t)bb * N + k) * n + (rr < 6 ? 6 * nd + rr : nx + 2 * nd + (rr - 6));
+            kl4[u] = kl; cl4[u] = cl; rr4[u] = rr; b4[u] = bb;
+            mi4[u] = fp ? P.mu_in[off[u]] : 0.0;
+            si4[u] = fp ? P.sg_in[off[u]] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (!live[u]) continue;
+            const int kl = kl4[u], cl = cl4[u], rr = rr4[u], bb = b4[u];
+            const int k = k0s + kl;
+            const double mF = om[(kl * 8 + rr) * 16 + cl];
+            const double acc = os[(kl * 8 + rr) * 16 + cl];
             // sums of nonnegative terms, rounded upward; 2^-1000 covers any flushed subnormal part
-            const double sF = k > jinf ? INFINITY : as[s][i] + as[s][i] * A.wid + 0x1p-1000, mF = am[s][i];
+            const double sF = k > sjinf[cl] ? INFINITY : acc + acc * A.wid + 0x1p-1000;
             double so = sF;
+            bool frozen = false;
             if (fp) {
-                const double mi = P.mu_in[o], si = P.sg_in[o];
-                // [mF - sF, mF + sF] inside [mi - si, mi + si], with the rounding of the test
-                // covered; a tube that is not finite is never accepted
-                bad |= !(sF <= DBL_MAX && (fabs(mF - mi) + sF) * (1.0 + 0x1p-50) <= si);
+                frozen = (P.state[bb] & FP_CERT) != 0u;
+                // [mF - sF, mF + sF] inside [mi - si, mi + si], with the rounding of the
+                // test covered; a tube that is not finite is never accepted
+                if (!frozen && !(sF <= DBL_MAX && (fabs(mF - mi4[u]) + sF) * (1.0 + 0x1p-50) <= si4[u]))
+                    sbad[bb - bfirst] = 1u;
                 so = sF + sF * P.tol + P.abs_;
             }
-            if (!frozen) { A.mu[o] = mF; A.sigma[o] = so; }
+            if (!frozen) { A.mu[off[u]] = mF; A.sigma[off[u]] = so; }
         }
     }
     if (!fp) return;
-    if (bad && !frozen) sbad[b - bfirst] = 1u;
     __syncthreads();
     if (tid < 16 && sbad[tid] && bfirst + tid < A.B) atomicOr(&P.state[bfirst + tid], FP_OPEN);
 }
@@ -258,9 +345,10 @@ static int launch_tube(int B, int N, int U, const double* phi, const double* e, 
     const int nrt = (N + 1) / 2;
     const int gy = (nrt + 4 * TM_RT - 1) / (4 * TM_RT);
     if (gx > 0x7fffffff || (int64_t)cols > 0x7fffffff) return LEB_EINVAL;
-    // Phi, e (padded to 8) and the B block (c and w for 16 columns)
+    // Phi, e (padded to 8) and the B block (c and w for 16 columns); later the
+    // output of 8 steps (mu and sigma, 64 rows x 16 columns)
     const size_t nm1 = N > 1 ? N - 1 : 0;
-    const size_t smem = (nm1 * 48 + 8 + 2 * 6 * nm1 * 16) * sizeof(double);
+    const size_t smem = std::max((size_t)(N + 4) * 48 + 8 + 2 * (6 * nm1 + 8) * 16, (size_t)2 * 64 * 16) * sizeof(double);
     if (smem > 160 * 1024 - 256) return LEB_ENOTSUP;     // N <= 86
     static bool lds_attr = false;      // the kernel may use up to 160 KB of LDS (set once)
     if (smem > 65536 && !lds_attr) {
