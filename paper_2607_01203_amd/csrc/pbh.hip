@@ -104,33 +104,65 @@ __global__ void __launch_bounds__(PBH_BLOCK) pbh_chain_fwd(ChainArgs A) {
     for (int i = tid; i < T; i += PBH_BLOCK) s_flag[i] = 0u;
     __syncthreads();
 
-    // ---- stage inputs (coalesced)
-    for (int idx = tid; idx < nloc * nx; idx += PBH_BLOCK) {
-        int lt = idx / nx, c = idx - lt * nx;
-        double x = Z[idx];
-        if (!isfinite(x)) atomicOr(&s_flag[lt], LEB_FLAG_BAD_INPUT);
-        s_nom[lt * n + c] = x;
+    // ---- stage inputs (coalesced, 8 loads in flight per thread)
+    for (int i0 = tid; i0 < nloc * nx; i0 += 8 * PBH_BLOCK) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = i0 + u * PBH_BLOCK;
+            x[u] = idx < nloc * nx ? Z[idx] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = i0 + u * PBH_BLOCK;
+            if (idx >= nloc * nx) break;
+            const int lt = idx / nx, c = idx - lt * nx;
+            if (!isfinite(x[u])) atomicOr(&s_flag[lt], LEB_FLAG_BAD_INPUT);
+            s_nom[lt * n + c] = x[u];
+        }
     }
-    for (int idx = tid; idx < nloc * nu; idx += PBH_BLOCK) {
-        int lt = idx / nu, c = idx - lt * nu;
-        double x = V[idx];
-        if (!isfinite(x)) atomicOr(&s_flag[lt], LEB_FLAG_BAD_INPUT);
-        s_nom[lt * n + nx + c] = x;
+    for (int i0 = tid; i0 < nloc * nu; i0 += 8 * PBH_BLOCK) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = i0 + u * PBH_BLOCK;
+            x[u] = idx < nloc * nu ? V[idx] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = i0 + u * PBH_BLOCK;
+            if (idx >= nloc * nu) break;
+            const int lt = idx / nu, c = idx - lt * nu;
+            if (!isfinite(x[u])) atomicOr(&s_flag[lt], LEB_FLAG_BAD_INPUT);
+            s_nom[lt * n + nx + c] = x[u];
+        }
     }
-    for (int idx = tid; idx < nloc * n; idx += PBH_BLOCK) {
-        int lt = idx / n;
-        double sg = SG[idx];
-        double m = MU ? MU[idx] : 0.0;
-        uint32_t f = 0;
-        if (!isfinite(sg) || !isfinite(m) || !(sg >= 0.0)) f |= LEB_FLAG_BAD_INPUT;
-        if (fabs(m) > sg) f |= LEB_FLAG_HULL_EXTENDED;
-        if (f) atomicOr(&s_flag[lt], f);
-        // Delta = [min(mu - sigma, 0), max(mu + sigma, 0)]; the FP64
-        // difference is widened by its rounding bound (exact zeros stay 0).
-        double l = m - sg, h = m + sg;
-        l = l - fabs(l) * 0x1p-52;
-        h = h + fabs(h) * 0x1p-52;
-        s_d[idx] = iv(rd32(fmin(l, 0.0)), ru32(fmax(h, 0.0)));
+    for (int i0 = tid; i0 < nloc * n; i0 += 8 * PBH_BLOCK) {
+        double sgv[8], mv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = i0 + u * PBH_BLOCK;
+            const bool in = idx < nloc * n;
+            sgv[u] = in ? SG[idx] : 0.0;
+            mv[u] = (in && MU) ? MU[idx] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = i0 + u * PBH_BLOCK;
+            if (idx >= nloc * n) break;
+            const int lt = idx / n;
+            const double sg = sgv[u], m = mv[u];
+            uint32_t f = 0;
+            if (!isfinite(sg) || !isfinite(m) || !(sg >= 0.0)) f |= LEB_FLAG_BAD_INPUT;
+            if (fabs(m) > sg) f |= LEB_FLAG_HULL_EXTENDED;
+            if (f) atomicOr(&s_flag[lt], f);
+            // Delta = [min(mu - sigma, 0), max(mu + sigma, 0)]; the FP64
+            // difference is widened by its rounding bound (exact zeros stay 0).
+            double l = m - sg, h = m + sg;
+            l = l - fabs(l) * 0x1p-52;
+            h = h + fabs(h) * 0x1p-52;
+            s_d[idx] = iv(rd32(fmin(l, 0.0)), ru32(fmax(h, 0.0)));
+        }
     }
     __syncthreads();
 
