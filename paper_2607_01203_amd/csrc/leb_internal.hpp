@@ -29,6 +29,9 @@ size_t pbh_smem_bytes(int U);
 size_t bwd_smem_bytes(int U);
 int launch_tube_map(int B, int N, int U, const double* phi, const double* e, const double* cbar,
                     const double* rbar, double* mu, double* sigma, hipStream_t s);
+// tube of the residual zonotopes (0, pad) at every step (the disturbance-only tube)
+int launch_disturbance_tube(int B, int N, int U, const double* phi, const double* e, double pad, double* mu,
+                            double* sigma, hipStream_t s);
 
 // ReLU-MLP bound with caller-provided work buffers
 constexpr int NN_NBUF = 21;
@@ -38,7 +41,7 @@ int nn_bound_run(const leb_mlp_s* net, int64_t units, const double* z, const dou
                  uint32_t* flags, int CB, double* const* buf, hipStream_t st);
 void nn_dims(const leb_mlp_s* net, int* nx, int* nu, int* m);
 
-// one surrogate sweep over a chain tube (features -> BF16 MLP -> residual zonotope rows 6i+3, 6i+4)
+// one surrogate sweep over a chain tube (features -> BF16 MLP -> residual zonotope, all rows)
 int surrogate_chain_sweep(leb_surrogate s, const double* z, const double* v, const double* mu, const double* sigma,
                           int nodes, int U, double L0, double pad, double* cbar, double* rbar, hipStream_t st);
 

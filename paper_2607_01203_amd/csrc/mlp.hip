@@ -34,10 +34,15 @@ namespace leb {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 constexpr int MLP_MAX_LAYERS = 8;
 constexpr int MLP_MAX_WIDTH = 256;
 constexpr int FWD_ROWS = 64;            // rows (samples) per forward workgroup
+// LDS row stride (BF16) of the forward activation tile: the widest layer the
+// variant serves (128 or 256) + 8, which skews the rows over the banks
+constexpr int fwd_lda(int ct) { return ct == 2 ? 136 : 264; }
+constexpr size_t fwd_smem(int ct) { return 2 * (size_t)FWD_ROWS * fwd_lda(ct) * 2; }
 
 // Standard normal CDF Phi(z) = (1 + erf(z / sqrt 2)) / 2 and exp(-z^2 / 2),
 // with erf from Abramowitz and Stegun, Handbook of Mathematical Functions,
@@ -89,7 +94,6 @@ struct FwdArgs {
     float* zsave;             // optional [L-1][B][np]   pre-activations
     __bf16* aT;               // optional [L][MAX_WIDTH][B]  a_l^T for l = 0..L-1
     int B;
-    int ldA;                  // LDS row stride (BF16): widest padded layer + 8
     // chain surrogate sweep (FWD_CHAIN): rows are (unit, node) of a chain tube
     const double *cz, *cv, *cmu, *csg;
     double *cbar, *rbar;      // rows 6i+3, 6i+4 of every unit written
@@ -100,12 +104,16 @@ struct FwdArgs {
 enum { FWD_PLAIN = 0, FWD_SAVE = 1, FWD_CHAIN = 2 };
 
 // One workgroup (4 waves) carries 64 rows through every layer.  The
-// activation tile lives in LDS ([64][ldA] BF16, ldA = widest padded layer
-// + 8, the pad skews banks); weight fragments are read from global memory
-// (L2-resident).  Wave w owns the 16-column output tiles w, w+4, ..., up to
-// CT of them, over all four 16-row tiles.  The loads of a k-step are
-// issued together and unconditionally (a slot beyond the layer's width
-// reads a valid tile and is never stored), so no MFMA waits on a branch.
+// activation tile lives in LDS ([64][ldA] BF16, ldA = fwd_lda(CT)); weight
+// fragments are read from global memory (L2-resident).  Wave w owns the
+// 16-feature output tiles w, w+4, ..., up to CT of them, over all four
+// 16-row tiles.  The MFMA computes the transposed tile, D = W~ a^T (weights
+// as the A operand, activations as B), so each lane ends with 4
+// consecutive features of one row: the epilogue writes 8 bytes per lane
+// and tile.  The accumulators start at the bias; padded weight rows and
+// biases are zero, so padded features come out as gelu(0) = 0 without a
+// test.  The next layer's first weight chunk and bias are in flight during
+// each epilogue.
 //
 // FWD_CHAIN: the rows are the nodes of a chain tube; the inputs are the
 // chain surrogate's features, computed in the staging step, and the output
@@ -114,16 +122,44 @@ enum { FWD_PLAIN = 0, FWD_SAVE = 1, FWD_CHAIN = 2 };
 template <int CT, int MODE>
 __global__ void __launch_bounds__(256) mlp_fwd_kernel(FwdArgs A) {
     constexpr bool SAVE = MODE == FWD_SAVE;
-    __shared__ float sy[FWD_ROWS][LEB_CHAIN_OUTPUTS];
+    __shared__ __align__(16) float sy[FWD_ROWS][LEB_CHAIN_OUTPUTS];
     extern __shared__ __align__(16) unsigned char smem[];
-    const int ldA = A.ldA;
+    constexpr int ldA = fwd_lda(CT);
     __bf16* buf0 = reinterpret_cast<__bf16*>(smem);
     __bf16* buf1 = buf0 + FWD_ROWS * ldA;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int row0 = blockIdx.x * FWD_ROWS;
     const MlpLayout& G = A.G;
-    const int lr = lane & 15, lk = 8 * (lane >> 4);
+    const int lr = lane & 15, lk = 8 * (lane >> 4), lf = 4 * (lane >> 4);
+    // k-steps of 32 per weight chunk (registers: KS * CT fragments)
+    constexpr int KS = CT == 2 ? 4 : 2;
+    // weight fragments of chunk kc of layer l (and, for kc = 0, the bias of
+    // the 4 features each lane accumulates in each slot)
+    auto fetch = [&](int l, int kc, bf16x8 (&bb)[KS][CT], f32x4 (&bias_r)[CT]) {
+        const int kp = G.kp[l], nout = G.w[l + 1];
+        const int ntc = (l == G.L - 1) ? (nout + 15) / 16 : G.np[l] / 16;
+        const int ns = __builtin_amdgcn_readfirstlane((ntc - wave + 3) >> 2);
+        const __bf16* W = A.Wt + G.woff[l];
+        const float* bias = A.params + G.poff[l] + (int64_t)nout * G.w[l];
+#pragma unroll
+        for (int s = 0; s < CT; ++s) {
+            if (s >= ns) continue;
+            const int ct = wave + 4 * s;
+            const __bf16* wr = W + (int64_t)(ct * 16 + lr) * kp + lk + kc;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+                if (kc + 32 * ks < kp) bb[ks][s] = *reinterpret_cast<const bf16x8*>(wr + 32 * ks);
+            if (kc == 0) {
+                const int c = ct * 16 + lf;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) bias_r[s][i] = c + i < nout ? bias[c + i] : 0.0f;
+            }
+        }
+    };
+    bf16x8 b[KS][CT];
+    f32x4 bnext[CT];
+    fetch(0, 0, b, bnext);
     // stage a_0 = bf16(x), zero padded
     if (MODE == FWD_CHAIN) {
         if (tid < FWD_ROWS) {
@@ -139,7 +175,12 @@ __global__ void __launch_bounds__(256) mlp_fwd_kernel(FwdArgs A) {
                 for (int k = 0; k < LEB_CHAIN_FEATURES; ++k) f[k] = 0.0f;
             }
 #pragma unroll
-            for (int k = 0; k < LEB_CHAIN_FEATURES; ++k) buf0[tid * ldA + k] = (__bf16)f[k];
+            for (int k = 0; k < LEB_CHAIN_FEATURES; k += 8) {
+                bf16x8 v;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) v[j] = (__bf16)f[k + j];
+                *reinterpret_cast<bf16x8*>(buf0 + tid * ldA + k) = v;
+            }
         }
     } else {
         const int d0 = G.w[0], k0 = G.kp[0];
@@ -156,98 +197,95 @@ __global__ void __launch_bounds__(256) mlp_fwd_kernel(FwdArgs A) {
     __bf16* cur = buf0;
     __bf16* nxt = buf1;
     for (int l = 0; l < G.L; ++l) {
-        const int kp = G.kp[l], np = G.np[l], nout = G.w[l + 1];
+        const int kp = G.kp[l], nout = G.w[l + 1];
         const bool last = (l == G.L - 1);
-        const __bf16* W = A.Wt + G.woff[l];
-        const float* bias = A.params + G.poff[l] + (int64_t)nout * G.w[l];
-        // column tiles of this layer (the output layer stops at its true width)
-        const int ntc = last ? (nout + 15) / 16 : np / 16;
+        // feature tiles of this layer (the output layer stops at its true width)
+        const int ntc = last ? (nout + 15) / 16 : G.np[l] / 16;
         const int ns = __builtin_amdgcn_readfirstlane((ntc - wave + 3) >> 2);   // slots of this wave (may be <= 0)
         f32x4 acc[CT][4];
 #pragma unroll
         for (int s = 0; s < CT; ++s)
 #pragma unroll
-            for (int rt = 0; rt < 4; ++rt) acc[s][rt] = f32x4{0.f, 0.f, 0.f, 0.f};
-        const __bf16* wrow[CT];
-#pragma unroll
-        for (int s = 0; s < CT; ++s) {
-            const int ct = min(wave + 4 * s, ntc - 1);
-            wrow[s] = W + (int64_t)(ct * 16 + lr) * kp + lk;
-        }
+            for (int rt = 0; rt < 4; ++rt) acc[s][rt] = bnext[s];
         if (ns > 0) {
-            for (int k = 0; k < kp; k += 32) {
-                bf16x8 a[4], b[CT];
+            // the first chunk was fetched before the previous layer's epilogue
+            for (int kc = 0; kc < kp; kc += 32 * KS) {
+                if (kc > 0) fetch(l, kc, b, bnext);
 #pragma unroll
-                for (int s = 0; s < CT; ++s)
-                    if (s < ns) b[s] = *reinterpret_cast<const bf16x8*>(wrow[s] + k);
+                for (int ks = 0; ks < KS; ++ks) {
+                    const int k = kc + 32 * ks;
+                    if (k >= kp) break;
+                    bf16x8 a[4];
 #pragma unroll
-                for (int rt = 0; rt < 4; ++rt)
-                    a[rt] = *reinterpret_cast<const bf16x8*>(cur + (rt * 16 + lr) * ldA + k + lk);
+                    for (int rt = 0; rt < 4; ++rt)
+                        a[rt] = *reinterpret_cast<const bf16x8*>(cur + (rt * 16 + lr) * ldA + k + lk);
 #pragma unroll
-                for (int s = 0; s < CT; ++s)
-                    if (s < ns)
+                    for (int s = 0; s < CT; ++s)
+                        if (s < ns)
 #pragma unroll
-                        for (int rt = 0; rt < 4; ++rt)
-                            acc[s][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rt], b[s], acc[s][rt], 0, 0, 0);
+                            for (int rt = 0; rt < 4; ++rt)
+                                acc[s][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[ks][s], a[rt], acc[s][rt], 0, 0, 0);
+                }
             }
         }
-        // epilogue
+        // next layer's first weight chunk and bias, in flight during this epilogue
+        if (!last) fetch(l + 1, 0, b, bnext);
+        // lane holds pre-activations of features c..c+3 of row rt * 16 + lr
         if (last) {
 #pragma unroll
             for (int s = 0; s < CT; ++s) {
                 if (s >= ns) continue;
-                const int c = (wave + 4 * s) * 16 + lr;
-                const float bc = c < nout ? bias[c] : 0.0f;
+                const int c = (wave + 4 * s) * 16 + lf;
 #pragma unroll
-                for (int rt = 0; rt < 4; ++rt)
+                for (int rt = 0; rt < 4; ++rt) {
+                    const int r = rt * 16 + lr;
+                    const int row = row0 + r;
+                    if (MODE == FWD_CHAIN) {
+                        if (c == 0) *reinterpret_cast<f32x4*>(&sy[r][0]) = acc[s][rt];
+                    } else if (row < A.B) {
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int r = rt * 16 + 4 * (lane >> 4) + i;
-                        const int row = row0 + r;
-                        if (MODE == FWD_CHAIN) {
-                            if (c < LEB_CHAIN_OUTPUTS) sy[r][c] = acc[s][rt][i] + bc;
-                        } else if (row < A.B && c < nout) {
-                            A.y[(int64_t)row * nout + c] = acc[s][rt][i] + bc;
-                        }
+                        for (int i = 0; i < 4; ++i)
+                            if (c + i < nout) A.y[(int64_t)row * nout + c + i] = acc[s][rt][i];
                     }
+                }
             }
         } else {
 #pragma unroll
             for (int s = 0; s < CT; ++s) {
                 if (s >= ns) continue;
-                const int c = (wave + 4 * s) * 16 + lr;
-                const bool cin = c < nout;
-                const float bc = cin ? bias[c] : 0.0f;
+                const int c = (wave + 4 * s) * 16 + lf;
 #pragma unroll
-                for (int rt = 0; rt < 4; ++rt)
+                for (int rt = 0; rt < 4; ++rt) {
+                    const int r = rt * 16 + lr;
+                    bf16x4 av;
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int r = rt * 16 + 4 * (lane >> 4) + i;
-                        const float z = acc[s][rt][i] + bc;
-                        const __bf16 av = (__bf16)(cin ? gelu_f(z) : 0.0f);
-                        nxt[r * ldA + c] = av;
-                        if (SAVE) {
-                            const int row = row0 + r;
-                            if (row < A.B) {
-                                A.zsave[((int64_t)l * A.B + row) * MLP_MAX_WIDTH + c] = cin ? z : 0.0f;
-                                A.aT[((int64_t)(l + 1) * MLP_MAX_WIDTH + c) * A.B + row] = av;
-                            }
+                    for (int i = 0; i < 4; ++i) av[i] = (__bf16)gelu_f(acc[s][rt][i]);
+                    *reinterpret_cast<bf16x4*>(nxt + r * ldA + c) = av;
+                    if (SAVE) {
+                        const int row = row0 + r;
+                        if (row < A.B) {
+                            *reinterpret_cast<f32x4*>(A.zsave + ((int64_t)l * A.B + row) * MLP_MAX_WIDTH + c) = acc[s][rt];
+#pragma unroll
+                            for (int i = 0; i < 4; ++i)
+                                A.aT[((int64_t)(l + 1) * MLP_MAX_WIDTH + c + i) * A.B + row] = av[i];
                         }
                     }
+                }
             }
         }
         __syncthreads();
         __bf16* t_ = cur; cur = nxt; nxt = t_;
     }
-    if (MODE == FWD_CHAIN && tid < 2 * FWD_ROWS) {
-        // decode: thread (row, vx | vz) writes that row of the residual zonotope
-        const int r = tid >> 1, w = tid & 1;
-        const int row = row0 + r;
-        if (row < A.B) {
+    if (MODE == FWD_CHAIN) {
+        // decode: the 6 residual rows of each node, (0, pad) on the affine rows
+        for (int idx = tid; idx < 6 * FWD_ROWS; idx += 256) {
+            const int r = idx / 6, rc = idx - 6 * r;
+            const int row = row0 + r;
+            if (row >= A.B) continue;
             const int U = A.U, u = row / U, i = row - u * U;
-            double c, rad;
-            chain_decode_row(sy[r][2 * w], sy[r][2 * w + 1], &c, &rad);
-            const int64_t o = (int64_t)u * 6 * U + 6 * i + 3 + w;
+            double c = 0.0, rad = 0.0;
+            if (rc == 3 || rc == 4) chain_decode_row(sy[r][2 * (rc - 3)], sy[r][2 * (rc - 3) + 1], &c, &rad);
+            const int64_t o = (int64_t)u * 6 * U + 6 * i + rc;
             A.cbar[o] = c;
             A.rbar[o] = rad + A.pad;
         }
@@ -416,7 +454,7 @@ using namespace leb;
 
 struct leb_surrogate_s {
     MlpLayout G;
-    int ldA = 0;               // forward LDS row stride
+    bool narrow = true;        // every layer at most 128 wide: the CT = 2 forward variants
     float* params = nullptr;   // device FP32, flat
     float* m = nullptr;
     float* v = nullptr;
@@ -488,8 +526,8 @@ extern "C" int leb_surrogate_create(int32_t n_layers, const int32_t* widths, con
     int widest = 0;
     for (int l = 0; l < n_layers; ++l) widest = widest > G.kp[l] ? widest : G.kp[l];
     for (int l = 0; l < n_layers; ++l) widest = widest > G.np[l] ? widest : G.np[l];
-    s->ldA = widest + 8;
-    const size_t smem = 2 * (size_t)FWD_ROWS * s->ldA * sizeof(__bf16);
+    s->narrow = widest <= 128;
+    const size_t smem = fwd_smem(s->narrow ? 2 : 4);
     const void* fns[] = {(const void*)mlp_fwd_kernel<2, FWD_PLAIN>, (const void*)mlp_fwd_kernel<2, FWD_SAVE>,
                          (const void*)mlp_fwd_kernel<2, FWD_CHAIN>, (const void*)mlp_fwd_kernel<4, FWD_PLAIN>,
                          (const void*)mlp_fwd_kernel<4, FWD_SAVE>, (const void*)mlp_fwd_kernel<4, FWD_CHAIN>};
@@ -551,10 +589,9 @@ extern "C" int leb_surrogate_dims(leb_surrogate s, int32_t* d_in, int32_t* d_out
 }
 
 static int fwd_dispatch(leb_surrogate_s* s, const FwdArgs& a, int mode, hipStream_t st) {
-    const size_t smem = 2 * (size_t)FWD_ROWS * s->ldA * sizeof(__bf16);
+    const size_t smem = fwd_smem(s->narrow ? 2 : 4);
     const dim3 g(nb(a.B, FWD_ROWS)), t(256);
-    const bool narrow = s->ldA - 8 <= 128;
-    if (narrow) {
+    if (s->narrow) {
         if (mode == FWD_SAVE) hipLaunchKernelGGL((mlp_fwd_kernel<2, FWD_SAVE>), g, t, smem, st, a);
         else if (mode == FWD_CHAIN) hipLaunchKernelGGL((mlp_fwd_kernel<2, FWD_CHAIN>), g, t, smem, st, a);
         else hipLaunchKernelGGL((mlp_fwd_kernel<2, FWD_PLAIN>), g, t, smem, st, a);
@@ -571,19 +608,18 @@ static int fwd_launch(leb_surrogate_s* s, int B, const float* x, float* y, bool 
     a.G = s->G; a.Wt = s->Wt; a.params = s->params; a.x = x; a.y = y; a.B = B;
     a.zsave = save ? s->zsave : nullptr;
     a.aT = save ? s->aT : nullptr;
-    a.ldA = s->ldA;
     return fwd_dispatch(s, a, save ? FWD_SAVE : FWD_PLAIN, st);
 }
 
 namespace leb {
-// One surrogate sweep over a chain tube: features -> MLP -> rows 6i+3, 6i+4 of
-// (c_bar, rho_bar) for every (unit, node); the other rows are left as they are.
+// One surrogate sweep over a chain tube: features -> MLP -> (c_bar, rho_bar) for
+// every (unit, node): the decoded bound on rows 6i+3, 6i+4, (0, pad) elsewhere.
 int surrogate_chain_sweep(leb_surrogate s, const double* z, const double* v, const double* mu, const double* sigma,
                           int nodes, int U, double L0, double pad, double* cbar, double* rbar, hipStream_t st) {
     if (s->G.w[0] != LEB_CHAIN_FEATURES || s->G.w[s->G.L] != LEB_CHAIN_OUTPUTS) return LEB_EINVAL;
     if (nodes == 0) return LEB_OK;
     FwdArgs a = {};
-    a.G = s->G; a.Wt = s->Wt; a.params = s->params; a.B = nodes; a.ldA = s->ldA;
+    a.G = s->G; a.Wt = s->Wt; a.params = s->params; a.B = nodes;
     a.cz = z; a.cv = v; a.cmu = mu; a.csg = sigma; a.cbar = cbar; a.rbar = rbar; a.U = U; a.L0 = L0; a.pad = pad;
     return fwd_dispatch(s, a, FWD_CHAIN, st);
 }

@@ -160,9 +160,6 @@ extern "C" int leb_chain_surrogate_bound(const leb_dynamics* dyn, int32_t batch,
     if (!z || !v || !sigma || !c_bar || !rho_bar) return LEB_EINVAL;
     if (units * dyn->n_units > 0x7fffffff) return LEB_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(fill64_kernel, dim3(nbk(units * dyn->nx)), dim3(256), 0, s, c_bar, units * dyn->nx, 0.0);
-    hipLaunchKernelGGL(fill64_kernel, dim3(nbk(units * dyn->nx)), dim3(256), 0, s, rho_bar, units * dyn->nx, pad);
-    if (hipGetLastError() != hipSuccess) return LEB_EDEVICE;
     return surrogate_chain_sweep(net, z, v, mu, sigma, (int)(units * dyn->n_units), dyn->n_units, dyn->rest_len, pad,
                                  c_bar, rho_bar, s);
 }
@@ -191,11 +188,8 @@ extern "C" int leb_fixed_point_learned(const leb_dynamics* dyn, int32_t batch, i
         std::lock_guard<std::mutex> lock(g_sw.mu);
         if ((rc = sw_get(nodes, units * nx))) return rc;
         // C_0: disturbance-only tube
-        hipLaunchKernelGGL(fill64_kernel, dim3(nbk(units * nx)), dim3(256), 0, s, g_sw.cb, units * nx, 0.0);
-        hipLaunchKernelGGL(fill64_kernel, dim3(nbk(units * nx)), dim3(256), 0, s, g_sw.rb, units * nx, opt->pad);
-        if ((rc = launch_tube_map(batch, N, U, phi, e, g_sw.cb, g_sw.rb, mu, sigma, s))) return rc;
-        // surrogate sweeps: C <- T(surrogate bound of C); only the rows 6i+3, 6i+4 of
-        // (c_bar, rho_bar) change, the affine rows keep (0, pad)
+        if ((rc = launch_disturbance_tube(batch, N, U, phi, e, opt->pad, mu, sigma, s))) return rc;
+        // surrogate sweeps: C <- T(surrogate bound of C)
         for (int t = 0; t < ws->sweeps; ++t) {
             if ((rc = surrogate_chain_sweep(ws->net, z, v, mu, sigma, (int)nodes, U, dyn->rest_len, opt->pad, g_sw.cb,
                                             g_sw.rb, s)))

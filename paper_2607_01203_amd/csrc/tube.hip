@@ -316,6 +316,36 @@ __global__ void fp_init_kernel(uint32_t* state, int B) {
     if (t == B) state[B] = (uint32_t)B;     // open count
 }
 
+// The tube of residuals (c_bar, rho_bar) = (0, pad) at every step -- the
+// disturbance-only tube -- is the same for every (trajectory, node):
+//   mu_k = 0,  sigma_k[r] = sum_{j<k} sum_q |Phi_{k-j-1}[r][q]| (e_q + pad),
+// rounded upward like the tube map.  Each workgroup forms the N x 8 table in
+// LDS and writes its share of the broadcast.
+__global__ void __launch_bounds__(256) disturbance_tube_kernel(const double* __restrict__ phi, TubeArgs A, double pad,
+                                                               int64_t count) {
+    extern __shared__ double tab[];       // [N][8]
+    const int N = A.N, U = A.U, nx = 6 * U, n = 8 * U;
+    for (int t = threadIdx.x; t < N * 8; t += 256) {
+        const int k = t >> 3, r = t & 7;
+        double acc = 0.0;
+        for (int j = 0; j < k; ++j) {
+            const double* P = phi + (int64_t)(k - j - 1) * 48 + r * 6;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) acc = __builtin_fma(fabs(P[q]), A.e[q] + pad, acc);
+        }
+        tab[t] = k > 0 ? acc + acc * A.wid + 0x1p-1000 : 0.0;
+    }
+    __syncthreads();
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < count; q += (int64_t)gridDim.x * 256) {
+        const int64_t bk = q / n;
+        const int k = (int)(bk % N);
+        const int row = (int)(q - bk * n);
+        const int rr = row < nx ? row % 6 : 6 + ((row - nx) & 1);
+        A.mu[q] = 0.0;
+        A.sigma[q] = tab[k * 8 + rr];
+    }
+}
+
 __global__ void cert_out_kernel(const uint32_t* state, uint32_t* out, int B) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b < B) out[b] = state[b] & FP_CERT;
@@ -361,6 +391,20 @@ static int launch_tube(int B, int N, int U, const double* phi, const double* e, 
     return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
 }
 
+int launch_disturbance_tube(int B, int N, int U, const double* phi, const double* e, double pad, double* mu,
+                            double* sigma, hipStream_t s) {
+    TubeArgs a = {};
+    for (int q = 0; q < 6; ++q) a.e[q] = e[q];
+    a.mu = mu; a.sigma = sigma; a.B = B; a.N = N; a.U = U;
+    a.wid = fmax(0x1p-44, (6.0 * (N > 0 ? N - 1 : 0) + 4.0) * 0x1p-52);
+    const int64_t count = (int64_t)B * N * 8 * U;
+    if (count == 0) return LEB_OK;
+    const int64_t blocks = std::min<int64_t>((count + 255) / 256, 1024);
+    hipLaunchKernelGGL(disturbance_tube_kernel, dim3((unsigned)blocks), dim3(256), (size_t)N * 8 * sizeof(double), s,
+                       phi, a, pad, count);
+    return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
+}
+
 int launch_tube_map(int B, int N, int U, const double* phi, const double* e, const double* cbar,
                     const double* rbar, double* mu, double* sigma, hipStream_t s) {
     TubeFP none{nullptr, nullptr, nullptr, 0.0, 0.0};
@@ -375,7 +419,6 @@ struct Workspace {
     std::vector<size_t> sizes;
     uint32_t* host_open = nullptr;      // pinned, host-mapped
     uint32_t* host_open_dev = nullptr;
-    hipEvent_t ev[2] = {nullptr, nullptr};
 };
 static Workspace g_ws;
 
@@ -394,7 +437,7 @@ static int ws_get(int slot, size_t bytes, void** out) {
     return LEB_OK;
 }
 
-static int ws_host_and_events() {
+static int ws_host() {
     if (!g_ws.host_open) {
         void* h = nullptr;
         if (hipHostMalloc(&h, FP_SLOTS * sizeof(uint32_t), hipHostMallocMapped) != hipSuccess) return LEB_ENOMEM;
@@ -403,9 +446,6 @@ static int ws_host_and_events() {
         g_ws.host_open = (uint32_t*)h;
         g_ws.host_open_dev = (uint32_t*)d;
     }
-    for (int q = 0; q < 2; ++q)
-        if (!g_ws.ev[q] && hipEventCreateWithFlags(&g_ws.ev[q], hipEventDisableTiming) != hipSuccess)
-            return LEB_EDEVICE;
     return LEB_OK;
 }
 
@@ -457,7 +497,7 @@ extern "C" int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int
     const size_t bx = (size_t)units * nx * sizeof(double), bn = (size_t)units * n * sizeof(double);
     if ((rc = ws_get(0, bx, (void**)&cb)) || (rc = ws_get(1, bx, (void**)&rb)) ||
         (rc = ws_get(2, bn, (void**)&xm1)) || (rc = ws_get(3, bn, (void**)&xs1)) ||
-        (rc = ws_get(4, ((size_t)batch + 1) * sizeof(uint32_t), (void**)&state)) || (rc = ws_host_and_events()))
+        (rc = ws_get(4, ((size_t)batch + 1) * sizeof(uint32_t), (void**)&state)) || (rc = ws_host()))
         return rc;
     // iterates: buffer 0 = the caller's (mu, sigma), buffer 1 = workspace; sweep t reads C_{t-1}
     // from buffer (t-1) & 1 and writes C_t to buffer t & 1
@@ -466,11 +506,8 @@ extern "C" int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int
     const int64_t cnt = units * n, per = (int64_t)N * n;
     auto ok = [](hipError_t e_) { return e_ == hipSuccess; };
     hipLaunchKernelGGL(fp_init_kernel, dim3(nblk(batch + 1)), dim3(256), 0, s, state, batch);
-    if (!opt->warm) {       // C_0: the disturbance-only tube (LEB = 0), below the fixed point
-        hipLaunchKernelGGL(fill_kernel, dim3(nblk(units * nx)), dim3(256), 0, s, cb, units * nx, 0.0);
-        hipLaunchKernelGGL(fill_kernel, dim3(nblk(units * nx)), dim3(256), 0, s, rb, units * nx, opt->pad);
-        if ((rc = launch_tube_map(batch, N, U, phi, e, cb, rb, mu, sigma, s))) return rc;
-    }
+    if (!opt->warm)         // C_0: the disturbance-only tube (LEB = 0), below the fixed point
+        if ((rc = launch_disturbance_tube(batch, N, U, phi, e, opt->pad, mu, sigma, s))) return rc;
     volatile uint32_t* hopen = g_ws.host_open;
     auto sweep = [&](int t) -> int {
         const int a = (t - 1) & 1, w = t & 1;
@@ -481,7 +518,26 @@ extern "C" int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int
         const TubeFP fp{xm[a], xs[a], state, opt->tol, opt->inflate_abs};
         if ((r = launch_tube(batch, N, U, phi, e, cb, rb, xm[w], xs[w], fp, s))) return r;
         hipLaunchKernelGGL(fp_state_kernel, dim3(1), dim3(256), 0, s, state, batch, g_ws.host_open_dev, t);
-        return ok(hipEventRecord(g_ws.ev[t & 1], s)) ? LEB_OK : LEB_EDEVICE;
+        return ok(hipGetLastError()) ? LEB_OK : LEB_EDEVICE;
+    };
+    // Wait until sweep t has published its open count.  The count is written to
+    // pinned host memory by the state kernel; the stream is queried now and then
+    // so that the wait also ends if the stream drains (or fails) without it.
+    auto wait_count = [&](int t, uint32_t* out) -> int {
+        for (uint64_t spin = 1;; ++spin) {
+            const uint32_t v = hopen[t % FP_SLOTS];
+            if (v != 0xffffffffu) { *out = v; return LEB_OK; }
+            if ((spin & 255) == 0) {
+                const hipError_t q = hipStreamQuery(s);
+                if (q == hipSuccess) {
+                    const uint32_t v2 = hopen[t % FP_SLOTS];
+                    if (v2 == 0xffffffffu) return LEB_EDEVICE;     // drained without a count
+                    *out = v2;
+                    return LEB_OK;
+                }
+                if (q != hipErrorNotReady) return LEB_EDEVICE;
+            }
+        }
     };
     // one sweep stays in flight while the host reads the previous sweep's
     // open count; a sweep enqueued after the last needed one exits at once
@@ -489,9 +545,8 @@ extern "C" int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int
     int t = 1;
     for (;;) {
         if (t < opt->max_sweeps && (rc = sweep(t + 1))) return rc;
-        if (!ok(hipEventSynchronize(g_ws.ev[t & 1]))) return LEB_EDEVICE;
-        const uint32_t open = hopen[t % FP_SLOTS];
-        if (open == 0xffffffffu) return LEB_EDEVICE;     // the sweep did not publish its count
+        uint32_t open = 0;
+        if ((rc = wait_count(t, &open))) return rc;
         if (open == 0 || t == opt->max_sweeps) break;
         ++t;
     }
