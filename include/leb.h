@@ -166,7 +166,9 @@ int leb_nn_bound(leb_mlp net, int32_t batch, int32_t N, const double* z, const d
  * magnitude |E| 1.  c_bar, rho_bar [batch][N][6*n_units]; mu, sigma
  * [batch][N][8*n_units] outputs.  sigma is rounded upward and also covers
  * the rounding of mu.  A residual that is not finite (c_bar or rho_bar) at
- * step j makes sigma +inf at every later step of that node.
+ * step j makes sigma +inf at every later step of that node.  Horizons up
+ * to N = 83 (LEB_ENOTSUP beyond: a workgroup keeps the residuals of all
+ * steps of its 16 nodes in LDS).
  */
 int leb_tube_map(int32_t batch, int32_t N, int32_t n_units, const double* phi, const double* e,
                  const double* c_bar, const double* rho_bar, double* mu, double* sigma, void* stream);

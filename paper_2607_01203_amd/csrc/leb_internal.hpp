@@ -7,6 +7,15 @@
 
 namespace leb {
 
+// Workgroup barrier that orders LDS only: each wave's LDS accesses complete
+// before it, its global loads and stores stay in flight (__syncthreads would
+// drain them too).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // one workgroup's share of a batched bound launch: up to T units of one problem
 struct PbhTile {
     const double* z; const double* v; const double* mu; const double* sigma;

@@ -28,10 +28,12 @@
 // as intervals before the product with the displacement product.
 //
 // Work mapping: one workgroup of 256 lanes holds T = 256 / U timesteps.
-// Lane (t, i) first evaluates spring i (between nodes i and i+1) of
-// timestep t, then node i's two rows.  Spring i hands node i+1 its terms
-// through LDS.  Inputs are staged with coalesced loads into LDS and the
-// outputs leave through LDS with coalesced stores.
+// Lane (t, i) = t U + i loads the coordinates of node i at timestep t (and
+// the two positions of node i+1 that spring i needs) straight into
+// registers: the offset of node i's rows is linear in the lane index, so
+// the loads and the stores of the node's six output rows are coalesced.
+// The lane evaluates spring i (between nodes i and i+1), hands node i+1
+// its terms through LDS, then evaluates node i's two rows.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -53,8 +55,6 @@ struct SpringOut {      // what spring i passes to node i+1 (row i+1)
     uint32_t pad_;
 };
 
-struct RowOut { double xlo, xhi, zlo, zhi; };
-
 struct ChainArgs {
     const double* z; const double* v; const double* mu; const double* sigma;
     double* r_lo; double* r_hi; double* c_bar; double* rho_bar; uint32_t* flags;
@@ -69,108 +69,68 @@ struct ChainArgs {
 };
 
 
-__global__ void __launch_bounds__(PBH_BLOCK) pbh_chain_fwd(ChainArgs A) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int U = A.U, T = A.T;
-    const int nx = 6 * U, nu = 2 * U, n = nx + nu;
-    double* s_nom = reinterpret_cast<double*>(smem);                       // [T][n]
-    IV<float>* s_d = reinterpret_cast<IV<float>*>(s_nom + (size_t)T * n);  // [T][n]
-    SpringOut* s_sp = reinterpret_cast<SpringOut*>(s_d + (size_t)T * n);   // [T][U]
-    RowOut* s_row = reinterpret_cast<RowOut*>(s_sp + (size_t)T * U);       // [T][U]
-    uint32_t* s_flag = reinterpret_cast<uint32_t*>(s_row + (size_t)T * U); // [T]
-
-    if (A.open && *A.open == 0u) return;
-    const int tid = threadIdx.x;
+// T timesteps with their own pointers (nloc <= T of them present).
+struct TileRef {
     const double *Z, *V, *MU, *SG;
     double *RLO, *RHI, *CB, *RB;
     uint32_t* FL;
     int nloc;
-    if (A.tiles) {
-        const PbhTile& tl = A.tiles[blockIdx.x];
-        Z = tl.z; V = tl.v; MU = tl.mu; SG = tl.sigma;
-        RLO = tl.r_lo; RHI = tl.r_hi; CB = tl.c_bar; RB = tl.rho_bar; FL = tl.flags;
-        nloc = tl.n;
-    } else {
-        const int64_t u0 = (int64_t)blockIdx.x * T;
-        const int64_t left = A.units - u0;
-        nloc = left < T ? (int)left : T;
-        Z = A.z + u0 * nx; V = A.v ? A.v + u0 * nu : nullptr; MU = A.mu ? A.mu + u0 * n : nullptr;
-        SG = A.sigma + u0 * n;
-        RLO = A.r_lo ? A.r_lo + u0 * nx : nullptr; RHI = A.r_hi ? A.r_hi + u0 * nx : nullptr;
-        CB = A.c_bar ? A.c_bar + u0 * nx : nullptr; RB = A.rho_bar ? A.rho_bar + u0 * nx : nullptr;
-        FL = A.flags ? A.flags + u0 : nullptr;
-    }
+};
 
-    for (int i = tid; i < T; i += PBH_BLOCK) s_flag[i] = 0u;
-    __syncthreads();
+// Coordinates of node i at one timestep (state rows 6i.., inputs 2i..) and
+// the positions of node i+1 that spring i needs.
+struct NodeIn { double zs[6], vs[2], ms[8], ss[8], zj[2], mj[2], sj[2]; };
 
-    // ---- stage inputs (coalesced, 8 loads in flight per thread)
-    for (int i0 = tid; i0 < nloc * nx; i0 += 8 * PBH_BLOCK) {
-        double x[8];
+__device__ __forceinline__ void node_load(const TileRef& t, int U, int lt, int i, NodeIn& d) {
+    const int nx = 6 * U, nu = 2 * U, n = nx + nu;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int idx = i0 + u * PBH_BLOCK;
-            x[u] = idx < nloc * nx ? Z[idx] : 0.0;
-        }
+    for (int c = 0; c < 6; ++c) d.zs[c] = 0.0;
+    d.vs[0] = d.vs[1] = 0.0;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int idx = i0 + u * PBH_BLOCK;
-            if (idx >= nloc * nx) break;
-            const int lt = idx / nx, c = idx - lt * nx;
-            if (!isfinite(x[u])) atomicOr(&s_flag[lt], LEB_FLAG_BAD_INPUT);
-            s_nom[lt * n + c] = x[u];
-        }
+    for (int c = 0; c < 8; ++c) { d.ms[c] = 0.0; d.ss[c] = 0.0; }
+    d.zj[0] = d.zj[1] = d.mj[0] = d.mj[1] = d.sj[0] = d.sj[1] = 0.0;
+    if (lt >= t.nloc) return;
+    const bool right = i < U - 1;
+    const double* zp = t.Z + (int64_t)lt * nx + 6 * i;
+    const double* vp = t.V + (int64_t)lt * nu + 2 * i;
+    const double* sp = t.SG + (int64_t)lt * n;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) { d.zs[c] = zp[c]; d.ss[c] = sp[6 * i + c]; }
+    d.vs[0] = vp[0]; d.vs[1] = vp[1];
+    d.ss[6] = sp[nx + 2 * i]; d.ss[7] = sp[nx + 2 * i + 1];
+    if (t.MU) {
+        const double* mp = t.MU + (int64_t)lt * n;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) d.ms[c] = mp[6 * i + c];
+        d.ms[6] = mp[nx + 2 * i]; d.ms[7] = mp[nx + 2 * i + 1];
+        if (right) { d.mj[0] = mp[6 * i + 6]; d.mj[1] = mp[6 * i + 7]; }
     }
-    for (int i0 = tid; i0 < nloc * nu; i0 += 8 * PBH_BLOCK) {
-        double x[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int idx = i0 + u * PBH_BLOCK;
-            x[u] = idx < nloc * nu ? V[idx] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int idx = i0 + u * PBH_BLOCK;
-            if (idx >= nloc * nu) break;
-            const int lt = idx / nu, c = idx - lt * nu;
-            if (!isfinite(x[u])) atomicOr(&s_flag[lt], LEB_FLAG_BAD_INPUT);
-            s_nom[lt * n + nx + c] = x[u];
-        }
-    }
-    for (int i0 = tid; i0 < nloc * n; i0 += 8 * PBH_BLOCK) {
-        double sgv[8], mv[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int idx = i0 + u * PBH_BLOCK;
-            const bool in = idx < nloc * n;
-            sgv[u] = in ? SG[idx] : 0.0;
-            mv[u] = (in && MU) ? MU[idx] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int idx = i0 + u * PBH_BLOCK;
-            if (idx >= nloc * n) break;
-            const int lt = idx / n;
-            const double sg = sgv[u], m = mv[u];
-            uint32_t f = 0;
-            if (!isfinite(sg) || !isfinite(m) || !(sg >= 0.0)) f |= LEB_FLAG_BAD_INPUT;
-            if (fabs(m) > sg) f |= LEB_FLAG_HULL_EXTENDED;
-            if (f) atomicOr(&s_flag[lt], f);
-            // Delta = [min(mu - sigma, 0), max(mu + sigma, 0)]; the FP64
-            // difference is widened by its rounding bound (exact zeros stay 0).
-            double l = m - sg, h = m + sg;
-            l = l - fabs(l) * 0x1p-52;
-            h = h + fabs(h) * 0x1p-52;
-            s_d[idx] = iv(rd32(fmin(l, 0.0)), ru32(fmax(h, 0.0)));
-        }
-    }
-    __syncthreads();
+    if (right) { d.zj[0] = zp[6]; d.zj[1] = zp[7]; d.sj[0] = sp[6 * i + 6]; d.sj[1] = sp[6 * i + 7]; }
+}
 
-    const int lt = tid / U;
-    const int i = tid - lt * U;
-    const bool active = (lt < nloc);
-    const double* nom = s_nom + lt * n;
-    const IV<float>* D = s_d + lt * n;
+// Spring i and node i of timestep lt; s_sp [T][U], s_flag [T] (cleared).
+// Contains one workgroup barrier.
+__device__ __forceinline__ void node_pass(const ChainArgs& A, const TileRef& t, const NodeIn& d, int lt, int i,
+                                          SpringOut* s_sp, uint32_t* s_flag) {
+    const int U = A.U, nx = 6 * U;
+    const bool active = lt < t.nloc;
+    const bool right = active && i < U - 1;      // spring i exists
+    if (active) {
+        uint32_t f = 0;
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+            if (!isfinite(d.zs[c])) f |= LEB_FLAG_BAD_INPUT;
+        if (!isfinite(d.vs[0]) || !isfinite(d.vs[1])) f |= LEB_FLAG_BAD_INPUT;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            if (!isfinite(d.ss[c]) || !isfinite(d.ms[c]) || !(d.ss[c] >= 0.0)) f |= LEB_FLAG_BAD_INPUT;
+            if (fabs(d.ms[c]) > d.ss[c]) f |= LEB_FLAG_HULL_EXTENDED;
+        }
+        if (f) atomicOr(&s_flag[lt], f);
+    }
+    const IV<float> Dx = disp_interval(d.ms[0], d.ss[0]), Dz = disp_interval(d.ms[1], d.ss[1]);
+    const IV<float> Dth = disp_interval(d.ms[2], d.ss[2]);
+    const IV<float> Du1 = disp_interval(d.ms[6], d.ss[6]), Du2 = disp_interval(d.ms[7], d.ss[7]);
 
     // constants with c folded in (all >= 0 for kL >= 0)
     const double K3 = 3.0 * A.kL * A.c, K15 = 1.5 * A.kL * A.c, K1 = A.kL * A.c, K05 = 0.5 * A.kL * A.c;
@@ -181,9 +141,10 @@ __global__ void __launch_bounds__(PBH_BLOCK) pbh_chain_fwd(ChainArgs A) {
 #pragma unroll
     for (int q = 0; q < 5; ++q) R[q] = iv(0.0f, 0.0f);
     uint32_t unb = 0;
-    if (active && i < U - 1) {
+    if (right) {
         SpringSetup st;
-        spring_setup(nom, D, i, A.L0, st);
+        spring_setup_v(d.zs[0], d.zs[1], d.zj[0], d.zj[1], Dx, Dz, disp_interval(d.mj[0], d.sj[0]),
+                       disp_interval(d.mj[1], d.sj[1]), A.L0, st);
         AccPrimal acc;
         SpringPieces<float> pc;
         const bool ok = spring_core<float, AccPrimal>(st.dxA, st.dxB, st.dz0, st.dz1, st.dz2, st.Dxi, st.Dzi,
@@ -206,78 +167,98 @@ __global__ void __launch_bounds__(PBH_BLOCK) pbh_chain_fwd(ChainArgs A) {
         }
         s_sp[lt * U + i] = o;
     }
-    __syncthreads();
+    __syncthreads();      // spring terms and flags complete
 
-    // ---- node i: attitude block, shared position pairs, totals
-    if (active) {
-        const int th = 6 * i + 2, pxc = 6 * i, pzc = 6 * i + 1;
-        const int u1 = nx + 2 * i, u2 = u1 + 1;
-        IV<float> L[5];
+    // ---- node i: attitude block, shared position pairs, totals; the node's six rows out
+    if (!active) return;
+    IV<float> L[5];
 #pragma unroll
-        for (int q = 0; q < 5; ++q) L[q] = iv(0.0f, 0.0f);
-        div_ ox = rx, oz = rz;
-        uint32_t row_unb = unb;
-        if (i > 0) {
-            const SpringOut& o = s_sp[lt * U + i - 1];
-            row_unb |= o.unbounded;
-            ox.lo += o.xlo; ox.hi += o.xhi; oz.lo += o.zlo; oz.hi += o.zhi;
+    for (int q = 0; q < 5; ++q) L[q] = iv(0.0f, 0.0f);
+    div_ ox = rx, oz = rz;
+    uint32_t row_unb = unb;
+    if (i > 0) {
+        const SpringOut& o = s_sp[lt * U + i - 1];
+        row_unb |= o.unbounded;
+        ox.lo += o.xlo; ox.hi += o.xhi; oz.lo += o.zlo; oz.hi += o.zhi;
 #pragma unroll
-            for (int q = 0; q < 5; ++q) L[q] = o.L[q];
-        }
-        NodeTerms nt;
-        const IV<float> Dth = D[th], Du1 = D[u1], Du2 = D[u2], Dx = D[pxc], Dz = D[pzc];
-        node_terms(nom[th], nom[u1] + nom[u2], Dth, Du1, Du2, Dx, Dz, R, L, U > 1 && !row_unb, A.c, K15, K1,
-                   K05, maskv(Dth), maskv(Du1), maskv(Du2), maskv(Dx), maskv(Dz), nt);
-#pragma unroll
-        for (int q = 0; q < 12; ++q) {
-            div_& acc = node_term_row(q) == 0 ? ox : oz;
-            const float a = nt.neg[q] ? nt.T[q].hi : nt.T[q].lo;
-            const float b = nt.neg[q] ? nt.T[q].lo : nt.T[q].hi;
-            acc.lo = __builtin_fma(nt.k[q], (double)a, acc.lo);
-            acc.hi = __builtin_fma(nt.k[q], (double)b, acc.hi);
-        }
-        RowOut r;
-        if (row_unb) {
-            r.xlo = r.zlo = -INFINITY; r.xhi = r.zhi = INFINITY;
-        } else {
-            // all lower-end summands are <= 0 and all upper-end summands >= 0,
-            // so 2^-45 relative covers every FP64 rounding in the sums
-            r.xlo = wlo64(ox.lo); r.xhi = whi64(ox.hi); r.zlo = wlo64(oz.lo); r.zhi = whi64(oz.hi);
-        }
-        s_row[lt * U + i] = r;
+        for (int q = 0; q < 5; ++q) L[q] = o.L[q];
     }
-    __syncthreads();
-
-    // ---- store (coalesced), zeros on the affine rows
-    for (int idx = tid; idx < nloc * nx; idx += PBH_BLOCK) {
-        int t = idx / nx, row = idx - t * nx;
-        int node = row / 6, rc = row - node * 6;
-        uint32_t f = s_flag[t];
-        double lo = 0.0, hi = 0.0;
-        if (f & LEB_FLAG_BAD_INPUT) { lo = -INFINITY; hi = INFINITY; }
-        else if (rc == 3) { lo = s_row[t * U + node].xlo; hi = s_row[t * U + node].xhi; }
-        else if (rc == 4) { lo = s_row[t * U + node].zlo; hi = s_row[t * U + node].zhi; }
-        const int o = idx;
-        if (RLO) {
-            RLO[o] = lo;
-            RHI[o] = hi;
-        }
-        if (CB) {
+    NodeTerms nt;
+    node_terms(d.zs[2], d.vs[0] + d.vs[1], Dth, Du1, Du2, Dx, Dz, R, L, U > 1 && !row_unb, A.c, K15, K1, K05,
+               maskv(Dth), maskv(Du1), maskv(Du2), maskv(Dx), maskv(Dz), nt);
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+        div_& acc = node_term_row(q) == 0 ? ox : oz;
+        const float a = nt.neg[q] ? nt.T[q].hi : nt.T[q].lo;
+        const float b = nt.neg[q] ? nt.T[q].lo : nt.T[q].hi;
+        acc.lo = __builtin_fma(nt.k[q], (double)a, acc.lo);
+        acc.hi = __builtin_fma(nt.k[q], (double)b, acc.hi);
+    }
+    const uint32_t ft = s_flag[lt];
+    double lo[6], hi[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) { lo[c] = 0.0; hi[c] = 0.0; }
+    if (ft & LEB_FLAG_BAD_INPUT) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) { lo[c] = -INFINITY; hi[c] = INFINITY; }
+    } else if (row_unb) {
+        lo[3] = lo[4] = -INFINITY; hi[3] = hi[4] = INFINITY;
+    } else {
+        // all lower-end summands are <= 0 and all upper-end summands >= 0,
+        // so 2^-45 relative covers every FP64 rounding in the sums
+        lo[3] = wlo64(ox.lo); hi[3] = whi64(ox.hi); lo[4] = wlo64(oz.lo); hi[4] = whi64(oz.hi);
+    }
+    const int64_t o = (int64_t)lt * nx + 6 * i;
+    if (t.RLO) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) { t.RLO[o + c] = lo[c]; t.RHI[o + c] = hi[c]; }
+    }
+    if (t.CB) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
             double cb, rb;
-            if (isfinite(lo) && isfinite(hi)) {
-                cb = 0.5 * (lo + hi);
-                rb = fmax(hi - cb, cb - lo);
+            if (isfinite(lo[c]) && isfinite(hi[c])) {
+                cb = 0.5 * (lo[c] + hi[c]);
+                rb = fmax(hi[c] - cb, cb - lo[c]);
                 rb = rb + fabs(rb) * 0x1p-50 + A.pad;
             } else { cb = 0.0; rb = INFINITY; }
-            CB[o] = cb;
-            RB[o] = rb;
+            t.CB[o + c] = cb;
+            t.RB[o + c] = rb;
         }
     }
-    if (FL)
-        for (int t = tid; t < nloc; t += PBH_BLOCK) {
-            uint32_t f = s_flag[t];
-            FL[t] = (f & LEB_FLAG_BAD_INPUT) ? (f & ~LEB_FLAG_UNBOUNDED) : f;
-        }
+    if (t.FL && i == 0) t.FL[lt] = (ft & LEB_FLAG_BAD_INPUT) ? (ft & ~LEB_FLAG_UNBOUNDED) : ft;
+}
+
+__global__ void __launch_bounds__(PBH_BLOCK) pbh_chain_fwd(ChainArgs A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int U = A.U, T = A.T;
+    const int nx = 6 * U, nu = 2 * U, n = nx + nu;
+    SpringOut* s_sp = reinterpret_cast<SpringOut*>(smem);                  // [T][U]
+    uint32_t* s_flag = reinterpret_cast<uint32_t*>(s_sp + (size_t)T * U);   // [T]
+
+    if (A.open && *A.open == 0u) return;
+    const int tid = threadIdx.x;
+    TileRef t0;
+    if (A.tiles) {
+        const PbhTile& pt = A.tiles[blockIdx.x];
+        t0 = TileRef{pt.z, pt.v, pt.mu, pt.sigma, pt.r_lo, pt.r_hi, pt.c_bar, pt.rho_bar, pt.flags, pt.n};
+    } else {
+        const int64_t u0 = (int64_t)blockIdx.x * T;
+        const int64_t left = A.units - u0;
+        t0.nloc = left < T ? (int)left : T;
+        t0.Z = A.z + u0 * nx; t0.V = A.v + u0 * nu; t0.MU = A.mu ? A.mu + u0 * n : nullptr;
+        t0.SG = A.sigma + u0 * n;
+        t0.RLO = A.r_lo ? A.r_lo + u0 * nx : nullptr; t0.RHI = A.r_hi ? A.r_hi + u0 * nx : nullptr;
+        t0.CB = A.c_bar ? A.c_bar + u0 * nx : nullptr; t0.RB = A.rho_bar ? A.rho_bar + u0 * nx : nullptr;
+        t0.FL = A.flags ? A.flags + u0 : nullptr;
+    }
+    for (int q = tid; q < T; q += PBH_BLOCK) s_flag[q] = 0u;
+    const int lt = tid / U;
+    const int i = tid - lt * U;
+    NodeIn d0;
+    node_load(t0, U, lt, i, d0);
+    __syncthreads();      // s_flag cleared
+    node_pass(A, t0, d0, lt, i, s_sp, s_flag);
 }
 
 __global__ void fill_zero_kernel(double* a, double* b, double* c, double* d, double pad, uint32_t* flags,
@@ -292,13 +273,10 @@ __global__ void fill_zero_kernel(double* a, double* b, double* c, double* d, dou
         for (int64_t k = idx; k < nflags; k += stride) flags[k] = 0u;
 }
 
-size_t pbh_smem_bytes(int U) { return pbh_smem_bytes_T(U, PBH_BLOCK / U); }
-
 size_t pbh_smem_bytes_T(int U, int T) {
-    const int n = 8 * U;
-    return (size_t)T * n * sizeof(double) + (size_t)T * n * sizeof(IV<float>) + (size_t)T * U * sizeof(SpringOut)
-         + (size_t)T * U * sizeof(RowOut) + (size_t)T * sizeof(uint32_t) + 16;
+    return (size_t)T * U * sizeof(SpringOut) + (size_t)T * sizeof(uint32_t) + 16;
 }
+size_t pbh_smem_bytes(int U) { return pbh_smem_bytes_T(U, PBH_BLOCK / U); }
 
 int launch_pbh_chain(const leb_dynamics* dyn, int64_t units, const double* z, const double* v,
                      const double* mu, const double* sigma, double* r_lo, double* r_hi, double* c_bar,
@@ -317,8 +295,7 @@ int launch_pbh_chain(const leb_dynamics* dyn, int64_t units, const double* z, co
     a.pad = pad;
     int64_t blocks = (units + a.T - 1) / a.T;
     if (blocks > 0x7fffffff) return LEB_EINVAL;
-    size_t smem = pbh_smem_bytes(a.U);
-    hipLaunchKernelGGL(pbh_chain_fwd, dim3((unsigned)blocks), dim3(PBH_BLOCK), smem, stream, a);
+    hipLaunchKernelGGL(pbh_chain_fwd, dim3((unsigned)blocks), dim3(PBH_BLOCK), pbh_smem_bytes(a.U), stream, a);
     return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
 }
 

@@ -25,10 +25,10 @@ struct SpringSetup {
     double dxn, dzn;
 };
 
-__device__ __forceinline__ void spring_setup(const double* nom, const IV<float>* D, int i, double L0, SpringSetup& s) {
-    const int pi_ = 6 * i, pj = 6 * (i + 1);
-    const double pxi = nom[pi_], pzi = nom[pi_ + 1], pxj = nom[pj], pzj = nom[pj + 1];
-    s.Dxi = D[pi_]; s.Dzi = D[pi_ + 1]; s.Dxj = D[pj]; s.Dzj = D[pj + 1];
+__device__ __forceinline__ void spring_setup_v(double pxi, double pzi, double pxj, double pzj, IV<float> Dxi,
+                                              IV<float> Dzi, IV<float> Dxj, IV<float> Dzj, double L0,
+                                              SpringSetup& s) {
+    s.Dxi = Dxi; s.Dzi = Dzi; s.Dxj = Dxj; s.Dzj = Dzj;
     s.dxn = L0 + pxj - pxi;
     s.dzn = pzj - pzi;
     const double sx = fabs(L0) + fabs(pxj) + fabs(pxi) + fabs(s.Dxi.lo) + fabs(s.Dxi.hi) + fabs(s.Dxj.lo) + fabs(s.Dxj.hi);
@@ -40,6 +40,21 @@ __device__ __forceinline__ void spring_setup(const double* nom, const IV<float>*
     s.dz0 = from64(dzn, dzn, ez);
     s.dz1 = from64(dzn - (double)s.Dzi.hi, dzn - (double)s.Dzi.lo, ez);
     s.dz2 = from64(dzn + (double)s.Dzj.lo - (double)s.Dzi.hi, dzn + (double)s.Dzj.hi - (double)s.Dzi.lo, ez);
+}
+
+__device__ __forceinline__ void spring_setup(const double* nom, const IV<float>* D, int i, double L0, SpringSetup& s) {
+    const int pi_ = 6 * i, pj = 6 * (i + 1);
+    spring_setup_v(nom[pi_], nom[pi_ + 1], nom[pj], nom[pj + 1], D[pi_], D[pi_ + 1], D[pj], D[pj + 1], L0, s);
+}
+
+// Displacement interval Delta = [min(mu - sigma, 0), max(mu + sigma, 0)] of
+// one coordinate in FP32; the FP64 difference is widened by its rounding
+// bound (exact zeros stay 0).
+__device__ __forceinline__ IV<float> disp_interval(double m, double sg) {
+    double l = m - sg, h = m + sg;
+    l = l - fabs(l) * 0x1p-52;
+    h = h + fabs(h) * 0x1p-52;
+    return iv(rd32(fmin(l, 0.0)), ru32(fmax(h, 0.0)));
 }
 
 }  // namespace leb

@@ -99,6 +99,23 @@ __global__ void __launch_bounds__(256) tube_map_kernel(const double* __restrict_
     double* se = sphi + (N + 4) * 48;
     double* sc = se + 8;
     double* sw = sc + (size_t)kpad * 16;
+    __shared__ int64_t srow[16];   // column c0 + cl: offset of its node's rows in the residual arrays at step 0
+    __shared__ int64_t stub[16];   // ... and of its trajectory in the tube arrays
+    __shared__ int snode[16];      // ... its node
+    __shared__ uint32_t sfrz[16];  // ... its trajectory is frozen (certified by an earlier sweep)
+    const int cols = A.B * U;
+    const int c0 = blockIdx.x * 16;
+    const int ncol = min(16, cols - c0);
+    if (tid < 16) {
+        const int col = min(c0 + tid, cols - 1);
+        const int bb = col / U, nd = col - bb * U;
+        srow[tid] = (int64_t)bb * N * nx + 6 * nd;
+        stub[tid] = (int64_t)bb * N * n;
+        snode[tid] = nd;
+        sfrz[tid] = fp ? (P.state[bb] & FP_CERT) : 0u;
+        sbad[tid] = 0u;
+        sjinf[tid] = 0x7fffffff;
+    }
     // Phi (8 loads in flight per thread)
     for (int i0 = tid; i0 < (N + 4) * 48; i0 += 8 * 256) {
         double v[8];
@@ -112,81 +129,120 @@ __global__ void __launch_bounds__(256) tube_map_kernel(const double* __restrict_
             if (i0 + 256 * u < (N + 4) * 48) sp[i0 + 256 * u] = v[u];
     }
     if (tid < 6) se[tid] = A.e[tid];
-    if (tid < 16) { sbad[tid] = 0u; sjinf[tid] = 0x7fffffff; }
+    if (tid < 128) { sc[kfull * 16 + tid] = 0.0; sw[kfull * 16 + tid] = 0.0; }   // 8 zero rows past the end
     __syncthreads();
-    const int cols = A.B * U;
-    const int c0 = blockIdx.x * 16;
-    // stage c_bar and w = e + rho_bar + |c_bar| wid: 16 threads per column, entry
-    // kk = 6 j + q of a column at j * nx + q (6 contiguous per step), 8 loads of
-    // each in flight per thread.  A residual radius that is not finite enters as 0
-    // and every later step of its column gets sigma = +inf (a product 0 * inf with
-    // the zero entries of T would otherwise make earlier rows NaN); a centre that
-    // is not finite enters as 0 the same way.
-    {
-        const int cl = tid >> 4, sub = tid & 15;
-        const int col = c0 + cl;
-        const bool cin = col < cols;
-        const int bb = cin ? col / U : 0, nd = cin ? col - bb * U : 0;
-        const double* cbp = A.cbar + (int64_t)bb * N * nx + 6 * nd;
-        const double* rbp = A.rbar + (int64_t)bb * N * nx + 6 * nd;
-        for (int k0 = sub; k0 < kpad; k0 += 8 * 16) {
-            double cv[8], rv[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int kk = max(0, min(k0 + 16 * u, kfull - 1));     // a valid address; N = 1 has no entries
-                const int j = kk / 6, q = kk - 6 * j;
-                cv[u] = cin ? cbp[(int64_t)j * nx + q] : 0.0;
-                rv[u] = cin ? rbp[(int64_t)j * nx + q] : 0.0;
+    // c_bar and w = e + rho_bar + |c_bar| wid of steps [j0, j1): entry (j, p) of the 96
+    // per step, column cl = p / 6 and row q = p % 6, so consecutive threads read
+    // consecutive addresses.  A residual radius that is not finite enters as 0 and
+    // every later step of its column gets sigma = +inf (a product 0 * inf with the
+    // zero entries of T would otherwise make earlier rows NaN); a centre that is
+    // not finite enters as 0 the same way.
+    auto stage_load = [&](int j0, int idx, double& c, double& r) {
+        const int j = j0 + idx / 96, p = idx % 96, cl = p / 6, q = p - 6 * cl;
+        const bool in = cl < ncol;
+        const int64_t off = srow[in ? cl : 0] + (int64_t)j * nx + q;
+        c = in ? A.cbar[off] : 0.0;
+        r = in ? A.rbar[off] : 0.0;
+    };
+    auto stage_store = [&](int j0, int idx, double c, double r) {
+        const int j = j0 + idx / 96, p = idx % 96, cl = p / 6, q = p - 6 * cl;
+        double w = 0.0;
+        if (cl < ncol) {
+            const bool cfin = fabs(c) <= DBL_MAX;
+            if (!cfin) c = 0.0;
+            w = se[q] + r + fabs(c) * A.wid;
+            if (!(cfin && w <= DBL_MAX)) {
+                atomicMin(&sjinf[cl], j);
+                w = 0.0;
             }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int kk = k0 + 16 * u;
-                if (kk >= kpad) break;
-                double c = 0.0, w = 0.0;
-                if (kk < kfull && cin) {
-                    const int j = kk / 6, q = kk - 6 * j;
-                    c = cv[u];
-                    const bool cfin = fabs(c) <= DBL_MAX;
-                    if (!cfin) c = 0.0;
-                    w = se[q] + rv[u] + fabs(c) * A.wid;
-                    if (!(cfin && w <= DBL_MAX)) {
-                        atomicMin(&sjinf[cl], j);
-                        w = 0.0;
-                    }
-                }
-                sc[kk * 16 + cl] = c;
-                sw[kk * 16 + cl] = w;
-            }
+        } else {
+            c = 0.0;
         }
+        const int kk = 6 * j + q;
+        sc[kk * 16 + cl] = c;
+        sw[kk * 16 + cl] = w;
+    };
+    // Steps are staged in chunks of 8 (the steps the row tiles of one slot add):
+    // slot s of row group g reads the steps of chunks 0 .. 5g + s only, so
+    // chunks 0 .. 5g are staged first and chunk 5g + s + 1 is written to LDS
+    // after slot s.  Every load (the first chunks, the later chunks, the tube
+    // C_{t-1} for the containment test) is issued before any of them is used.
+    const int nst = N - 1;                                   // steps with residuals
+    const int gch = blockIdx.y * TM_RT;                      // first chunk of this row group's slot 0
+    const int pent = min(nst, 8 * (gch + 1)) * 96;           // entries staged before slot 0
+    double pc[16], pr[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+        if (tid + 256 * u < pent) stage_load(0, tid + 256 * u, pc[u], pr[u]);
+    double cn[TM_RT - 1][3], rn[TM_RT - 1][3];
+#pragma unroll
+    for (int s = 0; s + 1 < TM_RT; ++s) {
+        const int nj0 = 8 * (gch + s + 1);
+        const int nne = max(0, min(nst, nj0 + 8) - nj0) * 96;
+#pragma unroll
+        for (int u = 0; u < 3; ++u)
+            if (tid + 256 * u < nne) stage_load(nj0, tid + 256 * u, cn[s][u], rn[s][u]);
     }
-    __syncthreads();
     const int nrt = (N + 1) >> 1;
     const int lr = lane & 15, lq = lane >> 4;
-    int kmax[TM_RT], abase[TM_RT];
+    const bool cin = lr < ncol;
+    const int bfirst = c0 / U;
+    // The tube entries of this lane's accumulators: element i of slot s is row
+    // r = 16 rt + 4 i + lq of the slot's tile, i.e. step k = r / 8, row r % 8 of
+    // node column lr.
+    auto tube_off = [&](int rr, int k) -> int64_t {
+        const int nd = snode[lr];
+        return stub[lr] + (int64_t)k * n + (rr < 6 ? 6 * nd + rr : nx + 2 * nd + (rr - 6));
+    };
+    double mi[TM_RT][4], si[TM_RT][4];
 #pragma unroll
     for (int s = 0; s < TM_RT; ++s) {
         const int rt = tm_tile(wave, s, blockIdx.y);
-        kmax[s] = rt < nrt ? 6 * min(N - 1, 2 * rt + 1) : 0;
-        const int r = 16 * rt + lr, k = r >> 3, rr = r & 7;
-        // A[(k, rr)][(j, q)] = Phi_{k-j-1}[rr][q] at sp[(k - j + 3) * 48 + rr * 6 + q]
-        abase[s] = (k + 3) * 48 + rr * 6;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 16 * rt + 4 * i + lq, k = r >> 3;
+            mi[s][i] = 0.0;
+            si[s][i] = 0.0;
+            if (fp && cin && rt < nrt && k < N && !sfrz[lr]) {
+                const int64_t o = tube_off(r & 7, k);
+                mi[s][i] = P.mu_in[o];
+                si[s][i] = P.sg_in[o];
+            }
+        }
     }
-    d4 am[TM_RT], as[TM_RT];
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+        if (tid + 256 * u < pent) stage_store(0, tid + 256 * u, pc[u], pr[u]);
+    for (int i0 = tid + 16 * 256; i0 < pent; i0 += 16 * 256) {    // horizons beyond 43 steps
+        double cv[16], rv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            if (i0 + 256 * u < pent) stage_load(0, i0 + 256 * u, cv[u], rv[u]);
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            if (i0 + 256 * u < pent) stage_store(0, i0 + 256 * u, cv[u], rv[u]);
+    }
+    __syncthreads();
+    const bool frozen = sfrz[lr] != 0u;
     // one K loop per slot, two K steps per iteration into separate accumulators
     // (four independent MFMA chains); the zero padding of Phi (lags down to -4)
     // and of the B block (8 rows) covers the reads past a tile's range.
     // kk = k0 + lq = 6 j + q, and the A offset of kk is abase - (48 j - q).
 #pragma unroll
     for (int s = 0; s < TM_RT; ++s) {
+        const int rt = tm_tile(wave, s, blockIdx.y);
+        const int kmax = rt < nrt ? 6 * min(N - 1, 2 * rt + 1) : 0;
+        // A[(k, rr)][(j, q)] = Phi_{k-j-1}[rr][q] at sp[(k - j + 3) * 48 + rr * 6 + q]
+        const int abase = (((16 * rt + lr) >> 3) + 3) * 48 + ((16 * rt + lr) & 7) * 6;
         d4 m0 = d4{0.0, 0.0, 0.0, 0.0}, v0 = m0, m1 = m0, v1 = m0;
         int j = 0, q = lq;                     // entry kk
         int j2 = (lq + 4) / 6, q2 = lq + 4 - 6 * ((lq + 4) / 6);   // entry kk + 4
-        for (int k0 = 0; k0 < kmax[s]; k0 += 8) {
+        for (int k0 = 0; k0 < kmax; k0 += 8) {
             const int kk = k0 + lq;
             const double c0v = sc[kk * 16 + lr], w0v = sw[kk * 16 + lr];
             const double c1v = sc[(kk + 4) * 16 + lr], w1v = sw[(kk + 4) * 16 + lr];
-            const double a0 = sp[abase[s] - (48 * j - q)];
-            const double a1 = sp[abase[s] - (48 * j2 - q2)];
+            const double a0 = sp[abase - (48 * j - q)];
+            const double a1 = sp[abase - (48 * j2 - q2)];
             m0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, c0v, m0, 0, 0, 0);
             v0 = __builtin_amdgcn_mfma_f64_16x16x4f64(fabs(a0), w0v, v0, 0, 0, 0);
             m1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, c1v, m1, 0, 0, 0);
@@ -195,75 +251,40 @@ __global__ void __launch_bounds__(256) tube_map_kernel(const double* __restrict_
             q += 2; j += 1; if (q >= 6) { q -= 6; ++j; }
             q2 += 2; j2 += 1; if (q2 >= 6) { q2 -= 6; ++j2; }
         }
-        am[s] = m0 + m1;
-        as[s] = v0 + v1;
-    }
-    // phase 2, one slot at a time: the slot-s tiles of the four waves are four
-    // consecutive row tiles (8 steps); they go through LDS ([row][column]) so
-    // that the tube is read (containment) and written with coalesced accesses
-    double* om = sphi;
-    double* os = sphi + 64 * 16;
-    const int ncol = min(16, cols - c0);
-    const int bfirst = c0 / U;
-#pragma unroll
-    for (int s = 0; s < TM_RT; ++s) {
-        const int base = blockIdx.y * 4 * TM_RT + 4 * s;      // first tile of the slot
-        if (base >= nrt) break;                                // uniform over the workgroup
-        __syncthreads();
-        const int rt = tm_tile(wave, s, blockIdx.y);
-        if (rt < nrt) {
+        const d4 am = m0 + m1, as = v0 + v1;
+        const int sjl = sjinf[lr];       // every step below this slot's rows is staged
+        // this slot's tube entries straight from the accumulators (the lanes of a
+        // row write 16 nodes' rows; the L2 merges the partial lines)
+        if (cin && rt < nrt) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int r = 16 * (rt - base) + 4 * i + lq;   // row within the slot: (k, row) = (r >> 3, r & 7)
-                om[r * 16 + lr] = am[s][i];
-                os[r * 16 + lr] = as[s][i];
+                const int r = 16 * rt + 4 * i + lq, k = r >> 3, rr = r & 7;
+                if (k >= N) continue;
+                const double mF = am[i];
+                // sums of nonnegative terms, rounded upward; 2^-1000 covers any flushed subnormal part
+                const double sF = k > sjl ? INFINITY : as[i] + as[i] * A.wid + 0x1p-1000;
+                double so = sF;
+                if (fp) {
+                    // [mF - sF, mF + sF] inside [mi - si, mi + si], with the rounding of the
+                    // test covered; a tube that is not finite is never accepted
+                    if (!frozen && !(sF <= DBL_MAX && (fabs(mF - mi[s][i]) + sF) * (1.0 + 0x1p-50) <= si[s][i]))
+                        sbad[(c0 + lr) / U - bfirst] = 1u;
+                    so = sF + sF * P.tol + P.abs_;
+                }
+                if (!frozen) {
+                    const int64_t o = tube_off(rr, k);
+                    A.mu[o] = mF;
+                    A.sigma[o] = so;
+                }
             }
         }
-        __syncthreads();
-        const int k0s = 2 * base;
-        const int nk = min(8, N - k0s);
-        // thread -> (step within the slot, column, row); 8 x 16 x 8 = 1024 entries, 4 per
-        // thread with their tube loads in flight together
-        int64_t off[4];
-        bool live[4];
-        int kl4[4], cl4[4], rr4[4], b4[4];
-        double mi4[4], si4[4];
+        if (s + 1 < TM_RT) {
+            const int nj0 = 8 * (gch + s + 1);
+            const int nne = max(0, min(nst, nj0 + 8) - nj0) * 96;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int idx = tid + 256 * u;
-            const int kl = idx >> 7, rem = idx & 127;
-            const bool st = rem < 96;                               // 6 state rows per node, contiguous
-            const int cl = st ? (rem * 43) >> 8 : (rem - 96) >> 1;  // rem / 6 for rem < 96
-            const int rr = st ? rem - cl * 6 : 6 + ((rem - 96) & 1);
-            live[u] = kl < nk && cl < ncol;
-            const int col = min(c0 + cl, cols - 1);
-            const int bb = col / U, nd = col - bb * U;
-            const int k = min(k0s + kl, N - 1);
-            off[u] = ((int64_t)bb * N + k) * n + (rr < 6 ? 6 * nd + rr : nx + 2 * nd + (rr - 6));
-            kl4[u] = kl; cl4[u] = cl; rr4[u] = rr; b4[u] = bb;
-            mi4[u] = fp ? P.mu_in[off[u]] : 0.0;
-            si4[u] = fp ? P.sg_in[off[u]] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (!live[u]) continue;
-            const int kl = kl4[u], cl = cl4[u], rr = rr4[u], bb = b4[u];
-            const int k = k0s + kl;
-            const double mF = om[(kl * 8 + rr) * 16 + cl];
-            const double acc = os[(kl * 8 + rr) * 16 + cl];
-            // sums of nonnegative terms, rounded upward; 2^-1000 covers any flushed subnormal part
-            const double sF = k > sjinf[cl] ? INFINITY : acc + acc * A.wid + 0x1p-1000;
-            double so = sF;
-            bool frozen = false;
-            if (fp) {
-                frozen = (P.state[bb] & FP_CERT) != 0u;
-                // [mF - sF, mF + sF] inside [mi - si, mi + si], with the rounding of the
-                // test covered; a tube that is not finite is never accepted
-                if (!frozen && !(sF <= DBL_MAX && (fabs(mF - mi4[u]) + sF) * (1.0 + 0x1p-50) <= si4[u]))
-                    sbad[bb - bfirst] = 1u;
-                so = sF + sF * P.tol + P.abs_;
-            }
-            if (!frozen) { A.mu[off[u]] = mF; A.sigma[off[u]] = so; }
+            for (int u = 0; u < 3; ++u)
+                if (tid + 256 * u < nne) stage_store(nj0, tid + 256 * u, cn[s][u], rn[s][u]);
+            lds_barrier();
         }
     }
     if (!fp) return;
@@ -379,14 +400,18 @@ static int launch_tube(int B, int N, int U, const double* phi, const double* e, 
     // output of 8 steps (mu and sigma, 64 rows x 16 columns)
     const size_t nm1 = N > 1 ? N - 1 : 0;
     const size_t smem = std::max((size_t)(N + 4) * 48 + 8 + 2 * (6 * nm1 + 8) * 16, (size_t)2 * 64 * 16) * sizeof(double);
-    if (smem > 160 * 1024 - 256) return LEB_ENOTSUP;     // N <= 86
-    static bool lds_attr = false;      // the kernel may use up to 160 KB of LDS (set once)
-    if (smem > 65536 && !lds_attr) {
-        if (hipFuncSetAttribute((const void*)tube_map_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                160 * 1024 - 256) != hipSuccess)
+    // the kernel may use all 160 KB of LDS, static part included (set once)
+    static size_t dyn_max = 0;
+    if (dyn_max == 0) {
+        hipFuncAttributes fa;
+        if (hipFuncGetAttributes(&fa, (const void*)tube_map_kernel) != hipSuccess) return LEB_EDEVICE;
+        const size_t cap = 160 * 1024 - fa.sharedSizeBytes;
+        if (hipFuncSetAttribute((const void*)tube_map_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cap) !=
+            hipSuccess)
             return LEB_EDEVICE;
-        lds_attr = true;
+        dyn_max = cap;
     }
+    if (smem > dyn_max) return LEB_ENOTSUP;     // N <= 83
     hipLaunchKernelGGL(tube_map_kernel, dim3((unsigned)gx, gy), dim3(256), smem, s, phi, a, fp);
     return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
 }
