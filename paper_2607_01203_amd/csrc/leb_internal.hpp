@@ -16,6 +16,10 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Per-trajectory fixed-point state word.
+constexpr uint32_t FP_CERT = 1u;          // certified (frozen)
+constexpr uint32_t FP_OPEN = 1u << 31;    // this sweep: F(C) not inside C
+
 // one workgroup's share of a batched bound launch: up to T units of one problem
 struct PbhTile {
     const double* z; const double* v; const double* mu; const double* sigma;

@@ -41,19 +41,11 @@
 #include "ivl.hpp"
 #include "leb.h"
 #include "leb_internal.hpp"
-#include "node.hpp"
-#include "pbh_common.hpp"
+#include "pbh_node.hpp"
 
 namespace leb {
 
 constexpr int PBH_BLOCK = 256;
-
-struct SpringOut {      // what spring i passes to node i+1 (row i+1)
-    double xlo, xhi, zlo, zhi;      // -(cross + own-of-node-i terms), already scaled
-    IV<float> L[5];                 // node i+1's shared own-position entries
-    uint32_t unbounded;
-    uint32_t pad_;
-};
 
 struct ChainArgs {
     const double* z; const double* v; const double* mu; const double* sigma;
@@ -69,45 +61,6 @@ struct ChainArgs {
 };
 
 
-// T timesteps with their own pointers (nloc <= T of them present).
-struct TileRef {
-    const double *Z, *V, *MU, *SG;
-    double *RLO, *RHI, *CB, *RB;
-    uint32_t* FL;
-    int nloc;
-};
-
-// Coordinates of node i at one timestep (state rows 6i.., inputs 2i..) and
-// the positions of node i+1 that spring i needs.
-struct NodeIn { double zs[6], vs[2], ms[8], ss[8], zj[2], mj[2], sj[2]; };
-
-__device__ __forceinline__ void node_load(const TileRef& t, int U, int lt, int i, NodeIn& d) {
-    const int nx = 6 * U, nu = 2 * U, n = nx + nu;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) d.zs[c] = 0.0;
-    d.vs[0] = d.vs[1] = 0.0;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) { d.ms[c] = 0.0; d.ss[c] = 0.0; }
-    d.zj[0] = d.zj[1] = d.mj[0] = d.mj[1] = d.sj[0] = d.sj[1] = 0.0;
-    if (lt >= t.nloc) return;
-    const bool right = i < U - 1;
-    const double* zp = t.Z + (int64_t)lt * nx + 6 * i;
-    const double* vp = t.V + (int64_t)lt * nu + 2 * i;
-    const double* sp = t.SG + (int64_t)lt * n;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) { d.zs[c] = zp[c]; d.ss[c] = sp[6 * i + c]; }
-    d.vs[0] = vp[0]; d.vs[1] = vp[1];
-    d.ss[6] = sp[nx + 2 * i]; d.ss[7] = sp[nx + 2 * i + 1];
-    if (t.MU) {
-        const double* mp = t.MU + (int64_t)lt * n;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) d.ms[c] = mp[6 * i + c];
-        d.ms[6] = mp[nx + 2 * i]; d.ms[7] = mp[nx + 2 * i + 1];
-        if (right) { d.mj[0] = mp[6 * i + 6]; d.mj[1] = mp[6 * i + 7]; }
-    }
-    if (right) { d.zj[0] = zp[6]; d.zj[1] = zp[7]; d.sj[0] = sp[6 * i + 6]; d.sj[1] = sp[6 * i + 7]; }
-}
-
 // Spring i and node i of timestep lt; s_sp [T][U], s_flag [T] (cleared).
 // Contains one workgroup barrier.
 __device__ __forceinline__ void node_pass(const ChainArgs& A, const TileRef& t, const NodeIn& d, int lt, int i,
@@ -116,98 +69,26 @@ __device__ __forceinline__ void node_pass(const ChainArgs& A, const TileRef& t, 
     const bool active = lt < t.nloc;
     const bool right = active && i < U - 1;      // spring i exists
     if (active) {
-        uint32_t f = 0;
-#pragma unroll
-        for (int c = 0; c < 6; ++c)
-            if (!isfinite(d.zs[c])) f |= LEB_FLAG_BAD_INPUT;
-        if (!isfinite(d.vs[0]) || !isfinite(d.vs[1])) f |= LEB_FLAG_BAD_INPUT;
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            if (!isfinite(d.ss[c]) || !isfinite(d.ms[c]) || !(d.ss[c] >= 0.0)) f |= LEB_FLAG_BAD_INPUT;
-            if (fabs(d.ms[c]) > d.ss[c]) f |= LEB_FLAG_HULL_EXTENDED;
-        }
+        const uint32_t f = node_flags(d);
         if (f) atomicOr(&s_flag[lt], f);
     }
-    const IV<float> Dx = disp_interval(d.ms[0], d.ss[0]), Dz = disp_interval(d.ms[1], d.ss[1]);
-    const IV<float> Dth = disp_interval(d.ms[2], d.ss[2]);
-    const IV<float> Du1 = disp_interval(d.ms[6], d.ss[6]), Du2 = disp_interval(d.ms[7], d.ss[7]);
-
-    // constants with c folded in (all >= 0 for kL >= 0)
-    const double K3 = 3.0 * A.kL * A.c, K15 = 1.5 * A.kL * A.c, K1 = A.kL * A.c, K05 = 0.5 * A.kL * A.c;
-
-    // ---- spring i (nodes i, i+1)
-    div_ rx = {0.0, 0.0}, rz = {0.0, 0.0};       // spring i's terms for row i
-    IV<float> R[5];
-#pragma unroll
-    for (int q = 0; q < 5; ++q) R[q] = iv(0.0f, 0.0f);
-    uint32_t unb = 0;
-    if (right) {
-        SpringSetup st;
-        spring_setup_v(d.zs[0], d.zs[1], d.zj[0], d.zj[1], Dx, Dz, disp_interval(d.mj[0], d.sj[0]),
-                       disp_interval(d.mj[1], d.sj[1]), A.L0, st);
-        AccPrimal acc;
-        SpringPieces<float> pc;
-        const bool ok = spring_core<float, AccPrimal>(st.dxA, st.dxB, st.dz0, st.dz1, st.dz2, st.Dxi, st.Dzi,
-                                                      st.Dxj, st.Dzj, maskv(st.Dxi), maskv(st.Dzi),
-                                                      maskv(st.Dxj), maskv(st.Dzj), K3, K15, K1, K05, acc, pc);
-        SpringOut o = {};
-        if (ok) {
-            rx.lo = acc.a[S_CX].lo + acc.a[S_BX].lo; rx.hi = acc.a[S_CX].hi + acc.a[S_BX].hi;
-            rz.lo = acc.a[S_CZ].lo + acc.a[S_BZ].lo; rz.hi = acc.a[S_CZ].hi + acc.a[S_BZ].hi;
-            // row i+1 receives -(cross + node i's own pairs)
-            o.xlo = -(acc.a[S_CX].hi + acc.a[S_AX].hi); o.xhi = -(acc.a[S_CX].lo + acc.a[S_AX].lo);
-            o.zlo = -(acc.a[S_CZ].hi + acc.a[S_AZ].hi); o.zhi = -(acc.a[S_CZ].lo + acc.a[S_AZ].lo);
-#pragma unroll
-            for (int q = 0; q < 5; ++q) { o.L[q] = pc.L[q]; R[q] = pc.R[q]; }
-            o.unbounded = 0;
-        } else {
-            unb = 1;
-            o.unbounded = 1;
-            atomicOr(&s_flag[lt], LEB_FLAG_UNBOUNDED);
-        }
-        s_sp[lt * U + i] = o;
-    }
+    const NodeConsts K = node_consts(A.c, A.kL, A.L0);
+    SpringKeep k;
+    spring_step(K, d, right, k, &s_sp[lt * U + i]);
+    if (k.unb) atomicOr(&s_flag[lt], LEB_FLAG_UNBOUNDED);
     __syncthreads();      // spring terms and flags complete
-
-    // ---- node i: attitude block, shared position pairs, totals; the node's six rows out
     if (!active) return;
-    IV<float> L[5];
-#pragma unroll
-    for (int q = 0; q < 5; ++q) L[q] = iv(0.0f, 0.0f);
-    div_ ox = rx, oz = rz;
-    uint32_t row_unb = unb;
-    if (i > 0) {
-        const SpringOut& o = s_sp[lt * U + i - 1];
-        row_unb |= o.unbounded;
-        ox.lo += o.xlo; ox.hi += o.xhi; oz.lo += o.zlo; oz.hi += o.zhi;
-#pragma unroll
-        for (int q = 0; q < 5; ++q) L[q] = o.L[q];
-    }
-    NodeTerms nt;
-    node_terms(d.zs[2], d.vs[0] + d.vs[1], Dth, Du1, Du2, Dx, Dz, R, L, U > 1 && !row_unb, A.c, K15, K1, K05,
-               maskv(Dth), maskv(Du1), maskv(Du2), maskv(Dx), maskv(Dz), nt);
-#pragma unroll
-    for (int q = 0; q < 12; ++q) {
-        div_& acc = node_term_row(q) == 0 ? ox : oz;
-        const float a = nt.neg[q] ? nt.T[q].hi : nt.T[q].lo;
-        const float b = nt.neg[q] ? nt.T[q].lo : nt.T[q].hi;
-        acc.lo = __builtin_fma(nt.k[q], (double)a, acc.lo);
-        acc.hi = __builtin_fma(nt.k[q], (double)b, acc.hi);
-    }
     const uint32_t ft = s_flag[lt];
+    double lo34[2], hi34[2];
+    bool all_inf;
+    node_step(K, U, d, k, i > 0 ? &s_sp[lt * U + i - 1] : nullptr, ft, lo34, hi34, &all_inf);
     double lo[6], hi[6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) { lo[c] = 0.0; hi[c] = 0.0; }
-    if (ft & LEB_FLAG_BAD_INPUT) {
-#pragma unroll
-        for (int c = 0; c < 6; ++c) { lo[c] = -INFINITY; hi[c] = INFINITY; }
-    } else if (row_unb) {
-        lo[3] = lo[4] = -INFINITY; hi[3] = hi[4] = INFINITY;
-    } else {
-        // all lower-end summands are <= 0 and all upper-end summands >= 0,
-        // so 2^-45 relative covers every FP64 rounding in the sums
-        lo[3] = wlo64(ox.lo); hi[3] = whi64(ox.hi); lo[4] = wlo64(oz.lo); hi[4] = whi64(oz.hi);
+    for (int c = 0; c < 6; ++c) {
+        lo[c] = all_inf ? -INFINITY : 0.0;
+        hi[c] = all_inf ? INFINITY : 0.0;
     }
+    lo[3] = lo34[0]; hi[3] = hi34[0]; lo[4] = lo34[1]; hi[4] = hi34[1];
     const int64_t o = (int64_t)lt * nx + 6 * i;
     if (t.RLO) {
 #pragma unroll
@@ -215,16 +96,7 @@ __device__ __forceinline__ void node_pass(const ChainArgs& A, const TileRef& t, 
     }
     if (t.CB) {
 #pragma unroll
-        for (int c = 0; c < 6; ++c) {
-            double cb, rb;
-            if (isfinite(lo[c]) && isfinite(hi[c])) {
-                cb = 0.5 * (lo[c] + hi[c]);
-                rb = fmax(hi[c] - cb, cb - lo[c]);
-                rb = rb + fabs(rb) * 0x1p-50 + A.pad;
-            } else { cb = 0.0; rb = INFINITY; }
-            t.CB[o + c] = cb;
-            t.RB[o + c] = rb;
-        }
+        for (int c = 0; c < 6; ++c) row_zono(lo[c], hi[c], A.pad, &t.CB[o + c], &t.RB[o + c]);
     }
     if (t.FL && i == 0) t.FL[lt] = (ft & LEB_FLAG_BAD_INPUT) ? (ft & ~LEB_FLAG_UNBOUNDED) : ft;
 }

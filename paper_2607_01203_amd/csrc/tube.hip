@@ -36,9 +36,6 @@
 
 namespace leb {
 
-// Per-trajectory fixed-point state word.
-constexpr uint32_t FP_CERT = 1u;          // certified (frozen)
-constexpr uint32_t FP_OPEN = 1u << 31;    // this sweep: F(C) not inside C
 constexpr int FP_SLOTS = 4096;            // host-visible open counts, one per sweep (mod FP_SLOTS)
 
 // Fixed-point epilogue of the tube map (state == NULL for the plain map).
@@ -379,17 +376,19 @@ __global__ void fill_kernel(double* dst, int64_t count, double v) {
 
 static unsigned nblk(int64_t count) { return (unsigned)((count + 255) / 256); }
 
+// Relative allowance of the tube sums: a sum of m rounded products (and the 3
+// operations forming a weight) errs by at most gamma_{m+3} ~ (m+3) 2^-53
+// relative, in any order of accumulation; twice that covers both the sigma
+// sums and, through |c_bar| wid in the weights, the rounding of the centre sums.
+static double tube_wid(int N) { return fmax(0x1p-44, (6.0 * (N > 0 ? N - 1 : 0) + 4.0) * 0x1p-52); }
+
 static int launch_tube(int B, int N, int U, const double* phi, const double* e, const double* cbar,
                        const double* rbar, double* mu, double* sigma, const TubeFP& fp, hipStream_t s) {
     TubeArgs a;
     a.cbar = cbar; a.rbar = rbar;
     for (int q = 0; q < 6; ++q) a.e[q] = e[q];
     a.mu = mu; a.sigma = sigma; a.B = B; a.N = N; a.U = U;
-    // A sum of m rounded products (and the 3 operations forming a weight)
-    // errs by at most gamma_{m+3} ~ (m+3) 2^-53 relative, in any order of
-    // accumulation; twice that covers both the sigma sums and, through
-    // |c_bar| wid in the weights, the rounding of the centre sums.
-    a.wid = fmax(0x1p-44, (6.0 * (N > 0 ? N - 1 : 0) + 4.0) * 0x1p-52);
+    a.wid = tube_wid(N);
     const int64_t cols = (int64_t)B * U;
     if (cols == 0 || N == 0) return LEB_OK;
     const int64_t gx = (cols + 15) / 16;
@@ -421,7 +420,7 @@ int launch_disturbance_tube(int B, int N, int U, const double* phi, const double
     TubeArgs a = {};
     for (int q = 0; q < 6; ++q) a.e[q] = e[q];
     a.mu = mu; a.sigma = sigma; a.B = B; a.N = N; a.U = U;
-    a.wid = fmax(0x1p-44, (6.0 * (N > 0 ? N - 1 : 0) + 4.0) * 0x1p-52);
+    a.wid = tube_wid(N);
     const int64_t count = (int64_t)B * N * 8 * U;
     if (count == 0) return LEB_OK;
     const int64_t blocks = std::min<int64_t>((count + 255) / 256, 1024);
