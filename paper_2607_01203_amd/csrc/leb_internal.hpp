@@ -41,7 +41,8 @@ int launch_fill_zero(int64_t count, double* r_lo, double* r_hi, double* c_bar, d
 size_t pbh_smem_bytes(int U);
 size_t bwd_smem_bytes(int U);
 int launch_tube_map(int B, int N, int U, const double* phi, const double* e, const double* cbar,
-                    const double* rbar, double* mu, double* sigma, hipStream_t s);
+                    const double* rbar, double* mu, double* sigma, hipStream_t s,
+                    double scale = 1.0, double shift = 0.0);
 // tube of the residual zonotopes (0, pad) at every step (the disturbance-only tube)
 int launch_disturbance_tube(int B, int N, int U, const double* phi, const double* e, double pad, double* mu,
                             double* sigma, hipStream_t s);

@@ -59,10 +59,32 @@ __device__ __forceinline__ void normal_cdf(float z, float* Phi, float* ex) {
     *Phi = fmaf(0.5f, copysignf(erf_abs, z), 0.5f);
     *ex = e;
 }
-__device__ __forceinline__ float gelu_f(float z) {
+// GELU of the training forward: z Phi(z) with Phi from normal_cdf, the same
+// approximation the backward differentiates.
+__device__ __forceinline__ float gelu_train_f(float z) {
     float P, e;
     normal_cdf(z, &P, &e);
     return z * P;
+}
+// GELU of inference: z Phi(z) = max(z, 0) - |z| erfc(|z| / sqrt 2) / 2, with erfc from
+// Abramowitz and Stegun, formula 7.1.28 (|error of erf| <= 3e-7):
+// erf(x) ~ 1 - (1 + a1 x + ... + a6 x^6)^-16, x >= 0 -- one reciprocal and no
+// exponential.  The coefficients below are a_i / sqrt(2)^i, so the
+// polynomial is evaluated at |z|; a large |z| drives the 16th power to +inf
+// and the correction to 0.
+__device__ __forceinline__ float gelu_f(float z) {
+    const float x = fabsf(z);
+    float p = fmaf(x, 5.38297500e-6f, 4.88906356e-5f);
+    p = fmaf(x, p, 3.80035750e-5f);
+    p = fmaf(x, p, 3.27762632e-3f);
+    p = fmaf(x, p, 2.11410061e-2f);
+    p = fmaf(x, p, 4.98673470e-2f);
+    p = fmaf(x, p, 1.0f);
+    p = p * p;
+    p = p * p;
+    p = p * p;
+    p = p * p;
+    return fmaf(-0.5f * x, __builtin_amdgcn_rcpf(p), fmaxf(z, 0.0f));
 }
 __device__ __forceinline__ float gelu_grad_f(float z) {
     float P, e;
@@ -259,7 +281,7 @@ __global__ void __launch_bounds__(256) mlp_fwd_kernel(FwdArgs A) {
                     const int r = rt * 16 + lr;
                     bf16x4 av;
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) av[i] = (__bf16)gelu_f(acc[s][rt][i]);
+                    for (int i = 0; i < 4; ++i) av[i] = (__bf16)(SAVE ? gelu_train_f(acc[s][rt][i]) : gelu_f(acc[s][rt][i]));
                     *reinterpret_cast<bf16x4*>(nxt + r * ldA + c) = av;
                     if (SAVE) {
                         const int row = row0 + r;

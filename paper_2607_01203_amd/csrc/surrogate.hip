@@ -189,17 +189,23 @@ extern "C" int leb_fixed_point_learned(const leb_dynamics* dyn, int32_t batch, i
         if ((rc = sw_get(nodes, units * nx))) return rc;
         // C_0: disturbance-only tube
         if ((rc = launch_disturbance_tube(batch, N, U, phi, e, opt->pad, mu, sigma, s))) return rc;
-        // surrogate sweeps: C <- T(surrogate bound of C)
+        // surrogate sweeps: C <- T(surrogate bound of C); the last one stores sigma
+        // inflated, sigma (1 + margin) + inflate_abs: the warm start above the
+        // surrogate's fixed point
         for (int t = 0; t < ws->sweeps; ++t) {
             if ((rc = surrogate_chain_sweep(ws->net, z, v, mu, sigma, (int)nodes, U, dyn->rest_len, opt->pad, g_sw.cb,
                                             g_sw.rb, s)))
                 return rc;
-            if ((rc = launch_tube_map(batch, N, U, phi, e, g_sw.cb, g_sw.rb, mu, sigma, s))) return rc;
+            const bool last = t == ws->sweeps - 1;
+            if ((rc = launch_tube_map(batch, N, U, phi, e, g_sw.cb, g_sw.rb, mu, sigma, s, last ? 1.0 + ws->margin : 1.0,
+                                      last ? opt->inflate_abs : 0.0)))
+                return rc;
         }
-        // warm start above the surrogate's fixed point
-        hipLaunchKernelGGL(scale_sigma_kernel, dim3(nbk(units * n)), dim3(256), 0, s, sigma, units * n,
-                           1.0 + ws->margin, opt->inflate_abs);
-        if (hipGetLastError() != hipSuccess) return LEB_EDEVICE;
+        if (ws->sweeps == 0) {
+            hipLaunchKernelGGL(scale_sigma_kernel, dim3(nbk(units * n)), dim3(256), 0, s, sigma, units * n,
+                               1.0 + ws->margin, opt->inflate_abs);
+            if (hipGetLastError() != hipSuccess) return LEB_EDEVICE;
+        }
     }
     leb_fp_options o = *opt;
     o.warm = 1;

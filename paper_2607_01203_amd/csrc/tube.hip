@@ -51,6 +51,7 @@ struct TubeArgs {
     double e[6];
     double* mu; double* sigma;                // [B][N][n] out
     double wid;        // relative rounding allowance of the tube sums
+    double scale, shift;   // plain map: sigma stored as sigma * scale + shift (1, 0: as computed)
     int B, N, U;
 };
 
@@ -260,7 +261,7 @@ __global__ void __launch_bounds__(256) tube_map_kernel(const double* __restrict_
                 const double mF = am[i];
                 // sums of nonnegative terms, rounded upward; 2^-1000 covers any flushed subnormal part
                 const double sF = k > sjl ? INFINITY : as[i] + as[i] * A.wid + 0x1p-1000;
-                double so = sF;
+                double so = sF * A.scale + A.shift;
                 if (fp) {
                     // [mF - sF, mF + sF] inside [mi - si, mi + si], with the rounding of the
                     // test covered; a tube that is not finite is never accepted
@@ -320,12 +321,16 @@ __global__ void __launch_bounds__(256) fp_state_kernel(uint32_t* state, int B, u
 // uncertified trajectory takes the latest iterate C_T from buffer T & 1.
 // Buffer 0 is the caller's; buffer 1 is copied into it where needed.
 __global__ void fp_final_kernel(const double* xm1, const double* xs1, double* mu, double* sg,
-                                const uint32_t* state, int64_t per_traj, int64_t count, int last_sweep) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= count) return;
-    const uint32_t st = state[q / per_traj];
+                                const uint32_t* state, int64_t per_traj, int last_sweep) {
+    const int b = blockIdx.x;        // one trajectory per blockIdx.x
+    const uint32_t st = state[b];
     const int src = (st & FP_CERT) ? (int)(((st >> 1) - 1) & 1u) : (last_sweep & 1);
-    if (src == 1) { mu[q] = xm1[q]; sg[q] = xs1[q]; }
+    if (src == 0) return;
+    const int64_t base = (int64_t)b * per_traj;
+    for (int64_t q = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; q < per_traj; q += (int64_t)gridDim.y * blockDim.x) {
+        mu[base + q] = xm1[base + q];
+        sg[base + q] = xs1[base + q];
+    }
 }
 
 __global__ void fp_init_kernel(uint32_t* state, int B) {
@@ -337,30 +342,41 @@ __global__ void fp_init_kernel(uint32_t* state, int B) {
 // The tube of residuals (c_bar, rho_bar) = (0, pad) at every step -- the
 // disturbance-only tube -- is the same for every (trajectory, node):
 //   mu_k = 0,  sigma_k[r] = sum_{j<k} sum_q |Phi_{k-j-1}[r][q]| (e_q + pad),
-// rounded upward like the tube map.  Each workgroup forms the N x 8 table in
-// LDS and writes its share of the broadcast.
+// rounded upward like the tube map (the per-lag sums are added in order of
+// the lag; any order of a sum of nonnegative terms is covered by wid).  Each
+// workgroup forms the N x 8 table in LDS and writes its rows of the broadcast.
 __global__ void __launch_bounds__(256) disturbance_tube_kernel(const double* __restrict__ phi, TubeArgs A, double pad,
-                                                               int64_t count) {
-    extern __shared__ double tab[];       // [N][8]
+                                                               int rows) {
+    extern __shared__ double tab[];       // [N][8], then the per-lag sums [N-1][8]
     const int N = A.N, U = A.U, nx = 6 * U, n = 8 * U;
-    for (int t = threadIdx.x; t < N * 8; t += 256) {
-        const int k = t >> 3, r = t & 7;
+    double* g = tab + N * 8;
+    for (int t = threadIdx.x; t < (N - 1) * 8; t += 256) {
+        const double* P = phi + (int64_t)t * 6;       // Phi_d[r][.], t = 8 d + r
         double acc = 0.0;
-        for (int j = 0; j < k; ++j) {
-            const double* P = phi + (int64_t)(k - j - 1) * 48 + r * 6;
 #pragma unroll
-            for (int q = 0; q < 6; ++q) acc = __builtin_fma(fabs(P[q]), A.e[q] + pad, acc);
-        }
-        tab[t] = k > 0 ? acc + acc * A.wid + 0x1p-1000 : 0.0;
+        for (int q = 0; q < 6; ++q) acc = __builtin_fma(fabs(P[q]), A.e[q] + pad, acc);
+        g[t] = acc;
     }
     __syncthreads();
-    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < count; q += (int64_t)gridDim.x * 256) {
-        const int64_t bk = q / n;
-        const int k = (int)(bk % N);
-        const int row = (int)(q - bk * n);
-        const int rr = row < nx ? row % 6 : 6 + ((row - nx) & 1);
-        A.mu[q] = 0.0;
-        A.sigma[q] = tab[k * 8 + rr];
+    if (threadIdx.x < 8) {
+        const int r = threadIdx.x;
+        double acc = 0.0;
+        tab[r] = 0.0;
+        for (int k = 1; k < N; ++k) {
+            acc += g[(k - 1) * 8 + r];
+            tab[k * 8 + r] = acc + acc * A.wid + 0x1p-1000;
+        }
+    }
+    __syncthreads();
+    for (int row = blockIdx.x; row < rows; row += gridDim.x) {       // row = (trajectory, step)
+        const int k = row % N;
+        double* mrow = A.mu + (int64_t)row * n;
+        double* srow = A.sigma + (int64_t)row * n;
+        for (int c = threadIdx.x; c < n; c += 256) {
+            const int rr = c < nx ? c % 6 : 6 + ((c - nx) & 1);
+            mrow[c] = 0.0;
+            srow[c] = tab[k * 8 + rr];
+        }
     }
 }
 
@@ -383,9 +399,11 @@ static unsigned nblk(int64_t count) { return (unsigned)((count + 255) / 256); }
 static double tube_wid(int N) { return fmax(0x1p-44, (6.0 * (N > 0 ? N - 1 : 0) + 4.0) * 0x1p-52); }
 
 static int launch_tube(int B, int N, int U, const double* phi, const double* e, const double* cbar,
-                       const double* rbar, double* mu, double* sigma, const TubeFP& fp, hipStream_t s) {
+                       const double* rbar, double* mu, double* sigma, const TubeFP& fp, hipStream_t s,
+                       double scale = 1.0, double shift = 0.0) {
     TubeArgs a;
     a.cbar = cbar; a.rbar = rbar;
+    a.scale = scale; a.shift = shift;
     for (int q = 0; q < 6; ++q) a.e[q] = e[q];
     a.mu = mu; a.sigma = sigma; a.B = B; a.N = N; a.U = U;
     a.wid = tube_wid(N);
@@ -421,18 +439,19 @@ int launch_disturbance_tube(int B, int N, int U, const double* phi, const double
     for (int q = 0; q < 6; ++q) a.e[q] = e[q];
     a.mu = mu; a.sigma = sigma; a.B = B; a.N = N; a.U = U;
     a.wid = tube_wid(N);
-    const int64_t count = (int64_t)B * N * 8 * U;
-    if (count == 0) return LEB_OK;
-    const int64_t blocks = std::min<int64_t>((count + 255) / 256, 1024);
-    hipLaunchKernelGGL(disturbance_tube_kernel, dim3((unsigned)blocks), dim3(256), (size_t)N * 8 * sizeof(double), s,
-                       phi, a, pad, count);
+    const int64_t rows = (int64_t)B * N;
+    if (rows == 0 || U == 0) return LEB_OK;
+    if (rows > 0x7fffffff) return LEB_EINVAL;
+    const int blocks = (int)std::min<int64_t>(rows, 2048);
+    hipLaunchKernelGGL(disturbance_tube_kernel, dim3((unsigned)blocks), dim3(256), (size_t)(2 * N) * 8 * sizeof(double),
+                       s, phi, a, pad, (int)rows);
     return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
 }
 
 int launch_tube_map(int B, int N, int U, const double* phi, const double* e, const double* cbar,
-                    const double* rbar, double* mu, double* sigma, hipStream_t s) {
+                    const double* rbar, double* mu, double* sigma, hipStream_t s, double scale, double shift) {
     TubeFP none{nullptr, nullptr, nullptr, 0.0, 0.0};
-    return launch_tube(B, N, U, phi, e, cbar, rbar, mu, sigma, none, s);
+    return launch_tube(B, N, U, phi, e, cbar, rbar, mu, sigma, none, s, scale, shift);
 }
 
 // ------------------------------------------------------------ workspace
@@ -527,7 +546,7 @@ extern "C" int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int
     // from buffer (t-1) & 1 and writes C_t to buffer t & 1
     double* xm[2] = {mu, xm1};
     double* xs[2] = {sigma, xs1};
-    const int64_t cnt = units * n, per = (int64_t)N * n;
+    const int64_t per = (int64_t)N * n;
     auto ok = [](hipError_t e_) { return e_ == hipSuccess; };
     hipLaunchKernelGGL(fp_init_kernel, dim3(nblk(batch + 1)), dim3(256), 0, s, state, batch);
     if (!opt->warm)         // C_0: the disturbance-only tube (LEB = 0), below the fixed point
@@ -574,7 +593,8 @@ extern "C" int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int
         if (open == 0 || t == opt->max_sweeps) break;
         ++t;
     }
-    hipLaunchKernelGGL(fp_final_kernel, dim3(nblk(cnt)), dim3(256), 0, s, xm1, xs1, mu, sigma, state, per, cnt, t);
+    hipLaunchKernelGGL(fp_final_kernel, dim3(batch, (unsigned)std::min<int64_t>((per + 255) / 256, 16)), dim3(256), 0,
+                       s, xm1, xs1, mu, sigma, state, per, t);
     hipLaunchKernelGGL(cert_out_kernel, dim3(nblk(batch)), dim3(256), 0, s, state, certified, batch);
     *sweeps_out = t;
     return ok(hipGetLastError()) ? LEB_OK : LEB_EDEVICE;
