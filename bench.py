@@ -14,8 +14,10 @@ library's kernels on certified bounds of other trajectories.
 value = 10,240 / (learned ms per solve); the plain rate is reported too.
 
 Prints ONE JSON line.  Extra objects:
-  roofline      dominant kernel (the bound kernel) at the solve's launch
-                shape, timed with HIP events on its stream;
+  roofline      dominant kernel: the tube map of the certified sweeps (FP64
+                MFMA), its launches in one learned solve timed with HIP
+                events on the solve's stream; roofline_bound: the bound
+                kernel of the same sweeps (HBM);
   cpu_baseline  the FP64 oracle solving (and certifying) the same fixed
                 point on a bounded sample of trajectories, on host cores.
 """
@@ -33,6 +35,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
+# HBM traffic of one fixed-point tube-map launch at the bench shape, FETCH_SIZE and
+# WRITE_SIZE (KiB per dispatch, rocprofv3 --pmc), and the factors that map each
+# counter to bytes, measured on a copy kernel of known size; None until taken for
+# the kernel as it is now.
+TUBE_PMC_KIB = (36101, 35854)
+FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 matrix (= vector) peak
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # lane-ops/s of non-packed VALU issue (39.3 T)
 
@@ -64,6 +72,21 @@ def copy_calibration(nbytes):
         torch.neg(src, out=dst)
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration_bytes": nbytes, "launches": 5}))
+
+
+def tube_flops_per_column(N):
+    """Algorithmic FLOPs of the tube map per (trajectory, node) column: for
+    every step k and earlier step j < k, the 8 x 6 block products Phi c_bar
+    (centre) and |Phi| w (width), 2 FLOPs per multiply-add."""
+    return 2 * 2 * 8 * 6 * (N * (N - 1) // 2)
+
+
+def tube_bytes_per_launch(B, N, nx, nu):
+    """Algorithmic HBM bytes of the fixed-point tube-map launch: reads c_bar,
+    rho_bar [B][N][nx] and C_{t-1} (mu, sigma) [B][N][nx+nu] for the
+    containment test, writes C_t (mu, sigma), all FP64."""
+    n = nx + nu
+    return 8 * B * N * (2 * nx + 2 * n + 2 * n)
 
 
 def bytes_per_unit_fixed_point_launch(nx, nu):
@@ -133,34 +156,38 @@ def main():
     ms_per_step = learned_ms
     value = units * 1e3 / learned_ms
 
-    # dominant kernel: the bound launch of a sweep, at the certified tube
-    cb = torch.empty((B, N, nx), dtype=torch.float64, device=dev)
-    rb = torch.empty_like(cb)
-    out = {"r_lo": None, "r_hi": None, "c_bar": cb, "rho_bar": rb, "flags": None}
-
-    def bound_launch():
-        rc = leb.lib().leb_analytic_bound(
-            ctypes.byref(dyn), B, N, leb._dev_ptr(z, "z"), leb._dev_ptr(v, "v"), leb._dev_ptr(mu, "mu"),
-            leb._dev_ptr(sg, "sigma"), None, None, leb._dev_ptr(cb, "c"), leb._dev_ptr(rb, "r"), 0.0, None,
-            leb._stream(stream))
-        leb._check(rc)
-
-    for _ in range(3):
-        bound_launch()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.kernel_reps):
-        bound_launch()
-    e1.record(stream)
+    # Dominant kernel: the tube map of the certified sweeps (6 of the ~11 launches
+    # of a learned solve, the largest share of its time).  Its launches in one
+    # learned solve are timed with HIP events on the solve's stream; the
+    # speculative sweep after the certifying one is left out.
+    leb.launch_timing(True)
+    _, _, _, sw_t = leb.fixed_point_learned(dyn, z, v, phi, tp.e, net, sweeps=args.surrogate_sweeps,
+                                            margin=args.margin, tol=1e-6, max_sweeps=200)
     torch.cuda.synchronize()
-    kern_us = e0.elapsed_time(e1) * 1e3 / args.kernel_reps
+    tube_ms = leb.launch_times(leb.LAUNCH_TUBE)[:sw_t]
+    bound_ms = leb.launch_times(leb.LAUNCH_BOUND)[:sw_t]
+    leb.launch_timing(False)
+    U = nx // 6
+    tube_us = 1e3 * float(np.mean(tube_ms))
+    tflops = tube_flops_per_column(N) * B * U / (tube_us * 1e-6) / 1e12
+    tube_bytes = tube_bytes_per_launch(B, N, nx, nu)
+    traffic = None
+    if TUBE_PMC_KIB is not None:
+        traffic = int(TUBE_PMC_KIB[0] * 1024 * FETCH_SCALE + TUBE_PMC_KIB[1] * 1024 * WRITE_SCALE)
+    roofline = {"bound": "mfma", "achieved": round(tflops, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(tflops / FP64_PEAK_TFLOPS, 4), "traffic": traffic,
+                "kernel": "tube_map_kernel", "launch_us": round(tube_us, 2), "launches": len(tube_ms),
+                "units_per_launch": B * U, "flops_per_unit": tube_flops_per_column(N),
+                "hbm_bytes_per_launch": tube_bytes,
+                "hbm_frac": round(tube_bytes / (tube_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+    # the bound kernel of the same sweeps
+    bound_us = 1e3 * float(np.mean(bound_ms))
     bpu = bytes_per_unit_fixed_point_launch(nx, nu)
-    achieved = bpu * units / (kern_us * 1e-6) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "pbh_chain_fwd", "launch_us": round(kern_us, 3), "units_per_launch": units,
-                "bytes_per_unit": bpu}
+    achieved = bpu * units / (bound_us * 1e-6) / 1e9
+    roofline_bound = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": round(achieved / HBM_PEAK_GBS, 4), "kernel": "pbh_chain_fwd",
+                      "launch_us": round(bound_us, 2), "launches": len(bound_ms), "units_per_launch": units,
+                      "bytes_per_unit": bpu}
 
     nn_line = None if args.no_extra else nn_roofline(leb, W, dev, stream, args)
     batch_line = None if args.no_extra else batched_uneven(leb, W, dev, stream, args)
@@ -186,7 +213,7 @@ def main():
                     "sigma_over_plain_max": round(float(excess.max()), 6), "training": train_info},
         "plain": {"value": round(units * 1e3 / plain_ms, 1), "ms_per_solve": round(plain_ms, 4),
                   "certified_sweeps": plain_sweeps, "certified": plain_cert},
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "cpu_baseline": cpu, "roofline_bound": roofline_bound,
         "roofline_nn": nn_line, "batched_uneven": batch_line,
     }
     print(json.dumps(line))

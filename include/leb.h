@@ -208,6 +208,20 @@ int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int32_t N, con
                           double* mu, double* sigma, uint32_t* certified, int32_t* sweeps_out, void* stream);
 
 /*
+ * Launch timing of the fixed-point sweeps (instrumentation, off by default).
+ * leb_launch_timing(1) clears the record and starts timing; from then on
+ * leb_fixed_point_solve (and leb_fixed_point_learned) launch each sweep's
+ * bound kernel (kernel 0) and tube-map kernel (kernel 1) with a pair of HIP
+ * events taken at the kernel's start and end, up to 256 launches each;
+ * leb_launch_timing(0) stops.  leb_launch_times writes the durations in ms of kernel's recorded
+ * launches, in launch order, to ms[0 .. min(count, cap)) (waiting for them)
+ * and their number to *count.  A sweep enqueued after the certifying one
+ * exits at once and is recorded too.
+ */
+int leb_launch_timing(int32_t enable);
+int leb_launch_times(int32_t kernel, float* ms, int32_t cap, int32_t* count);
+
+/*
  * Learned warm start (section V: the fixed point is started from a tube the
  * surrogate predicts; every accepted tube is still certified by the plain
  * bound).  A GELU MLP with widths [d_0, ..., d_L] (L <= 8, every width in

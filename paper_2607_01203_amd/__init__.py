@@ -93,6 +93,11 @@ def lib():
         L.leb_tube_map.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp,
                                    ctypes.POINTER(ctypes.c_double), vp, vp, vp, vp, vp]
         L.leb_tube_map.restype = ctypes.c_int
+        L.leb_launch_timing.argtypes = [ctypes.c_int32]
+        L.leb_launch_timing.restype = ctypes.c_int
+        L.leb_launch_times.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_float), ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_int32)]
+        L.leb_launch_times.restype = ctypes.c_int
         L.leb_fixed_point_solve.argtypes = [ctypes.POINTER(Dynamics), ctypes.c_int32, ctypes.c_int32, vp, vp,
                                             vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(FPOptions),
                                             vp, vp, vp, ctypes.POINTER(ctypes.c_int32), vp]
@@ -254,6 +259,25 @@ def leb_analytic(dyn: Dynamics, z, v, sigma, mu=None):
 def _host6(e):
     arr = (ctypes.c_double * 6)(*[float(x) for x in e])
     return arr
+
+
+LAUNCH_BOUND, LAUNCH_TUBE = 0, 1
+
+
+def launch_timing(enable: bool):
+    """Start (clearing the record) or stop timing the fixed-point sweeps'
+    bound and tube-map launches (see leb.h: leb_launch_timing)."""
+    _check(lib().leb_launch_timing(1 if enable else 0))
+
+
+def launch_times(kernel: int):
+    """Durations in ms of the recorded launches of kernel (LAUNCH_BOUND or
+    LAUNCH_TUBE), in launch order."""
+    n = ctypes.c_int32(0)
+    _check(lib().leb_launch_times(kernel, None, 0, ctypes.byref(n)))
+    buf = (ctypes.c_float * max(1, n.value))()
+    _check(lib().leb_launch_times(kernel, buf, n.value, ctypes.byref(n)))
+    return [float(buf[i]) for i in range(n.value)]
 
 
 def tube_map(n_units, phi, e, c_bar, rho_bar, stream=None, out=None):

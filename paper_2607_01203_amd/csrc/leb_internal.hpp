@@ -35,7 +35,7 @@ size_t pbh_smem_bytes_T(int U, int T);
 int launch_pbh_chain(const leb_dynamics* dyn, int64_t units, const double* z, const double* v,
                      const double* mu, const double* sigma, double* r_lo, double* r_hi, double* c_bar,
                      double* rho_bar, double pad, uint32_t* flags, hipStream_t stream,
-                     const uint32_t* open = nullptr);
+                     const uint32_t* open = nullptr, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 int launch_fill_zero(int64_t count, double* r_lo, double* r_hi, double* c_bar, double* rho_bar, double pad,
                      uint32_t* flags, int64_t nflags, hipStream_t stream);
 size_t pbh_smem_bytes(int U);

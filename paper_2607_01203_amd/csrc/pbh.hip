@@ -34,6 +34,7 @@
 // the loads and the stores of the node's six output rows are coalesced.
 // The lane evaluates spring i (between nodes i and i+1), hands node i+1
 // its terms through LDS, then evaluates node i's two rows.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -152,7 +153,8 @@ size_t pbh_smem_bytes(int U) { return pbh_smem_bytes_T(U, PBH_BLOCK / U); }
 
 int launch_pbh_chain(const leb_dynamics* dyn, int64_t units, const double* z, const double* v,
                      const double* mu, const double* sigma, double* r_lo, double* r_hi, double* c_bar,
-                     double* rho_bar, double pad, uint32_t* flags, hipStream_t stream, const uint32_t* open) {
+                     double* rho_bar, double pad, uint32_t* flags, hipStream_t stream, const uint32_t* open,
+                     hipEvent_t ev0, hipEvent_t ev1) {
     ChainArgs a;
     a.z = z; a.v = v; a.mu = mu; a.sigma = sigma;
     a.r_lo = r_lo; a.r_hi = r_hi; a.c_bar = c_bar; a.rho_bar = rho_bar; a.flags = flags;
@@ -167,7 +169,11 @@ int launch_pbh_chain(const leb_dynamics* dyn, int64_t units, const double* z, co
     a.pad = pad;
     int64_t blocks = (units + a.T - 1) / a.T;
     if (blocks > 0x7fffffff) return LEB_EINVAL;
-    hipLaunchKernelGGL(pbh_chain_fwd, dim3((unsigned)blocks), dim3(PBH_BLOCK), pbh_smem_bytes(a.U), stream, a);
+    if (ev0)        // timed: events at the kernel's start and end
+        hipExtLaunchKernelGGL(pbh_chain_fwd, dim3((unsigned)blocks), dim3(PBH_BLOCK), pbh_smem_bytes(a.U), stream, ev0,
+                              ev1, 0, a);
+    else
+        hipLaunchKernelGGL(pbh_chain_fwd, dim3((unsigned)blocks), dim3(PBH_BLOCK), pbh_smem_bytes(a.U), stream, a);
     return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
 }
 

@@ -22,6 +22,7 @@
 //   C <- F(C) (1 + tol) + abs
 // converges to one of them, about tol above C*.  A trajectory is certified
 // (and frozen) by the sweep that shows F(C) inside C.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <float.h>
 #include <math.h>
@@ -400,7 +401,7 @@ static double tube_wid(int N) { return fmax(0x1p-44, (6.0 * (N > 0 ? N - 1 : 0) 
 
 static int launch_tube(int B, int N, int U, const double* phi, const double* e, const double* cbar,
                        const double* rbar, double* mu, double* sigma, const TubeFP& fp, hipStream_t s,
-                       double scale = 1.0, double shift = 0.0) {
+                       double scale = 1.0, double shift = 0.0, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
     TubeArgs a;
     a.cbar = cbar; a.rbar = rbar;
     a.scale = scale; a.shift = shift;
@@ -429,7 +430,10 @@ static int launch_tube(int B, int N, int U, const double* phi, const double* e, 
         dyn_max = cap;
     }
     if (smem > dyn_max) return LEB_ENOTSUP;     // N <= 83
-    hipLaunchKernelGGL(tube_map_kernel, dim3((unsigned)gx, gy), dim3(256), smem, s, phi, a, fp);
+    if (ev0)        // timed: events at the kernel's start and end
+        hipExtLaunchKernelGGL(tube_map_kernel, dim3((unsigned)gx, gy), dim3(256), smem, s, ev0, ev1, 0, phi, a, fp);
+    else
+        hipLaunchKernelGGL(tube_map_kernel, dim3((unsigned)gx, gy), dim3(256), smem, s, phi, a, fp);
     return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
 }
 
@@ -492,9 +496,58 @@ static int ws_host() {
     return LEB_OK;
 }
 
+// Launch timing of the fixed-point sweeps (off unless enabled): a pair of HIP
+// events per bound and tube-map launch, recorded by the launch itself at the
+// kernel's start and end, in launch order.
+struct LaunchTiming {
+    std::mutex mu;
+    bool on = false;
+    std::vector<hipEvent_t> ev[2];      // (start, stop) pairs per kernel
+    int used[2] = {0, 0};
+};
+static LaunchTiming g_lt;
+constexpr int LT_PAIRS = 256;
+
+// the next event pair of kernel (0: bound, 1: tube map), or false when off or full
+static bool lt_pair(int kernel, hipEvent_t* e0, hipEvent_t* e1) {
+    *e0 = *e1 = nullptr;
+    if (!g_lt.on || g_lt.used[kernel] >= LT_PAIRS) return false;
+    std::vector<hipEvent_t>& ev = g_lt.ev[kernel];
+    const size_t k = 2 * (size_t)g_lt.used[kernel];
+    while (ev.size() < k + 2) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return false;
+        ev.push_back(e);
+    }
+    *e0 = ev[k];
+    *e1 = ev[k + 1];
+    ++g_lt.used[kernel];
+    return true;
+}
+
 }  // namespace leb
 
 using namespace leb;
+
+extern "C" int leb_launch_timing(int32_t enable) {
+    std::lock_guard<std::mutex> lock(g_lt.mu);
+    g_lt.on = enable != 0;
+    g_lt.used[0] = g_lt.used[1] = 0;
+    return LEB_OK;
+}
+
+extern "C" int leb_launch_times(int32_t kernel, float* ms, int32_t cap, int32_t* count) {
+    if (kernel < 0 || kernel > 1 || !count || cap < 0 || (cap > 0 && !ms)) return LEB_EINVAL;
+    std::lock_guard<std::mutex> lock(g_lt.mu);
+    const int n = g_lt.used[kernel];
+    *count = n;
+    for (int i = 0; i < n && i < cap; ++i) {
+        if (hipEventSynchronize(g_lt.ev[kernel][2 * i + 1]) != hipSuccess) return LEB_EDEVICE;
+        if (hipEventElapsedTime(&ms[i], g_lt.ev[kernel][2 * i], g_lt.ev[kernel][2 * i + 1]) != hipSuccess)
+            return LEB_EDEVICE;
+    }
+    return LEB_OK;
+}
 
 extern "C" int leb_tube_map(int32_t batch, int32_t N, int32_t n_units, const double* phi, const double* e,
                             const double* c_bar, const double* rho_bar, double* mu, double* sigma,
@@ -552,14 +605,18 @@ extern "C" int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int
     if (!opt->warm)         // C_0: the disturbance-only tube (LEB = 0), below the fixed point
         if ((rc = launch_disturbance_tube(batch, N, U, phi, e, opt->pad, mu, sigma, s))) return rc;
     volatile uint32_t* hopen = g_ws.host_open;
+    std::lock_guard<std::mutex> lt_lock(g_lt.mu);
     auto sweep = [&](int t) -> int {
         const int a = (t - 1) & 1, w = t & 1;
+        hipEvent_t b0, b1, t0, t1;
+        lt_pair(0, &b0, &b1);
+        lt_pair(1, &t0, &t1);
         int r = launch_pbh_chain(dyn, units, z, v, xm[a], xs[a], nullptr, nullptr, cb, rb, opt->pad, nullptr, s,
-                                 state + batch);
+                                 state + batch, b0, b1);
         if (r) return r;
         hopen[t % FP_SLOTS] = 0xffffffffu;
         const TubeFP fp{xm[a], xs[a], state, opt->tol, opt->inflate_abs};
-        if ((r = launch_tube(batch, N, U, phi, e, cb, rb, xm[w], xs[w], fp, s))) return r;
+        if ((r = launch_tube(batch, N, U, phi, e, cb, rb, xm[w], xs[w], fp, s, 1.0, 0.0, t0, t1))) return r;
         hipLaunchKernelGGL(fp_state_kernel, dim3(1), dim3(256), 0, s, state, batch, g_ws.host_open_dev, t);
         return ok(hipGetLastError()) ? LEB_OK : LEB_EDEVICE;
     };
