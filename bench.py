@@ -14,10 +14,10 @@ library's kernels on certified bounds of other trajectories.
 value = 10,240 / (learned ms per solve); the plain rate is reported too.
 
 Prints ONE JSON line.  Extra objects:
-  roofline      dominant kernel: the tube map of the certified sweeps (FP64
-                MFMA), its launches in one learned solve timed with HIP
-                events on the solve's stream; roofline_bound: the bound
-                kernel of the same sweeps (HBM);
+  roofline      dominant kernel: the tube map of the certified sweeps (HBM;
+                its FP64 MFMA rate beside), its launches in one learned
+                solve timed with HIP events on the solve's stream;
+                roofline_bound: the bound kernel of the same sweeps (HBM);
   cpu_baseline  the FP64 oracle solving (and certifying) the same fixed
                 point on a bounded sample of trajectories, on host cores.
 """
@@ -39,7 +39,7 @@ HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
 # WRITE_SIZE (KiB per dispatch, rocprofv3 --pmc), and the factors that map each
 # counter to bytes, measured on a copy kernel of known size; None until taken for
 # the kernel as it is now.
-TUBE_PMC_KIB = (36101, 35854)
+TUBE_PMC_KIB = None
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 matrix (= vector) peak
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # lane-ops/s of non-packed VALU issue (39.3 T)
@@ -75,25 +75,30 @@ def copy_calibration(nbytes):
 
 
 def tube_flops_per_column(N):
-    """Algorithmic FLOPs of the tube map per (trajectory, node) column: for
-    every step k and earlier step j < k, the 8 x 6 block products Phi c_bar
-    (centre) and |Phi| w (width), 2 FLOPs per multiply-add."""
-    return 2 * 2 * 8 * 6 * (N * (N - 1) // 2)
+    """Algorithmic FLOPs of the fixed point's tube map per (trajectory, node)
+    column: for every step k and earlier step j < k, the products of the 8
+    tube rows with the node's two non-affine residual rows (vx, vz), for the
+    centre (Phi c_bar) and the width (|Phi| w), 2 FLOPs per multiply-add.  The
+    four affine rows carry the residual (0, pad) exactly; their share of the
+    width is one table over (k, row) for all columns."""
+    return 2 * 2 * 8 * 2 * (N * (N - 1) // 2)
 
 
 def tube_bytes_per_launch(B, N, nx, nu):
-    """Algorithmic HBM bytes of the fixed-point tube-map launch: reads c_bar,
-    rho_bar [B][N][nx] and C_{t-1} (mu, sigma) [B][N][nx+nu] for the
-    containment test, writes C_t (mu, sigma), all FP64."""
+    """Algorithmic HBM bytes of the fixed-point tube-map launch: reads the
+    residual rows 3 and 4 of each node (c_bar, rho_bar [B][N][U][2]) and
+    C_{t-1} (mu, sigma) [B][N][nx+nu] for the containment test, writes C_t
+    (mu, sigma), all FP64."""
     n = nx + nu
-    return 8 * B * N * (2 * nx + 2 * n + 2 * n)
+    return 8 * B * N * (2 * (2 * (nx // 6)) + 2 * n + 2 * n)
 
 
 def bytes_per_unit_fixed_point_launch(nx, nu):
     """Algorithmic HBM bytes of one unit in the fixed point's bound launch:
-    reads z, v, mu, sigma; writes c_bar, rho_bar (all FP64)."""
+    reads z, v, mu, sigma; writes c_bar, rho_bar of rows 3 and 4 of each node
+    (all FP64)."""
     n = nx + nu
-    return 8 * (nx + nu + n + n) + 8 * (2 * nx)
+    return 8 * (nx + nu + n + n) + 8 * (2 * 2 * (nx // 6))
 
 
 def main():
@@ -171,15 +176,17 @@ def main():
     tube_us = 1e3 * float(np.mean(tube_ms))
     tflops = tube_flops_per_column(N) * B * U / (tube_us * 1e-6) / 1e12
     tube_bytes = tube_bytes_per_launch(B, N, nx, nu)
+    gbs = tube_bytes / (tube_us * 1e-6) / 1e9
     traffic = None
     if TUBE_PMC_KIB is not None:
         traffic = int(TUBE_PMC_KIB[0] * 1024 * FETCH_SCALE + TUBE_PMC_KIB[1] * 1024 * WRITE_SCALE)
-    roofline = {"bound": "mfma", "achieved": round(tflops, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(tflops / FP64_PEAK_TFLOPS, 4), "traffic": traffic,
-                "kernel": "tube_map_kernel", "launch_us": round(tube_us, 2), "launches": len(tube_ms),
-                "units_per_launch": B * U, "flops_per_unit": tube_flops_per_column(N),
-                "hbm_bytes_per_launch": tube_bytes,
-                "hbm_frac": round(tube_bytes / (tube_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+    # HBM-bound: 82.6 MB against 0.36 GFLOP per launch at the bench shape
+    roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "tube_map2_kernel", "launch_us": round(tube_us, 2), "launches": len(tube_ms),
+                "units_per_launch": B * U, "bytes_per_launch": tube_bytes,
+                "flops_per_unit": tube_flops_per_column(N), "mfma_tflops": round(tflops, 2),
+                "mfma_frac": round(tflops / FP64_PEAK_TFLOPS, 4)}
     # the bound kernel of the same sweeps
     bound_us = 1e3 * float(np.mean(bound_ms))
     bpu = bytes_per_unit_fixed_point_launch(nx, nu)

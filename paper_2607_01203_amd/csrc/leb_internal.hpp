@@ -35,7 +35,8 @@ size_t pbh_smem_bytes_T(int U, int T);
 int launch_pbh_chain(const leb_dynamics* dyn, int64_t units, const double* z, const double* v,
                      const double* mu, const double* sigma, double* r_lo, double* r_hi, double* c_bar,
                      double* rho_bar, double pad, uint32_t* flags, hipStream_t stream,
-                     const uint32_t* open = nullptr, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                     const uint32_t* open = nullptr, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                     bool compact = false);
 int launch_fill_zero(int64_t count, double* r_lo, double* r_hi, double* c_bar, double* rho_bar, double pad,
                      uint32_t* flags, int64_t nflags, hipStream_t stream);
 size_t pbh_smem_bytes(int U);
@@ -43,6 +44,11 @@ size_t bwd_smem_bytes(int U);
 int launch_tube_map(int B, int N, int U, const double* phi, const double* e, const double* cbar,
                     const double* rbar, double* mu, double* sigma, hipStream_t s,
                     double scale = 1.0, double shift = 0.0);
+// the tube map of compact residuals c2, r2 [B][N][U][2] (rows 3 and 4 of each
+// node; the four affine rows are (0, pad))
+int launch_tube_map_compact(int B, int N, int U, const double* phi, const double* e, double pad, const double* c2,
+                            const double* r2, double* mu, double* sigma, hipStream_t s, double scale = 1.0,
+                            double shift = 0.0);
 // tube of the residual zonotopes (0, pad) at every step (the disturbance-only tube)
 int launch_disturbance_tube(int B, int N, int U, const double* phi, const double* e, double pad, double* mu,
                             double* sigma, hipStream_t s);
@@ -55,9 +61,11 @@ int nn_bound_run(const leb_mlp_s* net, int64_t units, const double* z, const dou
                  uint32_t* flags, int CB, double* const* buf, hipStream_t st);
 void nn_dims(const leb_mlp_s* net, int* nx, int* nu, int* m);
 
-// one surrogate sweep over a chain tube (features -> BF16 MLP -> residual zonotope, all rows)
+// one surrogate sweep over a chain tube (features -> BF16 MLP -> residual zonotope,
+// all rows [unit][6U], or compact: rows 3 and 4 [unit][U][2])
 int surrogate_chain_sweep(leb_surrogate s, const double* z, const double* v, const double* mu, const double* sigma,
-                          int nodes, int U, double L0, double pad, double* cbar, double* rbar, hipStream_t st);
+                          int nodes, int U, double L0, double pad, double* cbar, double* rbar, hipStream_t st,
+                          bool compact = false);
 
 // argument checks shared by the entry points
 bool aligned8(const void* p);

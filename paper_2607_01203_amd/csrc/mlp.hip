@@ -118,8 +118,9 @@ struct FwdArgs {
     int B;
     // chain surrogate sweep (FWD_CHAIN): rows are (unit, node) of a chain tube
     const double *cz, *cv, *cmu, *csg;
-    double *cbar, *rbar;      // rows 6i+3, 6i+4 of every unit written
+    double *cbar, *rbar;      // all 6 rows of each node, or (compact) rows 3, 4: [unit][U][2]
     int U;
+    int compact;
     double L0, pad;
 };
 
@@ -299,6 +300,20 @@ __global__ void __launch_bounds__(256) mlp_fwd_kernel(FwdArgs A) {
         __bf16* t_ = cur; cur = nxt; nxt = t_;
     }
     if (MODE == FWD_CHAIN) {
+        if (A.compact) {
+            // decode: rows 3 and 4 of each node (row = u U + i, so [row][2])
+            if (tid < 2 * FWD_ROWS) {
+                const int r = tid >> 1, w = tid & 1;
+                const int row = row0 + r;
+                if (row < A.B) {
+                    double c, rad;
+                    chain_decode_row(sy[r][2 * w], sy[r][2 * w + 1], &c, &rad);
+                    A.cbar[(int64_t)row * 2 + w] = c;
+                    A.rbar[(int64_t)row * 2 + w] = rad + A.pad;
+                }
+            }
+            return;
+        }
         // decode: the 6 residual rows of each node, (0, pad) on the affine rows
         for (int idx = tid; idx < 6 * FWD_ROWS; idx += 256) {
             const int r = idx / 6, rc = idx - 6 * r;
@@ -637,12 +652,14 @@ namespace leb {
 // One surrogate sweep over a chain tube: features -> MLP -> (c_bar, rho_bar) for
 // every (unit, node): the decoded bound on rows 6i+3, 6i+4, (0, pad) elsewhere.
 int surrogate_chain_sweep(leb_surrogate s, const double* z, const double* v, const double* mu, const double* sigma,
-                          int nodes, int U, double L0, double pad, double* cbar, double* rbar, hipStream_t st) {
+                          int nodes, int U, double L0, double pad, double* cbar, double* rbar, hipStream_t st,
+                          bool compact) {
     if (s->G.w[0] != LEB_CHAIN_FEATURES || s->G.w[s->G.L] != LEB_CHAIN_OUTPUTS) return LEB_EINVAL;
     if (nodes == 0) return LEB_OK;
     FwdArgs a = {};
     a.G = s->G; a.Wt = s->Wt; a.params = s->params; a.B = nodes;
     a.cz = z; a.cv = v; a.cmu = mu; a.csg = sigma; a.cbar = cbar; a.rbar = rbar; a.U = U; a.L0 = L0; a.pad = pad;
+    a.compact = compact ? 1 : 0;
     return fwd_dispatch(s, a, FWD_CHAIN, st);
 }
 }  // namespace leb

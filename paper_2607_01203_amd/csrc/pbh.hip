@@ -59,6 +59,7 @@ struct ChainArgs {
     double kL;       // k_spring * rest_len
     double L0;
     double pad;
+    int compact;     // 1: c_bar, rho_bar hold rows 3 and 4 of each node only, [unit][U][2]
 };
 
 
@@ -95,7 +96,13 @@ __device__ __forceinline__ void node_pass(const ChainArgs& A, const TileRef& t, 
 #pragma unroll
         for (int c = 0; c < 6; ++c) { t.RLO[o + c] = lo[c]; t.RHI[o + c] = hi[c]; }
     }
-    if (t.CB) {
+    if (t.CB && A.compact) {
+        // the four affine rows are exactly (0, pad) unless the unit is bad, and then
+        // rows 3 and 4 are not finite either
+        const int64_t o2 = 2 * ((int64_t)lt * U + i);
+        row_zono(lo[3], hi[3], A.pad, &t.CB[o2], &t.RB[o2]);
+        row_zono(lo[4], hi[4], A.pad, &t.CB[o2 + 1], &t.RB[o2 + 1]);
+    } else if (t.CB) {
 #pragma unroll
         for (int c = 0; c < 6; ++c) row_zono(lo[c], hi[c], A.pad, &t.CB[o + c], &t.RB[o + c]);
     }
@@ -122,7 +129,8 @@ __global__ void __launch_bounds__(PBH_BLOCK) pbh_chain_fwd(ChainArgs A) {
         t0.Z = A.z + u0 * nx; t0.V = A.v + u0 * nu; t0.MU = A.mu ? A.mu + u0 * n : nullptr;
         t0.SG = A.sigma + u0 * n;
         t0.RLO = A.r_lo ? A.r_lo + u0 * nx : nullptr; t0.RHI = A.r_hi ? A.r_hi + u0 * nx : nullptr;
-        t0.CB = A.c_bar ? A.c_bar + u0 * nx : nullptr; t0.RB = A.rho_bar ? A.rho_bar + u0 * nx : nullptr;
+        const int64_t ro = A.compact ? 2 * U : nx;       // row length of c_bar, rho_bar
+        t0.CB = A.c_bar ? A.c_bar + u0 * ro : nullptr; t0.RB = A.rho_bar ? A.rho_bar + u0 * ro : nullptr;
         t0.FL = A.flags ? A.flags + u0 : nullptr;
     }
     for (int q = tid; q < T; q += PBH_BLOCK) s_flag[q] = 0u;
@@ -154,7 +162,7 @@ size_t pbh_smem_bytes(int U) { return pbh_smem_bytes_T(U, PBH_BLOCK / U); }
 int launch_pbh_chain(const leb_dynamics* dyn, int64_t units, const double* z, const double* v,
                      const double* mu, const double* sigma, double* r_lo, double* r_hi, double* c_bar,
                      double* rho_bar, double pad, uint32_t* flags, hipStream_t stream, const uint32_t* open,
-                     hipEvent_t ev0, hipEvent_t ev1) {
+                     hipEvent_t ev0, hipEvent_t ev1, bool compact) {
     ChainArgs a;
     a.z = z; a.v = v; a.mu = mu; a.sigma = sigma;
     a.r_lo = r_lo; a.r_hi = r_hi; a.c_bar = c_bar; a.rho_bar = rho_bar; a.flags = flags;
@@ -167,6 +175,7 @@ int launch_pbh_chain(const leb_dynamics* dyn, int64_t units, const double* z, co
     a.kL = dyn->k_spring * dyn->rest_len;
     a.L0 = dyn->rest_len;
     a.pad = pad;
+    a.compact = compact ? 1 : 0;
     int64_t blocks = (units + a.T - 1) / a.T;
     if (blocks > 0x7fffffff) return LEB_EINVAL;
     if (ev0)        // timed: events at the kernel's start and end

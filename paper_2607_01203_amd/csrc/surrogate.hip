@@ -194,11 +194,11 @@ extern "C" int leb_fixed_point_learned(const leb_dynamics* dyn, int32_t batch, i
         // surrogate's fixed point
         for (int t = 0; t < ws->sweeps; ++t) {
             if ((rc = surrogate_chain_sweep(ws->net, z, v, mu, sigma, (int)nodes, U, dyn->rest_len, opt->pad, g_sw.cb,
-                                            g_sw.rb, s)))
+                                            g_sw.rb, s, true)))
                 return rc;
             const bool last = t == ws->sweeps - 1;
-            if ((rc = launch_tube_map(batch, N, U, phi, e, g_sw.cb, g_sw.rb, mu, sigma, s, last ? 1.0 + ws->margin : 1.0,
-                                      last ? opt->inflate_abs : 0.0)))
+            if ((rc = launch_tube_map_compact(batch, N, U, phi, e, opt->pad, g_sw.cb, g_sw.rb, mu, sigma, s,
+                                              last ? 1.0 + ws->margin : 1.0, last ? opt->inflate_abs : 0.0)))
                 return rc;
         }
         if (ws->sweeps == 0) {

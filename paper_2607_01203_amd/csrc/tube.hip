@@ -57,6 +57,8 @@ struct TubeArgs {
 };
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double se_row(const double (&e)[6], int q) { return q == 3 ? e[3] : e[4]; }
 constexpr int TM_RT = 5;        // 16-row tiles per wave and row group
 
 // The tube map as a contraction on FP64 MFMA (v_mfma_f64_16x16x4f64):
@@ -291,6 +293,196 @@ __global__ void __launch_bounds__(256) tube_map_kernel(const double* __restrict_
     if (tid < 16 && sbad[tid] && bfirst + tid < A.B) atomicOr(&P.state[bfirst + tid], FP_OPEN);
 }
 
+// Tube map for residual zonotopes that are (0, pad) on the four affine rows
+// of every node -- the chain dynamics of the fixed point, whose bound is
+// exactly zero there (Theorem 1: no curvature in those rows).  The residuals
+// come compact, rows 3 and 4 (vx, vz) of each node: c2, r2 [B][N][U][2].
+// Only those rows enter the contraction, K = 2 (N-1); the affine rows add
+//   sigma_k[r] += sum_{j<k} sum_{q in {0,1,2,5}} |Phi_{k-j-1}[r][q]| (e_q + pad)
+// (a table over (k, r) shared by every column) and nothing to mu.  The rest is
+// the tube map kernel above: 16 node columns per workgroup, row tiles of two
+// steps per wave, the same rounding allowance wid (the same number of terms).
+struct Tube2Args {
+    const double* c2; const double* r2;      // [B][N][U][2]
+    double e[6];
+    double pad;
+    double* mu; double* sigma;               // [B][N][n] out
+    double wid;
+    double scale, shift;                     // plain map: sigma stored as sigma * scale + shift
+    int B, N, U;
+};
+
+__global__ void __launch_bounds__(256) tube_map2_kernel(const double* __restrict__ phi, Tube2Args A, TubeFP P) {
+    // LDS: Phi rows' columns 3, 4 for lags -4..N-1 [(N+4)*16], the affine table
+    // [N][8], per-lag affine sums [N-1][8], c and w [2(N-1)+8][16]
+    extern __shared__ double lds2[];
+    __shared__ int64_t srow[16], stub[16];
+    __shared__ int snode[16];
+    __shared__ uint32_t sfrz[16], sbad[16];
+    __shared__ int sjinf[16];
+    const bool fp = P.state != nullptr;
+    if (fp && P.state[A.B] == 0u) return;     // every trajectory certified by an earlier sweep
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int N = A.N, U = A.U, nx = 6 * U, n = 8 * U;
+    const int nst = N - 1;
+    const int kfull = 2 * nst, kpad = kfull + 8;
+    double* sp = lds2;                                  // sp[(lag + 4) * 16 + r * 2 + q'], q' = row 3 + q'
+    double* dtab = sp + (N + 4) * 16;                   // [N][8]
+    double* g = dtab + N * 8;                           // [N-1][8]
+    double* sc = g + nst * 8;                           // [kpad][16]
+    double* sw = sc + (size_t)kpad * 16;
+    const int cols = A.B * U;
+    const int c0 = blockIdx.x * 16;
+    const int ncol = min(16, cols - c0);
+    if (tid < 16) {
+        const int col = min(c0 + tid, cols - 1);
+        const int bb = col / U, nd = col - bb * U;
+        srow[tid] = ((int64_t)bb * N * U + nd) * 2;
+        stub[tid] = (int64_t)bb * N * n;
+        snode[tid] = nd;
+        sfrz[tid] = fp ? (P.state[bb] & FP_CERT) : 0u;
+        sbad[tid] = 0u;
+        sjinf[tid] = 0x7fffffff;
+    }
+    for (int q = tid; q < (N + 4) * 16; q += 256) {
+        const int lag = q / 16 - 4, rem = q - 16 * (q / 16);
+        sp[q] = (lag >= 0 && lag < nst) ? phi[(int64_t)lag * 48 + (rem >> 1) * 6 + 3 + (rem & 1)] : 0.0;
+    }
+    for (int t = tid; t < nst * 8; t += 256) {          // t = 8 d + r
+        const double* Pr = phi + (int64_t)t * 6;
+        double acc = 0.0;
+        acc = __builtin_fma(fabs(Pr[0]), A.e[0] + A.pad, acc);
+        acc = __builtin_fma(fabs(Pr[1]), A.e[1] + A.pad, acc);
+        acc = __builtin_fma(fabs(Pr[2]), A.e[2] + A.pad, acc);
+        acc = __builtin_fma(fabs(Pr[5]), A.e[5] + A.pad, acc);
+        g[t] = acc;
+    }
+    if (tid < 128) { sc[kfull * 16 + tid] = 0.0; sw[kfull * 16 + tid] = 0.0; }   // 8 zero rows past the end
+    __syncthreads();
+    // residual rows 3, 4 of the 16 columns: entry (j, p), p = 2 cl + q', consecutive
+    // threads on consecutive addresses; a radius or centre that is not finite
+    // enters as 0 and makes sigma +inf at every later step of its column
+    const int nent = nst * 32;
+    for (int i0 = tid; i0 < nent; i0 += 8 * 256) {
+        double cv[8], rv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = i0 + 256 * u;
+            const int j = idx >> 5, p = idx & 31, cl = p >> 1;
+            const bool in = idx < nent && cl < ncol;
+            const int64_t off = srow[in ? cl : 0] + (int64_t)(in ? j : 0) * U * 2 + (p & 1);
+            cv[u] = in ? A.c2[off] : 0.0;
+            rv[u] = in ? A.r2[off] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = i0 + 256 * u;
+            if (idx >= nent) break;
+            const int j = idx >> 5, p = idx & 31, cl = p >> 1, qq = p & 1;
+            double c = 0.0, w = 0.0;
+            if (cl < ncol) {
+                c = cv[u];
+                const bool cfin = fabs(c) <= DBL_MAX;
+                if (!cfin) c = 0.0;
+                w = se_row(A.e, 3 + qq) + rv[u] + fabs(c) * A.wid;
+                if (!(cfin && w <= DBL_MAX)) {
+                    atomicMin(&sjinf[cl], j);
+                    w = 0.0;
+                }
+            }
+            sc[(2 * j + qq) * 16 + cl] = c;
+            sw[(2 * j + qq) * 16 + cl] = w;
+        }
+    }
+    if (tid < 8) {                                      // affine table: prefix sums over the lag
+        double acc = 0.0;
+        dtab[tid] = 0.0;
+        for (int k = 1; k < N; ++k) {
+            acc += g[(k - 1) * 8 + tid];
+            dtab[k * 8 + tid] = acc;
+        }
+    }
+    const int nrt = (N + 1) >> 1;
+    const int lr = lane & 15, lq = lane >> 4;
+    const bool cin = lr < ncol;
+    const int bfirst = c0 / U;
+    auto tube_off = [&](int rr, int k) -> int64_t {
+        const int nd = snode[lr];
+        return stub[lr] + (int64_t)k * n + (rr < 6 ? 6 * nd + rr : nx + 2 * nd + (rr - 6));
+    };
+    double mi[TM_RT][4], si[TM_RT][4];
+#pragma unroll
+    for (int s = 0; s < TM_RT; ++s) {
+        const int rt = tm_tile(wave, s, blockIdx.y);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 16 * rt + 4 * i + lq, k = r >> 3;
+            mi[s][i] = 0.0;
+            si[s][i] = 0.0;
+            if (fp && cin && rt < nrt && k < N && !sfrz[lr]) {
+                const int64_t o = tube_off(r & 7, k);
+                mi[s][i] = P.mu_in[o];
+                si[s][i] = P.sg_in[o];
+            }
+        }
+    }
+    __syncthreads();
+    const bool frozen = sfrz[lr] != 0u;
+    const int sjl = sjinf[lr];
+    // K loop per slot, two K steps per iteration into separate accumulators;
+    // kk = k4 + lq = 2 j + q', the A entry of kk is sp[(k - j + 3) * 16 + rr * 2 + q']
+#pragma unroll
+    for (int s = 0; s < TM_RT; ++s) {
+        const int rt = tm_tile(wave, s, blockIdx.y);
+        if (rt >= nrt) continue;
+        const int r = 16 * rt + lr, kr = r >> 3, rrr = r & 7;
+        const int kmax = 2 * min(nst, 2 * rt + 1);
+        const int abase = (kr + 3) * 16 + rrr * 2 + (lq & 1);
+        d4 m0 = d4{0.0, 0.0, 0.0, 0.0}, v0 = m0, m1 = m0, v1 = m0;
+        for (int k4 = 0; k4 < kmax; k4 += 8) {
+            const int kk = k4 + lq;
+            const int j0 = kk >> 1, j1 = (kk + 4) >> 1;
+            const double c0v = sc[kk * 16 + lr], w0v = sw[kk * 16 + lr];
+            const double c1v = sc[(kk + 4) * 16 + lr], w1v = sw[(kk + 4) * 16 + lr];
+            const double a0 = sp[abase - 16 * j0];
+            const double a1 = sp[abase - 16 * j1];
+            m0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, c0v, m0, 0, 0, 0);
+            v0 = __builtin_amdgcn_mfma_f64_16x16x4f64(fabs(a0), w0v, v0, 0, 0, 0);
+            m1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, c1v, m1, 0, 0, 0);
+            v1 = __builtin_amdgcn_mfma_f64_16x16x4f64(fabs(a1), w1v, v1, 0, 0, 0);
+        }
+        const d4 am = m0 + m1, as = v0 + v1;
+        if (!cin) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int rr4 = 16 * rt + 4 * i + lq, k = rr4 >> 3, rr = rr4 & 7;
+            if (k >= N) continue;
+            const double mF = am[i];
+            // both sums have nonnegative terms; rounded upward as a whole, 2^-1000 for
+            // any flushed subnormal part
+            const double tot = as[i] + dtab[k * 8 + rr];
+            const double sF = k > sjl ? INFINITY : tot + tot * A.wid + 0x1p-1000;
+            double so = sF * A.scale + A.shift;
+            if (fp) {
+                // [mF - sF, mF + sF] inside [mi - si, mi + si], with the rounding of the
+                // test covered; a tube that is not finite is never accepted
+                if (!frozen && !(sF <= DBL_MAX && (fabs(mF - mi[s][i]) + sF) * (1.0 + 0x1p-50) <= si[s][i]))
+                    sbad[(c0 + lr) / U - bfirst] = 1u;
+                so = sF + sF * P.tol + P.abs_;
+            }
+            if (!frozen) {
+                const int64_t o = tube_off(rr, k);
+                A.mu[o] = mF;
+                A.sigma[o] = so;
+            }
+        }
+    }
+    if (!fp) return;
+    __syncthreads();
+    if (tid < 16 && sbad[tid] && bfirst + tid < A.B) atomicOr(&P.state[bfirst + tid], FP_OPEN);
+}
+
 // After the tube map of sweep t: fold this sweep's containment into the
 // state words (certified at t, or open) and publish the open count to the
 // device word and to host memory.  One workgroup.
@@ -435,6 +627,50 @@ static int launch_tube(int B, int N, int U, const double* phi, const double* e, 
     else
         hipLaunchKernelGGL(tube_map_kernel, dim3((unsigned)gx, gy), dim3(256), smem, s, phi, a, fp);
     return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
+}
+
+// Tube map of compact residuals (rows 3 and 4 of each node, the affine rows
+// (0, pad)); fp as launch_tube's
+static int launch_tube2(int B, int N, int U, const double* phi, const double* e, double pad, const double* c2,
+                        const double* r2, double* mu, double* sigma, const TubeFP& fp, hipStream_t s,
+                        double scale = 1.0, double shift = 0.0, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
+    Tube2Args a;
+    a.c2 = c2; a.r2 = r2;
+    for (int q = 0; q < 6; ++q) a.e[q] = e[q];
+    a.pad = pad;
+    a.mu = mu; a.sigma = sigma; a.B = B; a.N = N; a.U = U;
+    a.wid = tube_wid(N);
+    a.scale = scale; a.shift = shift;
+    const int64_t cols = (int64_t)B * U;
+    if (cols == 0 || N == 0) return LEB_OK;
+    const int64_t gx = (cols + 15) / 16;
+    const int nrt = (N + 1) / 2;
+    const int gy = (nrt + 4 * TM_RT - 1) / (4 * TM_RT);
+    if (gx > 0x7fffffff || cols > 0x7fffffff) return LEB_EINVAL;
+    const size_t nst = N > 1 ? N - 1 : 0;
+    const size_t smem = ((size_t)(N + 4) * 16 + (size_t)N * 8 + nst * 8 + 2 * (2 * nst + 8) * 16) * sizeof(double);
+    static size_t dyn_max = 0;
+    if (dyn_max == 0) {
+        hipFuncAttributes fa;
+        if (hipFuncGetAttributes(&fa, (const void*)tube_map2_kernel) != hipSuccess) return LEB_EDEVICE;
+        const size_t cap = 160 * 1024 - fa.sharedSizeBytes;
+        if (hipFuncSetAttribute((const void*)tube_map2_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cap) !=
+            hipSuccess)
+            return LEB_EDEVICE;
+        dyn_max = cap;
+    }
+    if (smem > dyn_max) return LEB_ENOTSUP;
+    if (ev0)        // timed: events at the kernel's start and end
+        hipExtLaunchKernelGGL(tube_map2_kernel, dim3((unsigned)gx, gy), dim3(256), smem, s, ev0, ev1, 0, phi, a, fp);
+    else
+        hipLaunchKernelGGL(tube_map2_kernel, dim3((unsigned)gx, gy), dim3(256), smem, s, phi, a, fp);
+    return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
+}
+
+int launch_tube_map_compact(int B, int N, int U, const double* phi, const double* e, double pad, const double* c2,
+                            const double* r2, double* mu, double* sigma, hipStream_t s, double scale, double shift) {
+    TubeFP none{nullptr, nullptr, nullptr, 0.0, 0.0};
+    return launch_tube2(B, N, U, phi, e, pad, c2, r2, mu, sigma, none, s, scale, shift);
 }
 
 int launch_disturbance_tube(int B, int N, int U, const double* phi, const double* e, double pad, double* mu,
@@ -590,7 +826,8 @@ extern "C" int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int
     std::lock_guard<std::mutex> lock(g_ws.mu);
     double *cb, *rb, *xm1, *xs1;
     uint32_t* state;
-    const size_t bx = (size_t)units * nx * sizeof(double), bn = (size_t)units * n * sizeof(double);
+    // residuals: rows 3 and 4 of each node (the affine rows are (0, pad))
+    const size_t bx = (size_t)units * 2 * U * sizeof(double), bn = (size_t)units * n * sizeof(double);
     if ((rc = ws_get(0, bx, (void**)&cb)) || (rc = ws_get(1, bx, (void**)&rb)) ||
         (rc = ws_get(2, bn, (void**)&xm1)) || (rc = ws_get(3, bn, (void**)&xs1)) ||
         (rc = ws_get(4, ((size_t)batch + 1) * sizeof(uint32_t), (void**)&state)) || (rc = ws_host()))
@@ -612,11 +849,11 @@ extern "C" int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int
         lt_pair(0, &b0, &b1);
         lt_pair(1, &t0, &t1);
         int r = launch_pbh_chain(dyn, units, z, v, xm[a], xs[a], nullptr, nullptr, cb, rb, opt->pad, nullptr, s,
-                                 state + batch, b0, b1);
+                                 state + batch, b0, b1, true);
         if (r) return r;
         hopen[t % FP_SLOTS] = 0xffffffffu;
         const TubeFP fp{xm[a], xs[a], state, opt->tol, opt->inflate_abs};
-        if ((r = launch_tube(batch, N, U, phi, e, cb, rb, xm[w], xs[w], fp, s, 1.0, 0.0, t0, t1))) return r;
+        if ((r = launch_tube2(batch, N, U, phi, e, opt->pad, cb, rb, xm[w], xs[w], fp, s, 1.0, 0.0, t0, t1))) return r;
         hipLaunchKernelGGL(fp_state_kernel, dim3(1), dim3(256), 0, s, state, batch, g_ws.host_open_dev, t);
         return ok(hipGetLastError()) ? LEB_OK : LEB_EDEVICE;
     };
