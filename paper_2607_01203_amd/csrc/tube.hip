@@ -29,6 +29,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <chrono>
 #include <mutex>
 #include <vector>
 
@@ -858,13 +859,16 @@ extern "C" int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int
         return ok(hipGetLastError()) ? LEB_OK : LEB_EDEVICE;
     };
     // Wait until sweep t has published its open count.  The count is written to
-    // pinned host memory by the state kernel; the stream is queried now and then
-    // so that the wait also ends if the stream drains (or fails) without it.
+    // pinned host memory by the state kernel.  The stream is queried only after
+    // 2 ms without it (a query can put a marker between the sweeps' kernels), so
+    // that the wait also ends if the stream drains (or fails) without a count.
     auto wait_count = [&](int t, uint32_t* out) -> int {
+        auto last = std::chrono::steady_clock::now();
         for (uint64_t spin = 1;; ++spin) {
             const uint32_t v = hopen[t % FP_SLOTS];
             if (v != 0xffffffffu) { *out = v; return LEB_OK; }
-            if ((spin & 255) == 0) {
+            if ((spin & 1023) == 0 && std::chrono::steady_clock::now() - last > std::chrono::milliseconds(2)) {
+                last = std::chrono::steady_clock::now();
                 const hipError_t q = hipStreamQuery(s);
                 if (q == hipSuccess) {
                     const uint32_t v2 = hopen[t % FP_SLOTS];
@@ -880,15 +884,20 @@ extern "C" int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int
     // open count; a sweep enqueued after the last needed one exits at once
     if ((rc = sweep(1))) return rc;
     int t = 1;
+    uint32_t open = 0, open_before = (uint32_t)batch;    // open counts after sweeps t and t - 1
     for (;;) {
         if (t < opt->max_sweeps && (rc = sweep(t + 1))) return rc;
-        uint32_t open = 0;
         if ((rc = wait_count(t, &open))) return rc;
         if (open == 0 || t == opt->max_sweeps) break;
+        open_before = open;
         ++t;
     }
-    hipLaunchKernelGGL(fp_final_kernel, dim3(batch, (unsigned)std::min<int64_t>((per + 255) / 256, 16)), dim3(256), 0,
-                       s, xm1, xs1, mu, sigma, state, per, t);
+    // every trajectory certified by sweep t has its tube C_{t-1} in buffer (t-1) & 1:
+    // nothing to copy when that is the caller's buffer
+    const bool in_place = open == 0 && open_before == (uint32_t)batch && ((t - 1) & 1) == 0;
+    if (!in_place)
+        hipLaunchKernelGGL(fp_final_kernel, dim3(batch, (unsigned)std::min<int64_t>((per + 255) / 256, 16)), dim3(256),
+                           0, s, xm1, xs1, mu, sigma, state, per, t);
     hipLaunchKernelGGL(cert_out_kernel, dim3(nblk(batch)), dim3(256), 0, s, state, certified, batch);
     *sweeps_out = t;
     return ok(hipGetLastError()) ? LEB_OK : LEB_EDEVICE;
