@@ -313,16 +313,21 @@ struct Tube2Args {
     int B, N, U;
 };
 
+__device__ double kZero8[8];          // zero-initialised; stands in for Phi at a single step
+
+// Loads are issued unconditionally (clamped to a valid address, the value
+// then selected) so that no load sits in a branch: the wait counters stay
+// exact and a wait for one batch of loads never also waits for a later batch.
+// LONG (more than 65 steps) stages Phi and the residuals in passes, before
+// and after the tube loads; the short form has no loop around a load.
+template <bool FP, bool LONG>
 __global__ void __launch_bounds__(256) tube_map2_kernel(const double* __restrict__ phi, Tube2Args A, TubeFP P) {
     // LDS: Phi rows' columns 3, 4 for lags -4..N-1 [(N+4)*16], the affine table
-    // [N][8], per-lag affine sums [N-1][8], c and w [2(N-1)+8][16]
+    // [N][8], per-lag affine sums [N-1][8], c and w [2(N-1)+8][16], a spare [4]
     extern __shared__ double lds2[];
-    __shared__ int64_t srow[16], stub[16];
-    __shared__ int snode[16];
-    __shared__ uint32_t sfrz[16], sbad[16];
+    __shared__ uint32_t sbad[16];
     __shared__ int sjinf[16];
-    const bool fp = P.state != nullptr;
-    if (fp && P.state[A.B] == 0u) return;     // every trajectory certified by an earlier sweep
+    if (FP && P.state[A.B] == 0u) return;     // every trajectory certified by an earlier sweep
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int N = A.N, U = A.U, nx = 6 * U, n = 8 * U;
@@ -333,125 +338,197 @@ __global__ void __launch_bounds__(256) tube_map2_kernel(const double* __restrict
     double* g = dtab + N * 8;                           // [N-1][8]
     double* sc = g + nst * 8;                           // [kpad][16]
     double* sw = sc + (size_t)kpad * 16;
+    double* spare = sw + (size_t)kpad * 16;             // [4], written, never read
     const int cols = A.B * U;
     const int c0 = blockIdx.x * 16;
     const int ncol = min(16, cols - c0);
-    if (tid < 16) {
-        const int col = min(c0 + tid, cols - 1);
+    const int bfirst = c0 / U;
+    // this lane's accumulator column (lr) and its trajectory's state word
+    const int lr = lane & 15, lq = lane >> 4;
+    const bool cin = lr < ncol;
+    int64_t ob_s, ob_i;
+    uint32_t stw = 0u;
+    {
+        const int col = min(c0 + lr, cols - 1);
         const int bb = col / U, nd = col - bb * U;
-        srow[tid] = ((int64_t)bb * N * U + nd) * 2;
-        stub[tid] = (int64_t)bb * N * n;
-        snode[tid] = nd;
-        sfrz[tid] = fp ? (P.state[bb] & FP_CERT) : 0u;
-        sbad[tid] = 0u;
-        sjinf[tid] = 0x7fffffff;
+        const int64_t tub = (int64_t)bb * N * n;
+        ob_s = tub + 6 * nd;
+        ob_i = tub + nx + 2 * nd - 6;
+        if (FP) stw = P.state[bb];
     }
-    for (int q = tid; q < (N + 4) * 16; q += 256) {
-        const int lag = q / 16 - 4, rem = q - 16 * (q / 16);
-        sp[q] = (lag >= 0 && lag < nst) ? phi[(int64_t)lag * 48 + (rem >> 1) * 6 + 3 + (rem & 1)] : 0.0;
-    }
-    for (int t = tid; t < nst * 8; t += 256) {          // t = 8 d + r
-        const double* Pr = phi + (int64_t)t * 6;
-        double acc = 0.0;
-        acc = __builtin_fma(fabs(Pr[0]), A.e[0] + A.pad, acc);
-        acc = __builtin_fma(fabs(Pr[1]), A.e[1] + A.pad, acc);
-        acc = __builtin_fma(fabs(Pr[2]), A.e[2] + A.pad, acc);
-        acc = __builtin_fma(fabs(Pr[5]), A.e[5] + A.pad, acc);
-        g[t] = acc;
-    }
-    if (tid < 128) { sc[kfull * 16 + tid] = 0.0; sw[kfull * 16 + tid] = 0.0; }   // 8 zero rows past the end
-    __syncthreads();
-    // residual rows 3, 4 of the 16 columns: entry (j, p), p = 2 cl + q', consecutive
-    // threads on consecutive addresses; a radius or centre that is not finite
-    // enters as 0 and makes sigma +inf at every later step of its column
-    const int nent = nst * 32;
-    for (int i0 = tid; i0 < nent; i0 += 8 * 256) {
-        double cv[8], rv[8];
+    if (tid < 16) { sbad[tid] = 0u; sjinf[tid] = 0x7fffffff; }
+    // Every load of the first pass is issued before any of it is used, in the
+    // order it is needed: Phi (columns 3, 4 and the per-lag affine sums), the
+    // residual rows of the first 64 steps, the tube C_{t-1}.  Phi and the
+    // residuals wait only for themselves; the tube is used after the contraction.
+    const int nsp = (N + 4) * 16, ng = nst * 8;
+    const double* ph = nst > 0 ? phi : kZero8;         // no Phi for a single step
+    // Phi rows t = 8 lag + r (six columns) two per thread and pass: columns
+    // 3, 4 go to sp, the others into the per-lag affine sums g
+    double pr[2][6];
+    auto phi_load = [&](int t0) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int idx = i0 + 256 * u;
-            const int j = idx >> 5, p = idx & 31, cl = p >> 1;
-            const bool in = idx < nent && cl < ncol;
-            const int64_t off = srow[in ? cl : 0] + (int64_t)(in ? j : 0) * U * 2 + (p & 1);
-            cv[u] = in ? A.c2[off] : 0.0;
-            rv[u] = in ? A.r2[off] : 0.0;
+        for (int u = 0; u < 2; ++u) {
+            const int t = t0 + tid + 256 * u;
+            const double* Pr = ph + (int64_t)(t < ng ? t : 0) * 6;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) pr[u][q] = Pr[q];
         }
+    };
+    // (rows past the end are written to a spare LDS slot rather than skipped,
+    // so that no branch holds the loads' only use and they stay where issued)
+    auto phi_store = [&](int t0) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int t = t0 + tid + 256 * u;
+            const bool in = t < ng;
+            const int lag = t >> 3, r = t & 7;
+            double* d34 = in ? sp + (lag + 4) * 16 + r * 2 : spare;
+            d34[0] = pr[u][3];
+            d34[1] = pr[u][4];
+            double acc = 0.0;
+            acc = __builtin_fma(fabs(pr[u][0]), A.e[0] + A.pad, acc);
+            acc = __builtin_fma(fabs(pr[u][1]), A.e[1] + A.pad, acc);
+            acc = __builtin_fma(fabs(pr[u][2]), A.e[2] + A.pad, acc);
+            acc = __builtin_fma(fabs(pr[u][5]), A.e[5] + A.pad, acc);
+            (in ? g + t : spare + 2)[0] = acc;
+        }
+    };
+    // residual rows 3, 4 of the 16 columns: entry (j, p), p = 2 cl + q' = tid % 32,
+    // so each thread stages one (column, row) at steps j = tid / 32 + 8 u and
+    // consecutive threads read consecutive addresses.  A radius or centre that
+    // is not finite enters as 0 and makes sigma +inf at every later step of its column
+    const int scl = (tid & 31) >> 1, sq = tid & 1;
+    const bool sin_ = scl < ncol;
+    int64_t srow;
+    {
+        const int col = min(c0 + scl, cols - 1);
+        const int bb = col / U;
+        srow = ((int64_t)bb * N * U + (col - bb * U)) * 2 + sq;
+    }
+    const double se = se_row(A.e, 3 + sq);
+    double cv[8], rv[8];
+    auto stage_load = [&](int j0) {
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int idx = i0 + 256 * u;
-            if (idx >= nent) break;
-            const int j = idx >> 5, p = idx & 31, cl = p >> 1, qq = p & 1;
+            const int j = j0 + (tid >> 5) + 8 * u;
+            const int64_t off = srow + (int64_t)(j < nst ? j : 0) * U * 2;
+            cv[u] = A.c2[off];
+            rv[u] = A.r2[off];
+        }
+    };
+    auto stage_store = [&](int j0) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int j = j0 + (tid >> 5) + 8 * u;
+            if (j >= nst) break;
             double c = 0.0, w = 0.0;
-            if (cl < ncol) {
+            if (sin_) {
                 c = cv[u];
                 const bool cfin = fabs(c) <= DBL_MAX;
                 if (!cfin) c = 0.0;
-                w = se_row(A.e, 3 + qq) + rv[u] + fabs(c) * A.wid;
+                w = se + rv[u] + fabs(c) * A.wid;
                 if (!(cfin && w <= DBL_MAX)) {
-                    atomicMin(&sjinf[cl], j);
+                    atomicMin(&sjinf[scl], j);
                     w = 0.0;
                 }
             }
-            sc[(2 * j + qq) * 16 + cl] = c;
-            sw[(2 * j + qq) * 16 + cl] = w;
+            sc[(2 * j + sq) * 16 + scl] = c;
+            sw[(2 * j + sq) * 16 + scl] = w;
         }
-    }
-    if (tid < 8) {                                      // affine table: prefix sums over the lag
-        double acc = 0.0;
-        dtab[tid] = 0.0;
-        for (int k = 1; k < N; ++k) {
-            acc += g[(k - 1) * 8 + tid];
-            dtab[k * 8 + tid] = acc;
-        }
-    }
-    const int nrt = (N + 1) >> 1;
-    const int lr = lane & 15, lq = lane >> 4;
-    const bool cin = lr < ncol;
-    const int bfirst = c0 / U;
-    auto tube_off = [&](int rr, int k) -> int64_t {
-        const int nd = snode[lr];
-        return stub[lr] + (int64_t)k * n + (rr < 6 ? 6 * nd + rr : nx + 2 * nd + (rr - 6));
     };
+    const int nrt = (N + 1) >> 1;
+    const bool frozen = FP && (stw & FP_CERT) != 0u;
+    auto tube_off = [&](int rr, int k) -> int64_t { return (rr < 6 ? ob_s : ob_i) + rr + (int64_t)k * n; };
+    // The slots of a wave run from the longest K range down or the other way
+    // round, alternating between blocks 256 apart (the two blocks that share
+    // a compute unit when the grid holds more than one block per unit), so that
+    // one wave's contraction overlaps the other's memory traffic.  The tube
+    // C_{t-1} under this lane's accumulators is read two slots ahead of its use;
+    // mi[p], si[p] belong to the p-th slot processed.
+    const bool down = ((blockIdx.x >> 8) & 1) == 0;
+    auto ord = [&](int p) { return down ? TM_RT - 1 - p : p; };
     double mi[TM_RT][4], si[TM_RT][4];
-#pragma unroll
-    for (int s = 0; s < TM_RT; ++s) {
-        const int rt = tm_tile(wave, s, blockIdx.y);
+    auto tube_load = [&](int p) {
+        const int rt = tm_tile(wave, ord(p), blockIdx.y);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int r = 16 * rt + 4 * i + lq, k = r >> 3;
-            mi[s][i] = 0.0;
-            si[s][i] = 0.0;
-            if (fp && cin && rt < nrt && k < N && !sfrz[lr]) {
-                const int64_t o = tube_off(r & 7, k);
-                mi[s][i] = P.mu_in[o];
-                si[s][i] = P.sg_in[o];
-            }
+            const bool ok = cin && rt < nrt && k < N;     // (a frozen column's values go unused)
+            const int64_t o = ok ? tube_off(r & 7, k) : ob_s;
+            mi[p][i] = P.mu_in[o];
+            si[p][i] = P.sg_in[o];
+        }
+    };
+    phi_load(0);
+    if (LONG) {
+        phi_store(0);
+        for (int t0 = 2 * 256; t0 < ng; t0 += 2 * 256) {
+            phi_load(t0);
+            phi_store(t0);
         }
     }
+    stage_load(0);
+    if (!LONG) phi_store(0);
+    if (FP) {
+        tube_load(0);
+        tube_load(1);
+    }
+    // zero lags -4..-1 and N-1 of sp (the rows past a tile's causal range)
+    if (tid < 64) sp[tid] = 0.0;
+    else if (tid < 80) sp[(nst + 4) * 16 + tid - 64] = 0.0;
+    if (tid < 128) { sc[kfull * 16 + tid] = 0.0; sw[kfull * 16 + tid] = 0.0; }   // 8 zero rows past the end
     __syncthreads();
-    const bool frozen = sfrz[lr] != 0u;
+    // affine table: dtab[k][r] = sum_{d<k} g[d][r], summed in increasing d
+    for (int t = tid; t < N * 8; t += 256) {
+        const int k = t >> 3, r = t & 7;
+        double acc = 0.0;
+        for (int d = 0; d < k; ++d) acc += g[d * 8 + r];
+        dtab[t] = acc;
+    }
+    stage_store(0);
+    if (LONG)
+        for (int j0 = 64; j0 < nst; j0 += 64) {
+            stage_load(j0);
+            stage_store(j0);
+        }
+    __syncthreads();
     const int sjl = sjinf[lr];
-    // K loop per slot, two K steps per iteration into separate accumulators;
+    // K loop per slot, two K steps per iteration into separate accumulators, the
+    // next iteration's fragments read before this one's MFMAs;
     // kk = k4 + lq = 2 j + q', the A entry of kk is sp[(k - j + 3) * 16 + rr * 2 + q']
 #pragma unroll
-    for (int s = 0; s < TM_RT; ++s) {
-        const int rt = tm_tile(wave, s, blockIdx.y);
+    for (int p = 0; p < TM_RT; ++p) {
+        if (FP && p + 2 < TM_RT) tube_load(p + 2);
+        const int rt = tm_tile(wave, ord(p), blockIdx.y);
         if (rt >= nrt) continue;
         const int r = 16 * rt + lr, kr = r >> 3, rrr = r & 7;
         const int kmax = 2 * min(nst, 2 * rt + 1);
-        const int abase = (kr + 3) * 16 + rrr * 2 + (lq & 1);
+        // A offsets of kk and kk + 4 at k4 = 0 (j = lq / 2 and lq / 2 + 2); -8 per K step
+        const int abase = (kr + 3) * 16 + rrr * 2 + (lq & 1) - 16 * (lq >> 1);
+        double dt[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int rr4 = 16 * rt + 4 * i + lq;
+            dt[i] = (rr4 >> 3) < N ? dtab[(rr4 >> 3) * 8 + (rr4 & 7)] : 0.0;
+        }
         d4 m0 = d4{0.0, 0.0, 0.0, 0.0}, v0 = m0, m1 = m0, v1 = m0;
+        double c0v = sc[lane], w0v = sw[lane], c1v = sc[64 + lane], w1v = sw[64 + lane];
+        double a0 = sp[abase], a1 = sp[abase - 32];
         for (int k4 = 0; k4 < kmax; k4 += 8) {
-            const int kk = k4 + lq;
-            const int j0 = kk >> 1, j1 = (kk + 4) >> 1;
-            const double c0v = sc[kk * 16 + lr], w0v = sw[kk * 16 + lr];
-            const double c1v = sc[(kk + 4) * 16 + lr], w1v = sw[(kk + 4) * 16 + lr];
-            const double a0 = sp[abase - 16 * j0];
-            const double a1 = sp[abase - 16 * j1];
+            const int kn = k4 + 8 < kmax ? k4 + 8 : k4;    // the last prefetch re-reads this step
+            const double c0n = sc[kn * 16 + lane], w0n = sw[kn * 16 + lane];
+            const double c1n = sc[kn * 16 + 64 + lane], w1n = sw[kn * 16 + 64 + lane];
+            const double a0n = sp[abase - 8 * kn], a1n = sp[abase - 8 * kn - 32];
+            // the reads stay ahead of the MFMAs and their results are consumed
+            // only after all four are issued
+            __builtin_amdgcn_sched_barrier(0);
             m0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, c0v, m0, 0, 0, 0);
             v0 = __builtin_amdgcn_mfma_f64_16x16x4f64(fabs(a0), w0v, v0, 0, 0, 0);
             m1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, c1v, m1, 0, 0, 0);
             v1 = __builtin_amdgcn_mfma_f64_16x16x4f64(fabs(a1), w1v, v1, 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+            c0v = c0n; w0v = w0n; c1v = c1n; w1v = w1n; a0 = a0n; a1 = a1n;
         }
         const d4 am = m0 + m1, as = v0 + v1;
         if (!cin) continue;
@@ -462,13 +539,13 @@ __global__ void __launch_bounds__(256) tube_map2_kernel(const double* __restrict
             const double mF = am[i];
             // both sums have nonnegative terms; rounded upward as a whole, 2^-1000 for
             // any flushed subnormal part
-            const double tot = as[i] + dtab[k * 8 + rr];
+            const double tot = as[i] + dt[i];
             const double sF = k > sjl ? INFINITY : tot + tot * A.wid + 0x1p-1000;
             double so = sF * A.scale + A.shift;
-            if (fp) {
+            if (FP) {
                 // [mF - sF, mF + sF] inside [mi - si, mi + si], with the rounding of the
                 // test covered; a tube that is not finite is never accepted
-                if (!frozen && !(sF <= DBL_MAX && (fabs(mF - mi[s][i]) + sF) * (1.0 + 0x1p-50) <= si[s][i]))
+                if (!frozen && !(sF <= DBL_MAX && (fabs(mF - mi[p][i]) + sF) * (1.0 + 0x1p-50) <= si[p][i]))
                     sbad[(c0 + lr) / U - bfirst] = 1u;
                 so = sF + sF * P.tol + P.abs_;
             }
@@ -479,7 +556,7 @@ __global__ void __launch_bounds__(256) tube_map2_kernel(const double* __restrict
             }
         }
     }
-    if (!fp) return;
+    if (!FP) return;
     __syncthreads();
     if (tid < 16 && sbad[tid] && bfirst + tid < A.B) atomicOr(&P.state[bfirst + tid], FP_OPEN);
 }
@@ -649,22 +726,27 @@ static int launch_tube2(int B, int N, int U, const double* phi, const double* e,
     const int gy = (nrt + 4 * TM_RT - 1) / (4 * TM_RT);
     if (gx > 0x7fffffff || cols > 0x7fffffff) return LEB_EINVAL;
     const size_t nst = N > 1 ? N - 1 : 0;
-    const size_t smem = ((size_t)(N + 4) * 16 + (size_t)N * 8 + nst * 8 + 2 * (2 * nst + 8) * 16) * sizeof(double);
-    static size_t dyn_max = 0;
-    if (dyn_max == 0) {
+    const size_t smem = ((size_t)(N + 4) * 16 + (size_t)N * 8 + nst * 8 + 2 * (2 * nst + 8) * 16 + 4) * sizeof(double);
+    const bool isfp = fp.state != nullptr, lng = N > 65;
+    const int which = (isfp ? 2 : 0) + (lng ? 1 : 0);
+    using K2 = void (*)(const double*, Tube2Args, TubeFP);
+    static const K2 kern[4] = {tube_map2_kernel<false, false>, tube_map2_kernel<false, true>,
+                               tube_map2_kernel<true, false>, tube_map2_kernel<true, true>};
+    static size_t dyn_max[4] = {0, 0, 0, 0};
+    if (dyn_max[which] == 0) {
         hipFuncAttributes fa;
-        if (hipFuncGetAttributes(&fa, (const void*)tube_map2_kernel) != hipSuccess) return LEB_EDEVICE;
+        if (hipFuncGetAttributes(&fa, (const void*)kern[which]) != hipSuccess) return LEB_EDEVICE;
         const size_t cap = 160 * 1024 - fa.sharedSizeBytes;
-        if (hipFuncSetAttribute((const void*)tube_map2_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cap) !=
+        if (hipFuncSetAttribute((const void*)kern[which], hipFuncAttributeMaxDynamicSharedMemorySize, (int)cap) !=
             hipSuccess)
             return LEB_EDEVICE;
-        dyn_max = cap;
+        dyn_max[which] = cap;
     }
-    if (smem > dyn_max) return LEB_ENOTSUP;
+    if (smem > dyn_max[which]) return LEB_ENOTSUP;
     if (ev0)        // timed: events at the kernel's start and end
-        hipExtLaunchKernelGGL(tube_map2_kernel, dim3((unsigned)gx, gy), dim3(256), smem, s, ev0, ev1, 0, phi, a, fp);
+        hipExtLaunchKernelGGL(kern[which], dim3((unsigned)gx, gy), dim3(256), smem, s, ev0, ev1, 0, phi, a, fp);
     else
-        hipLaunchKernelGGL(tube_map2_kernel, dim3((unsigned)gx, gy), dim3(256), smem, s, phi, a, fp);
+        hipLaunchKernelGGL(kern[which], dim3((unsigned)gx, gy), dim3(256), smem, s, phi, a, fp);
     return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
 }
 
