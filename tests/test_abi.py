@@ -96,3 +96,32 @@ def test_binding_refuses_cpu_tensors():
         leb.analytic_bound(d, z, torch.zeros((1, 2, 2), dtype=torch.float64),
                            torch.zeros((1, 2, 8), dtype=torch.float64),
                            out={"r_lo": z, "r_hi": z, "flags": torch.zeros((1, 2), dtype=torch.int32)})
+
+
+def test_fixed_point_rejects_bad_options_without_launching(L):
+    """Options are checked before anything touches a device: a tolerance below
+    zero, no sweeps or no absolute inflation is LEB_EINVAL (-1)."""
+    import ctypes
+    import paper_2607_01203_amd as leb
+    d = leb.chain_dynamics(2)
+    e = (ctypes.c_double * 6)(*([0.0] * 3 + [0.01, 0.01, 0.0]))
+    sw = ctypes.c_int32(7)
+    vp = ctypes.c_void_p(8)
+
+    def call(**kw):
+        o = dict(tol=1e-6, max_sweeps=10, pad=0.0, inflate_abs=1e-12, warm=0)
+        o.update(kw)
+        opt = leb.FPOptions(o["tol"], o["max_sweeps"], o["pad"], o["inflate_abs"], o["warm"])
+        return L.leb_fixed_point_solve(ctypes.byref(d), 4, 3, vp, vp, vp, e, ctypes.byref(opt), vp, vp, vp,
+                                       ctypes.byref(sw), None)
+
+    L.leb_fixed_point_solve.restype = ctypes.c_int
+    assert call(tol=-1.0) == -1
+    assert call(max_sweeps=0) == -1
+    assert call(inflate_abs=0.0) == -1
+    assert call(pad=-1.0) == -1
+    # zero work: accepted without a launch
+    opt = leb.FPOptions(1e-6, 10, 0.0, 1e-12, 0)
+    assert L.leb_fixed_point_solve(ctypes.byref(d), 0, 3, None, None, None, e, ctypes.byref(opt), None, None, None,
+                                   ctypes.byref(sw), None) == 0
+    assert sw.value == 0
