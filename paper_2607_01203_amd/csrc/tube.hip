@@ -40,7 +40,7 @@ namespace leb {
 
 constexpr int FP_SLOTS = 4096;            // host-visible open counts, one per sweep (mod FP_SLOTS)
 
-// Fixed-point epilogue of the tube map (state == NULL for the plain map).
+// Fixed-point epilogue of the compact tube map (state == NULL for the plain map).
 struct TubeFP {
     const double* mu_in;  // C_{t-1}: the tube whose bounds produced (c_bar, rho_bar)
     const double* sg_in;
@@ -73,8 +73,6 @@ constexpr int TM_RT = 5;        // 16-row tiles per wave and row group
 // (shared in L1 by the four waves).  Lane l supplies A[l%16][l/16] and
 // B[l/16][l%16]; element i of its accumulator is D[4i + l/16][l%16].
 //
-// Fixed-point form: frozen trajectories are not written; containment
-// failures are or-ed into the state words (fp_state_kernel folds them).
 // row tile of slot s of a wave: tiles are dealt so that each wave gets a
 // mix of short (early steps) and long (late steps) K ranges
 __device__ __forceinline__ int tm_tile(int wave, int s, int group) {
@@ -82,15 +80,12 @@ __device__ __forceinline__ int tm_tile(int wave, int s, int group) {
     return base + ((s & 1) ? 3 - wave : wave);
 }
 
-__global__ void __launch_bounds__(256) tube_map_kernel(const double* __restrict__ phi, TubeArgs A, TubeFP P) {
+__global__ void __launch_bounds__(256) tube_map_kernel(const double* __restrict__ phi, TubeArgs A) {
     // LDS, phase 1: Phi with zero blocks at lags -4..-1 and N-1 [(N+4)*48],
     // e[8], c [6(N-1)+8][16], w [6(N-1)+8][16] (8 zero rows past the end);
     // phase 2 (after the contraction): mu, sigma of 8 steps [64][16] each
     extern __shared__ double sphi[];
-    __shared__ uint32_t sbad[16];
     __shared__ int sjinf[16];
-    const bool fp = P.state != nullptr;
-    if (fp && P.state[A.B] == 0u) return;     // every trajectory certified by an earlier sweep
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int N = A.N, U = A.U, nx = 6 * U, n = 8 * U;
@@ -104,7 +99,6 @@ __global__ void __launch_bounds__(256) tube_map_kernel(const double* __restrict_
     __shared__ int64_t srow[16];   // column c0 + cl: offset of its node's rows in the residual arrays at step 0
     __shared__ int64_t stub[16];   // ... and of its trajectory in the tube arrays
     __shared__ int snode[16];      // ... its node
-    __shared__ uint32_t sfrz[16];  // ... its trajectory is frozen (certified by an earlier sweep)
     const int cols = A.B * U;
     const int c0 = blockIdx.x * 16;
     const int ncol = min(16, cols - c0);
@@ -114,8 +108,6 @@ __global__ void __launch_bounds__(256) tube_map_kernel(const double* __restrict_
         srow[tid] = (int64_t)bb * N * nx + 6 * nd;
         stub[tid] = (int64_t)bb * N * n;
         snode[tid] = nd;
-        sfrz[tid] = fp ? (P.state[bb] & FP_CERT) : 0u;
-        sbad[tid] = 0u;
         sjinf[tid] = 0x7fffffff;
     }
     // Phi (8 loads in flight per thread)
@@ -188,7 +180,6 @@ __global__ void __launch_bounds__(256) tube_map_kernel(const double* __restrict_
     const int nrt = (N + 1) >> 1;
     const int lr = lane & 15, lq = lane >> 4;
     const bool cin = lr < ncol;
-    const int bfirst = c0 / U;
     // The tube entries of this lane's accumulators: element i of slot s is row
     // r = 16 rt + 4 i + lq of the slot's tile, i.e. step k = r / 8, row r % 8 of
     // node column lr.
@@ -196,22 +187,6 @@ __global__ void __launch_bounds__(256) tube_map_kernel(const double* __restrict_
         const int nd = snode[lr];
         return stub[lr] + (int64_t)k * n + (rr < 6 ? 6 * nd + rr : nx + 2 * nd + (rr - 6));
     };
-    double mi[TM_RT][4], si[TM_RT][4];
-#pragma unroll
-    for (int s = 0; s < TM_RT; ++s) {
-        const int rt = tm_tile(wave, s, blockIdx.y);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int r = 16 * rt + 4 * i + lq, k = r >> 3;
-            mi[s][i] = 0.0;
-            si[s][i] = 0.0;
-            if (fp && cin && rt < nrt && k < N && !sfrz[lr]) {
-                const int64_t o = tube_off(r & 7, k);
-                mi[s][i] = P.mu_in[o];
-                si[s][i] = P.sg_in[o];
-            }
-        }
-    }
 #pragma unroll
     for (int u = 0; u < 16; ++u)
         if (tid + 256 * u < pent) stage_store(0, tid + 256 * u, pc[u], pr[u]);
@@ -225,7 +200,6 @@ __global__ void __launch_bounds__(256) tube_map_kernel(const double* __restrict_
             if (i0 + 256 * u < pent) stage_store(0, i0 + 256 * u, cv[u], rv[u]);
     }
     __syncthreads();
-    const bool frozen = sfrz[lr] != 0u;
     // one K loop per slot, two K steps per iteration into separate accumulators
     // (four independent MFMA chains); the zero padding of Phi (lags down to -4)
     // and of the B block (8 rows) covers the reads past a tile's range.
@@ -265,19 +239,9 @@ __global__ void __launch_bounds__(256) tube_map_kernel(const double* __restrict_
                 const double mF = am[i];
                 // sums of nonnegative terms, rounded upward; 2^-1000 covers any flushed subnormal part
                 const double sF = k > sjl ? INFINITY : as[i] + as[i] * A.wid + 0x1p-1000;
-                double so = sF * A.scale + A.shift;
-                if (fp) {
-                    // [mF - sF, mF + sF] inside [mi - si, mi + si], with the rounding of the
-                    // test covered; a tube that is not finite is never accepted
-                    if (!frozen && !(sF <= DBL_MAX && (fabs(mF - mi[s][i]) + sF) * (1.0 + 0x1p-50) <= si[s][i]))
-                        sbad[(c0 + lr) / U - bfirst] = 1u;
-                    so = sF + sF * P.tol + P.abs_;
-                }
-                if (!frozen) {
-                    const int64_t o = tube_off(rr, k);
-                    A.mu[o] = mF;
-                    A.sigma[o] = so;
-                }
+                const int64_t o = tube_off(rr, k);
+                A.mu[o] = mF;
+                A.sigma[o] = sF * A.scale + A.shift;
             }
         }
         if (s + 1 < TM_RT) {
@@ -289,9 +253,6 @@ __global__ void __launch_bounds__(256) tube_map_kernel(const double* __restrict_
             lds_barrier();
         }
     }
-    if (!fp) return;
-    __syncthreads();
-    if (tid < 16 && sbad[tid] && bfirst + tid < A.B) atomicOr(&P.state[bfirst + tid], FP_OPEN);
 }
 
 // Tube map for residual zonotopes that are (0, pad) on the four affine rows
@@ -670,7 +631,7 @@ static unsigned nblk(int64_t count) { return (unsigned)((count + 255) / 256); }
 static double tube_wid(int N) { return fmax(0x1p-44, (6.0 * (N > 0 ? N - 1 : 0) + 4.0) * 0x1p-52); }
 
 static int launch_tube(int B, int N, int U, const double* phi, const double* e, const double* cbar,
-                       const double* rbar, double* mu, double* sigma, const TubeFP& fp, hipStream_t s,
+                       const double* rbar, double* mu, double* sigma, hipStream_t s,
                        double scale = 1.0, double shift = 0.0, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
     TubeArgs a;
     a.cbar = cbar; a.rbar = rbar;
@@ -701,9 +662,9 @@ static int launch_tube(int B, int N, int U, const double* phi, const double* e, 
     }
     if (smem > dyn_max) return LEB_ENOTSUP;     // N <= 83
     if (ev0)        // timed: events at the kernel's start and end
-        hipExtLaunchKernelGGL(tube_map_kernel, dim3((unsigned)gx, gy), dim3(256), smem, s, ev0, ev1, 0, phi, a, fp);
+        hipExtLaunchKernelGGL(tube_map_kernel, dim3((unsigned)gx, gy), dim3(256), smem, s, ev0, ev1, 0, phi, a);
     else
-        hipLaunchKernelGGL(tube_map_kernel, dim3((unsigned)gx, gy), dim3(256), smem, s, phi, a, fp);
+        hipLaunchKernelGGL(tube_map_kernel, dim3((unsigned)gx, gy), dim3(256), smem, s, phi, a);
     return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
 }
 
@@ -773,8 +734,7 @@ int launch_disturbance_tube(int B, int N, int U, const double* phi, const double
 
 int launch_tube_map(int B, int N, int U, const double* phi, const double* e, const double* cbar,
                     const double* rbar, double* mu, double* sigma, hipStream_t s, double scale, double shift) {
-    TubeFP none{nullptr, nullptr, nullptr, 0.0, 0.0};
-    return launch_tube(B, N, U, phi, e, cbar, rbar, mu, sigma, none, s, scale, shift);
+    return launch_tube(B, N, U, phi, e, cbar, rbar, mu, sigma, s, scale, shift);
 }
 
 // ------------------------------------------------------------ workspace
