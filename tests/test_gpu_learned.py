@@ -134,20 +134,23 @@ def test_learned_fixed_point_certified_and_fewer_sweeps(trained, orc):
     assert tube.contains(mu1[idx], sg1[idx], m2, s2).all()
 
 
-def test_untrained_surrogate_still_certifies(trained, orc):
+@pytest.mark.parametrize("batch,N,U", [(4, 12, 28), (2, 70, 3)])
+def test_untrained_surrogate_still_certifies(trained, orc, batch, N, U):
     """A surrogate that predicts nonsense changes the start, not the
-    certificate: the certified iteration converges from any start."""
+    certificate: the certified iteration converges from any start (also at
+    70 steps, where the tube maps stage their inputs in passes)."""
     import torch
     from paper_2607_01203_amd import learned
     leb, _, dev, _ = trained
     bad = leb.Surrogate(learned.CHAIN_WIDTHS, learned.he_init(learned.CHAIN_WIDTHS, 9))
-    tp = W.fixed_point_cfg(seed=50, batch=4, N=12, n_units=28)
+    tp = W.fixed_point_cfg(seed=50, batch=batch, N=N, n_units=U)
     b = tp.batch
     dyn = leb.dynamics_like(b.dyn)
+    print("case: untrained surrogate B=%d N=%d U=%d" % (batch, N, U), flush=True)
     mu, sg, cert, sw = leb.fixed_point_learned(dyn, _t(b.z, dev), _t(b.v, dev), _t(tp.phi, dev), tp.e, bad,
                                                sweeps=3, margin=0.0)
     torch.cuda.synchronize()
     bad.close()
     assert bool((cert == 1).all())
-    mo, so, _, _ = _oracle_fixed_point(orc, tp, np.arange(4))
+    mo, so, _, _ = _oracle_fixed_point(orc, tp, np.arange(batch))
     assert (sg.cpu().numpy() >= so * (1 - 1e-12)).all()
