@@ -230,12 +230,21 @@ struct StepArgs {
 // MFMA f64 16x16x4 operand layout (per 64-lane wave; checked on gfx950):
 // lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator
 // element i of lane l is D[4 i + l / 16][l % 16].
+// The K loop runs in chunks of 16: the W tile and the chunk's per-k vectors
+// (slopes, offsets, bias, rounding weights) go through LDS (two buffers), the
+// A values into registers; the next chunk's loads are in flight during this
+// chunk's MFMAs, with one barrier per chunk.  Loads are unconditional
+// (clamped addresses, values selected), so no wait covers a later chunk.
 template <int WR, int WC, int TPW>
 __global__ void __launch_bounds__(256) nn_step_kernel(StepArgs S) {
     constexpr int NT = 16 * TPW * WC;
-    __shared__ double s_w[16][NT];
+    constexpr int WPT = 16 * NT / 256;               // W tile values per thread and chunk
+    static_assert(WPT >= 1 && 16 * NT % 256 == 0, "W tile split");
+    __shared__ double s_w[2][16][NT];
+    __shared__ double s_v[2][6][16];                 // spos, sneg, tpos, tneg, bias, e of the chunk's k
     __shared__ double s_red[4][64][3];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
     const int wr = wave / WC, wc = wave % WC;
     const int zidx = blockIdx.y;                 // mode * nbox + box
     const int mode = zidx / S.nbox, box = zidx - mode * S.nbox;
@@ -244,37 +253,77 @@ __global__ void __launch_bounds__(256) nn_step_kernel(StepArgs S) {
     const int kq = lane >> 4;
     const StepMode md = S.md[mode];
     const size_t boxW = (size_t)box * NN_MAXW;
-    const double* Arow = S.a_shared ? S.A + (size_t)row * S.K
-                                    : S.A + (((size_t)mode * S.nbox + box) * S.M + row) * S.K;
     const bool rowok = row < S.M;
+    const double* Arow = S.a_shared ? S.A + (size_t)(rowok ? row : 0) * S.K
+                                    : S.A + (((size_t)mode * S.nbox + box) * S.M + (rowok ? row : 0)) * S.K;
+    const bool has_tpos = md.tpos != nullptr, has_tneg = md.tneg != nullptr;
+    // the per-k vector of thread tid < 96: q = tid / 16 (0 spos, 1 sneg, 2 tpos, 3 tneg, 4 bias, 5 e)
+    const int vq = tid >> 4, vk = tid & 15;
+    const double* vsrc = nullptr;
+    if (tid < 96) {
+        switch (vq) {
+            case 0: vsrc = md.spos + boxW; break;
+            case 1: vsrc = md.sneg + boxW; break;
+            case 2: vsrc = has_tpos ? md.tpos + boxW : nullptr; break;
+            case 3: vsrc = has_tneg ? md.tneg + boxW : nullptr; break;
+            case 4: vsrc = S.bias; break;
+            default: vsrc = S.e + boxW; break;
+        }
+    }
+    double wv[WPT], vv = 0.0, ar[4];
+    auto gload = [&](int kc) {
+#pragma unroll
+        for (int u = 0; u < WPT; ++u) {
+            const int idx = tid + 256 * u;
+            const int kk = idx / NT, nn = idx - kk * NT;
+            const int k = kc + kk;
+            const bool ok = k < S.K && nn < S.N;
+            const double x = S.W[ok ? (size_t)k * S.N + nn : 0];
+            wv[u] = ok ? x : 0.0;
+        }
+        if (vsrc) {
+            const int k = kc + vk;
+            const double x = vsrc[k < S.K ? k : 0];
+            vv = k < S.K ? x : 0.0;
+        }
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            const int k = kc + 4 * st + kq;
+            const bool ok = rowok && k < S.K;
+            const double x = Arow[ok ? k : 0];
+            ar[st] = ok ? x : 0.0;
+        }
+    };
     d4 acc[TPW];
 #pragma unroll
     for (int t = 0; t < TPW; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
     double pb = 0.0, pe = 0.0;                    // per-lane partial bias / rounding sums
-    for (int kc = 0; kc < S.K; kc += 16) {
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < 16 * NT; idx += 256) {
+    gload(0);
+    for (int kc = 0, c = 0; kc < S.K; kc += 16, ++c) {
+        const int buf = c & 1;
+#pragma unroll
+        for (int u = 0; u < WPT; ++u) {
+            const int idx = tid + 256 * u;
             const int kk = idx / NT, nn = idx - kk * NT;
-            const int k = kc + kk;
-            s_w[kk][nn] = (k < S.K && nn < S.N) ? S.W[(size_t)k * S.N + nn] : 0.0;
+            s_w[buf][kk][nn] = wv[u];
         }
-        __syncthreads();
+        if (tid < 96) s_v[buf][vq][vk] = vv;       // (a missing t vector stays 0 and unused)
+        double a[4];
+#pragma unroll
+        for (int st = 0; st < 4; ++st) a[st] = ar[st];
+        if (kc + 16 < S.K) gload(kc + 16);         // the next chunk, in flight during this one's MFMAs
+        __syncthreads();                            // buffer buf written; buffer buf^1 no longer read
         double av[4];
 #pragma unroll
         for (int st = 0; st < 4; ++st) {
-            const int k = kc + 4 * st + kq;
-            double om = 0.0;
-            if (rowok && k < S.K) {
-                const double a = Arow[k];
-                const bool pos = a >= 0.0;
-                const double sl = pos ? md.spos[boxW + k] : md.sneg[boxW + k];
-                om = a * sl;
-                if (wc == 0) {
-                    const double* tp = pos ? md.tpos : md.tneg;
-                    if (tp) pb = __builtin_fma(a, tp[boxW + k], pb);
-                    pb = __builtin_fma(om, S.bias[k], pb);
-                    pe = __builtin_fma(fabs(a), S.e[boxW + k], pe);
-                }
+            const int kk = 4 * st + kq;
+            const double x = a[st];
+            const bool pos = x >= 0.0;
+            const double om = x * (pos ? s_v[buf][0][kk] : s_v[buf][1][kk]);
+            if (wc == 0) {
+                if (pos ? has_tpos : has_tneg) pb = __builtin_fma(x, pos ? s_v[buf][2][kk] : s_v[buf][3][kk], pb);
+                pb = __builtin_fma(om, s_v[buf][4][kk], pb);
+                pe = __builtin_fma(fabs(x), s_v[buf][5][kk], pe);
             }
             av[st] = om;
         }
@@ -282,7 +331,7 @@ __global__ void __launch_bounds__(256) nn_step_kernel(StepArgs S) {
         for (int st = 0; st < 4; ++st) {
 #pragma unroll
             for (int t = 0; t < TPW; ++t) {
-                const double bv = s_w[4 * st + kq][16 * (wc * TPW + t) + (lane & 15)];
+                const double bv = s_w[buf][4 * st + kq][16 * (wc * TPW + t) + (lane & 15)];
                 acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[st], bv, acc[t], 0, 0, 0);
             }
         }
