@@ -132,7 +132,20 @@ __global__ void __launch_bounds__(256) nn_prep_kernel(PrepArgs A) {
             const double* WT = A.WT[l];
             z = A.b[l][q];
             mz = fabs(A.b[l][q]);
-            for (int k = 0; k < in; ++k) {
+            // eight k at a time, the weight loads of a group issued before its sums
+            int k = 0;
+            for (; k + 8 <= in; k += 8) {
+                double wv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) wv[u] = WT[(size_t)(k + u) * out + q];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    z = __builtin_fma(wv[u], s_a[k + u], z);
+                    mz = __builtin_fma(fabs(wv[u]), s_m[k + u], mz);
+                    vz = __builtin_fma(fabs(wv[u]), s_v[k + u], vz);
+                }
+            }
+            for (; k < in; ++k) {
                 const double wk = WT[(size_t)k * out + q];
                 z = __builtin_fma(wk, s_a[k], z);
                 mz = __builtin_fma(fabs(wk), s_m[k], mz);
@@ -197,7 +210,15 @@ __global__ void __launch_bounds__(256) nn_relax_kernel(RelaxArgs A) {
         a = (u >= -l) ? 1.0 : 0.0;
     }
     double wa = 0.0;
-    for (int k = 0; k < A.in; ++k) wa = __builtin_fma(fabs(A.WT[(size_t)k * A.out + q]), s_am[k], wa);
+    int k = 0;
+    for (; k + 8 <= A.in; k += 8) {           // the weight loads of a group issued before its sums
+        double wv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) wv[u] = A.WT[(size_t)(k + u) * A.out + q];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) wa = __builtin_fma(fabs(wv[u]), s_am[k + u], wa);
+    }
+    for (; k < A.in; ++k) wa = __builtin_fma(fabs(A.WT[(size_t)k * A.out + q]), s_am[k], wa);
     A.s[o] = s; A.t[o] = t; A.a[o] = a;
     A.D[o] = A.zhat[o] > 0.0 ? 1.0 : 0.0;
     A.e[o] = fmax(fabs(l), fabs(u)) + wa + fabs(A.b[q]) + fabs(t);
@@ -383,7 +404,20 @@ __global__ void __launch_bounds__(256) nn_concretize_kernel(ConcArgs A) {
     const double* c = A.c + (size_t)box * A.n0;
     const double* rho = A.rho + (size_t)box * A.n0;
     double lin = 0.0, mag = 0.0, ab = 0.0;
-    for (int k = 0; k < A.n0; ++k) {
+    // eight k at a time, every load of a group issued before its sums (same order of summation)
+    int k = 0;
+    for (; k + 8 <= A.n0; k += 8) {
+        double lv[8], cv[8], rv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) { lv[u] = Lr[k + u]; cv[u] = c[k + u]; rv[u] = rho[k + u]; }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            lin = __builtin_fma(lv[u], cv[u], lin);
+            mag = __builtin_fma(fabs(lv[u]), rv[u], mag);
+            ab = __builtin_fma(fabs(lv[u]), fabs(cv[u]), ab);
+        }
+    }
+    for (; k < A.n0; ++k) {
         lin = __builtin_fma(Lr[k], c[k], lin);
         mag = __builtin_fma(fabs(Lr[k]), rho[k], mag);
         ab = __builtin_fma(fabs(Lr[k]), fabs(c[k]), ab);
