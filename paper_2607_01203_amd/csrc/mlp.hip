@@ -441,15 +441,33 @@ __global__ void __launch_bounds__(256) sum_kernel(const float* partial, int n, f
 }
 
 // db[c] = sum_b X[b][c] (c < n), one workgroup per 64 columns, fixed order
+// Column sums of X [B][n] (row stride ldx): a workgroup takes 4 columns, its
+// 256 lanes 64 row phases of each (every lane's loads in flight together),
+// then a fixed-order tree over the phases.
 __global__ void __launch_bounds__(256) colsum_kernel(const float* X, int64_t ldx, int B, int n, float* db) {
-    __shared__ float red[4][64];
-    const int c = blockIdx.x * 64 + (threadIdx.x & 63), part = threadIdx.x >> 6;
+    __shared__ float red[64][4];
+    const int cq = threadIdx.x & 3, part = threadIdx.x >> 2;
+    const int c = blockIdx.x * 4 + cq;
+    const int cc = c < n ? c : 0;
     float acc = 0.0f;
-    if (c < n)
-        for (int b = part; b < B; b += 4) acc += X[(int64_t)b * ldx + c];
-    red[part][threadIdx.x & 63] = acc;
+    for (int b0 = part; b0 < B; b0 += 8 * 64) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int b = b0 + 64 * u;
+            const float x = X[(int64_t)(b < B ? b : 0) * ldx + cc];
+            v[u] = b < B ? x : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    red[part][cq] = acc;
     __syncthreads();
-    if (part == 0 && c < n) db[c] = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+    for (int h = 32; h > 0; h >>= 1) {
+        if (part < h) red[part][cq] += red[part + h][cq];
+        __syncthreads();
+    }
+    if (part == 0 && c < n) db[c] = red[0][cq];
 }
 
 // Adam with the step-dependent factors formed on the host in FP64:
@@ -688,7 +706,7 @@ static int bwd_core(leb_surrogate_s* s, int B, float* grads, hipStream_t st) {
         p.C = dW; p.ldc = in; p.Mst = out; p.Nst = in;
         hipLaunchKernelGGL(mlp_gemm_kernel, dim3(nb(in, 64), nb(out, 64)), dim3(256), 0, st, p);
         // db_l = column sums of dz_l
-        hipLaunchKernelGGL(colsum_kernel, dim3(nb(out, 64)), dim3(256), 0, st, s->dz[cur], (int64_t)W, B, out, db);
+        hipLaunchKernelGGL(colsum_kernel, dim3(nb(out, 4)), dim3(256), 0, st, s->dz[cur], (int64_t)W, B, out, db);
         if (l > 0) {
             // dz_{l-1} = (g_l W~_l) * gelu'(z_{l-1}): A = g [B][np_l], Bt = W~_l^T [kp_l][np_l]
             GemmArgs q{};
