@@ -69,22 +69,23 @@ __device__ __forceinline__ float gelu_train_f(float z) {
 // GELU of inference: z Phi(z) = max(z, 0) - |z| erfc(|z| / sqrt 2) / 2, with erfc from
 // Abramowitz and Stegun, formula 7.1.28 (|error of erf| <= 3e-7):
 // erf(x) ~ 1 - (1 + a1 x + ... + a6 x^6)^-16, x >= 0 -- one reciprocal and no
-// exponential.  The coefficients below are a_i / sqrt(2)^i, so the
-// polynomial is evaluated at |z|; a large |z| drives the 16th power to +inf
-// and the correction to 0.
+// exponential.  The coefficients below are c a_i / sqrt(2)^i with c = 2^(1/16):
+// the polynomial is evaluated at |z| and its 16th power is 2 (1 + ...)^16, so
+// the correction |z| / (2 (1 + ...)^16) is one fma; a large |z| drives the
+// power to +inf and the correction to 0.  max(z, 0) is a median of three.
 __device__ __forceinline__ float gelu_f(float z) {
     const float x = fabsf(z);
-    float p = fmaf(x, 5.38297500e-6f, 4.88906356e-5f);
-    p = fmaf(x, p, 3.80035750e-5f);
-    p = fmaf(x, p, 3.27762632e-3f);
-    p = fmaf(x, p, 2.11410061e-2f);
-    p = fmaf(x, p, 4.98673470e-2f);
-    p = fmaf(x, p, 1.0f);
+    float p = fmaf(x, 5.62129966e-6f, 5.10552090e-5f);
+    p = fmaf(x, p, 3.96861370e-5f);
+    p = fmaf(x, p, 3.42273924e-3f);
+    p = fmaf(x, p, 2.20769985e-2f);
+    p = fmaf(x, p, 5.20751630e-2f);
+    p = fmaf(x, p, 1.04427378f);
     p = p * p;
     p = p * p;
     p = p * p;
     p = p * p;
-    return fmaf(-0.5f * x, __builtin_amdgcn_rcpf(p), fmaxf(z, 0.0f));
+    return fmaf(-x, __builtin_amdgcn_rcpf(p), __builtin_amdgcn_fmed3f(z, 0.0f, INFINITY));
 }
 __device__ __forceinline__ float gelu_grad_f(float z) {
     float P, e;

@@ -590,14 +590,13 @@ __global__ void __launch_bounds__(256) disturbance_tube_kernel(const double* __r
         g[t] = acc;
     }
     __syncthreads();
-    if (threadIdx.x < 8) {
-        const int r = threadIdx.x;
+    // tab[k][r] from the lag sums in increasing d, one (k, r) per thread (the
+    // loads of a sum are independent; the order of each sum is fixed)
+    for (int t = threadIdx.x; t < N * 8; t += 256) {
+        const int k = t >> 3, r = t & 7;
         double acc = 0.0;
-        tab[r] = 0.0;
-        for (int k = 1; k < N; ++k) {
-            acc += g[(k - 1) * 8 + r];
-            tab[k * 8 + r] = acc + acc * A.wid + 0x1p-1000;
-        }
+        for (int d = 0; d < k; ++d) acc += g[d * 8 + r];
+        tab[t] = k == 0 ? 0.0 : acc + acc * A.wid + 0x1p-1000;
     }
     __syncthreads();
     for (int row = blockIdx.x; row < rows; row += gridDim.x) {       // row = (trajectory, step)
