@@ -19,6 +19,27 @@ __device__ __forceinline__ void lds_barrier() {
 // Per-trajectory fixed-point state word.
 constexpr uint32_t FP_CERT = 1u;          // certified (frozen)
 constexpr uint32_t FP_OPEN = 1u << 31;    // this sweep: F(C) not inside C
+constexpr int FP_SLOTS = 4096;            // host-visible open counts, one per sweep (mod FP_SLOTS)
+
+// The fold of fixed-point sweep t, done by the bound launch of sweep t + 1:
+// every workgroup counts the trajectories left open by sweep t (and returns
+// at once when there are none); workgroup 0 also writes the folded state
+// words (certified at t, or open) and the count for sweep t + 1 and publishes
+// the count to host memory.  sweep == 0: nothing to fold, every trajectory open.
+struct SweepFold {
+    const uint32_t* prev;   // [B] state words after sweep t's containment marks
+    uint32_t* next;         // [B] folded words, [B] open count after sweep t
+    uint32_t* host_open;    // host-mapped counts, slot t % FP_SLOTS
+    int B;
+    int sweep;              // t
+};
+// fold of state words: certified at sweep t unless marked open
+__device__ __forceinline__ uint32_t fp_fold_word(uint32_t st, int sweep) {
+    return (st & FP_CERT) ? st : ((st & FP_OPEN) ? 0u : (FP_CERT | ((uint32_t)sweep << 1)));
+}
+__device__ __forceinline__ uint32_t fp_is_open(uint32_t st) {
+    return (!(st & FP_CERT) && (st & FP_OPEN)) ? 1u : 0u;
+}
 
 // one workgroup's share of a batched bound launch: up to T units of one problem
 struct PbhTile {
@@ -35,7 +56,7 @@ size_t pbh_smem_bytes_T(int U, int T);
 int launch_pbh_chain(const leb_dynamics* dyn, int64_t units, const double* z, const double* v,
                      const double* mu, const double* sigma, double* r_lo, double* r_hi, double* c_bar,
                      double* rho_bar, double pad, uint32_t* flags, hipStream_t stream,
-                     const uint32_t* open = nullptr, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                     const SweepFold* fold = nullptr, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
                      bool compact = false);
 int launch_fill_zero(int64_t count, double* r_lo, double* r_hi, double* c_bar, double* rho_bar, double pad,
                      uint32_t* flags, int64_t nflags, hipStream_t stream);

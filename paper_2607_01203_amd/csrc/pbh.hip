@@ -51,7 +51,7 @@ constexpr int PBH_BLOCK = 256;
 struct ChainArgs {
     const double* z; const double* v; const double* mu; const double* sigma;
     double* r_lo; double* r_hi; double* c_bar; double* rho_bar; uint32_t* flags;
-    const uint32_t* open;   // optional: return at once when *open == 0 (fixed point already certified)
+    SweepFold fold;         // fixed point: the previous sweep's fold (fold.prev == NULL: none)
     const PbhTile* tiles;   // optional: one tile (its own pointers, <= T units) per workgroup
     int64_t units;
     int U, T;
@@ -116,8 +116,19 @@ __global__ void __launch_bounds__(PBH_BLOCK) pbh_chain_fwd(ChainArgs A) {
     SpringOut* s_sp = reinterpret_cast<SpringOut*>(smem);                  // [T][U]
     uint32_t* s_flag = reinterpret_cast<uint32_t*>(s_sp + (size_t)T * U);   // [T]
 
-    if (A.open && *A.open == 0u) return;
     const int tid = threadIdx.x;
+    // fixed point: trajectories left open by the previous sweep, counted by every
+    // workgroup (a wave reduction, then the four wave sums after the barrier below)
+    __shared__ uint32_t s_wopen[PBH_BLOCK / 64];
+    const bool fold = A.fold.prev != nullptr;
+    if (fold) {
+        uint32_t my = 0;
+        if (A.fold.sweep > 0)
+            for (int b = tid; b < A.fold.B; b += PBH_BLOCK) my += fp_is_open(A.fold.prev[b]);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) my += __shfl_xor(my, off);
+        if ((tid & 63) == 0) s_wopen[tid >> 6] = my;
+    }
     TileRef t0;
     if (A.tiles) {
         const PbhTile& pt = A.tiles[blockIdx.x];
@@ -138,7 +149,26 @@ __global__ void __launch_bounds__(PBH_BLOCK) pbh_chain_fwd(ChainArgs A) {
     const int i = tid - lt * U;
     NodeIn d0;
     node_load(t0, U, lt, i, d0);
-    __syncthreads();      // s_flag cleared
+    __syncthreads();      // s_flag cleared, s_wopen written
+    if (fold) {
+        uint32_t open = (uint32_t)A.fold.B;
+        if (A.fold.sweep > 0) {
+            open = 0;
+#pragma unroll
+            for (int w = 0; w < PBH_BLOCK / 64; ++w) open += s_wopen[w];
+        }
+        if (blockIdx.x == 0) {
+            for (int b = tid; b < A.fold.B; b += PBH_BLOCK)
+                A.fold.next[b] = A.fold.sweep > 0 ? fp_fold_word(A.fold.prev[b], A.fold.sweep) : 0u;
+            if (tid == 0) {
+                A.fold.next[A.fold.B] = open;
+                if (A.fold.sweep > 0)
+                    __hip_atomic_store(&A.fold.host_open[A.fold.sweep % FP_SLOTS], open, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+        }
+        if (open == 0u) return;       // every trajectory certified by an earlier sweep
+    }
     node_pass(A, t0, d0, lt, i, s_sp, s_flag);
 }
 
@@ -161,12 +191,12 @@ size_t pbh_smem_bytes(int U) { return pbh_smem_bytes_T(U, PBH_BLOCK / U); }
 
 int launch_pbh_chain(const leb_dynamics* dyn, int64_t units, const double* z, const double* v,
                      const double* mu, const double* sigma, double* r_lo, double* r_hi, double* c_bar,
-                     double* rho_bar, double pad, uint32_t* flags, hipStream_t stream, const uint32_t* open,
+                     double* rho_bar, double pad, uint32_t* flags, hipStream_t stream, const SweepFold* fold,
                      hipEvent_t ev0, hipEvent_t ev1, bool compact) {
     ChainArgs a;
     a.z = z; a.v = v; a.mu = mu; a.sigma = sigma;
     a.r_lo = r_lo; a.r_hi = r_hi; a.c_bar = c_bar; a.rho_bar = rho_bar; a.flags = flags;
-    a.open = open;
+    a.fold = fold ? *fold : SweepFold{nullptr, nullptr, nullptr, 0, 0};
     a.tiles = nullptr;
     a.units = units;
     a.U = dyn->n_units;

@@ -38,7 +38,6 @@
 
 namespace leb {
 
-constexpr int FP_SLOTS = 4096;            // host-visible open counts, one per sweep (mod FP_SLOTS)
 
 // Fixed-point epilogue of the compact tube map (state == NULL for the plain map).
 struct TubeFP {
@@ -522,29 +521,23 @@ __global__ void __launch_bounds__(256) tube_map2_kernel(const double* __restrict
     if (tid < 16 && sbad[tid] && bfirst + tid < A.B) atomicOr(&P.state[bfirst + tid], FP_OPEN);
 }
 
-// After the tube map of sweep t: fold this sweep's containment into the
-// state words (certified at t, or open) and publish the open count to the
-// device word and to host memory.  One workgroup.
-__global__ void __launch_bounds__(256) fp_state_kernel(uint32_t* state, int B, uint32_t* host_open, int sweep) {
-    if (state[B] == 0u) return;       // nothing open: this sweep was not needed
+// The fold of sweep t when no bound launch of sweep t + 1 follows (the sweep
+// cap): the same as that launch's workgroup 0 (one workgroup).
+__global__ void __launch_bounds__(256) fp_fold_kernel(SweepFold F) {
     __shared__ uint32_t cnt;
     if (threadIdx.x == 0) cnt = 0;
     __syncthreads();
     uint32_t open = 0;
-    for (int t = threadIdx.x; t < B; t += 256) {
-        const uint32_t st = state[t];
-        uint32_t ns = st;
-        if (!(st & FP_CERT)) {
-            ns = (st & FP_OPEN) ? 0u : (FP_CERT | ((uint32_t)sweep << 1));
-            state[t] = ns;
-        }
-        open += (ns & FP_CERT) ? 0u : 1u;
+    for (int b = threadIdx.x; b < F.B; b += 256) {
+        const uint32_t st = F.prev[b];
+        open += fp_is_open(st);
+        F.next[b] = fp_fold_word(st, F.sweep);
     }
     atomicAdd(&cnt, open);
     __syncthreads();
     if (threadIdx.x == 0) {
-        state[B] = cnt;
-        __hip_atomic_store(&host_open[sweep % FP_SLOTS], cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        F.next[F.B] = cnt;
+        __hip_atomic_store(&F.host_open[F.sweep % FP_SLOTS], cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
@@ -872,15 +865,18 @@ extern "C" int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int
     const size_t bx = (size_t)units * 2 * U * sizeof(double), bn = (size_t)units * n * sizeof(double);
     if ((rc = ws_get(0, bx, (void**)&cb)) || (rc = ws_get(1, bx, (void**)&rb)) ||
         (rc = ws_get(2, bn, (void**)&xm1)) || (rc = ws_get(3, bn, (void**)&xs1)) ||
-        (rc = ws_get(4, ((size_t)batch + 1) * sizeof(uint32_t), (void**)&state)) || (rc = ws_host()))
+        (rc = ws_get(4, 2 * ((size_t)batch + 1) * sizeof(uint32_t), (void**)&state)) || (rc = ws_host()))
         return rc;
     // iterates: buffer 0 = the caller's (mu, sigma), buffer 1 = workspace; sweep t reads C_{t-1}
     // from buffer (t-1) & 1 and writes C_t to buffer t & 1
     double* xm[2] = {mu, xm1};
     double* xs[2] = {sigma, xs1};
+    // state words [B] + open count: sweep t marks st[t & 1]; the bound launch of
+    // sweep t + 1 folds them into st[(t + 1) & 1] (st[0] starts all open)
+    uint32_t* st[2] = {state, state + batch + 1};
     const int64_t per = (int64_t)N * n;
     auto ok = [](hipError_t e_) { return e_ == hipSuccess; };
-    hipLaunchKernelGGL(fp_init_kernel, dim3(nblk(batch + 1)), dim3(256), 0, s, state, batch);
+    hipLaunchKernelGGL(fp_init_kernel, dim3(nblk(batch + 1)), dim3(256), 0, s, st[0], batch);
     if (!opt->warm)         // C_0: the disturbance-only tube (LEB = 0), below the fixed point
         if ((rc = launch_disturbance_tube(batch, N, U, phi, e, opt->pad, mu, sigma, s))) return rc;
     volatile uint32_t* hopen = g_ws.host_open;
@@ -890,17 +886,17 @@ extern "C" int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int
         hipEvent_t b0, b1, t0, t1;
         lt_pair(0, &b0, &b1);
         lt_pair(1, &t0, &t1);
+        // this launch folds sweep t - 1 and publishes its count
+        hopen[(t - 1) % FP_SLOTS] = 0xffffffffu;
+        const SweepFold fold{st[a], st[w], g_ws.host_open_dev, batch, t - 1};
         int r = launch_pbh_chain(dyn, units, z, v, xm[a], xs[a], nullptr, nullptr, cb, rb, opt->pad, nullptr, s,
-                                 state + batch, b0, b1, true);
+                                 &fold, b0, b1, true);
         if (r) return r;
-        hopen[t % FP_SLOTS] = 0xffffffffu;
-        const TubeFP fp{xm[a], xs[a], state, opt->tol, opt->inflate_abs};
-        if ((r = launch_tube2(batch, N, U, phi, e, opt->pad, cb, rb, xm[w], xs[w], fp, s, 1.0, 0.0, t0, t1))) return r;
-        hipLaunchKernelGGL(fp_state_kernel, dim3(1), dim3(256), 0, s, state, batch, g_ws.host_open_dev, t);
-        return ok(hipGetLastError()) ? LEB_OK : LEB_EDEVICE;
+        const TubeFP fp{xm[a], xs[a], st[w], opt->tol, opt->inflate_abs};
+        return launch_tube2(batch, N, U, phi, e, opt->pad, cb, rb, xm[w], xs[w], fp, s, 1.0, 0.0, t0, t1);
     };
-    // Wait until sweep t has published its open count.  The count is written to
-    // pinned host memory by the state kernel.  The stream is queried only after
+    // Wait until the open count of sweep t is published: the bound launch of
+    // sweep t + 1 (or the fold kernel at the sweep cap) writes it to pinned host memory.  The stream is queried only after
     // 2 ms without it (a query can put a marker between the sweeps' kernels), so
     // that the wait also ends if the stream drains (or fails) without a count.
     auto wait_count = [&](int t, uint32_t* out) -> int {
@@ -927,7 +923,14 @@ extern "C" int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int
     int t = 1;
     uint32_t open = 0, open_before = (uint32_t)batch;    // open counts after sweeps t and t - 1
     for (;;) {
-        if (t < opt->max_sweeps && (rc = sweep(t + 1))) return rc;
+        if (t < opt->max_sweeps) {
+            if ((rc = sweep(t + 1))) return rc;
+        } else {                                        // the cap: fold the last sweep on its own
+            hopen[t % FP_SLOTS] = 0xffffffffu;
+            const SweepFold fold{st[t & 1], st[(t + 1) & 1], g_ws.host_open_dev, batch, t};
+            hipLaunchKernelGGL(fp_fold_kernel, dim3(1), dim3(256), 0, s, fold);
+            if (!ok(hipGetLastError())) return LEB_EDEVICE;
+        }
         if ((rc = wait_count(t, &open))) return rc;
         if (open == 0 || t == opt->max_sweeps) break;
         open_before = open;
@@ -938,8 +941,8 @@ extern "C" int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int
     const bool in_place = open == 0 && open_before == (uint32_t)batch && ((t - 1) & 1) == 0;
     if (!in_place)
         hipLaunchKernelGGL(fp_final_kernel, dim3(batch, (unsigned)std::min<int64_t>((per + 255) / 256, 16)), dim3(256),
-                           0, s, xm1, xs1, mu, sigma, state, per, t);
-    hipLaunchKernelGGL(cert_out_kernel, dim3(nblk(batch)), dim3(256), 0, s, state, certified, batch);
+                           0, s, xm1, xs1, mu, sigma, st[(t + 1) & 1], per, t);
+    hipLaunchKernelGGL(cert_out_kernel, dim3(nblk(batch)), dim3(256), 0, s, st[(t + 1) & 1], certified, batch);
     *sweeps_out = t;
     return ok(hipGetLastError()) ? LEB_OK : LEB_EDEVICE;
 }
