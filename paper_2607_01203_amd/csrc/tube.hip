@@ -558,11 +558,6 @@ __global__ void fp_final_kernel(const double* xm1, const double* xs1, double* mu
     }
 }
 
-__global__ void fp_init_kernel(uint32_t* state, int B) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < B) state[t] = 0u;
-    if (t == B) state[B] = (uint32_t)B;     // open count
-}
 
 // The tube of residuals (c_bar, rho_bar) = (0, pad) at every step -- the
 // disturbance-only tube -- is the same for every (trajectory, node):
@@ -872,11 +867,11 @@ extern "C" int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int
     double* xm[2] = {mu, xm1};
     double* xs[2] = {sigma, xs1};
     // state words [B] + open count: sweep t marks st[t & 1]; the bound launch of
-    // sweep t + 1 folds them into st[(t + 1) & 1] (st[0] starts all open)
+    // sweep t + 1 folds them into st[(t + 1) & 1].  The launch of sweep 1 folds
+    // nothing (it writes st[1] all open), so st[0] needs no initial value.
     uint32_t* st[2] = {state, state + batch + 1};
     const int64_t per = (int64_t)N * n;
     auto ok = [](hipError_t e_) { return e_ == hipSuccess; };
-    hipLaunchKernelGGL(fp_init_kernel, dim3(nblk(batch + 1)), dim3(256), 0, s, st[0], batch);
     if (!opt->warm)         // C_0: the disturbance-only tube (LEB = 0), below the fixed point
         if ((rc = launch_disturbance_tube(batch, N, U, phi, e, opt->pad, mu, sigma, s))) return rc;
     volatile uint32_t* hopen = g_ws.host_open;
