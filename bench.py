@@ -197,6 +197,7 @@ def main():
                       "bytes_per_unit": bpu}
 
     nn_line = None if args.no_extra else nn_roofline(leb, W, dev, stream, args)
+    nn_learned_line = None if args.no_extra else nn_learned(leb, W, dev, stream, args)
     batch_line = None if args.no_extra else batched_uneven(leb, W, dev, stream, args)
 
     cpu = None
@@ -221,7 +222,7 @@ def main():
         "plain": {"value": round(units * 1e3 / plain_ms, 1), "ms_per_solve": round(plain_ms, 4),
                   "certified_sweeps": plain_sweeps, "certified": plain_cert},
         "roofline": roofline, "cpu_baseline": cpu, "roofline_bound": roofline_bound,
-        "roofline_nn": nn_line, "batched_uneven": batch_line,
+        "roofline_nn": nn_line, "learned_nn": nn_learned_line, "batched_uneven": batch_line,
     }
     print(json.dumps(line))
 
@@ -269,6 +270,54 @@ def nn_roofline(leb, W, dev, stream, args):
             "timestep_bounds_per_s": round(boxes / (ms * 1e-3), 1),
             "bound": "mfma", "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "flops_per_box": nn_crown_flops(widths)}
+
+
+def nn_learned(leb, W, dev, stream, args):
+    """NN family of the learned start: 10^5 certified samples (boxes drawn
+    like the MLP-bound workload's, bounded by CROWN + Theorem 2), the
+    32-128-128-128-24 surrogate trained by the library's kernels, and its
+    prediction for the 64 x 50 boxes of the MLP-bound workload against
+    their certified bound (error in log space; call time, HIP events)."""
+    import torch
+    from paper_2607_01203_amd import learned
+    b = W.nn_cfg()
+    mlp = leb.MLP(b.net.W, b.net.b, b.net.nx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    X, T = learned.nn_samples(mlp, 100000, seed=31)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    widths = learned.nn_widths(mlp)
+    net = leb.Surrogate(widths, learned.he_init(widths, 0))
+    hist = learned.train(net, X, T, epochs=args.epochs, batch=512, lr=2e-3)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    z = torch.from_numpy(b.z).to(dev)
+    v = torch.from_numpy(b.v).to(dev)
+    sg = torch.from_numpy(b.sigma).to(dev)
+    cert = leb.nn_bound(mlp, z, v, sg)
+    lo, hi = leb.nn_surrogate_bound(net, z, v, sg, stream=stream)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record(stream)
+    for _ in range(reps):
+        leb.nn_surrogate_bound(net, z, v, sg, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    floor = 1e-14
+    err = torch.cat([(hi.clamp_min(floor).log() - cert["r_hi"].clamp_min(floor).log()).abs().reshape(-1),
+                     ((-lo).clamp_min(floor).log() - (-cert["r_lo"]).clamp_min(floor).log()).abs().reshape(-1)])
+    q = torch.quantile(err, torch.tensor([0.5, 0.9], dtype=err.dtype, device=err.device)).cpu().numpy()
+    under = float((hi < cert["r_hi"]).double().mean().item())
+    net.close()
+    mlp.close()
+    return {"workload": "NN-family surrogate %s on 64 x 50 boxes of the MLP-bound workload" % widths,
+            "samples": int(X.shape[0]), "epochs": args.epochs, "sample_s": round(t1 - t0, 2),
+            "train_s": round(t2 - t1, 2), "loss_first": round(hist[0], 5), "loss_last": round(hist[-1], 5),
+            "abs_log_err_q50_q90": [round(float(x), 4) for x in q],
+            "hi_below_certified_frac": round(under, 4), "ms_per_call": round(ms, 4)}
 
 
 def batched_uneven(leb, W, dev, stream, args):

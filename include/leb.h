@@ -309,6 +309,44 @@ int leb_chain_surrogate_bound(const leb_dynamics* dyn, int32_t batch, int32_t N,
                               const double* mu, const double* sigma, leb_surrogate net, double* c_bar,
                               double* rho_bar, double pad, void* stream);
 
+/*
+ * NN surrogate (the learned start's second family, section V): for ReLU-MLP
+ * dynamics with n = nx + nu network inputs and m outputs (leb_nn_bound),
+ * one box of the network's input is described by 2n features
+ *   x[0..n-1]    a~ = [z; v] (the nominal point)
+ *   x[n..2n-1]   20 rho, rho = (hi - lo) / 2 of the displacement interval
+ *                Delta = [fmin(mu - sigma, 0), fmax(mu + sigma, 0)] (mu NULL: 0;
+ *                fmin/fmax ignore a NaN operand)
+ * and its regression targets are, per output row r, log(max(hi_r, 1e-14))
+ * (r < m) then log(max(-lo_r, 1e-14)) (the bound of Theorem 2 contains 0,
+ * so lo <= 0 <= hi).  FP32 rounding of each feature is from the FP64 value;
+ * the logarithm is FP32.
+ */
+#define LEB_NN_MAX_FEATURES 256
+
+/* x [batch][N][2 (nx + nu)] (device FP32, 8-byte aligned) from z [batch][N][nx],
+ * v [batch][N][nu], mu (NULL = 0) and sigma [batch][N][nx + nu] (device FP64).
+ * LEB_EINVAL: nx < 1, nu < 0, 2 (nx + nu) > LEB_NN_MAX_FEATURES, null or
+ * misaligned pointers. */
+int leb_nn_features(int32_t nx, int32_t nu, int32_t batch, int32_t N, const double* z, const double* v,
+                    const double* mu, const double* sigma, float* x, void* stream);
+/* t [batch][N][2m] (device FP32, 8-byte aligned) from a bound r_lo, r_hi [batch][N][m]
+ * (device FP64); 1 <= m, 2m <= LEB_NN_MAX_FEATURES. */
+int leb_nn_targets(int32_t m, int32_t batch, int32_t N, const double* r_lo, const double* r_hi, float* t,
+                   void* stream);
+/*
+ * leb_nn_surrogate_bound -- the surrogate's predicted bound of each box:
+ * features, the BF16 MLP (widths [2 (nx + nu), ..., 2m]) and the decoding
+ * hi = exp(min(y_r, 80)), lo = -exp(min(y_{m+r}, 80)); a prediction that is
+ * not finite gives 0.  Not a certified bound.
+ *   z, v, mu (NULL = 0), sigma as leb_nn_features; r_lo, r_hi [batch][N][m] (device FP64).
+ * LEB_EINVAL also when the network's widths do not match.  Uses a library-
+ * owned grow-only workspace (batch N (2n + 2m) floats); calls serialise.
+ */
+int leb_nn_surrogate_bound(leb_surrogate net, int32_t nx, int32_t nu, int32_t batch, int32_t N, const double* z,
+                           const double* v, const double* mu, const double* sigma, double* r_lo, double* r_hi,
+                           void* stream);
+
 typedef struct {
     leb_surrogate net;     /* widths [32, ..., 4] */
     int32_t sweeps;        /* tube sweeps with surrogate bounds before certification (>= 0) */

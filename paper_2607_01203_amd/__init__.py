@@ -143,6 +143,13 @@ def lib():
         L.leb_chain_surrogate_bound.argtypes = [ctypes.POINTER(Dynamics), ctypes.c_int32, ctypes.c_int32] + \
             [vp] * 5 + [vp, vp, ctypes.c_double, vp]
         L.leb_chain_surrogate_bound.restype = ctypes.c_int
+        i32 = ctypes.c_int32
+        L.leb_nn_features.argtypes = [i32, i32, i32, i32] + [vp] * 6
+        L.leb_nn_features.restype = ctypes.c_int
+        L.leb_nn_targets.argtypes = [i32, i32, i32] + [vp] * 4
+        L.leb_nn_targets.restype = ctypes.c_int
+        L.leb_nn_surrogate_bound.argtypes = [vp, i32, i32, i32, i32] + [vp] * 7
+        L.leb_nn_surrogate_bound.restype = ctypes.c_int
         L.leb_strerror.argtypes = [ctypes.c_int]
         L.leb_strerror.restype = ctypes.c_char_p
         L.leb_version.restype = ctypes.c_char_p
@@ -381,6 +388,44 @@ def chain_targets(dyn: Dynamics, r_lo, r_hi, stream=None):
     _check(lib().leb_chain_targets(ctypes.byref(dyn), B, N, _dev_ptr(r_lo, "r_lo", f64),
                                    _dev_ptr(r_hi, "r_hi", f64), _dev_ptr(t, "t", torch.float32), _stream(stream)))
     return t
+
+
+def nn_features(z, v, sigma, mu=None, stream=None):
+    """NN-surrogate inputs [B][N][2 (nx + nu)] (float32) of the boxes of
+    ReLU-MLP dynamics (see leb.h: leb_nn_features)."""
+    import torch
+    B, N, nx, nu = int(z.shape[0]), int(z.shape[1]), int(z.shape[2]), int(v.shape[2])
+    x = torch.empty((B, N, 2 * (nx + nu)), dtype=torch.float32, device=z.device)
+    f64 = torch.float64
+    _check(lib().leb_nn_features(nx, nu, B, N, _dev_ptr(z, "z", f64), _dev_ptr(v, "v", f64), _dev_ptr(mu, "mu", f64),
+                                 _dev_ptr(sigma, "sigma", f64), _dev_ptr(x, "x", torch.float32), _stream(stream)))
+    return x
+
+
+def nn_targets(r_lo, r_hi, stream=None):
+    """NN-surrogate targets [B][N][2m] (float32) from a bound [B][N][m]."""
+    import torch
+    B, N, m = int(r_lo.shape[0]), int(r_lo.shape[1]), int(r_lo.shape[2])
+    t = torch.empty((B, N, 2 * m), dtype=torch.float32, device=r_lo.device)
+    f64 = torch.float64
+    _check(lib().leb_nn_targets(m, B, N, _dev_ptr(r_lo, "r_lo", f64), _dev_ptr(r_hi, "r_hi", f64),
+                                _dev_ptr(t, "t", torch.float32), _stream(stream)))
+    return t
+
+
+def nn_surrogate_bound(net, z, v, sigma, mu=None, stream=None):
+    """The NN surrogate's predicted (r_lo, r_hi) [B][N][m] (see leb.h:
+    leb_nn_surrogate_bound).  Not certified."""
+    import torch
+    B, N, nx, nu = int(z.shape[0]), int(z.shape[1]), int(z.shape[2]), int(v.shape[2])
+    m = net.widths[-1] // 2
+    f64 = torch.float64
+    lo = torch.empty((B, N, m), dtype=f64, device=z.device)
+    hi = torch.empty_like(lo)
+    _check(lib().leb_nn_surrogate_bound(net.handle, nx, nu, B, N, _dev_ptr(z, "z", f64), _dev_ptr(v, "v", f64),
+                                        _dev_ptr(mu, "mu", f64), _dev_ptr(sigma, "sigma", f64),
+                                        _dev_ptr(lo, "r_lo", f64), _dev_ptr(hi, "r_hi", f64), _stream(stream)))
+    return lo, hi
 
 
 class MLP:

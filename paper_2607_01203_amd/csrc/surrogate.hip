@@ -12,6 +12,10 @@
 // Outputs (regression targets): log(max(hi, 1e-14)) and log(max(-lo, 1e-14))
 // of the vx and vz rows (every term of the bound contains 0, so lo <= 0 <= hi).
 //
+// The second family covers ReLU-MLP dynamics: one box of the network's input
+// (the nominal a~ = [z; v] and the half width of its displacement interval)
+// maps to the log-bounds of every output row.
+//
 // The learned fixed point runs the tube iteration with surrogate bounds
 // for a few sweeps (the initial tube), inflates it, and hands it to the
 // certified iteration as a warm start; the result is certified by the
@@ -29,6 +33,7 @@
 namespace leb {
 
 constexpr float LOG_FLOOR = 1e-14f;
+constexpr float NN_LOG_CEIL = 80.0f;
 
 // one thread per (unit, node); rows of 32 floats written as 8 float4
 __global__ void chain_features_kernel(const double* z, const double* v, const double* mu, const double* sigma,
@@ -73,6 +78,46 @@ __global__ void chain_decode_kernel(const float* Y, int64_t units, int U, double
     rb[q] = r + pad;
 }
 
+// NN surrogate inputs: one thread per (unit, network input c); row of 2n
+// floats [a~ (n), 20 rho (n)], rho the half width of
+// Delta = [fmin(mu - sigma, 0), fmax(mu + sigma, 0)]
+__global__ void nn_features_kernel(const double* z, const double* v, const double* mu, const double* sigma,
+                                   int64_t units, int nx, int nu, float* X) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = nx + nu;
+    if (q >= units * n) return;
+    const int64_t u = q / n;
+    const int c = (int)(q - u * n);
+    const double a = c < nx ? z[u * nx + c] : v[u * nu + (c - nx)];
+    const double sg = sigma[q], m = mu ? mu[q] : 0.0;
+    const double rho = 0.5 * (fmax(m + sg, 0.0) - fmin(m - sg, 0.0));
+    X[u * 2 * n + c] = (float)a;
+    X[u * 2 * n + n + c] = (float)(20.0 * rho);
+}
+
+// NN surrogate targets: one thread per (unit, output row r); row of 2m
+// floats [log hi (m), log -lo (m)]
+__global__ void nn_targets_kernel(const double* r_lo, const double* r_hi, int64_t units, int m, float* T) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= units * m) return;
+    const int64_t u = q / m;
+    const int r = (int)(q - u * m);
+    T[u * 2 * m + r] = logf(fmaxf((float)r_hi[q], LOG_FLOOR));
+    T[u * 2 * m + m + r] = logf(fmaxf((float)-r_lo[q], LOG_FLOOR));
+}
+
+// predicted log-bounds -> [lo, hi]: hi = exp(min(y_hi, 80)), lo = -exp(min(y_lo, 80));
+// a prediction that is not finite gives 0
+__global__ void nn_decode_kernel(const float* Y, int64_t units, int m, double* r_lo, double* r_hi) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= units * m) return;
+    const int64_t u = q / m;
+    const int r = (int)(q - u * m);
+    const float yh = Y[u * 2 * m + r], yl = Y[u * 2 * m + m + r];
+    r_hi[q] = isfinite(yh) ? exp((double)fminf(yh, NN_LOG_CEIL)) : 0.0;
+    r_lo[q] = isfinite(yl) ? -exp((double)fminf(yl, NN_LOG_CEIL)) : 0.0;
+}
+
 __global__ void scale_sigma_kernel(double* sigma, int64_t count, double f, double a) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q < count) sigma[q] = sigma[q] * f + a;
@@ -89,6 +134,8 @@ struct SurWorkspace {
     std::mutex mu;
     float* X = nullptr; float* Y = nullptr; double* cb = nullptr; double* rb = nullptr;
     int64_t cap_nodes = 0, cap_rows = 0;
+    float* nX = nullptr; float* nY = nullptr;   // NN family: features and predictions
+    int64_t cap_nx = 0, cap_ny = 0;             // floats
 };
 static SurWorkspace g_sw;
 
@@ -111,6 +158,15 @@ static int sw_get(int64_t nodes, int64_t rows) {
             return LEB_ENOMEM;
         g_sw.cap_rows = rows;
     }
+    return LEB_OK;
+}
+
+static int grow_f32(float** p, int64_t* cap, int64_t count) {
+    if (count <= *cap) return LEB_OK;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr; *cap = 0;
+    if (hipMalloc(p, (size_t)count * sizeof(float)) != hipSuccess) { *p = nullptr; return LEB_ENOMEM; }
+    *cap = count;
     return LEB_OK;
 }
 
@@ -162,6 +218,51 @@ extern "C" int leb_chain_surrogate_bound(const leb_dynamics* dyn, int32_t batch,
     hipStream_t s = (hipStream_t)stream;
     return surrogate_chain_sweep(net, z, v, mu, sigma, (int)(units * dyn->n_units), dyn->n_units, dyn->rest_len, pad,
                                  c_bar, rho_bar, s);
+}
+
+extern "C" int leb_nn_features(int32_t nx, int32_t nu, int32_t batch, int32_t N, const double* z, const double* v,
+                               const double* mu, const double* sigma, float* x, void* stream) {
+    if (nx < 1 || nu < 0 || 2 * (nx + nu) > LEB_NN_MAX_FEATURES || batch < 0 || N < 0) return LEB_EINVAL;
+    const int64_t units = (int64_t)batch * N;
+    if (units == 0) return LEB_OK;
+    if (!z || (nu > 0 && !v) || !sigma || !x || ((uintptr_t)x & 7)) return LEB_EINVAL;
+    const int64_t cnt = units * (nx + nu);
+    hipLaunchKernelGGL(nn_features_kernel, dim3(nbk(cnt)), dim3(256), 0, (hipStream_t)stream, z, v, mu, sigma, units,
+                       (int)nx, (int)nu, x);
+    return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
+}
+
+extern "C" int leb_nn_targets(int32_t m, int32_t batch, int32_t N, const double* r_lo, const double* r_hi, float* t,
+                              void* stream) {
+    if (m < 1 || 2 * m > LEB_NN_MAX_FEATURES || batch < 0 || N < 0) return LEB_EINVAL;
+    const int64_t units = (int64_t)batch * N;
+    if (units == 0) return LEB_OK;
+    if (!r_lo || !r_hi || !t || ((uintptr_t)t & 7)) return LEB_EINVAL;
+    hipLaunchKernelGGL(nn_targets_kernel, dim3(nbk(units * m)), dim3(256), 0, (hipStream_t)stream, r_lo, r_hi, units,
+                       (int)m, t);
+    return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
+}
+
+extern "C" int leb_nn_surrogate_bound(leb_surrogate net, int32_t nx, int32_t nu, int32_t batch, int32_t N,
+                                      const double* z, const double* v, const double* mu, const double* sigma,
+                                      double* r_lo, double* r_hi, void* stream) {
+    if (!net || nx < 1 || nu < 0 || batch < 0 || N < 0) return LEB_EINVAL;
+    int32_t din = 0, dout = 0;
+    if (leb_surrogate_dims(net, &din, &dout) || din != 2 * (nx + nu) || dout < 2 || (dout & 1)) return LEB_EINVAL;
+    const int64_t units = (int64_t)batch * N;
+    if (units == 0) return LEB_OK;
+    if (!z || (nu > 0 && !v) || !sigma || !r_lo || !r_hi) return LEB_EINVAL;
+    if (units > 0x7fffffff) return LEB_EINVAL;
+    const int m = dout / 2;
+    hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lock(g_sw.mu);
+    int rc;
+    if ((rc = grow_f32(&g_sw.nX, &g_sw.cap_nx, units * din)) || (rc = grow_f32(&g_sw.nY, &g_sw.cap_ny, units * dout)))
+        return rc;
+    if ((rc = leb_nn_features(nx, nu, batch, N, z, v, mu, sigma, g_sw.nX, stream))) return rc;
+    if ((rc = leb_mlp_fwd_bf16(net, (int32_t)units, g_sw.nX, g_sw.nY, stream))) return rc;
+    hipLaunchKernelGGL(nn_decode_kernel, dim3(nbk(units * m)), dim3(256), 0, s, g_sw.nY, units, m, r_lo, r_hi);
+    return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
 }
 
 extern "C" int leb_fixed_point_learned(const leb_dynamics* dyn, int32_t batch, int32_t N, const double* z,

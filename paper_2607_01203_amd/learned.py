@@ -1,10 +1,12 @@
 """Learned warm start: certified training samples and surrogate training.
 
-Samples are bounds the method itself certifies: tubes around a certified
-fixed point are scaled and shifted (host-side, seeded), the plain
-path-based bound is evaluated on them by the library, and the library's
-feature and target kernels turn the bounds into (input, target) pairs.
-Training runs the library's BF16 MFMA forward/backward/Adam kernels.
+Samples are bounds the method itself certifies.  Chain family: tubes
+around a certified fixed point are scaled and shifted (host-side, seeded)
+and the plain path-based bound is evaluated on them.  NN family: boxes of
+a ReLU-MLP's input (nominal point and radii drawn host-side, seeded) are
+bounded by CROWN and Theorem 2.  The library's feature and target kernels
+turn the bounds into (input, target) pairs, and training runs the
+library's BF16 MFMA forward/backward/Adam kernels.
 """
 from __future__ import annotations
 
@@ -12,10 +14,17 @@ import math
 
 import numpy as np
 
-from . import (CHAIN_FEATURES, CHAIN_OUTPUTS, Dynamics, Surrogate, analytic_bound, chain_features,
-               chain_targets)
+from . import (CHAIN_FEATURES, CHAIN_OUTPUTS, MLP, Dynamics, Surrogate, analytic_bound, chain_features,
+               chain_targets, nn_bound, nn_features, nn_targets)
 
 CHAIN_WIDTHS = [CHAIN_FEATURES, 128, 128, 128, CHAIN_OUTPUTS]
+
+
+def nn_widths(mlp: MLP, hidden=128):
+    """NN-family surrogate widths: 2 (nx + nu) features, three hidden
+    layers, 2m log-bounds (32 -> 128 -> 128 -> 128 -> 24 for a 16-input,
+    12-output network)."""
+    return [2 * mlp.widths[0], hidden, hidden, hidden, 2 * mlp.m]
 
 
 def he_init(widths, seed):
@@ -54,6 +63,29 @@ def chain_samples(dyn: Dynamics, z, v, mu_star, sigma_star, draws, seed, scale=(
     T = torch.cat(ts)
     perm = torch.from_numpy(rng.permutation(X.shape[0])).to(z.device)
     return X.index_select(0, perm).contiguous(), T.index_select(0, perm).contiguous()
+
+
+def nn_samples(mlp: MLP, boxes, seed, nominal=(-1.0, 1.0), radii=(0.005, 0.05), chunk=4096, device="cuda:0"):
+    """Certified-bound samples of ReLU-MLP dynamics: `boxes` boxes with the
+    nominal input ~ U(nominal) and radii ~ U(radii) per input (drawn on the
+    host, seeded), bounded by leb_nn_bound in chunks.  Returns (X [boxes][2n],
+    T [boxes][2m]) float32 GPU tensors; the draws are independent, so the
+    order is already random."""
+    import torch
+    rng = np.random.default_rng(seed)
+    n, nx = mlp.widths[0], mlp.nx
+    xs, ts = [], []
+    done = 0
+    while done < boxes:
+        c = min(chunk, boxes - done)
+        a = torch.from_numpy(rng.uniform(nominal[0], nominal[1], (c, 1, n))).to(device)
+        sg = torch.from_numpy(rng.uniform(radii[0], radii[1], (c, 1, n))).to(device)
+        z, v = a[..., :nx].contiguous(), a[..., nx:].contiguous()
+        out = nn_bound(mlp, z, v, sg)
+        xs.append(nn_features(z, v, sg).reshape(c, 2 * n))
+        ts.append(nn_targets(out["r_lo"], out["r_hi"]).reshape(c, 2 * mlp.m))
+        done += c
+    return torch.cat(xs).contiguous(), torch.cat(ts).contiguous()
 
 
 def train(net: Surrogate, X, T, epochs, batch=1024, lr=2e-3, lr_final=1e-4, log_every=0):

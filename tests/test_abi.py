@@ -87,6 +87,24 @@ def test_empty_problem_is_ok_without_launching(L):
     assert _call(L, d, batch=4, N=0, z=None, v=None, sigma=None, lo=None, hi=None) == 0
 
 
+def test_nn_surrogate_entry_points_reject_bad_arguments_without_launching(L):
+    vp = ctypes.c_void_p(8)
+    # leb_nn_features(nx, nu, batch, N, z, v, mu, sigma, x, stream)
+    assert L.leb_nn_features(0, 4, 1, 1, vp, vp, None, vp, vp, None) != 0
+    assert L.leb_nn_features(12, -1, 1, 1, vp, vp, None, vp, vp, None) != 0
+    assert L.leb_nn_features(100, 29, 1, 1, vp, vp, None, vp, vp, None) != 0     # 2n > 256
+    assert L.leb_nn_features(12, 4, 1, 1, vp, vp, None, None, vp, None) != 0    # no sigma
+    assert L.leb_nn_features(12, 4, 1, 1, vp, vp, None, vp, ctypes.c_void_p(12), None) != 0  # misaligned x
+    assert L.leb_nn_features(12, 4, 0, 5, None, None, None, None, None, None) == 0
+    # leb_nn_targets(m, batch, N, r_lo, r_hi, t, stream)
+    assert L.leb_nn_targets(0, 1, 1, vp, vp, vp, None) != 0
+    assert L.leb_nn_targets(129, 1, 1, vp, vp, vp, None) != 0
+    assert L.leb_nn_targets(12, 1, 1, vp, None, vp, None) != 0
+    assert L.leb_nn_targets(12, 3, 0, None, None, None, None) == 0
+    # leb_nn_surrogate_bound(net, nx, nu, batch, N, z, v, mu, sigma, r_lo, r_hi, stream)
+    assert L.leb_nn_surrogate_bound(None, 12, 4, 1, 1, vp, vp, None, vp, vp, vp, None) != 0
+
+
 def test_binding_refuses_cpu_tensors():
     import torch
     import paper_2607_01203_amd as leb
