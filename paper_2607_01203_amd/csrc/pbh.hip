@@ -117,24 +117,13 @@ __global__ void __launch_bounds__(PBH_BLOCK) pbh_chain_fwd(ChainArgs A) {
     uint32_t* s_flag = reinterpret_cast<uint32_t*>(s_sp + (size_t)T * U);   // [T]
 
     const int tid = threadIdx.x;
-    // fixed point: trajectories left open by the previous sweep, counted by every
-    // workgroup (a wave reduction, then the four wave sums after the barrier below)
-    __shared__ uint32_t s_wopen[PBH_BLOCK / 64];
-    const bool fold = A.fold.prev != nullptr;
-    if (fold) {
-        uint32_t my = 0;
-        if (A.fold.sweep > 0)
-            for (int b = tid; b < A.fold.B; b += PBH_BLOCK) my += fp_is_open(A.fold.prev[b]);
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) my += __shfl_xor(my, off);
-        if ((tid & 63) == 0) s_wopen[tid >> 6] = my;
-    }
     TileRef t0;
+    int64_t u0 = 0;
     if (A.tiles) {
         const PbhTile& pt = A.tiles[blockIdx.x];
         t0 = TileRef{pt.z, pt.v, pt.mu, pt.sigma, pt.r_lo, pt.r_hi, pt.c_bar, pt.rho_bar, pt.flags, pt.n};
     } else {
-        const int64_t u0 = (int64_t)blockIdx.x * T;
+        u0 = (int64_t)blockIdx.x * T;
         const int64_t left = A.units - u0;
         t0.nloc = left < T ? (int)left : T;
         t0.Z = A.z + u0 * nx; t0.V = A.v + u0 * nu; t0.MU = A.mu ? A.mu + u0 * n : nullptr;
@@ -144,6 +133,23 @@ __global__ void __launch_bounds__(PBH_BLOCK) pbh_chain_fwd(ChainArgs A) {
         t0.CB = A.c_bar ? A.c_bar + u0 * ro : nullptr; t0.RB = A.rho_bar ? A.rho_bar + u0 * ro : nullptr;
         t0.FL = A.flags ? A.flags + u0 : nullptr;
     }
+    // fixed point: is any trajectory of this workgroup's units left open by the
+    // previous sweep's containment test?  (Its T units of consecutive timesteps
+    // span at most T <= PBH_BLOCK trajectories.)  A certified trajectory's tube is
+    // frozen, so its residuals are not needed again.
+    __shared__ uint32_t s_wopen[PBH_BLOCK / 64];
+    const bool fold = A.fold.prev != nullptr;
+    if (fold) {
+        uint32_t my = 1u;
+        if (A.fold.sweep > 0) {
+            const int64_t N = A.units / A.fold.B;
+            const int64_t b0 = u0 / N, nb = (u0 + t0.nloc - 1) / N - b0 + 1;
+            my = tid < nb ? fp_is_open(A.fold.prev[b0 + tid]) : 0u;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) my |= __shfl_xor(my, off);
+        if ((tid & 63) == 0) s_wopen[tid >> 6] = my;
+    }
     for (int q = tid; q < T; q += PBH_BLOCK) s_flag[q] = 0u;
     const int lt = tid / U;
     const int i = tid - lt * U;
@@ -151,23 +157,41 @@ __global__ void __launch_bounds__(PBH_BLOCK) pbh_chain_fwd(ChainArgs A) {
     node_load(t0, U, lt, i, d0);
     __syncthreads();      // s_flag cleared, s_wopen written
     if (fold) {
-        uint32_t open = (uint32_t)A.fold.B;
-        if (A.fold.sweep > 0) {
-            open = 0;
+        uint32_t mine = 0u;
 #pragma unroll
-            for (int w = 0; w < PBH_BLOCK / 64; ++w) open += s_wopen[w];
-        }
+        for (int w = 0; w < PBH_BLOCK / 64; ++w) mine |= s_wopen[w];
         if (blockIdx.x == 0) {
-            for (int b = tid; b < A.fold.B; b += PBH_BLOCK)
-                A.fold.next[b] = A.fold.sweep > 0 ? fp_fold_word(A.fold.prev[b], A.fold.sweep) : 0u;
+            // the fold itself: state words of the previous sweep -> next, and the
+            // number of trajectories still open, published to the device and the host
+            __shared__ uint32_t s_gopen[PBH_BLOCK / 64];
+            uint32_t c = 0;
+            for (int b = tid; b < A.fold.B; b += PBH_BLOCK) {
+                uint32_t w = 0u;
+                if (A.fold.sweep > 0) {
+                    const uint32_t st = A.fold.prev[b];
+                    c += fp_is_open(st);
+                    w = fp_fold_word(st, A.fold.sweep);
+                }
+                A.fold.next[b] = w;
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+            if ((tid & 63) == 0) s_gopen[tid >> 6] = c;
+            __syncthreads();
             if (tid == 0) {
+                uint32_t open = (uint32_t)A.fold.B;
+                if (A.fold.sweep > 0) {
+                    open = 0;
+#pragma unroll
+                    for (int w = 0; w < PBH_BLOCK / 64; ++w) open += s_gopen[w];
+                }
                 A.fold.next[A.fold.B] = open;
                 if (A.fold.sweep > 0)
                     __hip_atomic_store(&A.fold.host_open[A.fold.sweep % FP_SLOTS], open, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_SYSTEM);
             }
         }
-        if (open == 0u) return;       // every trajectory certified by an earlier sweep
+        if (mine == 0u) return;       // every trajectory of this workgroup is certified
     }
     node_pass(A, t0, d0, lt, i, s_sp, s_flag);
 }

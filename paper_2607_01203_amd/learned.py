@@ -88,6 +88,23 @@ def nn_samples(mlp: MLP, boxes, seed, nominal=(-1.0, 1.0), radii=(0.005, 0.05), 
     return torch.cat(xs).contiguous(), torch.cat(ts).contiguous()
 
 
+def save_samples(path, X, T):
+    """Writes a sample set (X, T float32 tensors) to an .npz file (no
+    pickled objects), so a surrogate can be retrained without bounding the
+    samples again."""
+    np.savez(path, X=X.detach().cpu().numpy().astype(np.float32), T=T.detach().cpu().numpy().astype(np.float32))
+
+
+def load_samples(path, device="cuda:0"):
+    """Reads a sample set written by save_samples (pickles refused)."""
+    import torch
+    with np.load(path, allow_pickle=False) as f:
+        X, T = f["X"], f["T"]
+    if X.ndim != 2 or T.ndim != 2 or X.shape[0] != T.shape[0] or X.dtype != np.float32 or T.dtype != np.float32:
+        raise ValueError("%s: not a sample set" % path)
+    return torch.from_numpy(X).to(device), torch.from_numpy(T).to(device)
+
+
 def train(net: Surrogate, X, T, epochs, batch=1024, lr=2e-3, lr_final=1e-4, log_every=0):
     """Adam on mean-squared error over (X, T) (GPU float32), batches taken
     in order (the sample order is already random), cosine-decayed learning

@@ -143,3 +143,19 @@ def test_fixed_point_rejects_bad_options_without_launching(L):
     assert L.leb_fixed_point_solve(ctypes.byref(d), 0, 3, None, None, None, e, ctypes.byref(opt), None, None, None,
                                    ctypes.byref(sw), None) == 0
     assert sw.value == 0
+
+
+def test_sample_cache_round_trip(tmp_path):
+    import numpy as np
+    import torch
+    from paper_2607_01203_amd import learned
+    rng = np.random.default_rng(0)
+    X = torch.from_numpy(rng.normal(size=(10, 32)).astype(np.float32))
+    T = torch.from_numpy(rng.normal(size=(10, 24)).astype(np.float32))
+    p = str(tmp_path / "samples.npz")
+    learned.save_samples(p, X, T)
+    X2, T2 = learned.load_samples(p, device="cpu")
+    assert torch.equal(X, X2) and torch.equal(T, T2)
+    np.savez(p, X=np.zeros((3, 2)), T=np.zeros((4, 2), dtype=np.float32))
+    with pytest.raises(ValueError):
+        learned.load_samples(p, device="cpu")

@@ -116,12 +116,13 @@ def test_fixed_point_full_shape(gpu, orc):
     _check_against_oracle(orc, tp, mu, sg, np.array([0, 77, 255]))
 
 
-@pytest.mark.parametrize("batch,N,U", [(3, 46, 6), (2, 9, 40), (2, 70, 3), (1, 131, 2)])
+@pytest.mark.parametrize("batch,N,U", [(3, 46, 6), (2, 9, 40), (2, 70, 3), (1, 131, 2), (300, 2, 1)])
 def test_fixed_point_long_horizon_and_long_chain(gpu, orc, batch, N, U):
     """A horizon of 46 steps (two row groups in the tube map), a chain of 40
-    nodes (6 steps per bound workgroup), and horizons of 70 and 131 steps
-    (Phi and the residuals staged in two and three passes, up to four row
-    groups)."""
+    nodes (6 steps per bound workgroup), horizons of 70 and 131 steps (Phi
+    and the residuals staged in two and three passes, up to four row
+    groups), and 300 two-step trajectories of one node (a bound workgroup
+    spans 128 trajectories; the fold covers more trajectories than lanes)."""
     import paper_2607_01203_amd as leb
     tp = W.fixed_point_cfg(seed=60 + N, batch=batch, N=N, n_units=U)
     print("case: fixed point B=%d N=%d U=%d" % (batch, N, U), flush=True)
@@ -171,6 +172,23 @@ def test_fixed_point_warm_start_from_above(gpu, orc):
     mo, so, _, _ = tube.fixed_point(d, b.z, b.v, tp.phi, tp.e)
     assert (sg2 >= so * (1 - 1e-12)).all() and (sg2 <= so * 1.011 + 1e-11).all()
     assert (np.abs(mu2 - mo) <= 1e-2 * np.maximum(so, 1e-12)).all()
+
+
+def test_fixed_point_warm_start_from_below(gpu, orc):
+    """A warm start that is not a post-fixed point (half the least fixed
+    point's width, zero centre) still ends certified at the cold start's
+    tube: the causal map forgets its start within N + 1 sweeps."""
+    import paper_2607_01203_amd as leb
+    from oracle import tube
+    tp = W.fixed_point_cfg(seed=49, batch=3, N=12, n_units=4)
+    b = tp.batch
+    d = orc.Dyn.like(b.dyn)
+    mo, so, _, _ = tube.fixed_point(d, b.z, b.v, tp.phi, tp.e)
+    print("case: warm start from below B=3 N=12 U=4", flush=True)
+    mu, sg, cert, sweeps = _solve(leb, tp, gpu, mu=_t(np.zeros_like(mo), gpu), sigma=_t(0.5 * so, gpu))
+    assert (cert == 1).all()
+    assert 2 <= sweeps <= 12 + 2, sweeps
+    _check_against_oracle(orc, tp, mu, sg, np.arange(3))
 
 
 def test_fixed_point_trajectories_certified_at_different_sweeps(gpu, orc):
