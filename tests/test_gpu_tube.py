@@ -116,6 +116,19 @@ def test_fixed_point_full_shape(gpu, orc):
     _check_against_oracle(orc, tp, mu, sg, np.array([0, 77, 255]))
 
 
+def test_fixed_point_large_batch(gpu, orc):
+    """1,024 trajectories x 40 steps, 168 states (four times the bench
+    batch: 4,552 bound workgroups, a fold over four state words per lane);
+    the oracle on a sample."""
+    import paper_2607_01203_amd as leb
+    tp = W.fixed_point_cfg(seed=5, batch=1024, N=40)
+    print("case: fixed point 1024x40x168", flush=True)
+    mu, sg, cert, sweeps = _solve(leb, tp, gpu)
+    print("sweeps", sweeps)
+    assert (cert == 1).all()
+    _check_against_oracle(orc, tp, mu, sg, np.array([0, 513, 1023]))
+
+
 @pytest.mark.parametrize("batch,N,U", [(3, 46, 6), (2, 9, 40), (2, 70, 3), (1, 131, 2), (300, 2, 1)])
 def test_fixed_point_long_horizon_and_long_chain(gpu, orc, batch, N, U):
     """A horizon of 46 steps (two row groups in the tube map), a chain of 40
