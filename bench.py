@@ -39,7 +39,7 @@ HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
 # WRITE_SIZE (KiB per dispatch, rocprofv3 --pmc), and the factors that map each
 # counter to bytes, measured on a copy kernel of known size; None until taken for
 # the kernel as it is now.
-TUBE_PMC_KIB = (27249, 35841)
+TUBE_PMC_KIB = (27251, 35859)
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 matrix (= vector) peak
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # lane-ops/s of non-packed VALU issue (39.3 T)

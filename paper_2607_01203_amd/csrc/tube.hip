@@ -45,6 +45,8 @@ struct TubeFP {
     const double* sg_in;
     uint32_t* state;      // [B] state words, [B] open count
     double tol, abs_;     // C_t = (mu_F, sigma_F (1 + tol) + abs_)
+    uint32_t* cert;       // NULL, or [B]: written (state & FP_CERT) by a launch that finds every
+                          // trajectory certified (the sweep enqueued after the last one)
 };
 
 struct TubeArgs {
@@ -287,7 +289,15 @@ __global__ void __launch_bounds__(256) tube_map2_kernel(const double* __restrict
     extern __shared__ double lds2[];
     __shared__ uint32_t sbad[16];
     __shared__ int sjinf[16];
-    if (FP && P.state[A.B] == 0u) return;     // every trajectory certified by an earlier sweep
+    if (FP && P.state[A.B] == 0u) {           // every trajectory certified by an earlier sweep
+        if (P.cert) {
+            const int64_t stride = (int64_t)gridDim.x * gridDim.y * blockDim.x;
+            for (int64_t b = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x; b < A.B;
+                 b += stride)
+                P.cert[b] = P.state[b] & FP_CERT;
+        }
+        return;
+    }
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int N = A.N, U = A.U, nx = 6 * U, n = 8 * U;
@@ -700,7 +710,7 @@ static int launch_tube2(int B, int N, int U, const double* phi, const double* e,
 
 int launch_tube_map_compact(int B, int N, int U, const double* phi, const double* e, double pad, const double* c2,
                             const double* r2, double* mu, double* sigma, hipStream_t s, double scale, double shift) {
-    TubeFP none{nullptr, nullptr, nullptr, 0.0, 0.0};
+    TubeFP none{nullptr, nullptr, nullptr, 0.0, 0.0, nullptr};
     return launch_tube2(B, N, U, phi, e, pad, c2, r2, mu, sigma, none, s, scale, shift);
 }
 
@@ -887,7 +897,7 @@ extern "C" int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int
         int r = launch_pbh_chain(dyn, units, z, v, xm[a], xs[a], nullptr, nullptr, cb, rb, opt->pad, nullptr, s,
                                  &fold, b0, b1, true);
         if (r) return r;
-        const TubeFP fp{xm[a], xs[a], st[w], opt->tol, opt->inflate_abs};
+        const TubeFP fp{xm[a], xs[a], st[w], opt->tol, opt->inflate_abs, certified};
         return launch_tube2(batch, N, U, phi, e, opt->pad, cb, rb, xm[w], xs[w], fp, s, 1.0, 0.0, t0, t1);
     };
     // Wait until the open count of sweep t is published: the bound launch of
@@ -937,7 +947,10 @@ extern "C" int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int
     if (!in_place)
         hipLaunchKernelGGL(fp_final_kernel, dim3(batch, (unsigned)std::min<int64_t>((per + 255) / 256, 16)), dim3(256),
                            0, s, xm1, xs1, mu, sigma, st[(t + 1) & 1], per, t);
-    hipLaunchKernelGGL(cert_out_kernel, dim3(nblk(batch)), dim3(256), 0, s, st[(t + 1) & 1], certified, batch);
+    // the sweep enqueued after the last one (t < cap) finds every trajectory
+    // certified and writes the certificate flags itself
+    if (!(open == 0 && t < opt->max_sweeps))
+        hipLaunchKernelGGL(cert_out_kernel, dim3(nblk(batch)), dim3(256), 0, s, st[(t + 1) & 1], certified, batch);
     *sweeps_out = t;
     return ok(hipGetLastError()) ? LEB_OK : LEB_EDEVICE;
 }
