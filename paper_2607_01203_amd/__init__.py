@@ -305,6 +305,15 @@ def tube_map(n_units, phi, e, c_bar, rho_bar, stream=None, out=None):
     return out
 
 
+def _cert_out(B, N, device):
+    """The certificate flags: every entry is written by a solve with
+    timesteps; an empty horizon launches nothing, so its flags start at 0."""
+    import torch
+    if B * N == 0:
+        return torch.zeros((B,), dtype=torch.int32, device=device)
+    return torch.empty((B,), dtype=torch.int32, device=device)
+
+
 def fixed_point_solve(dyn: Dynamics, z, v, phi, e, tol=1e-6, max_sweeps=200, pad=0.0, inflate_abs=1e-12,
                       mu=None, sigma=None, stream=None):
     """Certified tube/LEB fixed point (see leb.h: leb_fixed_point_solve).
@@ -315,10 +324,10 @@ def fixed_point_solve(dyn: Dynamics, z, v, phi, e, tol=1e-6, max_sweeps=200, pad
     B, N = int(z.shape[0]), int(z.shape[1])
     n = dyn.nx + dyn.nu
     warm = mu is not None
-    if not warm:
-        mu = torch.zeros((B, N, n), dtype=torch.float64, device=z.device)
-        sigma = torch.zeros((B, N, n), dtype=torch.float64, device=z.device)
-    cert = torch.zeros((B,), dtype=torch.int32, device=z.device)
+    if not warm:        # the cold start writes every entry
+        mu = torch.empty((B, N, n), dtype=torch.float64, device=z.device)
+        sigma = torch.empty((B, N, n), dtype=torch.float64, device=z.device)
+    cert = _cert_out(B, N, z.device)
     opt = FPOptions(tol, max_sweeps, pad, inflate_abs, 1 if warm else 0)
     sweeps = ctypes.c_int32(0)
     f64 = torch.float64
@@ -339,7 +348,7 @@ def fixed_point_learned(dyn: Dynamics, z, v, phi, e, net, sweeps=1, margin=5e-2,
     n = dyn.nx + dyn.nu
     mu = torch.empty((B, N, n), dtype=torch.float64, device=z.device)
     sigma = torch.empty((B, N, n), dtype=torch.float64, device=z.device)
-    cert = torch.zeros((B,), dtype=torch.int32, device=z.device)
+    cert = _cert_out(B, N, z.device)
     opt = FPOptions(tol, max_sweeps, pad, inflate_abs, 1)
     ws = WarmStart(net.handle, int(sweeps), float(margin))
     sw = ctypes.c_int32(0)
