@@ -83,10 +83,12 @@ int nn_bound_run(const leb_mlp_s* net, int64_t units, const double* z, const dou
 void nn_dims(const leb_mlp_s* net, int* nx, int* nu, int* m);
 
 // one surrogate sweep over a chain tube (features -> BF16 MLP -> residual zonotope,
-// all rows [unit][6U], or compact: rows 3 and 4 [unit][U][2])
+// all rows [unit][6U], or compact: rows 3 and 4 [unit][U][2]).  sg_period > 0: the
+// tube is the same for every trajectory, sigma holds one trajectory [sg_period][8U]
+// and unit u reads row u % sg_period
 int surrogate_chain_sweep(leb_surrogate s, const double* z, const double* v, const double* mu, const double* sigma,
                           int nodes, int U, double L0, double pad, double* cbar, double* rbar, hipStream_t st,
-                          bool compact = false);
+                          bool compact = false, int sg_period = 0);
 
 // argument checks shared by the entry points
 bool aligned8(const void* p);

@@ -122,6 +122,7 @@ struct FwdArgs {
     double *cbar, *rbar;      // all 6 rows of each node, or (compact) rows 3, 4: [unit][U][2]
     int U;
     int compact;
+    int sg_period;            // > 0: csg holds one trajectory's tube, unit u reads row u % sg_period
     double L0, pad;
 };
 
@@ -192,8 +193,9 @@ __global__ void __launch_bounds__(256) mlp_fwd_kernel(FwdArgs A) {
             if (row < A.B) {
                 const int U = A.U, nx = 6 * U, nu = 2 * U, n = nx + nu;
                 const int u = row / U, i = row - u * U;
+                const int us = A.sg_period > 0 ? u % A.sg_period : u;
                 chain_node_features(A.cz + (int64_t)u * nx, A.cv + (int64_t)u * nu,
-                                    A.cmu ? A.cmu + (int64_t)u * n : nullptr, A.csg + (int64_t)u * n, i, U, A.L0, f);
+                                    A.cmu ? A.cmu + (int64_t)u * n : nullptr, A.csg + (int64_t)us * n, i, U, A.L0, f);
             } else {
 #pragma unroll
                 for (int k = 0; k < LEB_CHAIN_FEATURES; ++k) f[k] = 0.0f;
@@ -672,13 +674,14 @@ namespace leb {
 // every (unit, node): the decoded bound on rows 6i+3, 6i+4, (0, pad) elsewhere.
 int surrogate_chain_sweep(leb_surrogate s, const double* z, const double* v, const double* mu, const double* sigma,
                           int nodes, int U, double L0, double pad, double* cbar, double* rbar, hipStream_t st,
-                          bool compact) {
+                          bool compact, int sg_period) {
     if (s->G.w[0] != LEB_CHAIN_FEATURES || s->G.w[s->G.L] != LEB_CHAIN_OUTPUTS) return LEB_EINVAL;
     if (nodes == 0) return LEB_OK;
     FwdArgs a = {};
     a.G = s->G; a.Wt = s->Wt; a.params = s->params; a.B = nodes;
     a.cz = z; a.cv = v; a.cmu = mu; a.csg = sigma; a.cbar = cbar; a.rbar = rbar; a.U = U; a.L0 = L0; a.pad = pad;
     a.compact = compact ? 1 : 0;
+    a.sg_period = sg_period;
     return fwd_dispatch(s, a, FWD_CHAIN, st);
 }
 }  // namespace leb

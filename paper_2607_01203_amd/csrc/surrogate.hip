@@ -136,6 +136,8 @@ struct SurWorkspace {
     int64_t cap_nodes = 0, cap_rows = 0;
     float* nX = nullptr; float* nY = nullptr;   // NN family: features and predictions
     int64_t cap_nx = 0, cap_ny = 0;             // floats
+    double* dist = nullptr;                     // one trajectory's disturbance-only tube (mu, sigma)
+    int64_t cap_dist = 0;                       // doubles
 };
 static SurWorkspace g_sw;
 
@@ -166,6 +168,15 @@ static int grow_f32(float** p, int64_t* cap, int64_t count) {
     if (*p) (void)hipFree(*p);
     *p = nullptr; *cap = 0;
     if (hipMalloc(p, (size_t)count * sizeof(float)) != hipSuccess) { *p = nullptr; return LEB_ENOMEM; }
+    *cap = count;
+    return LEB_OK;
+}
+
+static int grow_f64(double** p, int64_t* cap, int64_t count) {
+    if (count <= *cap) return LEB_OK;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr; *cap = 0;
+    if (hipMalloc(p, (size_t)count * sizeof(double)) != hipSuccess) { *p = nullptr; return LEB_ENOMEM; }
     *cap = count;
     return LEB_OK;
 }
@@ -288,15 +299,25 @@ extern "C" int leb_fixed_point_learned(const leb_dynamics* dyn, int32_t batch, i
     {
         std::lock_guard<std::mutex> lock(g_sw.mu);
         if ((rc = sw_get(nodes, units * nx))) return rc;
-        // C_0: disturbance-only tube
-        if ((rc = launch_disturbance_tube(batch, N, U, phi, e, opt->pad, mu, sigma, s))) return rc;
+        // C_0: the disturbance-only tube (centre 0).  It is the same for every
+        // trajectory, so the first surrogate sweep reads one trajectory's copy;
+        // without surrogate sweeps it is written out whole and inflated below.
+        if (ws->sweeps > 0) {
+            if ((rc = grow_f64(&g_sw.dist, &g_sw.cap_dist, 2 * (int64_t)N * n))) return rc;
+            if ((rc = launch_disturbance_tube(1, N, U, phi, e, opt->pad, g_sw.dist, g_sw.dist + (int64_t)N * n, s)))
+                return rc;
+        } else if ((rc = launch_disturbance_tube(batch, N, U, phi, e, opt->pad, mu, sigma, s))) {
+            return rc;
+        }
         // surrogate sweeps: C <- T(surrogate bound of C); the last one stores sigma
         // inflated, sigma (1 + margin) + inflate_abs: the warm start above the
         // surrogate's fixed point
         for (int t = 0; t < ws->sweeps; ++t) {
-            if ((rc = surrogate_chain_sweep(ws->net, z, v, mu, sigma, (int)nodes, U, dyn->rest_len, opt->pad, g_sw.cb,
-                                            g_sw.rb, s, true)))
-                return rc;
+            rc = t == 0 ? surrogate_chain_sweep(ws->net, z, v, nullptr, g_sw.dist + (int64_t)N * n, (int)nodes, U,
+                                                dyn->rest_len, opt->pad, g_sw.cb, g_sw.rb, s, true, N)
+                        : surrogate_chain_sweep(ws->net, z, v, mu, sigma, (int)nodes, U, dyn->rest_len, opt->pad,
+                                                g_sw.cb, g_sw.rb, s, true);
+            if (rc) return rc;
             const bool last = t == ws->sweeps - 1;
             if ((rc = launch_tube_map_compact(batch, N, U, phi, e, opt->pad, g_sw.cb, g_sw.rb, mu, sigma, s,
                                               last ? 1.0 + ws->margin : 1.0, last ? opt->inflate_abs : 0.0)))
