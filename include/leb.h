@@ -199,9 +199,14 @@ typedef struct {
  *   mu, sigma [batch][N][nx+nu] in/out: warm start in (opt->warm), certified tube out
  *   certified [batch] device uint32 out: 1 = certified, 0 = sweep cap reached first
  *   sweeps_out host int32 out: number of bound sweeps, including the certifying one
- * Synchronises `stream` once per sweep (the stopping test reads one
- * value per trajectory).  Uses a library-owned, grow-only device workspace
- * (kept until process exit); calls from several host threads serialise.
+ * The host reads one open-trajectory count per sweep from pinned memory
+ * (published by the next sweep's bound launch) while one sweep stays in
+ * flight; it never synchronises `stream`.  On return the certificate
+ * flags and the tube are enqueued on `stream`.  Horizons up to N = 210
+ * (LEB_ENOTSUP beyond).  Options, e and N are checked before any launch
+ * (LEB_EINVAL, LEB_ENOTSUP).  Device pointers must be 8-byte aligned.
+ * Uses a library-owned, grow-only device workspace (kept until process
+ * exit); calls from several host threads serialise.
  */
 int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int32_t N, const double* z,
                           const double* v, const double* phi, const double* e, const leb_fp_options* opt,
@@ -362,8 +367,9 @@ typedef struct {
  * unchanged: every accepted tube satisfies F(C) inside C with the plain
  * bound, whatever the surrogate predicted.  Arguments as
  * leb_fixed_point_solve (opt->warm is ignored); sweeps_out counts the
- * certified (plain-bound) sweeps only.  Uses a library-owned workspace;
- * calls serialise.
+ * certified (plain-bound) sweeps only; the options, e, ws and N are
+ * checked before the first surrogate sweep is launched.  Uses a library-
+ * owned workspace; calls serialise.
  */
 int leb_fixed_point_learned(const leb_dynamics* dyn, int32_t batch, int32_t N, const double* z, const double* v,
                             const double* phi, const double* e, const leb_fp_options* opt, const leb_warm_start* ws,

@@ -71,6 +71,10 @@ int launch_tube_map_compact(int B, int N, int U, const double* phi, const double
                             const double* r2, double* mu, double* sigma, hipStream_t s, double scale = 1.0,
                             double shift = 0.0);
 // tube of the residual zonotopes (0, pad) at every step (the disturbance-only tube)
+// fixed-point arguments checked before any launch: options and e (LEB_EINVAL),
+// the horizon the compact tube map supports (LEB_ENOTSUP)
+constexpr int FP_MAX_N = 210;
+int fp_check_args(const leb_fp_options* opt, const double* e, int N);
 int launch_disturbance_tube(int B, int N, int U, const double* phi, const double* e, double pad, double* mu,
                             double* sigma, hipStream_t s);
 

@@ -283,8 +283,9 @@ extern "C" int leb_fixed_point_learned(const leb_dynamics* dyn, int32_t batch, i
     int rc = check_chain_dynamics(dyn);
     if (rc != LEB_OK) return rc;
     if (dyn->kind != LEB_DYN_PQUAD_CHAIN) return LEB_ENOTSUP;
-    if (!opt || !ws || !ws->net || !e || !sweeps_out || batch < 0 || N < 0) return LEB_EINVAL;
+    if (!ws || !ws->net || !sweeps_out || batch < 0 || N < 0) return LEB_EINVAL;
     if (ws->sweeps < 0 || !(ws->margin >= 0.0) || !isfinite(ws->margin)) return LEB_EINVAL;
+    if ((rc = fp_check_args(opt, e, N))) return rc;      // before any launch
     int32_t din = 0, dout = 0;
     if (leb_surrogate_dims(ws->net, &din, &dout) || din != LEB_CHAIN_FEATURES || dout != LEB_CHAIN_OUTPUTS)
         return LEB_EINVAL;
@@ -292,6 +293,9 @@ extern "C" int leb_fixed_point_learned(const leb_dynamics* dyn, int32_t batch, i
     const int64_t units = (int64_t)batch * N;
     if (units == 0) return LEB_OK;
     if (!z || !v || !mu || !sigma || !certified || (N > 1 && !phi)) return LEB_EINVAL;
+    const void* ptrs[] = {z, v, phi, mu, sigma};
+    for (const void* p : ptrs)
+        if (p && ((uintptr_t)p & 7)) return LEB_EINVAL;
     const int U = dyn->n_units, nx = dyn->nx, n = dyn->nx + dyn->nu;
     const int64_t nodes = units * U;
     if (nodes > 0x7fffffff) return LEB_EINVAL;

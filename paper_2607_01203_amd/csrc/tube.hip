@@ -839,6 +839,21 @@ extern "C" int leb_tube_map(int32_t batch, int32_t N, int32_t n_units, const dou
     return launch_tube_map(batch, N, n_units, phi, e, c_bar, rho_bar, mu, sigma, (hipStream_t)stream);
 }
 
+namespace leb {
+int fp_check_args(const leb_fp_options* opt, const double* e, int N) {
+    if (!opt || !e) return LEB_EINVAL;
+    if (!(opt->tol >= 0.0) || !isfinite(opt->tol) || opt->max_sweeps < 1 || !(opt->pad >= 0.0) ||
+        !(opt->inflate_abs > 0.0) || !isfinite(opt->inflate_abs))
+        return LEB_EINVAL;
+    for (int q = 0; q < 6; ++q)
+        if (!(e[q] >= 0.0) || !isfinite(e[q])) return LEB_EINVAL;
+    // the compact tube map keeps Phi's two residual columns, the affine sums and
+    // the residuals of all steps of 16 node columns in LDS: 768 N + 2016 bytes
+    if (N > FP_MAX_N) return LEB_ENOTSUP;
+    return LEB_OK;
+}
+}  // namespace leb
+
 extern "C" int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int32_t N, const double* z,
                                      const double* v, const double* phi, const double* e,
                                      const leb_fp_options* opt, double* mu, double* sigma,
@@ -846,13 +861,8 @@ extern "C" int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int
     int rc = check_chain_dynamics(dyn);
     if (rc != LEB_OK) return rc;
     if (dyn->kind != LEB_DYN_PQUAD_CHAIN) return LEB_ENOTSUP;
-    if (!opt || !e || !sweeps_out) return LEB_EINVAL;
-    if (batch < 0 || N < 0) return LEB_EINVAL;
-    if (!(opt->tol >= 0.0) || !isfinite(opt->tol) || opt->max_sweeps < 1 || !(opt->pad >= 0.0) ||
-        !(opt->inflate_abs > 0.0) || !isfinite(opt->inflate_abs))
-        return LEB_EINVAL;
-    for (int q = 0; q < 6; ++q)
-        if (!(e[q] >= 0.0) || !isfinite(e[q])) return LEB_EINVAL;
+    if (!sweeps_out || batch < 0 || N < 0) return LEB_EINVAL;
+    if ((rc = fp_check_args(opt, e, N))) return rc;
     *sweeps_out = 0;
     const int64_t units = (int64_t)batch * N;
     if (units == 0) return LEB_OK;

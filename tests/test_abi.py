@@ -138,6 +138,25 @@ def test_fixed_point_rejects_bad_options_without_launching(L):
     assert call(max_sweeps=0) == -1
     assert call(inflate_abs=0.0) == -1
     assert call(pad=-1.0) == -1
+    # a horizon beyond what the compact tube map keeps in LDS: LEB_ENOTSUP (-4)
+    opt = leb.FPOptions(1e-6, 10, 0.0, 1e-12, 0)
+    assert L.leb_fixed_point_solve(ctypes.byref(d), 4, 211, vp, vp, vp, e, ctypes.byref(opt), vp, vp, vp,
+                                   ctypes.byref(sw), None) == -4
+    # the learned form checks the same options before its surrogate sweeps (the
+    # network handle is not touched on these paths)
+    ws = leb.WarmStart(ctypes.c_void_p(8), 1, 0.05)
+
+    def learned(N=3, **kw):
+        o = dict(tol=1e-6, max_sweeps=10, pad=0.0, inflate_abs=1e-12, warm=0)
+        o.update(kw)
+        opt = leb.FPOptions(o["tol"], o["max_sweeps"], o["pad"], o["inflate_abs"], o["warm"])
+        return L.leb_fixed_point_learned(ctypes.byref(d), 4, N, vp, vp, vp, e, ctypes.byref(opt), ctypes.byref(ws),
+                                         vp, vp, vp, ctypes.byref(sw), None)
+
+    assert learned(tol=-1.0) == -1
+    assert learned(max_sweeps=0) == -1
+    assert learned(inflate_abs=0.0) == -1
+    assert learned(N=211) == -4
     # zero work: accepted without a launch
     opt = leb.FPOptions(1e-6, 10, 0.0, 1e-12, 0)
     assert L.leb_fixed_point_solve(ctypes.byref(d), 0, 3, None, None, None, e, ctypes.byref(opt), None, None, None,

@@ -129,14 +129,15 @@ def test_fixed_point_large_batch(gpu, orc):
     _check_against_oracle(orc, tp, mu, sg, np.array([0, 513, 1023]))
 
 
-@pytest.mark.parametrize("batch,N,U", [(3, 46, 6), (2, 9, 40), (2, 70, 3), (1, 131, 2), (300, 2, 1), (4, 1, 3)])
+@pytest.mark.parametrize("batch,N,U", [(3, 46, 6), (2, 9, 40), (2, 70, 3), (1, 131, 2), (300, 2, 1), (4, 1, 3), (1, 210, 2)])
 def test_fixed_point_long_horizon_and_long_chain(gpu, orc, batch, N, U):
     """A horizon of 46 steps (two row groups in the tube map), a chain of 40
     nodes (6 steps per bound workgroup), horizons of 70 and 131 steps (Phi
     and the residuals staged in two and three passes, up to four row
     groups), and 300 two-step trajectories of one node (a bound workgroup
     spans 128 trajectories; the fold covers more trajectories than lanes),
-    and a horizon of one step (no Phi: the tube is the known initial state)."""
+    a horizon of one step (no Phi: the tube is the known initial state), and
+    the longest horizon the compact tube map keeps in LDS (210 steps)."""
     import paper_2607_01203_amd as leb
     tp = W.fixed_point_cfg(seed=60 + N, batch=batch, N=N, n_units=U)
     print("case: fixed point B=%d N=%d U=%d" % (batch, N, U), flush=True)
