@@ -154,3 +154,28 @@ def test_untrained_surrogate_still_certifies(trained, orc, batch, N, U):
     assert bool((cert == 1).all())
     mo, so, _, _ = _oracle_fixed_point(orc, tp, np.arange(batch))
     assert (sg.cpu().numpy() >= so * (1 - 1e-12)).all()
+
+
+def test_learned_form_without_surrogate_sweeps(trained, orc):
+    """No surrogate sweeps: the start is the disturbance-only tube inflated
+    by the margin, and the certified iteration runs from there."""
+    import torch
+    leb, net, dev, _ = trained
+    tp = W.fixed_point_cfg(seed=51, batch=3, N=12, n_units=5)
+    b = tp.batch
+    dyn = leb.dynamics_like(b.dyn)
+    print("case: learned form, 0 surrogate sweeps B=3 N=12 U=5", flush=True)
+    mu, sg, cert, sw = leb.fixed_point_learned(dyn, _t(b.z, dev), _t(b.v, dev), _t(tp.phi, dev), tp.e, net,
+                                               sweeps=0, margin=0.1)
+    torch.cuda.synchronize()
+    assert bool((cert == 1).all()) and 1 <= sw <= 12 + 2
+    mo, so, _, _ = _oracle_fixed_point(orc, tp, np.arange(3))
+    sg = sg.cpu().numpy()
+    assert (sg >= so * (1 - 1e-12)).all()
+    pos = so > 0
+    ratio = sg[pos] / so[pos]
+    print("sigma / least fixed point: median %.6f max %.6f" % (np.median(ratio), ratio.max()))
+    # a trajectory is accepted at the first tube shown to contain its image, so a
+    # start above the least fixed point may be kept: the disturbance-only tube
+    # lies below it, and 10% over it stays within the map's gain of it
+    assert ratio.max() <= 1.25
