@@ -161,6 +161,20 @@ def main():
     ms_per_step = learned_ms
     value = units * 1e3 / learned_ms
 
+    # comparison start without the surrogate: one plain sweep from the
+    # disturbance-only tube, sigma inflated by the same margin, then the
+    # certified iteration (two library calls)
+    def exact_start():
+        m, s_, _, _ = leb.fixed_point_solve(dyn, z, v, phi, tp.e, tol=1e-6, max_sweeps=1)
+        s_.mul_(1.0 + args.margin).add_(1e-12)
+        return leb.fixed_point_solve(dyn, z, v, phi, tp.e, tol=1e-6, max_sweeps=200, mu=m, sigma=s_)
+    exact_ms, (_, sg_x, cert_x, _), exact_sweeps = timed(exact_start)
+    ex_x = sg_x.cpu().numpy()[pos] / s0[pos] - 1.0
+    exact_line = {"ms_per_solve": round(exact_ms, 4), "certified_sweeps": 1 + exact_sweeps,
+                  "certified": bool((cert_x == 1).all().item()),
+                  "sigma_over_plain_median": round(float(np.median(ex_x)), 6),
+                  "sigma_over_plain_max": round(float(ex_x.max()), 6)}
+
     # Dominant kernel: the tube map of the certified sweeps (6 of the ~11 launches
     # of a learned solve, the largest share of its time).  Its launches in one
     # learned solve are timed with HIP events on the solve's stream; the
@@ -219,6 +233,7 @@ def main():
                     "margin": args.margin, "ms_per_solve": round(learned_ms, 4),
                     "sigma_over_plain_median": round(float(np.median(excess)), 6),
                     "sigma_over_plain_max": round(float(excess.max()), 6), "training": train_info},
+        "exact_start_same_margin": exact_line,
         "plain": {"value": round(units * 1e3 / plain_ms, 1), "ms_per_solve": round(plain_ms, 4),
                   "certified_sweeps": plain_sweeps, "certified": plain_cert},
         "roofline": roofline, "cpu_baseline": cpu, "roofline_bound": roofline_bound,
