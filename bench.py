@@ -57,6 +57,8 @@ def parse():
     p.add_argument("--surrogate-sweeps", type=int, default=1)
     p.add_argument("--margin", type=float, default=5e-2, help="relative inflation of the surrogate tube")
     p.add_argument("--no-extra", action="store_true", help="skip the MLP-bound roofline and the uneven batch")
+    p.add_argument("--nn-only", action="store_true",
+                   help="only run the MLP-bound roofline measurement (for profiling its kernels)")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                    help="only run an elementwise copy (read BYTES, write BYTES) 5 times: the known-size "
                         "kernel that scales FETCH_SIZE / WRITE_SIZE counters")
@@ -117,6 +119,9 @@ def main():
     import workloads as W
 
     dev = torch.device("cuda:0")
+    if args.nn_only:
+        print(json.dumps({"roofline_nn": nn_roofline(leb, W, dev, torch.cuda.current_stream(), args)}))
+        return
     tp = W.fixed_point_cfg()
     b = tp.batch
     B, N, nx = b.z.shape
