@@ -178,3 +178,14 @@ def test_sample_cache_round_trip(tmp_path):
     np.savez(p, X=np.zeros((3, 2)), T=np.zeros((4, 2), dtype=np.float32))
     with pytest.raises(ValueError):
         learned.load_samples(p, device="cpu")
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus above 1 exits with a message and
+    status 2 before touching a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
