@@ -346,7 +346,9 @@ int leb_nn_targets(int32_t m, int32_t batch, int32_t N, const double* r_lo, cons
  * not finite gives 0.  Not a certified bound.
  *   z, v, mu (NULL = 0), sigma as leb_nn_features; r_lo, r_hi [batch][N][m] (device FP64).
  * LEB_EINVAL also when the network's widths do not match.  Uses a library-
- * owned grow-only workspace (batch N (2n + 2m) floats); calls serialise.
+ * owned grow-only workspace (batch N (2n + 2m) floats); calls serialise on
+ * the host, and calls enqueued on different streams must not overlap on the
+ * device (they share the workspace).
  */
 int leb_nn_surrogate_bound(leb_surrogate net, int32_t nx, int32_t nu, int32_t batch, int32_t N, const double* z,
                            const double* v, const double* mu, const double* sigma, double* r_lo, double* r_hi,
