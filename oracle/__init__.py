@@ -64,6 +64,8 @@ def lib():
         L.orc_nonlin.argtypes = [ctypes.POINTER(_Dyn), ctypes.c_int, dp, dp, dp]
         L.orc_leb_grad.argtypes = [ctypes.POINTER(_Dyn), ctypes.c_long, dp, dp, dp, dp, dp, dp, dp, dp,
                                    dp, dp, dp, ctypes.c_int]
+        L.orc_step.argtypes = [ctypes.POINTER(_Dyn), ctypes.c_long, dp, dp, dp]
+        L.orc_jacobian.argtypes = [ctypes.POINTER(_Dyn), ctypes.c_long, dp, dp, dp, dp]
         L.orc_isin.argtypes = [ctypes.c_double, ctypes.c_double, dp]
         L.orc_icos.argtypes = [ctypes.c_double, ctypes.c_double, dp]
         _lib = L
@@ -161,6 +163,32 @@ def nonlin(dyn: Dyn, l, point):
     grad = np.zeros(dyn.n)
     lib().orc_nonlin(ctypes.byref(dyn.c), int(l), _ptr(p), _ptr(val), _ptr(grad))
     return float(val[0]), grad
+
+
+def step(dyn: Dyn, z, v):
+    """Discretised dynamics f(x, u) at points z [..., nx], v [..., nu]."""
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    lead = z.shape[:-1]
+    U = int(np.prod(lead)) if lead else 1
+    vv = np.ascontiguousarray(v, dtype=np.float64).reshape(U, dyn.nu) if dyn.nu else np.zeros((U, 1))
+    f = np.empty((U, dyn.nx))
+    if lib().orc_step(ctypes.byref(dyn.c), U, _ptr(z.reshape(U, dyn.nx)), _ptr(vv), _ptr(f)) != 0:
+        raise ValueError("oracle step rejected the arguments")
+    return f.reshape(lead + (dyn.nx,))
+
+
+def jacobian(dyn: Dyn, z, v):
+    """Point Jacobians A = df/dx [..., nx, nx], B = df/du [..., nx, nu]
+    (eq. linearizations) at the nominal points."""
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    lead = z.shape[:-1]
+    U = int(np.prod(lead)) if lead else 1
+    vv = np.ascontiguousarray(v, dtype=np.float64).reshape(U, dyn.nu) if dyn.nu else np.zeros((U, 1))
+    A = np.empty((U, dyn.nx, dyn.nx))
+    B = np.empty((U, dyn.nx, max(dyn.nu, 1)))
+    if lib().orc_jacobian(ctypes.byref(dyn.c), U, _ptr(z.reshape(U, dyn.nx)), _ptr(vv), _ptr(A), _ptr(B)) != 0:
+        raise ValueError("oracle jacobian rejected the arguments")
+    return A.reshape(lead + (dyn.nx, dyn.nx)), B[..., :dyn.nu].reshape(lead + (dyn.nx, dyn.nu))
 
 
 def isin(lo, hi):

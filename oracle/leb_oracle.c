@@ -590,3 +590,74 @@ int orc_nonlin(const orc_dyn* d, int l, const double* a, double* val, double* gr
     else test_nonlin(d, l, a, val, grad, &mag);
     return 0;
 }
+
+/* ------------------------------------------- dynamics and linearization */
+
+/* Affine part of the discretised chain dynamics (explicit Euler, x+ = x +
+ * dt xdot): row l of its Jacobian in a = [x; u] is written to row[n] and its
+ * constant term returned.  Per node i: px+ = px + dt vx, pz+ = pz + dt vz,
+ * theta+ = theta + dt omega, vx+ = vx (+ N), vz+ = vz - dt g (+ N),
+ * omega+ = omega + dt (u1 - u2) arm / inertia.  The remaining terms of the
+ * velocity rows (thrust and springs) are the nonlinear part N above. */
+static double chain_affine_row(const orc_dyn* d, int l, double* row) {
+    int n = dyn_n(d), i = l / 6, comp = l % 6;
+    memset(row, 0, sizeof(double) * n);
+    row[l] = 1.0;
+    double cst = 0.0;
+    switch (comp) {
+    case 0: case 1: case 2: row[6 * i + comp + 3] = d->dt; break;
+    case 4: cst = -d->dt * d->g; break;
+    case 5: row[c_u(d, i, 0)] = d->dt * d->arm / d->inertia;
+            row[c_u(d, i, 1)] = -d->dt * d->arm / d->inertia; break;
+    }
+    return cst;
+}
+
+/* f(x, u) of the discretised dynamics at `units` points: the affine part
+ * (chain only; the test kinds have none) plus N.  f [units][nx]. */
+int orc_step(const orc_dyn* d, long units, const double* z, const double* v, double* f) {
+    int n = dyn_n(d);
+    if (n > MAXN || d->kind == ORC_LINEAR) return -1;
+    for (long u = 0; u < units; ++u) {
+        double a[MAXN], row[MAXN];
+        for (int i = 0; i < d->nx; ++i) a[i] = z[u * d->nx + i];
+        for (int i = 0; i < d->nu; ++i) a[d->nx + i] = v[u * d->nu + i];
+        for (int l = 0; l < d->nx; ++l) {
+            double val, mag, aff = 0.0;
+            if (d->kind == ORC_CHAIN) {
+                aff = chain_affine_row(d, l, row);
+                for (int k = 0; k < n; ++k) aff += row[k] * a[k];
+                chain_nonlin(d, l, a, &val, NULL, &mag);
+            } else {
+                test_nonlin(d, l, a, &val, NULL, &mag);
+            }
+            f[u * d->nx + l] = aff + val;
+        }
+    }
+    return 0;
+}
+
+/* Jacobians A = df/dx [units][nx][nx] and B = df/du [units][nx][nu] at the
+ * nominal points (eq. linearizations): affine rows plus grad N. */
+int orc_jacobian(const orc_dyn* d, long units, const double* z, const double* v, double* A, double* B) {
+    int n = dyn_n(d);
+    if (n > MAXN || d->kind == ORC_LINEAR) return -1;
+    for (long u = 0; u < units; ++u) {
+        double a[MAXN], row[MAXN], grad[MAXN];
+        for (int i = 0; i < d->nx; ++i) a[i] = z[u * d->nx + i];
+        for (int i = 0; i < d->nu; ++i) a[d->nx + i] = v[u * d->nu + i];
+        for (int l = 0; l < d->nx; ++l) {
+            double val, mag;
+            if (d->kind == ORC_CHAIN) {
+                chain_affine_row(d, l, row);
+                chain_nonlin(d, l, a, &val, grad, &mag);
+            } else {
+                memset(row, 0, sizeof(double) * n);
+                test_nonlin(d, l, a, &val, grad, &mag);
+            }
+            for (int k = 0; k < d->nx; ++k) A[(u * d->nx + l) * d->nx + k] = row[k] + grad[k];
+            for (int k = 0; k < d->nu; ++k) B[(u * d->nx + l) * d->nu + k] = row[d->nx + k] + grad[d->nx + k];
+        }
+    }
+    return 0;
+}
