@@ -49,6 +49,8 @@ typedef enum {
 
 typedef enum {
     LEB_DYN_LINEAR = 0,        /* affine dynamics: the remainder is identically 0 */
+    LEB_DYN_QUADRATIC = 1,     /* f_l(a) = 1/2 a^T Q_l a + affine: constant Hessian Q_l */
+    LEB_DYN_SINCOS = 2,        /* nx = 1: f = sin(a_1); nx = 2: f = (sin a_1 cos a_2, cos a_1 sin a_2); nu = 0 */
     LEB_DYN_PQUAD_CHAIN = 4    /* planar quadrotors (1 = a single one) joined by springs */
 } leb_dyn_kind;
 
@@ -64,9 +66,13 @@ typedef enum {
  * coordinate-wise path of Theorem 1. */
 typedef struct {
     int32_t kind;       /* leb_dyn_kind */
-    int32_t nx, nu;     /* LINEAR: any sizes; CHAIN: must equal 6*n_units, 2*n_units */
+    int32_t nx, nu;     /* LINEAR: any sizes; CHAIN: must equal 6*n_units, 2*n_units;
+                           QUADRATIC: 1 <= nx + nu <= 64; SINCOS: nx in {1, 2}, nu = 0 */
     int32_t n_units;    /* CHAIN: 1 .. 256 */
     double dt, m, g, arm, inertia, k_spring, rest_len;   /* CHAIN: dt > 0, m > 0, k_spring >= 0, rest_len >= 0 */
+    const double* coeffs;  /* QUADRATIC: DEVICE pointer to Q [nx][nx+nu][nx+nu] (row l holds Q_l; only the
+                              entries k >= j are read, as the lower triangle of a symmetric matrix, and each
+                              must be finite); NULL for every other kind */
 } leb_dynamics;
 
 /*
@@ -88,12 +94,24 @@ typedef struct {
  *            includes the diagonal padding `pad` (>= 0) that keeps the
  *            zonotope generator right-invertible (section V.A)
  *   flags    [batch][N] optional per-unit flags (NULL to skip)
+ *   A, B     optional outputs (NULL to skip; CHAIN dynamics only, LEB_EINVAL
+ *            otherwise): the point Jacobians of the discretised dynamics at
+ *            the nominal (eq. linearizations), A [batch][N][nx][nx] = df/dx,
+ *            B [batch][N][nx][nu] = df/du, row-major, FP64 (round to nearest;
+ *            they define the linearization, they are not enclosures).  Every
+ *            entry is written.
+ * Kinds: CHAIN (nodes in one workgroup, FP32 outward intervals, FP64
+ * accumulation); LINEAR ([0, 0] for valid data); QUADRATIC and SINCOS,
+ * closed-form test dynamics (one thread per unit; QUADRATIC reads Q through
+ * dyn->coeffs).  Invalid data (non-finite nominal, mu or sigma, negative
+ * sigma) gives [-inf, +inf] on every row of the unit and LEB_FLAG_BAD_INPUT
+ * for every kind; z and sigma (and v when nu > 0) are required for every kind.
  * Returns LEB_OK or a negative leb_status.
  */
 int leb_analytic_bound(const leb_dynamics* dyn, int32_t batch, int32_t N,
                        const double* z, const double* v, const double* mu, const double* sigma,
                        double* r_lo, double* r_hi, double* c_bar, double* rho_bar, double pad,
-                       uint32_t* flags, void* stream);
+                       uint32_t* flags, double* A, double* B, void* stream);
 
 /*
  * leb_backward -- adjoint of leb_analytic_bound: the gradient of
@@ -146,12 +164,20 @@ int leb_mlp_destroy(leb_mlp net);
  *   z [batch][N][nx], v [batch][N][nu], mu (NULL = 0) and sigma
  *   [batch][N][nx+nu], outputs r_lo, r_hi (and optional c_bar, rho_bar)
  *   [batch][N][m], flags [batch][N] (optional), as leb_analytic_bound.
+ *   J        [batch][N][m][nx+nu] (FP64) or NULL: the matrix of the
+ *            linearization.  NULL: the network's Jacobian at the nominal,
+ *            computed by the library.  Given: Theorem 2 with this J (it holds
+ *            for any J), so the bound encloses g(a) - g(a~) - J (a - a~);
+ *            a unit whose J has a non-finite entry gets [-inf, +inf] on every
+ *            row and LEB_FLAG_BAD_INPUT.
  * Uses a library-owned grow-only workspace (about 1.5 GB at the largest
- * chunk of 1024 boxes); calls from several host threads serialise.
+ * chunk of 1024 boxes).  Calls from several host threads serialise on the
+ * host, and a call's kernels wait (on the device) for those of the previous
+ * call that used the workspace, whatever its stream.
  */
 int leb_nn_bound(leb_mlp net, int32_t batch, int32_t N, const double* z, const double* v, const double* mu,
-                 const double* sigma, double* r_lo, double* r_hi, double* c_bar, double* rho_bar, double pad,
-                 uint32_t* flags, void* stream);
+                 const double* sigma, const double* J, double* r_lo, double* r_hi, double* c_bar, double* rho_bar,
+                 double pad, uint32_t* flags, void* stream);
 
 /*
  * leb_tube_map -- tube centre and width from the residual zonotopes
@@ -173,27 +199,46 @@ int leb_nn_bound(leb_mlp net, int32_t batch, int32_t N, const double* z, const d
 int leb_tube_map(int32_t batch, int32_t N, int32_t n_units, const double* phi, const double* e,
                  const double* c_bar, const double* rho_bar, double* mu, double* sigma, void* stream);
 
+/*
+ * leb_zonotope_hull -- interval hull of zonotopes (eq. tight_tube_width):
+ * for each row i of a zonotope {c + G xi : |xi|_inf <= 1} with generator
+ * matrix G [rows][n_gen] (row-major) and centre c [rows],
+ *     mu[i] = c[i],    sigma[i] = ||G_i||_1 = sum_j |G_ij|   (rounded upward).
+ * rows >= 0, n_gen >= 0 (0: sigma = 0); c may be NULL (mu = 0).  A row with a
+ * non-finite generator entry gets sigma = +inf.  One wave per row.
+ */
+int leb_zonotope_hull(int32_t rows, int32_t n_gen, const double* G, const double* c, double* mu, double* sigma,
+                      void* stream);
+
 typedef struct {
-    double tol;            /* relative inflation per sweep (>= 0, e.g. 1e-6): the certified tube lies
-                              about tol above the least fixed point */
+    double tol;            /* relative inflation per sweep (>= 0, e.g. 1e-6) */
     int32_t max_sweeps;    /* cap on bound sweeps (plain LEB evaluations of all steps), >= 1 */
     double pad;            /* zonotope radius padding (>= 0) */
     double inflate_abs;    /* absolute inflation per sweep (> 0); floor of the relative change */
     int32_t warm;          /* 1: start from the (mu, sigma) passed in; 0: disturbance-only tube */
+    double conv_tol;       /* acceptance also needs convergence: the next iterate C' differs from C by at
+                              most |sigma' - sigma| <= conv_tol sigma + 2 inflate_abs and
+                              |mu' - mu| <= conv_tol sigma + inflate_abs, per entry (>= tol).  From the
+                              cold start (below the fixed point) every certified iterate meets this with
+                              conv_tol = tol; a warm start above the fixed point keeps sweeping until it does */
 } leb_fp_options;
 
 /*
  * leb_fixed_point_solve -- certified tube/LEB fixed point for chain
- * dynamics (the loop of section V: bound -> zonotope -> tube map, until
- * the tube stops changing; Theorem 3 gives containment of the reachable
- * set in the tube).  Each sweep bounds every (trajectory, step) at once
- * with leb_analytic_bound's kernel and applies leb_tube_map: C' = F(C).
- * A tube C is certified when F(C) lies inside C for every step (a
- * post-fixed point of the inclusion-isotone map F, so the Theorem 3
- * induction goes through).  Iteration: C <- F(C) (1 + tol) + inflate_abs
- * on sigma (mu <- mu_F), which converges, by causality of F, in at most
- * N + 1 sweeps to a tube about tol above the least fixed point; each
- * trajectory is frozen at the first iterate shown to be certified.
+ * dynamics (the loop of section V, Nonlinear SLS Formulation: bound ->
+ * zonotope -> tube map, until the change of the iterates falls below a
+ * threshold; Theorem 3 gives containment of the reachable set in the
+ * tube).  Each sweep bounds every (trajectory, step) at once with
+ * leb_analytic_bound's kernel and applies leb_tube_map: C' = F(C).  A tube
+ * C is certified when F(C) lies inside C for every step (a post-fixed
+ * point of the inclusion-isotone map F, so the Theorem 3 induction goes
+ * through).  Iteration: C <- F(C) (1 + tol) + inflate_abs on sigma
+ * (mu <- mu_F), which converges, by causality of F, in at most N + 1 sweeps
+ * to a tube about tol above the least fixed point.  Each trajectory is
+ * accepted (frozen) at the first iterate C that is certified and converged
+ * (opt->conv_tol): from the cold start or any warm start the accepted tube
+ * lies within about conv_tol of the least fixed point's neighbourhood
+ * reached by the cold start.
  *   z, v    [batch][N][nx], [batch][N][nu] nominal trajectories
  *   phi, e  as leb_tube_map
  *   mu, sigma [batch][N][nx+nu] in/out: warm start in (opt->warm), certified tube out
@@ -206,7 +251,9 @@ typedef struct {
  * (LEB_ENOTSUP beyond).  Options, e and N are checked before any launch
  * (LEB_EINVAL, LEB_ENOTSUP).  Device pointers must be 8-byte aligned.
  * Uses a library-owned, grow-only device workspace (kept until process
- * exit); calls from several host threads serialise.
+ * exit).  Calls from several host threads serialise on the host, and a
+ * call's kernels wait (on the device) for those of the previous call that
+ * used the workspace, whatever its stream.
  */
 int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int32_t N, const double* z,
                           const double* v, const double* phi, const double* e, const leb_fp_options* opt,
@@ -227,9 +274,9 @@ int leb_launch_timing(int32_t enable);
 int leb_launch_times(int32_t kernel, float* ms, int32_t cap, int32_t* count);
 
 /*
- * Learned warm start (section V: the fixed point is started from a tube the
- * surrogate predicts; every accepted tube is still certified by the plain
- * bound).  A GELU MLP with widths [d_0, ..., d_L] (L <= 8, every width in
+ * Learned warm start (not a step of the paper: a surrogate network that
+ * starts the section-V fixed point from a predicted tube; every accepted
+ * tube is still certified by the plain bound).  A GELU MLP with widths [d_0, ..., d_L] (L <= 8, every width in
  * 1..256), FP32 master parameters and BF16 MFMA arithmetic with FP32
  * accumulation:
  *   a_0 = bf16(x); z_l = bf16(W_l) a_{l-1} + b_l; a_l = bf16(gelu(z_l));
@@ -315,7 +362,7 @@ int leb_chain_surrogate_bound(const leb_dynamics* dyn, int32_t batch, int32_t N,
                               double* rho_bar, double pad, void* stream);
 
 /*
- * NN surrogate (the learned start's second family, section V): for ReLU-MLP
+ * NN surrogate (the learned start's second family; not a step of the paper): for ReLU-MLP
  * dynamics with n = nx + nu network inputs and m outputs (leb_nn_bound),
  * one box of the network's input is described by 2n features
  *   x[0..n-1]    a~ = [z; v] (the nominal point)
@@ -365,13 +412,14 @@ typedef struct {
  * learned tube: from the disturbance-only tube, ws->sweeps tube sweeps use
  * the surrogate's predicted bounds (features -> BF16 MLP -> zonotope ->
  * tube map); sigma is then inflated to sigma (1 + margin) + opt->inflate_abs
- * and passed to leb_fixed_point_solve as a warm start.  Certification is
+ * and passed to leb_fixed_point_solve as a warm start.  Acceptance is
  * unchanged: every accepted tube satisfies F(C) inside C with the plain
- * bound, whatever the surrogate predicted.  Arguments as
- * leb_fixed_point_solve (opt->warm is ignored); sweeps_out counts the
- * certified (plain-bound) sweeps only; the options, e, ws and N are
- * checked before the first surrogate sweep is launched.  Uses a library-
- * owned workspace; calls serialise.
+ * bound, whatever the surrogate predicted, and has converged to within
+ * opt->conv_tol like the cold start's.  Arguments as leb_fixed_point_solve
+ * (opt->warm is ignored); sweeps_out counts the certified (plain-bound)
+ * sweeps only; the options, e, ws and N are checked before the first
+ * surrogate sweep is launched.  Uses a library-owned workspace, ordered on
+ * the device across streams like leb_fixed_point_solve's.
  */
 int leb_fixed_point_learned(const leb_dynamics* dyn, int32_t batch, int32_t N, const double* z, const double* v,
                             const double* phi, const double* e, const leb_fp_options* opt, const leb_warm_start* ws,

@@ -126,9 +126,12 @@ def layer_bounds(W, b, c, rho):
     return bounds, rel
 
 
-def leb(W, b, alpha, sigma, mu=None, centred=True):
+def leb(W, b, alpha, sigma, mu=None, centred=True, J=None):
     """Theorem 2 bound [r_lo, r_hi] per unit (alpha, sigma [..., n0]).
 
+    J [..., m, n0]: the matrix of the linearization (None: the network's
+    Jacobian at alpha).  Theorem 2 holds for any J: the bound then encloses
+    g(a) - g(a~) - J (a - a~).
     Returns dict with r_lo, r_hi (direct form), c_lo, c_hi (centred form),
     J, g, Lambda_hi, Lambda_lo, beta_hi, beta_lo, unstable counts."""
     W = [np.asarray(w, dtype=np.float64) for w in W]
@@ -138,7 +141,7 @@ def leb(W, b, alpha, sigma, mu=None, centred=True):
     L = len(W)
     zs = forward(W, b, alpha)
     g = zs[-1]
-    J = jacobian(W, zs)
+    J = jacobian(W, zs) if J is None else np.asarray(J, dtype=np.float64)
     bounds, rel = layer_bounds(W, b, c, rho)
     tw = np.broadcast_to(W[-1], alpha.shape[:-1] + W[-1].shape)
     tb = np.broadcast_to(b[-1], alpha.shape[:-1] + b[-1].shape)
@@ -169,14 +172,15 @@ def leb(W, b, alpha, sigma, mu=None, centred=True):
     return out
 
 
-def remainder(W, b, alpha_nom, pts):
+def remainder(W, b, alpha_nom, pts, J=None):
     """True remainder g(a) - g(a~) - J(a~)(a - a~) at points [..., S, n0]
     for nominals [..., n0], in FP64 (long double where numpy provides it is
-    not needed: the allowance below bounds the FP64 error)."""
+    not needed: the allowance below bounds the FP64 error).  J [..., m, n0]
+    replaces the network's Jacobian when given."""
     W = [np.asarray(w, dtype=np.float64) for w in W]
     b = [np.asarray(x, dtype=np.float64) for x in b]
     zs0 = forward(W, b, alpha_nom)
-    J = jacobian(W, zs0)
+    J = jacobian(W, zs0) if J is None else np.asarray(J, dtype=np.float64)
     g0 = zs0[-1]
     zs = forward(W, b, pts)
     d = pts - alpha_nom[..., None, :]

@@ -99,3 +99,15 @@ def contains(mu_in, sg_in, mu_out, sg_out):
     """Box (mu_out +/- sg_out) inside box (mu_in +/- sg_in), per trajectory."""
     ok = (mu_out - sg_out >= mu_in - sg_in) & (mu_out + sg_out <= mu_in + sg_in)
     return ok.reshape(ok.shape[0], -1).all(1)
+
+
+def zonotope_hull(G, c=None):
+    """Interval hull of the zonotopes {c + G xi : |xi|_inf <= 1}, row by row
+    (eq. tight_tube_width): mu = c, sigma_i = sum_j |G_ij|, the row's
+    maximum of |G_i xi| over the unit box.  G [rows][n_gen]; the sums are
+    exact to the last bit (math.fsum), then rounded to nearest."""
+    import math
+    G = np.asarray(G, dtype=np.float64)
+    sg = np.array([math.fsum(np.abs(row)) for row in G]) if G.shape[1] else np.zeros(G.shape[0])
+    mu = np.zeros(G.shape[0]) if c is None else np.asarray(c, dtype=np.float64).copy()
+    return mu, sg

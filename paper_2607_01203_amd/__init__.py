@@ -10,14 +10,15 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["lib", "Dynamics", "LebError", "analytic_bound", "chain_dynamics", "tube_map", "fixed_point_solve", "FLAG_UNBOUNDED",
-           "FLAG_BAD_INPUT", "FLAG_HULL_EXTENDED", "DYN_LINEAR", "DYN_PQUAD_CHAIN"]
+__all__ = ["lib", "Dynamics", "LebError", "analytic_bound", "chain_dynamics", "linear_dynamics", "quadratic_dynamics",
+           "sincos_dynamics", "tube_map", "zonotope_hull", "fixed_point_solve", "FLAG_UNBOUNDED",
+           "FLAG_BAD_INPUT", "FLAG_HULL_EXTENDED", "DYN_LINEAR", "DYN_QUADRATIC", "DYN_SINCOS", "DYN_PQUAD_CHAIN"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libleb.so")
 
 FLAG_UNBOUNDED, FLAG_BAD_INPUT, FLAG_HULL_EXTENDED = 1, 2, 4
-DYN_LINEAR, DYN_PQUAD_CHAIN = 0, 4
+DYN_LINEAR, DYN_QUADRATIC, DYN_SINCOS, DYN_PQUAD_CHAIN = 0, 1, 2, 4
 
 _lib = None
 
@@ -30,7 +31,7 @@ class Dynamics(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("nx", ctypes.c_int32), ("nu", ctypes.c_int32),
                 ("n_units", ctypes.c_int32), ("dt", ctypes.c_double), ("m", ctypes.c_double),
                 ("g", ctypes.c_double), ("arm", ctypes.c_double), ("inertia", ctypes.c_double),
-                ("k_spring", ctypes.c_double), ("rest_len", ctypes.c_double)]
+                ("k_spring", ctypes.c_double), ("rest_len", ctypes.c_double), ("coeffs", ctypes.c_void_p)]
 
 
 class WarmStart(ctypes.Structure):
@@ -53,13 +54,35 @@ PROBLEM_NN = 1
 
 class FPOptions(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_sweeps", ctypes.c_int32), ("pad", ctypes.c_double),
-                ("inflate_abs", ctypes.c_double), ("warm", ctypes.c_int32)]
+                ("inflate_abs", ctypes.c_double), ("warm", ctypes.c_int32), ("conv_tol", ctypes.c_double)]
 
 
 def chain_dynamics(n_units, dt=0.05, m=1.0, g=9.81, arm=0.25, inertia=0.01, k_spring=2.0,
                    rest_len=1.0) -> Dynamics:
     return Dynamics(DYN_PQUAD_CHAIN, 6 * n_units, 2 * n_units, n_units, dt, m, g, arm, inertia,
-                    k_spring, rest_len)
+                    k_spring, rest_len, None)
+
+
+def linear_dynamics(nx, nu=0) -> Dynamics:
+    """Affine dynamics: the remainder is identically 0."""
+    return Dynamics(DYN_LINEAR, int(nx), int(nu), 0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, None)
+
+
+def quadratic_dynamics(Q, nu=0) -> Dynamics:
+    """f_l(a) = 1/2 a^T Q_l a + affine, Q a float64 GPU tensor [nx][n][n]
+    (kept alive by the returned object while it is in use)."""
+    import torch
+    Q = Q.contiguous()
+    nx, n = int(Q.shape[0]), int(Q.shape[1])
+    d = Dynamics(DYN_QUADRATIC, nx, n - nx if nu is None else int(nu), 0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0,
+                 _dev_ptr(Q, "Q", torch.float64).value)
+    d._Q = Q
+    return d
+
+
+def sincos_dynamics(nx) -> Dynamics:
+    """nx = 1: f = sin(a_1); nx = 2: f = (sin a_1 cos a_2, cos a_1 sin a_2)."""
+    return Dynamics(DYN_SINCOS, int(nx), 0, 0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, None)
 
 
 def dynamics_like(obj) -> Dynamics:
@@ -77,7 +100,7 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         vp = ctypes.c_void_p
         L.leb_analytic_bound.argtypes = [ctypes.POINTER(Dynamics), ctypes.c_int32, ctypes.c_int32,
-                                         vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, vp, vp]
+                                         vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, vp, vp, vp, vp]
         L.leb_analytic_bound.restype = ctypes.c_int
         L.leb_backward.argtypes = [ctypes.POINTER(Dynamics), ctypes.c_int32, ctypes.c_int32] + [vp] * 11
         L.leb_backward.restype = ctypes.c_int
@@ -88,11 +111,13 @@ def lib():
         L.leb_mlp_create.restype = ctypes.c_int
         L.leb_mlp_destroy.argtypes = [ctypes.c_void_p]
         L.leb_mlp_destroy.restype = ctypes.c_int
-        L.leb_nn_bound.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32] + [vp] * 8 + [ctypes.c_double, vp, vp]
+        L.leb_nn_bound.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32] + [vp] * 9 + [ctypes.c_double, vp, vp]
         L.leb_nn_bound.restype = ctypes.c_int
         L.leb_tube_map.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp,
                                    ctypes.POINTER(ctypes.c_double), vp, vp, vp, vp, vp]
         L.leb_tube_map.restype = ctypes.c_int
+        L.leb_zonotope_hull.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, vp]
+        L.leb_zonotope_hull.restype = ctypes.c_int
         L.leb_launch_timing.argtypes = [ctypes.c_int32]
         L.leb_launch_timing.restype = ctypes.c_int
         L.leb_launch_times.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_float), ctypes.c_int32,
@@ -182,12 +207,13 @@ def _stream(stream):
 
 
 def analytic_bound(dyn: Dynamics, z, v, sigma, mu=None, pad: float = 0.0, zonotope: bool = False,
-                   stream=None, out=None):
+                   jacobians: bool = False, stream=None, out=None):
     """Path-based Hessian bound for every (trajectory, timestep).
 
     z [B][N][nx], v [B][N][nu], sigma (and mu) [B][N][nx+nu]: float64 GPU
     tensors.  Returns dict with r_lo, r_hi [B][N][nx], flags [B][N] (int32
-    view of the uint32 flags) and, if zonotope, c_bar and rho_bar."""
+    view of the uint32 flags), if zonotope c_bar and rho_bar, and if
+    jacobians the point Jacobians A [B][N][nx][nx], B [B][N][nx][nu]."""
     import torch
     B, N = int(z.shape[0]), int(z.shape[1])
     f64 = torch.float64
@@ -198,13 +224,30 @@ def analytic_bound(dyn: Dynamics, z, v, sigma, mu=None, pad: float = 0.0, zonoto
         if zonotope:
             out["c_bar"] = torch.empty((B, N, dyn.nx), dtype=f64, device=z.device)
             out["rho_bar"] = torch.empty((B, N, dyn.nx), dtype=f64, device=z.device)
+        if jacobians:
+            out["A"] = torch.empty((B, N, dyn.nx, dyn.nx), dtype=f64, device=z.device)
+            out["B"] = torch.empty((B, N, dyn.nx, dyn.nu), dtype=f64, device=z.device)
     rc = lib().leb_analytic_bound(
         ctypes.byref(dyn), B, N, _dev_ptr(z, "z", f64), _dev_ptr(v, "v", f64), _dev_ptr(mu, "mu", f64),
-        _dev_ptr(sigma, "sigma", f64), _dev_ptr(out["r_lo"], "r_lo", f64), _dev_ptr(out["r_hi"], "r_hi", f64),
+        _dev_ptr(sigma, "sigma", f64), _dev_ptr(out.get("r_lo"), "r_lo", f64), _dev_ptr(out.get("r_hi"), "r_hi", f64),
         _dev_ptr(out.get("c_bar"), "c_bar", f64), _dev_ptr(out.get("rho_bar"), "rho_bar", f64),
-        float(pad), _dev_ptr(out["flags"], "flags"), _stream(stream))
+        float(pad), _dev_ptr(out.get("flags"), "flags"), _dev_ptr(out.get("A"), "A", f64),
+        _dev_ptr(out.get("B"), "B", f64), _stream(stream))
     _check(rc)
     return out
+
+
+def zonotope_hull(G, c=None, stream=None):
+    """Interval hull of zonotopes (see leb.h: leb_zonotope_hull): G [rows][n_gen],
+    c [rows] float64 GPU tensors -> (mu, sigma) [rows]."""
+    import torch
+    f64 = torch.float64
+    rows, ng = int(G.shape[0]), int(G.shape[1])
+    mu = torch.empty((rows,), dtype=f64, device=G.device)
+    sg = torch.empty((rows,), dtype=f64, device=G.device)
+    _check(lib().leb_zonotope_hull(rows, ng, _dev_ptr(G, "G", f64), _dev_ptr(c, "c", f64), _dev_ptr(mu, "mu", f64),
+                                   _dev_ptr(sg, "sigma", f64), _stream(stream)))
+    return mu, sg
 
 
 def backward(dyn: Dynamics, z, v, sigma, g_lo, g_hi, mu=None, stream=None):
@@ -315,7 +358,7 @@ def _cert_out(B, N, device):
 
 
 def fixed_point_solve(dyn: Dynamics, z, v, phi, e, tol=1e-6, max_sweeps=200, pad=0.0, inflate_abs=1e-12,
-                      mu=None, sigma=None, stream=None):
+                      mu=None, sigma=None, stream=None, conv_tol=None):
     """Certified tube/LEB fixed point (see leb.h: leb_fixed_point_solve).
 
     Warm start when mu and sigma are given (they are updated in place).
@@ -328,7 +371,7 @@ def fixed_point_solve(dyn: Dynamics, z, v, phi, e, tol=1e-6, max_sweeps=200, pad
         mu = torch.empty((B, N, n), dtype=torch.float64, device=z.device)
         sigma = torch.empty((B, N, n), dtype=torch.float64, device=z.device)
     cert = _cert_out(B, N, z.device)
-    opt = FPOptions(tol, max_sweeps, pad, inflate_abs, 1 if warm else 0)
+    opt = FPOptions(tol, max_sweeps, pad, inflate_abs, 1 if warm else 0, tol if conv_tol is None else conv_tol)
     sweeps = ctypes.c_int32(0)
     f64 = torch.float64
     rc = lib().leb_fixed_point_solve(ctypes.byref(dyn), B, N, _dev_ptr(z, "z", f64), _dev_ptr(v, "v", f64),
@@ -340,7 +383,7 @@ def fixed_point_solve(dyn: Dynamics, z, v, phi, e, tol=1e-6, max_sweeps=200, pad
 
 
 def fixed_point_learned(dyn: Dynamics, z, v, phi, e, net, sweeps=1, margin=5e-2, tol=1e-6, max_sweeps=200,
-                        pad=0.0, inflate_abs=1e-12, stream=None):
+                        pad=0.0, inflate_abs=1e-12, stream=None, conv_tol=None):
     """Certified fixed point from a learned initial tube (see leb.h:
     leb_fixed_point_learned).  Returns (mu, sigma, certified, certified sweeps)."""
     import torch
@@ -349,7 +392,7 @@ def fixed_point_learned(dyn: Dynamics, z, v, phi, e, net, sweeps=1, margin=5e-2,
     mu = torch.empty((B, N, n), dtype=torch.float64, device=z.device)
     sigma = torch.empty((B, N, n), dtype=torch.float64, device=z.device)
     cert = _cert_out(B, N, z.device)
-    opt = FPOptions(tol, max_sweeps, pad, inflate_abs, 1)
+    opt = FPOptions(tol, max_sweeps, pad, inflate_abs, 1, tol if conv_tol is None else conv_tol)
     ws = WarmStart(net.handle, int(sweeps), float(margin))
     sw = ctypes.c_int32(0)
     f64 = torch.float64
@@ -472,9 +515,10 @@ class MLP:
             pass
 
 
-def nn_bound(mlp: MLP, z, v, sigma, mu=None, pad: float = 0.0, zonotope: bool = False, stream=None):
+def nn_bound(mlp: MLP, z, v, sigma, mu=None, pad: float = 0.0, zonotope: bool = False, stream=None, J=None):
     """CROWN + Theorem 2 bound for ReLU-MLP dynamics (see leb.h: leb_nn_bound).
-    z [B][N][nx], v [B][N][nu], sigma (mu) [B][N][nx+nu] float64 GPU tensors."""
+    z [B][N][nx], v [B][N][nu], sigma (mu) [B][N][nx+nu] float64 GPU tensors;
+    J [B][N][m][nx+nu] the linearization's matrix (None: the network's Jacobian)."""
     import torch
     B, N = int(z.shape[0]), int(z.shape[1])
     f64 = torch.float64
@@ -485,7 +529,7 @@ def nn_bound(mlp: MLP, z, v, sigma, mu=None, pad: float = 0.0, zonotope: bool = 
         out["c_bar"] = torch.empty((B, N, mlp.m), dtype=f64, device=z.device)
         out["rho_bar"] = torch.empty((B, N, mlp.m), dtype=f64, device=z.device)
     rc = lib().leb_nn_bound(mlp.handle, B, N, _dev_ptr(z, "z", f64), _dev_ptr(v, "v", f64), _dev_ptr(mu, "mu", f64),
-                            _dev_ptr(sigma, "sigma", f64), _dev_ptr(out["r_lo"], "r_lo", f64),
+                            _dev_ptr(sigma, "sigma", f64), _dev_ptr(J, "J", f64), _dev_ptr(out["r_lo"], "r_lo", f64),
                             _dev_ptr(out["r_hi"], "r_hi", f64), _dev_ptr(out.get("c_bar"), "c_bar", f64),
                             _dev_ptr(out.get("rho_bar"), "rho_bar", f64), float(pad),
                             _dev_ptr(out["flags"], "flags"), _stream(stream))

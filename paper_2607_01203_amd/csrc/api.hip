@@ -24,6 +24,34 @@ int check_chain_dynamics(const leb_dynamics* dyn) {
     return LEB_OK;
 }
 
+int check_dynamics(const leb_dynamics* dyn) {
+    if (!dyn) return LEB_EINVAL;
+    switch (dyn->kind) {
+    case LEB_DYN_LINEAR:
+    case LEB_DYN_PQUAD_CHAIN: return check_chain_dynamics(dyn);
+    case LEB_DYN_QUADRATIC:
+        if (dyn->nx < 1 || dyn->nu < 0 || !dyn->coeffs || !aligned8(dyn->coeffs)) return LEB_EINVAL;
+        return dyn->nx + dyn->nu <= 64 ? LEB_OK : LEB_ENOTSUP;
+    case LEB_DYN_SINCOS: return (dyn->nx == 1 || dyn->nx == 2) && dyn->nu == 0 ? LEB_OK : LEB_EINVAL;
+    }
+    return LEB_ENOTSUP;
+}
+
+int WsFence::enter(hipStream_t s) {
+    if (armed && hipStreamWaitEvent(s, ev, 0) != hipSuccess) return LEB_EDEVICE;
+    return LEB_OK;
+}
+
+int WsFence::leave(hipStream_t s) {
+    if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        ev = nullptr;
+        return LEB_EDEVICE;
+    }
+    if (hipEventRecord(ev, s) != hipSuccess) return LEB_EDEVICE;
+    armed = true;
+    return LEB_OK;
+}
+
 }  // namespace leb
 
 using namespace leb;
@@ -31,30 +59,31 @@ using namespace leb;
 extern "C" int leb_analytic_bound(const leb_dynamics* dyn, int32_t batch, int32_t N, const double* z,
                                   const double* v, const double* mu, const double* sigma, double* r_lo,
                                   double* r_hi, double* c_bar, double* rho_bar, double pad, uint32_t* flags,
-                                  void* stream) {
-    int rc = check_chain_dynamics(dyn);
+                                  double* A, double* B, void* stream) {
+    int rc = check_dynamics(dyn);
     if (rc != LEB_OK) return rc;
     if (batch < 0 || N < 0) return LEB_EINVAL;
     if (!(pad >= 0.0) || !isfinite(pad)) return LEB_EINVAL;
-    if ((c_bar == nullptr) != (rho_bar == nullptr)) return LEB_EINVAL;
+    if ((A || B) && dyn->kind != LEB_DYN_PQUAD_CHAIN) return LEB_EINVAL;
     const int64_t units = (int64_t)batch * (int64_t)N;
     if (units == 0) return LEB_OK;
     const int64_t nx = dyn->nx, nu = dyn->nu;
     // outputs come in pairs; at least one pair
-    if (!r_lo != !r_hi || !c_bar != !rho_bar) return LEB_EINVAL;
+    if (!r_lo != !r_hi || !c_bar != !rho_bar || !A != !B) return LEB_EINVAL;
     if (nx > 0 && !r_lo && !c_bar) return LEB_EINVAL;
-    const void* ptrs[] = {z, v, mu, sigma, r_lo, r_hi, c_bar, rho_bar};
+    // every kind reads the nominal and the radii (the linear kind to validate them)
+    if ((nx > 0 && !z) || (nu > 0 && !v) || (nx + nu > 0 && !sigma)) return LEB_EINVAL;
+    const void* ptrs[] = {z, v, mu, sigma, r_lo, r_hi, c_bar, rho_bar, A, B};
     for (const void* p : ptrs)
         if (p && !aligned8(p)) return LEB_EINVAL;
     if (flags && (reinterpret_cast<uintptr_t>(flags) & 3u)) return LEB_EINVAL;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    if (dyn->kind == LEB_DYN_LINEAR) {
-        if (units * nx == 0 && !flags) return LEB_OK;
-        return launch_fill_zero(units * nx, r_lo, r_hi, c_bar, rho_bar, pad, flags, flags ? units : 0, s);
-    }
-    if (!z || !v || !sigma) return LEB_EINVAL;
     if (units * (nx + nu) > ((int64_t)1 << 46)) return LEB_EINVAL;
-    return launch_pbh_chain(dyn, units, z, v, mu, sigma, r_lo, r_hi, c_bar, rho_bar, pad, flags, s);
+    if (A && units * nx * (nx + nu) > ((int64_t)1 << 46)) return LEB_EINVAL;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (dyn->kind != LEB_DYN_PQUAD_CHAIN)
+        return launch_test_dyn(dyn, units, z, v, mu, sigma, r_lo, r_hi, c_bar, rho_bar, pad, flags, s);
+    if ((rc = launch_pbh_chain(dyn, units, z, v, mu, sigma, r_lo, r_hi, c_bar, rho_bar, pad, flags, s))) return rc;
+    return A ? launch_chain_jacobians(dyn, units, z, v, A, B, s) : LEB_OK;
 }
 
 extern "C" const char* leb_strerror(int code) {

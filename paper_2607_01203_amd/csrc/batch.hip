@@ -197,7 +197,7 @@ static int nn_run(const NNGroup& g, hipStream_t s) {
     hipLaunchKernelGGL(nn_gather_kernel, dim3(nbk(g.units * n0)), dim3(256), 0, s, g.ptrs, g.unit_prob, g.units, g.nx,
                        g.nu, g.zS, g.vS, g.muS, g.sgS);
     if (hipGetLastError() != hipSuccess) return LEB_EDEVICE;
-    int rc = nn_bound_run(g.net, g.units, g.zS, g.vS, g.muS, g.sgS, g.loS, g.hiS, nullptr, nullptr, 0.0, nullptr, g.CB,
+    int rc = nn_bound_run(g.net, g.units, g.zS, g.vS, g.muS, g.sgS, nullptr, g.loS, g.hiS, nullptr, nullptr, 0.0, nullptr, g.CB,
                           g.buf, s);
     if (rc) return rc;
     hipLaunchKernelGGL(nn_scatter_kernel, dim3(nbk(g.units * g.m)), dim3(256), 0, s, g.ptrs, g.unit_prob, g.units, g.m,

@@ -58,8 +58,6 @@ int launch_pbh_chain(const leb_dynamics* dyn, int64_t units, const double* z, co
                      double* rho_bar, double pad, uint32_t* flags, hipStream_t stream,
                      const SweepFold* fold = nullptr, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
                      bool compact = false);
-int launch_fill_zero(int64_t count, double* r_lo, double* r_hi, double* c_bar, double* rho_bar, double pad,
-                     uint32_t* flags, int64_t nflags, hipStream_t stream);
 size_t pbh_smem_bytes(int U);
 size_t bwd_smem_bytes(int U);
 int launch_tube_map(int B, int N, int U, const double* phi, const double* e, const double* cbar,
@@ -82,8 +80,8 @@ int launch_disturbance_tube(int B, int N, int U, const double* phi, const double
 constexpr int NN_NBUF = 21;
 void nn_buffer_sizes(const leb_mlp_s* net, int CB, size_t sizes[NN_NBUF]);
 int nn_bound_run(const leb_mlp_s* net, int64_t units, const double* z, const double* v, const double* mu,
-                 const double* sigma, double* r_lo, double* r_hi, double* c_bar, double* rho_bar, double pad,
-                 uint32_t* flags, int CB, double* const* buf, hipStream_t st);
+                 const double* sigma, const double* J, double* r_lo, double* r_hi, double* c_bar, double* rho_bar,
+                 double pad, uint32_t* flags, int CB, double* const* buf, hipStream_t st);
 void nn_dims(const leb_mlp_s* net, int* nx, int* nu, int* m);
 
 // one surrogate sweep over a chain tube (features -> BF16 MLP -> residual zonotope,
@@ -96,6 +94,34 @@ int surrogate_chain_sweep(leb_surrogate s, const double* z, const double* v, con
 
 // argument checks shared by the entry points
 bool aligned8(const void* p);
-int check_chain_dynamics(const leb_dynamics* dyn);
+int check_chain_dynamics(const leb_dynamics* dyn);     // CHAIN or LINEAR
+int check_dynamics(const leb_dynamics* dyn);           // any kind of leb_dyn_kind
+
+// Device-side order of the calls that share a library-owned workspace.  The
+// host mutex of the workspace orders the host side only; its kernels may
+// still be queued when the next call, on another stream, starts.  Each call
+// therefore makes its stream wait for the event that the previous call
+// recorded after its last launch (enter), and records its own (leave).
+// Both run under the workspace's mutex.
+struct WsFence {
+    hipEvent_t ev = nullptr;
+    bool armed = false;
+    int enter(hipStream_t s);
+    int leave(hipStream_t s);
+};
+// leave() on scope exit, for calls with several return paths after their first launch
+struct WsFenceScope {
+    WsFence& f;
+    hipStream_t s;
+    ~WsFenceScope() { (void)f.leave(s); }
+};
+
+// closed-form test dynamics (LINEAR, QUADRATIC, SINCOS): one thread per unit
+int launch_test_dyn(const leb_dynamics* dyn, int64_t units, const double* z, const double* v, const double* mu,
+                    const double* sigma, double* r_lo, double* r_hi, double* c_bar, double* rho_bar, double pad,
+                    uint32_t* flags, hipStream_t s);
+// point Jacobians A [units][nx][nx], B [units][nx][nu] of chain dynamics at the nominal
+int launch_chain_jacobians(const leb_dynamics* dyn, int64_t units, const double* z, const double* v, double* A,
+                           double* B, hipStream_t s);
 
 }  // namespace leb

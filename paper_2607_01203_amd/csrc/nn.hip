@@ -437,6 +437,7 @@ struct Thm2Args {
     const double* alpha; const double* c; const double* rho;   // [box][n0]
     const double* g; const double* eg;        // [box][m]
     const uint32_t* flags;       // [box]
+    const double* Juser;         // NULL, or the caller's J [unit][m][n0] (replaces mode 2)
     int m, n0, nbox;
     int64_t u0;
     double* r_lo; double* r_hi; double* c_bar; double* rho_bar; double pad;
@@ -449,7 +450,8 @@ __global__ void __launch_bounds__(64) nn_thm2_kernel(Thm2Args A) {
     const size_t sz = (size_t)A.nbox * A.m;
     const double* Lu = A.L0 + ((size_t)0 * sz + (size_t)box * A.m + i) * A.n0;
     const double* Ll = A.L0 + ((size_t)1 * sz + (size_t)box * A.m + i) * A.n0;
-    const double* J = A.L0 + ((size_t)2 * sz + (size_t)box * A.m + i) * A.n0;
+    const double* J = A.Juser ? A.Juser + ((size_t)(A.u0 + box) * A.m + i) * A.n0
+                              : A.L0 + ((size_t)2 * sz + (size_t)box * A.m + i) * A.n0;
     const double* al = A.alpha + (size_t)box * A.n0;
     const double* c = A.c + (size_t)box * A.n0;
     const double* rho = A.rho + (size_t)box * A.n0;
@@ -472,12 +474,20 @@ __global__ void __launch_bounds__(64) nn_thm2_kernel(Thm2Args A) {
     const double common = ab + mu_ + ml + fabs(ja) + fabs(g);
     hi += RT * (A.eps[ou] + common + fabs(bu) + fabs(hi)) + A.eg[ou];
     lo -= RT * (A.eps[ol] + common + fabs(bl) + fabs(lo)) + A.eg[ou];
-    // 0 = r(a~) lies in every valid bound
+    // 0 = r(a~) lies in every valid bound (for any J)
     hi = fmax(hi, 0.0);
     lo = fmin(lo, 0.0);
-    const uint32_t f = A.flags[box];
-    // no unstable neuron: g is affine on the box, so the remainder is exactly 0
-    if (!(f & NN_UNSTABLE)) { lo = 0.0; hi = 0.0; }
+    uint32_t f = A.flags[box];
+    // no unstable neuron: g is affine on the box and equal to its linearization
+    // with the computed Jacobian, so that remainder is exactly 0
+    if (!(f & NN_UNSTABLE) && !A.Juser) { lo = 0.0; hi = 0.0; }
+    // a caller's J with a non-finite entry in this row: the whole unit is invalid
+    if (A.Juser) {
+        const double* Jb = A.Juser + (size_t)(A.u0 + box) * A.m * A.n0;
+        bool bad = false;
+        for (int q = 0; q < A.m * A.n0; ++q) bad |= !isfinite(Jb[q]);
+        if (bad) f |= LEB_FLAG_BAD_INPUT;
+    }
     if (f & LEB_FLAG_BAD_INPUT) { lo = -INFINITY; hi = INFINITY; }
     const int64_t o = (A.u0 + box) * A.m + i;
     A.r_lo[o] = lo;
@@ -501,6 +511,7 @@ struct NNWorkspace {
     std::mutex mu;
     std::vector<void*> bufs;
     std::vector<size_t> sizes;
+    WsFence fence;
 };
 static NNWorkspace g_nnws;
 
@@ -635,8 +646,8 @@ void nn_buffer_sizes(const leb_mlp_s* net, int CB, size_t sizes[NN_NBUF]) {
 // The bound of `units` boxes in chunks of CB, with caller-provided work
 // buffers (nn_buffer_sizes); only kernels are enqueued on st.
 int nn_bound_run(const leb_mlp_s* net, int64_t units, const double* z, const double* v, const double* mu,
-                 const double* sigma, double* r_lo, double* r_hi, double* c_bar, double* rho_bar, double pad,
-                 uint32_t* flags, int CB, double* const* buf, hipStream_t st) {
+                 const double* sigma, const double* J, double* r_lo, double* r_hi, double* c_bar, double* rho_bar,
+                 double pad, uint32_t* flags, int CB, double* const* buf, hipStream_t st) {
     const int L = net->L, n0 = net->w[0], m = net->w[L];
     int rc;
     double *alpha = buf[0], *c = buf[1], *rho = buf[2], *zhat = buf[3], *lo = buf[4], *hi = buf[5], *g = buf[6],
@@ -711,10 +722,11 @@ int nn_bound_run(const leb_mlp_s* net, int64_t units, const double* z, const dou
             if ((rc = relax(k - 1))) return rc;
         }
         double *L0, *bt, *ep;
-        if ((rc = chain(L, 3, &L0, &bt, &ep))) return rc;
+        // the Jacobian chain (mode 2) only when the caller gives no J
+        if ((rc = chain(L, J ? 2 : 3, &L0, &bt, &ep))) return rc;
         Thm2Args ta;
         ta.L0 = L0; ta.beta = bt; ta.eps = ep; ta.alpha = alpha; ta.c = c; ta.rho = rho; ta.g = g; ta.eg = eg;
-        ta.flags = fl; ta.m = m; ta.n0 = n0; ta.nbox = CB; ta.u0 = u0;
+        ta.flags = fl; ta.Juser = J; ta.m = m; ta.n0 = n0; ta.nbox = CB; ta.u0 = u0;
         ta.r_lo = r_lo; ta.r_hi = r_hi; ta.c_bar = c_bar; ta.rho_bar = rho_bar; ta.pad = pad; ta.flags_out = flags;
         hipLaunchKernelGGL(nn_thm2_kernel, dim3(nb), dim3(64), 0, st, ta);
         if (hipGetLastError() != hipSuccess) return LEB_EDEVICE;
@@ -725,15 +737,15 @@ int nn_bound_run(const leb_mlp_s* net, int64_t units, const double* z, const dou
 }  // namespace leb
 
 extern "C" int leb_nn_bound(leb_mlp net, int32_t batch, int32_t N, const double* z, const double* v, const double* mu,
-                            const double* sigma, double* r_lo, double* r_hi, double* c_bar, double* rho_bar, double pad,
-                            uint32_t* flags, void* stream) {
+                            const double* sigma, const double* J, double* r_lo, double* r_hi, double* c_bar,
+                            double* rho_bar, double pad, uint32_t* flags, void* stream) {
     if (!net) return LEB_EINVAL;
     if (batch < 0 || N < 0 || !(pad >= 0.0) || !isfinite(pad)) return LEB_EINVAL;
     if ((c_bar == nullptr) != (rho_bar == nullptr)) return LEB_EINVAL;
     const int64_t units = (int64_t)batch * N;
     if (units == 0) return LEB_OK;
     if (!z || !sigma || !r_lo || !r_hi || (net->nu > 0 && !v) || (net->nx > 0 && !z)) return LEB_EINVAL;
-    const void* ptrs[] = {z, v, mu, sigma, r_lo, r_hi, c_bar, rho_bar};
+    const void* ptrs[] = {z, v, mu, sigma, J, r_lo, r_hi, c_bar, rho_bar};
     for (const void* p : ptrs)
         if (p && !aligned8(p)) return LEB_EINVAL;
     hipStream_t st = (hipStream_t)stream;
@@ -746,5 +758,7 @@ extern "C" int leb_nn_bound(leb_mlp net, int32_t batch, int32_t N, const double*
     int rc;
     for (int q = 0; q < NN_NBUF; ++q)
         if ((rc = nn_ws(q, sizes[q], &buf[q]))) return rc;
-    return nn_bound_run(net, units, z, v, mu, sigma, r_lo, r_hi, c_bar, rho_bar, pad, flags, CB, buf, st);
+    if ((rc = g_nnws.fence.enter(st))) return rc;
+    WsFenceScope leave{g_nnws.fence, st};
+    return nn_bound_run(net, units, z, v, mu, sigma, J, r_lo, r_hi, c_bar, rho_bar, pad, flags, CB, buf, st);
 }

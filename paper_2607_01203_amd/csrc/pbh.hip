@@ -196,17 +196,6 @@ __global__ void __launch_bounds__(PBH_BLOCK) pbh_chain_fwd(ChainArgs A) {
     node_pass(A, t0, d0, lt, i, s_sp, s_flag);
 }
 
-__global__ void fill_zero_kernel(double* a, double* b, double* c, double* d, double pad, uint32_t* flags,
-                                 int64_t count, int64_t nflags) {
-    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t k = idx; k < count; k += stride) {
-        if (a) { a[k] = 0.0; b[k] = 0.0; }
-        if (c) { c[k] = 0.0; d[k] = pad; }
-    }
-    if (flags)
-        for (int64_t k = idx; k < nflags; k += stride) flags[k] = 0u;
-}
 
 size_t pbh_smem_bytes_T(int U, int T) {
     return (size_t)T * U * sizeof(SpringOut) + (size_t)T * sizeof(uint32_t) + 16;
@@ -255,14 +244,5 @@ int launch_pbh_tiles(const leb_dynamics* dyn, const PbhTile* tiles, int n_tiles,
     return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
 }
 
-int launch_fill_zero(int64_t count, double* r_lo, double* r_hi, double* c_bar, double* rho_bar, double pad,
-                     uint32_t* flags, int64_t nflags, hipStream_t stream) {
-    int64_t blocks = (count + 255) / 256;
-    if (blocks < 1) blocks = 1;
-    if (blocks > 65535) blocks = 65535;
-    hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, r_lo, r_hi, c_bar,
-                       rho_bar, pad, flags, count, nflags);
-    return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
-}
 
 }  // namespace leb

@@ -138,6 +138,7 @@ struct SurWorkspace {
     int64_t cap_nx = 0, cap_ny = 0;             // floats
     double* dist = nullptr;                     // one trajectory's disturbance-only tube (mu, sigma)
     int64_t cap_dist = 0;                       // doubles
+    WsFence fence;
 };
 static SurWorkspace g_sw;
 
@@ -270,6 +271,8 @@ extern "C" int leb_nn_surrogate_bound(leb_surrogate net, int32_t nx, int32_t nu,
     int rc;
     if ((rc = grow_f32(&g_sw.nX, &g_sw.cap_nx, units * din)) || (rc = grow_f32(&g_sw.nY, &g_sw.cap_ny, units * dout)))
         return rc;
+    if ((rc = g_sw.fence.enter(s))) return rc;
+    WsFenceScope leave{g_sw.fence, s};
     if ((rc = leb_nn_features(nx, nu, batch, N, z, v, mu, sigma, g_sw.nX, stream))) return rc;
     if ((rc = leb_mlp_fwd_bf16(net, (int32_t)units, g_sw.nX, g_sw.nY, stream))) return rc;
     hipLaunchKernelGGL(nn_decode_kernel, dim3(nbk(units * m)), dim3(256), 0, s, g_sw.nY, units, m, r_lo, r_hi);
@@ -303,6 +306,8 @@ extern "C" int leb_fixed_point_learned(const leb_dynamics* dyn, int32_t batch, i
     {
         std::lock_guard<std::mutex> lock(g_sw.mu);
         if ((rc = sw_get(nodes, units * nx))) return rc;
+        if ((rc = g_sw.fence.enter(s))) return rc;
+        WsFenceScope leave{g_sw.fence, s};
         // C_0: the disturbance-only tube (centre 0).  It is the same for every
         // trajectory, so the first surrogate sweep reads one trajectory's copy;
         // without surrogate sweeps it is written out whole and inflated below.

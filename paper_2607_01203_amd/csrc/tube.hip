@@ -47,6 +47,7 @@ struct TubeFP {
     double tol, abs_;     // C_t = (mu_F, sigma_F (1 + tol) + abs_)
     uint32_t* cert;       // NULL, or [B]: written (state & FP_CERT) by a launch that finds every
                           // trajectory certified (the sweep enqueued after the last one)
+    double conv;          // acceptance also needs |C_t - C_{t-1}| within conv (relative to sigma)
 };
 
 struct TubeArgs {
@@ -515,9 +516,14 @@ __global__ void __launch_bounds__(256) tube_map2_kernel(const double* __restrict
             if (FP) {
                 // [mF - sF, mF + sF] inside [mi - si, mi + si], with the rounding of the
                 // test covered; a tube that is not finite is never accepted
-                if (!frozen && !(sF <= DBL_MAX && (fabs(mF - mi[p][i]) + sF) * (1.0 + 0x1p-50) <= si[p][i]))
-                    sbad[(c0 + lr) / U - bfirst] = 1u;
                 so = sF + sF * P.tol + P.abs_;
+                const double dm = fabs(mF - mi[p][i]);
+                const bool contained = sF <= DBL_MAX && (dm + sF) * (1.0 + 0x1p-50) <= si[p][i];
+                // converged: the next iterate within conv of this one (the slack 2^-44 si
+                // absorbs the rounding of the sums, far below any conv in use)
+                const double slack = P.conv * si[p][i] + 0x1p-44 * si[p][i];
+                const bool conv = fabs(so - si[p][i]) <= slack + 2.0 * P.abs_ && dm <= slack + P.abs_;
+                if (!frozen && !(contained && conv)) sbad[(c0 + lr) / U - bfirst] = 1u;
             }
             if (!frozen) {
                 const int64_t o = tube_off(rr, k);
@@ -742,6 +748,7 @@ struct Workspace {
     std::vector<size_t> sizes;
     uint32_t* host_open = nullptr;      // pinned, host-mapped
     uint32_t* host_open_dev = nullptr;
+    WsFence fence;
 };
 static Workspace g_ws;
 
@@ -843,7 +850,8 @@ namespace leb {
 int fp_check_args(const leb_fp_options* opt, const double* e, int N) {
     if (!opt || !e) return LEB_EINVAL;
     if (!(opt->tol >= 0.0) || !isfinite(opt->tol) || opt->max_sweeps < 1 || !(opt->pad >= 0.0) ||
-        !(opt->inflate_abs > 0.0) || !isfinite(opt->inflate_abs))
+        !(opt->inflate_abs > 0.0) || !isfinite(opt->inflate_abs) || !(opt->conv_tol >= opt->tol) ||
+        !isfinite(opt->conv_tol) || !isfinite(opt->pad))
         return LEB_EINVAL;
     for (int q = 0; q < 6; ++q)
         if (!(e[q] >= 0.0) || !isfinite(e[q])) return LEB_EINVAL;
@@ -882,6 +890,8 @@ extern "C" int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int
         (rc = ws_get(2, bn, (void**)&xm1)) || (rc = ws_get(3, bn, (void**)&xs1)) ||
         (rc = ws_get(4, 2 * ((size_t)batch + 1) * sizeof(uint32_t), (void**)&state)) || (rc = ws_host()))
         return rc;
+    if ((rc = g_ws.fence.enter(s))) return rc;
+    WsFenceScope leave{g_ws.fence, s};
     // iterates: buffer 0 = the caller's (mu, sigma), buffer 1 = workspace; sweep t reads C_{t-1}
     // from buffer (t-1) & 1 and writes C_t to buffer t & 1
     double* xm[2] = {mu, xm1};
@@ -907,7 +917,7 @@ extern "C" int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int
         int r = launch_pbh_chain(dyn, units, z, v, xm[a], xs[a], nullptr, nullptr, cb, rb, opt->pad, nullptr, s,
                                  &fold, b0, b1, true);
         if (r) return r;
-        const TubeFP fp{xm[a], xs[a], st[w], opt->tol, opt->inflate_abs, certified};
+        const TubeFP fp{xm[a], xs[a], st[w], opt->tol, opt->inflate_abs, certified, opt->conv_tol};
         return launch_tube2(batch, N, U, phi, e, opt->pad, cb, rb, xm[w], xs[w], fp, s, 1.0, 0.0, t0, t1);
     };
     // Wait until the open count of sweep t is published: the bound launch of

@@ -15,7 +15,7 @@ import math
 import numpy as np
 
 from . import (CHAIN_FEATURES, CHAIN_OUTPUTS, MLP, Dynamics, Surrogate, analytic_bound, chain_features,
-               chain_targets, nn_bound, nn_features, nn_targets)
+               chain_targets, nn_bound, nn_features, nn_targets, tube_map)
 
 CHAIN_WIDTHS = [CHAIN_FEATURES, 128, 128, 128, CHAIN_OUTPUTS]
 
@@ -61,6 +61,26 @@ def chain_samples(dyn: Dynamics, z, v, mu_star, sigma_star, draws, seed, scale=(
         ts.append(chain_targets(dyn, out["r_lo"], out["r_hi"]).reshape(-1, CHAIN_OUTPUTS))
     X = torch.cat(xs)
     T = torch.cat(ts)
+    perm = torch.from_numpy(rng.permutation(X.shape[0])).to(z.device)
+    return X.index_select(0, perm).contiguous(), T.index_select(0, perm).contiguous()
+
+
+def chain_fp_samples(dyn: Dynamics, z, v, phi, e, mu_star, sigma_star, seed):
+    """Fixed-point-target samples: the features of the disturbance-only tube
+    (the cold start, the same for every trajectory) paired with the targets
+    of the certified bound at the fixed point (mu_star, sigma_star), so that
+    one surrogate sweep from the cold start predicts the fixed point's
+    residuals instead of one step of the iteration.  z, v, phi: float64 GPU
+    tensors; mu_star, sigma_star: GPU tensors [B][N][n].  Returns (X, T)
+    float32 GPU tensors, B * N * n_units rows in a seeded random order."""
+    import torch
+    B, N = int(z.shape[0]), int(z.shape[1])
+    zero = torch.zeros((B, N, dyn.nx), dtype=torch.float64, device=z.device)
+    md, sd = tube_map(dyn.n_units, phi, e, zero, zero)
+    X = chain_features(dyn, z, v, sd, md).reshape(-1, CHAIN_FEATURES)
+    out = analytic_bound(dyn, z, v, sigma_star, mu_star)
+    T = chain_targets(dyn, out["r_lo"], out["r_hi"]).reshape(-1, CHAIN_OUTPUTS)
+    rng = np.random.default_rng(seed)
     perm = torch.from_numpy(rng.permutation(X.shape[0])).to(z.device)
     return X.index_select(0, perm).contiguous(), T.index_select(0, perm).contiguous()
 

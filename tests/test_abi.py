@@ -46,10 +46,11 @@ def test_strerror_and_version(L):
     assert L.leb_version().startswith(b"leb-mi355x")
 
 
-def _call(L, dyn, batch=1, N=1, z=8, v=8, mu=None, sigma=8, lo=8, hi=8, cb=None, rb=None, pad=0.0, flags=None):
+def _call(L, dyn, batch=1, N=1, z=8, v=8, mu=None, sigma=8, lo=8, hi=8, cb=None, rb=None, pad=0.0, flags=None,
+          A=None, B=None):
     vp = lambda x: None if x is None else ctypes.c_void_p(x)
     return L.leb_analytic_bound(None if dyn is None else ctypes.byref(dyn), batch, N, vp(z), vp(v), vp(mu),
-                                vp(sigma), vp(lo), vp(hi), vp(cb), vp(rb), pad, vp(flags), None)
+                                vp(sigma), vp(lo), vp(hi), vp(cb), vp(rb), pad, vp(flags), vp(A), vp(B), None)
 
 
 def test_rejects_bad_arguments_without_launching(L):
@@ -78,6 +79,47 @@ def test_rejects_bad_arguments_without_launching(L):
     bad = leb.chain_dynamics(2)
     bad.kind = 17
     assert _call(L, bad) == -4
+    assert _call(L, d, A=8) == -1                    # A without B
+    assert _call(L, d, A=8, B=12) == -1              # misaligned B
+
+
+def test_test_kinds_reject_bad_arguments_without_launching(L):
+    import paper_2607_01203_amd as leb
+    lin = leb.linear_dynamics(3, 1)
+    assert _call(L, lin, sigma=None) == -1           # the linear kind validates its data too
+    assert _call(L, lin, z=None) == -1
+    assert _call(L, lin, A=8, B=8) == -1             # Jacobians: chain dynamics only
+    q = leb.Dynamics(leb.DYN_QUADRATIC, 3, 1, 0, 0, 0, 0, 0, 0, 0, 0, None)
+    assert _call(L, q) == -1                         # no Q
+    q.coeffs = 12
+    assert _call(L, q) == -1                         # misaligned Q
+    q.coeffs = 8
+    q.nx, q.nu = 60, 8
+    assert _call(L, q) == -4                         # n > 64
+    s = leb.sincos_dynamics(2)
+    s.nu = 1
+    assert _call(L, s) == -1
+    s = leb.sincos_dynamics(3)
+    assert _call(L, s) == -1
+    assert _call(L, leb.sincos_dynamics(1), batch=0, z=None, v=None, sigma=None, lo=None, hi=None) == 0
+
+
+def test_zonotope_hull_rejects_bad_arguments_without_launching(L):
+    vp = ctypes.c_void_p
+    assert L.leb_zonotope_hull(-1, 3, vp(8), None, vp(8), vp(8), None) == -1
+    assert L.leb_zonotope_hull(2, -1, vp(8), None, vp(8), vp(8), None) == -1
+    assert L.leb_zonotope_hull(2, 3, None, None, vp(8), vp(8), None) == -1     # no G
+    assert L.leb_zonotope_hull(2, 3, vp(8), None, None, vp(8), None) == -1     # no mu
+    assert L.leb_zonotope_hull(2, 3, vp(12), None, vp(8), vp(8), None) == -1   # misaligned
+    assert L.leb_zonotope_hull(0, 3, None, None, None, None, None) == 0
+
+
+def test_nn_bound_rejects_misaligned_jacobian_without_launching(L):
+    vp = ctypes.c_void_p
+    # leb_nn_bound(net, batch, N, z, v, mu, sigma, J, r_lo, r_hi, c_bar, rho_bar, pad, flags, stream):
+    # a NULL network is refused first
+    assert L.leb_nn_bound(None, 1, 1, vp(8), vp(8), None, vp(8), vp(12), vp(8), vp(8), None, None, 0.0, None,
+                          None) == -1
 
 
 def test_empty_problem_is_ok_without_launching(L):
@@ -127,9 +169,9 @@ def test_fixed_point_rejects_bad_options_without_launching(L):
     vp = ctypes.c_void_p(8)
 
     def call(**kw):
-        o = dict(tol=1e-6, max_sweeps=10, pad=0.0, inflate_abs=1e-12, warm=0)
+        o = dict(tol=1e-6, max_sweeps=10, pad=0.0, inflate_abs=1e-12, warm=0, conv_tol=1e-6)
         o.update(kw)
-        opt = leb.FPOptions(o["tol"], o["max_sweeps"], o["pad"], o["inflate_abs"], o["warm"])
+        opt = leb.FPOptions(o["tol"], o["max_sweeps"], o["pad"], o["inflate_abs"], o["warm"], o["conv_tol"])
         return L.leb_fixed_point_solve(ctypes.byref(d), 4, 3, vp, vp, vp, e, ctypes.byref(opt), vp, vp, vp,
                                        ctypes.byref(sw), None)
 
@@ -138,8 +180,10 @@ def test_fixed_point_rejects_bad_options_without_launching(L):
     assert call(max_sweeps=0) == -1
     assert call(inflate_abs=0.0) == -1
     assert call(pad=-1.0) == -1
+    assert call(conv_tol=1e-7) == -1          # convergence tolerance below the inflation
+    assert call(conv_tol=float("nan")) == -1
     # a horizon beyond what the compact tube map keeps in LDS: LEB_ENOTSUP (-4)
-    opt = leb.FPOptions(1e-6, 10, 0.0, 1e-12, 0)
+    opt = leb.FPOptions(1e-6, 10, 0.0, 1e-12, 0, 1e-6)
     assert L.leb_fixed_point_solve(ctypes.byref(d), 4, 211, vp, vp, vp, e, ctypes.byref(opt), vp, vp, vp,
                                    ctypes.byref(sw), None) == -4
     # the learned form checks the same options before its surrogate sweeps (the
@@ -147,18 +191,19 @@ def test_fixed_point_rejects_bad_options_without_launching(L):
     ws = leb.WarmStart(ctypes.c_void_p(8), 1, 0.05)
 
     def learned(N=3, **kw):
-        o = dict(tol=1e-6, max_sweeps=10, pad=0.0, inflate_abs=1e-12, warm=0)
+        o = dict(tol=1e-6, max_sweeps=10, pad=0.0, inflate_abs=1e-12, warm=0, conv_tol=1e-6)
         o.update(kw)
-        opt = leb.FPOptions(o["tol"], o["max_sweeps"], o["pad"], o["inflate_abs"], o["warm"])
+        opt = leb.FPOptions(o["tol"], o["max_sweeps"], o["pad"], o["inflate_abs"], o["warm"], o["conv_tol"])
         return L.leb_fixed_point_learned(ctypes.byref(d), 4, N, vp, vp, vp, e, ctypes.byref(opt), ctypes.byref(ws),
                                          vp, vp, vp, ctypes.byref(sw), None)
 
     assert learned(tol=-1.0) == -1
     assert learned(max_sweeps=0) == -1
     assert learned(inflate_abs=0.0) == -1
+    assert learned(conv_tol=0.0) == -1
     assert learned(N=211) == -4
     # zero work: accepted without a launch
-    opt = leb.FPOptions(1e-6, 10, 0.0, 1e-12, 0)
+    opt = leb.FPOptions(1e-6, 10, 0.0, 1e-12, 0, 1e-6)
     assert L.leb_fixed_point_solve(ctypes.byref(d), 0, 3, None, None, None, e, ctypes.byref(opt), None, None, None,
                                    ctypes.byref(sw), None) == 0
     assert sw.value == 0

@@ -162,9 +162,11 @@ def test_fixed_point_certificate_holds(gpu, orc):
 
 
 def test_fixed_point_warm_start_from_above(gpu, orc):
-    """A warm start 1% above the certified tube is certified within two
-    sweeps (the oracle's iteration takes one on this case), stays above the
-    least fixed point, and is no wider than the tube passed in."""
+    """A warm start 1% above the certified tube is a post-fixed point, so
+    every iterate is certified; the solve keeps sweeping until the iterates
+    converge (conv_tol), ending within the parity tolerance of the least
+    fixed point like the cold start, never below it, no wider than the tube
+    passed in, and in no more sweeps than the cold start."""
     import torch
     import paper_2607_01203_amd as leb
     tp = W.fixed_point_cfg(seed=48, batch=4, N=14, n_units=4)
@@ -178,15 +180,10 @@ def test_fixed_point_warm_start_from_above(gpu, orc):
                                                  mu=_t(mu, gpu), sigma=_t(s_in, gpu))
     torch.cuda.synchronize()
     mu2, sg2 = mu2.cpu().numpy(), sg2.cpu().numpy()
-    assert (cert2.cpu().numpy() == 1).all() and 1 <= sw2 <= 2, sw2
-    if sw2 == 1:
-        assert np.array_equal(sg2, s_in) and np.array_equal(mu2, mu)
+    print("sweeps: cold %d, warm from above %d" % (sweeps, sw2))
+    assert (cert2.cpu().numpy() == 1).all() and 2 <= sw2 <= sweeps, (sw2, sweeps)
     assert (sg2 <= s_in * (1 + 1e-6) + 1e-11).all()
-    from oracle import tube
-    d = orc.Dyn.like(b.dyn)
-    mo, so, _, _ = tube.fixed_point(d, b.z, b.v, tp.phi, tp.e)
-    assert (sg2 >= so * (1 - 1e-12)).all() and (sg2 <= so * 1.011 + 1e-11).all()
-    assert (np.abs(mu2 - mo) <= 1e-2 * np.maximum(so, 1e-12)).all()
+    _check_against_oracle(orc, tp, mu2, sg2, np.arange(4))
 
 
 def test_fixed_point_warm_start_from_below(gpu, orc):
@@ -207,10 +204,11 @@ def test_fixed_point_warm_start_from_below(gpu, orc):
 
 
 def test_fixed_point_trajectories_certified_at_different_sweeps(gpu, orc):
-    """Half the batch starts from a certified tube (certified by the first
-    sweep, returned unchanged), half from a zero tube (certified several
-    sweeps later); 5 x 7 nodes = 35 columns per trajectory, so columns of
-    one trajectory straddle waves."""
+    """Half the batch starts from the accepted tube of a cold solve
+    (certified and converged, so accepted by the first sweep and returned
+    unchanged), half from a zero tube (accepted several sweeps later);
+    5 x 7 nodes = 35 columns per trajectory, so columns of one trajectory
+    straddle waves."""
     import torch
     import paper_2607_01203_amd as leb
     tp = W.fixed_point_cfg(seed=49, batch=6, N=13, n_units=7)
@@ -220,7 +218,7 @@ def test_fixed_point_trajectories_certified_at_different_sweeps(gpu, orc):
     b = tp.batch
     dyn = leb.dynamics_like(b.dyn)
     m_in = mu.copy()
-    s_in = sg * (1 + 1e-2)
+    s_in = sg.copy()
     m_in[1::2] = 0.0
     s_in[1::2] = 0.0
     mu2, sg2, cert2, sw2 = leb.fixed_point_solve(dyn, _t(b.z, gpu), _t(b.v, gpu), _t(tp.phi, gpu), tp.e,

@@ -183,3 +183,46 @@ def test_sampled_containment_nn():
     pts = W.sample_box_points(W.rng_for(1_000_001), c - rho, c + rho, 3000)
     r, eps = nn.remainder(b.net.W, b.net.b, a, pts)
     assert ((r > o["r_hi"][:, None] + eps) | (r < o["r_lo"][:, None] - eps)).sum() == 0
+
+
+def test_given_jacobian_equals_computed_and_encloses_its_remainder():
+    """Theorem 2 holds for any J.  Passing the network's own Jacobian gives
+    the default bound; a perturbed J gives a bound that contains 0 and every
+    sampled remainder g(a) - g(a~) - J (a - a~), and whose centred form
+    (independent of J's choice of split) agrees with the direct form."""
+    rng = np.random.default_rng(11)
+    Ws, bs = _net(rng, [6, 16, 16, 3])
+    a0 = rng.uniform(-1, 1, (4, 6))
+    sg = rng.uniform(0.05, 0.2, (4, 6))
+    o = nn.leb(Ws, bs, a0, sg)
+    o2 = nn.leb(Ws, bs, a0, sg, J=o["J"])
+    assert np.array_equal(o["r_lo"], o2["r_lo"]) and np.array_equal(o["r_hi"], o2["r_hi"])
+    Jp = o["J"] + rng.normal(0, 0.3, o["J"].shape)
+    oj = nn.leb(Ws, bs, a0, sg, J=Jp)
+    assert (oj["r_lo"] <= 0).all() and (oj["r_hi"] >= 0).all()
+    M = np.maximum(np.abs(oj["r_hi"]), np.abs(oj["r_lo"]))
+    assert np.allclose(oj["c_hi"], oj["r_hi"], rtol=0, atol=1e-12 * M.max())
+    assert np.allclose(oj["c_lo"], oj["r_lo"], rtol=0, atol=1e-12 * M.max())
+    lo, hi = a0 - sg, a0 + sg
+    pts = W.sample_box_points(rng, lo, hi, 4000)
+    r, eps = nn.remainder(Ws, bs, a0, pts, J=Jp)
+    assert (r <= oj["r_hi"][:, None, :] + eps).all() and (r >= oj["r_lo"][:, None, :] - eps).all()
+    # the perturbed J's bound is wider: the linear part it misses is J_true - J
+    assert (oj["r_hi"] - oj["r_lo"] > o["r_hi"] - o["r_lo"]).all()
+
+
+def test_given_jacobian_stable_box_closed_form():
+    """On a box with no unstable neuron g is affine with slope J*, so the
+    remainder with any J is (J* - J)(a - a~) exactly, whose range over the
+    symmetric box is +-|J* - J| rho: Theorem 2 must give exactly that."""
+    b = W.nn_cfg()
+    a = np.concatenate([b.z, b.v], -1)[0, :3]
+    sg = np.full((3, 16), 1e-7)
+    o = nn.leb(b.net.W, b.net.b, a, sg)
+    assert o["unstable"] == [0, 0, 0]
+    rng = np.random.default_rng(3)
+    Jp = o["J"] + rng.normal(0, 0.1, o["J"].shape)
+    oj = nn.leb(b.net.W, b.net.b, a, sg, J=Jp)
+    exp = np.einsum("bmn,n->bm", np.abs(o["J"] - Jp), np.full(16, 1e-7))
+    assert np.allclose(oj["r_hi"], exp, rtol=1e-9, atol=1e-15)
+    assert np.allclose(oj["r_lo"], -exp, rtol=1e-9, atol=1e-15)

@@ -139,3 +139,26 @@ def test_uniform_inflation_fails_when_bounds_dominate(orc):
     c_, r_ = tube.zono(l_, h_)
     m3, s3 = tube.tube_map(tp.phi, tp.e, c_, r_)
     assert not tube.contains(mu, sgs, m3, s3).any()
+
+
+def test_zonotope_hull_is_vertex_maximum():
+    """The hull radius of a zonotope row is max over the generator box of
+    |G_i xi|, attained at a vertex: brute force over all 2^n vertices."""
+    import itertools
+    from oracle import tube
+    rng = np.random.default_rng(5)
+    G = rng.normal(size=(7, 9)) * rng.uniform(0, 2, (7, 1))
+    G[3, :] = 0.0
+    c = rng.normal(size=7)
+    mu, sg = tube.zonotope_hull(G, c)
+    V = np.array(list(itertools.product([-1.0, 1.0], repeat=9)))
+    vals = V @ G.T                                  # [2^9][7]
+    assert np.array_equal(mu, c)
+    assert np.allclose(sg, np.abs(vals).max(0), rtol=1e-15, atol=0)
+    assert sg[3] == 0.0
+    # the tube width of the tube map is this hull of Phi_kj [E diag(rho_bar_j)]
+    E = np.diag(rng.uniform(0, 1, 9))
+    rb = rng.uniform(0, 1, 9)
+    P = rng.normal(size=(5, 9))
+    _, s1 = tube.zonotope_hull(np.concatenate([P @ E, P @ np.diag(rb)], 1))
+    assert np.allclose(s1, np.abs(P) @ (np.diag(E) + rb), rtol=1e-14)
