@@ -39,7 +39,8 @@ typedef enum {
     LEB_EINVAL = -1,     /* bad argument (shape, null pointer, parameter range) */
     LEB_ENOMEM = -2,     /* device allocation failed */
     LEB_EDEVICE = -3,    /* HIP runtime error on launch */
-    LEB_ENOTSUP = -4     /* dynamics kind or size not supported */
+    LEB_ENOTSUP = -4,    /* dynamics kind or size not supported */
+    LEB_ESCRATCH = -5    /* the problem does not fit the fixed scratch of a no-allocation entry point */
 } leb_status;
 
 /* per-unit flags (uint32, OR of): */
@@ -258,6 +259,31 @@ typedef struct {
 int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int32_t N, const double* z,
                           const double* v, const double* phi, const double* e, const leb_fp_options* opt,
                           double* mu, double* sigma, uint32_t* certified, int32_t* sweeps_out, void* stream);
+
+/*
+ * leb_fixed_point_solve_noalloc -- leb_fixed_point_solve for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): same arguments, same kernels and
+ * bitwise the same mu, sigma and certified flags.  It calls no hipMalloc,
+ * hipFree or other allocating routine and never reads back from the device:
+ *   - its workspace is a library-owned static device array of 64 MiB, one
+ *     per GPU, held until the process ends; a problem needs
+ *     2 B N (16 n_units + 8 (nx + nu)) + 8 (B + 1) bytes (each part rounded up to
+ *     256), and one that needs more returns LEB_ESCRATCH before any launch
+ *     (256 x 40 x 224: 46 MB);
+ *   - all opt->max_sweeps sweeps are enqueued (a sweep after every trajectory
+ *     is accepted exits at once), so *sweeps_out = opt->max_sweeps, the
+ *     sweeps enqueued; the certificate flags tell which trajectories were
+ *     accepted within them.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (other host threads, or other streams before the first call's kernels
+ * finish) race and corrupt each other's results; the caller orders them.
+ * The array keeps the last call's contents; nothing in it needs clearing
+ * (the first sweep writes every state word it reads).
+ */
+int leb_fixed_point_solve_noalloc(const leb_dynamics* dyn, int32_t batch, int32_t N, const double* z,
+                                  const double* v, const double* phi, const double* e, const leb_fp_options* opt,
+                                  double* mu, double* sigma, uint32_t* certified, int32_t* sweeps_out, void* stream);
 
 /*
  * Launch timing of the fixed-point sweeps (instrumentation, off by default).

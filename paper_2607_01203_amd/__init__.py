@@ -127,6 +127,8 @@ def lib():
                                             vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(FPOptions),
                                             vp, vp, vp, ctypes.POINTER(ctypes.c_int32), vp]
         L.leb_fixed_point_solve.restype = ctypes.c_int
+        L.leb_fixed_point_solve_noalloc.argtypes = L.leb_fixed_point_solve.argtypes
+        L.leb_fixed_point_solve_noalloc.restype = ctypes.c_int
         f32 = ctypes.c_float
         L.leb_surrogate_create.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), vp,
                                            ctypes.POINTER(ctypes.c_void_p)]
@@ -380,6 +382,24 @@ def fixed_point_solve(dyn: Dynamics, z, v, phi, e, tol=1e-6, max_sweeps=200, pad
                                      _dev_ptr(cert, "certified"), ctypes.byref(sweeps), _stream(stream))
     _check(rc)
     return mu, sigma, cert, int(sweeps.value)
+
+
+def fixed_point_solve_noalloc(dyn: Dynamics, z, v, phi, e, mu, sigma, certified, tol=1e-6, max_sweeps=20, pad=0.0,
+                              inflate_abs=1e-12, warm=False, stream=None, conv_tol=None):
+    """leb_fixed_point_solve_noalloc: the caller passes every output
+    (mu, sigma [B][N][n] float64, certified [B] int32 GPU tensors; mu and sigma
+    hold the warm start when warm).  Returns the number of sweeps enqueued."""
+    import torch
+    B, N = int(z.shape[0]), int(z.shape[1])
+    opt = FPOptions(tol, max_sweeps, pad, inflate_abs, 1 if warm else 0, tol if conv_tol is None else conv_tol)
+    sweeps = ctypes.c_int32(0)
+    f64 = torch.float64
+    rc = lib().leb_fixed_point_solve_noalloc(ctypes.byref(dyn), B, N, _dev_ptr(z, "z", f64), _dev_ptr(v, "v", f64),
+                                             _dev_ptr(phi, "phi", f64), _host6(e), ctypes.byref(opt),
+                                             _dev_ptr(mu, "mu", f64), _dev_ptr(sigma, "sigma", f64),
+                                             _dev_ptr(certified, "certified"), ctypes.byref(sweeps), _stream(stream))
+    _check(rc)
+    return int(sweeps.value)
 
 
 def fixed_point_learned(dyn: Dynamics, z, v, phi, e, net, sweeps=1, margin=5e-2, tol=1e-6, max_sweeps=200,

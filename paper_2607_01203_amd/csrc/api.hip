@@ -93,6 +93,7 @@ extern "C" const char* leb_strerror(int code) {
     case LEB_ENOMEM: return "device allocation failed";
     case LEB_EDEVICE: return "HIP runtime error";
     case LEB_ENOTSUP: return "not supported";
+    case LEB_ESCRATCH: return "problem larger than the fixed scratch of the no-allocation entry point";
     }
     return "unknown status";
 }

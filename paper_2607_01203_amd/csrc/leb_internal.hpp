@@ -29,7 +29,7 @@ constexpr int FP_SLOTS = 4096;            // host-visible open counts, one per s
 struct SweepFold {
     const uint32_t* prev;   // [B] state words after sweep t's containment marks
     uint32_t* next;         // [B] folded words, [B] open count after sweep t
-    uint32_t* host_open;    // host-mapped counts, slot t % FP_SLOTS
+    uint32_t* host_open;    // host-mapped counts, slot t % FP_SLOTS (NULL: device only)
     int B;
     int sweep;              // t
 };

@@ -186,7 +186,7 @@ __global__ void __launch_bounds__(PBH_BLOCK) pbh_chain_fwd(ChainArgs A) {
                     for (int w = 0; w < PBH_BLOCK / 64; ++w) open += s_gopen[w];
                 }
                 A.fold.next[A.fold.B] = open;
-                if (A.fold.sweep > 0)
+                if (A.fold.sweep > 0 && A.fold.host_open)
                     __hip_atomic_store(&A.fold.host_open[A.fold.sweep % FP_SLOTS], open, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_SYSTEM);
             }

@@ -553,7 +553,8 @@ __global__ void __launch_bounds__(256) fp_fold_kernel(SweepFold F) {
     __syncthreads();
     if (threadIdx.x == 0) {
         F.next[F.B] = cnt;
-        __hip_atomic_store(&F.host_open[F.sweep % FP_SLOTS], cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        if (F.host_open)
+            __hip_atomic_store(&F.host_open[F.sweep % FP_SLOTS], cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
@@ -973,4 +974,94 @@ extern "C" int leb_fixed_point_solve(const leb_dynamics* dyn, int32_t batch, int
         hipLaunchKernelGGL(cert_out_kernel, dim3(nblk(batch)), dim3(256), 0, s, st[(t + 1) & 1], certified, batch);
     *sweeps_out = t;
     return ok(hipGetLastError()) ? LEB_OK : LEB_EDEVICE;
+}
+
+// ------------------------------------------------------ no-allocation form
+//
+// For callers that cannot allocate (graph capture, serving loops): the
+// workspace of the fixed point lives in this array, one copy per GPU, held
+// until the process ends.  Host code never passes `scratch` itself to a
+// kernel: its device address comes from hipGetSymbolAddress, taken once per
+// device with that device current.
+namespace leb {
+constexpr size_t FP_SCRATCH_BYTES = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[FP_SCRATCH_BYTES];
+constexpr int FP_SCRATCH_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static unsigned char* g_scratch_ptr[FP_SCRATCH_DEVICES];
+
+static int scratch_on_current_device(unsigned char** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return LEB_EDEVICE;
+    if (dev >= FP_SCRATCH_DEVICES) return LEB_ENOTSUP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return LEB_EDEVICE;
+        g_scratch_ptr[dev] = (unsigned char*)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LEB_OK;
+}
+
+static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+}  // namespace leb
+
+extern "C" int leb_fixed_point_solve_noalloc(const leb_dynamics* dyn, int32_t batch, int32_t N, const double* z,
+                                             const double* v, const double* phi, const double* e,
+                                             const leb_fp_options* opt, double* mu, double* sigma,
+                                             uint32_t* certified, int32_t* sweeps_out, void* stream) {
+    int rc = check_chain_dynamics(dyn);
+    if (rc != LEB_OK) return rc;
+    if (dyn->kind != LEB_DYN_PQUAD_CHAIN) return LEB_ENOTSUP;
+    if (!sweeps_out || batch < 0 || N < 0) return LEB_EINVAL;
+    if ((rc = fp_check_args(opt, e, N))) return rc;
+    *sweeps_out = 0;
+    const int64_t units = (int64_t)batch * N;
+    if (units == 0) return LEB_OK;
+    if (!z || !v || !mu || !sigma || !certified || (N > 1 && !phi)) return LEB_EINVAL;
+    const void* ptrs[] = {z, v, phi, mu, sigma};
+    for (const void* p : ptrs)
+        if (p && !aligned8(p)) return LEB_EINVAL;
+    const int U = dyn->n_units, n = dyn->nx + dyn->nu;
+    // the same buffers as leb_fixed_point_solve's workspace, carved from scratch
+    const size_t bx = al256((size_t)units * 2 * U * sizeof(double));
+    const size_t bn = al256((size_t)units * n * sizeof(double));
+    const size_t bs = al256(2 * ((size_t)batch + 1) * sizeof(uint32_t));
+    if (2 * bx + 2 * bn + bs > FP_SCRATCH_BYTES) return LEB_ESCRATCH;
+    unsigned char* base = nullptr;
+    if ((rc = scratch_on_current_device(&base))) return rc;
+    double* cb = (double*)base;
+    double* rb = (double*)(base + bx);
+    double* xm1 = (double*)(base + 2 * bx);
+    double* xs1 = (double*)(base + 2 * bx + bn);
+    uint32_t* state = (uint32_t*)(base + 2 * bx + 2 * bn);
+    hipStream_t s = (hipStream_t)stream;
+    double* xm[2] = {mu, xm1};
+    double* xs[2] = {sigma, xs1};
+    uint32_t* st[2] = {state, state + batch + 1};
+    if (!opt->warm)
+        if ((rc = launch_disturbance_tube(batch, N, U, phi, e, opt->pad, mu, sigma, s))) return rc;
+    // every sweep up to the cap is enqueued; the folds publish the open count on
+    // the device only, and a sweep after the last needed one exits at once
+    const int T = opt->max_sweeps;
+    for (int t = 1; t <= T; ++t) {
+        const int a = (t - 1) & 1, w = t & 1;
+        const SweepFold fold{st[a], st[w], nullptr, batch, t - 1};
+        if ((rc = launch_pbh_chain(dyn, units, z, v, xm[a], xs[a], nullptr, nullptr, cb, rb, opt->pad, nullptr, s,
+                                   &fold, nullptr, nullptr, true)))
+            return rc;
+        const TubeFP fp{xm[a], xs[a], st[w], opt->tol, opt->inflate_abs, certified, opt->conv_tol};
+        if ((rc = launch_tube2(batch, N, U, phi, e, opt->pad, cb, rb, xm[w], xs[w], fp, s, 1.0, 0.0, nullptr,
+                               nullptr)))
+            return rc;
+    }
+    const SweepFold fold{st[T & 1], st[(T + 1) & 1], nullptr, batch, T};
+    hipLaunchKernelGGL(fp_fold_kernel, dim3(1), dim3(256), 0, s, fold);
+    const int64_t per = (int64_t)N * n;
+    hipLaunchKernelGGL(fp_final_kernel, dim3(batch, (unsigned)std::min<int64_t>((per + 255) / 256, 16)), dim3(256), 0,
+                       s, xm1, xs1, mu, sigma, st[(T + 1) & 1], per, T);
+    hipLaunchKernelGGL(cert_out_kernel, dim3(nblk(batch)), dim3(256), 0, s, st[(T + 1) & 1], certified, batch);
+    *sweeps_out = T;
+    return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
 }
