@@ -3,23 +3,33 @@
 Workload: 256 trajectories x 40 steps of a chain of 28 planar quadrotors
 (nx = 168, nu = 56) with a decentralised hover-LQR closed loop.  One step
 is one certified tube/LEB fixed-point solve from device-resident inputs to
-a certified tube on the device (host orchestration included), in two forms:
+a certified tube on the device (host orchestration included).  Every form
+accepts a trajectory only when its tube is certified (F(C) inside C) and
+converged (relative change <= 1e-6), so all forms end at the same tube:
   plain    Jacobi sweeps of the path-based Hessian bound over all 10,240
            (trajectory, step) units and the tube map, from the
-           disturbance-only tube, until F(C) lies inside C;
-  learned  a few tube sweeps with the BF16 surrogate's predicted bounds,
-           inflation, then the same certified sweeps from that tube.
-The surrogate is trained beforehand (outside the timed region) by the
+           disturbance-only tube;
+  learned  one tube sweep with the BF16 surrogate's predicted bounds, then
+           the same certified sweeps from that tube.  Two networks: one
+           trained to map a tube to its bound, one trained to map the cold
+           start to the fixed point's bound (value: the latter);
+  exact    one plain sweep, then the certified iteration (the start that a
+           bound-map surrogate sweep emulates).
+The surrogates are trained beforehand (outside the timed region) by the
 library's kernels on certified bounds of other trajectories.
 value = 10,240 / (learned ms per solve); the plain rate is reported too.
 
 Prints ONE JSON line.  Extra objects:
-  roofline      dominant kernel: the tube map of the certified sweeps (HBM;
-                its FP64 MFMA rate beside), its launches in one learned
-                solve timed with HIP events on the solve's stream;
-                roofline_bound: the bound kernel of the same sweeps (HBM);
-  cpu_baseline  the FP64 oracle solving (and certifying) the same fixed
-                point on a bounded sample of trajectories, on host cores.
+  roofline        dominant kernel: the tube map of the certified sweeps (HBM;
+                  its FP64 MFMA rate beside), its launches in one learned
+                  solve timed with HIP events on the solve's stream;
+  roofline_bound  the path-based bound kernel at 2,560 x 40 units per launch
+                  (VALU issue, HBM beside), and as one 40-step trajectory;
+  cpu_baseline    the FP64 oracle solving (and certifying) the same fixed
+                  point on a bounded sample of trajectories, on all host
+                  cores and on one;
+  latency, adjoint, batched_uneven (batch against per-problem launches),
+  roofline_nn, learned_nn.
 """
 from __future__ import annotations
 
@@ -43,6 +53,10 @@ TUBE_PMC_KIB = (27251, 35859)
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 matrix (= vector) peak
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # lane-ops/s of non-packed VALU issue (39.3 T)
+# VALU lane-operations per unit of the path-based bound kernel at nx = 168:
+# SQ_INSTS_VALU x 64 / units from rocprofv3 --pmc on the 2,560 x 40 launch
+# (None until taken for the kernel as it is now).
+PBH_VALU_LANE_OPS_PER_UNIT = None
 
 
 def parse():
@@ -55,10 +69,13 @@ def parse():
     p.add_argument("--kernel-reps", type=int, default=50)
     p.add_argument("--epochs", type=int, default=20, help="surrogate training epochs (outside the timed region)")
     p.add_argument("--surrogate-sweeps", type=int, default=1)
-    p.add_argument("--margin", type=float, default=5e-2, help="relative inflation of the surrogate tube")
+    p.add_argument("--margin", type=float, default=0.0, help="relative inflation of the surrogate tube")
     p.add_argument("--no-extra", action="store_true", help="skip the MLP-bound roofline and the uneven batch")
     p.add_argument("--nn-only", action="store_true",
                    help="only run the MLP-bound roofline measurement (for profiling its kernels)")
+    p.add_argument("--m2-only", action="store_true",
+                   help="only run the path-based bound at 2,560 x 40 units per launch (for profiling it)")
+    p.add_argument("--fp-epochs", type=int, default=100, help="epochs of the fixed-point-target surrogate")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                    help="only run an elementwise copy (read BYTES, write BYTES) 5 times: the known-size "
                         "kernel that scales FETCH_SIZE / WRITE_SIZE counters")
@@ -122,6 +139,9 @@ def main():
     if args.nn_only:
         print(json.dumps({"roofline_nn": nn_roofline(leb, W, dev, torch.cuda.current_stream(), args)}))
         return
+    if args.m2_only:
+        print(json.dumps({"roofline_bound": plain_m2(leb, W, dev, torch.cuda.current_stream(), args)}))
+        return
     tp = W.fixed_point_cfg()
     b = tp.batch
     B, N, nx = b.z.shape
@@ -151,41 +171,49 @@ def main():
     plain_ms, (mu0, sg0, cert0, _), plain_sweeps = timed(
         lambda: leb.fixed_point_solve(dyn, z, v, phi, tp.e, tol=1e-6, max_sweeps=200))
     plain_cert = bool((cert0 == 1).all().item())
-
-    # learned form: surrogate trained (outside the timed region) on certified
-    # bounds of other trajectories, then surrogate sweeps + certified sweeps
-    net, train_info = train_chain_surrogate(leb, W, dev, args)
-    learned_ms, (mu, sg, cert, _), learned_sweeps = timed(
-        lambda: leb.fixed_point_learned(dyn, z, v, phi, tp.e, net, sweeps=args.surrogate_sweeps,
-                                        margin=args.margin, tol=1e-6, max_sweeps=200))
-    certified = bool((cert == 1).all().item())
     s0 = sg0.cpu().numpy()
-    s1 = sg.cpu().numpy()
     pos = s0 > 0
-    excess = s1[pos] / s0[pos] - 1.0
+
+    def tightness(sg):
+        ex = sg.cpu().numpy()[pos] / s0[pos] - 1.0
+        return {"sigma_over_plain_median": float("%.3g" % np.median(ex)),
+                "sigma_over_plain_max": float("%.3g" % np.abs(ex).max())}
+
+    # learned forms: surrogates trained (outside the timed region) on certified
+    # bounds of other trajectories, then one surrogate sweep + certified sweeps
+    net, train_info = train_chain_surrogate(leb, W, dev, args)
+    net_fp, train_fp_info = train_fp_surrogate(leb, W, dev, args)
+    forms = {}
+    for name, nw, info in (("bound_map", net, train_info), ("fixed_point_target", net_fp, train_fp_info)):
+        ms, (_, sg, cert, _), sw = timed(
+            lambda: leb.fixed_point_learned(dyn, z, v, phi, tp.e, nw, sweeps=args.surrogate_sweeps,
+                                            margin=args.margin, tol=1e-6, max_sweeps=200))
+        forms[name] = dict({"ms_per_solve": round(ms, 4), "value": round(units * 1e3 / ms, 1),
+                            "certified_sweeps": sw, "certified": bool((cert == 1).all().item()),
+                            "training": info}, **tightness(sg))
+    learned_ms = forms["fixed_point_target"]["ms_per_solve"]
+    certified = forms["fixed_point_target"]["certified"] and plain_cert
     ms_per_step = learned_ms
     value = units * 1e3 / learned_ms
 
     # comparison start without the surrogate: one plain sweep from the
-    # disturbance-only tube, sigma inflated by the same margin, then the
-    # certified iteration (two library calls)
+    # disturbance-only tube (inflated by the same margin), then the certified
+    # iteration (two library calls)
     def exact_start():
         m, s_, _, _ = leb.fixed_point_solve(dyn, z, v, phi, tp.e, tol=1e-6, max_sweeps=1)
-        s_.mul_(1.0 + args.margin).add_(1e-12)
+        if args.margin:
+            s_.mul_(1.0 + args.margin).add_(1e-12)
         return leb.fixed_point_solve(dyn, z, v, phi, tp.e, tol=1e-6, max_sweeps=200, mu=m, sigma=s_)
     exact_ms, (_, sg_x, cert_x, _), exact_sweeps = timed(exact_start)
-    ex_x = sg_x.cpu().numpy()[pos] / s0[pos] - 1.0
-    exact_line = {"ms_per_solve": round(exact_ms, 4), "certified_sweeps": 1 + exact_sweeps,
-                  "certified": bool((cert_x == 1).all().item()),
-                  "sigma_over_plain_median": round(float(np.median(ex_x)), 6),
-                  "sigma_over_plain_max": round(float(ex_x.max()), 6)}
+    exact_line = dict({"ms_per_solve": round(exact_ms, 4), "certified_sweeps": 1 + exact_sweeps,
+                       "certified": bool((cert_x == 1).all().item())}, **tightness(sg_x))
 
     # Dominant kernel: the tube map of the certified sweeps (6 of the ~11 launches
     # of a learned solve, the largest share of its time).  Its launches in one
     # learned solve are timed with HIP events on the solve's stream; the
     # speculative sweep after the certifying one is left out.
     leb.launch_timing(True)
-    _, _, _, sw_t = leb.fixed_point_learned(dyn, z, v, phi, tp.e, net, sweeps=args.surrogate_sweeps,
+    _, _, _, sw_t = leb.fixed_point_learned(dyn, z, v, phi, tp.e, net_fp, sweeps=args.surrogate_sweeps,
                                             margin=args.margin, tol=1e-6, max_sweeps=200)
     torch.cuda.synchronize()
     tube_ms = leb.launch_times(leb.LAUNCH_TUBE)[:sw_t]
@@ -206,18 +234,24 @@ def main():
                 "units_per_launch": B * U, "bytes_per_launch": tube_bytes,
                 "flops_per_unit": tube_flops_per_column(N), "mfma_tflops": round(tflops, 2),
                 "mfma_frac": round(tflops / FP64_PEAK_TFLOPS, 4)}
-    # the bound kernel of the same sweeps
+    # the bound kernel of the same sweeps (its own roofline is taken at the
+    # replicated scale below)
     bound_us = 1e3 * float(np.mean(bound_ms))
     bpu = bytes_per_unit_fixed_point_launch(nx, nu)
-    achieved = bpu * units / (bound_us * 1e-6) / 1e9
-    roofline_bound = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                      "frac": round(achieved / HBM_PEAK_GBS, 4), "kernel": "pbh_chain_fwd",
-                      "launch_us": round(bound_us, 2), "launches": len(bound_ms), "units_per_launch": units,
-                      "bytes_per_unit": bpu}
+    bound_in_sweeps = {"kernel": "pbh_chain_fwd (fixed-point sweeps, with the fold)", "launch_us": round(bound_us, 2),
+                       "launches": len(bound_ms), "units_per_launch": units, "bytes_per_unit": bpu,
+                       "hbm_frac": round(bpu * units / (bound_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+    net.close()
+    net_fp.close()
 
-    nn_line = None if args.no_extra else nn_roofline(leb, W, dev, stream, args)
-    nn_learned_line = None if args.no_extra else nn_learned(leb, W, dev, stream, args)
-    batch_line = None if args.no_extra else batched_uneven(leb, W, dev, stream, args)
+    roofline_bound = plain_m2(leb, W, dev, stream, args)
+    roofline_bound["in_fixed_point_sweeps"] = bound_in_sweeps
+    extra = {} if args.no_extra else {
+        "latency": latency(leb, W, dev, stream),
+        "adjoint": adjoint(leb, W, dev, stream),
+        "roofline_nn": nn_roofline(leb, W, dev, stream, args),
+        "learned_nn": nn_learned(leb, W, dev, stream, args),
+        "batched_uneven": batched_uneven(leb, W, dev, stream, args)}
 
     cpu = None
     if not args.no_cpu:
@@ -230,21 +264,124 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32-interval+f64",
         "data": "synthetic",
         "config": {"workload": "certified tube/LEB fixed point, 256 chains of 28 planar quadrotors "
-                               "(nx=168, nu=56), N=40, batched Jacobi sweeps; value: learned warm start",
-                   "trajectories": B, "horizon": N, "nx": nx, "nu": nu, "tol": 1e-6,
+                               "(nx=168, nu=56), N=40, batched Jacobi sweeps, accepted when certified and "
+                               "converged to 1e-6; value: learned warm start (fixed-point-target network)",
+                   "trajectories": B, "horizon": N, "nx": nx, "nu": nu, "tol": 1e-6, "conv_tol": 1e-6,
                    "form": "batched + learned warm start"},
         "certified": certified,
-        "learned": {"certified_sweeps": learned_sweeps, "surrogate_sweeps": args.surrogate_sweeps,
-                    "margin": args.margin, "ms_per_solve": round(learned_ms, 4),
-                    "sigma_over_plain_median": round(float(np.median(excess)), 6),
-                    "sigma_over_plain_max": round(float(excess.max()), 6), "training": train_info},
+        "learned": forms["fixed_point_target"],
+        "learned_bound_map": forms["bound_map"],
         "exact_start_same_margin": exact_line,
         "plain": {"value": round(units * 1e3 / plain_ms, 1), "ms_per_solve": round(plain_ms, 4),
                   "certified_sweeps": plain_sweeps, "certified": plain_cert},
         "roofline": roofline, "cpu_baseline": cpu, "roofline_bound": roofline_bound,
-        "roofline_nn": nn_line, "learned_nn": nn_learned_line, "batched_uneven": batch_line,
     }
+    line.update(extra)
     print(json.dumps(line))
+
+
+def plain_m2(leb, W, dev, stream, args):
+    """The path-based bound on its own at nx = 168: 2,560 trajectories x 40
+    steps (102,400 units) per launch, 20 launches timed with HIP events on
+    the stream (VALU issue rate against the non-packed peak; HBM beside),
+    and one 40-step trajectory per launch (latency)."""
+    import numpy as np
+    import torch
+    b = W.chain_cfg(seed=2, N=40, n_units=28, batch=2560)
+    dyn = leb.dynamics_like(b.dyn)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    z, v, sg = t(b.z), t(b.v), t(b.sigma)
+    B, N, nx = b.z.shape
+    nu = b.v.shape[2]
+    units = B * N
+    out = {"r_lo": torch.empty((B, N, nx), dtype=torch.float64, device=dev),
+           "r_hi": torch.empty((B, N, nx), dtype=torch.float64, device=dev),
+           "flags": torch.empty((B, N), dtype=torch.int32, device=dev)}
+
+    def per_launch(zz, vv, ss, oo, reps):
+        for _ in range(3):
+            leb.analytic_bound(dyn, zz, vv, ss, stream=stream, out=oo)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            leb.analytic_bound(dyn, zz, vv, ss, stream=stream, out=oo)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e3
+
+    us = per_launch(z, v, sg, out, 20)
+    bpu = 8 * (nx + nu + (nx + nu)) + 8 * 2 * nx       # z, v, sigma in; r_lo, r_hi out
+    gbs = bpu * units / (us * 1e-6) / 1e9
+    one = {k: x[:1].contiguous() for k, x in out.items()}
+    us1 = per_launch(z[:1].contiguous(), v[:1].contiguous(), sg[:1].contiguous(), one, 200)
+    line = {"kernel": "pbh_chain_fwd", "workload": "2,560 x 40 chain units (nx=168) per launch",
+            "launch_us": round(us, 2), "launches": 20, "units_per_launch": units,
+            "timestep_bounds_per_s": round(units / (us * 1e-6), 1), "bytes_per_unit": bpu,
+            "hbm_achieved": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "one_trajectory_us": round(us1, 2)}
+    if PBH_VALU_LANE_OPS_PER_UNIT is not None:
+        tops = PBH_VALU_LANE_OPS_PER_UNIT * units / (us * 1e-6) / 1e12
+        line.update({"bound": "valu", "achieved": round(tops, 2), "peak": round(VALU_PEAK_TOPS, 1),
+                     "unit": "T lane-ops/s", "frac": round(tops / VALU_PEAK_TOPS, 4),
+                     "lane_ops_per_unit": PBH_VALU_LANE_OPS_PER_UNIT})
+    else:
+        line.update({"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 4)})
+    return line
+
+
+def latency(leb, W, dev, stream):
+    """The planar quadrotor of 20 steps, one call at a time: device time per
+    launch (HIP events over 200 back-to-back calls) and host wall time per
+    call including the binding."""
+    import torch
+    b = W.planar_quad_cfg()
+    dyn = leb.dynamics_like(b.dyn)
+    t = lambda a: torch.from_numpy(a).to(dev)
+    z, v, sg = t(b.z), t(b.v), t(b.sigma)
+    out = leb.analytic_bound(dyn, z, v, sg, stream=stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 200
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(reps):
+        leb.analytic_bound(dyn, z, v, sg, stream=stream, out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps * 1e6
+    return {"workload": "planar quadrotor, 1 x 20 steps (nx=6)", "device_us_per_call": round(e0.elapsed_time(e1) /
+                                                                                          reps * 1e3, 2),
+            "host_us_per_call": round(wall, 2)}
+
+
+def adjoint(leb, W, dev, stream):
+    """leb_backward (the adjoint of the path-based bound) at nx = 168: one
+    trajectory of 40 steps and 256 of them, HIP events over 20 calls."""
+    import torch
+    res = {}
+    for B in (1, 256):
+        b = W.chain_cfg(seed=2, N=40, n_units=28, batch=B)
+        dyn = leb.dynamics_like(b.dyn)
+        t = lambda a: torch.from_numpy(a).to(dev)
+        z, v, sg = t(b.z), t(b.v), t(b.sigma)
+        g = torch.ones((B, 40, 168), dtype=torch.float64, device=dev)
+        gn = -g
+        for _ in range(2):
+            leb.backward(dyn, z, v, sg, g, gn, stream=stream)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        reps = 20
+        e0.record(stream)
+        for _ in range(reps):
+            leb.backward(dyn, z, v, sg, g, gn, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / reps * 1e3
+        res["%dx40" % B] = {"us_per_call": round(us, 2), "timestep_gradients_per_s": round(B * 40 / (us * 1e-6), 1)}
+    return res
 
 
 def nn_crown_flops(widths):
@@ -381,11 +518,32 @@ def batched_uneven(leb, W, dev, stream, args):
     ms = e0.elapsed_time(e1) / reps
     info = bt.info().strip().splitlines()
     bt.close()
+
+    # the same problems, one library call each, back to back on the stream
+    def per_problem():
+        for p in probs:
+            if p["kind"] == "analytic":
+                leb.analytic_bound(p["dyn"], p["z"][None], p["v"][None], p["sigma"][None], stream=stream,
+                                   out={"r_lo": p["r_lo"][None], "r_hi": p["r_hi"][None], "flags": None})
+            else:
+                leb.nn_bound(p["net"], p["z"][None], p["v"][None], p["sigma"][None], stream=stream)
+    per_problem()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(reps):
+        per_problem()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_pp = e0.elapsed_time(e1) / reps
+    wall_pp = (time.perf_counter() - t0) / reps * 1e3
     for n in nets.values():
         n.close()
     return {"workload": "256 uneven problems, nx in {6,12,48,168}, N in 10..80, one graph launch",
             "timestep_bounds": units, "ms_per_submit": round(ms, 4),
             "timestep_bounds_per_s": round(units / (ms * 1e-3), 1), "create_s": round(create_s, 2),
+            "per_problem_calls": {"ms_device": round(ms_pp, 4), "ms_host_wall": round(wall_pp, 4),
+                                  "timestep_bounds_per_s": round(units / (max(ms_pp, wall_pp) * 1e-3), 1)},
             "groups": info}
 
 
@@ -413,6 +571,42 @@ def train_chain_surrogate(leb, W, dev, args):
                  "loss_last": round(hist[-1], 6), "sample_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2)}
 
 
+def train_fp_surrogate(leb, W, dev, args):
+    """Fixed-point-target network: features of the disturbance-only tube of
+    64 other trajectories (seed 100), targets of the certified bound at their
+    fixed point (71,680 node samples), trained with the library's kernels."""
+    import torch
+    from paper_2607_01203_amd import learned
+    t0 = time.perf_counter()
+    tp = W.fixed_point_cfg(seed=100, batch=64, N=40)
+    b = tp.batch
+    dyn = leb.dynamics_like(b.dyn)
+    z = torch.from_numpy(b.z).to(dev)
+    v = torch.from_numpy(b.v).to(dev)
+    phi = torch.from_numpy(tp.phi).to(dev)
+    mu, sg, _, _ = leb.fixed_point_solve(dyn, z, v, phi, tp.e)
+    X, T = learned.chain_fp_samples(dyn, z, v, phi, tp.e, mu, sg, seed=3)
+    net = leb.Surrogate(learned.CHAIN_WIDTHS, learned.he_init(learned.CHAIN_WIDTHS, 0))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    hist = learned.train(net, X, T, epochs=args.fp_epochs, batch=1024, lr=2e-3)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return net, {"samples": int(X.shape[0]), "epochs": args.fp_epochs, "loss_first": round(hist[0], 5),
+                 "loss_last": round(hist[-1], 6), "sample_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2)}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(W, tp, seconds):
     """Oracle fixed point (sequential sweep) plus its certifying sweep on a
     bounded sample of the trajectories, all host cores."""
@@ -425,28 +619,34 @@ def cpu_baseline(W, tp, seconds):
     b = tp.batch
     d = oracle.Dyn.like(b.dyn)
 
-    def solve(idx):
+    def solve(idx, threads):
         # exact fixed point by one sequential sweep, then the certifying sweep
         # (F(B) inside B; equality for the exact fixed point)
-        mu, sg, _, _ = tube.fixed_point(d, b.z[idx], b.v[idx], tp.phi, tp.e, threads=cores)
-        lo, hi, _ = oracle.leb(d, b.z[idx], b.v[idx], sg, mu=mu, threads=cores)
+        mu, sg, _, _ = tube.fixed_point(d, b.z[idx], b.v[idx], tp.phi, tp.e, threads=threads)
+        lo, hi, _ = oracle.leb(d, b.z[idx], b.v[idx], sg, mu=mu, threads=threads)
         c, r = tube.zono(lo, hi)
         m2, s2 = tube.tube_map(tp.phi, tp.e, c, r)
         return tube.contains(mu, sg, m2, s2)
 
-    t0 = time.perf_counter()
-    solve(np.arange(16))
-    per_traj = (time.perf_counter() - t0) / 16
-    count = int(max(16, min(b.z.shape[0], seconds / max(per_traj, 1e-6))))
-    idx = np.arange(count)
-    t0 = time.perf_counter()
-    ok = solve(idx)
-    dt = time.perf_counter() - t0
+    def rate(threads, budget):
+        t0 = time.perf_counter()
+        solve(np.arange(4), threads)
+        per_traj = (time.perf_counter() - t0) / 4
+        count = int(max(4, min(b.z.shape[0], budget / max(per_traj, 1e-6))))
+        t0 = time.perf_counter()
+        ok = solve(np.arange(count), threads)
+        dt = time.perf_counter() - t0
+        return count, dt, bool(ok.all())
+
     N = b.z.shape[1]
+    count, dt, ok = rate(cores, seconds)
+    c1, dt1, ok1 = rate(1, 0.4 * seconds)
     return {"value": round(count * N / dt, 2), "unit": "timestep-bounds/s", "cores": cores, "kind": "oracle",
             "sample": "%d of %d trajectories (N=%d, nx=168), exact fixed point + certifying sweep, %.1f s"
                       % (count, b.z.shape[0], N, dt),
-            "certified": bool(ok.all())}
+            "certified": ok and ok1, "cpu_model": cpu_model(),
+            "single_thread": {"value": round(c1 * N / dt1, 2), "cores": 1,
+                              "sample": "%d trajectories, %.1f s" % (c1, dt1)}}
 
 
 if __name__ == "__main__":
