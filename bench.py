@@ -55,8 +55,8 @@ FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 matrix (= vector) peak
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # lane-ops/s of non-packed VALU issue (39.3 T)
 # VALU lane-operations per unit of the path-based bound kernel at nx = 168:
 # SQ_INSTS_VALU x 64 / units from rocprofv3 --pmc on the 2,560 x 40 launch
-# (None until taken for the kernel as it is now).
-PBH_VALU_LANE_OPS_PER_UNIT = None
+# (profiles/pbh_chain_fwd_plain_2560x40x168.md; None until taken for the kernel as it is now).
+PBH_VALU_LANE_OPS_PER_UNIT = 52723
 
 
 def parse():
