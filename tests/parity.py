@@ -29,3 +29,22 @@ def check_bounds(lo_g, hi_g, lo_o, hi_o, where=""):
     assert worst <= REL, "%s: relative error %.3e" % (where, worst)
     assert (lg <= lo + NARROW * M).all() and (hg >= ho - NARROW * M).all(), "%s: GPU narrower" % where
     return worst
+
+
+def sampled_violations(remainder, nom, blo, bhi, lo, hi, per, seed, chunk=64):
+    """Violations of [lo, hi] (per unit) by the true remainder at `per`
+    sampled points of each unit's box [blo, bhi] (half uniform, a quarter
+    vertices, a quarter mixed).  remainder(nom_chunk, pts [U][per][n]) ->
+    (r, eps) [U][per][m] with eps bounding the FP64 evaluation error; a
+    violation is r > hi + eps or r < lo - eps.  Returns (violations, samples)."""
+    import workloads as W
+    rng = W.rng_for(seed)
+    viol = 0
+    count = 0
+    for s in range(0, nom.shape[0], chunk):
+        e = min(nom.shape[0], s + chunk)
+        pts = W.sample_box_points(rng, blo[s:e], bhi[s:e], per)
+        r, eps = remainder(nom[s:e], pts)
+        viol += int(((r > hi[s:e, None] + eps) | (r < lo[s:e, None] - eps)).sum())
+        count += (e - s) * per
+    return viol, count

@@ -137,3 +137,56 @@ def test_batch_rejects_bad_problems(gpu):
     b.submit()
     torch.cuda.synchronize()
     b.close()
+
+
+def test_batch_256_problems_oracle_and_1e6_samples(gpu, orc):
+    """The uneven-batch workload at full size (256 problems, nx in {6, 12,
+    48, 168}, N in 10..80, about 11,000 units): every problem equals its
+    standalone call bit for bit and the oracle within the parity tolerance,
+    and the bounds contain 10^6 sampled true remainders (spread over all
+    units, analytic and MLP)."""
+    import torch
+    import paper_2607_01203_amd as leb
+    from oracle import nn as onn
+    from parity import sampled_violations
+    mb = W.mixed_batch_cfg(seed=3, count=256)
+    nets = {}
+    probs = _problems(leb, mb, gpu, nets)
+    print("case: batch of 256 problems", flush=True)
+    b = leb.Batch(probs, tune_cache=None)
+    b.submit()
+    torch.cuda.synchronize()
+    units = sum(int(p["z"].shape[0]) for p in probs)
+    per = 1_000_000 // units + 1
+    viol = count = 0
+    for i, p in enumerate(probs):
+        lo_s, hi_s = _standalone(leb, p)
+        torch.cuda.synchronize()
+        assert torch.equal(p["r_lo"], lo_s) and torch.equal(p["r_hi"], hi_s), i
+        cfg = p["cfg"]
+        lo_g, hi_g = p["r_lo"].cpu().numpy(), p["r_hi"].cpu().numpy()
+        nom = np.concatenate([cfg.z[0], cfg.v[0]], -1)
+        if p["kind"] == "analytic":
+            d = orc.Dyn.like(cfg.dyn)
+            lo, hi, _ = orc.leb(d, cfg.z[0], cfg.v[0], cfg.sigma[0])
+
+            def rem(nm, pts, d=d):
+                U, P, n = pts.shape
+                r, eps = orc.remainder(d, nm, pts.reshape(-1, n), np.repeat(np.arange(U), P))
+                return r.reshape(U, P, -1), eps.reshape(U, P, -1)
+        else:
+            o = onn.leb(cfg.net.W, cfg.net.b, nom, cfg.sigma[0])
+            lo, hi = o["r_lo"], o["r_hi"]
+
+            def rem(nm, pts, net=cfg.net):
+                return onn.remainder(net.W, net.b, nm, pts)
+        check_bounds(lo_g, hi_g, lo, hi, "problem %d (%s)" % (i, p["kind"]))
+        blo, bhi = orc.box(nom, cfg.sigma[0])
+        v_, c_ = sampled_violations(rem, nom, blo, bhi, lo_g, hi_g, per, seed=3_000_000 + i)
+        viol += v_
+        count += c_
+    print("units %d samples %d violations %d" % (units, count, viol))
+    assert count >= 1_000_000 and viol == 0
+    b.close()
+    for n in nets.values():
+        n.close()

@@ -68,8 +68,11 @@ def test_backward_matches_oracle_gradient(gpu, orc, n_units, batch, N, offc):
 
 
 def test_backward_chain168_and_finite_differences(gpu, orc):
+    """The adjoint at the 28-node, 40-step shape against the oracle gradient
+    (every unit clear of kinks) and central differences of the oracle bound
+    at three units spread over the horizon."""
     import paper_2607_01203_amd as leb
-    b = W.chain_cfg(N=8)
+    b = W.chain_cfg(N=40)
     r = np.random.default_rng(7)
     gl = r.normal(size=b.z.shape)
     gh = r.normal(size=b.z.shape)
@@ -81,8 +84,13 @@ def test_backward_chain168_and_finite_differences(gpu, orc):
     _compare(g, o, ok, ["gz", "gv", "gsigma"])
     # central differences (h = 1e-6) of the oracle bound against the GPU gradient
     h = 1e-6
-    t = int(np.nonzero(ok)[0][0])
+    okt = np.nonzero(ok)[0]
+    assert len(okt) >= 20
+    for t in (int(okt[0]), int(okt[len(okt) // 2]), int(okt[-1])):
+        _fd_at(orc, d, b, gl, gh, g, t, h)
 
+
+def _fd_at(orc, d, b, gl, gh, g, t, h):
     def L(z, v, s):
         lo, hi, _ = orc.leb(d, z[:, t:t + 1], v[:, t:t + 1], s[:, t:t + 1])
         return float((gl[:, t:t + 1] * lo + gh[:, t:t + 1] * hi).sum())

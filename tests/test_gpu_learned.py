@@ -244,3 +244,114 @@ def test_learned_form_without_surrogate_sweeps(trained, orc):
     print("sigma / least fixed point: median %.6f max %.6f" % (np.median(ratio), ratio.max()))
     # accepted only once converged: within the parity tolerance of the least fixed point
     assert sw >= 2 and ratio.max() <= 1 + 1e-4
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2607_01203_amd as leb
+    leb.lib()
+    return torch.device("cuda:0")
+
+
+def _chain_features_numpy(z, v, mu, sg, U, L0):
+    """The 32 chain-surrogate inputs of every (unit, node), written out from
+    their definition in leb.h (FP64 arithmetic, then rounded to FP32)."""
+    nx = 6 * U
+    B, N = z.shape[:2]
+    X = np.zeros((B, N, U, 32), dtype=np.float32)
+    dlo = lambda c: np.float32(np.fmin(mu[..., c] - sg[..., c], 0.0) * 20.0)
+    dhi = lambda c: np.float32(np.fmax(mu[..., c] + sg[..., c], 0.0) * 20.0)
+    for i in range(U):
+        th, px, pz, u1, u2 = 6 * i + 2, 6 * i, 6 * i + 1, nx + 2 * i, nx + 2 * i + 1
+        f = X[:, :, i]
+        f[..., 0] = z[..., th]
+        f[..., 1] = (v[..., 2 * i] + v[..., 2 * i + 1]) * 0.1
+        for k, c in enumerate((th, u1, u2, px, pz)):
+            f[..., 2 + 2 * k] = dlo(c)
+            f[..., 3 + 2 * k] = dhi(c)
+        for side, j in ((0, i + 1), (1, i - 1)):
+            o = 12 + 7 * side
+            if 0 <= j < U:
+                a, b = (i, j) if side == 0 else (j, i)
+                f[..., o] = 1.0
+                f[..., o + 1] = (L0 + z[..., 6 * b]) - z[..., 6 * a]
+                f[..., o + 2] = z[..., 6 * b + 1] - z[..., 6 * a + 1]
+                f[..., o + 3], f[..., o + 4] = dlo(6 * j), dhi(6 * j)
+                f[..., o + 5], f[..., o + 6] = dlo(6 * j + 1), dhi(6 * j + 1)
+    return X
+
+
+@pytest.mark.parametrize("with_mu", [False, True])
+def test_chain_features_definition(dev, with_mu):
+    """leb_chain_features against its definition (leb.h): nominal attitude
+    and thrust, displacement intervals of the node's attitude, inputs and
+    position, and of each spring's far node, the spring separations and
+    presence flags, zeros past feature 26; the first and last nodes of the
+    chain have one spring each."""
+    import paper_2607_01203_amd as leb
+    b = W.chain_batch(71, 3, 5, 6)
+    r = np.random.default_rng(8)
+    mu = r.uniform(-1.5, 1.5, b.sigma.shape) * b.sigma if with_mu else np.zeros_like(b.sigma)
+    dyn = leb.dynamics_like(b.dyn)
+    print("case: chain features, mu=%s" % with_mu, flush=True)
+    x = leb.chain_features(dyn, _t(b.z, dev), _t(b.v, dev), _t(b.sigma, dev),
+                           mu=_t(mu, dev) if with_mu else None).cpu().numpy()
+    want = _chain_features_numpy(b.z, b.v, mu, b.sigma, 6, b.dyn.rest_len)
+    assert x.shape == (3, 5, 6, 32)
+    np.testing.assert_array_equal(x, want)
+    assert (x[:, :, 0, 19] == 0).all() and (x[:, :, -1, 12] == 0).all()     # chain ends
+
+
+def test_chain_targets_definition(dev):
+    """leb_chain_targets against its definition: log(max(hi, 1e-14)) and
+    log(max(-lo, 1e-14)) of rows 3 (vx) and 4 (vz) of every node, in FP32."""
+    import paper_2607_01203_amd as leb
+    rng = np.random.default_rng(4)
+    U = 5
+    hi = rng.exponential(1e-3, (2, 3, 6 * U))
+    lo = -rng.exponential(1e-3, (2, 3, 6 * U))
+    hi[0, 0, 3], lo[0, 0, 3] = 0.0, -0.0
+    hi[0, 0, 9], lo[0, 0, 10] = 1e-20, -2.5
+    dyn = leb.chain_dynamics(U)
+    print("case: chain targets", flush=True)
+    t = leb.chain_targets(dyn, _t(lo, dev), _t(hi, dev)).cpu().numpy()
+    f = np.float32(1e-14)
+    L = lambda a: np.log(np.maximum(a.astype(np.float32), f))
+    want = np.stack([L(hi[..., 3::6]), L(-lo[..., 3::6]), L(hi[..., 4::6]), L(-lo[..., 4::6])], -1)
+    np.testing.assert_allclose(t, want, rtol=1e-6, atol=1e-6)
+
+
+def test_learned_boxes_sound_1e6(trained, trained_fp, orc):
+    """The bound on every accepted box of the learned form (fixed-point-target
+    network, 256 x 40 x 168) contains 10^6 sampled true remainders."""
+    import torch
+    from parity import sampled_violations
+    leb, _, dev, _ = trained
+    net_fp, _ = trained_fp
+    tp = W.fixed_point_cfg(seed=4, batch=256, N=40)
+    b = tp.batch
+    dyn = leb.dynamics_like(b.dyn)
+    z, v, phi = _t(b.z, dev), _t(b.v, dev), _t(tp.phi, dev)
+    print("case: learned boxes, 10^6 samples", flush=True)
+    mu, sg, cert, _ = leb.fixed_point_learned(dyn, z, v, phi, tp.e, net_fp, sweeps=1, margin=0.0)
+    out = leb.analytic_bound(dyn, z, v, sg, mu)
+    torch.cuda.synchronize()
+    assert bool((cert == 1).all())
+    lo = out["r_lo"].cpu().numpy().reshape(-1, 168)
+    hi = out["r_hi"].cpu().numpy().reshape(-1, 168)
+    d = orc.Dyn.like(b.dyn)
+    nom = np.concatenate([b.z, b.v], -1).reshape(-1, 224)
+    blo, bhi = orc.box(nom, sg.cpu().numpy().reshape(-1, 224), mu.cpu().numpy().reshape(-1, 224))
+    per = 1_000_000 // nom.shape[0] + 1
+
+    def rem(nm, pts):
+        U, P, n = pts.shape
+        r, eps = orc.remainder(d, nm, pts.reshape(-1, n), np.repeat(np.arange(U), P))
+        return r.reshape(U, P, -1), eps.reshape(U, P, -1)
+
+    viol, count = sampled_violations(rem, nom, blo, bhi, lo, hi, per, seed=1_000_004, chunk=256)
+    print("samples %d violations %d" % (count, viol))
+    assert count >= 1_000_000 and viol == 0

@@ -79,3 +79,46 @@ def test_gradient_of_zero_upstream_is_zero(orc):
     z0 = np.zeros((1, 3, d.nx))
     g = orc.leb_grad(d, b.z, b.v, b.sigma, z0, z0)
     assert all((g[k] == 0).all() for k in ("gz", "gv", "gsigma"))
+
+
+def test_kink_margin_counts_only_slope_changes(orc):
+    """The margin rule: a tie between candidate endpoints is a kink of L
+    along a direction only when the tied candidates change at different
+    rates along it.  On symmetric boxes (mu = 0) lo*lo and hi*hi of a
+    displacement product tie exactly; along sigma, z and v they move at the
+    same rate (no kink: the margin stays away from 0 and one-sided
+    differences agree), along mu they move at opposite rates (a kink: the
+    margin is 0 and the one-sided differences differ)."""
+    b = W.planar_quad_cfg()
+    d = orc.Dyn.like(b.dyn)
+    r = np.random.default_rng(5)
+    gl = r.normal(size=b.z.shape)
+    gh = r.normal(size=b.z.shape)
+    mu0 = np.zeros_like(b.sigma)
+    smooth = orc.leb_grad(d, b.z, b.v, b.sigma, gl, gh)
+    kinked = orc.leb_grad(d, b.z, b.v, b.sigma, gl, gh, mu=mu0)
+    assert (smooth["margin"] > 1e-3).mean() >= 0.9
+    assert (kinked["margin"] < 1e-12).all()
+
+    def L(z_, v_, s_, m_):
+        lo, hi, _ = orc.leb(d, z_, v_, s_, mu=m_)
+        return float((gl * lo + gh * hi).sum())
+
+    t = int(np.nonzero(smooth["margin"][0] > 1e-3)[0][0])
+    base = L(b.z, b.v, b.sigma, mu0)
+
+    def one_sided(name, c):
+        arrs = {"z": b.z, "v": b.v, "s": b.sigma, "m": mu0}
+        up = {k: a.copy() for k, a in arrs.items()}
+        dn = {k: a.copy() for k, a in arrs.items()}
+        up[name][0, t, c] += H
+        dn[name][0, t, c] -= H
+        return ((L(up["z"], up["v"], up["s"], up["m"]) - base) / H,
+                (base - L(dn["z"], dn["v"], dn["s"], dn["m"])) / H)
+
+    for name, c in (("s", 2), ("z", 2), ("v", 0)):
+        right, left = one_sided(name, c)
+        # smooth: the one-sided slopes differ only by the curvature term O(h)
+        assert abs(right - left) <= 1e-4 * max(abs(right), 1e-9), (name, right, left)
+    right, left = one_sided("m", 2)
+    assert abs(right - left) > 1e-2 * max(abs(right), abs(left)), (right, left)

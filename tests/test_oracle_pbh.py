@@ -416,3 +416,44 @@ def test_sampled_soundness_off_centre(orc):
     lo, hi, _ = orc.leb(d, b.z, b.v, b.sigma, mu=mu)
     nv, _ = _violations(orc, d, b.z, b.v, b.sigma, lo, hi, 3000, 1_000_003, mu=mu)
     assert nv == 0
+
+
+def test_expand_and_classic_closed_forms(orc):
+    """The expanded (eq. expanded_interval_hessian) and classic (eq.
+    interval_quadratic_form) enclosures written out by hand for a quadratic
+    f = 1/2 a^T Q a with Q = [[a, b], [b, c]] on the symmetric box
+    Delta = ([-s, s], [-t, t]):
+      path = expand:  [-|b| s t + 1/2 min(a,0) s^2 + 1/2 min(c,0) t^2,
+                        |b| s t + 1/2 max(a,0) s^2 + 1/2 max(c,0) t^2]
+                      (point Hessian entries, so the prefix sets do not matter)
+      classic:        v = [Q] Delta, then 1/2 Delta . v:
+                      +-1/2 (|a| s^2 + 2 |b| s t + |c| t^2)
+    and for a diagonal Q on one-sided boxes (mu = sigma, Delta = [0, 2 sigma]),
+    where Delta x Delta = sq(Delta), all three are 1/2 Q_kk [0, 4 sigma_k^2]."""
+    for (a, b, c) in ((2.0, 0.7, -1.5), (-0.3, -1.1, 0.4), (1.0, 0.0, 3.0)):
+        Q = np.array([[[a, b], [b, c]]])
+        d = orc.Dyn("quadratic", 1, 1, Q=Q)
+        s, t = 0.3, 0.05
+        z, v, sg = np.array([[0.4]]), np.array([[-0.2]]), np.array([[s, t]])
+        hi_p = abs(b) * s * t + 0.5 * max(a, 0) * s * s + 0.5 * max(c, 0) * t * t
+        lo_p = -abs(b) * s * t + 0.5 * min(a, 0) * s * s + 0.5 * min(c, 0) * t * t
+        hc = 0.5 * (abs(a) * s * s + 2 * abs(b) * s * t + abs(c) * t * t)
+        for mode, lo_w, hi_w in (("path", lo_p, hi_p), ("expand", lo_p, hi_p), ("classic", -hc, hc)):
+            lo, hi, _ = orc.leb(d, z, v, sg, mode=mode)
+            assert lo[0, 0] <= lo_w and hi[0, 0] >= hi_w, mode
+            assert abs(lo[0, 0] - lo_w) <= 1e-14 and abs(hi[0, 0] - hi_w) <= 1e-14, (mode, lo, hi, lo_w, hi_w)
+    rng = np.random.default_rng(2)
+    n = 5
+    Q = np.zeros((2, n, n))
+    Q[0][np.diag_indices(n)] = rng.normal(size=n)
+    Q[1][np.diag_indices(n)] = rng.normal(size=n)
+    d = orc.Dyn("quadratic", 2, 3, Q=Q)
+    sg = rng.uniform(0.01, 0.2, (4, n))
+    z, v = rng.normal(size=(4, 2)), rng.normal(size=(4, 3))
+    want_hi = 0.5 * (np.maximum(Q[:, range(n), range(n)], 0)[None] * 4 * sg[:, None, :] ** 2).sum(-1)
+    want_lo = 0.5 * (np.minimum(Q[:, range(n), range(n)], 0)[None] * 4 * sg[:, None, :] ** 2).sum(-1)
+    for mode in ("path", "expand", "classic"):
+        lo, hi, _ = orc.leb(d, z, v, sg, mu=sg, mode=mode)
+        np.testing.assert_allclose(hi, want_hi, rtol=1e-13, atol=0)
+        np.testing.assert_allclose(lo, want_lo, rtol=1e-13, atol=0)
+        assert (hi >= want_hi).all() and (lo <= want_lo).all()
