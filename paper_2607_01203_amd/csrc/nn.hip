@@ -225,164 +225,178 @@ __global__ void __launch_bounds__(256) nn_relax_kernel(RelaxArgs A) {
     A.amax[o] = fmax(u, 0.0);
 }
 
-// ----------------------------------------------------------------- step
+// ---------------------------------------------------------- fused chain
 //
-// C[mode][box][M][N] = (A (.) Ssel) W   with Ssel = (A >= 0 ? spos : sneg)
-// beta[mode][box][M] (+)= sum_k (A >= 0 ? A tpos : A tneg) + sum_k Omega b
-// eps [mode][box][M] (+)= sum_k |A| e
-struct StepMode {
-    const double* spos; const double* sneg; const double* tpos; const double* tneg;   // [box][W]
+// The whole backward substitution of one target layer k, for one box, one
+// mode and a block of 16 target rows, in one workgroup:
+//   Lambda_{j-1} = (Lambda_j (.) S_j) W_j,   j = k-1, ..., 1,   Lambda_k = rows of W_k,
+//   beta += sum_i (Lambda_j t_sel)_i + (Omega_j b_j),   eps += |Lambda_j| e_j,
+// with Lambda kept in LDS between the steps (never in HBM).  The product is
+// formed transposed on FP64 MFMA (v_mfma_f64_16x16x4): Lambda^T_{j-1} =
+// W_j^T Omega^T, so the accumulator of one step (lane l holds element
+// [4i + l/16][l%16] of a 16 x 16 tile) is stored to LDS in the layout the
+// next step reads its B operand from (lane l supplies B[l/16][l%16]).  A
+// operands are W_j columns read from L2, 16 consecutive values per k.
+// Neurons of layer j that are stably inactive (u <= 0) have zero slopes and
+// intercepts in every mode, so their columns of Omega_j are exactly 0: each
+// step runs over the workgroup's list of the other neurons only.
+// Wave w produces the output tiles w, w + 4, ... of each step; wave 0 also
+// sums the bias and rounding terms of its rows.
+struct ChainArgs {
+    const double* Wt;              // target layer k: [M][w_{k-1}] (shared by every box)
+    const double* bt;              // [M]
+    const double* W[NN_MAXL];      // layer j at W[j-1]: [w_j][w_{j-1}]
+    const double* b[NN_MAXL];
+    int w[NN_MAXL + 1];
+    int k, M, nbox;
+    // per-box vectors of hidden layer j (1-based) at base + (j - 1) * lstride + box * NN_MAXW
+    const double* s; const double* t; const double* a; const double* D; const double* e; const double* hi;
+    size_t lstride;
+    double* C;                     // [mode][box][M][w_0]
+    double* beta; double* eps;     // [mode][box][M]
 };
 
-struct StepArgs {
-    const double* A;            // shared [M][K] (a_shared) or [mode][box][M][K]
-    int a_shared;
-    StepMode md[3];
-    const double* bias;         // [K]
-    const double* e;            // [box][W]
-    const double* W;            // [K][N]
-    double* C;                  // [mode][box][M][N]
-    double* beta; double* eps;  // [mode][box][M]
-    const double* beta_init;    // [M] or NULL (accumulate)
-    int M, K, N, nbox, nmode;
-    int nact;                   // boxes in use (the rest of the chunk is idle)
-};
+constexpr size_t CHAIN_STATE_BYTES = (size_t)NN_MAXW * 16 * sizeof(double);
+constexpr int CHAIN_PAD = NN_MAXW + 8;               // listed neurons, padded past the last k-step read
 
-// MFMA f64 16x16x4 operand layout (per 64-lane wave; checked on gfx950):
-// lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator
-// element i of lane l is D[4 i + l / 16][l % 16].
-// The K loop runs in chunks of 16: the W tile and the chunk's per-k vectors
-// (slopes, offsets, bias, rounding weights) go through LDS (two buffers), the
-// A values into registers; the next chunk's loads are in flight during this
-// chunk's MFMAs, with one barrier per chunk.  Loads are unconditional
-// (clamped addresses, values selected), so no wait covers a later chunk.
-template <int WR, int WC, int TPW>
-__global__ void __launch_bounds__(256) nn_step_kernel(StepArgs S) {
-    constexpr int NT = 16 * TPW * WC;
-    constexpr int WPT = 16 * NT / 256;               // W tile values per thread and chunk
-    static_assert(WPT >= 1 && 16 * NT % 256 == 0, "W tile split");
-    __shared__ double s_w[2][16][NT];
-    __shared__ double s_v[2][6][16];                 // spos, sneg, tpos, tneg, bias, e of the chunk's k
-    __shared__ double s_red[4][64][3];
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int wr = wave / WC, wc = wave % WC;
-    const int zidx = blockIdx.y;                 // mode * nbox + box
-    const int mode = zidx / S.nbox, box = zidx - mode * S.nbox;
-    if (box >= S.nact) return;
-    const int row = blockIdx.x * (16 * WR) + 16 * wr + (lane & 15);
-    const int kq = lane >> 4;
-    const StepMode md = S.md[mode];
-    const size_t boxW = (size_t)box * NN_MAXW;
-    const bool rowok = row < S.M;
-    const double* Arow = S.a_shared ? S.A + (size_t)(rowok ? row : 0) * S.K
-                                    : S.A + (((size_t)mode * S.nbox + box) * S.M + (rowok ? row : 0)) * S.K;
-    const bool has_tpos = md.tpos != nullptr, has_tneg = md.tneg != nullptr;
-    // the per-k vector of thread tid < 96: q = tid / 16 (0 spos, 1 sneg, 2 tpos, 3 tneg, 4 bias, 5 e)
-    const int vq = tid >> 4, vk = tid & 15;
-    const double* vsrc = nullptr;
-    if (tid < 96) {
-        switch (vq) {
-            case 0: vsrc = md.spos + boxW; break;
-            case 1: vsrc = md.sneg + boxW; break;
-            case 2: vsrc = has_tpos ? md.tpos + boxW : nullptr; break;
-            case 3: vsrc = has_tneg ? md.tneg + boxW : nullptr; break;
-            case 4: vsrc = S.bias; break;
-            default: vsrc = S.e + boxW; break;
-        }
+__global__ void __launch_bounds__(256) nn_chain_kernel(ChainArgs A) {
+    extern __shared__ double cst[];                    // [NN_MAXW][16]: Lambda^T of this block
+    __shared__ double cv[5][CHAIN_PAD];                // slope x >= 0, slope x < 0, intercept, bias, e (list order)
+    __shared__ int sk[CHAIN_PAD];                      // neurons of layer j that are not stably inactive
+    __shared__ int scnt[4];
+    __shared__ double spart[768];                      // partial tiles of the k-slices; then the row sums
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    const int row0 = 16 * blockIdx.x, mode = blockIdx.y, box = blockIdx.z;
+    const int K0 = A.w[A.k - 1];
+    // Lambda_k: rows row0 .. row0 + 15 of W_k (zero past M)
+    for (int q = tid; q < 16 * K0; q += 256) {
+        const int rr = q / K0, kk = q - rr * K0;
+        const bool ok = row0 + rr < A.M;
+        const double x = A.Wt[ok ? (size_t)(row0 + rr) * K0 + kk : 0];
+        cst[kk * 16 + rr] = ok ? x : 0.0;
     }
-    double wv[WPT], vv = 0.0, ar[4];
-    auto gload = [&](int kc) {
+    // intercept of the selected line: upper mode on x >= 0, lower mode on x < 0
+    const bool t_on_pos = mode == 0, t_on_neg = mode == 1;
+    double pb = 0.0, pe = 0.0;
+    for (int j = A.k - 1; j >= 1; --j) {
+        const int K = A.w[j], N = A.w[j - 1];
+        const double* Wj = A.W[j - 1];
+        const size_t vo = (size_t)(j - 1) * A.lstride + (size_t)box * NN_MAXW;
+        const bool keep = tid < K && A.hi[vo + tid] > 0.0;
+        const uint64_t bal = __ballot(keep);
+        if (lane == 0) scnt[wave] = __popcll(bal);
+        __syncthreads();                               // counts (and the previous step's state) written
+        int off = 0, Kc = 0;
 #pragma unroll
-        for (int u = 0; u < WPT; ++u) {
-            const int idx = tid + 256 * u;
-            const int kk = idx / NT, nn = idx - kk * NT;
-            const int k = kc + kk;
-            const bool ok = k < S.K && nn < S.N;
-            const double x = S.W[ok ? (size_t)k * S.N + nn : 0];
-            wv[u] = ok ? x : 0.0;
+        for (int q = 0; q < 4; ++q) { off += q < wave ? scnt[q] : 0; Kc += scnt[q]; }
+        if (keep) sk[off + __popcll(bal & ((1ull << lane) - 1ull))] = tid;
+        if (tid >= Kc) sk[tid] = 0;                    // padding (its x is forced to 0)
+        if (tid < CHAIN_PAD - 256) sk[256 + tid] = 0;
+        __syncthreads();
+        // this mode's slopes, intercept, bias and rounding weight of each listed neuron
+        for (int q = tid; q < CHAIN_PAD; q += 256) {
+            const int k = sk[q];
+            const size_t o = vo + k;
+            const double s_ = A.s[o], a_ = A.a[o];
+            cv[0][q] = mode == 0 ? s_ : (mode == 1 ? a_ : A.D[o]);
+            cv[1][q] = mode == 0 ? a_ : (mode == 1 ? s_ : A.D[o]);
+            cv[2][q] = mode == 2 ? 0.0 : A.t[o];
+            cv[3][q] = A.b[j - 1][k];
+            cv[4][q] = A.e[o];
         }
-        if (vsrc) {
-            const int k = kc + vk;
-            const double x = vsrc[k < S.K ? k : 0];
-            vv = k < S.K ? x : 0.0;
-        }
+        __syncthreads();
+        // work split: ntile >= 3: wave w owns tiles w, w + 4, ... over all k; ntile 2 or
+        // 1: the waves split the k-steps of the tile(s) into 2 or 4 slices
+        const int ntile = N / 16;
+        const int nslice = ntile >= 3 ? 1 : 4 / ntile;
+        const int slice = wave / (4 / nslice);
+        const int tfirst = ntile >= 3 ? wave : wave % ntile;
+        const int nmine = tfirst < ntile ? (ntile >= 3 ? (ntile - wave + 3) / 4 : 1) : 0;
+        const bool sums = tfirst == 0;                 // the waves of tile 0 sum the row terms of their slice
+        d4 acc[4];
 #pragma unroll
-        for (int st = 0; st < 4; ++st) {
-            const int k = kc + 4 * st + kq;
-            const bool ok = rowok && k < S.K;
-            const double x = Arow[ok ? k : 0];
-            ar[st] = ok ? x : 0.0;
-        }
-    };
-    d4 acc[TPW];
+        for (int i = 0; i < 4; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+        if (nmine > 0) {
+            // k-step covers list positions c0 .. c0 + 3 (lane group g takes c0 + g);
+            // this wave runs c0 = 4 slice, 4 slice + 4 nslice, ...; the operands of the
+            // next k-step (W columns from L2, the state and vectors from LDS) are read
+            // while this one's MFMAs run
+            const int stride = 4 * nslice;
+            double wn[4], xn, psn, nsn, tn, bn, en;
+            auto load = [&](int c0) {
+                const int c = c0 + g;
+                const int k = sk[c];
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-    double pb = 0.0, pe = 0.0;                    // per-lane partial bias / rounding sums
-    gload(0);
-    for (int kc = 0, c = 0; kc < S.K; kc += 16, ++c) {
-        const int buf = c & 1;
+                for (int i = 0; i < 4; ++i) {
+                    const int tt = i < nmine ? tfirst + 4 * i : tfirst;
+                    wn[i] = Wj[(size_t)k * N + 16 * tt + r];
+                }
+                xn = c < Kc ? cst[k * 16 + r] : 0.0;
+                psn = cv[0][c]; nsn = cv[1][c]; tn = cv[2][c]; bn = cv[3][c]; en = cv[4][c];
+            };
+            load(4 * slice);
+            for (int c0 = 4 * slice; c0 < Kc; c0 += stride) {
+                double wc[4];
 #pragma unroll
-        for (int u = 0; u < WPT; ++u) {
-            const int idx = tid + 256 * u;
-            const int kk = idx / NT, nn = idx - kk * NT;
-            s_w[buf][kk][nn] = wv[u];
-        }
-        if (tid < 96) s_v[buf][vq][vk] = vv;       // (a missing t vector stays 0 and unused)
-        double a[4];
+                for (int i = 0; i < 4; ++i) wc[i] = wn[i];
+                const double x = xn, ps = psn, ns = nsn, tv = tn, bb = bn, ee = en;
+                load(c0 + stride < Kc ? c0 + stride : c0);     // the last one re-reads in bounds
+                const bool pos = x >= 0.0;
+                const double om = x * (pos ? ps : ns);
 #pragma unroll
-        for (int st = 0; st < 4; ++st) a[st] = ar[st];
-        if (kc + 16 < S.K) gload(kc + 16);         // the next chunk, in flight during this one's MFMAs
-        __syncthreads();                            // buffer buf written; buffer buf^1 no longer read
-        double av[4];
-#pragma unroll
-        for (int st = 0; st < 4; ++st) {
-            const int kk = 4 * st + kq;
-            const double x = a[st];
-            const bool pos = x >= 0.0;
-            const double om = x * (pos ? s_v[buf][0][kk] : s_v[buf][1][kk]);
-            if (wc == 0) {
-                if (pos ? has_tpos : has_tneg) pb = __builtin_fma(x, pos ? s_v[buf][2][kk] : s_v[buf][3][kk], pb);
-                pb = __builtin_fma(om, s_v[buf][4][kk], pb);
-                pe = __builtin_fma(fabs(x), s_v[buf][5][kk], pe);
-            }
-            av[st] = om;
-        }
-#pragma unroll
-        for (int st = 0; st < 4; ++st) {
-#pragma unroll
-            for (int t = 0; t < TPW; ++t) {
-                const double bv = s_w[buf][4 * st + kq][16 * (wc * TPW + t) + (lane & 15)];
-                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[st], bv, acc[t], 0, 0, 0);
+                for (int i = 0; i < 4; ++i)
+                    if (i < nmine) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(wc[i], om, acc[i], 0, 0, 0);
+                if (sums) {
+                    if (pos ? t_on_pos : t_on_neg) pb = __builtin_fma(x, tv, pb);
+                    pb = __builtin_fma(om, bb, pb);
+                    pe = __builtin_fma(fabs(x), ee, pe);
+                }
             }
         }
-    }
-    // store the contraction (accumulator layout -> row-major)
+        // slices 1.. hand their partial tiles to slice 0 (added in slice order); every
+        // read of the state is done before it is overwritten
+        const int pidx = nslice == 4 ? slice - 1 : tfirst;
+        if (nslice > 1 && slice > 0 && nmine > 0) {
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) {
-        const int col = 16 * (wc * TPW + t) + (lane & 15);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int r = blockIdx.x * (16 * WR) + 16 * wr + 4 * i + kq;
-            if (r < S.M && col < S.N)
-                S.C[(((size_t)mode * S.nbox + box) * S.M + r) * S.N + col] = acc[t][i];
+            for (int q = 0; q < 4; ++q) spart[pidx * 256 + q * 64 + lane] = acc[0][q];
         }
+        __syncthreads();
+        if (nslice > 1 && slice == 0 && nmine > 0) {
+            for (int sl = 1; sl < nslice; ++sl) {
+                const int pi = nslice == 4 ? sl - 1 : tfirst;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[0][q] += spart[pi * 256 + q * 64 + lane];
+            }
+        }
+        if (slice == 0) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (i >= nmine) break;
+                const int tt = tfirst + 4 * i;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) cst[(16 * tt + 4 * q + g) * 16 + r] = acc[i][q];
+            }
+        }
+        __syncthreads();                               // the next step reads the state just written
     }
-    // row sums: lanes {j, j+16, j+32, j+48} of a wave hold row j's partials
-    if (wc == 0) {
-        s_red[wr][lane][0] = pb;
-        s_red[wr][lane][1] = pe;
+    // Lambda_0 rows of this block, and the bias and rounding sums of each row
+    const int n0 = A.w[0];
+    const size_t cbase = ((size_t)mode * A.nbox + box) * A.M;
+    for (int q = tid; q < 16 * n0; q += 256) {
+        const int rr = q / n0, n = q - rr * n0;
+        if (row0 + rr < A.M) A.C[(cbase + row0 + rr) * n0 + n] = cst[n * 16 + rr];
     }
+    spart[wave * 64 + lane] = pb;
+    spart[256 + wave * 64 + lane] = pe;
     __syncthreads();
-    if (wc == 0 && lane < 16) {
-        const double b_ = s_red[wr][lane][0] + s_red[wr][lane + 16][0] + s_red[wr][lane + 32][0] + s_red[wr][lane + 48][0];
-        const double e_ = s_red[wr][lane][1] + s_red[wr][lane + 16][1] + s_red[wr][lane + 32][1] + s_red[wr][lane + 48][1];
-        const int r = blockIdx.x * (16 * WR) + 16 * wr + lane;
-        if (r < S.M) {
-            const size_t o = ((size_t)mode * S.nbox + box) * S.M + r;
-            if (S.beta_init) { S.beta[o] = S.beta_init[r] + b_; S.eps[o] = e_ + fabs(S.beta_init[r]); }
-            else { S.beta[o] += b_; S.eps[o] += e_; }
-        }
+    if (tid < 16 && row0 + tid < A.M) {
+        double b_ = 0.0, e_ = 0.0;
+        for (int w = 0; w < 4; ++w)
+            for (int q = 0; q < 4; ++q) { b_ += spart[w * 64 + tid + 16 * q]; e_ += spart[256 + w * 64 + tid + 16 * q]; }
+        const double bt = A.bt[row0 + tid];
+        A.beta[cbase + row0 + tid] = bt + b_;
+        A.eps[cbase + row0 + tid] = e_ + fabs(bt);
     }
 }
 
@@ -529,30 +543,15 @@ static int nn_ws(int slot, size_t bytes, double** out) {
     return LEB_OK;
 }
 
-static int launch_step(const StepArgs& s, hipStream_t st) {
-    dim3 grid, block(256);
-    if (s.N % 16 != 0 || s.N > 256 || s.K % 16 != 0) return LEB_ENOTSUP;
-    const int tiles = s.N / 16;
-    const int z = s.nmode * s.nbox;
-    if (s.M <= 16 && tiles % 4 == 0) {
-        grid = dim3(1, z);
-        switch (tiles / 4) {
-        case 1: hipLaunchKernelGGL((nn_step_kernel<1, 4, 1>), grid, block, 0, st, s); break;
-        case 2: hipLaunchKernelGGL((nn_step_kernel<1, 4, 2>), grid, block, 0, st, s); break;
-        case 4: hipLaunchKernelGGL((nn_step_kernel<1, 4, 4>), grid, block, 0, st, s); break;
-        default: return LEB_ENOTSUP;
-        }
-    } else {
-        grid = dim3((s.M + 63) / 64, z);
-        switch (tiles) {
-        case 1: hipLaunchKernelGGL((nn_step_kernel<4, 1, 1>), grid, block, 0, st, s); break;
-        case 2: hipLaunchKernelGGL((nn_step_kernel<4, 1, 2>), grid, block, 0, st, s); break;
-        case 4: hipLaunchKernelGGL((nn_step_kernel<4, 1, 4>), grid, block, 0, st, s); break;
-        case 8: hipLaunchKernelGGL((nn_step_kernel<4, 1, 8>), grid, block, 0, st, s); break;
-        case 16: hipLaunchKernelGGL((nn_step_kernel<4, 1, 16>), grid, block, 0, st, s); break;
-        default: return LEB_ENOTSUP;
-        }
+static int launch_chain(const ChainArgs& c, int nmode, int nact, hipStream_t st) {
+    static bool attr = false;
+    if (!attr) {
+        if (hipFuncSetAttribute((const void*)nn_chain_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)CHAIN_STATE_BYTES) != hipSuccess)
+            return LEB_EDEVICE;
+        attr = true;
     }
+    hipLaunchKernelGGL(nn_chain_kernel, dim3((c.M + 15) / 16, nmode, nact), dim3(256), CHAIN_STATE_BYTES, st, c);
     return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
 }
 
@@ -634,12 +633,12 @@ void nn_dims(const leb_mlp_s* net, int* nx, int* nu, int* m) {
 void nn_buffer_sizes(const leb_mlp_s* net, int CB, size_t sizes[NN_NBUF]) {
     const int L = net->L, n0 = net->w[0], m = net->w[L];
     const size_t per = (size_t)CB * NN_MAXW * 8;
-    const size_t lam = (size_t)CB * 3 * NN_MAXW * NN_MAXW * 8;
+    const size_t lam = (size_t)CB * 3 * NN_MAXW * n0 * 8;          // Lambda_0 of every row, mode and box
     const size_t v3 = (size_t)CB * 3 * NN_MAXW * 8;
     const size_t tab[NN_NBUF] = {(size_t)CB * n0 * 8, (size_t)CB * n0 * 8, (size_t)CB * n0 * 8, per * (L - 1),
                                  per * (L - 1), per * (L - 1), (size_t)CB * m * 8, (size_t)CB * m * 8,
                                  per * (L - 1), per * (L - 1), per * (L - 1), per * (L - 1), per * (L - 1),
-                                 per * (L - 1), lam, lam, v3, v3, v3, v3, (size_t)CB * 8};
+                                 per * (L - 1), lam, 8, v3, v3, v3, v3, (size_t)CB * 8};
     for (int q = 0; q < NN_NBUF; ++q) sizes[q] = tab[q];
 }
 
@@ -652,7 +651,7 @@ int nn_bound_run(const leb_mlp_s* net, int64_t units, const double* z, const dou
     int rc;
     double *alpha = buf[0], *c = buf[1], *rho = buf[2], *zhat = buf[3], *lo = buf[4], *hi = buf[5], *g = buf[6],
            *eg = buf[7], *s = buf[8], *t = buf[9], *a = buf[10], *D = buf[11], *e = buf[12], *amax = buf[13],
-           *bufA = buf[14], *bufB = buf[15], *beta = buf[16], *eps = buf[17];
+           *bufA = buf[14], *beta = buf[16], *eps = buf[17];
     uint32_t* fl = (uint32_t*)buf[20];
     auto layer = [&](double* base, int l) { return base + (size_t)l * CB * NN_MAXW; };   // hidden layer l+1
 
@@ -684,30 +683,16 @@ int nn_bound_run(const leb_mlp_s* net, int64_t units, const double* z, const dou
         if ((rc = relax(0))) return rc;
         // backward chain for target layer k (1-based, 2..L): modes 0 upper, 1 lower (, 2 Jacobian)
         auto chain = [&](int k, int nmode, double** lam_out, double** beta_out, double** eps_out) -> int {
-            const int M = net->w[k];
-            double* src = nullptr;
-            double* dst = bufA;
-            double* bt = beta; double* ep = eps;
-            for (int j = k - 1; j >= 1; --j) {        // relax hidden layer j, multiply by W_j
-                StepArgs sa = {};
-                sa.a_shared = (j == k - 1);
-                sa.A = sa.a_shared ? net->W[k - 1] : src;
-                const int jl = j - 1;
-                sa.md[0] = {layer(s, jl), layer(a, jl), layer(t, jl), nullptr};
-                sa.md[1] = {layer(a, jl), layer(s, jl), nullptr, layer(t, jl)};
-                sa.md[2] = {layer(D, jl), layer(D, jl), nullptr, nullptr};
-                sa.bias = net->b[j - 1];
-                sa.e = layer(e, jl);
-                sa.W = net->W[j - 1];
-                sa.C = dst;
-                sa.beta = bt; sa.eps = ep;
-                sa.beta_init = (j == k - 1) ? net->b[k - 1] : nullptr;
-                sa.M = M; sa.K = net->w[j]; sa.N = net->w[j - 1]; sa.nbox = CB; sa.nmode = nmode; sa.nact = nb;
-                if ((rc = launch_step(sa, st))) return rc;
-                src = dst;
-                dst = (dst == bufA) ? bufB : bufA;
-            }
-            *lam_out = src; *beta_out = bt; *eps_out = ep;
+            ChainArgs ca = {};
+            ca.Wt = net->W[k - 1]; ca.bt = net->b[k - 1];
+            for (int l = 0; l < L; ++l) { ca.W[l] = net->W[l]; ca.b[l] = net->b[l]; }
+            for (int l = 0; l <= L; ++l) ca.w[l] = net->w[l];
+            ca.k = k; ca.M = net->w[k]; ca.nbox = CB;
+            ca.s = s; ca.t = t; ca.a = a; ca.D = D; ca.e = e; ca.hi = hi;
+            ca.lstride = (size_t)CB * NN_MAXW;
+            ca.C = bufA; ca.beta = beta; ca.eps = eps;
+            if ((rc = launch_chain(ca, nmode, nb, st))) return rc;
+            *lam_out = bufA; *beta_out = beta; *eps_out = eps;
             return LEB_OK;
         };
         for (int k = 2; k <= L - 1; ++k) {
