@@ -243,7 +243,7 @@ __global__ void __launch_bounds__(256) nn_relax_kernel(RelaxArgs A) {
 // Wave w produces the output tiles w, w + 4, ... of each step; wave 0 also
 // sums the bias and rounding terms of its rows.
 struct ChainArgs {
-    const double* Wt;              // target layer k: [M][w_{k-1}] (shared by every box)
+    const double* WTt;             // target layer k, transposed: [w_{k-1}][M] (shared by every box)
     const double* bt;              // [M]
     const double* W[NN_MAXL];      // layer j at W[j-1]: [w_j][w_{j-1}]
     const double* b[NN_MAXL];
@@ -267,34 +267,28 @@ __global__ void __launch_bounds__(256) nn_chain_kernel(ChainArgs A) {
     __shared__ double spart[768];                      // partial tiles of the k-slices; then the row sums
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 15, g = lane >> 4;
-    const int row0 = 16 * blockIdx.x, mode = blockIdx.y, box = blockIdx.z;
+    const int mode = blockIdx.y, box = blockIdx.z;
     const int K0 = A.w[A.k - 1];
-    // Lambda_k: rows row0 .. row0 + 15 of W_k (zero past M)
-    for (int q = tid; q < 16 * K0; q += 256) {
-        const int rr = q / K0, kk = q - rr * K0;
-        const bool ok = row0 + rr < A.M;
-        const double x = A.Wt[ok ? (size_t)(row0 + rr) * K0 + kk : 0];
-        cst[kk * 16 + rr] = ok ? x : 0.0;
-    }
     // intercept of the selected line: upper mode on x >= 0, lower mode on x < 0
     const bool t_on_pos = mode == 0, t_on_neg = mode == 1;
-    double pb = 0.0, pe = 0.0;
-    for (int j = A.k - 1; j >= 1; --j) {
-        const int K = A.w[j], N = A.w[j - 1];
-        const double* Wj = A.W[j - 1];
+    // list the neurons of layer j that are not stably inactive and stage this
+    // mode's slopes, intercept, bias and rounding weight of each, in list order
+    int Kc = 0;
+    auto prepare = [&](int j) {
+        const int K = A.w[j];
         const size_t vo = (size_t)(j - 1) * A.lstride + (size_t)box * NN_MAXW;
         const bool keep = tid < K && A.hi[vo + tid] > 0.0;
         const uint64_t bal = __ballot(keep);
         if (lane == 0) scnt[wave] = __popcll(bal);
         __syncthreads();                               // counts (and the previous step's state) written
-        int off = 0, Kc = 0;
+        int off = 0;
+        Kc = 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) { off += q < wave ? scnt[q] : 0; Kc += scnt[q]; }
         if (keep) sk[off + __popcll(bal & ((1ull << lane) - 1ull))] = tid;
         if (tid >= Kc) sk[tid] = 0;                    // padding (its x is forced to 0)
         if (tid < CHAIN_PAD - 256) sk[256 + tid] = 0;
         __syncthreads();
-        // this mode's slopes, intercept, bias and rounding weight of each listed neuron
         for (int q = tid; q < CHAIN_PAD; q += 256) {
             const int k = sk[q];
             const size_t o = vo + k;
@@ -306,6 +300,28 @@ __global__ void __launch_bounds__(256) nn_chain_kernel(ChainArgs A) {
             cv[4][q] = A.e[o];
         }
         __syncthreads();
+    };
+    // a target with one step (k = 2) runs every 16-row block in this workgroup with
+    // one list; deeper targets run one block per workgroup
+    const bool single = A.k == 2;
+    const int nrb = (A.M + 15) / 16;
+    if (single) prepare(1);
+    for (int rb = single ? 0 : blockIdx.x; rb < (single ? nrb : blockIdx.x + 1); ++rb) {
+    const int row0 = 16 * rb;
+    // Lambda_k: rows row0 .. row0 + 15 of W_k (zero past M), read from W_k^T so that
+    // both the loads and the LDS stores are consecutive
+    for (int q = tid; q < 16 * K0; q += 256) {
+        const int kk = q >> 4, rr = q & 15;
+        const bool ok = row0 + rr < A.M;
+        const double x = A.WTt[ok ? (size_t)kk * A.M + row0 + rr : 0];
+        cst[q] = ok ? x : 0.0;
+    }
+    if (single) __syncthreads();                       // (otherwise prepare() waits for the state)
+    double pb = 0.0, pe = 0.0;
+    for (int j = A.k - 1; j >= 1; --j) {
+        const int N = A.w[j - 1];
+        const double* Wj = A.W[j - 1];
+        if (!single) prepare(j);
         // work split: ntile >= 3: wave w owns tiles w, w + 4, ... over all k; ntile 2 or
         // 1: the waves split the k-steps of the tile(s) into 2 or 4 slices
         const int ntile = N / 16;
@@ -397,6 +413,128 @@ __global__ void __launch_bounds__(256) nn_chain_kernel(ChainArgs A) {
         const double bt = A.bt[row0 + tid];
         A.beta[cbase + row0 + tid] = bt + b_;
         A.eps[cbase + row0 + tid] = e_ + fabs(bt);
+    }
+    __syncthreads();                                   // the next block reuses the state and sums
+    }
+}
+
+// A target with a single step (k = 2) whose input layer is 16 wide:
+//   Lambda_0 = (W_2 (.) S_1) W_1   ([w_2] x [16]) for one box and mode,
+// every 16-row block in this workgroup.  The listed neurons of layer 1 are the
+// same for every block, so each lane loads the W_1 values of all its k-steps
+// once (up to 16 in registers, all in flight together); the k-steps of a block
+// are split over the four waves (slices) and summed in slice order.  The next
+// block's rows of W_2 are loaded while this block's MFMAs run.
+__global__ void __launch_bounds__(256) nn_chain1_kernel(ChainArgs A) {
+    extern __shared__ double cst[];                    // [NN_MAXW][16]: Omega^T of the current block
+    __shared__ double cv[5][CHAIN_PAD];
+    __shared__ int sk[CHAIN_PAD];
+    __shared__ int scnt[4];
+    __shared__ double spart[768];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    const int mode = blockIdx.y, box = blockIdx.z;
+    const int K = A.w[1], M = A.M;
+    const double* W1 = A.W[0];                         // [w_1][16]
+    const size_t vo = (size_t)box * NN_MAXW;
+    // the listed neurons of layer 1 and this mode's vectors
+    const bool keep = tid < K && A.hi[vo + tid] > 0.0;
+    const uint64_t bal = __ballot(keep);
+    if (lane == 0) scnt[wave] = __popcll(bal);
+    __syncthreads();
+    int off = 0, Kc = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) { off += q < wave ? scnt[q] : 0; Kc += scnt[q]; }
+    if (keep) sk[off + __popcll(bal & ((1ull << lane) - 1ull))] = tid;
+    if (tid >= Kc) sk[tid] = 0;
+    if (tid < CHAIN_PAD - 256) sk[256 + tid] = 0;
+    __syncthreads();
+    for (int q = tid; q < CHAIN_PAD; q += 256) {
+        const int k = sk[q];
+        const size_t o = vo + k;
+        const double s_ = A.s[o], a_ = A.a[o];
+        cv[0][q] = mode == 0 ? s_ : (mode == 1 ? a_ : A.D[o]);
+        cv[1][q] = mode == 0 ? a_ : (mode == 1 ? s_ : A.D[o]);
+        cv[2][q] = mode == 2 ? 0.0 : A.t[o];
+        cv[3][q] = A.b[0][k];
+        cv[4][q] = A.e[o];
+    }
+    // this lane's W_1 values: k-step m of slice `wave` covers list positions
+    // 4 wave + 16 m .. + 3, lane group g takes + g
+    double wv[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        const int c = 4 * wave + 16 * m + g;
+        const double x = W1[(size_t)sk[c < CHAIN_PAD ? c : 0] * 16 + r];
+        wv[m] = c < Kc ? x : 0.0;
+    }
+    const bool t_on_pos = mode == 0, t_on_neg = mode == 1;
+    const int nrb = (M + 15) / 16;
+    const size_t cbase = ((size_t)mode * A.nbox + box) * M;
+    // rows of W_2 for block rb: thread q < 16 K0 takes (kk, rr) = (q / 16, q % 16) for q = tid + 256 u
+    const int K0 = K;                                   // = w_1, the columns of W_2
+    double nx[16];
+    auto fetch = [&](int rb) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int q = tid + 256 * u, kk = q >> 4, rr = q & 15;
+            const bool ok = q < 16 * K0 && 16 * rb + rr < M;
+            const double x = A.WTt[ok ? (size_t)kk * M + 16 * rb + rr : 0];
+            nx[u] = ok ? x : 0.0;
+        }
+    };
+    fetch(0);
+    for (int rb = 0; rb < nrb; ++rb) {
+        __syncthreads();                               // vectors staged; the previous block is done with cst
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int q = tid + 256 * u;
+            if (q < 16 * NN_MAXW) cst[q] = nx[u];
+        }
+        __syncthreads();
+        if (rb + 1 < nrb) fetch(rb + 1);
+        d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+        double pb = 0.0, pe = 0.0;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const int c = 4 * wave + 16 * m + g;
+            if (4 * wave + 16 * m >= Kc) break;
+            const int k = sk[c];
+            const double x = c < Kc ? cst[k * 16 + r] : 0.0;
+            const bool pos = x >= 0.0;
+            const double om = x * (pos ? cv[0][c] : cv[1][c]);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(wv[m], om, acc, 0, 0, 0);
+            if (pos ? t_on_pos : t_on_neg) pb = __builtin_fma(x, cv[2][c], pb);
+            pb = __builtin_fma(om, cv[3][c], pb);
+            pe = __builtin_fma(fabs(x), cv[4][c], pe);
+        }
+        if (wave > 0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) spart[(wave - 1) * 256 + q * 64 + lane] = acc[q];
+        }
+        __syncthreads();
+        if (wave == 0) {
+            for (int sl = 1; sl < 4; ++sl) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q] += spart[(sl - 1) * 256 + q * 64 + lane];
+            }
+            // accumulator element q: row 4 q + g... of the transposed tile: n = 4 q + g, row = r
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (16 * rb + r < M) A.C[(cbase + 16 * rb + r) * 16 + 4 * q + g] = acc[q];
+        }
+        __syncthreads();                               // partial tiles read
+        spart[tid] = pb;
+        spart[256 + tid] = pe;
+        __syncthreads();
+        if (tid < 16 && 16 * rb + tid < M) {
+            double b_ = 0.0, e_ = 0.0;
+            for (int w = 0; w < 4; ++w)
+                for (int q = 0; q < 4; ++q) { b_ += spart[w * 64 + tid + 16 * q]; e_ += spart[256 + w * 64 + tid + 16 * q]; }
+            const double bt = A.bt[16 * rb + tid];
+            A.beta[cbase + 16 * rb + tid] = bt + b_;
+            A.eps[cbase + 16 * rb + tid] = e_ + fabs(bt);
+        }
     }
 }
 
@@ -547,11 +685,18 @@ static int launch_chain(const ChainArgs& c, int nmode, int nact, hipStream_t st)
     static bool attr = false;
     if (!attr) {
         if (hipFuncSetAttribute((const void*)nn_chain_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)CHAIN_STATE_BYTES) != hipSuccess ||
+            hipFuncSetAttribute((const void*)nn_chain1_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)CHAIN_STATE_BYTES) != hipSuccess)
             return LEB_EDEVICE;
         attr = true;
     }
-    hipLaunchKernelGGL(nn_chain_kernel, dim3((c.M + 15) / 16, nmode, nact), dim3(256), CHAIN_STATE_BYTES, st, c);
+    if (c.k == 2 && c.w[0] == 16) {
+        hipLaunchKernelGGL(nn_chain1_kernel, dim3(1, nmode, nact), dim3(256), CHAIN_STATE_BYTES, st, c);
+        return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
+    }
+    const unsigned rbs = c.k == 2 ? 1u : (unsigned)((c.M + 15) / 16);
+    hipLaunchKernelGGL(nn_chain_kernel, dim3(rbs, nmode, nact), dim3(256), CHAIN_STATE_BYTES, st, c);
     return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
 }
 
@@ -684,7 +829,7 @@ int nn_bound_run(const leb_mlp_s* net, int64_t units, const double* z, const dou
         // backward chain for target layer k (1-based, 2..L): modes 0 upper, 1 lower (, 2 Jacobian)
         auto chain = [&](int k, int nmode, double** lam_out, double** beta_out, double** eps_out) -> int {
             ChainArgs ca = {};
-            ca.Wt = net->W[k - 1]; ca.bt = net->b[k - 1];
+            ca.WTt = net->WT[k - 1]; ca.bt = net->b[k - 1];
             for (int l = 0; l < L; ++l) { ca.W[l] = net->W[l]; ca.b[l] = net->b[l]; }
             for (int l = 0; l <= L; ++l) ca.w[l] = net->w[l];
             ca.k = k; ca.M = net->w[k]; ca.nbox = CB;
