@@ -398,9 +398,17 @@ def nn_crown_flops(widths):
     return 2 * mac
 
 
+# MFMA instructions per box of the MLP bound on the 16-256-256-256-12 workload
+# (SQ_INSTS_MFMA / boxes, profiles/nn_chain_kernel_mlp_bound_64x50.md), each
+# v_mfma_f64_16x16x4f64 2,048 FLOP; None until taken for the kernels as they are now.
+NN_MFMA_INSTS_PER_BOX = 76.96e6 / 3200
+
+
 def nn_roofline(leb, W, dev, stream, args):
     """MLP bound (CROWN + Theorem 2) on 64 x 50 boxes of the 16-256-256-256-12
-    network: FP64 MFMA, timed with HIP events on its stream."""
+    network: FP64 MFMA, timed with HIP events on its stream.  `achieved` counts
+    the dense CROWN FLOPs (the method's work); `executed_frac` the MFMA FLOPs
+    the kernels issue (stably inactive neurons skipped) against the peak."""
     import torch
     b = W.nn_cfg()
     net = leb.MLP(b.net.W, b.net.b, b.net.nx, True)
@@ -426,7 +434,9 @@ def nn_roofline(leb, W, dev, stream, args):
     return {"workload": "MLP bound, 64 x 50 boxes, widths %s" % widths, "ms_per_call": round(ms, 4),
             "timestep_bounds_per_s": round(boxes / (ms * 1e-3), 1),
             "bound": "mfma", "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "flops_per_box": nn_crown_flops(widths)}
+            "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "flops_per_box": nn_crown_flops(widths),
+            "executed_frac": None if NN_MFMA_INSTS_PER_BOX is None else
+            round(NN_MFMA_INSTS_PER_BOX * 2048 * boxes / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)}
 
 
 def nn_learned(leb, W, dev, stream, args):
