@@ -29,7 +29,9 @@ Prints ONE JSON line.  Extra objects:
                   point on a bounded sample of trajectories, on all host
                   cores and on one;
   latency, adjoint, batched_uneven (batch against per-problem launches),
-  roofline_nn, learned_nn.
+  roofline_nn, learned_nn, nominal_pgd (nominal points refined by projected
+  gradient descent on the bound's width against random nominal points at
+  an equal GPU time budget).
 """
 from __future__ import annotations
 
@@ -249,6 +251,7 @@ def main():
     extra = {} if args.no_extra else {
         "latency": latency(leb, W, dev, stream),
         "adjoint": adjoint(leb, W, dev, stream),
+        "nominal_pgd": nominal_pgd(leb, W, dev, stream),
         "roofline_nn": nn_roofline(leb, W, dev, stream, args),
         "learned_nn": nn_learned(leb, W, dev, stream, args),
         "batched_uneven": batched_uneven(leb, W, dev, stream, args)}
@@ -381,6 +384,70 @@ def adjoint(leb, W, dev, stream):
         torch.cuda.synchronize()
         us = e0.elapsed_time(e1) / reps * 1e3
         res["%dx40" % B] = {"us_per_call": round(us, 2), "timestep_gradients_per_s": round(B * 40 / (us * 1e-6), 1)}
+    return res
+
+
+def _sample_nominal(leb, dyn, a0, sigma, radius, K, gen, stream, chunk=64):
+    """Narrowest bound (travelling box) over K nominal points drawn uniformly
+    from a0 +/- radius sigma, in batched launches of `chunk` candidates."""
+    import torch
+    nx = dyn.nx
+    U = a0.shape[0] * a0.shape[1]
+    best = None
+    done = 0
+    while done < K:
+        k = min(chunk, K - done)
+        u = torch.rand((k,) + tuple(a0.shape), generator=gen, dtype=torch.float64, device=a0.device)
+        a = (a0.unsqueeze(0) + (2.0 * u - 1.0) * radius * sigma.unsqueeze(0)).reshape(k * a0.shape[0], a0.shape[1], -1)
+        sg = sigma.unsqueeze(0).expand(k, -1, -1, -1).reshape(a.shape).contiguous()
+        o = leb.analytic_bound(dyn, a[..., :nx].contiguous(), a[..., nx:].contiguous(), sg, stream=stream)
+        w = (o["r_hi"] - o["r_lo"]).sum(-1).reshape(k, U).min(0).values
+        best = w if best is None else torch.minimum(best, w)
+        done += k
+    return best
+
+
+def nominal_pgd(leb, W, dev, stream):
+    """Nominal-point refinement (leb_pgd_nominal, 10 steps, search radius
+    sigma, travelling box) on the planar quadrotor (64 nominal points) and the
+    28-quadrotor chain (40 steps), against the best of as many random nominal
+    points as the GPU bounds in the same time."""
+    import torch
+    res = {}
+    radius, steps, lr = 1.0, 10, 0.3
+    for name, b in (("planar_quadrotor_64", W.planar_quad_cfg(N=64)), ("chain28_40", W.chain_cfg(N=40))):
+        dyn = leb.dynamics_like(b.dyn)
+        t = lambda a: torch.from_numpy(a).to(dev)
+        z0, v0, sg = t(b.z), t(b.v), t(b.sigma)
+        a0 = torch.cat([z0, v0], -1)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        leb.pgd_nominal(dyn, z0, v0, sg, radius=radius, steps=steps, lr=lr, stream=stream)
+        reps = 10
+        e0.record(stream)
+        for _ in range(reps):
+            z, v, w, w0 = leb.pgd_nominal(dyn, z0, v0, sg, radius=radius, steps=steps, lr=lr, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_pgd = e0.elapsed_time(e1) / reps
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(11)
+        _sample_nominal(leb, dyn, a0, sg, radius, 128, gen, stream)     # warm every library call
+        e0.record(stream)
+        _sample_nominal(leb, dyn, a0, sg, radius, 512, gen, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        per = e0.elapsed_time(e1) / 512
+        K = max(4 * steps, int(-(-ms_pgd // per)))
+        e0.record(stream)
+        best = _sample_nominal(leb, dyn, a0, sg, radius, K, gen, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        w, w0 = w.reshape(-1), w0.reshape(-1)
+        res[name] = {"ms_pgd": round(ms_pgd, 4), "ms_sampling": round(e0.elapsed_time(e1), 4), "samples": K,
+                     "mean_width_start": float(w0.mean()), "mean_width_sampling": float(best.mean()),
+                     "mean_width_pgd": float(w.mean()), "pgd_better_frac": float((w < best).double().mean()),
+                     "pgd_not_worse_frac": float((w <= best).double().mean())}
     return res
 
 

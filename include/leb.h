@@ -135,6 +135,35 @@ int leb_backward(const leb_dynamics* dyn, int32_t batch, int32_t N, const double
                  const double* mu, const double* sigma, const double* g_lo, const double* g_hi,
                  double* gz, double* gv, double* gmu, double* gsigma, void* stream);
 
+/*
+ * leb_pgd_nominal -- refinement of the nominal (linearization) point (the
+ * nominal-point optimization of the results section, Table II): projected
+ * gradient descent on the width
+ *     W(a~) = sum_l (r_hi,l - r_lo,l)
+ * of the path-based bound linearized at a~, searching a~ in a0 +/- radius sigma
+ * (a0 = [z0; v0], the start; 0 <= radius <= 1).  The set the bound covers is
+ *   fixed_box = 0: the travelling box a~ + mu0 +/- sigma (a fixed perturbation
+ *     radius around the nominal point, the paper's setting): dW/da~ = dW/dz;
+ *   fixed_box = 1: the fixed box (a0 + mu0) +/- sigma, passed as
+ *     a~ + mu +/- sigma with mu = a0 + mu0 - a~: dW/da~ = dW/dz - dW/dmu
+ *     (keep |mu0| + radius sigma <= sigma so that a~ stays inside the box),
+ * derivatives from the adjoint of leb_backward.  Step s moves each coordinate
+ * by lr radius sigma_i (1 - s / steps) against the sign of its derivative
+ * (not at all where it is 0) and projects onto the search box; `steps` steps
+ * take steps + 1 bound and `steps` adjoint evaluations.  CHAIN dynamics (as
+ * leb_backward).
+ *   z0, v0, sigma  [batch][N][nx], [batch][N][nu], [batch][N][nx+nu]
+ *   mu0            [batch][N][nx+nu] or NULL (0): box centre offset
+ *   z, v           outputs: the narrowest iterate seen (the start included)
+ *   width [batch][N] output: its W; width0 [batch][N] optional: W(a0)
+ * LEB_EINVAL for fixed_box not 0/1, radius outside [0, 1], lr not positive
+ * and finite, steps < 0.  Uses a library-owned grow-only workspace, ordered
+ * across streams like the other workspaces.
+ */
+int leb_pgd_nominal(const leb_dynamics* dyn, int32_t batch, int32_t N, const double* z0, const double* v0,
+                    const double* mu0, const double* sigma, int32_t fixed_box, double radius, int32_t steps,
+                    double lr, double* z, double* v, double* width, double* width0, void* stream);
+
 /* Opaque ReLU MLP prepared for the device (weights converted to FP64 and
  * laid out for the kernels).  Owned by the library. */
 typedef struct leb_mlp_s* leb_mlp;

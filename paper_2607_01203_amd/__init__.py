@@ -118,6 +118,10 @@ def lib():
         L.leb_tube_map.restype = ctypes.c_int
         L.leb_zonotope_hull.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, vp]
         L.leb_zonotope_hull.restype = ctypes.c_int
+        L.leb_pgd_nominal.argtypes = [ctypes.POINTER(Dynamics), ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp,
+                                      ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_double, vp, vp, vp,
+                                      vp, vp]
+        L.leb_pgd_nominal.restype = ctypes.c_int
         L.leb_launch_timing.argtypes = [ctypes.c_int32]
         L.leb_launch_timing.restype = ctypes.c_int
         L.leb_launch_times.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_float), ctypes.c_int32,
@@ -237,6 +241,25 @@ def analytic_bound(dyn: Dynamics, z, v, sigma, mu=None, pad: float = 0.0, zonoto
         _dev_ptr(out.get("B"), "B", f64), _stream(stream))
     _check(rc)
     return out
+
+
+def pgd_nominal(dyn: Dynamics, z0, v0, sigma, mu0=None, radius=0.5, steps=20, lr=0.25, fixed_box=False,
+                stream=None):
+    """Linearization point refined by projected gradient descent on the
+    bound's width (see leb.h: leb_pgd_nominal).  Returns (z, v, width, width0)."""
+    import torch
+    f64 = torch.float64
+    B, N = int(z0.shape[0]), int(z0.shape[1])
+    z = torch.empty_like(z0)
+    v = torch.empty_like(v0)
+    w = torch.empty((B, N), dtype=f64, device=z0.device)
+    w0 = torch.empty((B, N), dtype=f64, device=z0.device)
+    _check(lib().leb_pgd_nominal(ctypes.byref(dyn), B, N, _dev_ptr(z0, "z0", f64), _dev_ptr(v0, "v0", f64),
+                                 _dev_ptr(mu0, "mu0", f64), _dev_ptr(sigma, "sigma", f64), int(bool(fixed_box)),
+                                 float(radius), int(steps), float(lr),
+                                 _dev_ptr(z, "z", f64), _dev_ptr(v, "v", f64), _dev_ptr(w, "width", f64),
+                                 _dev_ptr(w0, "width0", f64), _stream(stream)))
+    return z, v, w, w0
 
 
 def zonotope_hull(G, c=None, stream=None):
