@@ -8,8 +8,9 @@ true-remainder sampler; `nn.py` holds the neural-network bounds and
 
 Dynamics are described by plain keyword parameters (never by GPU-library
 types): `kind` is one of "linear", "quadratic", "sin1d", "sincos2d",
-"chain"; chain dynamics also take n_units, dt, m, g, arm, inertia,
-k_spring, rest_len.
+"chain", "satellite", "quad3d"; chain dynamics also take n_units, dt, m, g,
+arm, inertia, k_spring, rest_len; the satellite dt and its inertia J; the
+3-D quadrotor dt, m, g and J = (Jx, Jy, Jz).
 """
 from __future__ import annotations
 
@@ -25,7 +26,7 @@ _SRC_GRAD = os.path.join(_HERE, "leb_grad.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-KINDS = {"linear": 0, "quadratic": 1, "sin1d": 2, "sincos2d": 3, "chain": 4}
+KINDS = {"linear": 0, "quadratic": 1, "sin1d": 2, "sincos2d": 3, "chain": 4, "satellite": 5, "quad3d": 6}
 MODES = {"path": 0, "expand": 1, "classic": 2}
 FLAG_UNBOUNDED, FLAG_BAD_INPUT, FLAG_HULL = 1, 2, 4
 
@@ -46,7 +47,7 @@ class _Dyn(ctypes.Structure):
                 ("n_units", ctypes.c_int32), ("dt", ctypes.c_double), ("m", ctypes.c_double),
                 ("g", ctypes.c_double), ("arm", ctypes.c_double), ("inertia", ctypes.c_double),
                 ("k_spring", ctypes.c_double), ("rest_len", ctypes.c_double),
-                ("Q", ctypes.POINTER(ctypes.c_double))]
+                ("Q", ctypes.POINTER(ctypes.c_double)), ("J", ctypes.c_double * 3)]
 
 
 def lib():
@@ -82,12 +83,22 @@ class Dyn:
     """Oracle-side dynamics description (keeps the Q array alive)."""
 
     def __init__(self, kind: str, nx: int, nu: int = 0, n_units: int = 0, dt=0.05, m=1.0, g=9.81,
-                 arm=0.25, inertia=0.01, k_spring=2.0, rest_len=1.0, Q=None):
+                 arm=0.25, inertia=0.01, k_spring=2.0, rest_len=1.0, Q=None, J=(0.0, 0.0, 0.0)):
         self.kind, self.nx, self.nu = kind, nx, nu
         self.n = nx + nu
         self.Q = None if Q is None else np.ascontiguousarray(Q, dtype=np.float64)
         self.c = _Dyn(KINDS[kind], nx, nu, n_units, dt, m, g, arm, inertia, k_spring, rest_len,
-                      _ptr(self.Q))
+                      _ptr(self.Q), (ctypes.c_double * 3)(*J))
+
+    @staticmethod
+    def satellite(dt, inertia=(5.0, 2.0, 1.0)):
+        """Satellite attitude (quaternion q, rates w; torques v): nx = 7, nu = 3."""
+        return Dyn("satellite", 7, 3, 0, dt, J=tuple(inertia))
+
+    @staticmethod
+    def quad3d(dt, m, g, J):
+        """3-D quadrotor (position, Euler angles, velocity, body rates; thrust, torques): nx = 12, nu = 4."""
+        return Dyn("quad3d", 12, 4, 0, dt, m, g, J=tuple(J))
 
     @staticmethod
     def chain(n_units, dt=0.05, m=1.0, g=9.81, arm=0.25, inertia=0.01, k_spring=2.0, rest_len=1.0):
@@ -95,7 +106,13 @@ class Dyn:
 
     @staticmethod
     def like(obj):
-        """Build from any object exposing chain parameters (n_units, dt, m, ...)."""
+        """Build from any object exposing chain parameters (n_units, dt, m, ...), or
+        a satellite / 3-D quadrotor description (kind, dt, m, g, J)."""
+        kind = getattr(obj, "kind", "chain")
+        if kind == "satellite":
+            return Dyn.satellite(obj.dt, obj.J)
+        if kind == "quad3d":
+            return Dyn.quad3d(obj.dt, obj.m, obj.g, obj.J)
         return Dyn.chain(obj.n_units, obj.dt, obj.m, obj.g, obj.arm, obj.inertia, obj.k_spring,
                          obj.rest_len)
 

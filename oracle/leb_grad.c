@@ -34,6 +34,7 @@ typedef struct {
     int32_t kind, nx, nu, n_units;
     double dt, m, g, arm, inertia, k_spring, rest_len;
     const double* Q;
+    double J[3];
 } orc_dyn;
 
 enum { ORC_CHAIN = 4 };

@@ -52,7 +52,8 @@
 
 typedef struct { double lo, hi; } iv;
 
-enum { ORC_LINEAR = 0, ORC_QUADRATIC = 1, ORC_SIN1D = 2, ORC_SINCOS2D = 3, ORC_CHAIN = 4 };
+enum { ORC_LINEAR = 0, ORC_QUADRATIC = 1, ORC_SIN1D = 2, ORC_SINCOS2D = 3, ORC_CHAIN = 4, ORC_SATELLITE = 5,
+       ORC_QUAD3D = 6 };
 enum { ORC_PATH = 0, ORC_EXPAND = 1, ORC_CLASSIC = 2 };
 enum { ORC_FLAG_UNBOUNDED = 1u, ORC_FLAG_BAD_INPUT = 2u, ORC_FLAG_HULL = 4u };
 
@@ -62,6 +63,7 @@ typedef struct {
     int32_t n_units;       /* chain: number of planar quadrotors */
     double dt, m, g, arm, inertia, k_spring, rest_len;
     const double* Q;       /* quadratic: [nx][n][n] symmetric Hessians */
+    double J[3];           /* satellite: inertia diag(I_S); 3-D quadrotor: Jx, Jy, Jz */
 } orc_dyn;
 
 /* ------------------------------------------------ directed FP64 rounding */
@@ -309,12 +311,166 @@ static int sincos_entry(const orc_dyn* d, int l, int k, int j, const iv* X, iv* 
     return 1;
 }
 
+/* Satellite (appendix, dynamical system definitions): a = (q0..q3, w1..w3,
+ * v1..v3), f = x + dt xdot with qdot = zeta(w) q (zeta carries the 1/2) and
+ * wdot = I^-1 (v - w x (I w)), I = diag(J).  Every second derivative is a
+ * constant: qdot_r is bilinear in (w, q) with coefficients +-1/2, and
+ *   wdot_1 = ... - (I3 - I2)/I1 w2 w3,  wdot_2 = ... - (I1 - I3)/I2 w1 w3,
+ *   wdot_3 = ... - (I2 - I1)/I3 w1 w2. */
+static const signed char SAT_Q[4][3][3] = {          /* row r of qdot: (w index 1..3, q index, sign) */
+    {{1, 1, -1}, {2, 2, -1}, {3, 3, -1}},
+    {{1, 0, 1}, {3, 2, 1}, {2, 3, -1}},
+    {{2, 0, 1}, {3, 1, -1}, {1, 3, 1}},
+    {{3, 0, 1}, {2, 1, 1}, {1, 2, -1}}};
+
+static iv sat_euler_coef(const orc_dyn* d, int row) {       /* -(I_b - I_c)/I_a times dt, row = a - 1 */
+    static const int B[3] = {2, 0, 1}, C[3] = {1, 2, 0};
+    iv num = isub(ipt(d->J[B[row]]), ipt(d->J[C[row]]));
+    return imul(ipt(-d->dt), imul(num, irecip(ipt(d->J[row]))));
+}
+
+static int sat_entry(const orc_dyn* d, int l, int k, int j, iv* out) {
+    if (l < 4) {
+        for (int t = 0; t < 3; ++t) {
+            int w = 3 + SAT_Q[l][t][0], q = SAT_Q[l][t][1];
+            if (k == w && j == q) { *out = ipt(0.5 * SAT_Q[l][t][2] * d->dt); return 1; }
+        }
+        return 0;
+    }
+    if (l < 7) {
+        static const int K[3] = {6, 6, 5}, Jn[3] = {5, 4, 4};
+        if (k == K[l - 4] && j == Jn[l - 4]) { *out = sat_euler_coef(d, l - 4); return 1; }
+    }
+    return 0;
+}
+
+/* 3-D quadrotor (appendix): a = (px, py, pz, phi, theta, psi, vx, vy, vz, p,
+ * q, r, T, tau_phi, tau_theta, tau_psi), f = x + dt xdot.  Curvature sits in
+ *   phidot   = p + A tan(theta),       A = q sin(phi) + r cos(phi)
+ *   thetadot = B,                      B = q cos(phi) - r sin(phi)
+ *   psidot   = A sec(theta)
+ *   v dot    = (T/m) (Rx, Ry, Rz) - (0, 0, g), with
+ *     Rx = cpsi stheta cphi + spsi sphi,  Ry = spsi stheta cphi - cpsi sphi,
+ *     Rz = ctheta cphi
+ *   pdot = (Jy - Jz)/Jx q r, qdot = (Jz - Jx)/Jy p r, rdot = (Jx - Jy)/Jz p q.
+ * Entries (k >= j) are natural interval extensions of the second
+ * derivatives written with A and B kept whole, sec = 1/cos(theta),
+ * tan = sin(theta) sec (a cos(theta) interval that is not positive makes
+ * the entry unbounded); each entry is multiplied by dt. */
+enum { Q3_PHI = 3, Q3_TH = 4, Q3_PSI = 5, Q3_P = 9, Q3_Q = 10, Q3_R = 11, Q3_T = 12 };
+
+/* rows phidot, thetadot, psidot: the structurally non-zero entries (k >= j) */
+static int q3_att_entry(int l, int k, int j) {
+    if (j == Q3_PHI) return k == Q3_PHI || k == Q3_Q || k == Q3_R || (l != 4 && k == Q3_TH);
+    if (j == Q3_TH) return l != 4 && (k == Q3_TH || k == Q3_Q || k == Q3_R);
+    return 0;
+}
+
+static int quad3d_entry(const orc_dyn* d, int l, int k, int j, const iv* X, iv* out) {
+    iv H;
+    if (l >= 3 && l <= 5) {
+        if (!q3_att_entry(l, k, j)) return 0;
+        iv sf = isin(X[Q3_PHI]), cf = icos(X[Q3_PHI]);
+        iv A = iadd(imul(X[Q3_Q], sf), imul(X[Q3_R], cf));
+        iv B = isub(imul(X[Q3_Q], cf), imul(X[Q3_R], sf));
+        iv sec = ipt(0.0), tn = ipt(0.0), sec2 = ipt(0.0);
+        if (l != 4) {
+            iv st = isin(X[Q3_TH]), ct = icos(X[Q3_TH]);
+            if (ct.lo <= 0.0) return -1;            /* sec, tan unbounded */
+            sec = irecip(ct);
+            tn = imul(st, sec);
+            sec2 = isq(sec);
+        }
+        if (l == 3) {
+            if (k == Q3_PHI && j == Q3_PHI) H = ineg(imul(A, tn));
+            else if (k == Q3_TH && j == Q3_PHI) H = imul(B, sec2);
+            else if (k == Q3_Q && j == Q3_PHI) H = imul(cf, tn);
+            else if (k == Q3_R && j == Q3_PHI) H = ineg(imul(sf, tn));
+            else if (k == Q3_TH) H = imul(iscale(2.0, A), imul(sec2, tn));
+            else if (k == Q3_Q) H = imul(sf, sec2);
+            else H = imul(cf, sec2);
+        } else if (l == 4) {
+            if (k == Q3_PHI) H = ineg(B);
+            else if (k == Q3_Q) H = ineg(sf);
+            else H = ineg(cf);
+        } else {
+            if (k == Q3_PHI && j == Q3_PHI) H = ineg(imul(A, sec));
+            else if (k == Q3_TH && j == Q3_PHI) H = imul(B, imul(sec, tn));
+            else if (k == Q3_Q && j == Q3_PHI) H = imul(cf, sec);
+            else if (k == Q3_R && j == Q3_PHI) H = ineg(imul(sf, sec));
+            else if (k == Q3_TH) H = imul(A, imul(sec, iadd(isq(tn), sec2)));
+            else if (k == Q3_Q) H = imul(sf, imul(sec, tn));
+            else H = imul(cf, imul(sec, tn));
+        }
+    } else if (l >= 6 && l <= 8) {
+        int a = (k == Q3_PHI || k == Q3_TH || k == Q3_PSI) ? k : (k == Q3_T ? Q3_T : -1);
+        int b = (j == Q3_PHI || j == Q3_TH || j == Q3_PSI) ? j : -1;
+        if (a < 0 || b < 0) return 0;
+        iv sf = isin(X[Q3_PHI]), cf = icos(X[Q3_PHI]);
+        iv st = isin(X[Q3_TH]), ct = icos(X[Q3_TH]);
+        iv sp = isin(X[Q3_PSI]), cp = icos(X[Q3_PSI]);
+        iv im = imk(div_rd(1.0, d->m), div_ru(1.0, d->m));
+        iv D;                        /* the derivative of R in (a, b); a = T: the first derivative in b */
+        int r = l - 6;               /* 0: Rx, 1: Ry, 2: Rz */
+        if (a == Q3_T) {
+            if (r == 0) {
+                if (b == Q3_PHI) D = isub(imul(sp, cf), imul(imul(cp, st), sf));
+                else if (b == Q3_TH) D = imul(imul(cp, ct), cf);
+                else D = isub(imul(cp, sf), imul(imul(sp, st), cf));
+            } else if (r == 1) {
+                if (b == Q3_PHI) D = ineg(iadd(imul(imul(sp, st), sf), imul(cp, cf)));
+                else if (b == Q3_TH) D = imul(imul(sp, ct), cf);
+                else D = iadd(imul(imul(cp, st), cf), imul(sp, sf));
+            } else {
+                if (b == Q3_PHI) D = ineg(imul(ct, sf));
+                else if (b == Q3_TH) D = ineg(imul(st, cf));
+                else return 0;
+            }
+            H = imul(im, D);
+        } else {
+            if (r == 0) {
+                if (a == Q3_PHI) D = ineg(iadd(imul(imul(cp, st), cf), imul(sp, sf)));          /* (phi, phi) */
+                else if (a == Q3_TH && b == Q3_PHI) D = ineg(imul(imul(cp, ct), sf));
+                else if (a == Q3_TH) D = ineg(imul(imul(cp, st), cf));                          /* (theta, theta) */
+                else if (b == Q3_PHI) D = iadd(imul(imul(sp, st), sf), imul(cp, cf));           /* (psi, phi) */
+                else if (b == Q3_TH) D = ineg(imul(imul(sp, ct), cf));                          /* (psi, theta) */
+                else D = ineg(iadd(imul(imul(cp, st), cf), imul(sp, sf)));                      /* (psi, psi) */
+            } else if (r == 1) {
+                if (a == Q3_PHI) D = isub(imul(cp, sf), imul(imul(sp, st), cf));
+                else if (a == Q3_TH && b == Q3_PHI) D = ineg(imul(imul(sp, ct), sf));
+                else if (a == Q3_TH) D = ineg(imul(imul(sp, st), cf));
+                else if (b == Q3_PHI) D = isub(imul(sp, cf), imul(imul(cp, st), sf));
+                else if (b == Q3_TH) D = imul(imul(cp, ct), cf);
+                else D = isub(imul(cp, sf), imul(imul(sp, st), cf));
+            } else {
+                if (a == Q3_PHI) D = ineg(imul(ct, cf));
+                else if (a == Q3_TH && b == Q3_PHI) D = imul(st, sf);
+                else if (a == Q3_TH) D = ineg(imul(ct, cf));
+                else return 0;
+            }
+            H = imul(imul(im, X[Q3_T]), D);
+        }
+    } else if (l >= 9 && l <= 11) {
+        static const int K[3] = {Q3_R, Q3_R, Q3_Q}, Jn[3] = {Q3_Q, Q3_P, Q3_P};
+        static const int NA[3] = {1, 2, 0}, NB[3] = {2, 0, 1};
+        int i = l - 9;
+        if (k != K[i] || j != Jn[i]) return 0;
+        H = imul(isub(ipt(d->J[NA[i]]), ipt(d->J[NB[i]])), irecip(ipt(d->J[i])));
+    } else {
+        return 0;
+    }
+    *out = imul(ipt(d->dt), H);
+    return 1;
+}
+
 static int hess_entry(const orc_dyn* d, int l, int k, int j, const iv* X, iv* out) {
     switch (d->kind) {
     case ORC_LINEAR: return 0;
     case ORC_QUADRATIC: return quad_entry(d, l, k, j, out);
     case ORC_SIN1D: case ORC_SINCOS2D: return sincos_entry(d, l, k, j, X, out);
     case ORC_CHAIN: return chain_entry(d, l, k, j, X, out);
+    case ORC_SATELLITE: return sat_entry(d, l, k, j, out);
+    case ORC_QUAD3D: return quad3d_entry(d, l, k, j, X, out);
     }
     return 0;
 }
@@ -535,6 +691,76 @@ static void test_nonlin(const orc_dyn* d, int l, const double* a, double* val, d
         *val = sin(a[0]); *mag = fabs(*val);
         if (grad) grad[0] = cos(a[0]);
         return;
+    case ORC_SATELLITE:
+        if (l < 4) {
+            for (int t = 0; t < 3; ++t) {
+                int w = 3 + SAT_Q[l][t][0], q = SAT_Q[l][t][1];
+                double c = 0.5 * SAT_Q[l][t][2] * d->dt;
+                double tv = c * a[w] * a[q];
+                *val += tv; *mag += fabs(tv);
+                if (grad) { grad[w] += c * a[q]; grad[q] += c * a[w]; }
+            }
+        } else if (l < 7) {
+            static const int K[3] = {6, 6, 5}, Jn[3] = {5, 4, 4}, B[3] = {2, 0, 1}, C[3] = {1, 2, 0};
+            int r = l - 4;
+            double c = -d->dt * (d->J[B[r]] - d->J[C[r]]) / d->J[r];
+            *val = c * a[K[r]] * a[Jn[r]]; *mag = fabs(*val);
+            if (grad) { grad[K[r]] = c * a[Jn[r]]; grad[Jn[r]] = c * a[K[r]]; }
+        }
+        return;
+    case ORC_QUAD3D: {
+        double dt = d->dt;
+        if (l >= 3 && l <= 5) {
+            double sf = sin(a[Q3_PHI]), cf = cos(a[Q3_PHI]), st = sin(a[Q3_TH]), ct = cos(a[Q3_TH]);
+            double q = a[Q3_Q], r = a[Q3_R];
+            double A = q * sf + r * cf, B = q * cf - r * sf, Am = fabs(q * sf) + fabs(r * cf);
+            if (l == 4) {
+                *val = dt * B; *mag = dt * (fabs(q * cf) + fabs(r * sf));
+                if (grad) { grad[Q3_PHI] = -dt * A; grad[Q3_Q] = dt * cf; grad[Q3_R] = -dt * sf; }
+            } else if (l == 3) {
+                double tn = st / ct;
+                *val = dt * A * tn; *mag = dt * Am * fabs(tn);
+                if (grad) {
+                    grad[Q3_PHI] = dt * B * tn; grad[Q3_TH] = dt * A / (ct * ct);
+                    grad[Q3_Q] = dt * sf * tn; grad[Q3_R] = dt * cf * tn;
+                }
+            } else {
+                *val = dt * A / ct; *mag = dt * Am / fabs(ct);
+                if (grad) {
+                    grad[Q3_PHI] = dt * B / ct; grad[Q3_TH] = dt * A * st / (ct * ct);
+                    grad[Q3_Q] = dt * sf / ct; grad[Q3_R] = dt * cf / ct;
+                }
+            }
+        } else if (l >= 6 && l <= 8) {
+            double sf = sin(a[Q3_PHI]), cf = cos(a[Q3_PHI]), st = sin(a[Q3_TH]), ct = cos(a[Q3_TH]);
+            double sp = sin(a[Q3_PSI]), cp = cos(a[Q3_PSI]);
+            double R, Rf, Rt, Rp, Rm;
+            if (l == 6) {
+                R = cp * st * cf + sp * sf; Rm = fabs(cp * st * cf) + fabs(sp * sf);
+                Rf = sp * cf - cp * st * sf; Rt = cp * ct * cf; Rp = cp * sf - sp * st * cf;
+            } else if (l == 7) {
+                R = sp * st * cf - cp * sf; Rm = fabs(sp * st * cf) + fabs(cp * sf);
+                Rf = -(sp * st * sf + cp * cf); Rt = sp * ct * cf; Rp = cp * st * cf + sp * sf;
+            } else {
+                R = ct * cf; Rm = fabs(R);
+                Rf = -ct * sf; Rt = -st * cf; Rp = 0.0;
+            }
+            double c = dt * a[Q3_T] / d->m;
+            *val = c * R; *mag = fabs(c) * Rm;
+            if (grad) {
+                grad[Q3_T] = dt * R / d->m;
+                grad[Q3_PHI] = c * Rf; grad[Q3_TH] = c * Rt; grad[Q3_PSI] = c * Rp;
+            }
+        } else if (l >= 9 && l <= 11) {
+            static const int K[3] = {Q3_R, Q3_R, Q3_Q}, Jn[3] = {Q3_Q, Q3_P, Q3_P};
+            static const int NA[3] = {1, 2, 0}, NB[3] = {2, 0, 1};
+            int i = l - 9;
+            double c = dt * (d->J[NA[i]] - d->J[NB[i]]) / d->J[i];
+            *val = c * a[K[i]] * a[Jn[i]]; *mag = fabs(*val);
+            if (grad) { grad[K[i]] = c * a[Jn[i]]; grad[Jn[i]] = c * a[K[i]]; }
+        }
+        return;
+    }
     case ORC_SINCOS2D:
         if (l == 0) {
             *val = sin(a[0]) * cos(a[1]);

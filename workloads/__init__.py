@@ -69,6 +69,28 @@ class ChainDynamics:
         return self.nx + self.nu
 
 
+@dataclass(frozen=True)
+class SmallDynamics:
+    """A small analytic system of the dynamics appendix: kind "satellite"
+    (nx = 7, nu = 3, inertia J) or "quad3d" (nx = 12, nu = 4, mass m,
+    inertia J)."""
+    kind: str
+    nx: int
+    nu: int
+    dt: float
+    m: float = 1.0
+    g: float = 9.81
+    J: tuple = (1.0, 1.0, 1.0)
+
+    @property
+    def n(self) -> int:
+        return self.nx + self.nu
+
+
+SATELLITE = SmallDynamics("satellite", 7, 3, dt=0.1, J=(5.0, 2.0, 1.0))
+QUAD3D = SmallDynamics("quad3d", 12, 4, dt=0.05, m=1.0, g=9.81, J=(0.01, 0.01, 0.02))
+
+
 @dataclass
 class AnalyticBatch:
     """Boxes ((z_k, v_k) + mu_k) +/- sigma_k for `batch` trajectories of N steps."""
@@ -177,6 +199,38 @@ def _chain_nominal(rng, shape, n_units, rest_len, min_gap, sigma=None):
     z[..., 4] = pos_other[..., 3]
     z[..., 5] = pos_other[..., 4]
     return z.reshape(B, N, 6 * U), u.reshape(B, N, 2 * U)
+
+
+def small_nominals(dyn: SmallDynamics, seed: int, count: int) -> tuple:
+    """`count` nominal points (z, v) [count][nx], [count][nu] of the state and
+    input sets: satellite, a unit quaternion, rates U(-1, 1), torques
+    U(-1, 1); 3-D quadrotor, positions and velocities U(-1, 1), roll and
+    pitch U(-0.5, 0.5), yaw U(-pi, pi), body rates U(-1, 1), thrust
+    U(0.5, 1.5) m g, torques U(-0.05, 0.05)."""
+    rng = rng_for(seed)
+    if dyn.kind == "satellite":
+        q = rng.normal(size=(count, 4))
+        q /= np.linalg.norm(q, axis=1, keepdims=True)
+        w = rng.uniform(-1.0, 1.0, (count, 3))
+        return np.concatenate([q, w], 1), rng.uniform(-1.0, 1.0, (count, 3))
+    z = np.empty((count, 12))
+    z[:, 0:3] = rng.uniform(-1.0, 1.0, (count, 3))
+    z[:, 3:5] = rng.uniform(-0.5, 0.5, (count, 2))
+    z[:, 5] = rng.uniform(-np.pi, np.pi, count)
+    z[:, 6:9] = rng.uniform(-1.0, 1.0, (count, 3))
+    z[:, 9:12] = rng.uniform(-1.0, 1.0, (count, 3))
+    v = np.empty((count, 4))
+    v[:, 0] = rng.uniform(0.5, 1.5, count) * dyn.m * dyn.g
+    v[:, 1:4] = rng.uniform(-0.05, 0.05, (count, 3))
+    return z, v
+
+
+def small_batch(dyn: SmallDynamics, seed: int, count: int, eps: float) -> AnalyticBatch:
+    """The local sets of the tightness study: nominal points and the box
+    (z, v) + eps [-1, 1]^(nx+nu), as one trajectory of `count` steps."""
+    z, v = small_nominals(dyn, seed, count)
+    sigma = np.full((count, dyn.n), float(eps))
+    return AnalyticBatch(dyn, z[None], v[None], sigma[None], None)
 
 
 def chain_batch(seed: int, batch: int, N: int, n_units: int,
