@@ -31,7 +31,10 @@ Prints ONE JSON line.  Extra objects:
   latency, adjoint, batched_uneven (batch against per-problem launches),
   roofline_nn, learned_nn, nominal_pgd (nominal points refined by projected
   gradient descent on the bound's width against random nominal points at
-  an equal GPU time budget).
+  an equal GPU time budget), interval_hessian_study (satellite and 3-D
+  quadrotor: mean row width of the path, expanded and classic enclosures and
+  of 10,000 random samples for radii 0.01 .. 0.2, and the time of one call
+  for a single local set).
 """
 from __future__ import annotations
 
@@ -252,6 +255,7 @@ def main():
         "latency": latency(leb, W, dev, stream),
         "adjoint": adjoint(leb, W, dev, stream),
         "nominal_pgd": nominal_pgd(leb, W, dev, stream),
+        "interval_hessian_study": interval_hessian_study(leb, W, dev, stream),
         "roofline_nn": nn_roofline(leb, W, dev, stream, args),
         "learned_nn": nn_learned(leb, W, dev, stream, args),
         "batched_uneven": batched_uneven(leb, W, dev, stream, args)}
@@ -448,6 +452,52 @@ def nominal_pgd(leb, W, dev, stream):
                      "mean_width_start": float(w0.mean()), "mean_width_sampling": float(best.mean()),
                      "mean_width_pgd": float(w.mean()), "pgd_better_frac": float((w < best).double().mean()),
                      "pgd_not_worse_frac": float((w <= best).double().mean())}
+    return res
+
+
+def interval_hessian_study(leb, W, dev, stream):
+    """Tightness against the radius and time per call of the three
+    interval-Hessian forms and of random sampling (10,000 points), on the
+    satellite and the 3-D quadrotor: 256 local sets (z, v) + eps [-1, 1]^n
+    per radius; times from HIP events over 200 calls for one local set."""
+    import torch
+    res = {}
+    K = 10000
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(5)
+    for name, sysd in (("satellite", W.SATELLITE), ("quad3d", W.QUAD3D)):
+        dyn = leb.dynamics_like(sysd)
+        t = (2.0 * torch.rand((K, sysd.n), generator=gen, dtype=torch.float64, device=dev) - 1.0).contiguous()
+        widths = {}
+        for eps in (0.01, 0.05, 0.1, 0.15, 0.2):
+            b = W.small_batch(sysd, 60, 256, eps)
+            z, v, sg = (torch.from_numpy(x).to(dev) for x in (b.z, b.v, b.sigma))
+            row = {}
+            for mode in ("path", "expand", "classic"):
+                lo, hi, fl = leb.interval_hessian_bound(dyn, z, v, sg, mode=mode, stream=stream)
+                row[mode] = float((hi - lo).mean())
+            slo, shi = leb.sample_remainder(dyn, z, v, sg, t, stream=stream)
+            row["random_10k"] = float((shi - slo).mean())
+            widths[str(eps)] = {k: float("%.4g" % x) for k, x in row.items()}
+        b = W.small_batch(sysd, 61, 1, 0.1)
+        z, v, sg = (torch.from_numpy(x).to(dev) for x in (b.z, b.v, b.sigma))
+        times = {}
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        for label, fn in (("path", lambda: leb.interval_hessian_bound(dyn, z, v, sg, mode="path", stream=stream)),
+                          ("classic", lambda: leb.interval_hessian_bound(dyn, z, v, sg, mode="classic",
+                                                                         stream=stream)),
+                          ("random_10k", lambda: leb.sample_remainder(dyn, z, v, sg, t, stream=stream))):
+            for _ in range(3):
+                fn()
+            reps = 200
+            e0.record(stream)
+            for _ in range(reps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times[label] = round(e0.elapsed_time(e1) / reps * 1e3, 2)
+        res[name] = {"mean_row_width": widths, "us_per_call_one_set": times}
     return res
 
 

@@ -52,8 +52,15 @@ typedef enum {
     LEB_DYN_LINEAR = 0,        /* affine dynamics: the remainder is identically 0 */
     LEB_DYN_QUADRATIC = 1,     /* f_l(a) = 1/2 a^T Q_l a + affine: constant Hessian Q_l */
     LEB_DYN_SINCOS = 2,        /* nx = 1: f = sin(a_1); nx = 2: f = (sin a_1 cos a_2, cos a_1 sin a_2); nu = 0 */
-    LEB_DYN_PQUAD_CHAIN = 4    /* planar quadrotors (1 = a single one) joined by springs */
+    LEB_DYN_PQUAD_CHAIN = 4,   /* planar quadrotors (1 = a single one) joined by springs */
+    LEB_DYN_SATELLITE = 5,     /* satellite attitude (dynamics appendix): nx = 7, nu = 3 */
+    LEB_DYN_QUAD3D = 6         /* 3-D quadrotor (dynamics appendix): nx = 12, nu = 4 */
 } leb_dyn_kind;
+
+/* Interval-Hessian forms of leb_interval_hessian_bound (section IV.A) */
+#define LEB_IH_PATH     0   /* Theorem 1: entries over the prefix boxes of the coordinate-wise path */
+#define LEB_IH_EXPAND   1   /* eq. expanded_interval_hessian: the same sum, every entry over the full box */
+#define LEB_IH_CLASSIC  2   /* eq. interval_quadratic_form: 1/2 Delta^T ([H](X) Delta) */
 
 /* Analytic dynamics, forward-Euler discretised (dynamics appendix,
  * "Planar Quadrotor"):  x+ = x + dt * xdot, per node i
@@ -64,16 +71,31 @@ typedef enum {
  * acting +F on node i and -F on node i+1.  State per node
  * (px, pz, theta, vx, vz, omega), input per node (u1, u2); the augmented
  * vector is [all node states; all node inputs] and this order defines the
- * coordinate-wise path of Theorem 1. */
+ * coordinate-wise path of Theorem 1.
+ *
+ * SATELLITE: a = (q0, q1, q2, q3, w1, w2, w3, v1, v2, v3), x+ = x + dt xdot with
+ *   qdot = zeta(w) q,  zeta(w) = 1/2 [[0,-w1,-w2,-w3],[w1,0,w3,-w2],[w2,-w3,0,w1],[w3,w2,-w1,0]],
+ *   wdot = I^-1 (v - w x (I w)),  I = diag(J[0], J[1], J[2]).
+ * QUAD3D: a = (px, py, pz, phi, theta, psi, vx, vy, vz, p, q, r, T, tau_phi,
+ *   tau_theta, tau_psi), x+ = x + dt xdot with the Euler-angle kinematics
+ *   (phidot = p + (q sin phi + r cos phi) tan theta, thetadot = q cos phi - r sin phi,
+ *   psidot = (q sin phi + r cos phi) / cos theta), vdot = (T/m) R e_3 - g e_3 and the
+ *   rigid-body rates (pdot = (Jy - Jz)/Jx q r + tau_phi/Jx, ...), J = (Jx, Jy, Jz).
+ *   Rows whose Hessian involves 1/cos(theta) are unbounded (LEB_FLAG_UNBOUNDED) where
+ *   the cos(theta) interval of the evaluation box is not positive. */
 typedef struct {
     int32_t kind;       /* leb_dyn_kind */
     int32_t nx, nu;     /* LINEAR: any sizes; CHAIN: must equal 6*n_units, 2*n_units;
-                           QUADRATIC: 1 <= nx + nu <= 64; SINCOS: nx in {1, 2}, nu = 0 */
+                           QUADRATIC: 1 <= nx + nu <= 64; SINCOS: nx in {1, 2}, nu = 0;
+                           SATELLITE: 7, 3; QUAD3D: 12, 4 */
     int32_t n_units;    /* CHAIN: 1 .. 256 */
-    double dt, m, g, arm, inertia, k_spring, rest_len;   /* CHAIN: dt > 0, m > 0, k_spring >= 0, rest_len >= 0 */
+    double dt, m, g, arm, inertia, k_spring, rest_len;   /* CHAIN: dt > 0, m > 0, k_spring >= 0, rest_len >= 0;
+                                                            SATELLITE: dt > 0; QUAD3D: dt > 0, m > 0 (g enters
+                                                            no Hessian) */
     const double* coeffs;  /* QUADRATIC: DEVICE pointer to Q [nx][nx+nu][nx+nu] (row l holds Q_l; only the
                               entries k >= j are read, as the lower triangle of a symmetric matrix, and each
                               must be finite); NULL for every other kind */
+    double J[3];        /* SATELLITE: inertia diagonal I_S; QUAD3D: (Jx, Jy, Jz); all > 0 */
 } leb_dynamics;
 
 /*
@@ -103,8 +125,8 @@ typedef struct {
  *            entry is written.
  * Kinds: CHAIN (nodes in one workgroup, FP32 outward intervals, FP64
  * accumulation); LINEAR ([0, 0] for valid data); QUADRATIC and SINCOS,
- * closed-form test dynamics (one thread per unit; QUADRATIC reads Q through
- * dyn->coeffs).  Invalid data (non-finite nominal, mu or sigma, negative
+ * closed-form test dynamics, SATELLITE and QUAD3D (one thread per unit, the
+ * same arithmetic; QUADRATIC reads Q through dyn->coeffs).  Invalid data (non-finite nominal, mu or sigma, negative
  * sigma) gives [-inf, +inf] on every row of the unit and LEB_FLAG_BAD_INPUT
  * for every kind; z and sigma (and v when nu > 0) are required for every kind.
  * Returns LEB_OK or a negative leb_status.
@@ -113,6 +135,41 @@ int leb_analytic_bound(const leb_dynamics* dyn, int32_t batch, int32_t N,
                        const double* z, const double* v, const double* mu, const double* sigma,
                        double* r_lo, double* r_hi, double* c_bar, double* rho_bar, double pad,
                        uint32_t* flags, double* A, double* B, void* stream);
+
+/*
+ * leb_interval_hessian_bound -- the three interval-Hessian enclosures the
+ * paper compares (section IV.A; Corollary 1 orders them: for a box symmetric
+ * about the nominal point PATH is inside EXPAND, which is inside CLASSIC):
+ *   mode LEB_IH_PATH    Theorem 1 (the same bound as leb_analytic_bound)
+ *   mode LEB_IH_EXPAND  eq. expanded_interval_hessian: sum_{j<k} [H_kj](X) (Delta_j Delta_k)
+ *                       + 1/2 sum_k [H_kk](X) Delta_k^2
+ *   mode LEB_IH_CLASSIC eq. interval_quadratic_form: 1/2 Delta^T v with v = [H](X) Delta
+ *                       over the symmetric interval Hessian
+ * for the kinds LINEAR, QUADRATIC, SINCOS, SATELLITE, QUAD3D (CHAIN:
+ * LEB_ENOTSUP).  Arguments, layout, flags and invalid-data handling as in
+ * leb_analytic_bound; r_lo, r_hi are required.  LEB_EINVAL for another mode.
+ */
+int leb_interval_hessian_bound(const leb_dynamics* dyn, int32_t mode, int32_t batch, int32_t N,
+                               const double* z, const double* v, const double* mu, const double* sigma,
+                               double* r_lo, double* r_hi, uint32_t* flags, void* stream);
+
+/*
+ * leb_sample_remainder -- the random-sampling under-approximation of the
+ * remainder that the tightness study compares against (results section):
+ * for every unit, the minimum and maximum over K points
+ *     a_s = a~ + mu + t_s * sigma   (elementwise; t_s in [-1, 1]^(nx+nu), caller-drawn)
+ * and the nominal point itself (r = 0) of
+ *     r_l(a; a~) = f_l(a) - f_l(a~) - J_l(a~) (a - a~)      (eq. linear_error_def)
+ * evaluated in FP64 (QUADRATIC: its exact form 1/2 d^T Q_l d).
+ *   t              DEVICE [K][nx+nu], shared by every unit
+ *   s_lo, s_hi     [batch][N][nx] outputs
+ * Kinds QUADRATIC, SINCOS, SATELLITE, QUAD3D with nx + nu <= 16 (else
+ * LEB_ENOTSUP).  One workgroup per unit; the result is an estimate from
+ * inside, not a bound.
+ */
+int leb_sample_remainder(const leb_dynamics* dyn, int32_t batch, int32_t N, const double* z, const double* v,
+                         const double* mu, const double* sigma, int32_t K, const double* t, double* s_lo,
+                         double* s_hi, void* stream);
 
 /*
  * leb_backward -- adjoint of leb_analytic_bound: the gradient of

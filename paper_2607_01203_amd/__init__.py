@@ -12,13 +12,15 @@ import os
 
 __all__ = ["lib", "Dynamics", "LebError", "analytic_bound", "chain_dynamics", "linear_dynamics", "quadratic_dynamics",
            "sincos_dynamics", "tube_map", "zonotope_hull", "fixed_point_solve", "FLAG_UNBOUNDED",
-           "FLAG_BAD_INPUT", "FLAG_HULL_EXTENDED", "DYN_LINEAR", "DYN_QUADRATIC", "DYN_SINCOS", "DYN_PQUAD_CHAIN"]
+           "FLAG_BAD_INPUT", "FLAG_HULL_EXTENDED", "DYN_LINEAR", "DYN_QUADRATIC", "DYN_SINCOS", "DYN_PQUAD_CHAIN",
+           "DYN_SATELLITE", "DYN_QUAD3D", "IH_MODES"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libleb.so")
 
 FLAG_UNBOUNDED, FLAG_BAD_INPUT, FLAG_HULL_EXTENDED = 1, 2, 4
-DYN_LINEAR, DYN_QUADRATIC, DYN_SINCOS, DYN_PQUAD_CHAIN = 0, 1, 2, 4
+DYN_LINEAR, DYN_QUADRATIC, DYN_SINCOS, DYN_PQUAD_CHAIN, DYN_SATELLITE, DYN_QUAD3D = 0, 1, 2, 4, 5, 6
+IH_MODES = {"path": 0, "expand": 1, "classic": 2}
 
 _lib = None
 
@@ -31,7 +33,8 @@ class Dynamics(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("nx", ctypes.c_int32), ("nu", ctypes.c_int32),
                 ("n_units", ctypes.c_int32), ("dt", ctypes.c_double), ("m", ctypes.c_double),
                 ("g", ctypes.c_double), ("arm", ctypes.c_double), ("inertia", ctypes.c_double),
-                ("k_spring", ctypes.c_double), ("rest_len", ctypes.c_double), ("coeffs", ctypes.c_void_p)]
+                ("k_spring", ctypes.c_double), ("rest_len", ctypes.c_double), ("coeffs", ctypes.c_void_p),
+                ("J", ctypes.c_double * 3)]
 
 
 class WarmStart(ctypes.Structure):
@@ -85,8 +88,26 @@ def sincos_dynamics(nx) -> Dynamics:
     return Dynamics(DYN_SINCOS, int(nx), 0, 0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, None)
 
 
+def satellite_dynamics(dt, inertia=(5.0, 2.0, 1.0)) -> Dynamics:
+    """Satellite attitude (quaternion, body rates; torques): nx = 7, nu = 3."""
+    return Dynamics(DYN_SATELLITE, 7, 3, 0, float(dt), 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, None,
+                    (ctypes.c_double * 3)(*inertia))
+
+
+def quad3d_dynamics(dt, m, g, J) -> Dynamics:
+    """3-D quadrotor (position, Euler angles, velocity, body rates; thrust, torques): nx = 12, nu = 4."""
+    return Dynamics(DYN_QUAD3D, 12, 4, 0, float(dt), float(m), float(g), 0.0, 0.0, 0.0, 0.0, None,
+                    (ctypes.c_double * 3)(*J))
+
+
 def dynamics_like(obj) -> Dynamics:
-    """From any object exposing n_units, dt, m, g, arm, inertia, k_spring, rest_len."""
+    """From any object exposing n_units, dt, m, g, arm, inertia, k_spring, rest_len
+    (a chain), or kind "satellite" / "quad3d" with dt, m, g, J."""
+    kind = getattr(obj, "kind", "chain")
+    if kind == "satellite":
+        return satellite_dynamics(obj.dt, obj.J)
+    if kind == "quad3d":
+        return quad3d_dynamics(obj.dt, obj.m, obj.g, obj.J)
     return chain_dynamics(obj.n_units, obj.dt, obj.m, obj.g, obj.arm, obj.inertia, obj.k_spring,
                           obj.rest_len)
 
@@ -118,6 +139,12 @@ def lib():
         L.leb_tube_map.restype = ctypes.c_int
         L.leb_zonotope_hull.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, vp]
         L.leb_zonotope_hull.restype = ctypes.c_int
+        L.leb_interval_hessian_bound.argtypes = [ctypes.POINTER(Dynamics), ctypes.c_int32, ctypes.c_int32,
+                                                 ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.leb_interval_hessian_bound.restype = ctypes.c_int
+        L.leb_sample_remainder.argtypes = [ctypes.POINTER(Dynamics), ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp,
+                                           ctypes.c_int32, vp, vp, vp, vp]
+        L.leb_sample_remainder.restype = ctypes.c_int
         L.leb_pgd_nominal.argtypes = [ctypes.POINTER(Dynamics), ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp,
                                       ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_double, vp, vp, vp,
                                       vp, vp]
@@ -260,6 +287,39 @@ def pgd_nominal(dyn: Dynamics, z0, v0, sigma, mu0=None, radius=0.5, steps=20, lr
                                  _dev_ptr(z, "z", f64), _dev_ptr(v, "v", f64), _dev_ptr(w, "width", f64),
                                  _dev_ptr(w0, "width0", f64), _stream(stream)))
     return z, v, w, w0
+
+
+def interval_hessian_bound(dyn: Dynamics, z, v, sigma, mu=None, mode="path", stream=None):
+    """One of the three interval-Hessian enclosures (see leb.h:
+    leb_interval_hessian_bound): mode "path" (Theorem 1), "expand" or
+    "classic".  Returns (r_lo, r_hi, flags)."""
+    import torch
+    f64 = torch.float64
+    B, N = int(z.shape[0]), int(z.shape[1])
+    lo = torch.empty((B, N, dyn.nx), dtype=f64, device=z.device)
+    hi = torch.empty_like(lo)
+    fl = torch.empty((B, N), dtype=torch.int32, device=z.device)
+    _check(lib().leb_interval_hessian_bound(ctypes.byref(dyn), IH_MODES[mode], B, N, _dev_ptr(z, "z", f64),
+                                            _dev_ptr(v, "v", f64), _dev_ptr(mu, "mu", f64),
+                                            _dev_ptr(sigma, "sigma", f64), _dev_ptr(lo, "r_lo", f64),
+                                            _dev_ptr(hi, "r_hi", f64), _dev_ptr(fl, "flags"), _stream(stream)))
+    return lo, hi, fl
+
+
+def sample_remainder(dyn: Dynamics, z, v, sigma, t, mu=None, stream=None):
+    """Minimum and maximum of the true remainder over the points
+    a~ + mu + t_s * sigma (t [K][nx+nu] in [-1, 1], a float64 GPU tensor) and
+    the nominal (see leb.h: leb_sample_remainder).  Returns (s_lo, s_hi)."""
+    import torch
+    f64 = torch.float64
+    B, N = int(z.shape[0]), int(z.shape[1])
+    lo = torch.empty((B, N, dyn.nx), dtype=f64, device=z.device)
+    hi = torch.empty_like(lo)
+    _check(lib().leb_sample_remainder(ctypes.byref(dyn), B, N, _dev_ptr(z, "z", f64), _dev_ptr(v, "v", f64),
+                                      _dev_ptr(mu, "mu", f64), _dev_ptr(sigma, "sigma", f64), int(t.shape[0]),
+                                      _dev_ptr(t, "t", f64), _dev_ptr(lo, "s_lo", f64), _dev_ptr(hi, "s_hi", f64),
+                                      _stream(stream)))
+    return lo, hi
 
 
 def zonotope_hull(G, c=None, stream=None):

@@ -33,6 +33,16 @@ int check_dynamics(const leb_dynamics* dyn) {
         if (dyn->nx < 1 || dyn->nu < 0 || !dyn->coeffs || !aligned8(dyn->coeffs)) return LEB_EINVAL;
         return dyn->nx + dyn->nu <= 64 ? LEB_OK : LEB_ENOTSUP;
     case LEB_DYN_SINCOS: return (dyn->nx == 1 || dyn->nx == 2) && dyn->nu == 0 ? LEB_OK : LEB_EINVAL;
+    case LEB_DYN_SATELLITE:
+    case LEB_DYN_QUAD3D: {
+        const bool sat = dyn->kind == LEB_DYN_SATELLITE;
+        if (dyn->nx != (sat ? 7 : 12) || dyn->nu != (sat ? 3 : 4)) return LEB_EINVAL;
+        if (!(dyn->dt > 0.0) || !isfinite(dyn->dt)) return LEB_EINVAL;
+        if (!sat && (!(dyn->m > 0.0) || !isfinite(dyn->m))) return LEB_EINVAL;
+        for (int i = 0; i < 3; ++i)
+            if (!(dyn->J[i] > 0.0) || !isfinite(dyn->J[i])) return LEB_EINVAL;
+        return LEB_OK;
+    }
     }
     return LEB_ENOTSUP;
 }
@@ -81,7 +91,8 @@ extern "C" int leb_analytic_bound(const leb_dynamics* dyn, int32_t batch, int32_
     if (A && units * nx * (nx + nu) > ((int64_t)1 << 46)) return LEB_EINVAL;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (dyn->kind != LEB_DYN_PQUAD_CHAIN)
-        return launch_test_dyn(dyn, units, z, v, mu, sigma, r_lo, r_hi, c_bar, rho_bar, pad, flags, s);
+        return launch_small_dyn(dyn, LEB_IH_PATH, units, z, v, mu, sigma, r_lo, r_hi, c_bar, rho_bar, pad, flags,
+                                s);
     if ((rc = launch_pbh_chain(dyn, units, z, v, mu, sigma, r_lo, r_hi, c_bar, rho_bar, pad, flags, s))) return rc;
     return A ? launch_chain_jacobians(dyn, units, z, v, A, B, s) : LEB_OK;
 }

@@ -117,9 +117,9 @@ struct WsFenceScope {
 };
 
 // closed-form test dynamics (LINEAR, QUADRATIC, SINCOS): one thread per unit
-int launch_test_dyn(const leb_dynamics* dyn, int64_t units, const double* z, const double* v, const double* mu,
-                    const double* sigma, double* r_lo, double* r_hi, double* c_bar, double* rho_bar, double pad,
-                    uint32_t* flags, hipStream_t s);
+int launch_small_dyn(const leb_dynamics* dyn, int mode, int64_t units, const double* z, const double* v,
+                     const double* mu, const double* sigma, double* r_lo, double* r_hi, double* c_bar,
+                     double* rho_bar, double pad, uint32_t* flags, hipStream_t s);
 // point Jacobians A [units][nx][nx], B [units][nx][nu] of chain dynamics at the nominal
 int launch_chain_jacobians(const leb_dynamics* dyn, int64_t units, const double* z, const double* v, double* A,
                            double* B, hipStream_t s);

@@ -1,16 +1,5 @@
-// testdyn.hip -- the closed-form dynamics of leb_analytic_bound (LINEAR,
-// QUADRATIC, SINCOS), the point Jacobians of chain dynamics (eq.
-// linearizations) and the zonotope hull (eq. tight_tube_width).
-//
-// The test kinds evaluate the path-based bound of Theorem 1 with the same
-// arithmetic as the chain kernel: displacement intervals rounded outward to
-// FP32, Hessian entries and term products in outward-rounded FP32, sums in
-// FP64.  Every term contains 0 (each has a displacement factor that does),
-// so every lower-end summand is <= 0 and every upper-end summand >= 0: the
-// FP64 sums do not cancel and one relative widening covers their rounding.
-// A term whose displacement factor is exactly [0, 0] contributes exactly 0.
-// One thread per unit; these kinds pin the interval machinery against closed
-// forms and are not tuned.
+// testdyn.hip -- the point Jacobians of chain dynamics (eq. linearizations)
+// and the zonotope hull (eq. tight_tube_width).
 #include <hip/hip_runtime.h>
 #include <float.h>
 #include <math.h>
@@ -22,125 +11,6 @@
 #include "pbh_node.hpp"
 
 namespace leb {
-
-constexpr int TD_MAX_N = 64;     // QUADRATIC: nx + nu
-
-struct TestArgs {
-    const double *z, *v, *mu, *sigma, *Q;
-    double *r_lo, *r_hi, *c_bar, *rho_bar;
-    uint32_t* flags;
-    double pad;
-    int64_t units;
-    int nx, nu, kind;
-};
-
-__device__ __forceinline__ double td_nom(const TestArgs& A, int64_t u, int i) {
-    return i < A.nx ? A.z[u * A.nx + i] : A.v[u * A.nu + (i - A.nx)];
-}
-__device__ __forceinline__ fiv td_disp(const TestArgs& A, int64_t u, int i) {
-    const int n = A.nx + A.nu;
-    const IV<float> d = disp_interval(A.mu ? A.mu[u * n + i] : 0.0, A.sigma[u * n + i]);
-    return mk(d.lo, d.hi);
-}
-__device__ __forceinline__ bool td_zero(fiv d) { return d.lo == 0.0f && d.hi == 0.0f; }
-
-// coordinate interval X_i = a~_i + Delta_i (FP64 endpoints, outward)
-__device__ __forceinline__ void td_box(double a, fiv d, double* lo, double* hi) {
-    const double l = a + (double)d.lo, h = a + (double)d.hi;
-    *lo = l - fabs(l) * 0x1p-52;
-    *hi = h + fabs(h) * 0x1p-52;
-}
-
-// -h * [t.lo, t.hi] for h an interval: neg(mul(h, t)) with outward rounding kept
-__device__ __forceinline__ fiv td_negmul(fiv a, fiv b) { return neg(mul(a, b)); }
-
-__global__ void __launch_bounds__(256) test_dyn_kernel(TestArgs A) {
-    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= A.units) return;
-    const int n = A.nx + A.nu;
-    uint32_t fl = 0;
-    for (int i = 0; i < n; ++i) {
-        const double a = td_nom(A, u, i), m = A.mu ? A.mu[u * n + i] : 0.0, s = A.sigma[u * n + i];
-        if (!isfinite(a) || !isfinite(m) || !isfinite(s) || !(s >= 0.0)) fl |= LEB_FLAG_BAD_INPUT;
-        if (fabs(m) > s) fl |= LEB_FLAG_HULL_EXTENDED;
-    }
-    for (int l = 0; l < A.nx; ++l) {
-        div_ acc{0.0, 0.0};
-        int terms = 0;
-        bool unbounded = false;
-        if (!(fl & LEB_FLAG_BAD_INPUT)) {
-            if (A.kind == LEB_DYN_QUADRATIC) {
-                // R_l = sum_{j<k} Q_l,kj (Delta_j Delta_k) + 1/2 sum_k Q_l,kk sq(Delta_k)
-                const double* Ql = A.Q + (size_t)l * n * n;
-                for (int k = 0; k < n; ++k) {
-                    const fiv dk = td_disp(A, u, k);
-                    for (int j = 0; j <= k; ++j) {
-                        const double q = Ql[k * n + j];
-                        if (!isfinite(q)) unbounded = true;
-                        if (q == 0.0 || unbounded) continue;
-                        const fiv dj = td_disp(A, u, j);
-                        if (td_zero(dk) || td_zero(dj)) continue;
-                        if (j < k) acc_any(acc, q, mul_zz(dj, dk));
-                        else acc_any(acc, 0.5 * q, sq_z(dk));
-                        ++terms;
-                    }
-                }
-            } else if (A.kind == LEB_DYN_SINCOS && A.nx == 1) {
-                // f = sin a: H = -sin over X^(1) = X; R = 1/2 H sq(Delta)
-                const fiv d0 = td_disp(A, u, 0);
-                if (!td_zero(d0)) {
-                    double x0l, x0h;
-                    td_box(td_nom(A, u, 0), d0, &x0l, &x0h);
-                    SinCos s0;
-                    isincos(x0l, x0h, &s0);
-                    acc_pos(acc, 0.5, mul_z(neg(s0.s), sq_z(d0)));
-                    ++terms;
-                }
-            } else if (A.kind == LEB_DYN_SINCOS) {
-                // f_1 = sin a1 cos a2, f_2 = cos a1 sin a2.  Entries over their prefix
-                // boxes: (1,1) and (2,1) over X^(1) = (X_1, a~_2), (2,2) over X^(2) = X.
-                const fiv d0 = td_disp(A, u, 0), d1 = td_disp(A, u, 1);
-                const double a0 = td_nom(A, u, 0), a1 = td_nom(A, u, 1);
-                double x0l, x0h, x1l, x1h;
-                td_box(a0, d0, &x0l, &x0h);
-                td_box(a1, d1, &x1l, &x1h);
-                SinCos s0, s1p, s1;
-                isincos(x0l, x0h, &s0);      // sin, cos of X_1
-                isincos(a1, a1, &s1p);       // of the point a~_2
-                isincos(x1l, x1h, &s1);      // of X_2
-                fiv h11, h21, h22;
-                if (l == 0) {
-                    h11 = td_negmul(s0.s, s1p.c);
-                    h21 = td_negmul(s0.c, s1p.s);
-                    h22 = td_negmul(s0.s, s1.c);
-                } else {
-                    h11 = td_negmul(s0.c, s1p.s);
-                    h21 = td_negmul(s0.s, s1p.c);
-                    h22 = td_negmul(s0.c, s1.s);
-                }
-                if (!td_zero(d0)) { acc_pos(acc, 0.5, mul_z(h11, sq_z(d0))); ++terms; }
-                if (!td_zero(d0) && !td_zero(d1)) { acc_pos(acc, 1.0, mul_z(h21, mul_zz(d0, d1))); ++terms; }
-                if (!td_zero(d1)) { acc_pos(acc, 0.5, mul_z(h22, sq_z(d1))); ++terms; }
-            }
-        }
-        double lo, hi;
-        if (fl & LEB_FLAG_BAD_INPUT) {
-            lo = -INFINITY; hi = INFINITY;
-        } else if (unbounded) {
-            lo = -INFINITY; hi = INFINITY;
-            fl |= LEB_FLAG_UNBOUNDED;
-        } else {
-            // at most 2080 same-sign FP64 roundings of 2^-53 each, relative to the sum
-            lo = acc.lo - fabs(acc.lo) * 0x1p-40;
-            hi = acc.hi + fabs(acc.hi) * 0x1p-40;
-            if (terms == 0) { lo = 0.0; hi = 0.0; }
-        }
-        const int64_t o = u * A.nx + l;
-        if (A.r_lo) { A.r_lo[o] = lo; A.r_hi[o] = hi; }
-        if (A.c_bar) row_zono(lo, hi, A.pad, &A.c_bar[o], &A.rho_bar[o]);
-    }
-    if (A.flags) A.flags[u] = fl;
-}
 
 // ------------------------------------------------------------ Jacobians
 //
@@ -236,18 +106,6 @@ __global__ void __launch_bounds__(256) zonotope_hull_kernel(int rows, int n_gen,
         sigma[row] = sg;
         mu[row] = c ? c[row] : 0.0;
     }
-}
-
-int launch_test_dyn(const leb_dynamics* dyn, int64_t units, const double* z, const double* v, const double* mu,
-                    const double* sigma, double* r_lo, double* r_hi, double* c_bar, double* rho_bar, double pad,
-                    uint32_t* flags, hipStream_t s) {
-    if ((units + 255) / 256 > 0x7fffffff) return LEB_EINVAL;
-    TestArgs A;
-    A.z = z; A.v = v; A.mu = mu; A.sigma = sigma; A.Q = dyn->coeffs;
-    A.r_lo = r_lo; A.r_hi = r_hi; A.c_bar = c_bar; A.rho_bar = rho_bar; A.flags = flags; A.pad = pad;
-    A.units = units; A.nx = dyn->nx; A.nu = dyn->nu; A.kind = dyn->kind;
-    hipLaunchKernelGGL(test_dyn_kernel, dim3((unsigned)((units + 255) / 256)), dim3(256), 0, s, A);
-    return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
 }
 
 int launch_chain_jacobians(const leb_dynamics* dyn, int64_t units, const double* z, const double* v, double* A,
