@@ -60,6 +60,7 @@ struct TubeArgs {
 };
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ double se_row(const double (&e)[6], int q) { return q == 3 ? e[3] : e[4]; }
 constexpr int TM_RT = 5;        // 16-row tiles per wave and row group
@@ -264,14 +265,26 @@ __global__ void __launch_bounds__(256) tube_map_kernel(const double* __restrict_
 // Only those rows enter the contraction, K = 2 (N-1); the affine rows add
 //   sigma_k[r] += sum_{j<k} sum_{q in {0,1,2,5}} |Phi_{k-j-1}[r][q]| (e_q + pad)
 // (a table over (k, r) shared by every column) and nothing to mu.  The rest is
-// the tube map kernel above: 16 node columns per workgroup, row tiles of two
-// steps per wave, the same rounding allowance wid (the same number of terms).
+// the tube map kernel above (16 node columns per workgroup, row tiles of two
+// steps per wave) with the contraction on FP32 MFMA (v_mfma_f32_16x16x4f32):
+// Phi's two residual columns, c_bar and w are rounded to nearest FP32, the
+// sums of K = 2 (N - 1) products accumulate in FP32 accumulators of at most
+// 32 products each (two per sum, reset every 8 K-loop iterations), which are
+// added in FP64.  A computed sum of n non-negative products is within
+// gamma_n + 2u (u = 2^-24) of the exact sum relative (accumulation and input
+// rounding), and each centre within the same multiple of sum |Phi| |c|;
+// wid32 = 1.1 (32 + 6) 2^-24 covers both: the widths
+// carry |c| (wid + wid32), so the centre's error is inside the width, and
+// every width is enlarged by (wid + wid32) relative plus 2^-90 absolute (for
+// products lost to FP32 underflow).  Residual entries above 2^100 count as not
+// finite.  Lane l's accumulator element i is D[4 (l/16) + i][l % 16].
 struct Tube2Args {
     const double* c2; const double* r2;      // [B][N][U][2]
     double e[6];
     double pad;
     double* mu; double* sigma;               // [B][N][n] out
     double wid;
+    double wid32;                            // FP32 contraction allowance (see above)
     double scale, shift;                     // plain map: sigma stored as sigma * scale + shift
     int B, N, U;
 };
@@ -284,9 +297,10 @@ __device__ double kZero8[8];          // zero-initialised; stands in for Phi at 
 // LONG (more than 65 steps) stages Phi and the residuals in passes, before
 // and after the tube loads; the short form has no loop around a load.
 template <bool FP, bool LONG>
-__global__ void __launch_bounds__(256) tube_map2_kernel(const double* __restrict__ phi, Tube2Args A, TubeFP P) {
-    // LDS: Phi rows' columns 3, 4 for lags -4..N-1 [(N+4)*16], the affine table
-    // [N][8], per-lag affine sums [N-1][8], c and w [2(N-1)+8][16], a spare [4]
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 3))) tube_map2_kernel(const double* __restrict__ phi, Tube2Args A, TubeFP P) {
+    // LDS: the affine table [N][8] and per-lag affine sums [N-1][8] (FP64), a
+    // spare [4]; then FP32: Phi rows' columns 3, 4 for lags -4..N-1 [(N+4)*16],
+    // c and w [2(N-1)+8][16]
     extern __shared__ double lds2[];
     __shared__ uint32_t sbad[16];
     __shared__ int sjinf[16];
@@ -304,12 +318,13 @@ __global__ void __launch_bounds__(256) tube_map2_kernel(const double* __restrict
     const int N = A.N, U = A.U, nx = 6 * U, n = 8 * U;
     const int nst = N - 1;
     const int kfull = 2 * nst, kpad = kfull + 8;
-    double* sp = lds2;                                  // sp[(lag + 4) * 16 + r * 2 + q'], q' = row 3 + q'
-    double* dtab = sp + (N + 4) * 16;                   // [N][8]
+    double* dtab = lds2;                                // [N][8]
     double* g = dtab + N * 8;                           // [N-1][8]
-    double* sc = g + nst * 8;                           // [kpad][16]
-    double* sw = sc + (size_t)kpad * 16;
-    double* spare = sw + (size_t)kpad * 16;             // [4], written, never read
+    double* spare = g + nst * 8;                        // [4], written, never read
+    float* sp = reinterpret_cast<float*>(spare + 4);    // sp[(lag + 4) * 16 + r * 2 + q'], q' = row 3 + q'
+    float* sc = sp + (N + 4) * 16;                      // [kpad][16]
+    float* sw = sc + (size_t)kpad * 16;
+    float* sparef = reinterpret_cast<float*>(spare);
     const int cols = A.B * U;
     const int c0 = blockIdx.x * 16;
     const int ncol = min(16, cols - c0);
@@ -354,9 +369,9 @@ __global__ void __launch_bounds__(256) tube_map2_kernel(const double* __restrict
             const int t = t0 + tid + 256 * u;
             const bool in = t < ng;
             const int lag = t >> 3, r = t & 7;
-            double* d34 = in ? sp + (lag + 4) * 16 + r * 2 : spare;
-            d34[0] = pr[u][3];
-            d34[1] = pr[u][4];
+            float* d34 = in ? sp + (lag + 4) * 16 + r * 2 : sparef;
+            d34[0] = (float)pr[u][3];
+            d34[1] = (float)pr[u][4];
             double acc = 0.0;
             acc = __builtin_fma(fabs(pr[u][0]), A.e[0] + A.pad, acc);
             acc = __builtin_fma(fabs(pr[u][1]), A.e[1] + A.pad, acc);
@@ -368,7 +383,8 @@ __global__ void __launch_bounds__(256) tube_map2_kernel(const double* __restrict
     // residual rows 3, 4 of the 16 columns: entry (j, p), p = 2 cl + q' = tid % 32,
     // so each thread stages one (column, row) at steps j = tid / 32 + 8 u and
     // consecutive threads read consecutive addresses.  A radius or centre that
-    // is not finite enters as 0 and makes sigma +inf at every later step of its column
+    // is not finite (or above 2^100) enters as 0 and makes sigma +inf at every
+    // later step of its column
     const int scl = (tid & 31) >> 1, sq = tid & 1;
     const bool sin_ = scl < ncol;
     int64_t srow;
@@ -396,21 +412,22 @@ __global__ void __launch_bounds__(256) tube_map2_kernel(const double* __restrict
             double c = 0.0, w = 0.0;
             if (sin_) {
                 c = cv[u];
-                const bool cfin = fabs(c) <= DBL_MAX;
+                const bool cfin = fabs(c) <= 0x1p100;
                 if (!cfin) c = 0.0;
-                w = se + rv[u] + fabs(c) * A.wid;
-                if (!(cfin && w <= DBL_MAX)) {
+                w = se + rv[u] + fabs(c) * (A.wid + A.wid32);
+                if (!(cfin && w <= 0x1p100)) {
                     atomicMin(&sjinf[scl], j);
                     w = 0.0;
                 }
             }
-            sc[(2 * j + sq) * 16 + scl] = c;
-            sw[(2 * j + sq) * 16 + scl] = w;
+            sc[(2 * j + sq) * 16 + scl] = (float)c;
+            sw[(2 * j + sq) * 16 + scl] = (float)w;
         }
     };
     const int nrt = (N + 1) >> 1;
     const bool frozen = FP && (stw & FP_CERT) != 0u;
-    auto tube_off = [&](int rr, int k) -> int64_t { return (rr < 6 ? ob_s : ob_i) + rr + (int64_t)k * n; };
+    const int64_t ob_d = ob_i - ob_s;       // (an arithmetic select keeps both offsets in registers)
+    auto tube_off = [&](int rr, int k) -> int64_t { return ob_s + (rr < 6 ? 0 : ob_d) + rr + (int64_t)k * n; };
     // The slots of a wave run from the longest K range down or the other way
     // round, alternating between blocks 256 apart (the two blocks that share
     // a compute unit when the grid holds more than one block per unit), so that
@@ -424,7 +441,7 @@ __global__ void __launch_bounds__(256) tube_map2_kernel(const double* __restrict
         const int rt = tm_tile(wave, ord(p), blockIdx.y);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int r = 16 * rt + 4 * i + lq, k = r >> 3;
+            const int r = 16 * rt + 4 * lq + i, k = r >> 3;
             const bool ok = cin && rt < nrt && k < N;     // (a frozen column's values go unused)
             const int64_t o = ok ? tube_off(r & 7, k) : ob_s;
             mi[p][i] = P.mu_in[o];
@@ -446,15 +463,21 @@ __global__ void __launch_bounds__(256) tube_map2_kernel(const double* __restrict
         tube_load(1);
     }
     // zero lags -4..-1 and N-1 of sp (the rows past a tile's causal range)
-    if (tid < 64) sp[tid] = 0.0;
-    else if (tid < 80) sp[(nst + 4) * 16 + tid - 64] = 0.0;
-    if (tid < 128) { sc[kfull * 16 + tid] = 0.0; sw[kfull * 16 + tid] = 0.0; }   // 8 zero rows past the end
+    if (tid < 64) sp[tid] = 0.0f;
+    else if (tid < 80) sp[(nst + 4) * 16 + tid - 64] = 0.0f;
+    if (tid < 128) { sc[kfull * 16 + tid] = 0.0f; sw[kfull * 16 + tid] = 0.0f; }   // 8 zero rows past the end
     __syncthreads();
     // affine table: dtab[k][r] = sum_{d<k} g[d][r], summed in increasing d
     for (int t = tid; t < N * 8; t += 256) {
         const int k = t >> 3, r = t & 7;
         double acc = 0.0;
-        for (int d = 0; d < k; ++d) acc += g[d * 8 + r];
+        for (int d0 = 0; d0 < k; d0 += 8) {      // eight loads in flight, then their sum in increasing d
+            double x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) x[u] = d0 + u < k ? g[(d0 + u) * 8 + r] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += x[u];
+        }
         dtab[t] = acc;
     }
     stage_store(0);
@@ -480,38 +503,48 @@ __global__ void __launch_bounds__(256) tube_map2_kernel(const double* __restrict
         double dt[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int rr4 = 16 * rt + 4 * i + lq;
+            const int rr4 = 16 * rt + 4 * lq + i;
             dt[i] = (rr4 >> 3) < N ? dtab[(rr4 >> 3) * 8 + (rr4 & 7)] : 0.0;
         }
-        d4 m0 = d4{0.0, 0.0, 0.0, 0.0}, v0 = m0, m1 = m0, v1 = m0;
-        double c0v = sc[lane], w0v = sw[lane], c1v = sc[64 + lane], w1v = sw[64 + lane];
-        double a0 = sp[abase], a1 = sp[abase - 32];
-        for (int k4 = 0; k4 < kmax; k4 += 8) {
-            const int kn = k4 + 8 < kmax ? k4 + 8 : k4;    // the last prefetch re-reads this step
-            const double c0n = sc[kn * 16 + lane], w0n = sw[kn * 16 + lane];
-            const double c1n = sc[kn * 16 + 64 + lane], w1n = sw[kn * 16 + 64 + lane];
-            const double a0n = sp[abase - 8 * kn], a1n = sp[abase - 8 * kn - 32];
-            // the reads stay ahead of the MFMAs and their results are consumed
-            // only after all four are issued
-            __builtin_amdgcn_sched_barrier(0);
-            m0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, c0v, m0, 0, 0, 0);
-            v0 = __builtin_amdgcn_mfma_f64_16x16x4f64(fabs(a0), w0v, v0, 0, 0, 0);
-            m1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, c1v, m1, 0, 0, 0);
-            v1 = __builtin_amdgcn_mfma_f64_16x16x4f64(fabs(a1), w1v, v1, 0, 0, 0);
-            __builtin_amdgcn_sched_barrier(0);
-            c0v = c0n; w0v = w0n; c1v = c1n; w1v = w1n; a0 = a0n; a1 = a1n;
+        float c0v = sc[lane], w0v = sw[lane], c1v = sc[64 + lane], w1v = sw[64 + lane];
+        float a0 = sp[abase], a1 = sp[abase - 32];
+        // FP32 accumulators over chunks of 8 iterations (32 products each), the
+        // chunks summed in FP64
+        double md[4] = {0.0, 0.0, 0.0, 0.0}, vd[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int cs = 0; cs < kmax; cs += 64) {
+            const int ce = cs + 64 < kmax ? cs + 64 : kmax;
+            f4 m0 = f4{0.0f, 0.0f, 0.0f, 0.0f}, v0 = m0, m1 = m0, v1 = m0;
+            for (int k4 = cs; k4 < ce; k4 += 8) {
+                const int kn = k4 + 8 < kmax ? k4 + 8 : k4;    // the last prefetch re-reads this step
+                const float c0n = sc[kn * 16 + lane], w0n = sw[kn * 16 + lane];
+                const float c1n = sc[kn * 16 + 64 + lane], w1n = sw[kn * 16 + 64 + lane];
+                const float a0n = sp[abase - 8 * kn], a1n = sp[abase - 8 * kn - 32];
+                // the reads stay ahead of the MFMAs and their results are consumed
+                // only after all four are issued
+                __builtin_amdgcn_sched_barrier(0);
+                m0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, c0v, m0, 0, 0, 0);
+                v0 = __builtin_amdgcn_mfma_f32_16x16x4f32(fabsf(a0), w0v, v0, 0, 0, 0);
+                m1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, c1v, m1, 0, 0, 0);
+                v1 = __builtin_amdgcn_mfma_f32_16x16x4f32(fabsf(a1), w1v, v1, 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+                c0v = c0n; w0v = w0n; c1v = c1n; w1v = w1n; a0 = a0n; a1 = a1n;
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                md[i] += (double)m0[i] + (double)m1[i];
+                vd[i] += (double)v0[i] + (double)v1[i];
+            }
         }
-        const d4 am = m0 + m1, as = v0 + v1;
         if (!cin) continue;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int rr4 = 16 * rt + 4 * i + lq, k = rr4 >> 3, rr = rr4 & 7;
+            const int rr4 = 16 * rt + 4 * lq + i, k = rr4 >> 3, rr = rr4 & 7;
             if (k >= N) continue;
-            const double mF = am[i];
-            // both sums have nonnegative terms; rounded upward as a whole, 2^-1000 for
-            // any flushed subnormal part
-            const double tot = as[i] + dt[i];
-            const double sF = k > sjl ? INFINITY : tot + tot * A.wid + 0x1p-1000;
+            const double mF = md[i];
+            // both sums have nonnegative terms; rounded upward as a whole (FP32
+            // chunks and FP64 sums), 2^-90 for products lost to underflow
+            const double tot = vd[i] + dt[i];
+            const double sF = k > sjl ? INFINITY : tot + tot * (A.wid + A.wid32) + 0x1p-90;
             double so = sF * A.scale + A.shift;
             if (FP) {
                 // [mF - sF, mF + sF] inside [mi - si, mi + si], with the rounding of the
@@ -683,6 +716,7 @@ static int launch_tube2(int B, int N, int U, const double* phi, const double* e,
     a.pad = pad;
     a.mu = mu; a.sigma = sigma; a.B = B; a.N = N; a.U = U;
     a.wid = tube_wid(N);
+    a.wid32 = 1.1 * (32.0 + 6.0) * 0x1p-24;
     a.scale = scale; a.shift = shift;
     const int64_t cols = (int64_t)B * U;
     if (cols == 0 || N == 0) return LEB_OK;
@@ -691,7 +725,8 @@ static int launch_tube2(int B, int N, int U, const double* phi, const double* e,
     const int gy = (nrt + 4 * TM_RT - 1) / (4 * TM_RT);
     if (gx > 0x7fffffff || cols > 0x7fffffff) return LEB_EINVAL;
     const size_t nst = N > 1 ? N - 1 : 0;
-    const size_t smem = ((size_t)(N + 4) * 16 + (size_t)N * 8 + nst * 8 + 2 * (2 * nst + 8) * 16 + 4) * sizeof(double);
+    const size_t smem = ((size_t)N * 8 + nst * 8 + 4) * sizeof(double) +
+                        ((size_t)(N + 4) * 16 + 2 * (2 * nst + 8) * 16) * sizeof(float);
     const bool isfp = fp.state != nullptr, lng = N > 65;
     const int which = (isfp ? 2 : 0) + (lng ? 1 : 0);
     using K2 = void (*)(const double*, Tube2Args, TubeFP);
@@ -857,7 +892,7 @@ int fp_check_args(const leb_fp_options* opt, const double* e, int N) {
     for (int q = 0; q < 6; ++q)
         if (!(e[q] >= 0.0) || !isfinite(e[q])) return LEB_EINVAL;
     // the compact tube map keeps Phi's two residual columns, the affine sums and
-    // the residuals of all steps of 16 node columns in LDS: 768 N + 2016 bytes
+    // the residuals of all steps of 16 node columns in LDS: 448 N + 990 bytes
     if (N > FP_MAX_N) return LEB_ENOTSUP;
     return LEB_OK;
 }
