@@ -10,10 +10,11 @@
 //     staging arrays, bounded in chunks of CB boxes, and scattered back.
 // T and CB are chosen by timing candidates on the batch's own data (the
 // autotuner), with results cached in a text file keyed by GPU
-// architecture and group shape.  The launches of all groups are captured
-// on two streams (analytic groups on one, MLP groups on the other, so the
-// VALU-bound and MFMA-bound work overlap) into one hipGraph; a submit is
-// one graph launch.
+// architecture and group shape.  The tiles of every analytic group then
+// form one work queue, bounded by one persistent launch (workgroups take
+// tiles from a device counter, largest tiles first); it and the MLP groups'
+// launches are captured on two streams (the VALU-bound and MFMA-bound work
+// overlap) into one hipGraph; a submit is one graph launch.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -104,6 +105,9 @@ struct leb_batch_s {
     hipEvent_t fork = nullptr, join = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    PbhQueueArgs queue = {nullptr, 0, 0, nullptr};   // every analytic group's tiles in one persistent launch
+    size_t queue_smem = 0;
+    int queue_grid = 0;
     std::string info;
 };
 
@@ -378,6 +382,36 @@ extern "C" int leb_batch_create(const leb_problem* probs, int32_t count, const c
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    // the analytic groups' tiles as one work queue, largest tiles first
+    if (!rc && !b->pbh.empty()) {
+        std::vector<const PbhGroup*> order;
+        for (const PbhGroup& g : b->pbh) order.push_back(&g);
+        std::stable_sort(order.begin(), order.end(), [](const PbhGroup* x, const PbhGroup* y) {
+            return x->T * x->dyn.n_units > y->T * y->dyn.n_units;
+        });
+        std::vector<PbhQueueGroup> hq;
+        int first = 0;
+        for (const PbhGroup* g : order) {
+            PbhQueueGroup q;
+            q.tiles = g->tiles; q.first = first; q.n_tiles = g->n_tiles;
+            q.U = g->dyn.n_units; q.T = g->T;
+            q.c = g->dyn.dt / g->dyn.m; q.kL = g->dyn.k_spring * g->dyn.rest_len; q.L0 = g->dyn.rest_len;
+            hq.push_back(q);
+            first += g->n_tiles;
+            b->queue_smem = std::max(b->queue_smem, pbh_smem_bytes_T(q.U, q.T));
+        }
+        PbhQueueGroup* dq = nullptr;
+        int* cnt = nullptr;
+        if ((rc = balloc(b, hq.size() * sizeof(PbhQueueGroup), (void**)&dq)) ||
+            (rc = balloc(b, sizeof(int), (void**)&cnt))) {
+        } else if (hipMemcpy(dq, hq.data(), hq.size() * sizeof(PbhQueueGroup), hipMemcpyHostToDevice) != hipSuccess) {
+            rc = LEB_EDEVICE;
+        } else {
+            b->queue = PbhQueueArgs{dq, (int)hq.size(), first, cnt};
+            b->queue_grid = pbh_queue_grid(b->queue_smem, first);
+            if (b->queue_grid < 1) rc = LEB_EDEVICE;
+        }
+    }
     if (!rc && hipDeviceSynchronize() != hipSuccess) rc = LEB_EDEVICE;
     // capture: analytic groups on s0, MLP groups on s1, joined
     if (!rc) {
@@ -385,8 +419,7 @@ extern "C" int leb_batch_create(const leb_problem* probs, int32_t count, const c
         bool capturing = !rc;
         if (!rc && (hipEventRecord(b->fork, b->s0) != hipSuccess || hipStreamWaitEvent(b->s1, b->fork, 0) != hipSuccess))
             rc = LEB_EDEVICE;
-        for (const PbhGroup& g : b->pbh)
-            if (!rc) rc = pbh_run(g, b->s0);
+        if (!rc && b->queue.total > 0) rc = launch_pbh_queue(b->queue, b->queue_smem, b->queue_grid, b->s0);
         for (const NNGroup& g : b->nn)
             if (!rc) rc = nn_run(g, b->s1);
         if (!rc && (hipEventRecord(b->join, b->s1) != hipSuccess || hipStreamWaitEvent(b->s0, b->join, 0) != hipSuccess))
@@ -404,6 +437,11 @@ extern "C" int leb_batch_create(const leb_problem* probs, int32_t count, const c
         return rc;
     }
     char line[256];
+    if (b->queue.total > 0) {
+        snprintf(line, sizeof line, "pbh work queue: %d tiles of %d groups, %d persistent workgroups\n", b->queue.total,
+                 b->queue.n_groups, b->queue_grid);
+        b->info += line;
+    }
     for (const PbhGroup& g : b->pbh) {
         snprintf(line, sizeof line, "pbh U=%d problems=%zu units=%lld T=%d%s\n", g.dyn.n_units, g.probs.size(),
                  (long long)g.units, g.T, g.cached ? " (cached)" : "");

@@ -51,6 +51,20 @@ struct PbhTile {
 constexpr int PBH_BLOCK_LANES = 256;
 // tiles: device array of n_tiles tiles, each of at most T units (T <= 256 / n_units)
 int launch_pbh_tiles(const leb_dynamics* dyn, const PbhTile* tiles, int n_tiles, int T, hipStream_t stream);
+// one analytic group of a batch in the work queue: its tiles are items first .. first + n_tiles - 1
+struct PbhQueueGroup {
+    const PbhTile* tiles;
+    int first, n_tiles;
+    int U, T;
+    double c, kL, L0;
+};
+struct PbhQueueArgs {
+    const PbhQueueGroup* groups;   // device, in item order
+    int n_groups, total;
+    int* counter;                  // device
+};
+int launch_pbh_queue(const PbhQueueArgs& q, size_t smem, int grid, hipStream_t stream);
+int pbh_queue_grid(size_t smem, int total);
 size_t pbh_smem_bytes_T(int U, int T);
 
 int launch_pbh_chain(const leb_dynamics* dyn, int64_t units, const double* z, const double* v,

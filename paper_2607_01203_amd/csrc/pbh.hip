@@ -39,6 +39,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "ivl.hpp"
 #include "leb.h"
 #include "leb_internal.hpp"
@@ -244,5 +246,62 @@ int launch_pbh_tiles(const leb_dynamics* dyn, const PbhTile* tiles, int n_tiles,
     return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
 }
 
+// ------------------------------------------------------------ work queue
+//
+// Every analytic group of a batch in one persistent launch: a workgroup
+// takes the next tile (group, tile) from a device counter until the tiles
+// run out, and bounds it exactly as pbh_chain_fwd bounds a tile launch of
+// that group (the same node passes, the group's U, T and constants), so the
+// results equal the per-group launches bit for bit.  The counter must be 0
+// when the launch starts (a one-thread reset kernel before it).
+__global__ void pbh_queue_reset_kernel(int* counter) { *counter = 0; }
+
+__global__ void __launch_bounds__(PBH_BLOCK) pbh_queue_kernel(PbhQueueArgs Q) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_item;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(Q.counter, 1);
+        __syncthreads();              // the item is visible; the previous tile's LDS use is over
+        const int item = s_item;
+        if (item >= Q.total) return;  // the same for every thread of the workgroup
+        int g = 0;
+        while (g + 1 < Q.n_groups && Q.groups[g + 1].first <= item) ++g;
+        const PbhQueueGroup& G = Q.groups[g];
+        ChainArgs A = {};
+        A.fold = SweepFold{nullptr, nullptr, nullptr, 0, 0};
+        A.U = G.U; A.T = G.T; A.c = G.c; A.kL = G.kL; A.L0 = G.L0; A.pad = 0.0; A.compact = 0;
+        const int U = G.U, T = G.T;
+        SpringOut* s_sp = reinterpret_cast<SpringOut*>(smem);                  // [T][U]
+        uint32_t* s_flag = reinterpret_cast<uint32_t*>(s_sp + (size_t)T * U);   // [T]
+        const PbhTile& pt = G.tiles[item - G.first];
+        const TileRef t0{pt.z, pt.v, pt.mu, pt.sigma, pt.r_lo, pt.r_hi, pt.c_bar, pt.rho_bar, pt.flags, pt.n};
+        for (int q = tid; q < T; q += PBH_BLOCK) s_flag[q] = 0u;
+        const int lt = tid / U;
+        const int i = tid - lt * U;
+        NodeIn d0;
+        node_load(t0, U, lt, i, d0);
+        __syncthreads();              // s_flag cleared
+        node_pass(A, t0, d0, lt, i, s_sp, s_flag);
+        __syncthreads();              // every thread has read s_item and finished with the LDS
+    }
+}
+
+int launch_pbh_queue(const PbhQueueArgs& q, size_t smem, int grid, hipStream_t stream) {
+    if (q.total == 0) return LEB_OK;
+    hipLaunchKernelGGL(pbh_queue_reset_kernel, dim3(1), dim3(1), 0, stream, q.counter);
+    hipLaunchKernelGGL(pbh_queue_kernel, dim3((unsigned)grid), dim3(PBH_BLOCK), smem, stream, q);
+    return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
+}
+
+int pbh_queue_grid(size_t smem, int total) {
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pbh_queue_kernel, PBH_BLOCK, smem) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return -1;
+    const int64_t g = (int64_t)std::max(per_cu, 1) * std::max(cus, 1);
+    return (int)std::min<int64_t>(g, total);
+}
 
 }  // namespace leb
