@@ -54,9 +54,10 @@ HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
 # WRITE_SIZE (KiB per dispatch, rocprofv3 --pmc), and the factors that map each
 # counter to bytes, measured on a copy kernel of known size; None until taken for
 # the kernel as it is now.
-TUBE_PMC_KIB = (27251, 35859)
+TUBE_PMC_KIB = (27280, 36110)
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 matrix (= vector) peak
+FP32_MFMA_PEAK_TFLOPS = 157.3    # MI355X dense FP32 matrix peak (the compact tube map's contraction)
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # lane-ops/s of non-packed VALU issue (39.3 T)
 # VALU lane-operations per unit of the path-based bound kernel at nx = 168:
 # SQ_INSTS_VALU x 64 / units from rocprofv3 --pmc on the 2,560 x 40 launch
@@ -238,7 +239,7 @@ def main():
                 "kernel": "tube_map2_kernel", "launch_us": round(tube_us, 2), "launches": len(tube_ms),
                 "units_per_launch": B * U, "bytes_per_launch": tube_bytes,
                 "flops_per_unit": tube_flops_per_column(N), "mfma_tflops": round(tflops, 2),
-                "mfma_frac": round(tflops / FP64_PEAK_TFLOPS, 4)}
+                "mfma_frac": round(tflops / FP32_MFMA_PEAK_TFLOPS, 4), "mfma_dtype": "f32"}
     # the bound kernel of the same sweeps (its own roofline is taken at the
     # replicated scale below)
     bound_us = 1e3 * float(np.mean(bound_ms))
