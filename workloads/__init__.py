@@ -324,6 +324,62 @@ def fixed_point_cfg(seed: int = 4, batch: int = 256, N: int = 40, n_units: int =
 
 
 # --------------------------------------------------------------------------
+# system-level synthesis layer (closed-loop responses from Riccati recursions)
+
+@dataclass
+class SlsProblem:
+    """One controller update of chain trajectories: nominal (z, v), the
+    diagonal SLS weights per (trajectory, k, j) and the disturbance model
+    E(x) = [diag(e) | thrust columns] (nw = nx + n_units)."""
+    dyn: ChainDynamics
+    z: np.ndarray                 # [batch][N][nx]
+    v: np.ndarray                 # [batch][N][nu]
+    qx: np.ndarray                # [batch][N+1][N][nx]
+    qu: np.ndarray                # [batch][N][N][nu]
+    e: np.ndarray                 # [nx]
+    thrust: float
+
+    @property
+    def batch(self) -> int:
+        return self.z.shape[0]
+
+    @property
+    def N(self) -> int:
+        return self.z.shape[1]
+
+
+def sls_cfg(seed: int = 5, batch: int = 256, N: int = 40, n_units: int = 1, e_scale: float = 2e-2,
+            thrust: float = 0.2, tau_max: float = 1.0) -> SlsProblem:
+    """Planar quadrotor chains (the paper's planar quadrotor task has N = 40)
+    with nominal states and inputs drawn like the chain workload (spring
+    separations kept 0.6 clear of zero).  Weights: the hover tracking
+    weights diag(Q~) = HOVER_Q per node and R~ = HOVER_R, plus dual weights
+    U(0, tau_max) per (k, j, coordinate) standing in for the constraint
+    duals of both faces of box constraints.  Disturbance: e_scale on every
+    node's (vx, vz) and a thrust-magnitude disturbance `thrust` (newtons)."""
+    dyn = ChainDynamics(n_units=n_units)
+    rng = rng_for(seed)
+    z, v = _chain_nominal(rng, (batch, N), n_units, dyn.rest_len, 0.6, None)
+    qx = np.tile(np.asarray(HOVER_Q, dtype=np.float64), n_units) + \
+        rng.uniform(0.0, tau_max, (batch, N + 1, N, dyn.nx))
+    qu = HOVER_R + rng.uniform(0.0, tau_max, (batch, N, N, dyn.nu))
+    e = np.tile(e_scale * np.array([0.0, 0.0, 0.0, 1.0, 1.0, 0.0]), n_units)
+    return SlsProblem(dyn, z, v, qx, qu, e, float(thrust))
+
+
+def random_ltv(seed: int, batch: int, N: int, nx: int, nu: int, scale: float = 0.1):
+    """Random time-varying pairs A_k = I + scale G, B_k = scale H (G, H
+    standard normal) [batch][N][nx][nx], [batch][N][nx][nu], and diagonal
+    weights qx U(0.5, 2) [batch][N+1][N][nx], qu U(0.05, 0.5) [batch][N][N][nu]."""
+    rng = rng_for(seed)
+    A = np.eye(nx) + scale * rng.normal(size=(batch, N, nx, nx))
+    B = scale * rng.normal(size=(batch, N, nx, nu))
+    qx = rng.uniform(0.5, 2.0, (batch, N + 1, N, nx))
+    qu = rng.uniform(0.05, 0.5, (batch, N, N, nu))
+    return A, B, qx, qu
+
+
+# --------------------------------------------------------------------------
 # uneven batch
 
 @dataclass
