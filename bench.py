@@ -34,7 +34,9 @@ Prints ONE JSON line.  Extra objects:
   an equal GPU time budget), interval_hessian_study (satellite and 3-D
   quadrotor: mean row width of the path, expanded and classic enclosures and
   of 10,000 random samples for radii 0.01 .. 0.2, and the time of one call
-  for a single local set).
+  for a single local set), sls_update (one controller update of the SLS
+  layer: linearization, Riccati responses, exact tube/LEB fixed point with
+  the state-dependent disturbance error, 256 trajectories of N = 40).
 """
 from __future__ import annotations
 
@@ -257,6 +259,7 @@ def main():
         "adjoint": adjoint(leb, W, dev, stream),
         "nominal_pgd": nominal_pgd(leb, W, dev, stream),
         "interval_hessian_study": interval_hessian_study(leb, W, dev, stream),
+        "sls_update": sls_update(leb, W, dev, stream),
         "roofline_nn": nn_roofline(leb, W, dev, stream, args),
         "learned_nn": nn_learned(leb, W, dev, stream, args),
         "batched_uneven": batched_uneven(leb, W, dev, stream, args)}
@@ -453,6 +456,76 @@ def nominal_pgd(leb, W, dev, stream):
                      "mean_width_start": float(w0.mean()), "mean_width_sampling": float(best.mean()),
                      "mean_width_pgd": float(w.mean()), "pgd_better_frac": float((w < best).double().mean()),
                      "pgd_not_worse_frac": float((w <= best).double().mean())}
+    return res
+
+
+def sls_update(leb, W, dev, stream):
+    """One controller update of the SLS layer on 256 trajectories, N = 40:
+    linearization with the thrust-disturbance matrix (leb_linearize),
+    closed-loop responses by the parallel Riccati recursions
+    (leb_sls_responses) and the exact tube/LEB fixed point with r_dist
+    (leb_sls_fixed_point), for the planar quadrotor (nx = 6) and chains of 2
+    and 5 (nx = 12, 30).  Each call is timed with HIP events on the stream
+    (buffers allocated beforehand); bytes are the algorithmic minimum: the
+    responses write Phi and K once, the fixed point reads Phi once."""
+    import numpy as np
+    import torch
+    L = leb.lib()
+    vp = lambda t: ctypes.c_void_p(t.data_ptr())
+    f64 = torch.float64
+    res = {}
+    for U in (1, 2, 5):
+        p = W.sls_cfg(n_units=U)
+        dyn = leb.dynamics_like(p.dyn)
+        B, N, nx, nu = p.batch, p.N, p.dyn.nx, p.dyn.nu
+        n, nw = nx + nu, nx + U
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        z, v, qx, qu = t(p.z), t(p.v), t(p.qx), t(p.qu)
+        A = torch.empty((B, N, nx, nx), dtype=f64, device=dev)
+        Bm = torch.empty((B, N, nx, nu), dtype=f64, device=dev)
+        E = torch.empty((B, N, nx, nw), dtype=f64, device=dev)
+        K = torch.zeros((B, N, N, nu, nx), dtype=f64, device=dev)
+        phi = torch.zeros((B, N, N, n, nx), dtype=f64, device=dev)
+        mu = torch.empty((B, N, n), dtype=f64, device=dev)
+        sg = torch.empty_like(mu)
+        lo = torch.empty((B, N, nx), dtype=f64, device=dev)
+        hi = torch.empty_like(lo)
+        cert = torch.empty((B,), dtype=torch.int32, device=dev)
+        eh = (ctypes.c_double * nx)(*[float(x) for x in p.e])
+        sp = ctypes.c_void_p(stream.cuda_stream)
+
+        def lin():
+            leb._check(L.leb_linearize(ctypes.byref(dyn), B, N, vp(z), vp(v), ctypes.cast(eh, ctypes.c_void_p),
+                                       p.thrust, vp(A), vp(Bm), vp(E), sp))
+
+        def resp():
+            leb._check(L.leb_sls_responses(nx, nu, B, N, vp(A), vp(Bm), vp(qx), vp(qu), vp(K), vp(phi), sp))
+
+        def fp():
+            leb._check(L.leb_sls_fixed_point(ctypes.byref(dyn), B, N, vp(z), vp(v), vp(phi), nw, vp(E), p.thrust,
+                                             1e-6, vp(mu), vp(sg), vp(lo), vp(hi), vp(cert), sp))
+
+        for _ in range(2):
+            lin(); resp(); fp()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        reps = 10
+        acc = [0.0, 0.0, 0.0]
+        for _ in range(reps):
+            ev[0].record(stream); lin(); ev[1].record(stream); resp(); ev[2].record(stream); fp(); ev[3].record(stream)
+            torch.cuda.synchronize()
+            for i in range(3):
+                acc[i] += ev[i].elapsed_time(ev[i + 1]) / reps
+        pairs = B * N * (N - 1) // 2
+        phi_bytes = pairs * n * nx * 8
+        k_bytes = pairs * nu * nx * 8
+        total = sum(acc)
+        res["chain%d_256x40" % U] = {
+            "nx": nx, "nu": nu, "nw": nw, "ms_linearize": round(acc[0], 4), "ms_responses": round(acc[1], 4),
+            "ms_fixed_point": round(acc[2], 4), "ms_update": round(total, 4),
+            "step_bounds_per_s": round(B * N / (total * 1e-3), 1),
+            "responses_hbm_frac": round((phi_bytes + k_bytes) / (acc[1] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "fixed_point_phi_read_hbm_frac": round(phi_bytes / (acc[2] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "certified": int(cert.sum().item()), "mean_sigma_state": float(sg[..., :nx].mean())}
     return res
 
 

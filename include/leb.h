@@ -577,6 +577,87 @@ int leb_batch_destroy(leb_batch b);
 /* One line per group: kind, shape, problems, steps, chosen tile and whether it came from the cache. */
 int leb_batch_info(leb_batch b, char* buf, int32_t len);
 
+/*
+ * System-level-synthesis layer: one controller update of section V (the
+ * linearization, the closed-loop responses Phi, and the tube with its LEBs).
+ * Sizes: nx <= 32 states, 1 <= nu <= 16 inputs, nw <= 64 disturbance
+ * columns (LEB_EINVAL beyond); batch <= 65535 trajectories.  All arrays are
+ * device FP64, row-major, 8-byte aligned; the caller owns every buffer.
+ *
+ * leb_linearize -- eq. linearizations for CHAIN dynamics:
+ *   A [batch][N][nx][nx] = df/dx, B [batch][N][nx][nu] = df/du at (z_k, v_k),
+ *   and, when E is not NULL, E [batch][N][nx][nx + U] = E(z_k) for the
+ *   disturbance model E(x) = [diag(e) | T(x)]: e (host, nx values >= 0) the
+ *   constant per-state disturbance, T(x) the thrust-magnitude disturbance of
+ *   every quadrotor (total thrust (u1 + u2) + thrust w_i, thrust >= 0 in
+ *   newtons): column i holds thrust dt/m (-sin theta_i, cos theta_i) on node
+ *   i's (vx, vz) rows (eqs. linearization_error_all, linearization_error_dist).
+ *   Other kinds: LEB_ENOTSUP.  E needs nx <= 32 (LEB_ENOTSUP beyond).
+ */
+int leb_linearize(const leb_dynamics* dyn, int32_t batch, int32_t N, const double* z, const double* v,
+                  const double* e, double thrust, double* A, double* B, double* E, void* stream);
+
+/*
+ * leb_sls_responses -- closed-loop responses of the reformulated SLS problem
+ * (eq. fastsls_qp_reform) by the parallel Riccati recursions (appendix on
+ * solving for Phi, eqs. backward_prop and forward_prop, with the start
+ * Phi^x_{j+1,j} = I of eq. fastsls_qp_cost_reform_init), one workgroup per
+ * (trajectory, disturbance time j):
+ *   A [batch][N][nx][nx], B [batch][N][nx][nu]   the LTV pairs (A_k, B_k)
+ *   qx [batch][N+1][N][nx], qu [batch][N][N][nu] diagonal weights Q^x_{k,j},
+ *       Q^u_{k,j} (Q^{ux} = 0; box constraints make Q^T Q of eq.
+ *       sls_cost_matrices_tau diagonal); qu > 0 and qx >= 0 make every
+ *       Cholesky pivot positive, otherwise that (trajectory, j) gets NaN gains
+ *   K [batch][N][N][nu][nx]     out: gains K_{k,j} for j < k < N
+ *   phi [batch][N][N][nx+nu][nx] out: Phi_{k,j} = [Phi^x_{k,j}; Phi^u_{k,j}]
+ *       for j < k < N (rows 0..nx-1 state, nx.. input responses)
+ * Entries with k <= j of K and phi are not written.  FP64 round-to-nearest
+ * (the responses define the controller; the tube map bounds their use).
+ */
+int leb_sls_responses(int32_t nx, int32_t nu, int32_t batch, int32_t N, const double* A, const double* B,
+                      const double* qx, const double* qu, double* K, double* phi, void* stream);
+
+/*
+ * leb_sls_tube_map -- tube centre and width of time-varying responses (eqs.
+ * tight_tube_center, tight_tube_width):
+ *   mu_k    = sum_{j<k} Phi_{k,j} c_bar_j
+ *   sigma_k = sum_{j<k} || Phi_{k,j} [E_j  diag(rho_bar_j)] ||_{1,r}
+ *           = sum_{j<k} |Phi_{k,j} E_j| 1 + |Phi_{k,j}| rho_bar_j
+ *   phi as leb_sls_responses (only j < k is read), E [batch][N][nx][nw]
+ *   (NULL when nw = 0), c_bar, rho_bar [batch][N][nx]; mu, sigma
+ *   [batch][N][nx+nu] outputs (mu_0 = sigma_0 = 0).  sigma is rounded upward
+ *   and covers the rounding of mu.  A non-finite input at some j < k makes
+ *   row k mu = 0, sigma = +inf.
+ */
+int leb_sls_tube_map(int32_t nx, int32_t nu, int32_t nw, int32_t batch, int32_t N, const double* phi,
+                     const double* E, const double* c_bar, const double* rho_bar, double* mu, double* sigma,
+                     void* stream);
+
+/*
+ * leb_sls_fixed_point -- the exact tube/LEB fixed point of one controller
+ * update (section V loop; Theorem 3): the tube at step k depends on the
+ * residual zonotopes of steps j < k only, so steps are taken in order:
+ * tube row k (as leb_sls_tube_map), then the path-based bound (as
+ * leb_analytic_bound) over the tube set (z_k, v_k) + mu_k +- sigma_k, plus
+ * the disturbance error r_dist of eq. interval_r_dist when thrust > 0 (CHAIN
+ * only: the last U columns of E are the thrust columns of leb_linearize's
+ * model; r_dist encloses (E(x) - E_k) w over the tube's theta interval),
+ * then c_bar = (lo + hi)/2, rho_bar = (hi - lo)/2 + pad.  The result is
+ * C = F(C) for the upward-rounded map: no further sweep changes it.
+ *   z, v [batch][N][nx], [batch][N][nu]; phi, E as leb_sls_tube_map
+ *   mu, sigma [batch][N][nx+nu] out: the tube
+ *   r_lo, r_hi [batch][N][nx] out (both NULL to skip): remainder enclosures
+ *   certified [batch] out (may be NULL): 1 when every tube entry and residual
+ *       is finite
+ * Kinds CHAIN, SATELLITE, QUAD3D (LEB_ENOTSUP otherwise).  2N + 1 launches
+ * on `stream`, no host synchronisation.  Uses a library-owned, grow-only
+ * device workspace; calls serialise on the host and their kernels on the
+ * device, like leb_fixed_point_solve.
+ */
+int leb_sls_fixed_point(const leb_dynamics* dyn, int32_t batch, int32_t N, const double* z, const double* v,
+                        const double* phi, int32_t nw, const double* E, double thrust, double pad, double* mu,
+                        double* sigma, double* r_lo, double* r_hi, uint32_t* certified, void* stream);
+
 /* Human-readable text of a leb_status code (static storage). */
 const char* leb_strerror(int code);
 

@@ -208,6 +208,16 @@ def lib():
         L.leb_nn_targets.restype = ctypes.c_int
         L.leb_nn_surrogate_bound.argtypes = [vp, i32, i32, i32, i32] + [vp] * 7
         L.leb_nn_surrogate_bound.restype = ctypes.c_int
+        f64c_ = ctypes.c_double
+        L.leb_linearize.argtypes = [ctypes.POINTER(Dynamics), i32, i32, vp, vp, vp, f64c_, vp, vp, vp, vp]
+        L.leb_linearize.restype = ctypes.c_int
+        L.leb_sls_responses.argtypes = [i32, i32, i32, i32] + [vp] * 7
+        L.leb_sls_responses.restype = ctypes.c_int
+        L.leb_sls_tube_map.argtypes = [i32, i32, i32, i32, i32] + [vp] * 7
+        L.leb_sls_tube_map.restype = ctypes.c_int
+        L.leb_sls_fixed_point.argtypes = [ctypes.POINTER(Dynamics), i32, i32, vp, vp, vp, i32, vp, f64c_, f64c_] + \
+            [vp] * 6
+        L.leb_sls_fixed_point.restype = ctypes.c_int
         L.leb_strerror.argtypes = [ctypes.c_int]
         L.leb_strerror.restype = ctypes.c_char_p
         L.leb_version.restype = ctypes.c_char_p
@@ -320,6 +330,91 @@ def sample_remainder(dyn: Dynamics, z, v, sigma, t, mu=None, stream=None):
                                       _dev_ptr(t, "t", f64), _dev_ptr(lo, "s_lo", f64), _dev_ptr(hi, "s_hi", f64),
                                       _stream(stream)))
     return lo, hi
+
+
+def linearize(dyn: Dynamics, z, v, e=None, thrust=0.0, stream=None):
+    """Point Jacobians A, B and, when e is given (nx values), the disturbance
+    matrices E(z_k) of the thrust model (see leb.h: leb_linearize).
+    Returns (A, B, E or None)."""
+    import torch
+    f64 = torch.float64
+    B_, N = int(z.shape[0]), int(z.shape[1])
+    nx, nu = dyn.nx, dyn.nu
+    A = torch.empty((B_, N, nx, nx), dtype=f64, device=z.device)
+    Bm = torch.empty((B_, N, nx, nu), dtype=f64, device=z.device)
+    E = None
+    eh = None
+    if e is not None:
+        E = torch.empty((B_, N, nx, nx + dyn.n_units), dtype=f64, device=z.device)
+        eh = (ctypes.c_double * nx)(*[float(x) for x in e])
+    _check(lib().leb_linearize(ctypes.byref(dyn), B_, N, _dev_ptr(z, "z", f64), _dev_ptr(v, "v", f64),
+                               None if eh is None else ctypes.cast(eh, ctypes.c_void_p), float(thrust),
+                               _dev_ptr(A, "A", f64), _dev_ptr(Bm, "B", f64), _dev_ptr(E, "E", f64),
+                               _stream(stream)))
+    return A, Bm, E
+
+
+def sls_responses(A, B, qx, qu, stream=None):
+    """Closed-loop responses by the parallel Riccati recursions (see leb.h:
+    leb_sls_responses).  A [b][N][nx][nx], B [b][N][nx][nu], qx [b][N+1][N][nx],
+    qu [b][N][N][nu] float64 GPU tensors.  Returns (K, phi); entries k <= j are
+    zero."""
+    import torch
+    f64 = torch.float64
+    b, N, nx, nu = (int(x) for x in B.shape)
+    K = torch.zeros((b, N, N, nu, nx), dtype=f64, device=A.device)
+    phi = torch.zeros((b, N, N, nx + nu, nx), dtype=f64, device=A.device)
+    _check(lib().leb_sls_responses(nx, nu, b, N, _dev_ptr(A, "A", f64), _dev_ptr(B, "B", f64),
+                                   _dev_ptr(qx, "qx", f64), _dev_ptr(qu, "qu", f64), _dev_ptr(K, "K", f64),
+                                   _dev_ptr(phi, "phi", f64), _stream(stream)))
+    return K, phi
+
+
+def sls_tube_map(phi, E, c_bar, rho_bar, stream=None):
+    """Tube of time-varying responses (see leb.h: leb_sls_tube_map).
+    phi [b][N][N][n][nx], E [b][N][nx][nw], c_bar, rho_bar [b][N][nx].
+    Returns (mu, sigma) [b][N][n]."""
+    import torch
+    f64 = torch.float64
+    b, N, _, n, nx = (int(x) for x in phi.shape)
+    nw = int(E.shape[3]) if E is not None else 0
+    mu = torch.empty((b, N, n), dtype=f64, device=phi.device)
+    sg = torch.empty_like(mu)
+    _check(lib().leb_sls_tube_map(nx, n - nx, nw, b, N, _dev_ptr(phi, "phi", f64), _dev_ptr(E, "E", f64),
+                                  _dev_ptr(c_bar, "c_bar", f64), _dev_ptr(rho_bar, "rho_bar", f64),
+                                  _dev_ptr(mu, "mu", f64), _dev_ptr(sg, "sigma", f64), _stream(stream)))
+    return mu, sg
+
+
+def sls_fixed_point(dyn: Dynamics, z, v, phi, E, thrust=0.0, pad=0.0, stream=None):
+    """Exact tube/LEB fixed point of one controller update (see leb.h:
+    leb_sls_fixed_point).  Returns (mu, sigma, r_lo, r_hi, certified)."""
+    import torch
+    f64 = torch.float64
+    b, N = int(z.shape[0]), int(z.shape[1])
+    n = dyn.nx + dyn.nu
+    nw = int(E.shape[3]) if E is not None else 0
+    mu = torch.empty((b, N, n), dtype=f64, device=z.device)
+    sg = torch.empty_like(mu)
+    lo = torch.empty((b, N, dyn.nx), dtype=f64, device=z.device)
+    hi = torch.empty_like(lo)
+    cert = torch.empty((b,), dtype=torch.int32, device=z.device)
+    _check(lib().leb_sls_fixed_point(ctypes.byref(dyn), b, N, _dev_ptr(z, "z", f64), _dev_ptr(v, "v", f64),
+                                     _dev_ptr(phi, "phi", f64), nw, _dev_ptr(E, "E", f64), float(thrust),
+                                     float(pad), _dev_ptr(mu, "mu", f64), _dev_ptr(sg, "sigma", f64),
+                                     _dev_ptr(lo, "r_lo", f64), _dev_ptr(hi, "r_hi", f64),
+                                     _dev_ptr(cert, "certified"), _stream(stream)))
+    return mu, sg, lo, hi, cert
+
+
+def sls_update(dyn: Dynamics, z, v, qx, qu, e, thrust=0.0, pad=0.0, stream=None):
+    """One controller update on the GPU: linearization, responses from the
+    Riccati recursions, and the exact tube/LEB fixed point.  Returns a dict
+    with A, B, E, K, phi, mu, sigma, r_lo, r_hi, certified."""
+    A, Bm, E = linearize(dyn, z, v, e, thrust, stream)
+    K, phi = sls_responses(A, Bm, qx, qu, stream)
+    mu, sg, lo, hi, cert = sls_fixed_point(dyn, z, v, phi, E, thrust, pad, stream)
+    return dict(A=A, B=Bm, E=E, K=K, phi=phi, mu=mu, sigma=sg, r_lo=lo, r_hi=hi, certified=cert)
 
 
 def zonotope_hull(G, c=None, stream=None):

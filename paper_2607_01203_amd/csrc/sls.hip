@@ -1,0 +1,607 @@
+// sls.hip -- the system-level-synthesis layer around the bound: closed-loop
+// responses from the parallel Riccati recursions, the time-varying tube map
+// over them, the state-dependent disturbance error, and the exact tube/LEB
+// fixed point of one controller update.
+//
+// Responses (appendix on solving for Phi, eqs. backward_prop and
+// forward_prop; reformulated problem eq. fastsls_qp_reform): the problem
+// splits over the disturbance time j, so one workgroup owns one (trajectory,
+// j) pair and runs, with every matrix in LDS,
+//   backward  P_{N,j} = diag(qx_{N,j}); for k = N-1 .. j+1:
+//             S = diag(qu_{k,j}) + B_k^T P B_k,  Bc = B_k^T P A_k,
+//             K_{k,j} = -S^-1 Bc (Cholesky),  P <- diag(qx_{k,j}) + A_k^T P A_k + K^T Bc
+//   forward   X = I; for k = j+1 .. N-1: Phi^x_{k,j} = X, Phi^u_{k,j} = K_{k,j} X,
+//             X <- (A_k + B_k K_{k,j}) X.
+// All FP64: the gains define the controller, they are not enclosures.
+//
+// Tube (eqs. tight_tube_center, tight_tube_width) with per-step disturbance
+// matrices E_j [nx][nw]:
+//   mu_k = sum_{j<k} Phi_{k,j} c_bar_j,
+//   sigma_k = sum_{j<k} |Phi_{k,j} E_j| 1 + |Phi_{k,j}| rho_bar_j,
+// plus an allowance that covers the FP64 rounding of both sums.  The blocks
+// Phi_{k,0..k-1} of one row k are contiguous, so a workgroup streams its row
+// once, coalesced, through LDS.
+//
+// Fixed point (section V loop, Theorem 3): the map from the bounds to the
+// tube is causal (the tube at k needs the bounds at j < k only), so one pass
+// over k in order gives the exact fixed point C = F(C): step k runs one row
+// launch (finish step k-1's residual zonotope, then the tube row k) and one
+// bound launch over all trajectories at step k.  The tube rows round upward
+// and the bounds are outward, so C is a post-fixed point of the exact map and
+// the Theorem 3 induction holds.
+//
+// Disturbance error (eqs. linearization_error_dist, interval_r_dist): with a
+// thrust-magnitude disturbance of every planar quadrotor of a chain (total
+// thrust (u1 + u2) + thrust w_i), node i's column of E(x) is
+// thrust dt/m (-sin theta_i, cos theta_i) on its (vx, vz) rows; over the tube
+// set, r_dist lies in +-s with s = mag([E](Omega^x_k) - E_k) row-summed.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <mutex>
+
+#include "leb.h"
+#include "leb_internal.hpp"
+
+namespace leb {
+
+constexpr int SLS_MAX_NX = 32;
+constexpr int SLS_MAX_NU = 16;
+constexpr int SLS_MAX_NW = 64;
+constexpr int SLS_THREADS = 256;
+constexpr size_t SLS_ROW_LDS = 48 * 1024;      // LDS budget of a tube-row workgroup
+
+// ------------------------------------------------------------ responses
+
+struct RiccatiArgs {
+    const double* A; const double* B; const double* qx; const double* qu;
+    double* K; double* phi;
+    int nx, nu, N;
+};
+
+__global__ void __launch_bounds__(SLS_THREADS) sls_riccati_kernel(RiccatiArgs a) {
+    const int j = blockIdx.x, b = blockIdx.y;
+    const int nx = a.nx, nu = a.nu, N = a.N, n = nx + nu;
+    if (j >= N - 1) return;                      // no k with j < k < N
+    extern __shared__ double sm[];
+    double* P = sm;                              // nx*nx   cost-to-go, then X of the forward pass
+    double* Ak = P + nx * nx;                    // nx*nx
+    double* PA = Ak + nx * nx;                   // nx*nx   P A_k, then X' of the forward pass
+    double* Acl = PA + nx * nx;                  // nx*nx   A_k + B_k K
+    double* Bk = Acl + nx * nx;                  // nx*nu
+    double* PB = Bk + nx * nu;                   // nx*nu
+    double* Bc = PB + nx * nu;                   // nu*nx
+    double* Kk = Bc + nu * nx;                   // nu*nx
+    double* L = Kk + nu * nx;                    // nu*nu   S, then its Cholesky factor
+    __shared__ int bad;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const double* Ab = a.A + (size_t)b * N * nx * nx;
+    const double* Bb = a.B + (size_t)b * N * nx * nu;
+    const double* qxb = a.qx + (size_t)b * (N + 1) * N * nx;
+    const double* qub = a.qu + (size_t)b * N * N * nu;
+    double* Kb = a.K + (size_t)b * N * N * nu * nx;
+    double* phib = a.phi + (size_t)b * N * N * n * nx;
+    if (tid == 0) bad = 0;
+    for (int q = tid; q < nx * nx; q += nt) {
+        const int r = q / nx, c = q - r * nx;
+        P[q] = r == c ? qxb[((size_t)N * N + j) * nx + r] : 0.0;
+    }
+    for (int k = N - 1; k > j; --k) {
+        for (int q = tid; q < nx * nx; q += nt) Ak[q] = Ab[(size_t)k * nx * nx + q];
+        for (int q = tid; q < nx * nu; q += nt) Bk[q] = Bb[(size_t)k * nx * nu + q];
+        __syncthreads();
+        // P A_k and P B_k
+        for (int q = tid; q < nx * n; q += nt) {
+            double s = 0.0;
+            if (q < nx * nx) {
+                const int r = q / nx, c = q - r * nx;
+                for (int l = 0; l < nx; ++l) s = fma(P[r * nx + l], Ak[l * nx + c], s);
+                PA[q] = s;
+            } else {
+                const int q2 = q - nx * nx, r = q2 / nu, c = q2 - r * nu;
+                for (int l = 0; l < nx; ++l) s = fma(P[r * nx + l], Bk[l * nu + c], s);
+                PB[q2] = s;
+            }
+        }
+        __syncthreads();
+        // S = diag(qu) + B^T (P B),  Bc = B^T (P A)
+        for (int q = tid; q < nu * n; q += nt) {
+            if (q < nu * nu) {
+                const int r = q / nu, c = q - r * nu;
+                double s = 0.0;
+                for (int l = 0; l < nx; ++l) s = fma(Bk[l * nu + r], PB[l * nu + c], s);
+                L[q] = (r == c ? qub[((size_t)k * N + j) * nu + r] : 0.0) + s;
+            } else {
+                const int q2 = q - nu * nu, r = q2 / nx, c = q2 - r * nx;
+                double s = 0.0;
+                for (int l = 0; l < nx; ++l) s = fma(Bk[l * nu + r], PA[l * nx + c], s);
+                Bc[q2] = s;
+            }
+        }
+        __syncthreads();
+        // Cholesky S = L L^T (lower triangle in place; diagonal holds 1/L_ii)
+        if (tid == 0) {
+            for (int c = 0; c < nu; ++c) {
+                double d = L[c * nu + c];
+                for (int m = 0; m < c; ++m) d -= L[c * nu + m] * L[c * nu + m];
+                if (!(d > 0.0) || !isfinite(d)) { bad = 1; d = 1.0; }
+                const double inv = 1.0 / sqrt(d);
+                L[c * nu + c] = inv;
+                for (int r = c + 1; r < nu; ++r) {
+                    double s = L[r * nu + c];
+                    for (int m = 0; m < c; ++m) s -= L[r * nu + m] * L[c * nu + m];
+                    L[r * nu + c] = s * inv;
+                }
+            }
+        }
+        __syncthreads();
+        // K = -S^-1 Bc, one column per thread: L y = Bc[:, c], then L^T x = y
+        for (int c = tid; c < nx; c += nt) {
+            for (int r = 0; r < nu; ++r) {
+                double s = Bc[r * nx + c];
+                for (int m = 0; m < r; ++m) s -= L[r * nu + m] * Kk[m * nx + c];
+                Kk[r * nx + c] = s * L[r * nu + r];
+            }
+            for (int r = nu - 1; r >= 0; --r) {
+                double s = Kk[r * nx + c];
+                for (int m = r + 1; m < nu; ++m) s -= L[m * nu + r] * Kk[m * nx + c];
+                Kk[r * nx + c] = s * L[r * nu + r];
+            }
+            for (int r = 0; r < nu; ++r) Kk[r * nx + c] = bad ? NAN : -Kk[r * nx + c];
+        }
+        __syncthreads();
+        // P <- diag(qx) + A^T (P A) + K^T Bc; the gain goes out
+        for (int q = tid; q < nx * nx; q += nt) {
+            const int r = q / nx, c = q - r * nx;
+            double s = 0.0;
+            for (int l = 0; l < nx; ++l) s = fma(Ak[l * nx + r], PA[l * nx + c], s);
+            double t = 0.0;
+            for (int m = 0; m < nu; ++m) t = fma(Kk[m * nx + r], Bc[m * nx + c], t);
+            P[q] = (r == c ? qxb[((size_t)k * N + j) * nx + r] : 0.0) + s + t;
+        }
+        for (int q = tid; q < nu * nx; q += nt) Kb[((size_t)k * N + j) * nu * nx + q] = Kk[q];
+        __syncthreads();
+    }
+    // forward propagation from Phi^x_{j+1,j} = I
+    double* X = P;
+    double* Xn = PA;
+    for (int q = tid; q < nx * nx; q += nt) X[q] = (q / nx == q % nx) ? 1.0 : 0.0;
+    for (int k = j + 1; k < N; ++k) {
+        for (int q = tid; q < nx * nx; q += nt) Ak[q] = Ab[(size_t)k * nx * nx + q];
+        for (int q = tid; q < nx * nu; q += nt) Bk[q] = Bb[(size_t)k * nx * nu + q];
+        for (int q = tid; q < nu * nx; q += nt) Kk[q] = Kb[((size_t)k * N + j) * nu * nx + q];
+        __syncthreads();
+        double* out = phib + ((size_t)k * N + j) * n * nx;
+        for (int q = tid; q < n * nx; q += nt) {
+            const int r = q / nx, c = q - r * nx;
+            double s;
+            if (r < nx) {
+                s = X[q];
+            } else {
+                s = 0.0;
+                for (int m = 0; m < nx; ++m) s = fma(Kk[(r - nx) * nx + m], X[m * nx + c], s);
+            }
+            out[q] = s;
+        }
+        for (int q = tid; q < nx * nx; q += nt) {
+            const int r = q / nx, c = q - r * nx;
+            double s = 0.0;
+            for (int m = 0; m < nu; ++m) s = fma(Bk[r * nu + m], Kk[m * nx + c], s);
+            Acl[q] = Ak[q] + s;
+        }
+        __syncthreads();
+        if (k + 1 < N) {
+            for (int q = tid; q < nx * nx; q += nt) {
+                const int r = q / nx, c = q - r * nx;
+                double s = 0.0;
+                for (int l = 0; l < nx; ++l) s = fma(Acl[r * nx + l], X[l * nx + c], s);
+                Xn[q] = s;
+            }
+            __syncthreads();
+            double* t = X; X = Xn; Xn = t;
+        }
+    }
+}
+
+static size_t riccati_smem(int nx, int nu) {
+    return sizeof(double) * (size_t)(4 * nx * nx + 4 * nx * nu + nu * nu);
+}
+
+// ------------------------------------------------------------ tube rows
+
+struct TubeRowArgs {
+    const double* phi;       // [b][N][N][n][nx]
+    const double* E;         // [b][N][nx][nw]
+    const double* cbar;      // [b][N][nx]
+    const double* rbar;      // [b][N][nx]
+    double* mu;              // [b][N][n]
+    double* sigma;           // [b][N][n]
+    int nx, nu, nw, N, jc;
+};
+
+struct RowAcc { double m, s, g; };
+
+// Tube row k of trajectory b; jc disturbance times per LDS chunk, thread
+// t = jj * n + i works on (j0 + jj, row i).  Leaves mu_k, sigma_k in mo[], so[]
+// (LDS, n entries) after the final barrier.
+__device__ void tube_row(const TubeRowArgs& a, int b, int k, double* sm, double* mo, double* so) {
+    const int nx = a.nx, nw = a.nw, N = a.N, n = nx + a.nu, jc = a.jc;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    double* sphi = sm;                           // jc*n*nx
+    double* sE = sphi + (size_t)jc * n * nx;     // jc*nx*nw
+    double* scb = sE + (size_t)jc * nx * nw;     // jc*nx
+    double* srb = scb + jc * nx;                 // jc*nx  (rho_bar)
+    double* se1 = srb + jc * nx;                 // jc*nx  (row sums |E| 1)
+    double* red = se1 + jc * nx;                 // 3*jc*n partial sums
+    const int jj = tid / n, i = tid - jj * n;
+    const bool act = jj < jc;
+    RowAcc acc = {0.0, 0.0, 0.0};
+    const double* prow = a.phi + (((size_t)b * N + k) * N) * n * nx;
+    for (int j0 = 0; j0 < k; j0 += jc) {
+        const int cnt = min(jc, k - j0);
+        const double* pp = prow + (size_t)j0 * n * nx;
+        for (int q = tid; q < cnt * n * nx; q += nt) sphi[q] = pp[q];
+        const double* ep = a.E + ((size_t)b * N + j0) * nx * nw;
+        for (int q = tid; q < cnt * nx * nw; q += nt) sE[q] = ep[q];
+        const size_t ro = ((size_t)b * N + j0) * nx;
+        for (int q = tid; q < cnt * nx; q += nt) { scb[q] = a.cbar[ro + q]; srb[q] = a.rbar[ro + q]; }
+        __syncthreads();
+        for (int q = tid; q < cnt * nx; q += nt) {
+            double s = 0.0;
+            for (int m = 0; m < nw; ++m) s += fabs(sE[q * nw + m]);
+            se1[q] = s;
+        }
+        __syncthreads();
+        if (act && jj < cnt) {
+            const double* row = sphi + ((size_t)jj * n + i) * nx;
+            const double* cb = scb + jj * nx;
+            const double* rb = srb + jj * nx;
+            const double* e1 = se1 + jj * nx;
+            const double* Ej = sE + (size_t)jj * nx * nw;
+            double m = 0.0, s = 0.0, g = 0.0;
+            for (int l = 0; l < nx; ++l) {
+                const double p = row[l], ap = fabs(p);
+                m = fma(p, cb[l], m);
+                s = fma(ap, rb[l], s);
+                g = fma(ap, fabs(cb[l]) + rb[l] + e1[l], g);
+            }
+            for (int w = 0; w < nw; ++w) {
+                double t = 0.0;
+                for (int l = 0; l < nx; ++l) t = fma(row[l], Ej[l * nw + w], t);
+                s += fabs(t);
+            }
+            acc.m += m; acc.s += s; acc.g += g;
+        }
+        __syncthreads();
+    }
+    if (act) { red[jj * n + i] = acc.m; red[(jc + jj) * n + i] = acc.s; red[(2 * jc + jj) * n + i] = acc.g; }
+    __syncthreads();
+    if (tid < n) {
+        double m = 0.0, s = 0.0, g = 0.0;
+        for (int q = 0; q < jc; ++q) { m += red[q * n + tid]; s += red[(jc + q) * n + tid]; g += red[(2 * jc + q) * n + tid]; }
+        // rounding of both sums: at most (nx + k (nw + 1) + jc) additions deep, each
+        // within 2^-53 of the magnitudes g; doubled for the centre's error and the
+        // final addition
+        const double coef = (double)(nx + k * (nw + 1) + jc + 8) * 0x1p-52;
+        if (!isfinite(g)) { m = 0.0; s = INFINITY; }
+        else s = s + coef * g * (1.0 + 0x1p-50) + 0x1p-1000;
+        if (k == 0) { m = 0.0; s = 0.0; }
+        mo[tid] = m;
+        so[tid] = s;
+    }
+    __syncthreads();
+}
+
+static int tube_jc(int nx, int nu, int nw, size_t* smem) {
+    const int n = nx + nu;
+    const size_t per_j = sizeof(double) * ((size_t)n * nx + (size_t)nx * nw + 3 * nx + 3 * n);
+    int jc = SLS_THREADS / n;
+    while (jc > 1 && per_j * jc + 2 * n * sizeof(double) > SLS_ROW_LDS) --jc;
+    *smem = per_j * jc;            // tube_row's region; callers add 2 n for the row results
+    return jc;
+}
+
+__global__ void __launch_bounds__(SLS_THREADS) sls_tube_kernel(TubeRowArgs a) {
+    const int k = blockIdx.x, b = blockIdx.y;
+    extern __shared__ double sm[];
+    const int n = a.nx + a.nu;
+    double* mo = sm;
+    double* so = sm + n;
+    tube_row(a, b, k, sm + 2 * n, mo, so);
+    const size_t o = ((size_t)b * a.N + k) * n;
+    for (int q = threadIdx.x; q < n; q += blockDim.x) { a.mu[o + q] = mo[q]; a.sigma[o + q] = so[q]; }
+}
+
+// ------------------------------------------------------------ disturbance error
+
+// FP64 interval sine and cosine of [lo, hi]: library values widened by 2^-40
+// relative plus 2^-100 absolute, +-1 where a critical point may lie inside
+// (tested against an outward pi).
+__device__ void sls_sincos(double lo, double hi, double* sl, double* sh, double* cl, double* ch) {
+    const double PI_LO = 3.141592653589793115997963468544185161590576171875;
+    const double PI_HI = 3.141592653589793560087173318606801331043243408203125;
+    if (!(hi - lo < 2.0 * PI_LO) || fabs(lo) > 1024.0 || fabs(hi) > 1024.0) {
+        *sl = -1.0; *sh = 1.0; *cl = -1.0; *ch = 1.0;
+        return;
+    }
+    const double sa = sin(lo), sb = sin(hi), ca = cos(lo), cb = cos(hi);
+    auto wdn = [](double x) { return x - fabs(x) * 0x1p-40 - 0x1p-100; };
+    auto wup = [](double x) { return x + fabs(x) * 0x1p-40 + 0x1p-100; };
+    double s0 = wdn(fmin(sa, sb)), s1 = wup(fmax(sa, sb));
+    double c0 = wdn(fmin(ca, cb)), c1 = wup(fmax(ca, cb));
+    auto may = [&](double frac) {
+        const double x0 = frac * PI_LO;
+        const double m = ceil((lo - x0) / (2.0 * PI_HI) - 1e-12);
+        const double crit = x0 + m * 2.0 * (m >= 0 ? PI_LO : PI_HI);
+        return crit <= hi + 1e-12;
+    };
+    if (may(0.5)) s1 = 1.0;
+    if (may(-0.5)) s0 = -1.0;
+    if (may(0.0)) c1 = 1.0;
+    if (may(1.0)) c0 = -1.0;
+    *sl = fmax(s0, -1.0); *sh = fmin(s1, 1.0);
+    *cl = fmax(c0, -1.0); *ch = fmin(c1, 1.0);
+}
+
+__device__ __forceinline__ double rdn(double x) { return x - fabs(x) * 0x1p-52 - 0x1p-1000; }
+__device__ __forceinline__ double rup(double x) { return x + fabs(x) * 0x1p-52 + 0x1p-1000; }
+
+// half-width of the thrust columns' disturbance error on row l (0 off the (vx, vz) rows)
+__device__ double thrust_rdist(int l, double zt, double mut, double sgt, double e0, double c) {
+    const int comp = l % 6;
+    if (comp != 3 && comp != 4) return 0.0;
+    const double lo = rdn(zt + mut - sgt), hi = rup(zt + mut + sgt);
+    if (!(lo <= hi) || !isfinite(lo) || !isfinite(hi)) return INFINITY;
+    double sl, sh, cl, ch;
+    sls_sincos(lo, hi, &sl, &sh, &cl, &ch);
+    // vx: -c [sin], vz: c [cos]; products of the point c >= 0 rounded outward
+    const double a = comp == 3 ? rdn(-c * sh) : rdn(c * cl);
+    const double bq = comp == 3 ? rup(-c * sl) : rup(c * ch);
+    return rup(fmax(fabs(rup(bq - e0)), fabs(rdn(a - e0))));
+}
+
+struct EDiag { double e[SLS_MAX_NX]; };
+
+// E(z_k) = [diag(e) | thrust columns], [units][nx][nx + U]
+__global__ void sls_disturbance_kernel(const double* z, EDiag e, double c, int nx, int U, int64_t units,
+                                       double* E) {
+    const int nw = nx + U;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= units * nx * nw) return;
+    const int64_t u = q / ((int64_t)nx * nw);
+    const int r = (int)((q / nw) % nx), w = (int)(q % nw);
+    double val = 0.0;
+    if (w < nx) val = w == r ? e.e[r] : 0.0;
+    else {
+        const int i = w - nx;
+        const double th = z[u * nx + 6 * i + 2];
+        if (r == 6 * i + 3) val = -c * sin(th);
+        else if (r == 6 * i + 4) val = c * cos(th);
+    }
+    E[q] = val;
+}
+
+// ------------------------------------------------------------ fixed point
+
+struct FpRowArgs {
+    TubeRowArgs t;           // cbar, rbar: workspace (written here through cbar_w, rbar_w)
+    double* cbar_w; double* rbar_w;
+    const double* z; const double* v;
+    const double* rlo_s; const double* rhi_s;   // [b][nx] bound of step k-1 (staging)
+    double* zs; double* vs; double* mus; double* sgs;   // staging for the bound of step k
+    double* r_lo; double* r_hi;                  // [b][N][nx] outputs (may be NULL)
+    uint32_t* certified;                         // [b] (may be NULL)
+    double thrust_c;                             // thrust dt / m (0: constant E)
+    double pad;
+    int U;
+};
+
+// Row launch of step k (k = N: only finishes step N-1).  One workgroup per trajectory.
+__global__ void __launch_bounds__(SLS_THREADS) sls_fp_row_kernel(FpRowArgs a, int k) {
+    const int b = blockIdx.x;
+    const TubeRowArgs& t = a.t;
+    const int nx = t.nx, nu = t.nu, n = nx + nu, N = t.N, nw = t.nw;
+    extern __shared__ double sm[];
+    double* mo = sm;
+    double* so = sm + n;
+    const int tid = threadIdx.x;
+    if (k > 0) {
+        // residual zonotope of step k-1: bound + disturbance error, outward
+        const int kp = k - 1;
+        for (int l = tid; l < nx; l += blockDim.x) {
+            double lo = a.rlo_s[(size_t)b * nx + l], hi = a.rhi_s[(size_t)b * nx + l];
+            if (a.thrust_c > 0.0) {
+                const int node = l / 6, th = 6 * node + 2;
+                const size_t ob = ((size_t)b * N + kp);
+                const double e0 = t.E[(ob * nx + l) * nw + (nw - a.U + node)];
+                const double s = thrust_rdist(l, a.z[ob * nx + th], t.mu[ob * n + th], t.sigma[ob * n + th], e0,
+                                              a.thrust_c);
+                if (s != 0.0) {
+                    lo = rdn(lo - s);
+                    hi = rup(hi + s);
+                }
+            }
+            const size_t o = ((size_t)b * N + kp) * nx + l;
+            if (a.r_lo) { a.r_lo[o] = lo; a.r_hi[o] = hi; }
+            double cb = 0.5 * (lo + hi), rb = fmax(hi - cb, cb - lo);
+            rb = rup(rup(rb) + a.pad);
+            if (!isfinite(lo) || !isfinite(hi)) { cb = NAN; rb = INFINITY; }
+            a.cbar_w[o] = cb;
+            a.rbar_w[o] = rb;
+        }
+        __syncthreads();
+    }
+    if (k == N) {
+        if (a.certified && tid == 0) {
+            // every tube entry and residual finite: the causal pass reached C = F(C)
+            bool fin = true;
+            for (int q = 0; q < N * n && fin; ++q) fin = isfinite(t.sigma[(size_t)b * N * n + q]);
+            for (int q = 0; q < N * nx && fin; ++q) fin = isfinite(t.rbar[(size_t)b * N * nx + q]);
+            a.certified[b] = fin ? 1u : 0u;
+        }
+        return;
+    }
+    tube_row(t, b, k, sm + 2 * n, mo, so);
+    const size_t o = ((size_t)b * N + k) * n;
+    for (int q = tid; q < n; q += blockDim.x) {
+        t.mu[o + q] = mo[q];
+        t.sigma[o + q] = so[q];
+        a.mus[(size_t)b * n + q] = mo[q];
+        a.sgs[(size_t)b * n + q] = so[q];
+    }
+    const size_t ob = (size_t)b * N + k;
+    for (int q = tid; q < nx; q += blockDim.x) a.zs[(size_t)b * nx + q] = a.z[ob * nx + q];
+    for (int q = tid; q < nu; q += blockDim.x) a.vs[(size_t)b * nu + q] = a.v[ob * nu + q];
+}
+
+struct SlsWorkspace {
+    std::mutex mu;
+    double* buf = nullptr;
+    size_t cap = 0;
+    WsFence fence;
+};
+static SlsWorkspace g_sls;
+
+static bool dims_ok(int nx, int nu) { return nx >= 1 && nx <= SLS_MAX_NX && nu >= 0 && nu <= SLS_MAX_NU; }
+
+}  // namespace leb
+
+using namespace leb;
+
+extern "C" int leb_sls_responses(int32_t nx, int32_t nu, int32_t batch, int32_t N, const double* A, const double* B,
+                                 const double* qx, const double* qu, double* K, double* phi, void* stream) {
+    if (!dims_ok(nx, nu) || nu < 1 || batch < 0 || N < 0) return LEB_EINVAL;
+    if (batch > 65535 || N > 65535) return LEB_ENOTSUP;
+    if ((int64_t)batch * N * N == 0) return LEB_OK;
+    if (!A || !B || !qx || !qu || !K || !phi) return LEB_EINVAL;
+    const void* ptrs[] = {A, B, qx, qu, K, phi};
+    for (const void* p : ptrs)
+        if (!aligned8(p)) return LEB_EINVAL;
+    RiccatiArgs a;
+    a.A = A; a.B = B; a.qx = qx; a.qu = qu; a.K = K; a.phi = phi;
+    a.nx = nx; a.nu = nu; a.N = N;
+    const int threads = min(SLS_THREADS, 64 * ((nx * nx + 63) / 64));
+    hipLaunchKernelGGL(sls_riccati_kernel, dim3((unsigned)N, (unsigned)batch), dim3(threads), riccati_smem(nx, nu),
+                       (hipStream_t)stream, a);
+    return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
+}
+
+extern "C" int leb_sls_tube_map(int32_t nx, int32_t nu, int32_t nw, int32_t batch, int32_t N, const double* phi,
+                                const double* E, const double* c_bar, const double* rho_bar, double* mu,
+                                double* sigma, void* stream) {
+    if (!dims_ok(nx, nu) || nw < 0 || nw > SLS_MAX_NW || batch < 0 || N < 0) return LEB_EINVAL;
+    if (batch > 65535 || N > 65535) return LEB_ENOTSUP;
+    if ((int64_t)batch * N == 0) return LEB_OK;
+    if (!phi || (nw > 0 && !E) || !c_bar || !rho_bar || !mu || !sigma) return LEB_EINVAL;
+    const void* ptrs[] = {phi, E, c_bar, rho_bar, mu, sigma};
+    for (const void* p : ptrs)
+        if (p && !aligned8(p)) return LEB_EINVAL;
+    TubeRowArgs a;
+    a.phi = phi; a.E = E; a.cbar = c_bar; a.rbar = rho_bar; a.mu = mu; a.sigma = sigma;
+    a.nx = nx; a.nu = nu; a.nw = nw; a.N = N;
+    size_t smem;
+    a.jc = tube_jc(nx, nu, nw, &smem);
+    hipLaunchKernelGGL(sls_tube_kernel, dim3((unsigned)N, (unsigned)batch), dim3(SLS_THREADS),
+                       smem + 2 * (nx + nu) * sizeof(double), (hipStream_t)stream, a);
+    return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
+}
+
+extern "C" int leb_linearize(const leb_dynamics* dyn, int32_t batch, int32_t N, const double* z, const double* v,
+                             const double* e, double thrust, double* A, double* B, double* E, void* stream) {
+    int rc = check_dynamics(dyn);
+    if (rc != LEB_OK) return rc;
+    if (dyn->kind != LEB_DYN_PQUAD_CHAIN) return LEB_ENOTSUP;
+    if (batch < 0 || N < 0 || !(thrust >= 0.0) || !isfinite(thrust)) return LEB_EINVAL;
+    const int64_t units = (int64_t)batch * N;
+    if (units == 0) return LEB_OK;
+    if (!z || !v || !A || !B || (E && !e)) return LEB_EINVAL;
+    const void* ptrs[] = {z, v, A, B, E};
+    for (const void* p : ptrs)
+        if (p && !aligned8(p)) return LEB_EINVAL;
+    const int nx = dyn->nx, U = dyn->n_units;
+    if (units * nx * (nx + dyn->nu + nx + U) > ((int64_t)1 << 46)) return LEB_EINVAL;
+    EDiag ed;
+    if (E) {
+        if (nx > SLS_MAX_NX) return LEB_ENOTSUP;
+        for (int i = 0; i < nx; ++i) {
+            if (!(e[i] >= 0.0) || !isfinite(e[i])) return LEB_EINVAL;
+            ed.e[i] = e[i];
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = launch_chain_jacobians(dyn, units, z, v, A, B, s))) return rc;
+    if (!E) return LEB_OK;
+    const int64_t cnt = units * nx * (nx + U);
+    hipLaunchKernelGGL(sls_disturbance_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, z, ed,
+                       thrust * dyn->dt / dyn->m, nx, U, units, E);
+    return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
+}
+
+extern "C" int leb_sls_fixed_point(const leb_dynamics* dyn, int32_t batch, int32_t N, const double* z,
+                                   const double* v, const double* phi, int32_t nw, const double* E, double thrust,
+                                   double pad, double* mu, double* sigma, double* r_lo, double* r_hi,
+                                   uint32_t* certified, void* stream) {
+    int rc = check_dynamics(dyn);
+    if (rc != LEB_OK) return rc;
+    const int nx = dyn->nx, nu = dyn->nu, n = nx + nu;
+    if (!dims_ok(nx, nu) || nw < 0 || nw > SLS_MAX_NW || batch < 0 || N < 0) return LEB_EINVAL;
+    if (!(pad >= 0.0) || !isfinite(pad) || !(thrust >= 0.0) || !isfinite(thrust)) return LEB_EINVAL;
+    const bool chain = dyn->kind == LEB_DYN_PQUAD_CHAIN;
+    if (dyn->kind == LEB_DYN_LINEAR || dyn->kind == LEB_DYN_QUADRATIC || dyn->kind == LEB_DYN_SINCOS)
+        return LEB_ENOTSUP;
+    if (thrust > 0.0 && (!chain || nw < dyn->n_units)) return LEB_EINVAL;
+    if (batch > 65535) return LEB_ENOTSUP;
+    if ((int64_t)batch * N == 0) return LEB_OK;
+    if (!z || (nu > 0 && !v) || !phi || (nw > 0 && !E) || !mu || !sigma || (!r_lo != !r_hi)) return LEB_EINVAL;
+    const void* ptrs[] = {z, v, phi, E, mu, sigma, r_lo, r_hi};
+    for (const void* p : ptrs)
+        if (p && !aligned8(p)) return LEB_EINVAL;
+    if (certified && (reinterpret_cast<uintptr_t>(certified) & 3u)) return LEB_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lock(g_sls.mu);
+    // cbar, rbar [b][N][nx]; staging zs [b][nx], vs [b][nu], mus, sgs [b][n], rlo_s, rhi_s [b][nx]
+    const size_t need = (size_t)batch * (2 * (size_t)N * nx + nx + nu + 2 * n + 2 * nx) + 1;
+    if (need > g_sls.cap) {
+        if (g_sls.buf) (void)hipFree(g_sls.buf);
+        g_sls.buf = nullptr;
+        g_sls.cap = 0;
+        if (hipMalloc(&g_sls.buf, need * sizeof(double)) != hipSuccess) return LEB_ENOMEM;
+        g_sls.cap = need;
+    }
+    if ((rc = g_sls.fence.enter(s))) return rc;
+    WsFenceScope leave{g_sls.fence, s};
+    double* p = g_sls.buf;
+    auto take = [&](size_t cnt) { double* q = p; p += cnt; return q; };
+    FpRowArgs a;
+    a.t.phi = phi; a.t.E = E; a.t.mu = mu; a.t.sigma = sigma;
+    a.cbar_w = take((size_t)batch * N * nx);
+    a.rbar_w = take((size_t)batch * N * nx);
+    a.t.cbar = a.cbar_w;
+    a.t.rbar = a.rbar_w;
+    a.t.nx = nx; a.t.nu = nu; a.t.nw = nw; a.t.N = N;
+    size_t smem;
+    a.t.jc = tube_jc(nx, nu, nw, &smem);
+    smem += 2 * n * sizeof(double);
+    a.zs = take((size_t)batch * nx);
+    a.vs = take((size_t)batch * nu);
+    a.mus = take((size_t)batch * n);
+    a.sgs = take((size_t)batch * n);
+    double* rlo_s = take((size_t)batch * nx);
+    double* rhi_s = take((size_t)batch * nx);
+    a.rlo_s = rlo_s; a.rhi_s = rhi_s;
+    a.z = z; a.v = v; a.r_lo = r_lo; a.r_hi = r_hi; a.certified = certified;
+    a.thrust_c = thrust > 0.0 ? thrust * dyn->dt / dyn->m : 0.0;
+    a.pad = pad;
+    a.U = chain ? dyn->n_units : 0;
+    for (int k = 0; k <= N; ++k) {
+        hipLaunchKernelGGL(sls_fp_row_kernel, dim3((unsigned)batch), dim3(SLS_THREADS), smem, s, a, k);
+        if (k == N) break;
+        rc = chain ? launch_pbh_chain(dyn, batch, a.zs, a.vs, a.mus, a.sgs, rlo_s, rhi_s, nullptr, nullptr, 0.0,
+                                      nullptr, s)
+                   : launch_small_dyn(dyn, LEB_IH_PATH, batch, a.zs, a.vs, a.mus, a.sgs, rlo_s, rhi_s, nullptr,
+                                      nullptr, 0.0, nullptr, s);
+        if (rc) return rc;
+    }
+    return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
+}

@@ -234,3 +234,47 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_sls_entry_points_reject_bad_arguments_without_launching(L):
+    import paper_2607_01203_amd as leb
+    vp = ctypes.c_void_p(8)
+    mis = ctypes.c_void_p(12)
+    # leb_sls_responses(nx, nu, batch, N, A, B, qx, qu, K, phi, stream)
+    assert L.leb_sls_responses(0, 2, 1, 4, vp, vp, vp, vp, vp, vp, None) == -1
+    assert L.leb_sls_responses(33, 2, 1, 4, vp, vp, vp, vp, vp, vp, None) == -1     # nx > 32
+    assert L.leb_sls_responses(6, 0, 1, 4, vp, vp, vp, vp, vp, vp, None) == -1      # no input
+    assert L.leb_sls_responses(6, 17, 1, 4, vp, vp, vp, vp, vp, vp, None) == -1     # nu > 16
+    assert L.leb_sls_responses(6, 2, 1, 4, vp, vp, None, vp, vp, vp, None) == -1    # no weights
+    assert L.leb_sls_responses(6, 2, 1, 4, vp, vp, vp, vp, vp, mis, None) == -1     # misaligned phi
+    assert L.leb_sls_responses(6, 2, 70000, 4, vp, vp, vp, vp, vp, vp, None) == -4
+    assert L.leb_sls_responses(6, 2, 0, 4, None, None, None, None, None, None, None) == 0
+    # leb_sls_tube_map(nx, nu, nw, batch, N, phi, E, c_bar, rho_bar, mu, sigma, stream)
+    assert L.leb_sls_tube_map(6, 2, 65, 1, 4, vp, vp, vp, vp, vp, vp, None) == -1   # nw > 64
+    assert L.leb_sls_tube_map(6, 2, 7, 1, 4, vp, None, vp, vp, vp, vp, None) == -1  # no E
+    assert L.leb_sls_tube_map(6, 2, 0, 1, 4, vp, None, vp, None, vp, vp, None) == -1  # no rho_bar
+    assert L.leb_sls_tube_map(6, 2, 7, 1, 4, vp, vp, vp, vp, mis, vp, None) == -1
+    assert L.leb_sls_tube_map(6, 2, 7, 3, 0, None, None, None, None, None, None, None) == 0
+    # leb_sls_fixed_point(dyn, batch, N, z, v, phi, nw, E, thrust, pad, mu, sigma, r_lo, r_hi, cert, stream)
+    d = leb.chain_dynamics(1)
+    fp = L.leb_sls_fixed_point
+    assert fp(ctypes.byref(d), 1, 4, vp, vp, vp, 7, vp, 0.1, -1.0, vp, vp, None, None, None, None) == -1  # pad
+    assert fp(ctypes.byref(d), 1, 4, vp, vp, vp, 7, vp, -0.1, 0.0, vp, vp, None, None, None, None) == -1  # thrust
+    assert fp(ctypes.byref(d), 1, 4, vp, vp, vp, 0, None, 0.1, 0.0, vp, vp, None, None, None, None) == -1  # nw < U
+    assert fp(ctypes.byref(d), 1, 4, vp, vp, vp, 7, vp, 0.0, 0.0, vp, vp, vp, None, None, None) == -1  # r_lo only
+    assert fp(ctypes.byref(d), 1, 4, vp, vp, vp, 7, vp, 0.0, 0.0, vp, vp, None, None, ctypes.c_void_p(6),
+              None) == -1                                                                          # misaligned flags
+    sat = leb.satellite_dynamics(0.1)
+    assert fp(ctypes.byref(sat), 1, 4, vp, vp, vp, 7, vp, 0.1, 0.0, vp, vp, None, None, None, None) == -1
+    assert fp(ctypes.byref(leb.linear_dynamics(3, 1)), 1, 4, vp, vp, vp, 3, vp, 0.0, 0.0, vp, vp, None, None,
+              None, None) == -4
+    big = leb.chain_dynamics(6)                       # nx = 36 > 32
+    assert fp(ctypes.byref(big), 1, 4, vp, vp, vp, 36, vp, 0.0, 0.0, vp, vp, None, None, None, None) == -1
+    assert fp(ctypes.byref(d), 0, 4, None, None, None, 7, None, 0.0, 0.0, None, None, None, None, None, None) == 0
+    # leb_linearize(dyn, batch, N, z, v, e, thrust, A, B, E, stream)
+    e = (ctypes.c_double * 6)(0.0, 0.0, 0.0, -1.0, 0.0, 0.0)
+    assert L.leb_linearize(ctypes.byref(d), 1, 4, vp, vp, ctypes.cast(e, ctypes.c_void_p), 0.1, vp, vp, vp,
+                           None) == -1                                                            # e < 0
+    assert L.leb_linearize(ctypes.byref(d), 1, 4, vp, vp, None, 0.1, vp, vp, vp, None) == -1        # E without e
+    assert L.leb_linearize(ctypes.byref(d), 1, 4, vp, vp, None, -1.0, vp, vp, None, None) == -1
+    assert L.leb_linearize(ctypes.byref(sat), 1, 4, vp, vp, None, 0.0, vp, vp, None, None) == -4
