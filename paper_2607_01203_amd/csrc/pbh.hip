@@ -65,52 +65,6 @@ struct ChainArgs {
 };
 
 
-// Spring i and node i of timestep lt; s_sp [T][U], s_flag [T] (cleared).
-// Contains one workgroup barrier.
-__device__ __forceinline__ void node_pass(const ChainArgs& A, const TileRef& t, const NodeIn& d, int lt, int i,
-                                          SpringOut* s_sp, uint32_t* s_flag) {
-    const int U = A.U, nx = 6 * U;
-    const bool active = lt < t.nloc;
-    const bool right = active && i < U - 1;      // spring i exists
-    if (active) {
-        const uint32_t f = node_flags(d);
-        if (f) atomicOr(&s_flag[lt], f);
-    }
-    const NodeConsts K = node_consts(A.c, A.kL, A.L0);
-    SpringKeep k;
-    spring_step(K, d, right, k, &s_sp[lt * U + i]);
-    if (k.unb) atomicOr(&s_flag[lt], LEB_FLAG_UNBOUNDED);
-    __syncthreads();      // spring terms and flags complete
-    if (!active) return;
-    const uint32_t ft = s_flag[lt];
-    double lo34[2], hi34[2];
-    bool all_inf;
-    node_step(K, U, d, k, i > 0 ? &s_sp[lt * U + i - 1] : nullptr, ft, lo34, hi34, &all_inf);
-    double lo[6], hi[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        lo[c] = all_inf ? -INFINITY : 0.0;
-        hi[c] = all_inf ? INFINITY : 0.0;
-    }
-    lo[3] = lo34[0]; hi[3] = hi34[0]; lo[4] = lo34[1]; hi[4] = hi34[1];
-    const int64_t o = (int64_t)lt * nx + 6 * i;
-    if (t.RLO) {
-#pragma unroll
-        for (int c = 0; c < 6; ++c) { t.RLO[o + c] = lo[c]; t.RHI[o + c] = hi[c]; }
-    }
-    if (t.CB && A.compact) {
-        // the four affine rows are exactly (0, pad) unless the unit is bad, and then
-        // rows 3 and 4 are not finite either
-        const int64_t o2 = 2 * ((int64_t)lt * U + i);
-        row_zono(lo[3], hi[3], A.pad, &t.CB[o2], &t.RB[o2]);
-        row_zono(lo[4], hi[4], A.pad, &t.CB[o2 + 1], &t.RB[o2 + 1]);
-    } else if (t.CB) {
-#pragma unroll
-        for (int c = 0; c < 6; ++c) row_zono(lo[c], hi[c], A.pad, &t.CB[o + c], &t.RB[o + c]);
-    }
-    if (t.FL && i == 0) t.FL[lt] = (ft & LEB_FLAG_BAD_INPUT) ? (ft & ~LEB_FLAG_UNBOUNDED) : ft;
-}
-
 __global__ void __launch_bounds__(PBH_BLOCK) pbh_chain_fwd(ChainArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int U = A.U, T = A.T;

@@ -43,6 +43,7 @@
 
 #include "leb.h"
 #include "leb_internal.hpp"
+#include "pbh_node.hpp"
 
 namespace leb {
 
@@ -50,7 +51,9 @@ constexpr int SLS_MAX_NX = 32;
 constexpr int SLS_MAX_NU = 16;
 constexpr int SLS_MAX_NW = 64;
 constexpr int SLS_THREADS = 256;
+constexpr int SLS_PF = 8;                      // prefetch registers per thread (nx^2 + 2 nx nu <= 8 threads)
 constexpr size_t SLS_ROW_LDS = 48 * 1024;      // LDS budget of a tube-row workgroup
+constexpr size_t SLS_LDS_MAX = 64 * 1024;      // LDS of the one-launch fixed point (resident data + row region)
 
 // ------------------------------------------------------------ responses
 
@@ -60,6 +63,7 @@ struct RiccatiArgs {
     int nx, nu, N;
 };
 
+template <int NUB, int PF>
 __global__ void __launch_bounds__(SLS_THREADS) sls_riccati_kernel(RiccatiArgs a) {
     const int j = blockIdx.x, b = blockIdx.y;
     const int nx = a.nx, nu = a.nu, N = a.N, n = nx + nu;
@@ -74,6 +78,8 @@ __global__ void __launch_bounds__(SLS_THREADS) sls_riccati_kernel(RiccatiArgs a)
     double* Bc = PB + nx * nu;                   // nu*nx
     double* Kk = Bc + nu * nx;                   // nu*nx
     double* L = Kk + nu * nx;                    // nu*nu   S, then its Cholesky factor
+    double* sqx = L + nu * nu;                   // nx      diag(Q^x_{k,j})
+    double* squ = sqx + nx;                      // nu      diag(Q^u_{k,j})
     __shared__ int bad;
     const int tid = threadIdx.x, nt = blockDim.x;
     const double* Ab = a.A + (size_t)b * N * nx * nx;
@@ -87,10 +93,40 @@ __global__ void __launch_bounds__(SLS_THREADS) sls_riccati_kernel(RiccatiArgs a)
         const int r = q / nx, c = q - r * nx;
         P[q] = r == c ? qxb[((size_t)N * N + j) * nx + r] : 0.0;
     }
+    // the next step's (A_k, B_k, weights) -- or (A_k, B_k, K_k) in the forward
+    // pass -- are loaded into registers while the current step computes, and
+    // stored to LDS after its last barrier
+    double pf[PF];
+    const int nab = nx * n;
+    auto fetch = [&](int k, bool fwd) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int q = tid + u * nt;
+            double x = 0.0;
+            if (q < nx * nx) x = Ab[(size_t)k * nx * nx + q];
+            else if (q < nab) x = Bb[(size_t)k * nx * nu + (q - nx * nx)];
+            else if (fwd) { if (q < nab + nu * nx) x = Kb[((size_t)k * N + j) * nu * nx + (q - nab)]; }
+            else if (q < nab + nx) x = qxb[((size_t)k * N + j) * nx + (q - nab)];
+            else if (q < nab + n) x = qub[((size_t)k * N + j) * nu + (q - nab - nx)];
+            pf[u] = x;
+        }
+    };
+    auto stash = [&](bool fwd) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int q = tid + u * nt;
+            if (q < nx * nx) Ak[q] = pf[u];
+            else if (q < nab) Bk[q - nx * nx] = pf[u];
+            else if (fwd) { if (q < nab + nu * nx) Kk[q - nab] = pf[u]; }
+            else if (q < nab + nx) sqx[q - nab] = pf[u];
+            else if (q < nab + n) squ[q - nab - nx] = pf[u];
+        }
+    };
+    fetch(N - 1, false);
+    stash(false);
     for (int k = N - 1; k > j; --k) {
-        for (int q = tid; q < nx * nx; q += nt) Ak[q] = Ab[(size_t)k * nx * nx + q];
-        for (int q = tid; q < nx * nu; q += nt) Bk[q] = Bb[(size_t)k * nx * nu + q];
-        __syncthreads();
+        lds_barrier();
+        if (k - 1 > j) fetch(k - 1, false);
         // P A_k and P B_k
         for (int q = tid; q < nx * n; q += nt) {
             double s = 0.0;
@@ -104,14 +140,14 @@ __global__ void __launch_bounds__(SLS_THREADS) sls_riccati_kernel(RiccatiArgs a)
                 PB[q2] = s;
             }
         }
-        __syncthreads();
+        lds_barrier();
         // S = diag(qu) + B^T (P B),  Bc = B^T (P A)
         for (int q = tid; q < nu * n; q += nt) {
             if (q < nu * nu) {
                 const int r = q / nu, c = q - r * nu;
                 double s = 0.0;
                 for (int l = 0; l < nx; ++l) s = fma(Bk[l * nu + r], PB[l * nu + c], s);
-                L[q] = (r == c ? qub[((size_t)k * N + j) * nu + r] : 0.0) + s;
+                L[q] = (r == c ? squ[r] : 0.0) + s;
             } else {
                 const int q2 = q - nu * nu, r = q2 / nx, c = q2 - r * nx;
                 double s = 0.0;
@@ -119,7 +155,7 @@ __global__ void __launch_bounds__(SLS_THREADS) sls_riccati_kernel(RiccatiArgs a)
                 Bc[q2] = s;
             }
         }
-        __syncthreads();
+        lds_barrier();
         // Cholesky S = L L^T (lower triangle in place; diagonal holds 1/L_ii)
         if (tid == 0) {
             for (int c = 0; c < nu; ++c) {
@@ -135,22 +171,34 @@ __global__ void __launch_bounds__(SLS_THREADS) sls_riccati_kernel(RiccatiArgs a)
                 }
             }
         }
-        __syncthreads();
-        // K = -S^-1 Bc, one column per thread: L y = Bc[:, c], then L^T x = y
+        lds_barrier();
+        // K = -S^-1 Bc, one column per thread: L y = Bc[:, c], then L^T x = y, in registers
         for (int c = tid; c < nx; c += nt) {
-            for (int r = 0; r < nu; ++r) {
-                double s = Bc[r * nx + c];
-                for (int m = 0; m < r; ++m) s -= L[r * nu + m] * Kk[m * nx + c];
-                Kk[r * nx + c] = s * L[r * nu + r];
+            double y[NUB];
+#pragma unroll
+            for (int r = 0; r < NUB; ++r) {
+                if (r < nu) {
+                    double s = Bc[r * nx + c];
+#pragma unroll
+                    for (int m = 0; m < r; ++m) s -= L[r * nu + m] * y[m];
+                    y[r] = s * L[r * nu + r];
+                }
             }
-            for (int r = nu - 1; r >= 0; --r) {
-                double s = Kk[r * nx + c];
-                for (int m = r + 1; m < nu; ++m) s -= L[m * nu + r] * Kk[m * nx + c];
-                Kk[r * nx + c] = s * L[r * nu + r];
+#pragma unroll
+            for (int r = NUB - 1; r >= 0; --r) {
+                if (r < nu) {
+                    double s = y[r];
+#pragma unroll
+                    for (int m = r + 1; m < NUB; ++m)
+                        if (m < nu) s -= L[m * nu + r] * y[m];
+                    y[r] = s * L[r * nu + r];
+                }
             }
-            for (int r = 0; r < nu; ++r) Kk[r * nx + c] = bad ? NAN : -Kk[r * nx + c];
+#pragma unroll
+            for (int r = 0; r < NUB; ++r)
+                if (r < nu) Kk[r * nx + c] = bad ? NAN : -y[r];
         }
-        __syncthreads();
+        lds_barrier();
         // P <- diag(qx) + A^T (P A) + K^T Bc; the gain goes out
         for (int q = tid; q < nx * nx; q += nt) {
             const int r = q / nx, c = q - r * nx;
@@ -158,20 +206,23 @@ __global__ void __launch_bounds__(SLS_THREADS) sls_riccati_kernel(RiccatiArgs a)
             for (int l = 0; l < nx; ++l) s = fma(Ak[l * nx + r], PA[l * nx + c], s);
             double t = 0.0;
             for (int m = 0; m < nu; ++m) t = fma(Kk[m * nx + r], Bc[m * nx + c], t);
-            P[q] = (r == c ? qxb[((size_t)k * N + j) * nx + r] : 0.0) + s + t;
+            P[q] = (r == c ? sqx[r] : 0.0) + s + t;
         }
         for (int q = tid; q < nu * nx; q += nt) Kb[((size_t)k * N + j) * nu * nx + q] = Kk[q];
-        __syncthreads();
+        lds_barrier();
+        if (k - 1 > j) stash(false);
     }
-    // forward propagation from Phi^x_{j+1,j} = I
+    // forward propagation from Phi^x_{j+1,j} = I; the gains were stored by this
+    // workgroup above, and this full barrier orders those stores before the loads
+    __syncthreads();
     double* X = P;
     double* Xn = PA;
     for (int q = tid; q < nx * nx; q += nt) X[q] = (q / nx == q % nx) ? 1.0 : 0.0;
+    fetch(j + 1, true);
+    stash(true);
     for (int k = j + 1; k < N; ++k) {
-        for (int q = tid; q < nx * nx; q += nt) Ak[q] = Ab[(size_t)k * nx * nx + q];
-        for (int q = tid; q < nx * nu; q += nt) Bk[q] = Bb[(size_t)k * nx * nu + q];
-        for (int q = tid; q < nu * nx; q += nt) Kk[q] = Kb[((size_t)k * N + j) * nu * nx + q];
-        __syncthreads();
+        lds_barrier();
+        if (k + 1 < N) fetch(k + 1, true);
         double* out = phib + ((size_t)k * N + j) * n * nx;
         for (int q = tid; q < n * nx; q += nt) {
             const int r = q / nx, c = q - r * nx;
@@ -190,7 +241,7 @@ __global__ void __launch_bounds__(SLS_THREADS) sls_riccati_kernel(RiccatiArgs a)
             for (int m = 0; m < nu; ++m) s = fma(Bk[r * nu + m], Kk[m * nx + c], s);
             Acl[q] = Ak[q] + s;
         }
-        __syncthreads();
+        lds_barrier();
         if (k + 1 < N) {
             for (int q = tid; q < nx * nx; q += nt) {
                 const int r = q / nx, c = q - r * nx;
@@ -198,14 +249,15 @@ __global__ void __launch_bounds__(SLS_THREADS) sls_riccati_kernel(RiccatiArgs a)
                 for (int l = 0; l < nx; ++l) s = fma(Acl[r * nx + l], X[l * nx + c], s);
                 Xn[q] = s;
             }
-            __syncthreads();
+            lds_barrier();
             double* t = X; X = Xn; Xn = t;
+            stash(true);
         }
     }
 }
 
 static size_t riccati_smem(int nx, int nu) {
-    return sizeof(double) * (size_t)(4 * nx * nx + 4 * nx * nu + nu * nu);
+    return sizeof(double) * (size_t)(4 * nx * nx + 4 * nx * nu + nu * nu + nx + nu);
 }
 
 // ------------------------------------------------------------ tube rows
@@ -217,100 +269,183 @@ struct TubeRowArgs {
     const double* rbar;      // [b][N][nx]
     double* mu;              // [b][N][n]
     double* sigma;           // [b][N][n]
+    const double* sigE;      // [b][N][n] the disturbance part of sigma (ROW_NOE reads it)
     int nx, nu, nw, N, jc;
 };
 
-struct RowAcc { double m, s, g; };
+// What a tube row sums: both parts of eq. tight_tube_width (ROW_FULL), only
+// the disturbance part sum_j |Phi_{k,j} E_j| 1, which does not depend on the
+// bounds (ROW_E), or the centre and the residual part, adding the disturbance
+// part from sigE (ROW_NOE).
+constexpr int ROW_FULL = 0, ROW_E = 1, ROW_NOE = 2;
 
-// Tube row k of trajectory b; jc disturbance times per LDS chunk, thread
-// t = jj * n + i works on (j0 + jj, row i).  Leaves mu_k, sigma_k in mo[], so[]
-// (LDS, n entries) after the final barrier.
-__device__ void tube_row(const TubeRowArgs& a, int b, int k, double* sm, double* mo, double* so) {
-    const int nx = a.nx, nw = a.nw, N = a.N, n = nx + a.nu, jc = a.jc;
+// Tube row k of trajectory b.  Thread t = jj * n + i works on row i of
+// Phi_{k, j0 + jj}, which it loads straight into registers (every entry of
+// Phi is used by one thread only); E_j, |E_j| 1, c_bar_j and rho_bar_j are
+// shared through LDS, jc disturbance times per chunk.  NXB >= nx is the
+// register length of a row.  Leaves the row's (mu, sigma) in mo[], so[] (LDS,
+// n entries) after the final barrier.
+// One trajectory's operands of tube row k (generic pointers: global or LDS).
+struct RowRef {
+    const double* phi;       // Phi_{k,0} (the row block of k)
+    const double* E;         // E_0 (ROW_FULL, ROW_E)
+    const double* cb;        // c_bar_0 (ROW_FULL, ROW_NOE)
+    const double* rb;        // rho_bar_0
+    const double* sigE;      // the disturbance part of row k, n values (ROW_NOE)
+};
+
+__device__ __forceinline__ RowRef row_ref(const TubeRowArgs& a, int b, int k) {
+    const int nx = a.nx, n = nx + a.nu, N = a.N;
+    RowRef r;
+    r.phi = a.phi + (((size_t)b * N + k) * N) * n * nx;
+    r.E = a.E ? a.E + (size_t)b * N * nx * a.nw : nullptr;
+    r.cb = a.cbar ? a.cbar + (size_t)b * N * nx : nullptr;
+    r.rb = a.rbar ? a.rbar + (size_t)b * N * nx : nullptr;
+    r.sigE = a.sigE ? a.sigE + ((size_t)b * N + k) * n : nullptr;
+    return r;
+}
+
+template <int MODE, int NXB>
+__device__ void tube_row(const TubeRowArgs& a, const RowRef& rr, int k, double* sm, double* mo, double* so) {
+    const int nx = a.nx, nw = a.nw, n = nx + a.nu, jc = a.jc;
     const int tid = threadIdx.x, nt = blockDim.x;
-    double* sphi = sm;                           // jc*n*nx
-    double* sE = sphi + (size_t)jc * n * nx;     // jc*nx*nw
-    double* scb = sE + (size_t)jc * nx * nw;     // jc*nx
-    double* srb = scb + jc * nx;                 // jc*nx  (rho_bar)
-    double* se1 = srb + jc * nx;                 // jc*nx  (row sums |E| 1)
-    double* red = se1 + jc * nx;                 // 3*jc*n partial sums
+    const bool useE = MODE != ROW_NOE, useR = MODE != ROW_E;
+    double* sE = sm;                                          // jc*nx*nw   (useE)
+    double* se1 = sE + (useE ? (size_t)jc * nx * nw : 0);     // jc*nx      (useE)
+    double* scb = se1 + (useE ? jc * nx : 0);                 // jc*nx      (useR)
+    double* srb = scb + (useR ? jc * nx : 0);                 // jc*nx      (useR)
+    double* red = srb + (useR ? jc * nx : 0);                 // 3*jc*n
     const int jj = tid / n, i = tid - jj * n;
     const bool act = jj < jc;
-    RowAcc acc = {0.0, 0.0, 0.0};
-    const double* prow = a.phi + (((size_t)b * N + k) * N) * n * nx;
+    double am = 0.0, as = 0.0, ag = 0.0;
+    const double* prow = rr.phi;
     for (int j0 = 0; j0 < k; j0 += jc) {
         const int cnt = min(jc, k - j0);
-        const double* pp = prow + (size_t)j0 * n * nx;
-        for (int q = tid; q < cnt * n * nx; q += nt) sphi[q] = pp[q];
-        const double* ep = a.E + ((size_t)b * N + j0) * nx * nw;
-        for (int q = tid; q < cnt * nx * nw; q += nt) sE[q] = ep[q];
-        const size_t ro = ((size_t)b * N + j0) * nx;
-        for (int q = tid; q < cnt * nx; q += nt) { scb[q] = a.cbar[ro + q]; srb[q] = a.rbar[ro + q]; }
-        __syncthreads();
-        for (int q = tid; q < cnt * nx; q += nt) {
-            double s = 0.0;
-            for (int m = 0; m < nw; ++m) s += fabs(sE[q * nw + m]);
-            se1[q] = s;
+        const bool mine = act && jj < cnt;
+        double r[NXB];
+        if (mine) {
+            const double* src = prow + ((size_t)(j0 + jj) * n + i) * nx;
+#pragma unroll
+            for (int l = 0; l < NXB; ++l) r[l] = l < nx ? src[l] : 0.0;
         }
-        __syncthreads();
-        if (act && jj < cnt) {
-            const double* row = sphi + ((size_t)jj * n + i) * nx;
-            const double* cb = scb + jj * nx;
-            const double* rb = srb + jj * nx;
-            const double* e1 = se1 + jj * nx;
-            const double* Ej = sE + (size_t)jj * nx * nw;
-            double m = 0.0, s = 0.0, g = 0.0;
-            for (int l = 0; l < nx; ++l) {
-                const double p = row[l], ap = fabs(p);
-                m = fma(p, cb[l], m);
-                s = fma(ap, rb[l], s);
-                g = fma(ap, fabs(cb[l]) + rb[l] + e1[l], g);
-            }
-            for (int w = 0; w < nw; ++w) {
+        if (useE) {
+            const double* ep = rr.E + (size_t)j0 * nx * nw;
+            for (int q = tid; q < cnt * nx * nw; q += nt) sE[q] = ep[q];
+        }
+        if (useR) {
+            const size_t ro = (size_t)j0 * nx;
+            for (int q = tid; q < cnt * nx; q += nt) { scb[q] = rr.cb[ro + q]; srb[q] = rr.rb[ro + q]; }
+        }
+        lds_barrier();
+        if (useE) {
+            for (int q = tid; q < cnt * nx; q += nt) {
                 double t = 0.0;
-                for (int l = 0; l < nx; ++l) t = fma(row[l], Ej[l * nw + w], t);
-                s += fabs(t);
+                for (int w = 0; w < nw; ++w) t += fabs(sE[q * nw + w]);
+                se1[q] = t;
             }
-            acc.m += m; acc.s += s; acc.g += g;
+            lds_barrier();
         }
-        __syncthreads();
+        if (mine) {
+            double m = 0.0, s = 0.0, g = 0.0;
+            if (useR) {
+                const double* cb = scb + jj * nx;
+                const double* rb = srb + jj * nx;
+#pragma unroll
+                for (int l = 0; l < NXB; ++l) {
+                    if (l < nx) {
+                        const double ap = fabs(r[l]);
+                        m = fma(r[l], cb[l], m);
+                        s = fma(ap, rb[l], s);
+                        g = fma(ap, fabs(cb[l]) + rb[l], g);
+                    }
+                }
+            }
+            if (useE) {
+                const double* e1 = se1 + jj * nx;
+                const double* Ej = sE + (size_t)jj * nx * nw;
+#pragma unroll
+                for (int l = 0; l < NXB; ++l)
+                    if (l < nx) g = fma(fabs(r[l]), e1[l], g);
+                for (int w = 0; w < nw; ++w) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int l = 0; l < NXB; ++l)
+                        if (l < nx) t = fma(r[l], Ej[l * nw + w], t);
+                    s += fabs(t);
+                }
+            }
+            am += m; as += s; ag += g;
+        }
+        lds_barrier();
     }
-    if (act) { red[jj * n + i] = acc.m; red[(jc + jj) * n + i] = acc.s; red[(2 * jc + jj) * n + i] = acc.g; }
-    __syncthreads();
+    if (act) { red[jj * n + i] = am; red[(jc + jj) * n + i] = as; red[(2 * jc + jj) * n + i] = ag; }
+    lds_barrier();
     if (tid < n) {
         double m = 0.0, s = 0.0, g = 0.0;
         for (int q = 0; q < jc; ++q) { m += red[q * n + tid]; s += red[(jc + q) * n + tid]; g += red[(2 * jc + q) * n + tid]; }
-        // rounding of both sums: at most (nx + k (nw + 1) + jc) additions deep, each
+        // rounding of the sums: at most nx + k (nw + 1) + jc additions deep, each
         // within 2^-53 of the magnitudes g; doubled for the centre's error and the
-        // final addition
+        // final additions
         const double coef = (double)(nx + k * (nw + 1) + jc + 8) * 0x1p-52;
-        if (!isfinite(g)) { m = 0.0; s = INFINITY; }
-        else s = s + coef * g * (1.0 + 0x1p-50) + 0x1p-1000;
+        s = s + coef * g * (1.0 + 0x1p-50) + 0x1p-1000;
+        if (MODE == ROW_NOE) {
+            const double se = rr.sigE[tid];
+            s = s + se;
+            s = s + fabs(s) * 0x1p-52;
+            if (!isfinite(se)) g = INFINITY;
+        }
+        if (!isfinite(g) || !isfinite(s)) { m = 0.0; s = INFINITY; }
         if (k == 0) { m = 0.0; s = 0.0; }
-        mo[tid] = m;
+        mo[tid] = MODE == ROW_E ? 0.0 : m;
         so[tid] = s;
     }
     __syncthreads();
 }
 
-static int tube_jc(int nx, int nu, int nw, size_t* smem) {
+static int tube_jc(int nx, int nu, int nw, int mode, size_t* smem, size_t budget = SLS_ROW_LDS) {
     const int n = nx + nu;
-    const size_t per_j = sizeof(double) * ((size_t)n * nx + (size_t)nx * nw + 3 * nx + 3 * n);
+    const size_t per_j = sizeof(double) * ((mode != ROW_NOE ? (size_t)nx * nw + nx : 0) +
+                                           (mode != ROW_E ? 2 * (size_t)nx : 0) + 3 * (size_t)n);
     int jc = SLS_THREADS / n;
-    while (jc > 1 && per_j * jc + 2 * n * sizeof(double) > SLS_ROW_LDS) --jc;
+    while (jc > 1 && per_j * jc + 2 * n * sizeof(double) > budget) --jc;
     *smem = per_j * jc;            // tube_row's region; callers add 2 n for the row results
     return jc;
 }
 
-__global__ void __launch_bounds__(SLS_THREADS) sls_tube_kernel(TubeRowArgs a) {
+// register length bucket of a row of Phi
+static int nx_bucket(int nx) { return nx <= 8 ? 8 : (nx <= 16 ? 16 : 32); }
+
+template <int MODE, int NXB>
+__global__ void __launch_bounds__(SLS_THREADS) sls_tube_kernel(TubeRowArgs a, double* out_sig) {
     const int k = blockIdx.x, b = blockIdx.y;
     extern __shared__ double sm[];
     const int n = a.nx + a.nu;
     double* mo = sm;
     double* so = sm + n;
-    tube_row(a, b, k, sm + 2 * n, mo, so);
+    tube_row<MODE, NXB>(a, row_ref(a, b, k), k, sm + 2 * n, mo, so);
     const size_t o = ((size_t)b * a.N + k) * n;
-    for (int q = threadIdx.x; q < n; q += blockDim.x) { a.mu[o + q] = mo[q]; a.sigma[o + q] = so[q]; }
+    for (int q = threadIdx.x; q < n; q += blockDim.x) {
+        if (MODE == ROW_E) {
+            out_sig[o + q] = so[q];
+        } else {
+            a.mu[o + q] = mo[q];
+            a.sigma[o + q] = so[q];
+        }
+    }
+}
+
+template <int MODE>
+static void launch_tube(const TubeRowArgs& a, int batch, double* out_sig, hipStream_t s) {
+    size_t smem;
+    TubeRowArgs t = a;
+    t.jc = tube_jc(a.nx, a.nu, a.nw, MODE, &smem);
+    smem += 2 * (a.nx + a.nu) * sizeof(double);
+    const dim3 grid((unsigned)a.N, (unsigned)batch);
+    switch (nx_bucket(a.nx)) {
+    case 8: hipLaunchKernelGGL((sls_tube_kernel<MODE, 8>), grid, dim3(SLS_THREADS), smem, s, t, out_sig); break;
+    case 16: hipLaunchKernelGGL((sls_tube_kernel<MODE, 16>), grid, dim3(SLS_THREADS), smem, s, t, out_sig); break;
+    default: hipLaunchKernelGGL((sls_tube_kernel<MODE, 32>), grid, dim3(SLS_THREADS), smem, s, t, out_sig); break;
+    }
 }
 
 // ------------------------------------------------------------ disturbance error
@@ -398,6 +533,7 @@ struct FpRowArgs {
 };
 
 // Row launch of step k (k = N: only finishes step N-1).  One workgroup per trajectory.
+template <int NXB>
 __global__ void __launch_bounds__(SLS_THREADS) sls_fp_row_kernel(FpRowArgs a, int k) {
     const int b = blockIdx.x;
     const TubeRowArgs& t = a.t;
@@ -442,7 +578,7 @@ __global__ void __launch_bounds__(SLS_THREADS) sls_fp_row_kernel(FpRowArgs a, in
         }
         return;
     }
-    tube_row(t, b, k, sm + 2 * n, mo, so);
+    tube_row<ROW_NOE, NXB>(t, row_ref(t, b, k), k, sm + 2 * n, mo, so);
     const size_t o = ((size_t)b * N + k) * n;
     for (int q = tid; q < n; q += blockDim.x) {
         t.mu[o + q] = mo[q];
@@ -453,6 +589,116 @@ __global__ void __launch_bounds__(SLS_THREADS) sls_fp_row_kernel(FpRowArgs a, in
     const size_t ob = (size_t)b * N + k;
     for (int q = tid; q < nx; q += blockDim.x) a.zs[(size_t)b * nx + q] = a.z[ob * nx + q];
     for (int q = tid; q < nu; q += blockDim.x) a.vs[(size_t)b * nu + q] = a.v[ob * nu + q];
+}
+
+// Chain dynamics: the whole causal pass of one trajectory in one workgroup.
+// Step k: tube row k, then the path-based bound of the unit (z_k, v_k) +
+// mu_k +- sigma_k by the chain bound's node pass (U of the 256 lanes; the
+// tube row sits in LDS and the bound writes its rows to LDS), then the
+// residual zonotope of step k for the later rows.
+struct FpChainArgs {
+    TubeRowArgs t;
+    double* cbar_w; double* rbar_w;
+    const double* z; const double* v;
+    double* r_lo; double* r_hi;
+    uint32_t* certified;
+    double thrust_c;
+    // node-pass constants
+    int U;
+    double c, kL, L0, pad;
+    int compact;
+};
+
+__device__ __forceinline__ void residual_row(int l, double lo, double hi, double zt, double mut, double sgt,
+                                             double e0, double thrust_c, double pad, double* cb, double* rb,
+                                             double* lo_o, double* hi_o) {
+    if (thrust_c > 0.0) {
+        const double s = thrust_rdist(l, zt, mut, sgt, e0, thrust_c);
+        if (s != 0.0) {
+            lo = rdn(lo - s);
+            hi = rup(hi + s);
+        }
+    }
+    *lo_o = lo;
+    *hi_o = hi;
+    double c = 0.5 * (lo + hi), r = fmax(hi - c, c - lo);
+    r = rup(rup(r) + pad);
+    if (!isfinite(lo) || !isfinite(hi)) { c = NAN; r = INFINITY; }
+    *cb = c;
+    *rb = r;
+}
+
+template <int NXB>
+__global__ void __launch_bounds__(SLS_THREADS) sls_fp_chain_kernel(FpChainArgs a) {
+    const int b = blockIdx.x;
+    const TubeRowArgs& t = a.t;
+    const int nx = t.nx, nu = t.nu, n = nx + nu, N = t.N, nw = t.nw, U = a.U;
+    extern __shared__ double sm[];
+    // the trajectory's nominal, disturbance parts, thrust entries and residual
+    // zonotopes stay in LDS for the whole pass
+    double* mo = sm;                    // n
+    double* so = mo + n;                // n
+    double* rl = so + n;                // nx
+    double* rh = rl + nx;               // nx
+    double* zl = rh + nx;               // N*nx
+    double* vl = zl + (size_t)N * nx;   // N*nu
+    double* sel = vl + (size_t)N * nu;  // N*n
+    double* eth = sel + (size_t)N * n;  // N*nx  E_k entry of row l's thrust column (0 off the thrust rows)
+    double* cbl = eth + (size_t)N * nx; // N*nx
+    double* rbl = cbl + (size_t)N * nx; // N*nx
+    SpringOut* s_sp = reinterpret_cast<SpringOut*>(rbl + (size_t)N * nx);      // [U]
+    uint32_t* s_flag = reinterpret_cast<uint32_t*>(s_sp + U);                   // [2]: flags, all finite
+    const size_t off = ((reinterpret_cast<uintptr_t>(s_flag + 2) - reinterpret_cast<uintptr_t>(sm)) + 15) & ~size_t(15);
+    double* region = reinterpret_cast<double*>(reinterpret_cast<unsigned char*>(sm) + off);
+    const int tid = threadIdx.x, bs = blockDim.x;
+    const int lt = tid / U, i = tid - lt * U;
+    const size_t b0 = (size_t)b * N;
+    for (int q = tid; q < N * nx; q += bs) {
+        zl[q] = a.z[b0 * nx + q];
+        const int k = q / nx, l = q - k * nx, comp = l % 6;
+        eth[q] = (a.thrust_c > 0.0 && (comp == 3 || comp == 4)) ? t.E[((b0 + k) * nx + l) * nw + (nw - U + l / 6)] : 0.0;
+    }
+    for (int q = tid; q < N * nu; q += bs) vl[q] = a.v[b0 * nu + q];
+    for (int q = tid; q < N * n; q += bs) sel[q] = t.sigE[b0 * n + q];
+    if (tid == 0) s_flag[1] = 1u;
+    __syncthreads();
+    RowRef rr;
+    rr.E = nullptr; rr.cb = cbl; rr.rb = rbl;
+    for (int k = 0; k < N; ++k) {
+        rr.phi = t.phi + ((b0 + k) * N) * n * nx;
+        rr.sigE = sel + (size_t)k * n;
+        tube_row<ROW_NOE, NXB>(t, rr, k, region, mo, so);
+        for (int q = tid; q < n; q += bs) {
+            t.mu[(b0 + k) * n + q] = mo[q];
+            t.sigma[(b0 + k) * n + q] = so[q];
+            if (!isfinite(so[q])) s_flag[1] = 0u;
+        }
+        if (tid == 0) s_flag[0] = 0u;
+        const TileRef t0{zl + (size_t)k * nx, vl + (size_t)k * nu, mo, so, rl, rh, nullptr, nullptr, nullptr, 1};
+        NodeIn d;
+        node_load(t0, U, lt, i, d);
+        lds_barrier();                        // s_flag cleared
+        node_pass(a, t0, d, lt, i, s_sp, s_flag);
+        lds_barrier();                        // the unit's rows are in rl, rh
+        for (int l = tid; l < nx; l += bs) {
+            const int th = 6 * (l / 6) + 2;
+            double lo, hi;
+            residual_row(l, rl[l], rh[l], zl[(size_t)k * nx + th], mo[th], so[th], eth[(size_t)k * nx + l],
+                         a.thrust_c, a.pad, &cbl[(size_t)k * nx + l], &rbl[(size_t)k * nx + l], &lo, &hi);
+            if (!isfinite(rbl[(size_t)k * nx + l])) s_flag[1] = 0u;
+            if (a.r_lo) { a.r_lo[(b0 + k) * nx + l] = lo; a.r_hi[(b0 + k) * nx + l] = hi; }
+        }
+        lds_barrier();                        // residual of step k in LDS for the later rows
+    }
+    if (a.certified && tid == 0) a.certified[b] = s_flag[1];
+}
+
+// LDS bytes of the resident part of sls_fp_chain_kernel (before its tube-row region)
+static size_t fp_chain_head_bytes(int nx, int nu, int U, int N) {
+    const int n = nx + nu;
+    const size_t b = sizeof(double) * ((size_t)2 * n + 2 * nx + (size_t)N * (nx + nu + n + 3 * nx)) +
+                     sizeof(SpringOut) * U + 2 * sizeof(uint32_t);
+    return (b + 15) & ~size_t(15);
 }
 
 struct SlsWorkspace {
@@ -482,8 +728,17 @@ extern "C" int leb_sls_responses(int32_t nx, int32_t nu, int32_t batch, int32_t 
     a.A = A; a.B = B; a.qx = qx; a.qu = qu; a.K = K; a.phi = phi;
     a.nx = nx; a.nu = nu; a.N = N;
     const int threads = min(SLS_THREADS, 64 * ((nx * nx + 63) / 64));
-    hipLaunchKernelGGL(sls_riccati_kernel, dim3((unsigned)N, (unsigned)batch), dim3(threads), riccati_smem(nx, nu),
-                       (hipStream_t)stream, a);
+    // registers per thread that hold one step's prefetch
+    const int step = max(nx * nx + 2 * nx * nu, nx * (nx + nu) + nx + nu);
+    const bool small = nu <= 4 && step <= 2 * threads;
+    if (!small && step > SLS_PF * threads) return LEB_ENOTSUP;
+    const dim3 grid((unsigned)N, (unsigned)batch);
+    const size_t sm = riccati_smem(nx, nu);
+    hipStream_t st = (hipStream_t)stream;
+    if (small)
+        hipLaunchKernelGGL((sls_riccati_kernel<4, 2>), grid, dim3(threads), sm, st, a);
+    else
+        hipLaunchKernelGGL((sls_riccati_kernel<SLS_MAX_NU, SLS_PF>), grid, dim3(threads), sm, st, a);
     return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
 }
 
@@ -498,12 +753,9 @@ extern "C" int leb_sls_tube_map(int32_t nx, int32_t nu, int32_t nw, int32_t batc
     for (const void* p : ptrs)
         if (p && !aligned8(p)) return LEB_EINVAL;
     TubeRowArgs a;
-    a.phi = phi; a.E = E; a.cbar = c_bar; a.rbar = rho_bar; a.mu = mu; a.sigma = sigma;
+    a.phi = phi; a.E = E; a.cbar = c_bar; a.rbar = rho_bar; a.mu = mu; a.sigma = sigma; a.sigE = nullptr;
     a.nx = nx; a.nu = nu; a.nw = nw; a.N = N;
-    size_t smem;
-    a.jc = tube_jc(nx, nu, nw, &smem);
-    hipLaunchKernelGGL(sls_tube_kernel, dim3((unsigned)N, (unsigned)batch), dim3(SLS_THREADS),
-                       smem + 2 * (nx + nu) * sizeof(double), (hipStream_t)stream, a);
+    launch_tube<ROW_FULL>(a, batch, nullptr, (hipStream_t)stream);
     return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
 }
 
@@ -560,8 +812,8 @@ extern "C" int leb_sls_fixed_point(const leb_dynamics* dyn, int32_t batch, int32
     if (certified && (reinterpret_cast<uintptr_t>(certified) & 3u)) return LEB_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     std::lock_guard<std::mutex> lock(g_sls.mu);
-    // cbar, rbar [b][N][nx]; staging zs [b][nx], vs [b][nu], mus, sgs [b][n], rlo_s, rhi_s [b][nx]
-    const size_t need = (size_t)batch * (2 * (size_t)N * nx + nx + nu + 2 * n + 2 * nx) + 1;
+    // cbar, rbar [b][N][nx]; sigE [b][N][n]; staging zs [b][nx], vs [b][nu], mus, sgs [b][n], rlo_s, rhi_s [b][nx]
+    const size_t need = (size_t)batch * (2 * (size_t)N * nx + (size_t)N * n + nx + nu + 2 * n + 2 * nx) + 1;
     if (need > g_sls.cap) {
         if (g_sls.buf) (void)hipFree(g_sls.buf);
         g_sls.buf = nullptr;
@@ -580,9 +832,15 @@ extern "C" int leb_sls_fixed_point(const leb_dynamics* dyn, int32_t batch, int32
     a.t.cbar = a.cbar_w;
     a.t.rbar = a.rbar_w;
     a.t.nx = nx; a.t.nu = nu; a.t.nw = nw; a.t.N = N;
+    // the disturbance part of every tube entry first: it does not depend on the bounds,
+    // so it runs over all (trajectory, step) rows at once
+    double* sigE = take((size_t)batch * N * n);
+    a.t.sigE = sigE;
+    launch_tube<ROW_E>(a.t, batch, sigE, s);
     size_t smem;
-    a.t.jc = tube_jc(nx, nu, nw, &smem);
+    a.t.jc = tube_jc(nx, nu, nw, ROW_NOE, &smem);
     smem += 2 * n * sizeof(double);
+    const int nxb = nx_bucket(nx);
     a.zs = take((size_t)batch * nx);
     a.vs = take((size_t)batch * nu);
     a.mus = take((size_t)batch * n);
@@ -594,8 +852,37 @@ extern "C" int leb_sls_fixed_point(const leb_dynamics* dyn, int32_t batch, int32
     a.thrust_c = thrust > 0.0 ? thrust * dyn->dt / dyn->m : 0.0;
     a.pad = pad;
     a.U = chain ? dyn->n_units : 0;
+    // chains whose trajectory data fits in LDS beside a tube-row region: the whole
+    // causal pass in one launch (one workgroup per trajectory)
+    const size_t head = chain ? fp_chain_head_bytes(nx, nu, dyn->n_units, N) : 0;
+    size_t region = 0;
+    int jc_res = 0;
+    if (chain && head < SLS_LDS_MAX) {
+        jc_res = tube_jc(nx, nu, nw, ROW_NOE, &region, SLS_LDS_MAX - head);
+        if (head + region > SLS_LDS_MAX) jc_res = 0;
+    }
+    if (jc_res > 0) {
+        FpChainArgs c;
+        c.t = a.t;
+        c.t.jc = jc_res;
+        c.cbar_w = a.cbar_w; c.rbar_w = a.rbar_w;
+        c.z = z; c.v = v; c.r_lo = r_lo; c.r_hi = r_hi; c.certified = certified;
+        c.thrust_c = a.thrust_c;
+        c.U = dyn->n_units;
+        c.c = dyn->dt / dyn->m; c.kL = dyn->k_spring * dyn->rest_len; c.L0 = dyn->rest_len; c.pad = pad;
+        c.compact = 0;
+        const dim3 g((unsigned)batch), bl(SLS_THREADS);
+        if (nxb == 8) hipLaunchKernelGGL(sls_fp_chain_kernel<8>, g, bl, head + region, s, c);
+        else if (nxb == 16) hipLaunchKernelGGL(sls_fp_chain_kernel<16>, g, bl, head + region, s, c);
+        else hipLaunchKernelGGL(sls_fp_chain_kernel<32>, g, bl, head + region, s, c);
+        return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
+    }
+    // otherwise one row launch and one bound launch per step
     for (int k = 0; k <= N; ++k) {
-        hipLaunchKernelGGL(sls_fp_row_kernel, dim3((unsigned)batch), dim3(SLS_THREADS), smem, s, a, k);
+        const dim3 g((unsigned)batch), bl(SLS_THREADS);
+        if (nxb == 8) hipLaunchKernelGGL(sls_fp_row_kernel<8>, g, bl, smem, s, a, k);
+        else if (nxb == 16) hipLaunchKernelGGL(sls_fp_row_kernel<16>, g, bl, smem, s, a, k);
+        else hipLaunchKernelGGL(sls_fp_row_kernel<32>, g, bl, smem, s, a, k);
         if (k == N) break;
         rc = chain ? launch_pbh_chain(dyn, batch, a.zs, a.vs, a.mus, a.sgs, rlo_s, rhi_s, nullptr, nullptr, 0.0,
                                       nullptr, s)

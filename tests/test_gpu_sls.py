@@ -192,6 +192,39 @@ def test_sls_update_parity(gpu, orc, sls, n_units, thrust, N):
         _close_interval(lo[b], hi[b], loo, hio, "bounds U=%d b=%d" % (n_units, b))
 
 
+def test_sls_update_per_step_launches_until_the_tube_blows_up(gpu, orc, sls):
+    """Five quadrotors at N = 60 do not fit the one-launch pass's LDS and take
+    the per-step launches.  On these random nominals the tube grows into a
+    spring singularity (the oracle's tube stops being finite near step 40):
+    parity while the tube is moderate (every radius <= 1; closer to the
+    singularity the bound's sensitivity amplifies the last-bit differences
+    of the two sides), finite on both sides up to the same step, every later
+    tube entry +inf, no certificate."""
+    import paper_2607_01203_amd as leb
+    p = W.sls_cfg(seed=35, batch=3, N=60, n_units=5, thrust=0.2)
+    dyn = leb.dynamics_like(p.dyn)
+    print("case: sls update U=5 N=60 per-step launches", flush=True)
+    out = leb.sls_update(dyn, _t(p.z, gpu), _t(p.v, gpu), _t(p.qx, gpu), _t(p.qu, gpu), p.e, p.thrust, pad=1e-6)
+    mu, sg, lo, hi, cert = (_np(out[k]) for k in ("mu", "sigma", "r_lo", "r_hi", "certified"))
+    assert (cert == 0).all()
+    for b in range(p.batch):
+        with np.errstate(invalid="ignore", over="ignore"):
+            mo, so, loo, hio = _oracle_update(orc, sls, p, b, 1e-6)
+        fin_t = np.isfinite(so).all(1) & np.isfinite(mo).all(1)
+        fin_r = np.isfinite(loo).all(1) & np.isfinite(hio).all(1)
+        kt = int(np.argmin(fin_t)) if not fin_t.all() else p.N
+        kr = int(np.argmin(fin_r)) if not fin_r.all() else p.N
+        assert 10 < kt < p.N and kr < kt
+        big = np.nanmax(np.where(np.isfinite(so), so, np.inf), 1) > 1.0
+        km = int(np.argmax(big)) if big.any() else kt
+        assert km > 10
+        _close_tube(mu[b, :km], sg[b, :km], mo[:km], so[:km], "U=5 tube b=%d" % b)
+        _close_interval(lo[b, :km], hi[b, :km], loo[:km], hio[:km], "U=5 bounds b=%d" % b)
+        assert np.isfinite(sg[b, :kt]).all() and np.isfinite(lo[b, :kr]).all() and np.isfinite(hi[b, :kr]).all()
+        assert np.isinf(sg[b, kt:]).all() and (mu[b, kt:] == 0).all()
+        assert (~np.isfinite(lo[b, kr]) | ~np.isfinite(hi[b, kr])).any()
+
+
 def test_sls_fixed_point_is_its_own_image(gpu):
     """The returned tube is C = F(C): the path-based bound over the returned
     tube (leb_analytic_bound) reproduces the returned bounds exactly (no
