@@ -83,6 +83,8 @@ def parse():
                    help="only run the MLP-bound roofline measurement (for profiling its kernels)")
     p.add_argument("--m2-only", action="store_true",
                    help="only run the path-based bound at 2,560 x 40 units per launch (for profiling it)")
+    p.add_argument("--sls-only", action="store_true",
+                   help="only run the SLS controller-update leg (for profiling its kernels)")
     p.add_argument("--fp-epochs", type=int, default=100, help="epochs of the fixed-point-target surrogate")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                    help="only run an elementwise copy (read BYTES, write BYTES) 5 times: the known-size "
@@ -149,6 +151,9 @@ def main():
         return
     if args.m2_only:
         print(json.dumps({"roofline_bound": plain_m2(leb, W, dev, torch.cuda.current_stream(), args)}))
+        return
+    if args.sls_only:
+        print(json.dumps({"sls_update": sls_update(leb, W, dev, torch.cuda.current_stream())}))
         return
     tp = W.fixed_point_cfg()
     b = tp.batch
@@ -464,8 +469,8 @@ def sls_update(leb, W, dev, stream):
     linearization with the thrust-disturbance matrix (leb_linearize),
     closed-loop responses by the parallel Riccati recursions
     (leb_sls_responses) and the exact tube/LEB fixed point with r_dist
-    (leb_sls_fixed_point), for the planar quadrotor (nx = 6) and chains of 2
-    and 5 (nx = 12, 30).  Each call is timed with HIP events on the stream
+    (leb_sls_fixed_point), for the planar quadrotor (nx = 6) and a chain of
+    2 (nx = 12).  Each call is timed with HIP events on the stream
     (buffers allocated beforehand); bytes are the algorithmic minimum: the
     responses write Phi and K once, the fixed point reads Phi once."""
     import numpy as np
@@ -474,7 +479,7 @@ def sls_update(leb, W, dev, stream):
     vp = lambda t: ctypes.c_void_p(t.data_ptr())
     f64 = torch.float64
     res = {}
-    for U in (1, 2, 5):
+    for U in (1, 2):
         p = W.sls_cfg(n_units=U)
         dyn = leb.dynamics_like(p.dyn)
         B, N, nx, nu = p.batch, p.N, p.dyn.nx, p.dyn.nu
@@ -518,14 +523,20 @@ def sls_update(leb, W, dev, stream):
         pairs = B * N * (N - 1) // 2
         phi_bytes = pairs * n * nx * 8
         k_bytes = pairs * nu * nx * 8
+        # FP64 flops of the recursions per (trajectory, j, k): backward P A, P B, S, Bc, P update;
+        # forward K X, A + B K, (A + B K) X
+        fl_step = (2 * nx ** 3 + 2 * nx * nx * nu + 2 * nu * nu * nx + 2 * nu * nx * nx + 2 * nx ** 3 +
+                   2 * nx * nx * nu) + (2 * nu * nx * nx + 2 * nx * nx * nu + 2 * nx ** 3)
         total = sum(acc)
         res["chain%d_256x40" % U] = {
             "nx": nx, "nu": nu, "nw": nw, "ms_linearize": round(acc[0], 4), "ms_responses": round(acc[1], 4),
             "ms_fixed_point": round(acc[2], 4), "ms_update": round(total, 4),
             "step_bounds_per_s": round(B * N / (total * 1e-3), 1),
             "responses_hbm_frac": round((phi_bytes + k_bytes) / (acc[1] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "responses_fp64_frac": round(pairs * fl_step / (acc[1] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
             "fixed_point_phi_read_hbm_frac": round(phi_bytes / (acc[2] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "certified": int(cert.sum().item()), "mean_sigma_state": float(sg[..., :nx].mean())}
+            "certified": int(cert.sum().item()),
+            "mean_sigma_state_certified": float(sg[cert.bool()][..., :nx].mean()) if bool(cert.any()) else None}
     return res
 
 
