@@ -256,6 +256,186 @@ __global__ void __launch_bounds__(SLS_THREADS) sls_riccati_kernel(RiccatiArgs a)
     }
 }
 
+// The same recursions on FP64 MFMA (v_mfma_f64_16x16x4f64) for nx <= 16,
+// nu <= 4: one wave per (trajectory, j), every matrix a zero-padded 16 x 16
+// tile held in registers in the accumulator layout (lane l holds element
+// [4i + l/16][l%16] of its tile, i = 0..3).  That layout is also the B operand
+// of a product and, read as the A operand, the transpose, so every product
+// takes the form X^T Y and stays in registers:
+//   P A = P^T A and P B = P^T B (P is symmetric), S = B^T (P B),
+//   Bc = B^T (P A), P' = diag(qx) + A^T (P A) + K^T Bc;
+//   forward: K X = (K^T)^T X, (A + B K)^T = A^T + K^T B^T, X' = ((A + B K)^T)^T X,
+// with A^T, B^T, K^T loaded straight into the accumulator layout.  Only S
+// and Bc pass through LDS, for the nu x nu Cholesky factor and the column
+// solves (lanes c < nx, each factoring S itself).
+typedef double sls_d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ sls_d4 mm_tn(const sls_d4& X, const sls_d4& Y, sls_d4 acc) {   // acc + X^T Y
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(X[t], Y[t], acc, 0, 0, 0);
+    return acc;
+}
+
+// M (R x C, leading dimension ld) in the accumulator layout; tr: M^T instead
+__device__ __forceinline__ sls_d4 tile_load(const double* M, int R, int C, int ld, int lr, int lq, bool tr) {
+    sls_d4 v;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int row = tr ? lr : 4 * i + lq, col = tr ? 4 * i + lq : lr;
+        v[i] = (row < R && col < C) ? M[row * ld + col] : 0.0;
+    }
+    return v;
+}
+
+template <int NUB>
+__global__ void __launch_bounds__(64) sls_riccati_mfma_kernel(RiccatiArgs a) {
+    const int j = blockIdx.x, b = blockIdx.y;
+    const int nx = a.nx, nu = a.nu, N = a.N, n = nx + nu;
+    if (j >= N - 1) return;
+    __shared__ double sS[NUB * NUB];
+    __shared__ double sBc[NUB * 16];
+    __shared__ double sK[16 * 16];
+    const int lane = threadIdx.x, lr = lane & 15, lq = lane >> 4;
+    const double* Ab = a.A + (size_t)b * N * nx * nx;
+    const double* Bb = a.B + (size_t)b * N * nx * nu;
+    const double* qxb = a.qx + (size_t)b * (N + 1) * N * nx;
+    const double* qub = a.qu + (size_t)b * N * N * nu;
+    double* Kb = a.K + (size_t)b * N * N * nu * nx;
+    double* phib = a.phi + (size_t)b * N * N * n * nx;
+    for (int q = lane; q < 256; q += 64) sK[q] = 0.0;          // rows >= nu stay 0
+    // element of this lane on the diagonal (row 4i + lq == lr), if any
+    const int di = (lr >= lq && ((lr - lq) & 3) == 0) ? (lr - lq) >> 2 : -1;
+    sls_d4 P;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) P[i] = (i == di && lr < nx) ? qxb[((size_t)N * N + j) * nx + lr] : 0.0;
+    auto wts = [&](int k, double* qx_d, double* qu_d) {
+        *qx_d = (di >= 0 && lr < nx) ? qxb[((size_t)k * N + j) * nx + lr] : 0.0;
+        *qu_d = (di >= 0 && lr < nu) ? qub[((size_t)k * N + j) * nu + lr] : 0.0;
+    };
+    sls_d4 An = tile_load(Ab + (size_t)(N - 1) * nx * nx, nx, nx, nx, lr, lq, false);
+    sls_d4 Bn = tile_load(Bb + (size_t)(N - 1) * nx * nu, nx, nu, nu, lr, lq, false);
+    double qxn, qun;
+    wts(N - 1, &qxn, &qun);
+    const sls_d4 z4 = {0.0, 0.0, 0.0, 0.0};
+    for (int k = N - 1; k > j; --k) {
+        const sls_d4 A = An, B = Bn;
+        const double qxd = qxn, qud = qun;
+        if (k - 1 > j) {
+            An = tile_load(Ab + (size_t)(k - 1) * nx * nx, nx, nx, nx, lr, lq, false);
+            Bn = tile_load(Bb + (size_t)(k - 1) * nx * nu, nx, nu, nu, lr, lq, false);
+            wts(k - 1, &qxn, &qun);
+        }
+        const sls_d4 PA = mm_tn(P, A, z4);
+        const sls_d4 PB = mm_tn(P, B, z4);
+        sls_d4 S = mm_tn(B, PB, z4);
+        const sls_d4 Bc = mm_tn(B, PA, z4);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = 4 * i + lq;
+            if (row < nu) {
+                if (lr < nu) sS[row * NUB + lr] = S[i] + (i == di ? qud : 0.0);
+                sBc[row * 16 + lr] = Bc[i];
+            }
+        }
+        lds_barrier();
+        if (lane < nx) {
+            // S = L L^T (nu <= NUB) in registers, then L y = Bc[:, c], L^T x = y
+            double L[NUB][NUB], inv[NUB];         // inv: 1 / L_cc, one division per pivot
+            bool bad = false;
+#pragma unroll
+            for (int c = 0; c < NUB; ++c) {
+                if (c < nu) {
+                    double d = sS[c * NUB + c];
+#pragma unroll
+                    for (int m = 0; m < c; ++m) d -= L[c][m] * L[c][m];
+                    if (!(d > 0.0) || !isfinite(d)) { bad = true; d = 1.0; }
+                    inv[c] = 1.0 / sqrt(d);
+#pragma unroll
+                    for (int r = c + 1; r < NUB; ++r) {
+                        if (r < nu) {
+                            double t = sS[r * NUB + c];
+#pragma unroll
+                            for (int m = 0; m < c; ++m) t -= L[r][m] * L[c][m];
+                            L[r][c] = t * inv[c];
+                        }
+                    }
+                }
+            }
+            double y[NUB];
+#pragma unroll
+            for (int r = 0; r < NUB; ++r) {
+                if (r < nu) {
+                    double t = sBc[r * 16 + lane];
+#pragma unroll
+                    for (int m = 0; m < r; ++m) t -= L[r][m] * y[m];
+                    y[r] = t * inv[r];
+                }
+            }
+#pragma unroll
+            for (int r = NUB - 1; r >= 0; --r) {
+                if (r < nu) {
+                    double t = y[r];
+#pragma unroll
+                    for (int m = r + 1; m < NUB; ++m)
+                        if (m < nu) t -= L[m][r] * y[m];
+                    y[r] = t * inv[r];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < NUB; ++r) {
+                if (r < nu) {
+                    const double kv = bad ? NAN : -y[r];
+                    sK[r * 16 + lane] = kv;
+                    Kb[((size_t)k * N + j) * nu * nx + r * nx + lane] = kv;
+                }
+            }
+        }
+        lds_barrier();
+        sls_d4 K;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) K[i] = sK[(4 * i + lq) * 16 + lr];
+        sls_d4 Pn;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) Pn[i] = i == di ? qxd : 0.0;
+        Pn = mm_tn(A, PA, Pn);
+        P = mm_tn(K, Bc, Pn);
+        lds_barrier();                         // sS, sBc, sK are rewritten by the next step
+    }
+    // forward propagation from Phi^x_{j+1,j} = I; the gains were stored above
+    // by this wave, and the full barrier orders those stores before the loads
+    __syncthreads();
+    sls_d4 X;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) X[i] = (i == di && lr < nx) ? 1.0 : 0.0;
+    auto fwd_load = [&](int k, sls_d4* AT, sls_d4* BT, sls_d4* Kt, sls_d4* KT) {
+        const double* Kp = Kb + ((size_t)k * N + j) * nu * nx;
+        *AT = tile_load(Ab + (size_t)k * nx * nx, nx, nx, nx, lr, lq, true);
+        *BT = tile_load(Bb + (size_t)k * nx * nu, nx, nu, nu, lr, lq, true);
+        *Kt = tile_load(Kp, nu, nx, nx, lr, lq, false);
+        *KT = tile_load(Kp, nu, nx, nx, lr, lq, true);
+    };
+    sls_d4 ATn, BTn, Kn, KTn;
+    fwd_load(j + 1, &ATn, &BTn, &Kn, &KTn);
+    for (int k = j + 1; k < N; ++k) {
+        const sls_d4 AT = ATn, BT = BTn, Kt = Kn, KT = KTn;
+        if (k + 1 < N) fwd_load(k + 1, &ATn, &BTn, &Kn, &KTn);
+        double* out = phib + ((size_t)k * N + j) * n * nx;
+        const sls_d4 U = mm_tn(KT, X, z4);          // K X
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = 4 * i + lq;
+            if (lr < nx) {
+                if (row < nx) out[row * nx + lr] = X[i];
+                if (row < nu) out[(nx + row) * nx + lr] = U[i];
+            }
+        }
+        if (k + 1 < N) {
+            const sls_d4 AclT = mm_tn(Kt, BT, AT);  // (A + B K)^T
+            X = mm_tn(AclT, X, z4);                 // (A + B K) X
+        }
+    }
+}
+
 static size_t riccati_smem(int nx, int nu) {
     return sizeof(double) * (size_t)(4 * nx * nx + 4 * nx * nu + nu * nu + nx + nu);
 }
@@ -735,7 +915,9 @@ extern "C" int leb_sls_responses(int32_t nx, int32_t nu, int32_t batch, int32_t 
     const dim3 grid((unsigned)N, (unsigned)batch);
     const size_t sm = riccati_smem(nx, nu);
     hipStream_t st = (hipStream_t)stream;
-    if (small)
+    if (nx > 8 && nx <= 16 && nu <= 4)
+        hipLaunchKernelGGL((sls_riccati_mfma_kernel<4>), grid, dim3(64), 0, st, a);
+    else if (small)
         hipLaunchKernelGGL((sls_riccati_kernel<4, 2>), grid, dim3(threads), sm, st, a);
     else
         hipLaunchKernelGGL((sls_riccati_kernel<SLS_MAX_NU, SLS_PF>), grid, dim3(threads), sm, st, a);

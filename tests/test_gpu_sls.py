@@ -69,8 +69,11 @@ def _close_tube(mu_g, sg_g, mu_o, sg_o, where):
     assert (sg_g >= sg_o - 1e-6 * scale - FLOOR).all(), "%s: sigma narrower" % where
 
 
-@pytest.mark.parametrize("nx,nu,N,batch", [(6, 2, 23, 3), (12, 4, 17, 2), (30, 10, 9, 2), (7, 3, 1, 2), (3, 1, 2, 2)])
+@pytest.mark.parametrize("nx,nu,N,batch", [(6, 2, 23, 3), (12, 4, 17, 2), (30, 10, 9, 2), (7, 3, 1, 2), (3, 1, 2, 2),
+                                            (16, 4, 11, 2), (9, 1, 6, 2), (16, 5, 5, 1)])
 def test_responses_parity(gpu, sls, nx, nu, N, batch):
+    """Both kernels: FP64 MFMA tiles for 8 < nx <= 16 with nu <= 4, the
+    LDS/VALU workgroup otherwise."""
     import paper_2607_01203_amd as leb
     A, B, qx, qu = W.random_ltv(100 + nx, batch, N, nx, nu, scale=0.2)
     print("case: responses nx=%d nu=%d N=%d batch=%d" % (nx, nu, N, batch), flush=True)
