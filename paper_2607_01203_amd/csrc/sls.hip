@@ -614,6 +614,74 @@ __global__ void __launch_bounds__(SLS_THREADS) sls_tube_kernel(TubeRowArgs a, do
     }
 }
 
+// The disturbance part sum_j |Phi_{k,j} E_j| 1 of tube row k on FP64 MFMA for
+// 8 < n <= 16, nw <= 16 (smaller blocks stay on the VALU row): one workgroup per (trajectory, k), wave w takes the blocks
+// j = w, w + 4, ...  Each block is one zero-padded 16 x 16 x 16 product
+// (A fragments from Phi_{k,j}, B fragments from E_j, both straight from
+// memory); the accumulator's entries are added up in absolute value over j,
+// and |Phi| |E| is accumulated beside it for the rounding allowance.  The
+// sixteen columns of each row are summed at the end.
+__global__ void __launch_bounds__(256) sls_tube_e_mfma_kernel(TubeRowArgs a, double* out_sig) {
+    const int k = blockIdx.x, b = blockIdx.y;
+    const int nx = a.nx, nw = a.nw, N = a.N, n = nx + a.nu;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lr = lane & 15, lq = lane >> 4;
+    __shared__ double red[2][4][4][64];
+    __shared__ double rows[2][16];
+    sls_d4 T = {0.0, 0.0, 0.0, 0.0}, G = {0.0, 0.0, 0.0, 0.0};
+    const double* prow = a.phi + (((size_t)b * N + k) * N) * n * nx;
+    const double* Eb = a.E + (size_t)b * N * nx * nw;
+    // fragments of block j: A[l%16][4t + l/16] from Phi_{k,j}, B[4t + l/16][l%16] from E_j;
+    // the next block's are loaded while this one multiplies
+    double an[4], bn[4];
+    auto frag = [&](int j) {
+        const double* Pj = prow + (size_t)j * n * nx;
+        const double* Ej = Eb + (size_t)j * nx * nw;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int kk = 4 * t + lq;
+            an[t] = (lr < n && kk < nx) ? Pj[lr * nx + kk] : 0.0;
+            bn[t] = (kk < nx && lr < nw) ? Ej[kk * nw + lr] : 0.0;
+        }
+    };
+    if (wave < k) frag(wave);
+    for (int j = wave; j < k; j += 4) {
+        double av[4], bv[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) { av[t] = an[t]; bv[t] = bn[t]; }
+        if (j + 4 < k) frag(j + 4);
+        sls_d4 D = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            D = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[t], D, 0, 0, 0);
+            G = __builtin_amdgcn_mfma_f64_16x16x4f64(fabs(av[t]), fabs(bv[t]), G, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) T[i] += fabs(D[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { red[0][wave][i][lane] = T[i]; red[1][wave][i][lane] = G[i]; }
+    __syncthreads();
+    if (tid < 32) {
+        // row r = 4 i + lq' of the tile: the 16 lanes lr of group lq', element i, all waves
+        const int which = tid >> 4, r = tid & 15, i = r >> 2, lqr = r & 3;
+        double acc = 0.0;
+        for (int w = 0; w < 4; ++w)
+            for (int c = 0; c < 16; ++c) acc += red[which][w][i][lqr * 16 + c];
+        rows[which][r] = acc;
+    }
+    __syncthreads();
+    if (tid < n) {
+        double sv = rows[0][tid];
+        const double g = rows[1][tid];
+        // depth of the sums: nx products per entry inside the MFMA, k blocks, 4 waves, 16 columns
+        const double coef = (double)(nx + k * (nw + 1) + 64) * 0x1p-52;
+        sv = sv + coef * g * (1.0 + 0x1p-50) + 0x1p-1000;
+        if (!isfinite(g) || !isfinite(sv)) sv = INFINITY;
+        if (k == 0) sv = 0.0;
+        out_sig[((size_t)b * N + k) * n + tid] = sv;
+    }
+}
+
 template <int MODE>
 static void launch_tube(const TubeRowArgs& a, int batch, double* out_sig, hipStream_t s) {
     size_t smem;
@@ -1018,7 +1086,10 @@ extern "C" int leb_sls_fixed_point(const leb_dynamics* dyn, int32_t batch, int32
     // so it runs over all (trajectory, step) rows at once
     double* sigE = take((size_t)batch * N * n);
     a.t.sigE = sigE;
-    launch_tube<ROW_E>(a.t, batch, sigE, s);
+    if (n > 8 && n <= 16 && nw <= 16 && nw > 0)
+        hipLaunchKernelGGL(sls_tube_e_mfma_kernel, dim3((unsigned)N, (unsigned)batch), dim3(256), 0, s, a.t, sigE);
+    else
+        launch_tube<ROW_E>(a.t, batch, sigE, s);
     size_t smem;
     a.t.jc = tube_jc(nx, nu, nw, ROW_NOE, &smem);
     smem += 2 * n * sizeof(double);
