@@ -288,3 +288,48 @@ def test_sls_update_full_size_sampled(gpu, orc, sls):
         mo, so, loo, hio = _oracle_update(orc, sls, p, b, 1e-6)
         _close_tube(mu[b], sg[b], mo, so, "full-size tube b=%d" % b)
         _close_interval(lo[b], hi[b], loo, hio, "full-size bounds b=%d" % b)
+
+
+def test_sls_update_sampled_soundness_1e6(gpu, orc, sls):
+    """The bench workload's residual enclosures hold at 10^6 sampled points:
+    for (x, u) in each step's tube box (z_k, v_k) + mu_k +- sigma_k (half
+    uniform, a quarter vertices, a quarter mixed) and w in the unit box
+    (vertices and uniform), the realised residual
+        f(x, u) + E(x) w - f(z, v) - A_k dx - B_k du - E_k w
+    (eq. linearization_error_all: r_lin + r_dist) lies in [r_lo, r_hi],
+    up to its FP64 evaluation error."""
+    import paper_2607_01203_amd as leb
+    p = W.sls_cfg()
+    dyn = leb.dynamics_like(p.dyn)
+    d = orc.Dyn.like(p.dyn)
+    print("case: sls update sampled soundness", flush=True)
+    out = leb.sls_update(dyn, _t(p.z, gpu), _t(p.v, gpu), _t(p.qx, gpu), _t(p.qu, gpu), p.e, p.thrust, pad=1e-6)
+    mu, sg, lo, hi, E = (_np(out[k]) for k in ("mu", "sigma", "r_lo", "r_hi", "E"))
+    nx, n = p.dyn.nx, p.dyn.n
+    nom = np.concatenate([p.z, p.v], -1).reshape(-1, n)
+    blo = (nom + mu.reshape(-1, n) - sg.reshape(-1, n))
+    bhi = (nom + mu.reshape(-1, n) + sg.reshape(-1, n))
+    lo, hi, E = lo.reshape(-1, nx), hi.reshape(-1, nx), E.reshape(-1, nx, E.shape[-1])
+    units = nom.shape[0]
+    per = 98                                   # 10,240 units x 98 = 1.0e6 samples
+    rng = W.rng_for(77)
+    viol = 0
+    total = 0
+    for s0 in range(0, units, 512):
+        s1 = min(units, s0 + 512)
+        U = s1 - s0
+        pts = W.sample_box_points(rng, blo[s0:s1], bhi[s0:s1], per)          # [U][per][n]
+        uo = np.repeat(np.arange(U), per)
+        r, eps = orc.remainder(d, nom[s0:s1], pts.reshape(-1, n), uo)
+        w = np.where(rng.random((U * per, E.shape[-1])) < 0.5, rng.uniform(-1, 1, (U * per, E.shape[-1])),
+                     np.sign(rng.uniform(-1, 1, (U * per, E.shape[-1]))))
+        Ex = sls.disturbance_matrix(d, pts.reshape(-1, n)[:, :nx], p.e, p.thrust)
+        rd = np.einsum("sij,sj->si", Ex - E[s0:s1][uo], w)
+        tot = r + rd
+        allow = eps + 1e-15 * (1.0 + np.abs(rd))
+        L = lo[s0:s1][uo]
+        H = hi[s0:s1][uo]
+        viol += int(((tot > H + allow) | (tot < L - allow)).sum())
+        total += U * per
+    assert total >= 1_000_000
+    assert viol == 0, viol
