@@ -649,10 +649,14 @@ int leb_sls_tube_map(int32_t nx, int32_t nu, int32_t nw, int32_t batch, int32_t 
  *   r_lo, r_hi [batch][N][nx] out (both NULL to skip): remainder enclosures
  *   certified [batch] out (may be NULL): 1 when every tube entry and residual
  *       is finite
- * Kinds CHAIN, SATELLITE, QUAD3D (LEB_ENOTSUP otherwise).  2N + 1 launches
- * on `stream`, no host synchronisation.  Uses a library-owned, grow-only
- * device workspace; calls serialise on the host and their kernels on the
- * device, like leb_fixed_point_solve.
+ * Kinds CHAIN, SATELLITE, QUAD3D (LEB_ENOTSUP otherwise).  The disturbance
+ * part of every tube entry (which does not depend on the bounds) is one launch
+ * over all rows; chains whose per-trajectory data fits in 64 KB of LDS then
+ * take the whole causal pass in one launch (one workgroup per trajectory),
+ * everything else one row launch and one bound launch per step.  All on
+ * `stream`, no host synchronisation.  Uses a library-owned, grow-only device
+ * workspace; calls serialise on the host and their kernels on the device,
+ * like leb_fixed_point_solve.
  */
 int leb_sls_fixed_point(const leb_dynamics* dyn, int32_t batch, int32_t N, const double* z, const double* v,
                         const double* phi, int32_t nw, const double* E, double thrust, double pad, double* mu,
