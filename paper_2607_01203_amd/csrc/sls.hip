@@ -558,11 +558,30 @@ __device__ void tube_row(const TubeRowArgs& a, const RowRef& rr, int k, double* 
         }
         lds_barrier();
     }
-    if (act) { red[jj * n + i] = am; red[(jc + jj) * n + i] = as; red[(2 * jc + jj) * n + i] = ag; }
+    // partial sums over the disturbance-time slots: within each wave by a
+    // butterfly over the lanes of one row (when n divides the wave and every
+    // lane holds a slot), then over the waves; otherwise slot by slot
+    const bool wave_red = (64 % n == 0) && (jc * n == nt);
+    if (wave_red) {
+        double m = am, s_ = as, g = ag;
+        for (int msk = n; msk < 64; msk <<= 1) {
+            m += __shfl_xor(m, msk);
+            s_ += __shfl_xor(s_, msk);
+            g += __shfl_xor(g, msk);
+        }
+        const int lane = tid & 63, wv = tid >> 6;
+        if (lane < n) { red[(3 * wv) * n + lane] = m; red[(3 * wv + 1) * n + lane] = s_; red[(3 * wv + 2) * n + lane] = g; }
+    } else if (act) {
+        red[jj * n + i] = am; red[(jc + jj) * n + i] = as; red[(2 * jc + jj) * n + i] = ag;
+    }
     lds_barrier();
     if (tid < n) {
         double m = 0.0, s = 0.0, g = 0.0;
-        for (int q = 0; q < jc; ++q) { m += red[q * n + tid]; s += red[(jc + q) * n + tid]; g += red[(2 * jc + q) * n + tid]; }
+        if (wave_red) {
+            for (int w = 0; w < nt / 64; ++w) { m += red[(3 * w) * n + tid]; s += red[(3 * w + 1) * n + tid]; g += red[(3 * w + 2) * n + tid]; }
+        } else {
+            for (int q = 0; q < jc; ++q) { m += red[q * n + tid]; s += red[(jc + q) * n + tid]; g += red[(2 * jc + q) * n + tid]; }
+        }
         // rounding of the sums: at most nx + k (nw + 1) + jc additions deep, each
         // within 2^-53 of the magnitudes g; doubled for the centre's error and the
         // final additions

@@ -333,3 +333,45 @@ def test_sls_update_sampled_soundness_1e6(gpu, orc, sls):
         total += U * per
     assert total >= 1_000_000
     assert viol == 0, viol
+
+
+@pytest.mark.parametrize("N", [1, 2])
+def test_sls_update_shortest_horizons(gpu, orc, sls, N):
+    """N = 1: no responses, the tube is 0 and the bound is the nominal
+    point's; N = 2: one response block."""
+    import paper_2607_01203_amd as leb
+    p = W.sls_cfg(seed=60 + N, batch=2, N=N, n_units=2, thrust=0.3)
+    dyn = leb.dynamics_like(p.dyn)
+    print("case: sls update N=%d" % N, flush=True)
+    out = leb.sls_update(dyn, _t(p.z, gpu), _t(p.v, gpu), _t(p.qx, gpu), _t(p.qu, gpu), p.e, p.thrust, pad=1e-6)
+    mu, sg, lo, hi, cert = (_np(out[k]) for k in ("mu", "sigma", "r_lo", "r_hi", "certified"))
+    assert (cert == 1).all() and (mu[:, 0] == 0).all() and (sg[:, 0] == 0).all()
+    for b in range(p.batch):
+        mo, so, loo, hio = _oracle_update(orc, sls, p, b, 1e-6)
+        _close_tube(mu[b], sg[b], mo, so, "N=%d tube b=%d" % (N, b))
+        _close_interval(lo[b], hi[b], loo, hio, "N=%d bounds b=%d" % (N, b))
+
+
+def test_sls_fixed_point_bad_nominal(gpu):
+    """A non-finite nominal state at step 5 of one trajectory: that step's
+    bound is [-inf, inf], every later tube entry +inf, the trajectory is not
+    certified; the other trajectory is unaffected."""
+    import torch
+    import paper_2607_01203_amd as leb
+    p = W.sls_cfg(seed=71, batch=2, N=12, n_units=1)
+    dyn = leb.dynamics_like(p.dyn)
+    z, v = _t(p.z, gpu), _t(p.v, gpu)
+    A, B, E = leb.linearize(dyn, z, v, p.e, p.thrust)
+    _, phi = leb.sls_responses(A, B, _t(p.qx, gpu), _t(p.qu, gpu))
+    ref = leb.sls_fixed_point(dyn, z, v, phi, E, p.thrust, 1e-6)
+    z2 = z.clone()
+    z2[0, 5, 1] = float("nan")
+    print("case: sls fixed point with a NaN nominal", flush=True)
+    mu, sg, lo, hi, cert = leb.sls_fixed_point(dyn, z2, v, phi, E, p.thrust, 1e-6)
+    torch.cuda.synchronize()
+    assert cert.tolist() == [0, 1]
+    assert torch.isinf(lo[0, 5]).all() and torch.isinf(hi[0, 5]).all()
+    assert torch.isinf(sg[0, 6:]).all() and torch.isfinite(sg[0, :6]).all()
+    assert torch.equal(sg[0, :6], ref[1][0, :6]) and torch.equal(mu[0, :6], ref[0][0, :6])
+    for t_new, t_ref in zip((mu, sg, lo, hi), ref[:4]):
+        assert torch.equal(t_new[1], t_ref[1])
