@@ -459,12 +459,6 @@ struct TubeRowArgs {
 // part from sigE (ROW_NOE).
 constexpr int ROW_FULL = 0, ROW_E = 1, ROW_NOE = 2;
 
-// Tube row k of trajectory b.  Thread t = jj * n + i works on row i of
-// Phi_{k, j0 + jj}, which it loads straight into registers (every entry of
-// Phi is used by one thread only); E_j, |E_j| 1, c_bar_j and rho_bar_j are
-// shared through LDS, jc disturbance times per chunk.  NXB >= nx is the
-// register length of a row.  Leaves the row's (mu, sigma) in mo[], so[] (LDS,
-// n entries) after the final barrier.
 // One trajectory's operands of tube row k (generic pointers: global or LDS).
 struct RowRef {
     const double* phi;       // Phi_{k,0} (the row block of k)
@@ -485,6 +479,12 @@ __device__ __forceinline__ RowRef row_ref(const TubeRowArgs& a, int b, int k) {
     return r;
 }
 
+// Tube row k of trajectory b.  Thread t = jj * n + i works on row i of
+// Phi_{k, j0 + jj}, which it loads straight into registers (every entry of
+// Phi is used by one thread only); E_j, |E_j| 1, c_bar_j and rho_bar_j are
+// shared through LDS, jc disturbance times per chunk.  NXB >= nx is the
+// register length of a row.  Leaves the row's (mu, sigma) in mo[], so[] (LDS,
+// n entries) after the final barrier.
 template <int MODE, int NXB>
 __device__ void tube_row(const TubeRowArgs& a, const RowRef& rr, int k, double* sm, double* mo, double* so) {
     const int nx = a.nx, nw = a.nw, n = nx + a.nu, jc = a.jc;
