@@ -470,7 +470,8 @@ def sls_update(leb, W, dev, stream):
     closed-loop responses by the parallel Riccati recursions
     (leb_sls_responses) and the exact tube/LEB fixed point with r_dist
     (leb_sls_fixed_point), for the planar quadrotor (nx = 6) and a chain of
-    2 (nx = 12).  Each call is timed with HIP events on the stream
+    2 (nx = 12), and for 1,024 planar-quadrotor trajectories (four per
+    compute unit in the causal pass).  Each call is timed with HIP events on the stream
     (buffers allocated beforehand); bytes are the algorithmic minimum: the
     responses write Phi and K once, the fixed point reads Phi once."""
     import numpy as np
@@ -479,8 +480,8 @@ def sls_update(leb, W, dev, stream):
     vp = lambda t: ctypes.c_void_p(t.data_ptr())
     f64 = torch.float64
     res = {}
-    for U in (1, 2):
-        p = W.sls_cfg(n_units=U)
+    for U, batch in ((1, 256), (2, 256), (1, 1024)):
+        p = W.sls_cfg(n_units=U, batch=batch)
         dyn = leb.dynamics_like(p.dyn)
         B, N, nx, nu = p.batch, p.N, p.dyn.nx, p.dyn.nu
         n, nw = nx + nu, nx + U
@@ -528,7 +529,7 @@ def sls_update(leb, W, dev, stream):
         fl_step = (2 * nx ** 3 + 2 * nx * nx * nu + 2 * nu * nu * nx + 2 * nu * nx * nx + 2 * nx ** 3 +
                    2 * nx * nx * nu) + (2 * nu * nx * nx + 2 * nx * nx * nu + 2 * nx ** 3)
         total = sum(acc)
-        res["chain%d_256x40" % U] = {
+        res["chain%d_%dx40" % (U, batch)] = {
             "nx": nx, "nu": nu, "nw": nw, "ms_linearize": round(acc[0], 4), "ms_responses": round(acc[1], 4),
             "ms_fixed_point": round(acc[2], 4), "ms_update": round(total, 4),
             "step_bounds_per_s": round(B * N / (total * 1e-3), 1),
