@@ -267,6 +267,31 @@ int leb_nn_bound(leb_mlp net, int32_t batch, int32_t N, const double* z, const d
                  double pad, uint32_t* flags, void* stream);
 
 /*
+ * leb_nn_backward -- adjoint of leb_nn_bound (the differentiable bound of
+ * section IV.D, for the ReLU-MLP bound of section IV.B): the gradient of
+ *     L = sum_{unit, row} g_lo r_lo + g_hi r_hi
+ * with respect to z, v, sigma (and mu) for the exact-arithmetic bound with
+ * J = J_g(a~) (rounding allowances are not differentiated; J a~ - g(a~)
+ * contributes 0, J being constant between kinks).  The bound is piecewise
+ * smooth; at ties the branch taken is: a CROWN coefficient of exactly 0 counts
+ * as non-negative, sign(0) = 0 in d|x|, the clamp min(mu - sigma, 0) passes
+ * the derivative only where mu - sigma < 0 and max(mu + sigma, 0) only where
+ * mu + sigma > 0, and a neuron is unstable when lo < 0 < hi.
+ *   z [batch][N][nx], v [batch][N][nu], mu (NULL = 0), sigma [batch][N][nx+nu]
+ *   g_lo, g_hi [batch][N][m]       upstream adjoints of r_lo, r_hi
+ *   gz, gv, gsigma                 outputs, shaped as z, v, sigma
+ *   gmu [batch][N][nx+nu]          output, may be NULL; must be NULL when mu is NULL
+ * Units with invalid data (non-finite input, sigma < 0) get a zero gradient.
+ * Every pass is recomputed (nothing of leb_nn_bound is reused), in FP64.
+ * Deterministic: every sum is taken in a fixed order.  Uses a library-owned
+ * grow-only workspace (about 80 MB), ordered across streams like the other
+ * workspaces.  LEB_EINVAL for null or misaligned pointers or gmu without mu.
+ */
+int leb_nn_backward(leb_mlp net, int32_t batch, int32_t N, const double* z, const double* v, const double* mu,
+                    const double* sigma, const double* g_lo, const double* g_hi, double* gz, double* gv,
+                    double* gmu, double* gsigma, void* stream);
+
+/*
  * leb_tube_map -- tube centre and width from the residual zonotopes
  * (eqs. tight_tube_center, tight_tube_width):
  *   mu_k    = sum_{j<k} Phi_{k,j} c_bar_j

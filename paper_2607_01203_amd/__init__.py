@@ -134,6 +134,8 @@ def lib():
         L.leb_mlp_destroy.restype = ctypes.c_int
         L.leb_nn_bound.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32] + [vp] * 9 + [ctypes.c_double, vp, vp]
         L.leb_nn_bound.restype = ctypes.c_int
+        L.leb_nn_backward.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32] + [vp] * 11
+        L.leb_nn_backward.restype = ctypes.c_int
         L.leb_tube_map.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp,
                                    ctypes.POINTER(ctypes.c_double), vp, vp, vp, vp, vp]
         L.leb_tube_map.restype = ctypes.c_int
@@ -732,6 +734,24 @@ def nn_bound(mlp: MLP, z, v, sigma, mu=None, pad: float = 0.0, zonotope: bool = 
                             _dev_ptr(out.get("rho_bar"), "rho_bar", f64), float(pad),
                             _dev_ptr(out["flags"], "flags"), _stream(stream))
     _check(rc)
+    return out
+
+
+def nn_backward(mlp: MLP, z, v, sigma, g_lo, g_hi, mu=None, stream=None):
+    """Gradient of sum g_lo r_lo + g_hi r_hi of the MLP bound (see leb.h:
+    leb_nn_backward).  Returns {"gz", "gv", "gsigma"} (and "gmu" when mu is
+    given), shaped as the inputs."""
+    import torch
+    f64 = torch.float64
+    out = {"gz": torch.empty_like(z), "gv": torch.empty_like(v), "gsigma": torch.empty_like(sigma)}
+    if mu is not None:
+        out["gmu"] = torch.empty_like(mu)
+    B, N = int(z.shape[0]), int(z.shape[1])
+    _check(lib().leb_nn_backward(mlp.handle, B, N, _dev_ptr(z, "z", f64), _dev_ptr(v, "v", f64),
+                                 _dev_ptr(mu, "mu", f64), _dev_ptr(sigma, "sigma", f64), _dev_ptr(g_lo, "g_lo", f64),
+                                 _dev_ptr(g_hi, "g_hi", f64), _dev_ptr(out["gz"], "gz", f64),
+                                 _dev_ptr(out["gv"], "gv", f64), _dev_ptr(out.get("gmu"), "gmu", f64),
+                                 _dev_ptr(out["gsigma"], "gsigma", f64), _stream(stream)))
     return out
 
 

@@ -38,27 +38,17 @@
 #include "leb.h"
 #include "leb_internal.hpp"
 
+#include "nn_net.hpp"
+
 namespace leb {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr double RT = 0x1p-40;   // rounding allowance factor
-constexpr int NN_MAXW = 256;     // widest layer handled
-constexpr int NN_MAXL = 8;       // most linear layers handled
 constexpr int NN_CHUNK = 1024;   // boxes per pass
 constexpr uint32_t NN_UNSTABLE = 1u << 31;   // private per-box bit: some neuron is unstable
 
 }  // namespace leb
-
-struct leb_mlp_s {
-    int L;                          // linear layers
-    int w[leb::NN_MAXL + 1];        // widths, w[0] inputs ... w[L] outputs
-    int nx, nu, residual;
-    double* W[leb::NN_MAXL];        // device, layer l+1: [w[l+1]][w[l]]
-    double* WT[leb::NN_MAXL];       // device, transposed [w[l]][w[l+1]]
-    double* b[leb::NN_MAXL];        // device [w[l+1]]
-    std::vector<void*> allocs;
-};
 
 namespace leb {
 

@@ -1,0 +1,511 @@
+// nn_bwd.hip -- adjoint of the ReLU-MLP remainder bound (sections IV.B and IV.D).
+//
+// The bound of nn.hip (CROWN with a full pass for every hidden layer's
+// pre-activation bounds, Theorem 2 with J = J_g(a~)) is piecewise smooth in
+// the nominal a~, the radii sigma and the offset mu; the paper differentiates
+// it to shape the nominal trajectory.  This file computes, for
+//     L = sum_rows g_hi r_hi + g_lo r_lo,
+// dL/da~, dL/dsigma and dL/dmu of the exact-arithmetic bound (rounding
+// allowances of the forward kernels are not part of it), by reverse mode.
+//
+// Forward quantities.  Box c = a~ + (dlo + dhi)/2, rho = (dhi - dlo)/2 with
+// dlo = min(mu - sigma, 0), dhi = max(mu + sigma, 0).  Layer-1 bounds
+// W_1 c + b_1 -/+ |W_1| rho.  The pass of target layer k (2 <= k <= L) runs
+//     Lambda^(k-1) = rows of W_k,  for j = k-1 .. 1:
+//       sel = (Lambda >= 0) for the upper pass, (Lambda < 0) for the lower one
+//       Omega_j = Lambda^(j) (.) S_j,  S_j = sel ? s_j : a_j
+//       beta += sum sel Lambda^(j) t_j + Omega_j b_j,  Lambda^(j-1) = Omega_j W_j
+// with the relaxation s = u/(u-l), t = -s l, a = [u >= -l] of each unstable
+// neuron (identity / zero for stable ones), and concretises
+// Lambda^(0) c +/- |Lambda^(0)| rho + beta (k < L: bounds of layer k; k = L:
+// Theorem 2 with Lambda^(0) - J in place of Lambda^(0)).
+//
+// Reverse.  With the row seeds y (g_hi / g_lo for k = L, the adjoints of the
+// bounds u_k / l_k otherwise), the adjoint of one pass is
+//     Lambda-bar^(0) = y (c +/- sign(D) rho),  c-bar += D^T y,  rho-bar +/-= |D|^T y
+//     for j = 1 .. k-1:
+//       Omega-bar_j = Lambda-bar^(j-1) W_j^T + y b_j^T
+//       s-bar_j += sum_rows sel Omega-bar_j Lambda^(j),  t-bar_j += sum_rows sel y Lambda^(j)
+//       Lambda-bar^(j) = Omega-bar_j (.) S_j + sel y t_j      (j < k-1)
+// (D = Lambda^(0) - J for k = L, Lambda^(0) otherwise), and the relaxation
+// adjoint of an unstable neuron is
+//     u-bar = (-l s-bar + l^2 t-bar) / (u-l)^2,  l-bar = (u s-bar - u^2 t-bar) / (u-l)^2.
+// Passes run from k = L down to 2: the bounds of layer j receive adjoints
+// only from passes with k > j, so each layer's adjoint is complete when its
+// own pass is reversed.  J a~ - g(a~) has derivative 0 (J is locally constant).
+//
+// GPU design.  One workgroup of 256 lanes per (box, pass direction); the
+// target rows go in blocks of 8.  Lane q owns neuron column q of every level:
+// it keeps Lambda^(j) of its column in registers for the reverse sweep, so
+// the forward chain of a block is recomputed once and never stored.  The
+// operand of each row-block product (8 rows x up to 256 neurons) is staged in
+// LDS in [neuron][row] order, so a lane reads one row set with wide LDS loads
+// and multiplies it by one weight from L2 (W_j forward, W_j^T in reverse,
+// both row-major and coalesced across lanes).  Narrow outputs (input layer)
+// split the sum over lane slices and add the slices in a fixed order.  The
+// per-neuron sums s-bar, t-bar, c-bar, rho-bar stay in the owning lane
+// across blocks; later passes add to them in launch order, so the result is
+// deterministic.  FP64 on the VALU: the adjoint is a sequence of narrow
+// (8-row) products, one block at a time.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "leb.h"
+#include "leb_internal.hpp"
+#include "nn_net.hpp"
+
+namespace leb {
+
+constexpr int NB_R = 8;          // target rows per block
+constexpr int NB_T = 256;        // lanes per workgroup
+constexpr int NB_CHUNK = 512;    // boxes per chunk of the workspace
+
+struct NbArgs {
+    int L;
+    int w[NN_MAXL + 1];
+    const double* W[NN_MAXL];
+    const double* WT[NN_MAXL];
+    const double* b[NN_MAXL];
+    int nx, nu;
+    int k;                         // target layer of a pass; layer of a relaxation adjoint
+    int64_t u0;                    // first unit of the chunk
+    const double* z; const double* v; const double* mu; const double* sigma;
+    const double* g_lo; const double* g_hi;
+    double* gz; double* gv; double* gmu; double* gsigma;
+    // chunk workspace (box-major)
+    double* cr;                    // [box][2][NN_MAXW]          c, rho
+    double* zn;                    // [box][NN_MAXL][NN_MAXW]    nominal pre-activations of hidden layer j (index j-1)
+    double* bd;                    // [box][NN_MAXL][2][NN_MAXW] lo, hi of hidden layer j
+    double* st;                    // [box][2][NN_MAXL][2][NN_MAXW] s-bar, t-bar per pass direction
+    double* ub;                    // [box][NN_MAXL][2][NN_MAXW] u-bar, l-bar of hidden layer j
+    double* cg;                    // [box][2][2][NN_MAXW]       c-bar, rho-bar per pass direction
+    uint32_t* ok;                  // [box] 1: valid input
+};
+
+__device__ __forceinline__ size_t ix_cr(int box, int which) { return ((size_t)box * 2 + which) * NN_MAXW; }
+__device__ __forceinline__ size_t ix_zn(int box, int j) { return ((size_t)box * NN_MAXL + j - 1) * NN_MAXW; }
+__device__ __forceinline__ size_t ix_bd(int box, int j, int hi) {
+    return (((size_t)box * NN_MAXL + j - 1) * 2 + hi) * NN_MAXW;
+}
+__device__ __forceinline__ size_t ix_st(int box, int mode, int j, int which) {
+    return ((((size_t)box * 2 + mode) * NN_MAXL + j - 1) * 2 + which) * NN_MAXW;
+}
+__device__ __forceinline__ size_t ix_ub(int box, int j, int which) {
+    return (((size_t)box * NN_MAXL + j - 1) * 2 + which) * NN_MAXW;
+}
+__device__ __forceinline__ size_t ix_cg(int box, int mode, int which) {
+    return (((size_t)box * 2 + mode) * 2 + which) * NN_MAXW;
+}
+
+// ReLU relaxation of a neuron with pre-activation bounds [lo, hi]: upper
+// line s z + t, lower line a z
+__device__ __forceinline__ void nb_relax(double lo, double hi, double& s, double& t, double& a) {
+    if (lo >= 0.0) { s = 1.0; t = 0.0; a = 1.0; }
+    else if (hi > 0.0) { s = hi / (hi - lo); t = -s * lo; a = hi >= -lo ? 1.0 : 0.0; }
+    else { s = 0.0; t = 0.0; a = 0.0; }
+}
+
+// out[r][i] = sum_{p < len} X[p][r] M[p nc + i] for i < nc, X in LDS as [p][NB_R];
+// lane q < nc receives column q.  Narrow outputs split p over 256 / nc lane
+// slices, added in slice order.  Every lane must call it (it may hold a barrier).
+__device__ __forceinline__ void nb_rowmat(const double* __restrict__ M, int nc, int len, const double* sX,
+                                          double* sP, int q, double acc[NB_R]) {
+    const int S = nc >= NB_T ? 1 : NB_T / nc;
+    const int i = q % nc, sl = q / nc;
+#pragma unroll
+    for (int r = 0; r < NB_R; ++r) acc[r] = 0.0;
+    if (sl < S) {
+        const int p0 = (int)(((int64_t)sl * len) / S), p1 = (int)(((int64_t)(sl + 1) * len) / S);
+        const double* Mi = M + i;
+#pragma unroll 4
+        for (int p = p0; p < p1; ++p) {
+            const double w = Mi[(size_t)p * nc];
+            const double* x = sX + p * NB_R;
+#pragma unroll
+            for (int r = 0; r < NB_R; ++r) acc[r] = __builtin_fma(x[r], w, acc[r]);
+        }
+    }
+    if (S > 1) {
+        if (sl >= 1 && sl < S) {
+#pragma unroll
+            for (int r = 0; r < NB_R; ++r) sP[((sl - 1) * nc + i) * NB_R + r] = acc[r];
+        }
+        lds_barrier();
+        if (q < nc) {
+            for (int s2 = 1; s2 < S; ++s2) {
+#pragma unroll
+                for (int r = 0; r < NB_R; ++r) acc[r] += sP[((s2 - 1) * nc + q) * NB_R + r];
+            }
+        }
+    }
+}
+
+// per box: validity, the box (c, rho), nominal pre-activations, layer-1
+// bounds, and zeroed adjoint sums
+__global__ void __launch_bounds__(NB_T) nb_box_kernel(NbArgs A) {
+    __shared__ double s_a[NN_MAXW], s_c[NN_MAXW], s_r[NN_MAXW];
+    __shared__ uint32_t s_bad;
+    const int box = blockIdx.x, q = threadIdx.x;
+    const int64_t unit = A.u0 + box;
+    const int n0 = A.w[0], L = A.L;
+    if (q == 0) s_bad = 0;
+    __syncthreads();
+    if (q < n0) {
+        const double x = q < A.nx ? A.z[unit * A.nx + q] : A.v[unit * A.nu + (q - A.nx)];
+        const double sg = A.sigma[unit * n0 + q];
+        const double mu = A.mu ? A.mu[unit * n0 + q] : 0.0;
+        if (!isfinite(x) || !isfinite(sg) || !isfinite(mu) || !(sg >= 0.0)) atomicOr(&s_bad, 1u);
+        const double dlo = fmin(mu - sg, 0.0), dhi = fmax(mu + sg, 0.0);
+        s_a[q] = x;
+        s_c[q] = x + 0.5 * (dlo + dhi);
+        s_r[q] = 0.5 * (dhi - dlo);
+        A.cr[ix_cr(box, 0) + q] = s_c[q];
+        A.cr[ix_cr(box, 1) + q] = s_r[q];
+    }
+    // zero the adjoint sums of this box
+    for (int j = 1; j < L; ++j)
+        for (int md = 0; md < 2; ++md)
+            for (int wh = 0; wh < 2; ++wh) A.st[ix_st(box, md, j, wh) + q] = 0.0;
+    for (int md = 0; md < 2; ++md)
+        for (int wh = 0; wh < 2; ++wh) A.cg[ix_cg(box, md, wh) + q] = 0.0;
+    __syncthreads();
+    if (q == 0) A.ok[box] = s_bad ? 0u : 1u;
+    const int n1 = A.w[1];
+    if (q < n1) {
+        const double* Wr = A.W[0] + (size_t)q * n0;
+        double lin = A.b[0][q], mag = 0.0;
+        for (int p = 0; p < n0; ++p) {
+            lin = __builtin_fma(Wr[p], s_c[p], lin);
+            mag = __builtin_fma(fabs(Wr[p]), s_r[p], mag);
+        }
+        A.bd[ix_bd(box, 1, 0) + q] = lin - mag;
+        A.bd[ix_bd(box, 1, 1) + q] = lin + mag;
+    }
+    // nominal pre-activations of the hidden layers (the masks of J)
+    for (int l = 0; l < L - 1; ++l) {
+        const int in = A.w[l], out = A.w[l + 1];
+        double zz = 0.0;
+        if (q < out) {
+            zz = A.b[l][q];
+            const double* WT = A.WT[l];
+            for (int p = 0; p < in; ++p) zz = __builtin_fma(WT[(size_t)p * out + q], s_a[p], zz);
+        }
+        __syncthreads();
+        if (q < out) {
+            A.zn[ix_zn(box, l + 1) + q] = zz;
+            s_a[q] = zz > 0.0 ? zz : 0.0;
+        }
+        __syncthreads();
+    }
+}
+
+// One CROWN pass of target layer A.k for one box (blockIdx.x) and direction
+// (blockIdx.y: 0 upper, 1 lower).  REV = false: the bounds of layer k
+// (hi for the upper pass, lo for the lower one).  REV = true: the adjoint of
+// the pass, added to the per-neuron sums.  LV >= k - 1: levels kept per lane.
+template <bool REV, int LV>
+__global__ void __launch_bounds__(NB_T) nb_pass_kernel(NbArgs A) {
+    __shared__ __attribute__((aligned(16))) double sX[NN_MAXW * NB_R];
+    __shared__ __attribute__((aligned(16))) double sP[NN_MAXW * NB_R];
+    __shared__ double sRed[NB_T / 64][NB_R];
+    const int box = blockIdx.x, mode = blockIdx.y, q = threadIdx.x;
+    if (!A.ok[box]) return;
+    const bool upper = mode == 0;
+    const double sgn = upper ? 1.0 : -1.0;
+    const int k = A.k, L = A.L, n0 = A.w[0];
+    const int rows = A.w[k], nk1 = A.w[k - 1];
+    const double* Wk = A.W[k - 1];
+    const double cq = q < n0 ? A.cr[ix_cr(box, 0) + q] : 0.0;
+    const double rq = q < n0 ? A.cr[ix_cr(box, 1) + q] : 0.0;
+    double sacc[LV], tacc[LV];
+#pragma unroll
+    for (int j = 0; j < LV; ++j) { sacc[j] = 0.0; tacc[j] = 0.0; }
+    double cacc = 0.0, racc = 0.0;
+
+    for (int r0 = 0; r0 < rows; r0 += NB_R) {
+        const int nr = min(NB_R, rows - r0);
+        double lam[LV][NB_R];                   // Lambda^(j) of column q, j = 0 .. k-2
+        double bpart[NB_R];
+#pragma unroll
+        for (int r = 0; r < NB_R; ++r) bpart[r] = 0.0;
+        // ---- forward chain of the block, j = k-1 .. 1
+#pragma unroll
+        for (int j = LV; j >= 1; --j) {
+            if (j > k - 1) continue;
+            const int nj = A.w[j];
+            if (q < nj) {
+                double s, t, a;
+                nb_relax(A.bd[ix_bd(box, j, 0) + q], A.bd[ix_bd(box, j, 1) + q], s, t, a);
+                const double bj = A.b[j - 1][q];
+#pragma unroll
+                for (int r = 0; r < NB_R; ++r) {
+                    double lm;
+                    if (j == k - 1) lm = r < nr ? Wk[(size_t)(r0 + r) * nk1 + q] : 0.0;
+                    else lm = lam[j < LV ? j : 0][r];     // j < LV whenever j < k - 1
+                    const bool sel = upper ? lm >= 0.0 : lm < 0.0;
+                    const double om = lm * (sel ? s : a);
+                    if (!REV) bpart[r] += (sel ? lm * t : 0.0) + om * bj;
+                    sX[q * NB_R + r] = om;
+                }
+            }
+            lds_barrier();
+            double acc[NB_R];
+            nb_rowmat(A.W[j - 1], A.w[j - 1], nj, sX, sP, q, acc);
+            if (q < A.w[j - 1]) {
+#pragma unroll
+                for (int r = 0; r < NB_R; ++r) lam[j - 1][r] = acc[r];
+            }
+            lds_barrier();
+        }
+        if (!REV) {
+            // concretise: row value = b_k + beta parts + Lambda^(0) c +/- |Lambda^(0)| rho
+            if (q < n0) {
+#pragma unroll
+                for (int r = 0; r < NB_R; ++r) bpart[r] += lam[0][r] * cq + sgn * fabs(lam[0][r]) * rq;
+            }
+            const int wv = q >> 6;
+#pragma unroll
+            for (int r = 0; r < NB_R; ++r) {
+                double x = bpart[r];
+#pragma unroll
+                for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
+                if ((q & 63) == 0) sRed[wv][r] = x;
+            }
+            lds_barrier();
+            if (q < nr) {
+                double x = A.b[k - 1][r0 + q];
+                for (int w2 = 0; w2 < NB_T / 64; ++w2) x += sRed[w2][q];
+                A.bd[ix_bd(box, k, upper ? 1 : 0) + r0 + q] = x;
+            }
+            lds_barrier();
+            continue;
+        }
+        // ---- reverse sweep of the block
+        double y[NB_R];
+#pragma unroll
+        for (int r = 0; r < NB_R; ++r) {
+            double yy = 0.0;
+            if (r < nr) {
+                if (k == L) yy = (upper ? A.g_hi : A.g_lo)[(A.u0 + box) * rows + r0 + r];
+                else yy = A.ub[ix_ub(box, k, upper ? 0 : 1) + r0 + r];
+            }
+            y[r] = yy;
+        }
+        double jv[NB_R];
+#pragma unroll
+        for (int r = 0; r < NB_R; ++r) jv[r] = 0.0;
+        if (k == L) {
+            // the rows of J = W_L D_{L-1} W_{L-1} ... D_1 W_1 (D = [z^ > 0]) for this block
+#pragma unroll
+            for (int r = 0; r < NB_R; ++r) jv[r] = (q < nk1 && r < nr) ? Wk[(size_t)(r0 + r) * nk1 + q] : 0.0;
+            for (int j = L - 1; j >= 1; --j) {
+                const int nj = A.w[j];
+                if (q < nj) {
+                    const double on = A.zn[ix_zn(box, j) + q] > 0.0 ? 1.0 : 0.0;
+#pragma unroll
+                    for (int r = 0; r < NB_R; ++r) sX[q * NB_R + r] = jv[r] * on;
+                }
+                lds_barrier();
+                nb_rowmat(A.W[j - 1], A.w[j - 1], nj, sX, sP, q, jv);
+                lds_barrier();
+            }
+        }
+        // seeds of Lambda^(0) and the direct c / rho terms
+        if (q < n0) {
+#pragma unroll
+            for (int r = 0; r < NB_R; ++r) {
+                const double d = lam[0][r] - jv[r];
+                const double sd = d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0);
+                cacc += y[r] * d;
+                racc += sgn * y[r] * fabs(d);
+                sX[q * NB_R + r] = y[r] * (cq + sgn * sd * rq);
+            }
+        }
+        lds_barrier();
+#pragma unroll
+        for (int j = 1; j <= LV; ++j) {
+            if (j > k - 1) continue;
+            const int nj = A.w[j];
+            double ob[NB_R];
+            nb_rowmat(A.WT[j - 1], nj, A.w[j - 1], sX, sP, q, ob);
+            lds_barrier();                      // sX is rewritten below
+            if (q < nj) {
+                double s, t, a;
+                nb_relax(A.bd[ix_bd(box, j, 0) + q], A.bd[ix_bd(box, j, 1) + q], s, t, a);
+                const double bj = A.b[j - 1][q];
+                double sa = 0.0, ta = 0.0;
+#pragma unroll
+                for (int r = 0; r < NB_R; ++r) {
+                    double lm;
+                    if (j == k - 1) lm = r < nr ? Wk[(size_t)(r0 + r) * nk1 + q] : 0.0;
+                    else lm = lam[j < LV ? j : 0][r];     // j < LV whenever j < k - 1
+                    const bool sel = upper ? lm >= 0.0 : lm < 0.0;
+                    const double obr = ob[r] + y[r] * bj;
+                    if (sel) {
+                        sa += obr * lm;
+                        ta += y[r] * lm;
+                    }
+                    if (j < k - 1) sX[q * NB_R + r] = obr * (sel ? s : a) + (sel ? y[r] * t : 0.0);
+                }
+                sacc[j - 1] += sa;
+                tacc[j - 1] += ta;
+            }
+            lds_barrier();
+        }
+    }
+    if (REV) {
+#pragma unroll
+        for (int j = 1; j <= LV; ++j) {
+            if (j > k - 1) continue;
+            if (q < A.w[j]) {
+                A.st[ix_st(box, mode, j, 0) + q] += sacc[j - 1];
+                A.st[ix_st(box, mode, j, 1) + q] += tacc[j - 1];
+            }
+        }
+        if (q < n0) {
+            A.cg[ix_cg(box, mode, 0) + q] += cacc;
+            A.cg[ix_cg(box, mode, 1) + q] += racc;
+        }
+    }
+}
+
+// adjoints u-bar, l-bar of the bounds of hidden layer A.k from s-bar, t-bar
+// (both pass directions, added in a fixed order)
+__global__ void __launch_bounds__(NB_T) nb_radj_kernel(NbArgs A) {
+    const int box = blockIdx.x, q = threadIdx.x, j = A.k;
+    if (!A.ok[box] || q >= A.w[j]) return;
+    const double sb = A.st[ix_st(box, 0, j, 0) + q] + A.st[ix_st(box, 1, j, 0) + q];
+    const double tb = A.st[ix_st(box, 0, j, 1) + q] + A.st[ix_st(box, 1, j, 1) + q];
+    const double lo = A.bd[ix_bd(box, j, 0) + q], hi = A.bd[ix_bd(box, j, 1) + q];
+    double ubar = 0.0, lbar = 0.0;
+    if (lo < 0.0 && hi > 0.0) {
+        const double den = hi - lo, d2 = den * den;
+        ubar = (-lo * sb + lo * lo * tb) / d2;
+        lbar = (hi * sb - hi * hi * tb) / d2;
+    }
+    A.ub[ix_ub(box, j, 0) + q] = ubar;
+    A.ub[ix_ub(box, j, 1) + q] = lbar;
+}
+
+// per box: c-bar, rho-bar (pass sums plus the layer-1 bounds), then the box
+// and its clamps back to a~, sigma, mu
+__global__ void __launch_bounds__(NB_T) nb_out_kernel(NbArgs A) {
+    const int box = blockIdx.x, q = threadIdx.x;
+    const int64_t unit = A.u0 + box;
+    const int n0 = A.w[0], n1 = A.w[1];
+    if (q >= n0) return;
+    double ga = 0.0, gs = 0.0, gm = 0.0;
+    if (A.ok[box]) {
+        double cb = A.cg[ix_cg(box, 0, 0) + q] + A.cg[ix_cg(box, 1, 0) + q];
+        double rb = A.cg[ix_cg(box, 0, 1) + q] + A.cg[ix_cg(box, 1, 1) + q];
+        const double* uu = A.ub + ix_ub(box, 1, 0);
+        const double* ll = A.ub + ix_ub(box, 1, 1);
+        const double* W1 = A.W[0];
+        for (int i = 0; i < n1; ++i) {
+            const double w = W1[(size_t)i * n0 + q];
+            cb = __builtin_fma(w, uu[i] + ll[i], cb);
+            rb = __builtin_fma(fabs(w), uu[i] - ll[i], rb);
+        }
+        const double sg = A.sigma[unit * n0 + q];
+        const double mu = A.mu ? A.mu[unit * n0 + q] : 0.0;
+        const double dlo_b = 0.5 * (cb - rb), dhi_b = 0.5 * (cb + rb);
+        const bool lo_on = mu - sg < 0.0, hi_on = mu + sg > 0.0;
+        ga = cb;
+        gs = (lo_on ? -dlo_b : 0.0) + (hi_on ? dhi_b : 0.0);
+        gm = (lo_on ? dlo_b : 0.0) + (hi_on ? dhi_b : 0.0);
+    }
+    if (q < A.nx) A.gz[unit * A.nx + q] = ga;
+    else A.gv[unit * A.nu + (q - A.nx)] = ga;
+    A.gsigma[unit * n0 + q] = gs;
+    if (A.gmu) A.gmu[unit * n0 + q] = gm;
+}
+
+struct NbWorkspace {
+    std::mutex mu;
+    void* buf = nullptr;
+    size_t cap = 0;
+    WsFence fence;
+};
+static NbWorkspace g_nbws;
+
+template <bool REV>
+static void nb_launch_pass(const NbArgs& a, int nb, hipStream_t st) {
+    const dim3 grid((unsigned)nb, 2u);
+    if (a.L - 1 <= 3) hipLaunchKernelGGL((nb_pass_kernel<REV, 3>), grid, dim3(NB_T), 0, st, a);
+    else hipLaunchKernelGGL((nb_pass_kernel<REV, NN_MAXL - 1>), grid, dim3(NB_T), 0, st, a);
+}
+
+extern "C" int leb_nn_backward(leb_mlp net, int32_t batch, int32_t N, const double* z, const double* v,
+                               const double* mu, const double* sigma, const double* g_lo, const double* g_hi,
+                               double* gz, double* gv, double* gmu, double* gsigma, void* stream) {
+    if (!net) return LEB_EINVAL;
+    if (batch < 0 || N < 0) return LEB_EINVAL;
+    if (gmu && !mu) return LEB_EINVAL;
+    const int64_t units = (int64_t)batch * N;
+    if (units == 0) return LEB_OK;
+    const int nx = net->nx, nu = net->nu;
+    if (!sigma || !g_lo || !g_hi || !gsigma || (nx > 0 && (!z || !gz)) || (nu > 0 && (!v || !gv)))
+        return LEB_EINVAL;
+    const void* ptrs[] = {z, v, mu, sigma, g_lo, g_hi, gz, gv, gmu, gsigma};
+    for (const void* p : ptrs)
+        if (p && !aligned8(p)) return LEB_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const int CB = (int)(units < NB_CHUNK ? units : NB_CHUNK);
+    // per box: cr 2, zn L, bd 2L, st 4L, ub 2L, cg 4 rows of NN_MAXW doubles, plus the flag
+    const size_t per_box = (size_t)NN_MAXW * (2 + 9 * NN_MAXL + 4);
+    const size_t need = (size_t)CB * per_box * sizeof(double) + (size_t)CB * sizeof(uint32_t);
+    std::lock_guard<std::mutex> lock(g_nbws.mu);
+    if (need > g_nbws.cap) {
+        if (g_nbws.buf) (void)hipFree(g_nbws.buf);
+        g_nbws.buf = nullptr;
+        g_nbws.cap = 0;
+        if (getenv("LEB_TEST_FAIL_ALLOC") || hipMalloc(&g_nbws.buf, need) != hipSuccess) return LEB_ENOMEM;
+        g_nbws.cap = need;
+    }
+    int rc;
+    if ((rc = g_nbws.fence.enter(st))) return rc;
+    WsFenceScope leave{g_nbws.fence, st};
+    NbArgs a;
+    memset(&a, 0, sizeof(a));
+    a.L = net->L;
+    for (int l = 0; l <= net->L; ++l) a.w[l] = net->w[l];
+    for (int l = 0; l < net->L; ++l) { a.W[l] = net->W[l]; a.WT[l] = net->WT[l]; a.b[l] = net->b[l]; }
+    a.nx = nx; a.nu = nu;
+    a.z = z; a.v = v; a.mu = mu; a.sigma = sigma; a.g_lo = g_lo; a.g_hi = g_hi;
+    a.gz = gz; a.gv = gv; a.gmu = gmu; a.gsigma = gsigma;
+    double* p = (double*)g_nbws.buf;
+    a.cr = p; p += (size_t)CB * 2 * NN_MAXW;
+    a.zn = p; p += (size_t)CB * NN_MAXL * NN_MAXW;
+    a.bd = p; p += (size_t)CB * NN_MAXL * 2 * NN_MAXW;
+    a.st = p; p += (size_t)CB * 2 * NN_MAXL * 2 * NN_MAXW;
+    a.ub = p; p += (size_t)CB * NN_MAXL * 2 * NN_MAXW;
+    a.cg = p; p += (size_t)CB * 2 * 2 * NN_MAXW;
+    a.ok = (uint32_t*)p;
+    const int L = net->L;
+    for (int64_t u0 = 0; u0 < units; u0 += CB) {
+        const int nb = (int)((units - u0) < CB ? (units - u0) : CB);
+        a.u0 = u0;
+        hipLaunchKernelGGL(nb_box_kernel, dim3((unsigned)nb), dim3(NB_T), 0, st, a);
+        for (int k = 2; k < L; ++k) {
+            a.k = k;
+            nb_launch_pass<false>(a, nb, st);
+        }
+        a.k = L;
+        nb_launch_pass<true>(a, nb, st);
+        for (int j = L - 1; j >= 1; --j) {
+            a.k = j;
+            hipLaunchKernelGGL(nb_radj_kernel, dim3((unsigned)nb), dim3(NB_T), 0, st, a);
+            if (j >= 2) nb_launch_pass<true>(a, nb, st);
+        }
+        hipLaunchKernelGGL(nb_out_kernel, dim3((unsigned)nb), dim3(NB_T), 0, st, a);
+    }
+    return hipGetLastError() == hipSuccess ? LEB_OK : LEB_EDEVICE;
+}
+
+}  // namespace leb

@@ -122,6 +122,13 @@ def test_nn_bound_rejects_misaligned_jacobian_without_launching(L):
                           None) == -1
 
 
+def test_nn_backward_rejects_null_network_without_launching(L):
+    vp = ctypes.c_void_p
+    # leb_nn_backward(net, batch, N, z, v, mu, sigma, g_lo, g_hi, gz, gv, gmu, gsigma, stream)
+    assert L.leb_nn_backward(None, 1, 1, vp(8), vp(8), None, vp(8), vp(8), vp(8), vp(8), vp(8), None, vp(8),
+                             None) == -1
+
+
 def test_empty_problem_is_ok_without_launching(L):
     import paper_2607_01203_amd as leb
     d = leb.chain_dynamics(3)
