@@ -29,7 +29,8 @@ Prints ONE JSON line.  Extra objects:
                   point on a bounded sample of trajectories, on all host
                   cores and on one;
   latency, adjoint, batched_uneven (batch against per-problem launches),
-  roofline_nn, learned_nn, nominal_pgd (nominal points refined by projected
+  roofline_nn, nn_adjoint (the MLP bound's gradient, against the bound's own
+  time), learned_nn, nominal_pgd (nominal points refined by projected
   gradient descent on the bound's width against random nominal points at
   an equal GPU time budget), interval_hessian_study (satellite and 3-D
   quadrotor: mean row width of the path, expanded and classic enclosures and
@@ -147,7 +148,8 @@ def main():
 
     dev = torch.device("cuda:0")
     if args.nn_only:
-        print(json.dumps({"roofline_nn": nn_roofline(leb, W, dev, torch.cuda.current_stream(), args)}))
+        st = torch.cuda.current_stream()
+        print(json.dumps({"roofline_nn": nn_roofline(leb, W, dev, st, args), "nn_adjoint": nn_adjoint(leb, W, dev, st)}))
         return
     if args.m2_only:
         print(json.dumps({"roofline_bound": plain_m2(leb, W, dev, torch.cuda.current_stream(), args)}))
@@ -266,6 +268,7 @@ def main():
         "interval_hessian_study": interval_hessian_study(leb, W, dev, stream),
         "sls_update": sls_update(leb, W, dev, stream),
         "roofline_nn": nn_roofline(leb, W, dev, stream, args),
+        "nn_adjoint": nn_adjoint(leb, W, dev, stream),
         "learned_nn": nn_learned(leb, W, dev, stream, args),
         "batched_uneven": batched_uneven(leb, W, dev, stream, args)}
 
@@ -640,6 +643,65 @@ def nn_roofline(leb, W, dev, stream, args):
             "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "flops_per_box": nn_crown_flops(widths),
             "executed_frac": None if NN_MFMA_INSTS_PER_BOX is None else
             round(NN_MFMA_INSTS_PER_BOX * 2048 * boxes / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)}
+
+
+def nn_adjoint_flops(widths):
+    """(algorithmic, executed) FLOPs per box of the MLP bound's adjoint.
+    Algorithmic: the bound's own passes (nn_crown_flops) plus the reverse of
+    every pass in both modes, each as large as the pass.  Executed: the
+    kernels also recompute each reversed pass's forward chain and the
+    Jacobian rows once per mode instead of storing them."""
+    L = len(widths) - 1
+    chain = lambda k: sum(widths[k] * widths[j] * widths[j - 1] for j in range(k - 1, 0, -1))
+    rev = sum(2 * chain(k) for k in range(2, L + 1))
+    fwd_hidden = sum(2 * chain(k) for k in range(2, L))
+    executed = fwd_hidden + 2 * rev + 2 * chain(L)
+    return nn_crown_flops(widths) + 2 * rev, 2 * executed
+
+
+def nn_adjoint(leb, W, dev, stream):
+    """Adjoint of the MLP bound (leb_nn_backward) on the 64 x 50 boxes of the
+    16-256-256-256-12 network, seeds g_lo = -1, g_hi = 1 (the gradient of the
+    bound's total width); FP64 on the VALU, timed with HIP events on its stream."""
+    import torch
+    b = W.nn_cfg()
+    net = leb.MLP(b.net.W, b.net.b, b.net.nx, True)
+    z = torch.from_numpy(b.z).to(dev)
+    v = torch.from_numpy(b.v).to(dev)
+    sg = torch.from_numpy(b.sigma).to(dev)
+    boxes = b.z.shape[0] * b.z.shape[1]
+    m = b.net.W[-1].shape[0]
+    g_hi = torch.ones((b.z.shape[0], b.z.shape[1], m), dtype=torch.float64, device=dev)
+    g_lo = -g_hi
+    for _ in range(2):
+        leb.nn_backward(net, z, v, sg, g_lo, g_hi, stream=stream)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record(stream)
+    for _ in range(reps):
+        leb.nn_backward(net, z, v, sg, g_lo, g_hi, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    for _ in range(2):
+        leb.nn_bound(net, z, v, sg, stream=stream)
+    e0.record(stream)
+    for _ in range(reps):
+        leb.nn_bound(net, z, v, sg, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_bound = e0.elapsed_time(e1) / reps
+    net.close()
+    widths = [b.net.W[0].shape[1]] + [w.shape[0] for w in b.net.W]
+    alg, exe = nn_adjoint_flops(widths)
+    achieved = alg * boxes / (ms * 1e-3) / 1e12
+    return {"workload": "MLP-bound adjoint, 64 x 50 boxes, widths %s" % widths, "ms_per_call": round(ms, 4),
+            "box_gradients_per_s": round(boxes / (ms * 1e-3), 1), "ms_bound": round(ms_bound, 4),
+            "over_bound": round(ms / ms_bound, 3), "bound": "valu", "achieved": round(achieved, 2),
+            "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+            "flops_per_box": alg, "executed_flops_per_box": exe,
+            "executed_frac": round(exe * boxes / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)}
 
 
 def nn_learned(leb, W, dev, stream, args):

@@ -284,8 +284,10 @@ int leb_nn_bound(leb_mlp net, int32_t batch, int32_t N, const double* z, const d
  * Units with invalid data (non-finite input, sigma < 0) get a zero gradient.
  * Every pass is recomputed (nothing of leb_nn_bound is reused), in FP64.
  * Deterministic: every sum is taken in a fixed order.  Uses a library-owned
- * grow-only workspace (about 80 MB), ordered across streams like the other
- * workspaces.  LEB_EINVAL for null or misaligned pointers or gmu without mu.
+ * grow-only workspace of up to about 1.1 GB (it holds the CROWN coefficients
+ * of the hidden-layer passes of up to 512 boxes; deep, wide networks take
+ * fewer boxes at a time), ordered across streams like the other workspaces.
+ * LEB_EINVAL for null or misaligned pointers or gmu without mu.
  */
 int leb_nn_backward(leb_mlp net, int32_t batch, int32_t N, const double* z, const double* v, const double* mu,
                     const double* sigma, const double* g_lo, const double* g_hi, double* gz, double* gv,

@@ -35,9 +35,11 @@
 // own pass is reversed.  J a~ - g(a~) has derivative 0 (J is locally constant).
 //
 // GPU design.  One workgroup of 256 lanes per (box, pass direction); the
-// target rows go in blocks of 8.  Lane q owns neuron column q of every level:
-// it keeps Lambda^(j) of its column in registers for the reverse sweep, so
-// the forward chain of a block is recomputed once and never stored.  The
+// target rows go in blocks of 8.  Lane q owns neuron column q of every level
+// and keeps Lambda^(j) of its column in registers for the reverse sweep.  The
+// forward pass of a hidden layer stores its levels (coalesced, [row][column])
+// and the reverse pass of that layer loads them; the output pass, which has
+// no forward launch of its own, recomputes its chain.  The
 // operand of each row-block product (8 rows x up to 256 neurons) is staged in
 // LDS in [neuron][row] order, so a lane reads one row set with wide LDS loads
 // and multiplies it by one weight from L2 (W_j forward, W_j^T in reverse,
@@ -64,7 +66,9 @@ namespace leb {
 
 constexpr int NB_R = 8;          // target rows per block
 constexpr int NB_T = 256;        // lanes per workgroup
-constexpr int NB_CHUNK = 512;    // boxes per chunk of the workspace
+constexpr int NB_CHUNK = 512;    // most boxes per chunk of the workspace
+constexpr int NB_CHUNK_MIN = 32; // fewest (deep, wide networks)
+constexpr size_t NB_LV_BUDGET = (size_t)1 << 30;   // workspace bytes that set the chunk size
 
 struct NbArgs {
     int L;
@@ -86,6 +90,9 @@ struct NbArgs {
     double* ub;                    // [box][NN_MAXL][2][NN_MAXW] u-bar, l-bar of hidden layer j
     double* cg;                    // [box][2][2][NN_MAXW]       c-bar, rho-bar per pass direction
     uint32_t* ok;                  // [box] 1: valid input
+    double* lv;                    // [box][2][lv_bm] levels Lambda^(j) of the hidden-layer passes
+    size_t lv_bm;                  // doubles per (box, direction)
+    int lv_off[NN_MAXL][NN_MAXL];  // offset of level j of pass k: [row][column], w[k] x w[j]
 };
 
 __device__ __forceinline__ size_t ix_cr(int box, int which) { return ((size_t)box * 2 + which) * NN_MAXW; }
@@ -234,10 +241,22 @@ __global__ void __launch_bounds__(NB_T) nb_pass_kernel(NbArgs A) {
         double bpart[NB_R];
 #pragma unroll
         for (int r = 0; r < NB_R; ++r) bpart[r] = 0.0;
-        // ---- forward chain of the block, j = k-1 .. 1
+        double* lvb = A.lv + ((size_t)box * 2 + mode) * A.lv_bm;
+        if (REV && k < L) {
+            // the levels stored by this layer's forward pass
+#pragma unroll
+            for (int j = 0; j < LV; ++j) {
+                if (j > k - 2 || q >= A.w[j]) continue;
+                const double* src = lvb + A.lv_off[k][j] + (size_t)r0 * A.w[j] + q;
+#pragma unroll
+                for (int r = 0; r < NB_R; ++r) lam[j][r] = r < nr ? src[(size_t)r * A.w[j]] : 0.0;
+            }
+        }
+        // ---- forward chain of the block, j = k-1 .. 1 (every pass but the
+        // reverse of a hidden layer's)
 #pragma unroll
         for (int j = LV; j >= 1; --j) {
-            if (j > k - 1) continue;
+            if (j > k - 1 || (REV && k < L)) continue;
             const int nj = A.w[j];
             if (q < nj) {
                 double s, t, a;
@@ -260,6 +279,12 @@ __global__ void __launch_bounds__(NB_T) nb_pass_kernel(NbArgs A) {
             if (q < A.w[j - 1]) {
 #pragma unroll
                 for (int r = 0; r < NB_R; ++r) lam[j - 1][r] = acc[r];
+                if (!REV) {
+                    double* dst = lvb + A.lv_off[k][j - 1] + (size_t)r0 * A.w[j - 1] + q;
+#pragma unroll
+                    for (int r = 0; r < NB_R; ++r)
+                        if (r < nr) dst[(size_t)r * A.w[j - 1]] = acc[r];
+                }
             }
             lds_barrier();
         }
@@ -456,9 +481,22 @@ extern "C" int leb_nn_backward(leb_mlp net, int32_t batch, int32_t N, const doub
     for (const void* p : ptrs)
         if (p && !aligned8(p)) return LEB_EINVAL;
     hipStream_t st = (hipStream_t)stream;
-    const int CB = (int)(units < NB_CHUNK ? units : NB_CHUNK);
-    // per box: cr 2, zn L, bd 2L, st 4L, ub 2L, cg 4 rows of NN_MAXW doubles, plus the flag
-    const size_t per_box = (size_t)NN_MAXW * (2 + 9 * NN_MAXL + 4);
+    const int L = net->L;
+    // stored levels of the hidden-layer passes: level j of pass k is w[k] x w[j]
+    NbArgs a;
+    memset(&a, 0, sizeof(a));
+    size_t lv_bm = 0;
+    for (int k = 2; k < L; ++k)
+        for (int j = 0; j <= k - 2; ++j) {
+            a.lv_off[k][j] = (int)lv_bm;
+            lv_bm += (size_t)net->w[k] * net->w[j];
+        }
+    a.lv_bm = lv_bm;
+    // per box: cr 2, zn L, bd 2L, st 4L, ub 2L, cg 4 rows of NN_MAXW doubles, the levels, the flag
+    const size_t per_box = (size_t)NN_MAXW * (2 + 9 * NN_MAXL + 4) + 2 * lv_bm;
+    int64_t cb = (int64_t)(NB_LV_BUDGET / (per_box * sizeof(double)));
+    cb = cb < NB_CHUNK_MIN ? NB_CHUNK_MIN : (cb > NB_CHUNK ? NB_CHUNK : cb);
+    const int CB = (int)(units < cb ? units : cb);
     const size_t need = (size_t)CB * per_box * sizeof(double) + (size_t)CB * sizeof(uint32_t);
     std::lock_guard<std::mutex> lock(g_nbws.mu);
     if (need > g_nbws.cap) {
@@ -471,8 +509,6 @@ extern "C" int leb_nn_backward(leb_mlp net, int32_t batch, int32_t N, const doub
     int rc;
     if ((rc = g_nbws.fence.enter(st))) return rc;
     WsFenceScope leave{g_nbws.fence, st};
-    NbArgs a;
-    memset(&a, 0, sizeof(a));
     a.L = net->L;
     for (int l = 0; l <= net->L; ++l) a.w[l] = net->w[l];
     for (int l = 0; l < net->L; ++l) { a.W[l] = net->W[l]; a.WT[l] = net->WT[l]; a.b[l] = net->b[l]; }
@@ -486,8 +522,8 @@ extern "C" int leb_nn_backward(leb_mlp net, int32_t batch, int32_t N, const doub
     a.st = p; p += (size_t)CB * 2 * NN_MAXL * 2 * NN_MAXW;
     a.ub = p; p += (size_t)CB * NN_MAXL * 2 * NN_MAXW;
     a.cg = p; p += (size_t)CB * 2 * 2 * NN_MAXW;
+    a.lv = p; p += (size_t)CB * 2 * lv_bm;
     a.ok = (uint32_t*)p;
-    const int L = net->L;
     for (int64_t u0 = 0; u0 < units; u0 += CB) {
         const int nb = (int)((units - u0) < CB ? (units - u0) : CB);
         a.u0 = u0;
