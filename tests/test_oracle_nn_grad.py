@@ -156,3 +156,40 @@ def test_stable_box_has_zero_gradient():
     assert sum(nn.leb(Ws, bs, a, s, centred=False)["unstable"]) == 0
     ga, gs, gm = nn_grad.leb_grad(Ws, bs, a, s, None, np.ones(4), np.ones(4))
     assert np.abs(ga).max() < 1e-12 and np.abs(gs).max() < 1e-12 and not gm.any()
+
+
+def _fd_gap(Ws, bs, rng, n0, trials=6):
+    """Largest |forward-mode - central difference| over a few kink-free points."""
+    worst = 0.0
+    for _ in range(trials):
+        a = rng.normal(0, 1, n0)
+        s = rng.uniform(0.1, 0.5, n0)
+        m = rng.uniform(-0.3, 0.3, n0)
+        da, ds, dm = rng.normal(0, 1, n0), rng.normal(0, 1, n0), rng.normal(0, 1, n0)
+        _, _, dlo, dhi = nn_grad.leb_jvp(Ws, bs, a, s, m, da, ds, dm)
+        h = 5e-7
+        lp, hp = _bound(Ws, bs, a + h * da, s + h * ds, m + h * dm)
+        lm, hm = _bound(Ws, bs, a - h * da, s - h * ds, m - h * dm)
+        worst = max(worst, np.abs(dlo - (lp - lm) / (2 * h)).max(), np.abs(dhi - (hp - hm) / (2 * h)).max())
+    return worst
+
+
+@pytest.mark.parametrize("mistake", ["dt dropped", "ds sign", "drho dropped", "dc dropped"])
+def test_pins_catch_planted_mistakes(monkeypatch, mistake):
+    """A plausible slip in the tangent code (planted here, in the oracle, on
+    the CPU) moves the derivative far outside the finite-difference pin."""
+    rng_net = np.random.default_rng(51)
+    Ws, bs = _net(rng_net, [6, 16, 16, 16, 4])
+    assert _fd_gap(Ws, bs, np.random.default_rng(52), 6) < 1e-5
+    relax, conc = nn_grad._relax_t, nn_grad._conc_t
+    if mistake == "dt dropped":
+        monkeypatch.setattr(nn_grad, "_relax_t", lambda *a: (relax(*a)[0], (relax(*a)[1][0], 0 * relax(*a)[1][1])))
+    elif mistake == "ds sign":
+        monkeypatch.setattr(nn_grad, "_relax_t", lambda *a: (relax(*a)[0], (-relax(*a)[1][0], relax(*a)[1][1])))
+    elif mistake == "drho dropped":
+        monkeypatch.setattr(nn_grad, "_conc_t",
+                            lambda L, dL, b, db, c, dc, r, dr, up: conc(L, dL, b, db, c, dc, r, 0 * dr, up))
+    else:
+        monkeypatch.setattr(nn_grad, "_conc_t",
+                            lambda L, dL, b, db, c, dc, r, dr, up: conc(L, dL, b, db, c, 0 * dc, r, dr, up))
+    assert _fd_gap(Ws, bs, np.random.default_rng(52), 6) > 1e-3
