@@ -476,7 +476,43 @@ def _autograd_class():
     return LEBAnalytic
 
 
+def _autograd_nn_class():
+    import torch
+
+    class LEBNN(torch.autograd.Function):
+        """(z, v, sigma, mu) -> (r_lo, r_hi) of the MLP bound with the
+        hand-written adjoint (leb_nn_backward recomputes every pass)."""
+
+        @staticmethod
+        def forward(ctx, net_box, z, v, sigma, mu):
+            net = net_box[0]
+            out = nn_bound(net, z, v, sigma, mu)
+            ctx.net = net
+            ctx.has_mu = mu is not None
+            ctx.save_for_backward(z, v, sigma, mu if mu is not None else sigma)
+            return out["r_lo"], out["r_hi"]
+
+        @staticmethod
+        def backward(ctx, g_lo, g_hi):
+            z, v, sigma, mu = ctx.saved_tensors
+            mu = mu if ctx.has_mu else None
+            g = nn_backward(ctx.net, z, v, sigma, g_lo.contiguous(), g_hi.contiguous(), mu=mu)
+            return None, g["gz"], g["gv"], g["gsigma"], g.get("gmu")
+
+    return LEBNN
+
+
 _LEBAnalytic = None
+_LEBNN = None
+
+
+def leb_nn(net, z, v, sigma, mu=None):
+    """Differentiable MLP bound: returns (r_lo, r_hi) tensors that
+    back-propagate through leb_nn_backward."""
+    global _LEBNN
+    if _LEBNN is None:
+        _LEBNN = _autograd_nn_class()
+    return _LEBNN.apply((net,), z, v, sigma, mu)
 
 
 def leb_analytic(dyn: Dynamics, z, v, sigma, mu=None):

@@ -135,3 +135,22 @@ def test_nn_backward_invalid_boxes_and_determinism(gpu):
     assert rc == -1
     torch.cuda.synchronize()
     mlp.close()
+
+
+def test_nn_autograd_function(gpu):
+    """leb_nn: torch autograd through the MLP bound equals the direct adjoint."""
+    import torch
+    import paper_2607_01203_amd as leb
+    rng = W.rng_for(331)
+    net, z, v, sg, mu, g_lo, g_hi = _case(rng, [16, 64, 64, 12], 12, 2, 4, 0.05, 0.3, True)
+    mlp = leb.MLP(net.W, net.b, net.nx, True)
+    tz, tv, ts, tm = (_t(x, gpu).requires_grad_(True) for x in (z, v, sg, mu))
+    print("case: nn autograd", flush=True)
+    lo, hi = leb.leb_nn(mlp, tz, tv, ts, tm)
+    gl, gh = _t(g_lo, gpu), _t(g_hi, gpu)
+    (gl * lo + gh * hi).sum().backward()
+    g = leb.nn_backward(mlp, tz.detach(), tv.detach(), ts.detach(), gl, gh, mu=tm.detach())
+    torch.cuda.synchronize()
+    assert torch.equal(tz.grad, g["gz"]) and torch.equal(tv.grad, g["gv"])
+    assert torch.equal(ts.grad, g["gsigma"]) and torch.equal(tm.grad, g["gmu"])
+    mlp.close()
