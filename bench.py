@@ -648,21 +648,22 @@ def nn_roofline(leb, W, dev, stream, args):
 def nn_adjoint_flops(widths):
     """(algorithmic, executed) FLOPs per box of the MLP bound's adjoint.
     Algorithmic: the bound's own passes (nn_crown_flops) plus the reverse of
-    every pass in both modes, each as large as the pass.  Executed: the
-    kernels also recompute each reversed pass's forward chain and the
-    Jacobian rows once per mode instead of storing them."""
+    every pass in both modes, each as large as the pass.  Executed, MFMA form
+    (at most three hidden layers): a forward launch for every pass (the output
+    pass's too, to store its levels), the reverse of every pass, and the
+    Jacobian rows once per mode."""
     L = len(widths) - 1
     chain = lambda k: sum(widths[k] * widths[j] * widths[j - 1] for j in range(k - 1, 0, -1))
     rev = sum(2 * chain(k) for k in range(2, L + 1))
-    fwd_hidden = sum(2 * chain(k) for k in range(2, L))
-    executed = fwd_hidden + 2 * rev + 2 * chain(L)
+    fwd = sum(2 * chain(k) for k in range(2, L + 1))
+    executed = fwd + rev + 2 * chain(L)
     return nn_crown_flops(widths) + 2 * rev, 2 * executed
 
 
 def nn_adjoint(leb, W, dev, stream):
     """Adjoint of the MLP bound (leb_nn_backward) on the 64 x 50 boxes of the
     16-256-256-256-12 network, seeds g_lo = -1, g_hi = 1 (the gradient of the
-    bound's total width); FP64 on the VALU, timed with HIP events on its stream."""
+    bound's total width); FP64 MFMA products, timed with HIP events on its stream."""
     import torch
     b = W.nn_cfg()
     net = leb.MLP(b.net.W, b.net.b, b.net.nx, True)
@@ -698,7 +699,7 @@ def nn_adjoint(leb, W, dev, stream):
     achieved = alg * boxes / (ms * 1e-3) / 1e12
     return {"workload": "MLP-bound adjoint, 64 x 50 boxes, widths %s" % widths, "ms_per_call": round(ms, 4),
             "box_gradients_per_s": round(boxes / (ms * 1e-3), 1), "ms_bound": round(ms_bound, 4),
-            "over_bound": round(ms / ms_bound, 3), "bound": "valu", "achieved": round(achieved, 2),
+            "over_bound": round(ms / ms_bound, 3), "bound": "mfma", "achieved": round(achieved, 2),
             "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
             "flops_per_box": alg, "executed_flops_per_box": exe,
             "executed_frac": round(exe * boxes / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)}

@@ -400,6 +400,274 @@ __global__ void __launch_bounds__(NB_T) nb_pass_kernel(NbArgs A) {
     }
 }
 
+// ---------------------------------------------------------------- MFMA form
+//
+// Networks with at most three hidden layers: the row-block products run on
+// FP64 MFMA (v_mfma_f64_16x16x4f64) with 16-row blocks.  The operand (16 rows
+// x len) and the product (16 rows x nc) sit in LDS as [neuron][row] with a
+// row stride of 17 doubles, so the A-operand reads (lane l: row l % 16 of
+// k-step 4 kk + l / 16) are consecutive and the owner lanes' column reads
+// spread over the banks.  B operands (the weights) come from L2, one per lane
+// and tile per k-step, the next k-step's loaded before this one's MFMAs.
+// Every pass, the output pass included, has a forward launch that stores its
+// levels; the reverse launches read them back, so no level lives in
+// registers across a product.
+typedef double nbd4 __attribute__((ext_vector_type(4)));
+constexpr int NBM_R = 16;        // rows per block
+constexpr int NBM_RS = 17;       // LDS row stride of operand and product
+
+// sD[col][row] = sum_{p < len} sA[p][row] M[p nc + col], col < nc, 16 rows.
+// len and nc multiples of 16.  Every lane calls it; it ends with a barrier
+// after which sD is complete (and sA no longer read).
+__device__ __forceinline__ void nbm_mm(const double* __restrict__ M, int nc, int len, const double* sA, double* sD,
+                                       int q) {
+    const int w = q >> 6, l = q & 63, lr = l & 15, lq = l >> 4;
+    const int nt = nc >> 4, nk = len >> 2;
+    if (nt >= 4) {
+        // column tiles t = w, w + 4, ... of this wave over the whole k range
+        nbd4 acc[4];
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) acc[s2] = nbd4{0.0, 0.0, 0.0, 0.0};
+        double bn[4];
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) {
+            const int t = w + 4 * s2;
+            bn[s2] = t < nt ? M[(size_t)lq * nc + 16 * t + lr] : 0.0;
+        }
+        for (int kk = 0; kk < nk; ++kk) {
+            double b[4];
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2) b[s2] = bn[s2];
+            if (kk + 1 < nk) {
+#pragma unroll
+                for (int s2 = 0; s2 < 4; ++s2) {
+                    const int t = w + 4 * s2;
+                    bn[s2] = t < nt ? M[(size_t)(4 * kk + 4 + lq) * nc + 16 * t + lr] : 0.0;
+                }
+            }
+            const double av = sA[(4 * kk + lq) * NBM_RS + lr];
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2)
+                if (w + 4 * s2 < nt) acc[s2] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b[s2], acc[s2], 0, 0, 0);
+        }
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) {
+            const int t = w + 4 * s2;
+            if (t < nt) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) sD[(16 * t + lr) * NBM_RS + 4 * i + lq] = acc[s2][i];
+            }
+        }
+        lds_barrier();
+        return;
+    }
+    // narrow output (1 to 3 tiles): the k range in four quarters, one per
+    // wave, partials added in wave order
+    nbd4 acc[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) acc[t] = nbd4{0.0, 0.0, 0.0, 0.0};
+    const int k0 = (w * nk) >> 2, k1 = ((w + 1) * nk) >> 2;
+    for (int kk = k0; kk < k1; ++kk) {
+        const double av = sA[(4 * kk + lq) * NBM_RS + lr];
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+            if (t < nt) {
+                const double bv = M[(size_t)(4 * kk + lq) * nc + 16 * t + lr];
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+            }
+    }
+    double* part = sD + 1024;            // [wave][tile][i][lane], past the product's 3 tiles
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+        if (t < nt) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) part[((w * 3 + t) * 4 + i) * 64 + l] = acc[t][i];
+        }
+    lds_barrier();
+    for (int e = q; e < nc * NBM_R; e += NB_T) {
+        const int col = e >> 4, row = e & 15;
+        const int t = col >> 4, li = (row & 3) * 16 + (col & 15), i = row >> 2;
+        double x = 0.0;
+        for (int w2 = 0; w2 < 4; ++w2) x += part[((w2 * 3 + t) * 4 + i) * 64 + li];
+        sD[col * NBM_RS + row] = x;
+    }
+    lds_barrier();
+}
+
+// One CROWN pass of target layer A.k (2 <= k <= L) for one box and direction,
+// MFMA form.  FWD: the levels of every 16-row block into lv, and for a
+// hidden layer its bounds.  REV: the adjoint of the pass from the stored levels.
+template <bool REV>
+__global__ void __launch_bounds__(NB_T) nbm_pass_kernel(NbArgs A) {
+    __shared__ __attribute__((aligned(16))) double sA[NN_MAXW * NBM_RS];
+    __shared__ __attribute__((aligned(16))) double sD[NN_MAXW * NBM_RS];
+    const int box = blockIdx.x, mode = blockIdx.y, q = threadIdx.x;
+    if (!A.ok[box]) return;
+    const bool upper = mode == 0;
+    const double sgn = upper ? 1.0 : -1.0;
+    const int k = A.k, L = A.L, n0 = A.w[0];
+    const int rows = A.w[k], nk1 = A.w[k - 1];
+    const double* Wk = A.W[k - 1];
+    const double cq = q < n0 ? A.cr[ix_cr(box, 0) + q] : 0.0;
+    const double rq = q < n0 ? A.cr[ix_cr(box, 1) + q] : 0.0;
+    double* lvb = A.lv + ((size_t)box * 2 + mode) * A.lv_bm;
+    double sacc[3] = {0.0, 0.0, 0.0}, tacc[3] = {0.0, 0.0, 0.0};
+    double cacc = 0.0, racc = 0.0;
+
+    for (int r0 = 0; r0 < rows; r0 += NBM_R) {
+        const int nr = min(NBM_R, rows - r0);
+        if (!REV) {
+            double bpart[NBM_R];
+#pragma unroll
+            for (int r = 0; r < NBM_R; ++r) bpart[r] = 0.0;
+            for (int j = k - 1; j >= 1; --j) {
+                const int nj = A.w[j];
+                if (q < nj) {
+                    double s, t, a;
+                    nb_relax(A.bd[ix_bd(box, j, 0) + q], A.bd[ix_bd(box, j, 1) + q], s, t, a);
+                    const double bj = A.b[j - 1][q];
+#pragma unroll
+                    for (int r = 0; r < NBM_R; ++r) {
+                        double lm;
+                        if (j == k - 1) lm = r < nr ? Wk[(size_t)(r0 + r) * nk1 + q] : 0.0;
+                        else lm = sD[q * NBM_RS + r];
+                        const bool sel = upper ? lm >= 0.0 : lm < 0.0;
+                        const double om = lm * (sel ? s : a);
+                        bpart[r] += (sel ? lm * t : 0.0) + om * bj;
+                        sA[q * NBM_RS + r] = om;
+                    }
+                }
+                lds_barrier();
+                const int nj1 = A.w[j - 1];
+                nbm_mm(A.W[j - 1], nj1, nj, sA, sD, q);
+                if (q < nj1) {
+                    double* dst = lvb + A.lv_off[k][j - 1] + (size_t)r0 * nj1 + q;
+                    for (int r = 0; r < nr; ++r) dst[(size_t)r * nj1] = sD[q * NBM_RS + r];
+                }
+            }
+            if (k < L) {
+                // concretise the rows: b_k + beta parts + Lambda^(0) c +/- |Lambda^(0)| rho
+                if (q < n0) {
+#pragma unroll
+                    for (int r = 0; r < NBM_R; ++r) {
+                        const double l0 = sD[q * NBM_RS + r];
+                        bpart[r] += l0 * cq + sgn * fabs(l0) * rq;
+                    }
+                }
+                const int wv = q >> 6;
+#pragma unroll
+                for (int r = 0; r < NBM_R; ++r) {
+                    double x = bpart[r];
+#pragma unroll
+                    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
+                    if ((q & 63) == 0) sA[wv * NBM_R + r] = x;
+                }
+                lds_barrier();
+                if (q < nr) {
+                    double x = A.b[k - 1][r0 + q];
+                    for (int w2 = 0; w2 < NB_T / 64; ++w2) x += sA[w2 * NBM_R + q];
+                    A.bd[ix_bd(box, k, upper ? 1 : 0) + r0 + q] = x;
+                }
+            }
+            lds_barrier();
+            continue;
+        }
+        // ---- reverse sweep of the block from the stored levels
+        double y[NBM_R];
+#pragma unroll
+        for (int r = 0; r < NBM_R; ++r) {
+            double yy = 0.0;
+            if (r < nr) {
+                if (k == L) yy = (upper ? A.g_hi : A.g_lo)[(A.u0 + box) * rows + r0 + r];
+                else yy = A.ub[ix_ub(box, k, upper ? 0 : 1) + r0 + r];
+            }
+            y[r] = yy;
+        }
+        double jv[NBM_R];
+#pragma unroll
+        for (int r = 0; r < NBM_R; ++r) jv[r] = 0.0;
+        if (k == L) {
+            // rows of J = W_L D_{L-1} W_{L-1} ... D_1 W_1 (D = [z^ > 0]) for this block
+            for (int j = L - 1; j >= 1; --j) {
+                const int nj = A.w[j];
+                if (q < nj) {
+                    const double on = A.zn[ix_zn(box, j) + q] > 0.0 ? 1.0 : 0.0;
+#pragma unroll
+                    for (int r = 0; r < NBM_R; ++r) {
+                        double x;
+                        if (j == L - 1) x = r < nr ? Wk[(size_t)(r0 + r) * nk1 + q] : 0.0;
+                        else x = sD[q * NBM_RS + r];
+                        sA[q * NBM_RS + r] = x * on;
+                    }
+                }
+                lds_barrier();
+                nbm_mm(A.W[j - 1], A.w[j - 1], nj, sA, sD, q);
+            }
+            if (q < n0) {
+#pragma unroll
+                for (int r = 0; r < NBM_R; ++r) jv[r] = sD[q * NBM_RS + r];
+            }
+            lds_barrier();
+        }
+        if (q < n0) {
+            const double* src = lvb + A.lv_off[k][0] + (size_t)r0 * n0 + q;
+#pragma unroll
+            for (int r = 0; r < NBM_R; ++r) {
+                const double l0 = r < nr ? src[(size_t)r * n0] : 0.0;
+                const double d = l0 - jv[r];
+                const double sd = d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0);
+                cacc += y[r] * d;
+                racc += sgn * y[r] * fabs(d);
+                sA[q * NBM_RS + r] = y[r] * (cq + sgn * sd * rq);
+            }
+        }
+        lds_barrier();
+        for (int j = 1; j <= k - 1; ++j) {
+            const int nj = A.w[j];
+            nbm_mm(A.WT[j - 1], nj, A.w[j - 1], sA, sD, q);
+            if (q < nj) {
+                double s, t, a;
+                nb_relax(A.bd[ix_bd(box, j, 0) + q], A.bd[ix_bd(box, j, 1) + q], s, t, a);
+                const double bj = A.b[j - 1][q];
+                const double* src = lvb + (j < k - 1 ? A.lv_off[k][j] : 0) + (size_t)r0 * nj + q;
+                double sa = 0.0, ta = 0.0;
+#pragma unroll
+                for (int r = 0; r < NBM_R; ++r) {
+                    double lm;
+                    if (j == k - 1) lm = r < nr ? Wk[(size_t)(r0 + r) * nk1 + q] : 0.0;
+                    else lm = r < nr ? src[(size_t)r * nj] : 0.0;
+                    const bool sel = upper ? lm >= 0.0 : lm < 0.0;
+                    const double obr = sD[q * NBM_RS + r] + y[r] * bj;
+                    if (sel) {
+                        sa += obr * lm;
+                        ta += y[r] * lm;
+                    }
+                    if (j < k - 1) sA[q * NBM_RS + r] = obr * (sel ? s : a) + (sel ? y[r] * t : 0.0);
+                }
+                // j <= k - 1 <= L - 1 <= 3
+                if (j == 1) { sacc[0] += sa; tacc[0] += ta; }
+                else if (j == 2) { sacc[1] += sa; tacc[1] += ta; }
+                else { sacc[2] += sa; tacc[2] += ta; }
+            }
+            lds_barrier();
+        }
+    }
+    if (REV) {
+        for (int j = 1; j <= k - 1; ++j) {
+            if (q < A.w[j]) {
+                const double sa = j == 1 ? sacc[0] : (j == 2 ? sacc[1] : sacc[2]);
+                const double ta = j == 1 ? tacc[0] : (j == 2 ? tacc[1] : tacc[2]);
+                A.st[ix_st(box, mode, j, 0) + q] += sa;
+                A.st[ix_st(box, mode, j, 1) + q] += ta;
+            }
+        }
+        if (q < n0) {
+            A.cg[ix_cg(box, mode, 0) + q] += cacc;
+            A.cg[ix_cg(box, mode, 1) + q] += racc;
+        }
+    }
+}
+
 // adjoints u-bar, l-bar of the bounds of hidden layer A.k from s-bar, t-bar
 // (both pass directions, added in a fixed order)
 __global__ void __launch_bounds__(NB_T) nb_radj_kernel(NbArgs A) {
@@ -482,11 +750,13 @@ extern "C" int leb_nn_backward(leb_mlp net, int32_t batch, int32_t N, const doub
         if (p && !aligned8(p)) return LEB_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     const int L = net->L;
-    // stored levels of the hidden-layer passes: level j of pass k is w[k] x w[j]
+    // stored levels of the passes: level j of pass k is w[k] x w[j]
     NbArgs a;
     memset(&a, 0, sizeof(a));
+    // the MFMA form (at most three hidden layers) stores the output pass's levels too
+    const bool use_mfma = L - 1 <= 3;
     size_t lv_bm = 0;
-    for (int k = 2; k < L; ++k)
+    for (int k = 2; k <= (use_mfma ? L : L - 1); ++k)
         for (int j = 0; j <= k - 2; ++j) {
             a.lv_off[k][j] = (int)lv_bm;
             lv_bm += (size_t)net->w[k] * net->w[j];
@@ -528,6 +798,24 @@ extern "C" int leb_nn_backward(leb_mlp net, int32_t batch, int32_t N, const doub
         const int nb = (int)((units - u0) < CB ? (units - u0) : CB);
         a.u0 = u0;
         hipLaunchKernelGGL(nb_box_kernel, dim3((unsigned)nb), dim3(NB_T), 0, st, a);
+        if (use_mfma) {
+            const dim3 grid((unsigned)nb, 2u);
+            for (int k = 2; k <= L; ++k) {
+                a.k = k;
+                hipLaunchKernelGGL(nbm_pass_kernel<false>, grid, dim3(NB_T), 0, st, a);
+            }
+            a.k = L;
+            hipLaunchKernelGGL(nbm_pass_kernel<true>, grid, dim3(NB_T), 0, st, a);
+            for (int j = L - 1; j >= 1; --j) {
+                a.k = j;
+                hipLaunchKernelGGL(nb_radj_kernel, dim3((unsigned)nb), dim3(NB_T), 0, st, a);
+                if (j >= 2) {
+                    hipLaunchKernelGGL(nbm_pass_kernel<true>, grid, dim3(NB_T), 0, st, a);
+                }
+            }
+            hipLaunchKernelGGL(nb_out_kernel, dim3((unsigned)nb), dim3(NB_T), 0, st, a);
+            continue;
+        }
         for (int k = 2; k < L; ++k) {
             a.k = k;
             nb_launch_pass<false>(a, nb, st);
