@@ -282,11 +282,12 @@ int leb_nn_bound(leb_mlp net, int32_t batch, int32_t N, const double* z, const d
  *   gz, gv, gsigma                 outputs, shaped as z, v, sigma
  *   gmu [batch][N][nx+nu]          output, may be NULL; must be NULL when mu is NULL
  * Units with invalid data (non-finite input, sigma < 0) get a zero gradient.
- * Every pass is recomputed (nothing of leb_nn_bound is reused), in FP64.
+ * Every pass is recomputed (nothing of leb_nn_bound is reused), in FP64 (on
+ * MFMA for networks with at most three hidden layers, on the VALU beyond).
  * Deterministic: every sum is taken in a fixed order.  Uses a library-owned
  * grow-only workspace of up to about 1.1 GB (it holds the CROWN coefficients
- * of the hidden-layer passes of up to 512 boxes; deep, wide networks take
- * fewer boxes at a time), ordered across streams like the other workspaces.
+ * of the passes of up to 512 boxes; deep, wide networks take fewer boxes at
+ * a time), ordered across streams like the other workspaces.
  * LEB_EINVAL for null or misaligned pointers or gmu without mu.
  */
 int leb_nn_backward(leb_mlp net, int32_t batch, int32_t N, const double* z, const double* v, const double* mu,
