@@ -1,6 +1,7 @@
 """GPU adjoint of the MLP bound (leb_nn_backward) against the oracle's
 forward-mode gradient: several widths and depths (narrow and non-power-of-two
-layers, both register-level variants), with and without mu, ragged chunks,
+layers, one hidden layer without control inputs, the MFMA and VALU forms),
+with and without mu, ragged chunks,
 the 16-256-256-256-12 workload on sampled boxes, invalid boxes, determinism."""
 import numpy as np
 import pytest
@@ -69,7 +70,7 @@ def _case(rng, widths, nx, batch, N, sg_lo, sg_hi, with_mu):
 
 @pytest.mark.parametrize("widths,nx,with_mu", [([16, 32, 32, 12], 12, False), ([16, 64, 48, 32, 8], 8, True),
                                                ([32, 16, 16, 16, 16, 16, 4], 4, True),
-                                               ([16, 256, 96, 12], 12, False)])
+                                               ([16, 256, 96, 12], 12, False), ([16, 48, 16], 16, True)])
 def test_nn_backward_parity_shapes(gpu, widths, nx, with_mu):
     import paper_2607_01203_amd as leb
     rng = W.rng_for(300 + len(widths) + widths[1])
