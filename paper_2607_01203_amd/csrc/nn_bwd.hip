@@ -416,13 +416,15 @@ typedef double nbd4 __attribute__((ext_vector_type(4)));
 constexpr int NBM_R = 16;        // rows per block
 constexpr int NBM_RS = 17;       // LDS row stride of operand and product
 
-// sD[col][row] = sum_{p < len} sA[p][row] M[p nc + col], col < nc, 16 rows.
-// len and nc multiples of 16.  Every lane calls it; it ends with a barrier
-// after which sD is complete (and sA no longer read).
-__device__ __forceinline__ void nbm_mm(const double* __restrict__ M, int nc, int len, const double* sA, double* sD,
-                                       int q) {
+// sD[col][row] = sum_{p < len} sA[p][row] M[kl[p] nc + col], col < nc, 16
+// rows; kl = NULL: kl[p] = p.  len a multiple of 4 (possibly 0), nc of 16.
+// Every lane calls it; it ends with a barrier after which sD is complete (and
+// sA no longer read).
+__device__ __forceinline__ void nbm_mm(const double* __restrict__ M, int nc, int len, const int* kl, const double* sA,
+                                       double* sD, int q) {
     const int w = q >> 6, l = q & 63, lr = l & 15, lq = l >> 4;
     const int nt = nc >> 4, nk = len >> 2;
+    auto krow = [&](int p) { return (size_t)(kl ? kl[p] : p); };
     if (nt >= 4) {
         // column tiles t = w, w + 4, ... of this wave over the whole k range
         nbd4 acc[4];
@@ -432,7 +434,7 @@ __device__ __forceinline__ void nbm_mm(const double* __restrict__ M, int nc, int
 #pragma unroll
         for (int s2 = 0; s2 < 4; ++s2) {
             const int t = w + 4 * s2;
-            bn[s2] = t < nt ? M[(size_t)lq * nc + 16 * t + lr] : 0.0;
+            bn[s2] = (t < nt && nk > 0) ? M[krow(lq) * nc + 16 * t + lr] : 0.0;
         }
         for (int kk = 0; kk < nk; ++kk) {
             double b[4];
@@ -442,7 +444,7 @@ __device__ __forceinline__ void nbm_mm(const double* __restrict__ M, int nc, int
 #pragma unroll
                 for (int s2 = 0; s2 < 4; ++s2) {
                     const int t = w + 4 * s2;
-                    bn[s2] = t < nt ? M[(size_t)(4 * kk + 4 + lq) * nc + 16 * t + lr] : 0.0;
+                    bn[s2] = t < nt ? M[krow(4 * kk + 4 + lq) * nc + 16 * t + lr] : 0.0;
                 }
             }
             const double av = sA[(4 * kk + lq) * NBM_RS + lr];
@@ -472,7 +474,7 @@ __device__ __forceinline__ void nbm_mm(const double* __restrict__ M, int nc, int
 #pragma unroll
         for (int t = 0; t < 3; ++t)
             if (t < nt) {
-                const double bv = M[(size_t)(4 * kk + lq) * nc + 16 * t + lr];
+                const double bv = M[krow(4 * kk + lq) * nc + 16 * t + lr];
                 acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
             }
     }
@@ -494,6 +496,11 @@ __device__ __forceinline__ void nbm_mm(const double* __restrict__ M, int nc, int
     lds_barrier();
 }
 
+// zero the operand rows tot .. len-1 (the padding of a neuron list)
+__device__ __forceinline__ void nbm_pad(double* sA, int tot, int len, int q) {
+    for (int e = q; e < (len - tot) * NBM_R; e += NB_T) sA[(tot + e / NBM_R) * NBM_RS + e % NBM_R] = 0.0;
+}
+
 // One CROWN pass of target layer A.k (2 <= k <= L) for one box and direction,
 // MFMA form.  FWD: the levels of every 16-row block into lv, and for a
 // hidden layer its bounds.  REV: the adjoint of the pass from the stored levels.
@@ -501,8 +508,32 @@ template <bool REV>
 __global__ void __launch_bounds__(NB_T) nbm_pass_kernel(NbArgs A) {
     __shared__ __attribute__((aligned(16))) double sA[NN_MAXW * NBM_RS];
     __shared__ __attribute__((aligned(16))) double sD[NN_MAXW * NBM_RS];
+    // per hidden layer j (index j-1): the neurons that are not stably inactive
+    // (an inactive neuron's column of Omega, and of Lambda-bar, is exactly 0),
+    // padded with row 0 to a multiple of 4; pos: a neuron's place in the list
+    __shared__ int sList[3][NN_MAXW], sPos[3][NN_MAXW], sLen[3], sTot[3];
+    __shared__ int sCnt[NB_T / 64];
     const int box = blockIdx.x, mode = blockIdx.y, q = threadIdx.x;
     if (!A.ok[box]) return;
+    for (int j = 1; j <= A.k - 1; ++j) {
+        const int nj = A.w[j];
+        const bool keep = q < nj && (A.bd[ix_bd(box, j, 0) + q] >= 0.0 || A.bd[ix_bd(box, j, 1) + q] > 0.0);
+        const uint64_t bal = __ballot(keep);
+        if ((q & 63) == 0) sCnt[q >> 6] = __popcll(bal);
+        lds_barrier();
+        int off = 0, tot = 0;
+        for (int w2 = 0; w2 < NB_T / 64; ++w2) {
+            if (w2 < (q >> 6)) off += sCnt[w2];
+            tot += sCnt[w2];
+        }
+        const int pos = off + __popcll(bal & ((1ull << (q & 63)) - 1ull));
+        if (keep) sList[j - 1][pos] = q;
+        if (q < nj) sPos[j - 1][q] = keep ? pos : -1;
+        const int padded = (tot + 3) & ~3;
+        if (q >= tot && q < padded) sList[j - 1][q] = 0;
+        if (q == 0) { sLen[j - 1] = padded; sTot[j - 1] = tot; }
+        lds_barrier();
+    }
     const bool upper = mode == 0;
     const double sgn = upper ? 1.0 : -1.0;
     const int k = A.k, L = A.L, n0 = A.w[0];
@@ -522,7 +553,8 @@ __global__ void __launch_bounds__(NB_T) nbm_pass_kernel(NbArgs A) {
             for (int r = 0; r < NBM_R; ++r) bpart[r] = 0.0;
             for (int j = k - 1; j >= 1; --j) {
                 const int nj = A.w[j];
-                if (q < nj) {
+                const int pq = q < nj ? sPos[j - 1][q] : -1;
+                if (pq >= 0) {
                     double s, t, a;
                     nb_relax(A.bd[ix_bd(box, j, 0) + q], A.bd[ix_bd(box, j, 1) + q], s, t, a);
                     const double bj = A.b[j - 1][q];
@@ -534,12 +566,14 @@ __global__ void __launch_bounds__(NB_T) nbm_pass_kernel(NbArgs A) {
                         const bool sel = upper ? lm >= 0.0 : lm < 0.0;
                         const double om = lm * (sel ? s : a);
                         bpart[r] += (sel ? lm * t : 0.0) + om * bj;
-                        sA[q * NBM_RS + r] = om;
+                        sA[pq * NBM_RS + r] = om;
                     }
                 }
+                const int len = sLen[j - 1];
+                nbm_pad(sA, sTot[j - 1], len, q);
                 lds_barrier();
                 const int nj1 = A.w[j - 1];
-                nbm_mm(A.W[j - 1], nj1, nj, sA, sD, q);
+                nbm_mm(A.W[j - 1], nj1, len, sList[j - 1], sA, sD, q);
                 if (q < nj1) {
                     double* dst = lvb + A.lv_off[k][j - 1] + (size_t)r0 * nj1 + q;
                     for (int r = 0; r < nr; ++r) dst[(size_t)r * nj1] = sD[q * NBM_RS + r];
@@ -601,7 +635,7 @@ __global__ void __launch_bounds__(NB_T) nbm_pass_kernel(NbArgs A) {
                     }
                 }
                 lds_barrier();
-                nbm_mm(A.W[j - 1], A.w[j - 1], nj, sA, sD, q);
+                nbm_mm(A.W[j - 1], A.w[j - 1], nj, nullptr, sA, sD, q);
             }
             if (q < n0) {
 #pragma unroll
@@ -624,7 +658,11 @@ __global__ void __launch_bounds__(NB_T) nbm_pass_kernel(NbArgs A) {
         lds_barrier();
         for (int j = 1; j <= k - 1; ++j) {
             const int nj = A.w[j];
-            nbm_mm(A.WT[j - 1], nj, A.w[j - 1], sA, sD, q);
+            // k over layer j-1: the inputs (all) or the listed neurons of a hidden layer
+            if (j == 1) nbm_mm(A.WT[0], nj, n0, nullptr, sA, sD, q);
+            else nbm_mm(A.WT[j - 1], nj, sLen[j - 2], sList[j - 2], sA, sD, q);
+            const int pq = q < nj ? sPos[j - 1][q] : -1;
+            if (j < k - 1) nbm_pad(sA, sTot[j - 1], sLen[j - 1], q);
             if (q < nj) {
                 double s, t, a;
                 nb_relax(A.bd[ix_bd(box, j, 0) + q], A.bd[ix_bd(box, j, 1) + q], s, t, a);
@@ -642,7 +680,7 @@ __global__ void __launch_bounds__(NB_T) nbm_pass_kernel(NbArgs A) {
                         sa += obr * lm;
                         ta += y[r] * lm;
                     }
-                    if (j < k - 1) sA[q * NBM_RS + r] = obr * (sel ? s : a) + (sel ? y[r] * t : 0.0);
+                    if (j < k - 1 && pq >= 0) sA[pq * NBM_RS + r] = obr * (sel ? s : a) + (sel ? y[r] * t : 0.0);
                 }
                 // j <= k - 1 <= L - 1 <= 3
                 if (j == 1) { sacc[0] += sa; tacc[0] += ta; }
