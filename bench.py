@@ -648,10 +648,11 @@ def nn_roofline(leb, W, dev, stream, args):
 def nn_adjoint_flops(widths):
     """(algorithmic, executed) FLOPs per box of the MLP bound's adjoint.
     Algorithmic: the bound's own passes (nn_crown_flops) plus the reverse of
-    every pass in both modes, each as large as the pass.  Executed, MFMA form
-    (at most three hidden layers): a forward launch for every pass (the output
-    pass's too, to store its levels), the reverse of every pass, and the
-    Jacobian rows once per mode."""
+    every pass in both modes, each as large as the pass.  Executed, dense MFMA
+    form (at most three hidden layers): a forward launch for every pass (the
+    output pass's too, to store its levels), the reverse of every pass, and the
+    Jacobian rows once per mode; the kernels skip the stably inactive neurons'
+    share of it."""
     L = len(widths) - 1
     chain = lambda k: sum(widths[k] * widths[j] * widths[j - 1] for j in range(k - 1, 0, -1))
     rev = sum(2 * chain(k) for k in range(2, L + 1))
