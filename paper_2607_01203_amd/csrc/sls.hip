@@ -63,10 +63,12 @@ struct RiccatiArgs {
     int nx, nu, N;
 };
 
-template <int NUB, int PF>
+// NXC, NUC > 0: nx and nu fixed at compile time (the short dot products are
+// then unrolled and their LDS loads issued together); 0: taken from a.
+template <int NUB, int PF, int NXC = 0, int NUC = 0>
 __global__ void __launch_bounds__(SLS_THREADS) sls_riccati_kernel(RiccatiArgs a) {
     const int j = blockIdx.x, b = blockIdx.y;
-    const int nx = a.nx, nu = a.nu, N = a.N, n = nx + nu;
+    const int nx = NXC ? NXC : a.nx, nu = NUC ? NUC : a.nu, N = a.N, n = nx + nu;
     if (j >= N - 1) return;                      // no k with j < k < N
     extern __shared__ double sm[];
     double* P = sm;                              // nx*nx   cost-to-go, then X of the forward pass
@@ -1004,6 +1006,8 @@ extern "C" int leb_sls_responses(int32_t nx, int32_t nu, int32_t batch, int32_t 
     hipStream_t st = (hipStream_t)stream;
     if (nx > 8 && nx <= 16 && nu <= 4)
         hipLaunchKernelGGL((sls_riccati_mfma_kernel<4>), grid, dim3(64), 0, st, a);
+    else if (nx == 6 && nu == 2 && threads == 64)
+        hipLaunchKernelGGL((sls_riccati_kernel<4, 2, 6, 2>), grid, dim3(threads), sm, st, a);
     else if (small)
         hipLaunchKernelGGL((sls_riccati_kernel<4, 2>), grid, dim3(threads), sm, st, a);
     else
