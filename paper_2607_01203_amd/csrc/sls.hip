@@ -95,12 +95,13 @@ __global__ void __launch_bounds__(SLS_THREADS) sls_riccati_kernel(RiccatiArgs a)
         const int r = q / nx, c = q - r * nx;
         P[q] = r == c ? qxb[((size_t)N * N + j) * nx + r] : 0.0;
     }
-    // the next step's (A_k, B_k, weights) -- or (A_k, B_k, K_k) in the forward
-    // pass -- are loaded into registers while the current step computes, and
-    // stored to LDS after its last barrier
-    double pf[PF];
+    // a step's (A_k, B_k, weights) -- or (A_k, B_k, K_k) in the forward pass --
+    // are loaded into registers two steps ahead (two buffers, the step loop
+    // taken two at a time so each buffer has a fixed role) and stored to LDS
+    // after the last barrier of the step before theirs
+    double pfa[PF], pfb[PF];
     const int nab = nx * n;
-    auto fetch = [&](int k, bool fwd) {
+    auto fetch = [&](int k, bool fwd, double* pf) {
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
             const int q = tid + u * nt;
@@ -113,7 +114,7 @@ __global__ void __launch_bounds__(SLS_THREADS) sls_riccati_kernel(RiccatiArgs a)
             pf[u] = x;
         }
     };
-    auto stash = [&](bool fwd) {
+    auto stash = [&](bool fwd, const double* pf) {
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
             const int q = tid + u * nt;
@@ -124,11 +125,12 @@ __global__ void __launch_bounds__(SLS_THREADS) sls_riccati_kernel(RiccatiArgs a)
             else if (q < nab + n) squ[q - nab - nx] = pf[u];
         }
     };
-    fetch(N - 1, false);
-    stash(false);
-    for (int k = N - 1; k > j; --k) {
+    fetch(N - 1, false, pfa);
+    stash(false, pfa);
+    if (N - 2 > j) fetch(N - 2, false, pfb);
+    auto bstep = [&](int k, double* fb, const double* sb) {
         lds_barrier();
-        if (k - 1 > j) fetch(k - 1, false);
+        if (k - 2 > j) fetch(k - 2, false, fb);
         // P A_k and P B_k
         for (int q = tid; q < nx * n; q += nt) {
             double s = 0.0;
@@ -212,7 +214,11 @@ __global__ void __launch_bounds__(SLS_THREADS) sls_riccati_kernel(RiccatiArgs a)
         }
         for (int q = tid; q < nu * nx; q += nt) Kb[((size_t)k * N + j) * nu * nx + q] = Kk[q];
         lds_barrier();
-        if (k - 1 > j) stash(false);
+        if (k - 1 > j) stash(false, sb);
+    };
+    for (int k = N - 1; k > j; k -= 2) {
+        bstep(k, pfa, pfb);
+        if (k - 1 > j) bstep(k - 1, pfb, pfa);
     }
     // forward propagation from Phi^x_{j+1,j} = I; the gains were stored by this
     // workgroup above, and this full barrier orders those stores before the loads
@@ -220,11 +226,12 @@ __global__ void __launch_bounds__(SLS_THREADS) sls_riccati_kernel(RiccatiArgs a)
     double* X = P;
     double* Xn = PA;
     for (int q = tid; q < nx * nx; q += nt) X[q] = (q / nx == q % nx) ? 1.0 : 0.0;
-    fetch(j + 1, true);
-    stash(true);
-    for (int k = j + 1; k < N; ++k) {
+    fetch(j + 1, true, pfa);
+    stash(true, pfa);
+    if (j + 2 < N) fetch(j + 2, true, pfb);
+    auto fstep = [&](int k, double* fb, const double* sb) {
         lds_barrier();
-        if (k + 1 < N) fetch(k + 1, true);
+        if (k + 2 < N) fetch(k + 2, true, fb);
         double* out = phib + ((size_t)k * N + j) * n * nx;
         for (int q = tid; q < n * nx; q += nt) {
             const int r = q / nx, c = q - r * nx;
@@ -253,8 +260,12 @@ __global__ void __launch_bounds__(SLS_THREADS) sls_riccati_kernel(RiccatiArgs a)
             }
             lds_barrier();
             double* t = X; X = Xn; Xn = t;
-            stash(true);
+            stash(true, sb);
         }
+    };
+    for (int k = j + 1; k < N; k += 2) {
+        fstep(k, pfa, pfb);
+        if (k + 1 < N) fstep(k + 1, pfb, pfa);
     }
 }
 
