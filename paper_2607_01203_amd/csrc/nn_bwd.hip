@@ -34,21 +34,21 @@
 // only from passes with k > j, so each layer's adjoint is complete when its
 // own pass is reversed.  J a~ - g(a~) has derivative 0 (J is locally constant).
 //
-// GPU design.  One workgroup of 256 lanes per (box, pass direction); the
-// target rows go in blocks of 8.  Lane q owns neuron column q of every level
-// and keeps Lambda^(j) of its column in registers for the reverse sweep.  The
-// forward pass of a hidden layer stores its levels (coalesced, [row][column])
-// and the reverse pass of that layer loads them; the output pass, which has
-// no forward launch of its own, recomputes its chain.  The
-// operand of each row-block product (8 rows x up to 256 neurons) is staged in
-// LDS in [neuron][row] order, so a lane reads one row set with wide LDS loads
-// and multiplies it by one weight from L2 (W_j forward, W_j^T in reverse,
-// both row-major and coalesced across lanes).  Narrow outputs (input layer)
-// split the sum over lane slices and add the slices in a fixed order.  The
-// per-neuron sums s-bar, t-bar, c-bar, rho-bar stay in the owning lane
-// across blocks; later passes add to them in launch order, so the result is
-// deterministic.  FP64 on the VALU: the adjoint is a sequence of narrow
-// (8-row) products, one block at a time.
+// GPU design.  One workgroup of 256 lanes per (box, pass direction); lane q
+// owns neuron column q of every level, applies the relaxation selection to
+// it and keeps the per-neuron sums s-bar, t-bar, c-bar, rho-bar of its column
+// across row blocks; later passes add to them in launch order, so the result
+// is deterministic.  The operand of each row-block product is staged in LDS
+// as [neuron][row]; the weights come from L2 (W_j forward, W_j^T in reverse,
+// both row-major, coalesced).  Two forms:
+//  * MFMA (at most three hidden layers, the usual case): 16-row blocks on
+//    FP64 MFMA; every pass has a forward launch that stores its levels and the
+//    reverse launch reads them back; the k range of each product runs over
+//    the neurons that are not stably inactive (see the MFMA section below).
+//  * VALU (deeper networks): 8-row blocks, Lambda^(j) of the lane's column
+//    kept in registers for the reverse sweep; hidden-layer passes store their
+//    levels, the output pass recomputes its chain; narrow outputs (the input
+//    layer) split the sum over lane slices added in a fixed order.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -765,11 +765,10 @@ struct NbWorkspace {
 };
 static NbWorkspace g_nbws;
 
+// VALU form: networks with four or more hidden layers (the MFMA form takes the rest)
 template <bool REV>
 static void nb_launch_pass(const NbArgs& a, int nb, hipStream_t st) {
-    const dim3 grid((unsigned)nb, 2u);
-    if (a.L - 1 <= 3) hipLaunchKernelGGL((nb_pass_kernel<REV, 3>), grid, dim3(NB_T), 0, st, a);
-    else hipLaunchKernelGGL((nb_pass_kernel<REV, NN_MAXL - 1>), grid, dim3(NB_T), 0, st, a);
+    hipLaunchKernelGGL((nb_pass_kernel<REV, NN_MAXL - 1>), dim3((unsigned)nb, 2u), dim3(NB_T), 0, st, a);
 }
 
 extern "C" int leb_nn_backward(leb_mlp net, int32_t batch, int32_t N, const double* z, const double* v,
