@@ -658,6 +658,20 @@ __global__ void __launch_bounds__(NB_T) nbm_pass_kernel(NbArgs A) {
         lds_barrier();
         for (int j = 1; j <= k - 1; ++j) {
             const int nj = A.w[j];
+            // this level's Lambda^(j) column, relaxation and bias, loaded before
+            // the product so their latency overlaps it
+            double lmv[NBM_R];
+            double lo_j = 0.0, hi_j = 0.0, bj = 0.0;
+            if (q < nj) {
+                const double* src = j == k - 1 ? Wk + (size_t)r0 * nk1 + q
+                                               : lvb + A.lv_off[k][j] + (size_t)r0 * nj + q;
+                const size_t ld = j == k - 1 ? (size_t)nk1 : (size_t)nj;
+#pragma unroll
+                for (int r = 0; r < NBM_R; ++r) lmv[r] = r < nr ? src[(size_t)r * ld] : 0.0;
+                lo_j = A.bd[ix_bd(box, j, 0) + q];
+                hi_j = A.bd[ix_bd(box, j, 1) + q];
+                bj = A.b[j - 1][q];
+            }
             // k over layer j-1: the inputs (all) or the listed neurons of a hidden layer
             if (j == 1) nbm_mm(A.WT[0], nj, n0, nullptr, sA, sD, q);
             else nbm_mm(A.WT[j - 1], nj, sLen[j - 2], sList[j - 2], sA, sD, q);
@@ -665,15 +679,11 @@ __global__ void __launch_bounds__(NB_T) nbm_pass_kernel(NbArgs A) {
             if (j < k - 1) nbm_pad(sA, sTot[j - 1], sLen[j - 1], q);
             if (q < nj) {
                 double s, t, a;
-                nb_relax(A.bd[ix_bd(box, j, 0) + q], A.bd[ix_bd(box, j, 1) + q], s, t, a);
-                const double bj = A.b[j - 1][q];
-                const double* src = lvb + (j < k - 1 ? A.lv_off[k][j] : 0) + (size_t)r0 * nj + q;
+                nb_relax(lo_j, hi_j, s, t, a);
                 double sa = 0.0, ta = 0.0;
 #pragma unroll
                 for (int r = 0; r < NBM_R; ++r) {
-                    double lm;
-                    if (j == k - 1) lm = r < nr ? Wk[(size_t)(r0 + r) * nk1 + q] : 0.0;
-                    else lm = r < nr ? src[(size_t)r * nj] : 0.0;
+                    const double lm = lmv[r];
                     const bool sel = upper ? lm >= 0.0 : lm < 0.0;
                     const double obr = sD[q * NBM_RS + r] + y[r] * bj;
                     if (sel) {
