@@ -544,6 +544,22 @@ __global__ void __launch_bounds__(NB_T) nbm_pass_kernel(NbArgs A) {
     double* lvb = A.lv + ((size_t)box * 2 + mode) * A.lv_bm;
     double sacc[3] = {0.0, 0.0, 0.0}, tacc[3] = {0.0, 0.0, 0.0};
     double cacc = 0.0, racc = 0.0;
+    // forward launches: the relaxation and bias of the lane's neuron in each
+    // layer j < k (loaded once), and the rows of W_k of the next block (loaded
+    // while the current block computes)
+    double fs[3] = {0.0, 0.0, 0.0}, ft[3] = {0.0, 0.0, 0.0}, fa[3] = {0.0, 0.0, 0.0}, fb[3] = {0.0, 0.0, 0.0};
+    double wk[NBM_R];
+    if (!REV) {
+#pragma unroll
+        for (int j = 1; j <= 3; ++j) {
+            if (j <= k - 1 && q < A.w[j]) {
+                nb_relax(A.bd[ix_bd(box, j, 0) + q], A.bd[ix_bd(box, j, 1) + q], fs[j - 1], ft[j - 1], fa[j - 1]);
+                fb[j - 1] = A.b[j - 1][q];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < NBM_R; ++r) wk[r] = (q < nk1 && r < rows) ? Wk[(size_t)r * nk1 + q] : 0.0;
+    }
 
     for (int r0 = 0; r0 < rows; r0 += NBM_R) {
         const int nr = min(NBM_R, rows - r0);
@@ -555,19 +571,25 @@ __global__ void __launch_bounds__(NB_T) nbm_pass_kernel(NbArgs A) {
                 const int nj = A.w[j];
                 const int pq = q < nj ? sPos[j - 1][q] : -1;
                 if (pq >= 0) {
-                    double s, t, a;
-                    nb_relax(A.bd[ix_bd(box, j, 0) + q], A.bd[ix_bd(box, j, 1) + q], s, t, a);
-                    const double bj = A.b[j - 1][q];
+                    const double s = j == 1 ? fs[0] : (j == 2 ? fs[1] : fs[2]);
+                    const double t = j == 1 ? ft[0] : (j == 2 ? ft[1] : ft[2]);
+                    const double a = j == 1 ? fa[0] : (j == 2 ? fa[1] : fa[2]);
+                    const double bj = j == 1 ? fb[0] : (j == 2 ? fb[1] : fb[2]);
 #pragma unroll
                     for (int r = 0; r < NBM_R; ++r) {
-                        double lm;
-                        if (j == k - 1) lm = r < nr ? Wk[(size_t)(r0 + r) * nk1 + q] : 0.0;
-                        else lm = sD[q * NBM_RS + r];
+                        const double lm = j == k - 1 ? wk[r] : sD[q * NBM_RS + r];
                         const bool sel = upper ? lm >= 0.0 : lm < 0.0;
                         const double om = lm * (sel ? s : a);
                         bpart[r] += (sel ? lm * t : 0.0) + om * bj;
                         sA[pq * NBM_RS + r] = om;
                     }
+                }
+                if (j == k - 1) {
+                    // the next block's rows of W_k
+                    const int r1 = r0 + NBM_R;
+#pragma unroll
+                    for (int r = 0; r < NBM_R; ++r)
+                        wk[r] = (q < nk1 && r1 + r < rows) ? Wk[(size_t)(r1 + r) * nk1 + q] : 0.0;
                 }
                 const int len = sLen[j - 1];
                 nbm_pad(sA, sTot[j - 1], len, q);
