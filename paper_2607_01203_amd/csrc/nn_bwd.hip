@@ -549,6 +549,13 @@ __global__ void __launch_bounds__(NB_T) nbm_pass_kernel(NbArgs A) {
     // while the current block computes)
     double fs[3] = {0.0, 0.0, 0.0}, ft[3] = {0.0, 0.0, 0.0}, fa[3] = {0.0, 0.0, 0.0}, fb[3] = {0.0, 0.0, 0.0};
     double wk[NBM_R];
+    // reverse launches: Lambda^(0) rows of the block (lanes q < n0), loaded a block ahead
+    double l0n[NBM_R];
+    if (REV) {
+#pragma unroll
+        for (int r = 0; r < NBM_R; ++r)
+            l0n[r] = (q < n0 && r < rows) ? lvb[A.lv_off[k][0] + (size_t)r * n0 + q] : 0.0;
+    }
     if (!REV) {
 #pragma unroll
         for (int j = 1; j <= 3; ++j) {
@@ -666,16 +673,19 @@ __global__ void __launch_bounds__(NB_T) nbm_pass_kernel(NbArgs A) {
             lds_barrier();
         }
         if (q < n0) {
-            const double* src = lvb + A.lv_off[k][0] + (size_t)r0 * n0 + q;
 #pragma unroll
             for (int r = 0; r < NBM_R; ++r) {
-                const double l0 = r < nr ? src[(size_t)r * n0] : 0.0;
-                const double d = l0 - jv[r];
+                const double d = l0n[r] - jv[r];
                 const double sd = d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0);
                 cacc += y[r] * d;
                 racc += sgn * y[r] * fabs(d);
                 sA[q * NBM_RS + r] = y[r] * (cq + sgn * sd * rq);
             }
+            // the next block's Lambda^(0) rows, in flight while this block runs
+            const int r1 = r0 + NBM_R;
+            const double* src = lvb + A.lv_off[k][0] + (size_t)r1 * n0 + q;
+#pragma unroll
+            for (int r = 0; r < NBM_R; ++r) l0n[r] = r1 + r < rows ? src[(size_t)r * n0] : 0.0;
         }
         lds_barrier();
         for (int j = 1; j <= k - 1; ++j) {
