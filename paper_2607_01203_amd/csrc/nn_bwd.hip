@@ -465,11 +465,30 @@ __device__ __forceinline__ void nbm_mm(const double* __restrict__ M, int nc, int
     }
     // narrow output (1 to 3 tiles): the k range in four quarters, one per
     // wave, partials added in wave order
-    nbd4 acc[3];
+    // two k-steps per trip into two accumulators (their loads issued
+    // together, two independent MFMA chains), added at the end
+    nbd4 acc[3], acc2[3];
 #pragma unroll
-    for (int t = 0; t < 3; ++t) acc[t] = nbd4{0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < 3; ++t) { acc[t] = nbd4{0.0, 0.0, 0.0, 0.0}; acc2[t] = nbd4{0.0, 0.0, 0.0, 0.0}; }
     const int k0 = (w * nk) >> 2, k1 = ((w + 1) * nk) >> 2;
-    for (int kk = k0; kk < k1; ++kk) {
+    int kk = k0;
+    for (; kk + 1 < k1; kk += 2) {
+        const double av0 = sA[(4 * kk + lq) * NBM_RS + lr];
+        const double av1 = sA[(4 * kk + 4 + lq) * NBM_RS + lr];
+        double b0[3], b1[3];
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            b0[t] = t < nt ? M[krow(4 * kk + lq) * nc + 16 * t + lr] : 0.0;
+            b1[t] = t < nt ? M[krow(4 * kk + 4 + lq) * nc + 16 * t + lr] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+            if (t < nt) {
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av0, b0[t], acc[t], 0, 0, 0);
+                acc2[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av1, b1[t], acc2[t], 0, 0, 0);
+            }
+    }
+    if (kk < k1) {
         const double av = sA[(4 * kk + lq) * NBM_RS + lr];
 #pragma unroll
         for (int t = 0; t < 3; ++t)
@@ -478,6 +497,8 @@ __device__ __forceinline__ void nbm_mm(const double* __restrict__ M, int nc, int
                 acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
             }
     }
+#pragma unroll
+    for (int t = 0; t < 3; ++t) acc[t] += acc2[t];
     double* part = sD + 1024;            // [wave][tile][i][lane], past the product's 3 tiles
 #pragma unroll
     for (int t = 0; t < 3; ++t)
@@ -505,7 +526,7 @@ __device__ __forceinline__ void nbm_pad(double* sA, int tot, int len, int q) {
 // MFMA form.  FWD: the levels of every 16-row block into lv, and for a
 // hidden layer its bounds.  REV: the adjoint of the pass from the stored levels.
 template <bool REV>
-__global__ void __launch_bounds__(NB_T) nbm_pass_kernel(NbArgs A) {
+__global__ void __launch_bounds__(NB_T) __attribute__((amdgpu_waves_per_eu(2))) nbm_pass_kernel(NbArgs A) {
     __shared__ __attribute__((aligned(16))) double sA[NN_MAXW * NBM_RS];
     __shared__ __attribute__((aligned(16))) double sD[NN_MAXW * NBM_RS];
     // per hidden layer j (index j-1): the neurons that are not stably inactive
