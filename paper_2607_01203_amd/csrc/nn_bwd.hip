@@ -416,15 +416,16 @@ typedef double nbd4 __attribute__((ext_vector_type(4)));
 constexpr int NBM_R = 16;        // rows per block
 constexpr int NBM_RS = 17;       // LDS row stride of operand and product
 
-// sD[col][row] = sum_{p < len} sA[p][row] M[kl[p] nc + col], col < nc, 16
-// rows; kl = NULL: kl[p] = p.  len a multiple of 4 (possibly 0), nc of 16.
-// Every lane calls it; it ends with a barrier after which sD is complete (and
-// sA no longer read).
-__device__ __forceinline__ void nbm_mm(const double* __restrict__ M, int nc, int len, const int* kl, const double* sA,
-                                       double* sD, int q) {
+// sD[col][row] = sum_{p < len} sA[p][row] M[kl[p] ld + cl[col]], col < nc,
+// 16 rows; kl = NULL: kl[p] = p, cl = NULL: cl[c] = c.  len a multiple of 4
+// (possibly 0), nc of 16.  Every lane calls it; it ends with a barrier after
+// which sD is complete (and sA no longer read).
+__device__ __forceinline__ void nbm_mm(const double* __restrict__ M, int ld, int nc, int len, const int* kl,
+                                       const int* cl, const double* sA, double* sD, int q) {
     const int w = q >> 6, l = q & 63, lr = l & 15, lq = l >> 4;
     const int nt = nc >> 4, nk = len >> 2;
-    auto krow = [&](int p) { return (size_t)(kl ? kl[p] : p); };
+    auto krow = [&](int p) { return (size_t)(kl ? kl[p] : p) * ld; };
+    auto kcol = [&](int t) { return (size_t)(cl ? cl[16 * t + lr] : 16 * t + lr); };
     if (nt >= 4) {
         // column tiles t = w, w + 4, ... of this wave over the whole k range
         nbd4 acc[4];
@@ -434,7 +435,7 @@ __device__ __forceinline__ void nbm_mm(const double* __restrict__ M, int nc, int
 #pragma unroll
         for (int s2 = 0; s2 < 4; ++s2) {
             const int t = w + 4 * s2;
-            bn[s2] = (t < nt && nk > 0) ? M[krow(lq) * nc + 16 * t + lr] : 0.0;
+            bn[s2] = (t < nt && nk > 0) ? M[krow(lq) + kcol(t)] : 0.0;
         }
         for (int kk = 0; kk < nk; ++kk) {
             double b[4];
@@ -444,7 +445,7 @@ __device__ __forceinline__ void nbm_mm(const double* __restrict__ M, int nc, int
 #pragma unroll
                 for (int s2 = 0; s2 < 4; ++s2) {
                     const int t = w + 4 * s2;
-                    bn[s2] = t < nt ? M[krow(4 * kk + 4 + lq) * nc + 16 * t + lr] : 0.0;
+                    bn[s2] = t < nt ? M[krow(4 * kk + 4 + lq) + kcol(t)] : 0.0;
                 }
             }
             const double av = sA[(4 * kk + lq) * NBM_RS + lr];
@@ -478,8 +479,8 @@ __device__ __forceinline__ void nbm_mm(const double* __restrict__ M, int nc, int
         double b0[3], b1[3];
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
-            b0[t] = t < nt ? M[krow(4 * kk + lq) * nc + 16 * t + lr] : 0.0;
-            b1[t] = t < nt ? M[krow(4 * kk + 4 + lq) * nc + 16 * t + lr] : 0.0;
+            b0[t] = t < nt ? M[krow(4 * kk + lq) + kcol(t)] : 0.0;
+            b1[t] = t < nt ? M[krow(4 * kk + 4 + lq) + kcol(t)] : 0.0;
         }
 #pragma unroll
         for (int t = 0; t < 3; ++t)
@@ -493,7 +494,7 @@ __device__ __forceinline__ void nbm_mm(const double* __restrict__ M, int nc, int
 #pragma unroll
         for (int t = 0; t < 3; ++t)
             if (t < nt) {
-                const double bv = M[krow(4 * kk + lq) * nc + 16 * t + lr];
+                const double bv = M[krow(4 * kk + lq) + kcol(t)];
                 acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
             }
     }
@@ -530,9 +531,13 @@ __global__ void __launch_bounds__(NB_T) __attribute__((amdgpu_waves_per_eu(2))) 
     __shared__ __attribute__((aligned(16))) double sA[NN_MAXW * NBM_RS];
     __shared__ __attribute__((aligned(16))) double sD[NN_MAXW * NBM_RS];
     // per hidden layer j (index j-1): the neurons that are not stably inactive
-    // (an inactive neuron's column of Omega, and of Lambda-bar, is exactly 0),
-    // padded with row 0 to a multiple of 4; pos: a neuron's place in the list
-    __shared__ int sList[3][NN_MAXW], sPos[3][NN_MAXW], sLen[3], sTot[3];
+    // (an inactive neuron's column of Omega, and of Lambda-bar, is exactly 0,
+    // and its own columns of Lambda and Omega-bar are never used), padded with
+    // entry 0 to a multiple of 4 (k range) and of 16 (output columns); pos: a
+    // neuron's place in the list.  Products over a hidden layer's neurons, in
+    // k or in output columns, run over its list; their outputs sit at list
+    // positions.
+    __shared__ int sList[3][NN_MAXW], sPos[3][NN_MAXW], sLen[3], sLen16[3], sTot[3];
     __shared__ int sCnt[NB_T / 64];
     const int box = blockIdx.x, mode = blockIdx.y, q = threadIdx.x;
     if (!A.ok[box]) return;
@@ -550,9 +555,9 @@ __global__ void __launch_bounds__(NB_T) __attribute__((amdgpu_waves_per_eu(2))) 
         const int pos = off + __popcll(bal & ((1ull << (q & 63)) - 1ull));
         if (keep) sList[j - 1][pos] = q;
         if (q < nj) sPos[j - 1][q] = keep ? pos : -1;
-        const int padded = (tot + 3) & ~3;
-        if (q >= tot && q < padded) sList[j - 1][q] = 0;
-        if (q == 0) { sLen[j - 1] = padded; sTot[j - 1] = tot; }
+        const int padded = (tot + 3) & ~3, padded16 = (tot + 15) & ~15;
+        if (q >= tot && q < padded16) sList[j - 1][q] = 0;
+        if (q == 0) { sLen[j - 1] = padded; sLen16[j - 1] = padded16; sTot[j - 1] = tot; }
         lds_barrier();
     }
     const bool upper = mode == 0;
@@ -605,7 +610,7 @@ __global__ void __launch_bounds__(NB_T) __attribute__((amdgpu_waves_per_eu(2))) 
                     const double bj = j == 1 ? fb[0] : (j == 2 ? fb[1] : fb[2]);
 #pragma unroll
                     for (int r = 0; r < NBM_R; ++r) {
-                        const double lm = j == k - 1 ? wk[r] : sD[q * NBM_RS + r];
+                        const double lm = j == k - 1 ? wk[r] : sD[pq * NBM_RS + r];
                         const bool sel = upper ? lm >= 0.0 : lm < 0.0;
                         const double om = lm * (sel ? s : a);
                         bpart[r] += (sel ? lm * t : 0.0) + om * bj;
@@ -623,10 +628,13 @@ __global__ void __launch_bounds__(NB_T) __attribute__((amdgpu_waves_per_eu(2))) 
                 nbm_pad(sA, sTot[j - 1], len, q);
                 lds_barrier();
                 const int nj1 = A.w[j - 1];
-                nbm_mm(A.W[j - 1], nj1, len, sList[j - 1], sA, sD, q);
+                if (j == 1) nbm_mm(A.W[0], nj1, nj1, len, sList[0], nullptr, sA, sD, q);
+                else nbm_mm(A.W[j - 1], nj1, sLen16[j - 2], len, sList[j - 1], sList[j - 2], sA, sD, q);
                 if (q < nj1) {
+                    // Lambda^(j-1) column q (0 for a stably inactive neuron: never used)
+                    const int pc = j == 1 ? q : sPos[j - 2][q];
                     double* dst = lvb + A.lv_off[k][j - 1] + (size_t)r0 * nj1 + q;
-                    for (int r = 0; r < nr; ++r) dst[(size_t)r * nj1] = sD[q * NBM_RS + r];
+                    for (int r = 0; r < nr; ++r) dst[(size_t)r * nj1] = pc >= 0 ? sD[pc * NBM_RS + r] : 0.0;
                 }
             }
             if (k < L) {
@@ -685,7 +693,7 @@ __global__ void __launch_bounds__(NB_T) __attribute__((amdgpu_waves_per_eu(2))) 
                     }
                 }
                 lds_barrier();
-                nbm_mm(A.W[j - 1], A.w[j - 1], nj, nullptr, sA, sD, q);
+                nbm_mm(A.W[j - 1], A.w[j - 1], A.w[j - 1], nj, nullptr, nullptr, sA, sD, q);
             }
             if (q < n0) {
 #pragma unroll
@@ -726,11 +734,12 @@ __global__ void __launch_bounds__(NB_T) __attribute__((amdgpu_waves_per_eu(2))) 
                 bj = A.b[j - 1][q];
             }
             // k over layer j-1: the inputs (all) or the listed neurons of a hidden layer
-            if (j == 1) nbm_mm(A.WT[0], nj, n0, nullptr, sA, sD, q);
-            else nbm_mm(A.WT[j - 1], nj, sLen[j - 2], sList[j - 2], sA, sD, q);
+            // output columns over layer j's list
+            if (j == 1) nbm_mm(A.WT[0], nj, sLen16[0], n0, nullptr, sList[0], sA, sD, q);
+            else nbm_mm(A.WT[j - 1], nj, sLen16[j - 1], sLen[j - 2], sList[j - 2], sList[j - 1], sA, sD, q);
             const int pq = q < nj ? sPos[j - 1][q] : -1;
             if (j < k - 1) nbm_pad(sA, sTot[j - 1], sLen[j - 1], q);
-            if (q < nj) {
+            if (pq >= 0) {
                 double s, t, a;
                 nb_relax(lo_j, hi_j, s, t, a);
                 double sa = 0.0, ta = 0.0;
@@ -738,7 +747,7 @@ __global__ void __launch_bounds__(NB_T) __attribute__((amdgpu_waves_per_eu(2))) 
                 for (int r = 0; r < NBM_R; ++r) {
                     const double lm = lmv[r];
                     const bool sel = upper ? lm >= 0.0 : lm < 0.0;
-                    const double obr = sD[q * NBM_RS + r] + y[r] * bj;
+                    const double obr = sD[pq * NBM_RS + r] + y[r] * bj;
                     if (sel) {
                         sa += obr * lm;
                         ta += y[r] * lm;
