@@ -155,3 +155,25 @@ def test_nn_autograd_function(gpu):
     assert torch.equal(tz.grad, g["gz"]) and torch.equal(tv.grad, g["gv"])
     assert torch.equal(ts.grad, g["gsigma"]) and torch.equal(tm.grad, g["gmu"])
     mlp.close()
+
+
+@pytest.mark.parametrize("case", ["layer1_inactive", "tiny_box", "wide_box"])
+def test_nn_backward_edge_boxes(gpu, case):
+    """Neuron lists at their extremes: a first hidden layer stably inactive
+    on every box (empty list: the bound and its gradient are 0), boxes so
+    small that every neuron is stable (gradient 0), and boxes so wide that
+    nearly every neuron is unstable."""
+    import paper_2607_01203_amd as leb
+    rng = W.rng_for(341)
+    sg_lo, sg_hi = {"layer1_inactive": (0.05, 0.4), "tiny_box": (1e-9, 2e-9), "wide_box": (2.0, 3.0)}[case]
+    net, z, v, sg, mu, g_lo, g_hi = _case(rng, [16, 64, 48, 12], 12, 2, 3, sg_lo, sg_hi, True)
+    if case == "layer1_inactive":
+        net.b[0][:] = np.float32(-100.0)
+    print("case: nn backward edge %s" % case, flush=True)
+    g = _gpu_grad(leb, net, z, v, sg, mu, g_lo, g_hi, gpu)
+    for b in range(2):
+        for k in range(3):
+            _check_box(net, g, b, k, z, v, sg, mu, g_lo, g_hi, case)
+    if case != "wide_box":
+        for key in g:
+            assert np.abs(g[key]).max() <= 1e-12, key
