@@ -285,9 +285,10 @@ int leb_nn_bound(leb_mlp net, int32_t batch, int32_t N, const double* z, const d
  * Every pass is recomputed (nothing of leb_nn_bound is reused), in FP64 (on
  * MFMA for networks with at most three hidden layers, on the VALU beyond).
  * Deterministic: every sum is taken in a fixed order.  Uses a library-owned
- * grow-only workspace of up to about 1.1 GB (it holds the CROWN coefficients
- * of the passes of up to 512 boxes; deep, wide networks take fewer boxes at
- * a time), ordered across streams like the other workspaces.
+ * grow-only workspace of up to about 8.6 GB (it holds the CROWN coefficients
+ * of the passes of up to 4,096 boxes: 1.34 MB per box of a 16-256-256-256-12
+ * network; deep, wide networks take fewer boxes at a time), ordered across
+ * streams like the other workspaces.
  * LEB_EINVAL for null or misaligned pointers or gmu without mu.
  */
 int leb_nn_backward(leb_mlp net, int32_t batch, int32_t N, const double* z, const double* v, const double* mu,

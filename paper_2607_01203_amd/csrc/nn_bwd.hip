@@ -66,9 +66,9 @@ namespace leb {
 
 constexpr int NB_R = 8;          // target rows per block
 constexpr int NB_T = 256;        // lanes per workgroup
-constexpr int NB_CHUNK = 512;    // most boxes per chunk of the workspace
+constexpr int NB_CHUNK = 4096;   // most boxes per chunk of the workspace
 constexpr int NB_CHUNK_MIN = 32; // fewest (deep, wide networks)
-constexpr size_t NB_LV_BUDGET = (size_t)1 << 30;   // workspace bytes that set the chunk size
+constexpr size_t NB_LV_BUDGET = (size_t)8 << 30;   // workspace bytes that set the chunk size
 
 struct NbArgs {
     int L;

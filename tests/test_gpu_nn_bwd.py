@@ -83,13 +83,14 @@ def test_nn_backward_parity_shapes(gpu, widths, nx, with_mu):
 
 
 def test_nn_backward_ragged_chunks(gpu):
-    """601 boxes: two chunks of the workspace, the second ragged."""
+    """4,200 boxes: two chunks of the workspace (4,096 boxes each at most),
+    the second ragged."""
     import paper_2607_01203_amd as leb
     rng = W.rng_for(311)
-    net, z, v, sg, mu, g_lo, g_hi = _case(rng, [16, 32, 32, 12], 12, 1, 601, 0.05, 0.4, True)
-    print("case: nn backward 601 boxes", flush=True)
+    net, z, v, sg, mu, g_lo, g_hi = _case(rng, [16, 32, 32, 12], 12, 1, 4200, 0.05, 0.4, True)
+    print("case: nn backward 4200 boxes", flush=True)
     g = _gpu_grad(leb, net, z, v, sg, mu, g_lo, g_hi, gpu)
-    for k in (0, 1, 511, 512, 513, 600):
+    for k in (0, 1, 4095, 4096, 4097, 4199):
         _check_box(net, g, 0, k, z, v, sg, mu, g_lo, g_hi, "ragged")
 
 
