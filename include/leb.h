@@ -257,8 +257,8 @@ int leb_mlp_destroy(leb_mlp net);
  *            for any J), so the bound encloses g(a) - g(a~) - J (a - a~);
  *            a unit whose J has a non-finite entry gets [-inf, +inf] on every
  *            row and LEB_FLAG_BAD_INPUT.
- * Uses a library-owned grow-only workspace (about 200 MB at the largest
- * chunk of 1024 boxes of a 256-wide network).  Calls from several host threads serialise on the
+ * Uses a library-owned grow-only workspace (about 800 MB at the largest
+ * chunk of 4096 boxes of a 256-wide network).  Calls from several host threads serialise on the
  * host, and a call's kernels wait (on the device) for those of the previous
  * call that used the workspace, whatever its stream.
  */

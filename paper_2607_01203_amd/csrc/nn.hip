@@ -45,7 +45,7 @@ namespace leb {
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr double RT = 0x1p-40;   // rounding allowance factor
-constexpr int NN_CHUNK = 1024;   // boxes per pass
+constexpr int NN_CHUNK = 4096;   // boxes per pass
 constexpr uint32_t NN_UNSTABLE = 1u << 31;   // private per-box bit: some neuron is unstable
 
 }  // namespace leb

@@ -54,7 +54,7 @@ def test_nn_small_slice_parity(gpu):
 
 
 def test_nn_full_config_sampled(gpu):
-    """64 trajectories x 50 steps (3200 boxes, 4 chunks of work): oracle on a sample."""
+    """64 trajectories x 50 steps (3200 boxes, one chunk of work): oracle on a sample."""
     import paper_2607_01203_amd as leb
     b = W.nn_cfg()
     print("case: nn full 64x50", flush=True)
@@ -115,3 +115,19 @@ def test_nn_soundness_1e6(gpu):
         r, eps = nn.remainder(b.net.W, b.net.b, a[s:s + 50], pts)
         viol += int(((r > hi[s:s + 50, None] + eps) | (r < lo[s:s + 50, None] - eps)).sum())
     assert viol == 0
+
+
+def test_nn_bound_two_chunks(gpu):
+    """4,300 boxes: two chunks of the bound's work buffers (4,096 boxes at
+    most), the second ragged; the oracle on boxes at both ends of each."""
+    import paper_2607_01203_amd as leb
+    rng = W.rng_for(78)
+    Wl, bl = W.mlp_weights(rng, [16, 32, 32, 12])
+    net = W.MLPNet(Wl, bl, 12, 4, True)
+    a = rng.uniform(-1, 1, (1, 4300, 16))
+    sg = rng.uniform(0.005, 0.1, (1, 4300, 16))
+    print("case: nn bound 4300 boxes", flush=True)
+    g = _run(leb, net, a[..., :12].copy(), a[..., 12:].copy(), sg, gpu)
+    idx = np.array([0, 1, 4095, 4096, 4097, 4299])
+    o = _oracle(net, a[0, idx, :12], a[0, idx, 12:], sg[0, idx])
+    check_bounds(g["r_lo"][0, idx], g["r_hi"][0, idx], o["r_lo"], o["r_hi"], "two chunks")
