@@ -327,7 +327,7 @@ extern "C" int leb_batch_create(const leb_problem* probs, int32_t count, const c
         }
         if (!rc) append_cache(tune_cache, key, g.T);
     }
-    // MLP groups: staging, work buffers, CB in {256, 512, 1024}
+    // MLP groups: staging, work buffers, CB in {256, ..., 4096}
     for (NNGroup& g : b->nn) {
         if (rc) break;
         const int n0 = g.nx + g.nu;
@@ -353,7 +353,7 @@ extern "C" int leb_batch_create(const leb_problem* probs, int32_t count, const c
             break;
         }
         std::vector<int> cand;
-        for (int CB : {256, 512, 1024}) cand.push_back((int)std::min<int64_t>(CB, g.units));
+        for (int CB : {256, 512, 1024, 2048, 4096}) cand.push_back((int)std::min<int64_t>(CB, g.units));
         cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
         const int cbmax = *std::max_element(cand.begin(), cand.end());
         size_t sizes[NN_NBUF];
